@@ -1,0 +1,134 @@
+/*
+ * fastperm.h -- C ABI of the MI355X (gfx950) patch-guided nested-dissection
+ * ordering library (libfastperm.so).
+ *
+ * What it computes (Zarebavani, Mahmoud et al., "Fast Sparse Matrix
+ * Permutation for Mesh-Based Direct Solvers"): given the sparsity pattern
+ * of a symmetric matrix A from a mesh (Sec. 4, "Inputs and outputs"), a
+ * fill-reducing permutation built by patch-guided nested dissection
+ * (Alg. 1-3), the separator tree it was built on (Sec. 4.2, stored as a heap
+ * array), and the elimination tree and column counts of the Cholesky factor
+ * of A(perm, perm) that a sparse Cholesky symbolic phase needs (Sec. 2).
+ *
+ * Conventions
+ *   - All arrays passed to fp_order / fp_order_batch are DEVICE pointers
+ *     owned by the caller; the library never frees them.  Server calls take
+ *     host arrays (documented there).
+ *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *     fp_order and fp_order_batch only enqueue work; results are ready when
+ *     the stream reaches that point.  Errors found by the device are read
+ *     with fp_last_error after the stream is synchronised.
+ *   - perm[new] = old, iperm[old] = new.  parent[j] is the elimination-tree
+ *     parent of column j of A(perm,perm), -1 for a root.  colcount[j] counts
+ *     the nonzeros of column j of L including the diagonal; nnzL is their sum.
+ *   - Block patterns (block_size b > 1): DOF b*k+r belongs to mesh vertex k;
+ *     the ordering is computed on the vertex graph and expanded so that the
+ *     b DOFs of a vertex stay consecutive (Sec. 6.5).  The expansion of the
+ *     elimination tree and column counts is exact when every vertex-level
+ *     nonzero is a dense b x b block.
+ *   - No function throws; every entry point returns an fp_status.  A handle
+ *     is not thread-safe: use one per host thread.
+ */
+#ifndef FASTPERM_H
+#define FASTPERM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FP_ABI_VERSION 1
+
+typedef enum {
+  FP_OK = 0,
+  FP_ERR_ARG = 1,          /* invalid scalar argument or null required pointer */
+  FP_ERR_NOT_SYMMETRIC = 2,
+  FP_ERR_INDEX = 3,        /* column index / row pointer out of range (device) */
+  FP_ERR_SIZE = 4,         /* workspace too small or a device pool overflowed */
+  FP_ERR_OOM = 5,          /* device allocation failed */
+  FP_ERR_UNSUPPORTED = 6,  /* option value not implemented */
+  FP_ERR_BUSY = 7,         /* server admission refused (slots or memory) */
+  FP_ERR_HIP = 8,          /* a HIP runtime call failed */
+  FP_ERR_DEVICE = 9        /* the device pipeline reported an internal failure */
+} fp_status;
+
+typedef struct fp_handle fp_handle;
+
+#define FP_SCHED_LEVEL 0 /* level order: leaves first, then upward (Sec. 5) */
+#define FP_SCHED_POST 1  /* post order: left, right, node (Sec. 5) */
+
+typedef struct {
+  int32_t patch_size;   /* target patch size S (Sec. 6 uses 256; default 512) */
+  int32_t nd_level;     /* -1: full depth (each leaf one patch); others unsupported */
+  int32_t schedule;     /* FP_SCHED_LEVEL (default) or FP_SCHED_POST */
+  int32_t block_size;   /* DOFs per mesh vertex, >= 1 (default 1) */
+  int32_t lloyd_iters;  /* Lloyd re-centre iterations of patching (default 1) */
+  uint64_t seed;        /* seed of the patch-seed hash (default 0) */
+  uint32_t flags;       /* reserved, must be 0 */
+} fp_options;
+
+/* Pattern of A in CSR form (device arrays).  Exactly one of rowptr32 /
+ * rowptr64 is non-NULL (n+1 entries); colind has nnz entries in [0, n).
+ * The pattern must be symmetric; the diagonal is optional; duplicates and
+ * column order do not matter.  n < 2^31. */
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* rowptr32;
+  const int64_t* rowptr64;
+  const int32_t* colind;
+} fp_csr;
+
+/* Outputs (device arrays owned by the caller).  perm, iperm, parent and
+ * colcount (n entries each) and nnzL (1 entry) are required; the rest are
+ * optional (NULL skips them).  node_begin/node_size receive the separator
+ * tree as a heap (node t has children 2t+1, 2t+2) in DOF units; their
+ * capacity max_nodes comes from fp_query.  gmap (n/b entries) receives the
+ * patch of every mesh vertex; n_nodes (1 entry) the heap size 2^(D+1)-1;
+ * status (1 entry) the device error bits (0 = success). */
+typedef struct {
+  int32_t* perm;
+  int32_t* iperm;
+  int32_t* parent;
+  int32_t* colcount;
+  int64_t* nnzL;
+  int32_t* node_begin;
+  int32_t* node_size;
+  int32_t* gmap;
+  int32_t* n_nodes;
+  uint32_t* status;
+  int32_t max_nodes;
+} fp_result;
+
+int fp_version(void);
+const char* fp_status_str(fp_status s);
+void fp_options_default(fp_options* opts);
+
+/* Create / destroy a handle bound to the current HIP device.  The handle
+ * owns device properties and the tuning table; fp_destroy(NULL) is a no-op. */
+fp_status fp_create(fp_handle** h);
+fp_status fp_destroy(fp_handle* h);
+
+/* Host-side sizing, no device work: bytes of device workspace fp_order needs
+ * for this pattern and options, and the capacity for node_begin/node_size. */
+fp_status fp_query(fp_handle* h, const fp_csr* A, const fp_options* opts,
+                   size_t* workspace_bytes, int32_t* max_nodes);
+
+/* Order one matrix (Alg. 1).  user_gmap (device, n/b entries, nullable)
+ * replaces patching with caller groups in [0, n/b) (Sec. 5).  workspace is
+ * device memory of at least the fp_query size, owned by the caller and not
+ * shared with another call in flight.  Asynchronous on `stream`. */
+fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
+                   const fp_options* opts, void* workspace, size_t ws_bytes,
+                   fp_result* out, void* stream);
+
+/* Synchronise `stream` and translate the device error bits of the last
+ * call that used `workspace`. */
+fp_status fp_last_error(fp_handle* h, void* workspace, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

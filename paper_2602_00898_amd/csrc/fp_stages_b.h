@@ -1,0 +1,362 @@
+// fp_stages_b.h -- separator tree (patch-guided nested dissection) and the
+// grouping of vertices by tree node in schedule order.
+#pragma once
+
+#include "fp_stages_a.h"
+
+// --------------------------------------------------------------------------
+// Workgroup BFS on the quotient subgraph of tree node t (alive arcs whose
+// both ends lie in t).  Local index i <-> patch pid[i]; ploc maps back.
+// lev[] must be -1 on the component of src.  The visit order goes to
+// queue[]; ls[L] = first queue slot of level L, ls[ecc+1] = count.
+// Returns the number of nodes reached; *ecc_out = eccentricity of src.
+// --------------------------------------------------------------------------
+struct BisectLds {
+  int tmp[FP_WAVES + 2];
+  int tail;
+  int r0;
+  unsigned long long red[FP_WAVES];
+};
+
+__device__ int wg_bfs(const FpMesh& M, int t, const int* pid, int src, int* lev, int* queue,
+                      int* ls, int* ecc_out, BisectLds* sh) {
+  if (threadIdx.x == 0) {
+    lev[src] = 0;
+    queue[0] = src;
+    ls[0] = 0;
+    sh->tail = 1;
+  }
+  __syncthreads();
+  int head = 0, tail = 1, L = 0;
+  while (true) {
+    for (int i = head + (int)threadIdx.x; i < tail; i += FP_WG) {
+      const int x = queue[i];
+      const int p = pid[x];
+      for (int a = M.qptr[p]; a < M.qptr[p + 1]; a++) {
+        if (M.qcnt[a] <= 0) continue;
+        const int q = M.qci[a];
+        if (M.pnode[q] != t) continue;
+        const int y = M.ploc[q];
+        if (atomicCAS(&lev[y], -1, L + 1) == -1) queue[atomicAdd(&sh->tail, 1)] = y;
+      }
+    }
+    __syncthreads();
+    const int nt = sh->tail;
+    __syncthreads();
+    if (nt == tail) break;
+    L++;
+    if (threadIdx.x == 0) ls[L] = tail;
+    head = tail;
+    tail = nt;
+  }
+  if (threadIdx.x == 0) ls[L + 1] = tail;
+  __syncthreads();
+  *ecc_out = L;
+  return tail;
+}
+
+__device__ unsigned long long wg_min_u64(unsigned long long x, BisectLds* sh) {
+  x = wave_min_u64(x);
+  if (lane_id() == 0) sh->red[wave_id()] = x;
+  __syncthreads();
+  unsigned long long m = sh->red[0];
+  for (int w = 1; w < FP_WAVES; w++) m = sh->red[w] < m ? sh->red[w] : m;
+  __syncthreads();
+  return m;
+}
+
+// Bisection of tree node t (Alg. 2 BiPartition; METIS is replaced by a BFS
+// level structure from a pseudo-peripheral start, George & Liu 1979).  The
+// node's patches are plist[s..s+m), ascending ids.  Writes the two child
+// segments back into plist (left ascending, then right ascending) and moves
+// each patch to its child in pnode.
+__device__ void wg_bisect(const FpMesh& M, int t, int s, int m, BisectLds* sh) {
+  int* pid = M.bs[0] + s;
+  int* deg = M.bs[1] + s;
+  int* levA = M.bs[2] + s;
+  int* levB = M.bs[3] + s;
+  int* qA = M.bs[4] + s;
+  int* qB = M.bs[5] + s;
+  // level starts need up to m+1 entries: node t's region is shifted by its
+  // rank inside its depth, so regions of one depth stay disjoint
+  const int rank_in_depth = t - ((1 << (31 - __clz(t + 1))) - 1);
+  int* lsA = M.bs[6] + s + rank_in_depth;
+  int* lsB = M.bs[7] + s + rank_in_depth;
+  int* Q = M.bs[8] + s;
+  int* flag = M.bs[9] + s;
+  const int P = M.ctl->P;
+  for (int i = threadIdx.x; i < m; i += FP_WG) {
+    int p = M.plist[s + i];
+    if (p < 0 || p >= P) {  // never expected: keep every later index in range
+      atomicOr(&M.ctl->err, FP_E_INTERNAL);
+      p = 0;
+    }
+    pid[i] = p;
+    M.ploc[p] = i;
+    levA[i] = -1;
+    levB[i] = -1;
+    flag[i] = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += FP_WG) {
+    const int p = pid[i];
+    int d = 0;
+    for (int a = M.qptr[p]; a < M.qptr[p + 1]; a++)
+      d += (M.qcnt[a] > 0 && M.pnode[M.qci[a]] == t);
+    deg[i] = d;
+  }
+  __syncthreads();
+  int base = 0, r0 = 0;
+  while (base < m) {
+    // the next component starts at its lowest unseen local index
+    unsigned long long cand = 0xFFFFFFFFFFFFFFFFull;
+    for (int i = r0 + (int)threadIdx.x; i < m; i += FP_WG)
+      if (!flag[i]) {
+        cand = (unsigned long long)i;
+        break;
+      }
+    r0 = (int)wg_min_u64(cand, sh);
+    int eccA, eccB;
+    int cnt = wg_bfs(M, t, pid, r0, levA, qA, lsA, &eccA, sh);
+    for (int round = 0; round < 8; round++) {
+      // least (degree, index) on the last level
+      unsigned long long best = 0xFFFFFFFFFFFFFFFFull;
+      for (int i = lsA[eccA] + (int)threadIdx.x; i < cnt; i += FP_WG) {
+        int x = qA[i];
+        unsigned long long k = ((unsigned long long)deg[x] << 32) | (unsigned)x;
+        best = k < best ? k : best;
+      }
+      const int c = (int)(wg_min_u64(best, sh) & 0xFFFFFFFFu);
+      wg_bfs(M, t, pid, c, levB, qB, lsB, &eccB, sh);
+      const bool accept = eccB > eccA;
+      int* clr_lev = accept ? levA : levB;
+      int* clr_q = accept ? qA : qB;
+      for (int i = threadIdx.x; i < cnt; i += FP_WG) clr_lev[clr_q[i]] = -1;
+      __syncthreads();
+      if (!accept) break;
+      int* tp;
+      tp = levA; levA = levB; levB = tp;
+      tp = qA; qA = qB; qB = tp;
+      tp = lsA; lsA = lsB; lsB = tp;
+      eccA = eccB;
+    }
+    // order by (level, index): rank inside the level by counting smaller ids
+    for (int i = threadIdx.x; i < cnt; i += FP_WG) {
+      const int x = qA[i];
+      const int L = levA[x];
+      const int a = lsA[L], b = lsA[L + 1];
+      int r = 0;
+      for (int j = a; j < b; j++) r += (qA[j] < x);
+      Q[base + a + r] = x;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt; i += FP_WG) {
+      const int x = qA[i];
+      flag[x] = 1;
+      levA[x] = -1;
+    }
+    __syncthreads();
+    base += cnt;
+  }
+  // weighted split: k* = least k with 2 * (weight of Q[0..k)) >= W, then
+  // clamp to the heap capacity of the children
+  long long W = 0;
+  for (int i = threadIdx.x; i < m; i += FP_WG) W += M.wp[pid[i]];
+  W = wg_sum_i64(W, (int64_t*)sh->red);
+  int kstar;
+  if (W == 0) {
+    kstar = (m + 1) / 2;
+  } else {
+    unsigned long long first = 0xFFFFFFFFFFFFFFFFull;
+    long long run = 0;
+    for (int c0 = 0; c0 < m; c0 += FP_WG) {
+      const int i = c0 + (int)threadIdx.x;
+      const int w = i < m ? M.wp[pid[Q[i]]] : 0;
+      int tt;
+      const int ex = wg_excl_scan(w, sh->tmp, &tt);
+      if (i < m && 2 * (run + ex + w) >= W && (unsigned long long)i < first) first = i;
+      run += tt;
+    }
+    first = wg_min_u64(first, sh);
+    kstar = first == 0xFFFFFFFFFFFFFFFFull ? m : (int)first + 1;
+  }
+  int h = 0;
+  while ((1 << h) < m) h++;
+  const int cap = 1 << (h - 1);
+  const int lo = max(1, m - cap), hi = min(m - 1, cap);
+  const int k = min(max(kstar, lo), hi);
+  for (int i = threadIdx.x; i < m; i += FP_WG) flag[Q[i]] = (i < k) ? 1 : 2;
+  __syncthreads();
+  // stable split in ascending id order
+  int rl = 0, rr = 0;
+  for (int c0 = 0; c0 < m; c0 += FP_WG) {
+    const int i = c0 + (int)threadIdx.x;
+    const int f = i < m ? flag[i] : 0;
+    int tl, tr;
+    const int el = wg_excl_scan(f == 1, sh->tmp, &tl);
+    const int er = wg_excl_scan(f == 2, sh->tmp, &tr);
+    if (f == 1) {
+      M.plist[s + rl + el] = pid[i];
+      M.pnode[pid[i]] = 2 * t + 1;
+    } else if (f == 2) {
+      M.plist[s + k + rr + er] = pid[i];
+      M.pnode[pid[i]] = 2 * t + 2;
+    }
+    rl += tl;
+    rr += tr;
+  }
+  if (threadIdx.x == 0) {
+    if (rl != k || rr != m - k) atomicOr(&M.ctl->err, FP_E_INTERNAL);
+    M.segS[2 * t + 1] = s;
+    M.segN[2 * t + 1] = k;
+    M.segS[2 * t + 2] = s + k;
+    M.segN[2 * t + 2] = m - k;
+  }
+  __syncthreads();
+}
+
+// --------------------------------------------------------------------------
+// Separator tree (Sec. 4.2 Step 3; Alg. 2; Sec. 5).  Level d: recount alive
+// quotient arcs from the boundary list, bisect every node of depth d, then
+// SuperSeparator (unmarked vertices with an unmarked neighbour across) and
+// RefineSeparator (keep the smaller side, ties to the left).  Node weights
+// are decremented as vertices are marked.
+// --------------------------------------------------------------------------
+__device__ bool stage_septree(const Team& T, const FpMesh& M, char* lds) {
+  FpCtl* C = M.ctl;
+  BisectLds* sh = (BisectLds*)lds;
+  const int n = M.n, P = C->P;
+  int D = 0;
+  while ((1 << D) < P) D++;
+  const int nn = (1 << (D + 1)) - 1;
+  if (nn > M.NNcap) {
+    if (T.gtid() == 0) atomicOr(&C->err, FP_E_SCRATCH);
+    return false;
+  }
+  if (T.gtid() == 0) {
+    C->D = D;
+    C->nn = nn;
+  }
+  for (int v = T.gtid(); v < n; v += T.gsize()) M.node_of[v] = -1;
+  for (int p = T.gtid(); p < P; p += T.gsize()) {
+    M.pnode[p] = 0;
+    M.plist[p] = p;
+  }
+  for (int x = T.gtid(); x < nn; x += T.gsize()) {
+    M.cntL[x] = 0;
+    M.cntR[x] = 0;
+    M.segN[x] = 0;
+    M.segS[x] = 0;
+  }
+  T.sync();
+  if (T.gtid() == 0) M.segN[0] = P;
+  const int nb = C->nbnd;
+  for (int d = 0; d < D; d++) {
+    const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
+    // alive arcs: crossing edges between unmarked vertices
+    for (int a = T.gtid(); a < C->nq; a += T.gsize()) M.qcnt[a] = 0;
+    T.sync();
+    for (int i = T.gtid(); i < nb; i += T.gsize()) {
+      const int v = M.bnd[i];
+      if (M.node_of[v] != -1) continue;
+      const int gv = M.gmap[v];
+      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+        const int u = M.gci[e];
+        if (M.node_of[u] != -1) continue;
+        const int gu = M.gmap[u];
+        if (gu == gv) continue;
+        const int a = arc_index(M, gv, gu);
+        if (a >= 0) atomicAdd(&M.qcnt[a], 1);
+      }
+    }
+    T.sync();
+    for (int t = lo + T.rank; t < hi; t += T.size) {
+      const int m = M.segN[t];
+      if (m >= 2)
+        wg_bisect(M, t, M.segS[t], m, sh);
+    }
+    T.sync();
+    // candidates on both sides
+    for (int i = T.gtid(); i < nb; i += T.gsize()) {
+      const int v = M.bnd[i];
+      M.cand[i] = 0;
+      if (M.node_of[v] != -1) continue;
+      const int c = M.pnode[M.gmap[v]];
+      if (c < hi) continue;  // patch not split at this level
+      const int sib = (c & 1) ? c + 1 : c - 1;
+      bool is = false;
+      for (int e = M.grp[v]; e < M.grp[v + 1] && !is; e++) {
+        const int u = M.gci[e];
+        is = (M.node_of[u] == -1 && M.pnode[M.gmap[u]] == sib);
+      }
+      if (is) {
+        M.cand[i] = 1;
+        atomicAdd((c & 1) ? &M.cntL[(c - 1) >> 1] : &M.cntR[(c - 1) >> 1], 1);
+      }
+    }
+    T.sync();
+    for (int i = T.gtid(); i < nb; i += T.gsize()) {
+      if (!M.cand[i]) continue;
+      const int v = M.bnd[i];
+      const int c = M.pnode[M.gmap[v]];
+      const int t = (c - 1) >> 1;
+      const bool left = c & 1;
+      const bool mark_left = M.cntL[t] <= M.cntR[t];
+      if (left == mark_left) {
+        M.node_of[v] = t;
+        atomicSub(&M.wp[M.gmap[v]], 1);
+      }
+    }
+    T.sync();
+  }
+  // leaves keep the remaining vertices of their patch
+  for (int v = T.gtid(); v < n; v += T.gsize())
+    if (M.node_of[v] == -1) M.node_of[v] = M.pnode[M.gmap[v]];
+  T.sync();
+  return true;
+}
+
+// --------------------------------------------------------------------------
+// Grouping (Alg. 3): node sizes, schedule offsets and vertices scattered into
+// their node's block (unordered inside a block; the local-order stage sorts
+// each block by vertex id).  Level order: depth descending, heap index
+// ascending.  Post order: left subtree, right subtree, node.
+// --------------------------------------------------------------------------
+__device__ __forceinline__ int sched_pos(int t, int D, int sched) {
+  int d = 31 - __clz(t + 1);
+  if (sched == 0) return ((1 << (D + 1)) - (1 << (d + 1))) + (t - ((1 << d) - 1));
+  // post order: start of t's subtree block plus its size minus one
+  int start = 0;
+  const int path = t + 1;
+  for (int i = d - 1; i >= 0; i--) {
+    const int depth_child = d - i;  // depth of the node reached by this step
+    if ((path >> i) & 1) start += (1 << (D - depth_child + 1)) - 1;  // skip left sibling subtree
+  }
+  return start + (1 << (D - d + 1)) - 2;
+}
+
+__device__ void stage_group(const Team& T, const FpMesh& M, int* lds_tmp) {
+  FpCtl* C = M.ctl;
+  const int n = M.n, nn = C->nn, D = C->D;
+  for (int x = T.gtid(); x < nn; x += T.gsize()) M.nsize[x] = 0;
+  T.sync();
+  for (int v = T.gtid(); v < n; v += T.gsize()) {
+    if ((unsigned)M.node_of[v] >= (unsigned)nn) {  // never expected
+      atomicOr(&C->err, FP_E_INTERNAL);
+      M.node_of[v] = 0;
+    }
+    atomicAdd(&M.nsize[M.node_of[v]], 1);
+  }
+  T.sync();
+  for (int x = T.gtid(); x < nn; x += T.gsize()) M.sbuf[sched_pos(x, D, M.sched)] = M.nsize[x];
+  T.sync();
+  team_excl_scan(T, M.sbuf, M.sbuf, nn, C->part, &C->tot, lds_tmp);
+  for (int x = T.gtid(); x < nn; x += T.gsize()) {
+    const int b = M.sbuf[sched_pos(x, D, M.sched)];
+    M.nbegin[x] = b;
+    M.ncur[x] = b;
+  }
+  T.sync();
+  for (int v = T.gtid(); v < n; v += T.gsize()) M.gbuf[atomicAdd(&M.ncur[M.node_of[v]], 1)] = v;
+  T.sync();
+}

@@ -1,0 +1,586 @@
+// fp_stages_md.h -- local orders: exact minimum degree on the subgraph
+// induced by each separator-tree node (Sec. 4.3 Step 4, LocalOrder; the
+// textbook one-vertex-per-step scheme of Tinney and Walker, ties to the
+// lowest local index = rank of the vertex id inside the node).
+//
+// One wave64 owns a node.  The elimination graph lives in LDS:
+//   BIT    -- adjacency bitsets (m x ceil(m/32) words); neighbours of the
+//             pivot are found word-wise and only the nonzero words of the
+//             pivot row are OR-ed into each neighbour row,
+//   SPARSE -- fixed-capacity rows of 16-bit local ids, for large nodes of
+//             low degree (separators are path-like); when the remaining
+//             vertices fit the BIT layout, or a row would overflow, the
+//             state is re-indexed (rank order kept, so tie-breaking is
+//             unchanged) into BIT form,
+//   BITG   -- BIT layout in a global-memory pool, for nodes too big for LDS.
+// The pivot is the minimum of keys (degree << 16 | index) found through a
+// 64-ary min tree: per-64 group minima are refreshed only for groups whose
+// keys changed, then reduced across the wave.
+#pragma once
+
+#include "fp_stages_b.h"
+
+#define FP_KEY_INF 0xFFFFFFFFu
+#define FP_MD_MAXM 65535  // 16-bit local ids
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// device-wide bump allocation from the fallback pool (32-bit words)
+__device__ __forceinline__ unsigned* pool_alloc(const FpMesh& M, unsigned long long words) {
+  unsigned long long off = 0;
+  if (lane_id() == 0) {
+    words = (words + 63) & ~63ull;
+    off = atomicAdd(&M.ctl->pool_top, words);
+    if (off + words > M.pool_words) {
+      atomicOr(&M.ctl->err, FP_E_SCRATCH);
+      off = ~0ull;
+    }
+  }
+  off = __shfl((unsigned long long)off, 0, 64);
+  return off == ~0ull ? nullptr : M.pool + off;
+}
+
+__device__ __forceinline__ int md_words(int m) { return (m + 31) >> 5; }
+__device__ __forceinline__ int md_groups(int m) { return (m + 63) >> 6; }
+
+// LDS bytes of the BIT layout for m vertices
+__device__ __forceinline__ long long md_bit_bytes(int m) {
+  const long long W = md_words(m), G = md_groups(m);
+  return 4ll * m * W + 12ll * W + 8ll * m + 12ll * G + 64;
+}
+__device__ __forceinline__ int md_bit_max(long long bytes) {
+  int lo = 0, hi = FP_MD_MAXM;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (md_bit_bytes(mid) <= bytes)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+struct MdBit {
+  uint32_t* rows;
+  uint32_t* alive;
+  uint32_t* nbm;
+  int* nzw;
+  int* nbl;
+  uint32_t* key;
+  uint32_t* gmin;
+  int* dl;  // dirty groups: flags [0,G) then list [G,2G)
+  int m, W, G;
+};
+
+__device__ __forceinline__ void md_bit_carve(MdBit& B, char* mem, int m) {
+  B.m = m;
+  B.W = md_words(m);
+  B.G = md_groups(m);
+  char* p = mem;
+  B.rows = (uint32_t*)p;
+  p += 4ll * m * B.W;
+  B.alive = (uint32_t*)p;
+  p += 4 * B.W;
+  B.nbm = (uint32_t*)p;
+  p += 4 * B.W;
+  B.nzw = (int*)p;
+  p += 4 * B.W;
+  B.nbl = (int*)p;
+  p += 4ll * m;
+  B.key = (uint32_t*)p;
+  p += 4ll * m;
+  B.gmin = (uint32_t*)p;
+  p += 4 * B.G;
+  B.dl = (int*)p;
+}
+
+__device__ __forceinline__ void md_refresh_all_groups(MdBit& B) {
+  for (int g = 0; g < B.G; g++) {
+    const int i = g * 64 + lane_id();
+    uint32_t k = i < B.m ? B.key[i] : FP_KEY_INF;
+    k = wave_min_u32(k);
+    if (lane_id() == 0) B.gmin[g] = k;
+    if (lane_id() == 0) B.dl[g] = 0;
+  }
+  __threadfence_block();
+}
+
+__device__ __forceinline__ uint32_t md_argmin(const uint32_t* gmin, int G) {
+  uint32_t km = FP_KEY_INF;
+  for (int g = lane_id(); g < G; g += 64) km = min(km, gmin[g]);
+  return wave_min_u32(km);
+}
+
+// refresh the minima of the groups flagged in dl[0..G) and clear the flags
+__device__ __forceinline__ void md_refresh_dirty(uint32_t* key, uint32_t* gmin, int* dl, int m,
+                                                 int G) {
+  int nd = 0;
+  for (int g0 = 0; g0 < G; g0 += 64) {
+    const int g = g0 + lane_id();
+    const bool d = g < G && dl[g];
+    const uint64_t bal = ballot64(d);
+    if (d) {
+      dl[G + nd + popc64(bal & lanemask_lt())] = g;
+      dl[g] = 0;
+    }
+    nd += popc64(bal);
+  }
+  __threadfence_block();
+  for (int j = 0; j < nd; j++) {
+    const int g = dl[G + j];
+    const int i = g * 64 + lane_id();
+    uint32_t k = i < m ? key[i] : FP_KEY_INF;
+    k = wave_min_u32(k);
+    if (lane_id() == 0) gmin[g] = k;
+  }
+  __threadfence_block();
+}
+
+// Run minimum degree steps on a BIT layout until every vertex is ordered.
+// vmap[i] = vertex id of current index i; outputs go to positions
+// pos0, pos0+1, ...
+__device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int* vmap, int pos0,
+                                           int nsteps) {
+  const int lane = lane_id();
+  const int W = B.W;
+  for (int s = 0; s < nsteps; s++) {
+    const uint32_t km = md_argmin(B.gmin, B.G);
+    const int p = (int)(km & 0xFFFFu);
+    if (km == FP_KEY_INF || p >= B.m) {  // never expected: stop before any wild index
+      if (lane == 0) atomicOr(&M.ctl->err, FP_E_INTERNAL);
+      return;
+    }
+    if (lane == 0) {
+      const int v = vmap[p];
+      M.vperm[pos0 + s] = v;
+      if ((unsigned)v < (unsigned)M.n) M.viperm[v] = pos0 + s;
+      B.alive[p >> 5] &= ~(1u << (p & 31));
+      B.key[p] = FP_KEY_INF;
+      B.dl[p >> 6] = 1;
+    }
+    __threadfence_block();
+    // neighbours of p among the remaining vertices, word by word
+    int nnzw = 0;
+    const uint32_t* rp = B.rows + (long long)p * W;
+    for (int w0 = 0; w0 < W; w0 += 64) {
+      const int w = w0 + lane;
+      const uint32_t x = (w < W) ? (rp[w] & B.alive[w]) : 0u;
+      if (w < W) B.nbm[w] = x;
+      const uint64_t bal = ballot64(x != 0);
+      if (x) B.nzw[nnzw + popc64(bal & lanemask_lt())] = w;
+      nnzw += popc64(bal);
+    }
+    __threadfence_block();
+    int k = 0;
+    for (int j0 = 0; j0 < nnzw; j0 += 64) {
+      const int j = j0 + lane;
+      uint32_t x = j < nnzw ? B.nbm[B.nzw[j]] : 0u;
+      const int w = j < nnzw ? B.nzw[j] : 0;
+      const int c = popc32(x);
+      const int inc = wave_incl_scan(c);
+      int off = k + inc - c;
+      while (x) {
+        const int bit = __ffs(x) - 1;
+        x &= x - 1;
+        B.nbl[off++] = w * 32 + bit;
+      }
+      k += __shfl(inc, 63, 64);
+    }
+    __threadfence_block();
+    // the neighbours become a clique: OR the pivot row into theirs
+    for (int i = lane; i < k; i += 64) {
+      const int u = B.nbl[i];
+      uint32_t* ru = B.rows + (long long)u * W;
+      const int uw = u >> 5;
+      const uint32_t ubit = 1u << (u & 31);
+      int added = 0;
+      for (int j = 0; j < nnzw; j++) {
+        const int w = B.nzw[j];
+        const uint32_t old = ru[w];
+        uint32_t nv = old | B.nbm[w];
+        if (w == uw) nv &= ~ubit;
+        added += popc32(nv & ~old);
+        ru[w] = nv;
+      }
+      const uint32_t deg = (B.key[u] >> 16) + added - 1;
+      B.key[u] = (deg << 16) | (uint32_t)u;
+      B.dl[u >> 6] = 1;
+    }
+    __threadfence_block();
+    md_refresh_dirty(B.key, B.gmin, B.dl, B.m, B.G);
+  }
+}
+
+// ---------------------------------------------------------------- SPARSE
+struct MdSp {
+  uint16_t* rows;  // m*C
+  uint16_t* len;   // m
+  uint32_t* key;   // m
+  uint32_t* gmin;  // G
+  int* dl;         // 2G
+  int* nbl;        // m
+  int m, C, G;
+};
+
+__device__ __forceinline__ long long md_sp_bytes(int m, int C) {
+  const long long G = md_groups(m);
+  return 2ll * m * C + 2ll * m + 4ll * m + 4 * G + 8 * G + 4ll * m + 64;
+}
+
+__device__ __forceinline__ void md_sp_carve(MdSp& S, char* mem, int m, int C) {
+  S.m = m;
+  S.C = C;
+  S.G = md_groups(m);
+  char* p = mem;
+  S.key = (uint32_t*)p;
+  p += 4ll * m;
+  S.nbl = (int*)p;
+  p += 4ll * m;
+  S.gmin = (uint32_t*)p;
+  p += 4 * S.G;
+  S.dl = (int*)p;
+  p += 8 * S.G;
+  S.len = (uint16_t*)p;
+  p += 2ll * m;
+  p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+  S.rows = (uint16_t*)p;
+}
+
+// ---------------------------------------------------------------- driver
+// sort the node's vertex ids (LDS bitonic sort over the next power of two)
+__device__ void wave_sort_ids(int* a, int m, int np2) {
+  for (int i = m + lane_id(); i < np2; i += 64) a[i] = 0x7FFFFFFF;
+  __threadfence_block();
+  for (int k = 2; k <= np2; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = lane_id(); i < np2; i += 64) {
+        const int ixj = i ^ j;
+        if (ixj > i) {
+          const int x = a[i], y = a[ixj];
+          const bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            a[i] = y;
+            a[ixj] = x;
+          }
+        }
+      }
+      __threadfence_block();
+    }
+}
+
+// Build BIT rows for the vertices vmap[0..m) of node t straight from G.
+__device__ void md_bit_build(const FpMesh& M, MdBit& B, int t, const int* vmap) {
+  const int m = B.m, W = B.W;
+  for (long long i = lane_id(); i < (long long)m * W; i += 64) B.rows[i] = 0u;
+  for (int w = lane_id(); w < W; w += 64) {
+    const int hi = min(32, m - w * 32);
+    B.alive[w] = hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
+  }
+  for (int g = lane_id(); g < 2 * B.G; g += 64) B.dl[g] = 0;
+  __threadfence_block();
+  for (int i = lane_id(); i < m; i += 64) {
+    const int v = vmap[i];
+    uint32_t* ri = B.rows + (long long)i * W;
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+      const int u = M.gci[e];
+      if (M.node_of[u] != t) continue;
+      const int j = M.lidx[u];
+      if (j != i) ri[j >> 5] |= 1u << (j & 31);
+    }
+    int d = 0;
+    for (int w = 0; w < W; w++) d += popc32(ri[w]);
+    B.key[i] = ((uint32_t)d << 16) | (uint32_t)i;
+  }
+  __threadfence_block();
+  md_refresh_all_groups(B);
+}
+
+// One node, one wave.  slice/slice_bytes: this wave's LDS.
+__device__ void md_node(const FpMesh& M, int t, char* slice, long long slice_bytes) {
+  const int m = M.nsize[t];
+  const int pos0 = M.nbegin[t];
+  int* V = M.gbuf + pos0;  // becomes the sorted vertex list
+  if (m == 0) return;
+  if (m > FP_MD_MAXM) {
+    // beyond 16-bit local ids: keep id order (flagged as unsupported)
+    if (lane_id() == 0) atomicOr(&M.ctl->err, FP_E_SCRATCH);
+    for (int i = lane_id(); i < m; i += 64) {
+      M.vperm[pos0 + i] = V[i];
+      M.viperm[V[i]] = pos0 + i;
+    }
+    return;
+  }
+  // 1. sort ids (LDS when it fits, else in a pool buffer)
+  int np2 = 1;
+  while (np2 < m) np2 <<= 1;
+  if (4ll * np2 <= slice_bytes) {
+    int* a = (int*)slice;
+    for (int i = lane_id(); i < m; i += 64) a[i] = V[i];
+    __threadfence_block();
+    wave_sort_ids(a, m, np2);
+    for (int i = lane_id(); i < m; i += 64) V[i] = a[i];
+  } else {
+    int* a = (int*)pool_alloc(M, np2);
+    if (!a) return;
+    for (int i = lane_id(); i < m; i += 64) a[i] = V[i];
+    __threadfence_block();
+    wave_sort_ids(a, m, np2);
+    for (int i = lane_id(); i < m; i += 64) V[i] = a[i];
+  }
+  __threadfence_block();
+  for (int i = lane_id(); i < m; i += 64) M.lidx[V[i]] = i;
+  __threadfence_block();
+
+  const int mbit = md_bit_max(slice_bytes);
+  if (m <= mbit) {
+    MdBit B;
+    md_bit_carve(B, slice, m);
+    md_bit_build(M, B, t, V);
+    md_bit_run(M, B, V, pos0, m);
+    return;
+  }
+  // SPARSE when the rows fit with a useful capacity
+  int C = 0;
+  {
+    const long long fixed = md_sp_bytes(m, 0) + 16;
+    C = (int)min(64ll, (slice_bytes - fixed) / (2ll * m));
+  }
+  bool sparse_ok = C >= 6;
+  MdSp S;
+  if (sparse_ok) {
+    md_sp_carve(S, slice, m, C);
+    int over = 0;
+    for (int g = lane_id(); g < 2 * S.G; g += 64) S.dl[g] = 0;
+    for (int i = lane_id(); i < m; i += 64) {
+      const int v = V[i];
+      uint16_t* ri = S.rows + (long long)i * C;
+      int len = 0;
+      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+        const int u = M.gci[e];
+        if (M.node_of[u] != t) continue;
+        const int j = M.lidx[u];
+        if (j == i) continue;
+        bool dup = false;
+        for (int q = 0; q < len && q < C; q++) dup |= (ri[q] == j);
+        if (dup) continue;
+        if (len < C) ri[len] = (uint16_t)j;
+        len++;
+      }
+      if (len > C) over = 1;
+      S.len[i] = (uint16_t)min(len, C);
+      S.key[i] = ((uint32_t)len << 16) | (uint32_t)i;
+    }
+    __threadfence_block();
+    sparse_ok = !ballot64(over);
+  }
+  int done = 0;           // vertices already ordered
+  int na = m;             // vertices remaining
+  const int* vmap = V;
+  if (sparse_ok) {
+    for (int g = 0; g < S.G; g++) {
+      const int i = g * 64 + lane_id();
+      uint32_t k = i < m ? S.key[i] : FP_KEY_INF;
+      k = wave_min_u32(k);
+      if (lane_id() == 0) S.gmin[g] = k;
+    }
+    __threadfence_block();
+    while (na > 0 && na > mbit) {
+      const uint32_t km = md_argmin(S.gmin, S.G);
+      const int p = (int)(km & 0xFFFFu);
+      if (km == FP_KEY_INF || p >= m) {
+        if (lane_id() == 0) atomicOr(&M.ctl->err, FP_E_INTERNAL);
+        goto fail;
+      }
+      const int kp = S.len[p];
+      const uint16_t* rpv = S.rows + (long long)p * C;
+      // dry run: would any neighbour row overflow?
+      int over = 0;
+      for (int i = lane_id(); i < kp; i += 64) {
+        const int u = rpv[i];
+        const uint16_t* ru = S.rows + (long long)u * C;
+        const int lu = S.len[u];
+        int add = -1;  // p leaves the row
+        for (int a = 0; a < kp; a++) {
+          const int x = rpv[a];
+          if (x == u) continue;
+          bool f = false;
+          for (int q = 0; q < lu; q++) f |= (ru[q] == x);
+          add += !f;
+        }
+        if (lu + add > C) over = 1;
+      }
+      if (ballot64(over)) break;  // convert with p still present
+      if (lane_id() == 0) {
+        const int v = vmap[p];
+        M.vperm[pos0 + done] = v;
+        M.viperm[v] = pos0 + done;
+        S.key[p] = FP_KEY_INF;
+        S.dl[p >> 6] = 1;
+      }
+      for (int i = lane_id(); i < kp; i += 64) S.nbl[i] = rpv[i];
+      __threadfence_block();
+      for (int i = lane_id(); i < kp; i += 64) {
+        const int u = S.nbl[i];
+        uint16_t* ru = S.rows + (long long)u * C;
+        int lu = S.len[u];
+        for (int q = 0; q < lu; q++)
+          if (ru[q] == p) {
+            ru[q] = ru[lu - 1];
+            lu--;
+            break;
+          }
+        for (int a = 0; a < kp; a++) {
+          const int x = S.nbl[a];
+          if (x == u) continue;
+          bool f = false;
+          for (int q = 0; q < lu; q++) f |= (ru[q] == x);
+          if (!f) ru[lu++] = (uint16_t)x;
+        }
+        S.len[u] = (uint16_t)lu;
+        S.key[u] = ((uint32_t)lu << 16) | (uint32_t)u;
+        S.dl[u >> 6] = 1;
+      }
+      __threadfence_block();
+      md_refresh_dirty(S.key, S.gmin, S.dl, m, S.G);
+      done++;
+      na--;
+    }
+    if (na == 0) return;
+    // re-index the remaining vertices (rank order) into BIT form; stage the
+    // sparse state in the pool first since the BIT layout reuses the slice
+    unsigned* st = pool_alloc(M, (unsigned long long)m * C / 2 + 2ull * m + 64);
+    if (!st) goto fail;
+    {
+      const long long wrows = ((long long)m * C + 1) / 2, wlen = (m + 1) / 2;
+      uint16_t* srows = (uint16_t*)st;
+      uint16_t* slen = (uint16_t*)(st + wrows);
+      int* ni = (int*)(st + wrows + wlen);
+      for (long long i = lane_id(); i < (long long)m * C; i += 64) srows[i] = S.rows[i];
+      int run = 0;
+      for (int i0 = 0; i0 < m; i0 += 64) {
+        const int i = i0 + lane_id();
+        const bool al = i < m && S.key[i] != FP_KEY_INF;
+        if (i < m) slen[i] = S.len[i];
+        const uint64_t bal = ballot64(al);
+        if (i < m) ni[i] = al ? run + popc64(bal & lanemask_lt()) : -1;
+        run += popc64(bal);
+      }
+      __threadfence_block();
+      int* vm2 = (int*)pool_alloc(M, na);
+      if (!vm2) goto fail;
+      for (int i = lane_id(); i < m; i += 64)
+        if (ni[i] >= 0) vm2[ni[i]] = vmap[i];
+      MdBit B;
+      char* mem;
+      if (na <= mbit) {
+        mem = slice;
+      } else {
+        const long long bytes = md_bit_bytes(na);
+        mem = (char*)pool_alloc(M, (bytes + 3) / 4);
+        if (!mem) goto fail;
+      }
+      __threadfence_block();
+      md_bit_carve(B, mem, na);
+      for (long long i = lane_id(); i < (long long)na * B.W; i += 64) B.rows[i] = 0u;
+      for (int w = lane_id(); w < B.W; w += 64) {
+        const int hi = min(32, na - w * 32);
+        B.alive[w] = hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
+      }
+      for (int g = lane_id(); g < 2 * B.G; g += 64) B.dl[g] = 0;
+      __threadfence_block();
+      for (int i = lane_id(); i < m; i += 64) {
+        const int r = ni[i];
+        if (r < 0) continue;
+        uint32_t* rr = B.rows + (long long)r * B.W;
+        const int l = slen[i];
+        for (int q = 0; q < l; q++) {
+          const int x = ni[srows[(long long)i * C + q]];
+          if (x >= 0) rr[x >> 5] |= 1u << (x & 31);
+        }
+        B.key[r] = ((uint32_t)l << 16) | (uint32_t)r;
+      }
+      __threadfence_block();
+      md_refresh_all_groups(B);
+      md_bit_run(M, B, vm2, pos0 + done, na);
+      return;
+    }
+  } else {
+    // too large for LDS: BIT layout in the pool
+    const long long bytes = md_bit_bytes(m);
+    char* mem = (char*)pool_alloc(M, (bytes + 3) / 4);
+    if (!mem) goto fail;
+    MdBit B;
+    md_bit_carve(B, mem, m);
+    md_bit_build(M, B, t, V);
+    md_bit_run(M, B, V, pos0, m);
+    return;
+  }
+fail:
+  // keep perm a bijection: remaining vertices in index order
+  {
+    int run = 0;
+    for (int i0 = 0; i0 < m; i0 += 64) {
+      const int i = i0 + lane_id();
+      bool rem = false;
+      if (i < m) {
+        const int v = V[i];
+        rem = true;
+        for (int q = 0; q < done; q++) rem &= (M.vperm[pos0 + q] != v);
+      }
+      const uint64_t bal = ballot64(rem);
+      if (rem) {
+        const int pos = pos0 + done + run + popc64(bal & lanemask_lt());
+        M.vperm[pos] = V[i];
+        M.viperm[V[i]] = pos;
+      }
+      run += popc64(bal);
+    }
+  }
+}
+
+// size class of a node: 0 = whole LDS, 1 = half, 2 = quarter, 3 = eighth
+__device__ __forceinline__ int md_class(int m, long long slice) {
+  if (m <= md_bit_max(slice / 8)) return 3;
+  if (m <= md_bit_max(slice / 4)) return 2;
+  if (m <= md_bit_max(slice / 2)) return 1;
+  return 0;
+}
+
+// Local orders of all nodes.  Each workgroup serves the classes from the
+// largest slice down; inside a class every participating wave pops nodes.
+__device__ void stage_local_orders(const Team& T, const FpMesh& M, char* lds) {
+  FpCtl* C = M.ctl;
+  const int nn = C->nn;
+  if (T.gtid() < 8) {
+    C->task_cnt[T.gtid()] = 0;
+    C->task_pop[T.gtid()] = 0;
+  }
+  T.sync();
+  for (int x = T.gtid(); x < nn; x += T.gsize()) {
+    const int m = M.nsize[x];
+    if (m == 0) continue;
+    const int c = md_class(m, M.lds_bytes);
+    M.tasks[c * M.NNcap + atomicAdd(&C->task_cnt[c], 1)] = x;
+  }
+  T.sync();
+  for (int c = 0; c < 4; c++) {
+    const int nsl = 1 << c;
+    const long long sb = (M.lds_bytes / nsl) & ~15ll;
+    const int cnt = C->task_cnt[c];
+    if (wave_id() < nsl) {
+      char* slice = lds + sb * wave_id();
+      while (true) {
+        int k = 0;
+        if (lane_id() == 0) k = atomicAdd(&C->task_pop[c], 1);
+        k = __shfl(k, 0, 64);
+        if (k >= cnt) break;
+        md_node(M, M.tasks[c * M.NNcap + k], slice, sb);
+      }
+    }
+    __syncthreads();
+  }
+  T.sync();
+}

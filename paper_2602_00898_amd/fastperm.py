@@ -1,0 +1,168 @@
+"""Python binding of libfastperm.so (argument marshalling only).
+
+Every step of the ordering runs in the HIP library; this module converts
+torch device tensors to raw pointers, sizes the workspace through fp_query
+and passes torch's current HIP stream.  It raises if the library is missing:
+there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+from .build import LIB
+
+SCHED_LEVEL = 0
+SCHED_POST = 1
+
+STATUS = {0: "ok", 1: "invalid argument", 2: "pattern not symmetric", 3: "index out of range",
+          4: "workspace or device pool too small", 5: "out of device memory",
+          6: "unsupported option", 7: "server busy", 8: "HIP runtime error",
+          9: "device pipeline failure"}
+
+
+class FpError(RuntimeError):
+    def __init__(self, code, what):
+        super().__init__(f"{what}: {STATUS.get(code, code)} (fp_status {code})")
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("patch_size", C.c_int32), ("nd_level", C.c_int32), ("schedule", C.c_int32),
+                ("block_size", C.c_int32), ("lloyd_iters", C.c_int32), ("seed", C.c_uint64),
+                ("flags", C.c_uint32)]
+
+
+class Csr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr32", C.c_void_p),
+                ("rowptr64", C.c_void_p), ("colind", C.c_void_p)]
+
+
+class Result(C.Structure):
+    _fields_ = [("perm", C.c_void_p), ("iperm", C.c_void_p), ("parent", C.c_void_p),
+                ("colcount", C.c_void_p), ("nnzL", C.c_void_p), ("node_begin", C.c_void_p),
+                ("node_size", C.c_void_p), ("gmap", C.c_void_p), ("n_nodes", C.c_void_p),
+                ("status", C.c_void_p), ("max_nodes", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libfastperm.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise ImportError(f"{LIB} is missing: build it with paper_2602_00898_amd.build.build()")
+        L = C.CDLL(LIB)
+        vp = C.c_void_p
+        L.fp_version.restype = C.c_int
+        L.fp_status_str.restype = C.c_char_p
+        L.fp_status_str.argtypes = [C.c_int]
+        L.fp_options_default.argtypes = [C.POINTER(Options)]
+        L.fp_options_default.restype = None
+        L.fp_create.argtypes = [C.POINTER(vp)]
+        L.fp_destroy.argtypes = [vp]
+        L.fp_query.argtypes = [vp, C.POINTER(Csr), C.POINTER(Options), C.POINTER(C.c_size_t),
+                               C.POINTER(C.c_int32)]
+        L.fp_order.argtypes = [vp, C.POINTER(Csr), vp, C.POINTER(Options), vp, C.c_size_t,
+                               C.POINTER(Result), vp]
+        L.fp_last_error.argtypes = [vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise FpError(rc, what)
+
+
+class Handle:
+    """fp_handle bound to the current device, with a reusable workspace."""
+
+    def __init__(self):
+        h = C.c_void_p()
+        _check(lib().fp_create(C.byref(h)), "fp_create")
+        self.h = h
+        self._ws = None
+
+    def __del__(self):
+        if getattr(self, "h", None) is not None and _lib is not None:
+            _lib.fp_destroy(self.h)
+            self.h = None
+
+    def workspace(self, nbytes, device):
+        if self._ws is None or self._ws.numel() < nbytes or self._ws.device != device:
+            self._ws = torch.empty(int(nbytes), dtype=torch.uint8, device=device)
+        return self._ws
+
+
+def options(patch_size=512, schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, seed=0):
+    o = Options()
+    lib().fp_options_default(C.byref(o))
+    o.patch_size = patch_size
+    o.schedule = schedule
+    o.block_size = block_size
+    o.lloyd_iters = lloyd_iters
+    o.seed = seed & 0xFFFFFFFFFFFFFFFF
+    return o
+
+
+def make_csr(n, rowptr, colind):
+    c = Csr()
+    c.n = n
+    c.nnz = int(colind.numel())
+    if rowptr.dtype == torch.int32:
+        c.rowptr32 = rowptr.data_ptr()
+    else:
+        c.rowptr64 = rowptr.data_ptr()
+    c.colind = colind.data_ptr() if colind.numel() else None
+    return c
+
+
+def query(handle, n, rowptr, colind, opts):
+    A = make_csr(n, rowptr, colind)
+    ws = C.c_size_t()
+    mx = C.c_int32()
+    _check(lib().fp_query(handle.h, C.byref(A), C.byref(opts), C.byref(ws), C.byref(mx)),
+           "fp_query")
+    return ws.value, mx.value
+
+
+def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size=1,
+          lloyd_iters=1, seed=0, user_gmap=None, handle=None, out=None, stream=None,
+          check=True):
+    """Order one matrix on the GPU.  rowptr (int32/int64) and colind (int32)
+    are device tensors.  Returns a dict of device tensors; with check=True
+    the call synchronises and raises on device-reported errors."""
+    dev = colind.device if colind.numel() else rowptr.device
+    handle = handle or Handle()
+    opts = options(patch_size, schedule, block_size, lloyd_iters, seed)
+    A = make_csr(n, rowptr, colind)
+    ws_bytes, max_nodes = query(handle, n, rowptr, colind, opts)
+    ws = handle.workspace(ws_bytes, dev)
+    if out is None:
+        i32 = dict(dtype=torch.int32, device=dev)
+        out = dict(perm=torch.empty(n, **i32), iperm=torch.empty(n, **i32),
+                   parent=torch.empty(n, **i32), colcount=torch.empty(n, **i32),
+                   nnzL=torch.zeros(1, dtype=torch.int64, device=dev),
+                   node_begin=torch.empty(max_nodes, **i32), node_size=torch.empty(max_nodes, **i32),
+                   gmap=torch.empty(max(n // block_size, 1), **i32),
+                   n_nodes=torch.zeros(1, **i32), status=torch.zeros(1, dtype=torch.int32, device=dev))
+    R = Result(_ptr(out["perm"]), _ptr(out["iperm"]), _ptr(out["parent"]), _ptr(out["colcount"]),
+               _ptr(out["nnzL"]), _ptr(out.get("node_begin")), _ptr(out.get("node_size")),
+               _ptr(out.get("gmap")), _ptr(out.get("n_nodes")), _ptr(out.get("status")),
+               int(out["node_begin"].numel()) if out.get("node_begin") is not None else 0)
+    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    _check(lib().fp_order(handle.h, C.byref(A), _ptr(user_gmap), C.byref(opts), _ptr(ws),
+                          ws_bytes, C.byref(R), C.c_void_p(s)), "fp_order")
+    if check:
+        _check(lib().fp_last_error(handle.h, _ptr(ws), C.c_void_p(s)), "device")
+    return out

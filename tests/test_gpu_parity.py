@@ -1,0 +1,101 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, bit-exact.
+
+Every output of the ordering is integer, so every comparison is exact:
+patches (gmap), separator-tree ranges, perm, iperm, elimination tree,
+column counts and nnz(L).
+"""
+
+import numpy as np
+import pytest
+
+from tests.gpu_util import compare, cpu_order, gpu_order, mesh, say
+
+from paper_2602_00898_amd import meshgen as mg
+
+pytestmark = pytest.mark.gpu
+
+
+def check(A, label, **kw):
+    say(f"[parity] {label} n={A.n} nnz={A.nnz} {kw}")
+    g = gpu_order(A, **kw)
+    c = cpu_order(A, **kw)
+    compare(g, c, label)
+    return g
+
+
+def test_tiny_planar_64x64_S64():
+    """64x64 planar grid, seeded diagonals, S = 64 (the tiny configuration)."""
+    check(mesh(64, 64, False, 1), "C1", patch_size=64, seed=1)
+
+
+@pytest.mark.parametrize("H,W,torus,seed,flip,S", [
+    (8, 8, False, 3, 0.0, 5),
+    (16, 16, True, 4, 0.0, 16),
+    (33, 17, False, 5, 0.05, 32),
+    (40, 40, True, 6, 0.05, 50),
+    (96, 80, True, 7, 0.05, 128),
+    (128, 128, False, 8, 0.0, 256),
+])
+def test_small_meshes(H, W, torus, seed, flip, S):
+    check(mesh(H, W, torus, seed, flip), f"{H}x{W}", patch_size=S, seed=seed)
+
+
+@pytest.mark.parametrize("sched", [0, 1])
+def test_schedules(sched):
+    check(mesh(48, 48, True, 9, 0.05), f"sched{sched}", patch_size=40, seed=9, schedule=sched)
+
+
+def test_lloyd_zero_and_two():
+    A = mesh(50, 30, False, 10)
+    check(A, "lloyd0", patch_size=30, seed=10, lloyd_iters=0)
+    check(A, "lloyd2", patch_size=30, seed=10, lloyd_iters=2)
+
+
+def test_block3_int64_rowptr():
+    A = mg.block_expand(mesh(24, 24, True, 11), 3)
+    check(A, "block3", patch_size=40, seed=11, block_size=3, rowptr64=True)
+
+
+def test_user_gmap():
+    A = mesh(30, 30, False, 12)
+    rng = np.random.default_rng(0)
+    g = (np.arange(A.n) // 37).astype(np.int32)
+    check(A, "user_gmap_blocks", patch_size=64, user_gmap=g)
+    g2 = rng.integers(0, 11, size=A.n).astype(np.int32)  # disconnected groups
+    check(A, "user_gmap_random", patch_size=64, user_gmap=g2)
+
+
+def test_disconnected_and_isolated():
+    # two meshes side by side plus isolated vertices: orphan patches
+    A = mesh(12, 12, False, 13)
+    B = mesh(9, 9, True, 14)
+    n = A.n + B.n + 5
+    rp = np.concatenate([A.rowptr[:-1], A.nnz + B.rowptr[:-1],
+                         A.nnz + B.nnz + np.arange(6)]).astype(np.int32)
+    ci = np.concatenate([A.colind, B.colind + A.n, A.n + B.n + np.arange(5)]).astype(np.int32)
+    C = mg.CSR(n, rp, ci)
+    check(C, "disconnected", patch_size=200, seed=2)
+
+
+def test_degenerate_sizes():
+    one = mg.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32))
+    check(one, "n=1", patch_size=4)
+    pair = mg.CSR(2, np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32))
+    check(pair, "n=2 no diagonal", patch_size=1)
+    A = mesh(20, 20, True, 15)
+    check(A, "single patch", patch_size=10 ** 6, seed=1)
+    check(mesh(12, 12, False, 16), "S=1", patch_size=1, seed=1)
+
+
+def test_determinism():
+    A = mesh(64, 64, True, 17, 0.05)
+    a = gpu_order(A, patch_size=64, seed=3)
+    b = gpu_order(A, patch_size=64, seed=3)
+    for k in ("perm", "parent", "colcount", "gmap", "node_begin"):
+        assert np.array_equal(a[k], b[k])
+
+
+@pytest.mark.slow
+def test_torus_1024_S512_full_parity():
+    """1024x1024 torus, seeded diagonals, S = 512: the benchmark workload."""
+    check(mesh(1024, 1024, True, 2), "C2", patch_size=512, seed=2)
