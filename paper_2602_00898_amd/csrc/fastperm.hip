@@ -1,11 +1,13 @@
-// fastperm.hip -- the persistent gfx950 ordering kernel and the C ABI
-// declared in include/fastperm.h.
+// fastperm.hip -- gfx950 kernels of the patch-guided nested-dissection
+// ordering and the C ABI declared in include/fastperm.h.
 //
-// One launch orders one matrix: a team made of every workgroup of the grid
-// (one 512-thread workgroup per CU, 160 KiB LDS each) runs the stages in
-// sequence, separated by team barriers:
-//   ingest -> patches -> quotient graph -> separator tree -> grouping ->
-//   local orders -> elimination tree / column counts -> block expansion.
+// Stages (one or a few kernels each, in stream order):
+//   ingest -> patches (seeds, frontier growth, Lloyd) -> quotient graph ->
+//   separator tree (per level: arc recount, bisection, separator marking) ->
+//   grouping in schedule order -> local minimum-degree orders ->
+//   elimination tree / column counts (per level) -> block expansion.
+// The job description lives in the workspace and is read through a pointer;
+// the host reads a few scalars between stages (patch count, frontier sizes).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -14,38 +16,539 @@
 #include <new>
 
 #include "../../include/fastperm.h"
-#include "fp_pipeline.h"
 #include "fp_plan.h"
+#include "fp_stages_sym.h"
 
-__global__ void __launch_bounds__(FP_WG) fp_plain_kernel(FpMesh M) {
-  extern __shared__ __align__(16) char lds[];
-  __shared__ int lds_tmp[FP_WAVES + 8];
-  Team T{(int)blockIdx.x, (int)gridDim.x, M.ctl->bar, &M.ctl->err};
-  pipeline(T, M, lds, lds_tmp);
-  T.sync();
-  if (T.gtid() == 0 && M.status_out) *M.status_out = M.ctl->err;
+#define MESH                  \
+  const FpMesh& M = *Mp;      \
+  FpCtl* C = M.ctl;           \
+  (void)C
+
+// ==========================================================================
+// generic helpers
+// ==========================================================================
+__global__ void k_fill(int* a, int n, int v) {
+  for (int i = gtid(); i < n; i += gsize()) a[i] = v;
+}
+__global__ void k_copy(int* dst, const int* src, int n) {
+  for (int i = gtid(); i < n; i += gsize()) dst[i] = src[i];
+}
+__global__ void k_set(int* a, const int* v) {
+  if (gtid() == 0) *a = *v;
 }
 
-__global__ void fp_ctl_init(unsigned* ctl, int words) {
-  for (int i = threadIdx.x + blockIdx.x * blockDim.x; i < words; i += blockDim.x * gridDim.x)
-    ctl[i] = 0u;
+// exclusive scan, three passes: chunk sums, scan of the sums, chunk scans
+__global__ void k_scan_part(const int* in, int n, int chunk, int* part) {
+  __shared__ int tmp[FP_WAVES + 2];
+  const int lo = min(n, (int)blockIdx.x * chunk), hi = min(n, lo + chunk);
+  int s = 0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += FP_WG) s += in[i];
+  int tot;
+  wg_excl_scan(s, tmp, &tot);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+__global__ void k_scan_top(int* part, int np, int* total) {
+  __shared__ int tmp[FP_WAVES + 2];
+  int base = 0;
+  for (int c0 = 0; c0 < np; c0 += FP_WG) {
+    const int i = c0 + (int)threadIdx.x;
+    const int x = i < np ? part[i] : 0;
+    int tt;
+    const int ex = wg_excl_scan(x, tmp, &tt);
+    if (i < np) part[i] = base + ex;
+    base += tt;
+  }
+  if (threadIdx.x == 0) *total = base;
+}
+__global__ void k_scan_apply(const int* in, int* out, int n, int chunk, const int* part) {
+  __shared__ int tmp[FP_WAVES + 2];
+  const int lo = min(n, (int)blockIdx.x * chunk), hi = min(n, lo + chunk);
+  int base = part[blockIdx.x];
+  for (int t0 = lo; t0 < hi; t0 += FP_WG) {
+    const int i = t0 + (int)threadIdx.x;
+    const int x = i < hi ? in[i] : 0;
+    int tt;
+    const int ex = wg_excl_scan(x, tmp, &tt);
+    if (i < hi) out[i] = base + ex;
+    base += tt;
+  }
 }
 
-// --------------------------------------------------------------------------
+// ==========================================================================
+// ingest: graph of A without its diagonal (Sec. 4.1 Step 2, Sec. 6.5)
+// ==========================================================================
+__global__ void k_ingest(const FpMesh* __restrict__ Mp, int fill) {
+  MESH;
+  unsigned eb = 0;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    if (fill)
+      gather_vertex_row(M, v, M.gci + M.grp[v], &eb);
+    else
+      M.pcnt[v] = gather_vertex_row(M, v, nullptr, &eb);
+  }
+  if (eb) atomicOr(&C->err, eb);
+}
+
+// ==========================================================================
+// patches (Sec. 4.1 Step 1; Lloyd's algorithm, Sec. 6).  Growth computes,
+// for every vertex, (hop distance to the nearest seed, id of the nearest
+// seed with ties to the lowest id) as the fixed point of 64-bit keys
+// (dist << 32 | id), one level per launch, atomicMin on the keys.
+// ==========================================================================
+__global__ void k_seeds(const FpMesh* __restrict__ Mp, int P0) {
+  MESH;
+  const int n = M.n, S = M.S;
+  for (int blk = gwave(); blk < P0; blk += nwaves()) {
+    const long long lo = (long long)blk * S, hi = min((long long)n, lo + S);
+    uint64_t bh = FP_UNSET;
+    uint32_t bv = 0xFFFFFFFFu;
+    for (long long v = lo + lane_id(); v < hi; v += 64) {
+      const uint64_t h = fp_mix64(M.seed, (uint64_t)v);
+      if (h < bh) {
+        bh = h;
+        bv = (uint32_t)v;
+      }
+    }
+    const uint64_t hm = wave_min_u64(bh);
+    const uint32_t vm = wave_min_u32(bh == hm ? bv : 0xFFFFFFFFu);
+    if (lane_id() == 0) M.seeds[blk] = (int)vm;
+  }
+}
+__global__ void k_key_unset(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) M.key[v] = FP_UNSET;
+  for (int i = gtid(); i < M.n + 16; i += gsize()) M.fcnt[i] = 0;
+}
+__global__ void k_seed_push(const FpMesh* __restrict__ Mp, int nseeds) {
+  MESH;
+  for (int k = gtid(); k < nseeds; k += gsize()) {
+    const int s = M.seeds[k];
+    atomicMin(&M.key[s], (unsigned long long)k);
+    M.fa[k] = s;
+  }
+  if (gtid() == 0) M.fcnt[0] = nseeds;
+}
+__global__ void k_bfs_level(const FpMesh* __restrict__ Mp, int lvl) {
+  MESH;
+  const int nf = M.fcnt[lvl];
+  const int* cur = (lvl & 1) ? M.fb : M.fa;
+  int* nxt = (lvl & 1) ? M.fa : M.fb;
+  for (int f = gtid(); f < nf; f += gsize()) {
+    const int v = cur[f];
+    const unsigned long long kv = M.key[v] + (1ull << 32);
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+      const int u = M.gci[e];
+      if (M.key[u] <= kv) continue;
+      const unsigned long long old = atomicMin(&M.key[u], kv);
+      if (old == FP_UNSET) nxt[atomicAdd(&M.fcnt[lvl + 1], 1)] = u;
+    }
+  }
+}
+__global__ void k_count_unset(const FpMesh* __restrict__ Mp) {
+  MESH;
+  int cnt = 0;
+  for (int v = gtid(); v < M.n; v += gsize()) cnt += (M.key[v] == FP_UNSET);
+  cnt = wave_sum_i32(cnt);
+  if (lane_id() == 0 && cnt) atomicAdd(&C->norphan, cnt);
+}
+// components without a seed: min-label fixed point, then ids P0 + rank of
+// the component's lowest vertex
+__global__ void k_cc_init(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) M.fb[v] = (M.key[v] == FP_UNSET) ? v : -1;
+}
+__global__ void k_cc_hook(const FpMesh* __restrict__ Mp) {
+  MESH;
+  int* comp = M.fb;
+  int ch = 0;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    const int cv = comp[v];
+    if (cv < 0) continue;
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+      const int cu = comp[M.gci[e]];
+      if (cu >= 0 && cu < cv) {
+        atomicMin(&comp[cv], cu);  // hook the larger label under the smaller
+        atomicMin(&comp[v], cu);
+        ch = 1;
+      }
+    }
+  }
+  if (ch) atomicOr((unsigned*)&C->chg, 1u);
+}
+__global__ void k_cc_jump(const FpMesh* __restrict__ Mp) {
+  MESH;
+  int* comp = M.fb;
+  int ch = 0;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    if (comp[v] < 0) continue;
+    int c = comp[v];
+    while (comp[c] != c) c = comp[c];
+    if (c != comp[v]) {
+      comp[v] = c;
+      ch = 1;
+    }
+  }
+  if (ch) atomicOr((unsigned*)&C->chg, 1u);
+}
+__global__ void k_cc_flags(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) M.pcnt[v] = (M.fb[v] == v) ? 1 : 0;
+}
+__global__ void k_cc_label(const FpMesh* __restrict__ Mp, int P0) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    const int c = M.fb[v];
+    if (c < 0) continue;
+    const int id = P0 + M.pcnt[c];
+    M.key[v] = (unsigned long long)id;
+    if (c == v) M.seeds[id] = v;
+  }
+}
+// Lloyd re-centre: new seed = vertex farthest from the patch boundary (the
+// distance inside the patch equals the distance to the boundary set of the
+// whole graph, because any path out of a patch passes its own boundary
+// first), ties to the lowest id; patches without a boundary keep their seed.
+__global__ void k_lloyd_gmap(const FpMesh* __restrict__ Mp, int P) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) M.gmap[v] = (int)(M.key[v] & 0xFFFFFFFFu);
+  for (int p = gtid(); p < P; p += gsize()) M.best[p] = 0;
+  for (int i = gtid(); i < M.n + 16; i += gsize()) M.fcnt[i] = 0;
+}
+__global__ void k_lloyd_bnd(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    const int g = M.gmap[v];
+    bool isb = false;
+    for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
+    M.key[v] = isb ? 0ull : FP_UNSET;
+    if (isb) M.fa[atomicAdd(&M.fcnt[0], 1)] = v;
+  }
+}
+__global__ void k_lloyd_best(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    const unsigned long long k = M.key[v];
+    if (k == FP_UNSET) continue;
+    const unsigned long long cand =
+        ((k >> 32) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)v) | (1ull << 63);
+    atomicMax(&M.best[M.gmap[v]], cand);
+  }
+}
+__global__ void k_lloyd_seed(const FpMesh* __restrict__ Mp, int P) {
+  MESH;
+  for (int p = gtid(); p < P; p += gsize()) {
+    const unsigned long long bb = M.best[p];
+    if (bb) M.seeds[p] = (int)(0xFFFFFFFFu - (unsigned)(bb & 0xFFFFFFFFu));
+  }
+}
+__global__ void k_gmap_final(const FpMesh* __restrict__ Mp, int P) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    const unsigned long long k = M.key[v];
+    const int g = k == FP_UNSET ? -1 : (int)(k & 0xFFFFFFFFu);
+    if (g < 0 || g >= P) atomicOr(&C->err, FP_E_INTERNAL);
+    M.gmap[v] = (g < 0 || g >= P) ? 0 : g;
+  }
+  if (gtid() == 0) C->P = P;
+}
+__global__ void k_user_gmap(const FpMesh* __restrict__ Mp) {
+  MESH;
+  int mx = 0;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    int g = M.user_gmap[v];
+    if (g < 0 || g >= M.n) {
+      atomicOr(&C->err, FP_E_GMAP);
+      g = 0;
+    }
+    M.gmap[v] = g;
+    mx = max(mx, g + 1);
+  }
+  mx = (int)wave_max_u32((uint32_t)mx);
+  if (lane_id() == 0 && mx > 0) atomicMax(&C->P, mx);
+}
+
+// ==========================================================================
+// patch members, boundary list, quotient graph (Sec. 2; built once, Sec. 5)
+// ==========================================================================
+__global__ void k_patch_count(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    const int g = M.gmap[v];
+    atomicAdd(&M.pcnt[g], 1);
+    bool isb = false;
+    for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
+    if (isb) M.bnd[atomicAdd(&C->nbnd, 1)] = v;
+  }
+}
+__global__ void k_patch_scatter(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) M.pvtx[atomicAdd(&M.pcnt[M.gmap[v]], 1)] = v;
+}
+// distinct neighbour patches of patch p, ascending, by repeated wave-wide
+// minimum over the foreign neighbours of its members
+__global__ void k_qrow(const FpMesh* __restrict__ Mp, int P, int fill) {
+  MESH;
+  for (int p = gwave(); p < P; p += nwaves()) {
+    const int a0 = M.pptr[p], a1 = M.pptr[p + 1];
+    int last = -1, cnt = 0;
+    int* out = fill ? M.qci + M.qptr[p] : nullptr;
+    while (true) {
+      uint32_t m = 0xFFFFFFFFu;
+      for (int i = a0 + lane_id(); i < a1; i += 64) {
+        const int v = M.pvtx[i];
+        for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+          const int q = M.gmap[M.gci[e]];
+          if (q != p && q > last && (uint32_t)q < m) m = (uint32_t)q;
+        }
+      }
+      m = wave_min_u32(m);
+      if (m == 0xFFFFFFFFu) break;
+      if (out && lane_id() == 0) out[cnt] = (int)m;
+      cnt++;
+      last = (int)m;
+    }
+    if (!fill && lane_id() == 0) M.pcnt[p] = cnt;
+  }
+}
+
+// ==========================================================================
+// separator tree (Sec. 4.2 Step 3; Alg. 2; Sec. 5).  Level d: recount the
+// alive quotient arcs from the boundary list, bisect every node of depth d,
+// SuperSeparator (unmarked vertices with an unmarked neighbour across) and
+// RefineSeparator (keep the smaller side, ties to the left).
+// ==========================================================================
+__global__ void k_sep_init(const FpMesh* __restrict__ Mp, int P, int D, int nn) {
+  MESH;
+  if (gtid() == 0) {
+    C->D = D;
+    C->nn = nn;
+  }
+  for (int v = gtid(); v < M.n; v += gsize()) M.node_of[v] = -1;
+  for (int p = gtid(); p < P; p += gsize()) {
+    M.pnode[p] = 0;
+    M.plist[p] = p;
+  }
+  for (int x = gtid(); x < nn; x += gsize()) {
+    M.cntL[x] = 0;
+    M.cntR[x] = 0;
+    M.segN[x] = 0;
+    M.segS[x] = 0;
+  }
+  if (gtid() == 0) M.segN[0] = P;
+}
+__global__ void k_arcs(const FpMesh* __restrict__ Mp) {
+  MESH;
+  const int nb = C->nbnd;
+  for (int i = gtid(); i < nb; i += gsize()) {
+    const int v = M.bnd[i];
+    if (M.node_of[v] != -1) continue;
+    const int gv = M.gmap[v];
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+      const int u = M.gci[e];
+      if (M.node_of[u] != -1) continue;
+      const int gu = M.gmap[u];
+      if (gu == gv) continue;
+      const int a = arc_index(M, gv, gu);
+      if (a >= 0) atomicAdd(&M.qcnt[a], 1);
+    }
+  }
+}
+__global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  __shared__ BisectLds sh;
+  const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
+  for (int t = lo + (int)blockIdx.x; t < hi; t += (int)gridDim.x) {
+    const int m = M.segN[t];
+    if (m >= 2) wg_bisect(M, t, M.segS[t], m, &sh);
+  }
+}
+__global__ void k_cand(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  const int hi = (1 << (d + 1)) - 1;
+  const int nb = C->nbnd;
+  for (int i = gtid(); i < nb; i += gsize()) {
+    const int v = M.bnd[i];
+    M.cand[i] = 0;
+    if (M.node_of[v] != -1) continue;
+    const int c = M.pnode[M.gmap[v]];
+    if (c < hi) continue;  // patch not split at this level
+    const int sib = (c & 1) ? c + 1 : c - 1;
+    bool is = false;
+    for (int e = M.grp[v]; e < M.grp[v + 1] && !is; e++) {
+      const int u = M.gci[e];
+      is = (M.node_of[u] == -1 && M.pnode[M.gmap[u]] == sib);
+    }
+    if (is) {
+      M.cand[i] = 1;
+      atomicAdd((c & 1) ? &M.cntL[(c - 1) >> 1] : &M.cntR[(c - 1) >> 1], 1);
+    }
+  }
+}
+__global__ void k_mark(const FpMesh* __restrict__ Mp) {
+  MESH;
+  const int nb = C->nbnd;
+  for (int i = gtid(); i < nb; i += gsize()) {
+    if (!M.cand[i]) continue;
+    const int v = M.bnd[i];
+    const int c = M.pnode[M.gmap[v]];
+    const int t = (c - 1) >> 1;
+    const bool left = c & 1;
+    const bool mark_left = M.cntL[t] <= M.cntR[t];
+    if (left == mark_left) {
+      M.node_of[v] = t;
+      atomicSub(&M.wp[M.gmap[v]], 1);
+    }
+  }
+}
+// leaves keep the remaining vertices of their patch
+__global__ void k_leaves(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize())
+    if (M.node_of[v] == -1) M.node_of[v] = M.pnode[M.gmap[v]];
+}
+
+// ==========================================================================
+// grouping in schedule order (Alg. 3)
+// ==========================================================================
+__global__ void k_nsize(const FpMesh* __restrict__ Mp, int nn) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) {
+    if ((unsigned)M.node_of[v] >= (unsigned)nn) {  // never expected
+      atomicOr(&C->err, FP_E_INTERNAL);
+      M.node_of[v] = 0;
+    }
+    atomicAdd(&M.nsize[M.node_of[v]], 1);
+  }
+}
+__global__ void k_sched_place(const FpMesh* __restrict__ Mp, int nn, int D) {
+  MESH;
+  for (int x = gtid(); x < nn; x += gsize()) M.sbuf[sched_pos(x, D, M.sched)] = M.nsize[x];
+}
+__global__ void k_nbegin(const FpMesh* __restrict__ Mp, int nn, int D) {
+  MESH;
+  for (int x = gtid(); x < nn; x += gsize()) {
+    const int b = M.sbuf[sched_pos(x, D, M.sched)];
+    M.nbegin[x] = b;
+    M.ncur[x] = b;
+  }
+}
+__global__ void k_scatter(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v = gtid(); v < M.n; v += gsize()) M.gbuf[atomicAdd(&M.ncur[M.node_of[v]], 1)] = v;
+}
+
+// ==========================================================================
+// local orders (Sec. 4.3 Step 4): one wave per node, LDS slice per wave
+// ==========================================================================
+__global__ void k_md_tasks(const FpMesh* __restrict__ Mp, int nn) {
+  MESH;
+  for (int x = gtid(); x < nn; x += gsize()) {
+    const int m = M.nsize[x];
+    if (m == 0) continue;
+    const int c = md_class(m, M.lds_bytes);
+    M.tasks[c * M.NNcap + atomicAdd(&C->task_cnt[c], 1)] = x;
+  }
+}
+__global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int c) {
+  MESH;
+  FP_LDS_DECL;
+  const int nsl = 1 << c;
+  const long long sb = (M.lds_bytes / nsl) & ~15ll;
+  const int cnt = C->task_cnt[c];
+  if (wave_id() >= nsl) return;
+  char* slice = fp_lds + sb * wave_id();
+  while (true) {
+    int k = 0;
+    if (lane_id() == 0) k = atomicAdd(&C->task_pop[c], 1);
+    k = __shfl(k, 0, 64);
+    if (k >= cnt) break;
+    md_node(M, M.tasks[c * M.NNcap + k], slice, sb);
+  }
+}
+
+// ==========================================================================
+// elimination tree and column counts, bottom-up over the tree levels
+// ==========================================================================
+__global__ void k_sym_level_init(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  if (gtid() == 0) {
+    C->arena_top[d & 1] = 0;
+    C->task_pop[0] = 0;
+    C->task_pop[1] = 0;
+  }
+}
+__global__ void __launch_bounds__(FP_WG) k_sym(const FpMesh* __restrict__ Mp, int d, int big) {
+  MESH;
+  FP_LDS_DECL;
+  const int nsl = big ? 1 : FP_WAVES;
+  const long long sb = (M.lds_bytes / nsl) & ~15ll;
+  if (wave_id() >= nsl) return;
+  char* slice = fp_lds + sb * wave_id();
+  const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
+  while (true) {
+    int k = 0;
+    if (lane_id() == 0) k = atomicAdd(&C->task_pop[big ? 0 : 1], 1);
+    k = __shfl(k, 0, 64);
+    if (k >= hi - lo) break;
+    const int t = lo + k;
+    if ((M.nsize[t] > 256) != (big != 0)) continue;
+    sym_node(M, t, d, slice, sb);
+  }
+}
+__global__ void k_nnzl(const FpMesh* __restrict__ Mp) {
+  MESH;
+  long long s = 0;
+  for (int i = gtid(); i < M.n; i += gsize()) s += M.vcc[i];
+  s = wave_sum_i64(s);
+  if (lane_id() == 0 && s) atomicAdd((unsigned long long*)&C->nnzL, (unsigned long long)s);
+}
+
+// ==========================================================================
+// block expansion and outputs (Sec. 6.5)
+// ==========================================================================
+__global__ void k_expand(const FpMesh* __restrict__ Mp, int nn) {
+  MESH;
+  const int b = M.b;
+  const long long nd = M.n_dof;
+  for (long long j = gtid(); j < nd; j += gsize()) {
+    const int k = (int)(j / b), r = (int)(j - (long long)k * b);
+    M.perm[j] = M.vperm[k] * b + r;
+    M.iperm[j] = M.viperm[k] * b + r;
+    M.colcount[j] = b * M.vcc[k] - r;
+    M.parent[j] = r < b - 1 ? (int)(j + 1) : (M.vpar[k] < 0 ? -1 : M.vpar[k] * b);
+  }
+  if (M.gmap_out)
+    for (int v = gtid(); v < M.n; v += gsize()) M.gmap_out[v] = M.gmap[v];
+  if ((M.node_begin_out || M.node_size_out) && nn <= M.max_nodes_out)
+    for (int x = gtid(); x < nn; x += gsize()) {
+      if (M.node_begin_out) M.node_begin_out[x] = M.nbegin[x] * b;
+      if (M.node_size_out) M.node_size_out[x] = M.nsize[x] * b;
+    }
+}
+__global__ void k_finish(const FpMesh* __restrict__ Mp, int nn) {
+  MESH;
+  if (gtid() != 0) return;
+  if ((M.node_begin_out || M.node_size_out) && nn > M.max_nodes_out) atomicOr(&C->err, FP_E_SCRATCH);
+  *M.nnzL = (long long)M.b * M.b * C->nnzL - (long long)M.n * M.b * (M.b - 1) / 2;
+  if (M.n_nodes_out) *M.n_nodes_out = nn;
+  if (M.status_out) *M.status_out = C->err;
+}
+
+// ==========================================================================
 // host side
-// --------------------------------------------------------------------------
+// ==========================================================================
 struct fp_handle {
   int device;
   int ncu;
   int lds_bytes;
-  int grid;
+  int* host;  // pinned: scalars read back between stages, and the job copy
 };
 
 namespace {
 
-using fpplan::Plan;
-using fpplan::make_plan;
 using fpplan::fill_mesh;
+using fpplan::make_plan;
+using fpplan::Plan;
 
 fp_status check_opts(const fp_options* o) {
   if (!o) return FP_ERR_ARG;
@@ -64,6 +567,211 @@ fp_status check_csr(const fp_csr* A, int b) {
   if (A->rowptr32 && A->nnz >= (1ll << 31)) return FP_ERR_ARG;
   if (A->n % b) return FP_ERR_ARG;
   return FP_OK;
+}
+
+fp_status map_err(unsigned e) {
+  if (e & (FP_E_INDEX | FP_E_GMAP)) return FP_ERR_INDEX;
+  if (e & FP_E_SCRATCH) return FP_ERR_SIZE;
+  if (e) return FP_ERR_DEVICE;
+  return FP_OK;
+}
+
+// one ordering job: launches in stream order, reads scalars through the
+// handle's pinned buffer
+struct Job {
+  fp_handle* h;
+  hipStream_t st;
+  FpMesh hm;         // host copy of the job description
+  const FpMesh* dm;  // device copy
+  FpCtl* ctl;
+  bool hip_failed = false;
+
+  int blocks(long long items, int per = FP_WG) const {
+    long long b = (items + per - 1) / per;
+    return (int)std::max(1ll, std::min(b, 8ll * h->ncu));
+  }
+  void check() {
+    if (hipGetLastError() != hipSuccess) hip_failed = true;
+  }
+  // read `count` ints of the control block starting at `field`
+  void read(const void* field, int count) {
+    if (hipMemcpyAsync(h->host, field, 4 * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      hip_failed = true;
+  }
+  int read1(const int* field) {
+    read(field, 1);
+    return hip_failed ? 0 : h->host[0];
+  }
+  unsigned err() {
+    read(&ctl->err, 1);
+    return hip_failed ? 0xFFFFFFFFu : (unsigned)h->host[0];
+  }
+  void scan(const int* in, int* out, int n, int* total) {
+    const int np = std::max(1, std::min(1024, (n + 4095) / 4096));
+    const int chunk = std::max(1, (n + np - 1) / np);
+    hipLaunchKernelGGL(k_scan_part, dim3(np), dim3(FP_WG), 0, st, in, n, chunk, ctl->part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(FP_WG), 0, st, ctl->part, np, total);
+    hipLaunchKernelGGL(k_scan_apply, dim3(np), dim3(FP_WG), 0, st, in, out, n, chunk, ctl->part);
+    check();
+  }
+  // frontier BFS from the level-0 frontier already in place; levels are
+  // launched in batches of 8, then the next frontier size is read back
+  void bfs() {
+    const int n = hm.n;
+    // a BFS has fewer than n levels: levels up to n+7 read counters that stay
+    // zero (the counter array holds n+16 entries)
+    for (int lvl = 0;; lvl += 8) {
+      for (int k = 0; k < 8; k++)
+        hipLaunchKernelGGL(k_bfs_level, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, lvl + k);
+      check();
+      if (lvl + 8 > n || hip_failed || read1(&hm.fcnt[lvl + 8]) == 0) break;
+    }
+  }
+  void grow(int nseeds) {
+    const int n = hm.n;
+    hipLaunchKernelGGL(k_key_unset, dim3(blocks(n)), dim3(FP_WG), 0, st, dm);
+    hipLaunchKernelGGL(k_seed_push, dim3(blocks(nseeds)), dim3(FP_WG), 0, st, dm, nseeds);
+    check();
+    bfs();
+  }
+};
+
+fp_status run_job(Job& J) {
+  const int n = J.hm.n;
+  const FpMesh* dm = J.dm;
+  hipStream_t st = J.st;
+  FpCtl* C = J.ctl;
+  auto B = [&](long long items) { return dim3(J.blocks(items)); };
+  const dim3 T(FP_WG);
+
+  // ingest
+  hipLaunchKernelGGL(k_ingest, B(n), T, 0, st, dm, 0);
+  J.scan(J.hm.pcnt, J.hm.grp, n, &C->nnz_g);
+  J.read(&C->err, 8);
+  if (J.hip_failed) return FP_ERR_HIP;
+  const unsigned e0 = (unsigned)J.h->host[0];
+  const int nnz_g = J.h->host[5];
+  if (e0) return map_err(e0);
+  if (nnz_g < 0 || nnz_g > J.hm.Ecap) return FP_ERR_SIZE;
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, st, J.hm.grp + n, &C->nnz_g);
+  hipLaunchKernelGGL(k_ingest, B(n), T, 0, st, dm, 1);
+  J.check();
+
+  // patches
+  int P = 0;
+  if (J.hm.user_gmap) {
+    hipLaunchKernelGGL(k_user_gmap, B(n), T, 0, st, dm);
+    J.check();
+    P = J.read1(&C->P);
+  } else if (n > 0) {
+    const int P0 = (int)(((long long)n + J.hm.S - 1) / J.hm.S);
+    hipLaunchKernelGGL(k_seeds, dim3(J.blocks(P0, FP_WAVES)), T, 0, st, dm, P0);
+    J.check();
+    J.grow(P0);
+    hipLaunchKernelGGL(k_count_unset, B(n), T, 0, st, dm);
+    J.check();
+    P = P0;
+    if (J.read1(&C->norphan) > 0) {
+      hipLaunchKernelGGL(k_cc_init, B(n), T, 0, st, dm);
+      for (int it = 0; it < n + 1; it++) {
+        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, &C->chg, 1, 0);
+        hipLaunchKernelGGL(k_cc_hook, B(n), T, 0, st, dm);
+        hipLaunchKernelGGL(k_cc_jump, B(n), T, 0, st, dm);
+        J.check();
+        if (J.read1(&C->chg) == 0 || J.hip_failed) break;
+      }
+      hipLaunchKernelGGL(k_cc_flags, B(n), T, 0, st, dm);
+      J.scan(J.hm.pcnt, J.hm.pcnt, n, &C->nroot);
+      hipLaunchKernelGGL(k_cc_label, B(n), T, 0, st, dm, P0);
+      J.check();
+      P = P0 + J.read1(&C->nroot);
+    }
+    for (int it = 0; it < J.hm.lloyd; it++) {
+      hipLaunchKernelGGL(k_lloyd_gmap, B(n), T, 0, st, dm, P);
+      hipLaunchKernelGGL(k_lloyd_bnd, B(n), T, 0, st, dm);
+      J.check();
+      J.bfs();
+      hipLaunchKernelGGL(k_lloyd_best, B(n), T, 0, st, dm);
+      hipLaunchKernelGGL(k_lloyd_seed, B(P), T, 0, st, dm, P);
+      J.check();
+      J.grow(P);
+    }
+    hipLaunchKernelGGL(k_gmap_final, B(n), T, 0, st, dm, P);
+    J.check();
+  }
+  if (J.hip_failed) return FP_ERR_HIP;
+  if (P < 0 || P > std::max(n, 1)) return FP_ERR_DEVICE;
+
+  // quotient graph
+  hipLaunchKernelGGL(k_fill, B(P + 1), T, 0, st, J.hm.pcnt, P + 1, 0);
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, &C->nbnd, 1, 0);
+  hipLaunchKernelGGL(k_patch_count, B(n), T, 0, st, dm);
+  hipLaunchKernelGGL(k_copy, B(P), T, 0, st, J.hm.wp, J.hm.pcnt, P);
+  J.check();
+  J.scan(J.hm.pcnt, J.hm.pptr, P, &C->tot);
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, st, J.hm.pptr + P, &C->tot);
+  hipLaunchKernelGGL(k_copy, B(P), T, 0, st, J.hm.pcnt, J.hm.pptr, P);
+  hipLaunchKernelGGL(k_patch_scatter, B(n), T, 0, st, dm);
+  hipLaunchKernelGGL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, 0, st, dm, P, 0);
+  J.check();
+  J.scan(J.hm.pcnt, J.hm.qptr, P, &C->nq);
+  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, st, J.hm.qptr + P, &C->nq);
+  const int nq = J.read1(&C->nq);
+  if (J.hip_failed) return FP_ERR_HIP;
+  if (nq < 0 || nq > J.hm.Ecap) return FP_ERR_SIZE;
+  hipLaunchKernelGGL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, 0, st, dm, P, 1);
+  J.check();
+
+  // separator tree
+  int D = 0;
+  while ((1ll << D) < P) D++;
+  const int nn = (1 << (D + 1)) - 1;
+  if (nn > J.hm.NNcap) return FP_ERR_SIZE;
+  hipLaunchKernelGGL(k_sep_init, B(std::max(n, nn)), T, 0, st, dm, P, D, nn);
+  for (int d = 0; d < D; d++) {
+    hipLaunchKernelGGL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
+    hipLaunchKernelGGL(k_arcs, B(n), T, 0, st, dm);
+    hipLaunchKernelGGL(k_bisect, dim3(std::min(1 << d, 4 * J.h->ncu)), T, 0, st, dm, d);
+    hipLaunchKernelGGL(k_cand, B(n), T, 0, st, dm, d);
+    hipLaunchKernelGGL(k_mark, B(n), T, 0, st, dm);
+    J.check();
+  }
+  hipLaunchKernelGGL(k_leaves, B(n), T, 0, st, dm);
+
+  // grouping in schedule order
+  hipLaunchKernelGGL(k_fill, B(nn), T, 0, st, J.hm.nsize, nn, 0);
+  hipLaunchKernelGGL(k_nsize, B(n), T, 0, st, dm, nn);
+  hipLaunchKernelGGL(k_sched_place, B(nn), T, 0, st, dm, nn, D);
+  J.check();
+  J.scan(J.hm.sbuf, J.hm.sbuf, nn, &C->tot);
+  hipLaunchKernelGGL(k_nbegin, B(nn), T, 0, st, dm, nn, D);
+  hipLaunchKernelGGL(k_scatter, B(n), T, 0, st, dm);
+  J.check();
+
+  // local orders
+  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
+  hipLaunchKernelGGL(k_md_tasks, B(nn), T, 0, st, dm, nn);
+  for (int c = 0; c < 3; c++)
+    hipLaunchKernelGGL(k_md, dim3(2 * J.h->ncu), T, J.h->lds_bytes, st, dm, c);
+  J.check();
+
+  // elimination tree and column counts
+  for (int d = D; d >= 0; d--) {
+    hipLaunchKernelGGL(k_sym_level_init, dim3(1), dim3(64), 0, st, dm, d);
+    hipLaunchKernelGGL(k_sym, dim3(std::min(1 << d, 2 * J.h->ncu)), T, J.h->lds_bytes, st, dm, d,
+                       1);
+    hipLaunchKernelGGL(k_sym, dim3(std::min(1 << d, 2 * J.h->ncu)), T, J.h->lds_bytes, st, dm, d,
+                       0);
+    J.check();
+  }
+  hipLaunchKernelGGL(k_nnzl, B(n), T, 0, st, dm);
+
+  // outputs
+  hipLaunchKernelGGL(k_expand, B(std::max<long long>(J.hm.n_dof, nn)), T, 0, st, dm, nn);
+  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, dm, nn);
+  J.check();
+  return J.hip_failed ? FP_ERR_HIP : FP_OK;
 }
 
 }  // namespace
@@ -104,38 +812,23 @@ fp_status fp_create(fp_handle** h) {
   *h = nullptr;
   fp_handle* H = new (std::nothrow) fp_handle();
   if (!H) return FP_ERR_OOM;
-  if (hipGetDevice(&H->device) != hipSuccess) {
+  int ncu = 0;
+  if (hipGetDevice(&H->device) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&H->host, 8192, hipHostMallocDefault) != hipSuccess) {
     delete H;
     return FP_ERR_HIP;
   }
-  int ncu = 0, maxsh = 0;
-  if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device) != hipSuccess ||
-      hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, H->device) !=
-          hipSuccess) {
-    delete H;
-    return FP_ERR_HIP;
-  }
-  H->ncu = ncu;
-  const int static_lds = (int)sizeof(int) * (FP_WAVES + 8);
-  H->lds_bytes = std::min(FP_LDS_BYTES, maxsh - static_lds - 64) & ~255;
-  if (hipFuncSetAttribute((const void*)fp_plain_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          H->lds_bytes) != hipSuccess) {
-    delete H;
-    return FP_ERR_HIP;
-  }
-  int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fp_plain_kernel, FP_WG,
-                                                   H->lds_bytes) != hipSuccess ||
-      per_cu < 1) {
-    delete H;
-    return FP_ERR_HIP;
-  }
-  H->grid = ncu * std::min(per_cu, 1);
+  H->ncu = std::max(1, ncu);
+  H->lds_bytes = FP_LDS_BYTES;
   *h = H;
   return FP_OK;
 }
 
 fp_status fp_destroy(fp_handle* h) {
+  if (!h) return FP_OK;
+  if (h->host) (void)hipHostFree(h->host);
   delete h;
   return FP_OK;
 }
@@ -165,10 +858,13 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   Plan P;
   if (!make_plan(A->n, opts->block_size, A->nnz, &P)) return FP_ERR_ARG;
   if (ws_bytes < P.total) return FP_ERR_SIZE;
-  hipStream_t st = (hipStream_t)stream;
-  FpMesh M;
+  Job J;
+  J.h = h;
+  J.st = (hipStream_t)stream;
+  FpMesh& M = J.hm;
   memset(&M, 0, sizeof(M));
-  fill_mesh(P, (char*)workspace, &M);
+  char* ws = (char*)workspace;
+  fill_mesh(P, ws, &M);
   M.rp32 = A->rowptr32;
   M.rp64 = (const long long*)A->rowptr64;
   M.ci_in = A->colind;
@@ -190,10 +886,23 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   M.status_out = out->status;
   M.max_nodes_out = out->max_nodes;
   M.lds_bytes = h->lds_bytes;
+  J.ctl = M.ctl;
+  J.dm = (const FpMesh*)(ws + P.o_mesh);
+  // control block cleared, job description copied in
   const int words = (int)(sizeof(FpCtl) / 4);
-  hipLaunchKernelGGL(fp_ctl_init, dim3(1), dim3(1024), 0, st, (unsigned*)M.ctl, words);
-  hipLaunchKernelGGL(fp_plain_kernel, dim3(h->grid), dim3(FP_WG), h->lds_bytes, st, M);
-  if (hipGetLastError() != hipSuccess) return FP_ERR_HIP;
+  hipLaunchKernelGGL(k_fill, dim3((words + FP_WG - 1) / FP_WG), dim3(FP_WG), 0, J.st, (int*)M.ctl,
+                     words, 0);
+  memcpy(h->host, &M, sizeof(M));
+  if (hipMemcpyAsync((void*)J.dm, h->host, sizeof(M), hipMemcpyHostToDevice, J.st) != hipSuccess ||
+      hipStreamSynchronize(J.st) != hipSuccess)
+    return FP_ERR_HIP;
+  s = run_job(J);
+  if (s != FP_OK) {
+    // leave the status word and error bits where the caller looks for them
+    if (out->status && s != FP_ERR_HIP)
+      hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, J.st, J.dm, 1);
+    return s;
+  }
   return FP_OK;
 }
 
@@ -203,11 +912,7 @@ fp_status fp_last_error(fp_handle* h, void* workspace, void* stream) {
   unsigned e = 0;
   if (hipMemcpy(&e, &((FpCtl*)workspace)->err, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess)
     return FP_ERR_HIP;
-  if (e & FP_E_INDEX) return FP_ERR_INDEX;
-  if (e & (FP_E_SCRATCH)) return FP_ERR_SIZE;
-  if (e & FP_E_GMAP) return FP_ERR_INDEX;
-  if (e) return FP_ERR_DEVICE;
-  return FP_OK;
+  return map_err(e);
 }
 
 }  // extern "C"

@@ -1,31 +1,27 @@
 // fp_device.h -- device-side building blocks for the gfx950 ordering path:
-// wave64 reductions and scans, the team barrier that lets a group of
-// co-resident workgroups run one mesh through all stages, and team-wide
-// prefix sums.  CDNA4 only (wave64, 160 KiB LDS per CU).
+// wave64 reductions and scans and workgroup scans.  CDNA4 only (wave64).
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#define FP_WG 512                // threads per workgroup of the persistent kernel
+#define FP_WG 256                // threads per workgroup
 #define FP_WAVES (FP_WG / 64)    // waves per workgroup
-#define FP_LDS_BYTES (160 * 1024) // dynamic LDS per workgroup (one workgroup per CU)
+#define FP_LDS_BYTES (64 * 1024) // dynamic LDS of the per-node kernels
 
 // error bits raised on the device; surfaced by fp_get_error
 #define FP_E_INDEX 0x1u       // column index out of range
-#define FP_E_BARRIER 0x2u     // a team barrier timed out
 #define FP_E_SCRATCH 0x4u     // a workspace pool overflowed
 #define FP_E_GMAP 0x8u        // user group id out of range
 #define FP_E_INTERNAL 0x10u   // an internal consistency check failed
 
-#define FP_SPIN_LIMIT (1u << 24)
-
-// debug hook: empty in device builds
-#ifndef FP_DBG
-#define FP_DBG(...)
-#endif
 #ifndef FP_DBGP
 #define FP_DBGP(...)
+#endif
+
+// the dynamic LDS array of every kernel that uses one
+#ifndef FP_LDS_DECL
+#define FP_LDS_DECL extern __shared__ __align__(16) char fp_lds[]
 #endif
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
@@ -112,85 +108,8 @@ __device__ __forceinline__ int64_t wg_sum_i64(int64_t x, int64_t* tmp) {
   return s;
 }
 
-// ---------------------------------------------------------------- team
-// A team is `size` co-resident workgroups that work on one mesh.  sync() is
-// a counting barrier with a generation word; an agent-scope fence on both
-// sides makes every global store before it visible to every workgroup of the
-// team after it, across XCDs.  A barrier that cannot complete within
-// FP_SPIN_LIMIT polls raises FP_E_BARRIER and releases the team, so every
-// wave exits.
-struct Team {
-  int rank;
-  int size;
-  unsigned* bar;  // [0] arrivals, [1] generation
-  unsigned* err;  // error bits of the mesh the team works on
-
-  __device__ __forceinline__ int gtid() const { return rank * FP_WG + (int)threadIdx.x; }
-  __device__ __forceinline__ int gsize() const { return size * FP_WG; }
-  __device__ __forceinline__ int gwave() const { return rank * FP_WAVES + wave_id(); }
-  __device__ __forceinline__ int nwaves() const { return size * FP_WAVES; }
-  __device__ __forceinline__ bool failed() const {
-    return __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FP_E_BARRIER;
-  }
-
-  __device__ void sync() const {
-    __syncthreads();
-    if (size > 1) {
-      if (threadIdx.x == 0 && !(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FP_E_BARRIER)) {
-        __threadfence();
-        unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (a == (unsigned)size - 1) {
-          __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          unsigned spins = 0;
-          while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
-            __builtin_amdgcn_s_sleep(2);
-            if (++spins > FP_SPIN_LIMIT ||
-                (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & FP_E_BARRIER)) {
-              atomicOr(err, FP_E_BARRIER);
-              break;
-            }
-          }
-        }
-        __threadfence();
-      }
-      __syncthreads();
-    }
-  }
-};
-
-// team-wide exclusive scan of int32 counts (in place allowed: out may equal
-// in).  Workgroup r owns the r-th chunk; chunk sums are exchanged through
-// `part` (team.size + 1 ints).  *total (global) receives the sum.  Two team
-// barriers.  lds_tmp holds FP_WAVES + 1 ints.
-__device__ void team_excl_scan(const Team& T, const int* in, int* out, int n, int* part,
-                               int* total, int* lds_tmp) {
-  const int chunk = (n + T.size - 1) / T.size;
-  const int lo = min(n, T.rank * chunk), hi = min(n, lo + chunk);
-  // pass 1: chunk sum
-  int s = 0;
-  for (int i = lo + (int)threadIdx.x; i < hi; i += FP_WG) s += in[i];
-  int tot;
-  wg_excl_scan(s, lds_tmp, &tot);
-  if (threadIdx.x == 0) part[T.rank] = tot;
-  T.sync();
-  // pass 2: base of this chunk, then scan the chunk in tiles of FP_WG
-  int base = 0, all = 0;
-  for (int r = 0; r < T.size; r++) {
-    int v = part[r];
-    if (r < T.rank) base += v;
-    all += v;
-  }
-  for (int t0 = lo; t0 < hi; t0 += FP_WG) {
-    int i = t0 + (int)threadIdx.x;
-    int x = i < hi ? in[i] : 0;
-    int tt;
-    int ex = wg_excl_scan(x, lds_tmp, &tt);
-    if (i < hi) out[i] = base + ex;
-    base += tt;
-  }
-  if (T.rank == 0 && threadIdx.x == 0) *total = all;
-  T.sync();
-}
+// grid-stride helpers of the one-thread-per-item kernels
+__device__ __forceinline__ int gtid() { return (int)(blockIdx.x * blockDim.x + threadIdx.x); }
+__device__ __forceinline__ int gsize() { return (int)(gridDim.x * blockDim.x); }
+__device__ __forceinline__ int gwave() { return (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); }
+__device__ __forceinline__ int nwaves() { return (int)((gridDim.x * blockDim.x) >> 6); }

@@ -7,7 +7,6 @@
 // control block at the start of every mesh workspace (device memory,
 // cleared by fp_ctl_init before the pipeline starts)
 struct FpCtl {
-  unsigned bar[2];       // team barrier: arrivals, generation
   unsigned err;          // FP_E_* bits
   int P;                 // patches
   int P0;                // seed blocks
@@ -16,20 +15,20 @@ struct FpCtl {
   int nnz_g;             // entries of the vertex graph
   int nbnd;              // boundary-list length
   int nq;                // quotient arcs
-  int fcount[4];         // frontier counters (rotating)
   int norphan;           // unlabelled vertices after growth
   int nroot;             // orphan components
-  int chg[3];            // fixed-point iteration flags (rotating)
+  int chg;               // fixed-point iteration flag
   int tot;               // scan total
-  int task_cnt[8];       // local-order / symbolic task counts per size class
-  int task_pop[8];       // task dispenser
+  int task_cnt[8];       // local-order task counts per size class
+  int task_pop[8];       // task dispensers
   int arena_top[2];      // element arena bump pointers (ping-pong per level)
   unsigned long long pool_top;  // global fallback pool bump pointer (words)
   long long nnzL;        // sum of vertex column counts
-  int part[1040];        // team scan partials
+  int part[1040];        // scan partials
 };
 
-// host-filled description of one ordering job (passed by value to kernels)
+// description of one ordering job; the host fills it and copies it into the
+// workspace, kernels read it through a pointer
 struct FpMesh {
   // input pattern (device)
   long long n_dof;
@@ -60,7 +59,7 @@ struct FpMesh {
   int n;          // vertices
   long long Ecap; // capacity of the vertex graph
   int NNcap;      // capacity of heap arrays
-  int lds_bytes;  // dynamic LDS per workgroup
+  int lds_bytes;  // dynamic LDS of the per-node kernels
   // workspace
   FpCtl* ctl;
   int* grp;       // n+1
@@ -68,6 +67,7 @@ struct FpMesh {
   unsigned long long* key;  // n
   unsigned long long* best; // n
   int* fa;        // n
+  int* fcnt;      // n+16: frontier size of every BFS level
   int* fb;        // n
   int* gmap;      // n
   int* seeds;     // n

@@ -7,6 +7,13 @@
 
 #include "fp_mesh.h"
 
+#ifndef FP_PLAN_GAP
+#define FP_PLAN_GAP 0
+#endif
+#ifndef FP_PLAN_RECORD
+#define FP_PLAN_RECORD(off, bytes)
+#endif
+
 namespace fpplan {
 
 struct Plan {
@@ -19,7 +26,7 @@ struct Plan {
   unsigned long long pool_words;
   size_t total;
   // byte offsets
-  size_t o_ctl, o_grp, o_gci, o_key, o_best, o_fa, o_fb, o_gmap, o_seeds, o_pcnt, o_pptr, o_pvtx,
+  size_t o_ctl, o_mesh, o_fcnt, o_grp, o_gci, o_key, o_best, o_fa, o_fb, o_gmap, o_seeds, o_pcnt, o_pptr, o_pvtx,
       o_bnd, o_qptr, o_qci, o_qcnt, o_wp, o_pnode, o_plist, o_ploc, o_node_of, o_cand, o_bs[10],
       o_nsize, o_nbegin, o_ncur, o_segS, o_segN, o_cntL, o_cntR, o_sbuf, o_eoff, o_tasks, o_gbuf,
       o_lidx, o_vperm, o_viperm, o_vpar, o_vcc, o_arena[2], o_pool;
@@ -44,11 +51,14 @@ bool make_plan(long long n_dof, int b, long long nnz, Plan* P) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
-    o = align_up(o + bytes);
+    FP_PLAN_RECORD(r, bytes);
+    o = align_up(o + bytes + FP_PLAN_GAP);
     return r;
   };
   const size_t N1 = (size_t)n + 1, E = (size_t)P->Ecap, NN = (size_t)P->NNcap;
   P->o_ctl = take(sizeof(FpCtl));
+  P->o_mesh = take(sizeof(FpMesh));
+  P->o_fcnt = take(4 * (N1 + 16));
   P->o_grp = take(4 * N1);
   P->o_gci = take(4 * E);
   P->o_key = take(8 * N1);
@@ -108,6 +118,7 @@ void fill_mesh(const Plan& P, char* ws, FpMesh* M) {
   M->key = (unsigned long long*)(ws + P.o_key);
   M->best = (unsigned long long*)(ws + P.o_best);
   M->fa = (int*)(ws + P.o_fa);
+  M->fcnt = (int*)(ws + P.o_fcnt);
   M->fb = (int*)(ws + P.o_fb);
   M->gmap = (int*)(ws + P.o_gmap);
   M->seeds = (int*)(ws + P.o_seeds);

@@ -1,5 +1,5 @@
-// fp_stages_b.h -- separator tree (patch-guided nested dissection) and the
-// grouping of vertices by tree node in schedule order.
+// fp_stages_b.h -- workgroup bisection of a separator-tree node on the
+// quotient graph, and schedule positions of tree nodes.
 #pragma once
 
 #include "fp_stages_a.h"
@@ -18,7 +18,7 @@ struct BisectLds {
   unsigned long long red[FP_WAVES];
 };
 
-__device__ int wg_bfs(const FpMesh& M, int t, const int* pid, int src, int* lev, int* queue,
+__device__ __forceinline__ int wg_bfs(const FpMesh& M, int t, const int* pid, int src, int* lev, int* queue,
                       int* ls, int* ecc_out, BisectLds* sh) {
   if (threadIdx.x == 0) {
     lev[src] = 0;
@@ -55,7 +55,7 @@ __device__ int wg_bfs(const FpMesh& M, int t, const int* pid, int src, int* lev,
   return tail;
 }
 
-__device__ unsigned long long wg_min_u64(unsigned long long x, BisectLds* sh) {
+__device__ __forceinline__ unsigned long long wg_min_u64(unsigned long long x, BisectLds* sh) {
   x = wave_min_u64(x);
   if (lane_id() == 0) sh->red[wave_id()] = x;
   __syncthreads();
@@ -70,7 +70,7 @@ __device__ unsigned long long wg_min_u64(unsigned long long x, BisectLds* sh) {
 // node's patches are plist[s..s+m), ascending ids.  Writes the two child
 // segments back into plist (left ascending, then right ascending) and moves
 // each patch to its child in pnode.
-__device__ void wg_bisect(const FpMesh& M, int t, int s, int m, BisectLds* sh) {
+__device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, BisectLds* sh) {
   int* pid = M.bs[0] + s;
   int* deg = M.bs[1] + s;
   int* levA = M.bs[2] + s;
@@ -216,111 +216,9 @@ __device__ void wg_bisect(const FpMesh& M, int t, int s, int m, BisectLds* sh) {
 }
 
 // --------------------------------------------------------------------------
-// Separator tree (Sec. 4.2 Step 3; Alg. 2; Sec. 5).  Level d: recount alive
-// quotient arcs from the boundary list, bisect every node of depth d, then
-// SuperSeparator (unmarked vertices with an unmarked neighbour across) and
-// RefineSeparator (keep the smaller side, ties to the left).  Node weights
-// are decremented as vertices are marked.
-// --------------------------------------------------------------------------
-__device__ bool stage_septree(const Team& T, const FpMesh& M, char* lds) {
-  FpCtl* C = M.ctl;
-  BisectLds* sh = (BisectLds*)lds;
-  const int n = M.n, P = C->P;
-  int D = 0;
-  while ((1 << D) < P) D++;
-  const int nn = (1 << (D + 1)) - 1;
-  if (nn > M.NNcap) {
-    if (T.gtid() == 0) atomicOr(&C->err, FP_E_SCRATCH);
-    return false;
-  }
-  if (T.gtid() == 0) {
-    C->D = D;
-    C->nn = nn;
-  }
-  for (int v = T.gtid(); v < n; v += T.gsize()) M.node_of[v] = -1;
-  for (int p = T.gtid(); p < P; p += T.gsize()) {
-    M.pnode[p] = 0;
-    M.plist[p] = p;
-  }
-  for (int x = T.gtid(); x < nn; x += T.gsize()) {
-    M.cntL[x] = 0;
-    M.cntR[x] = 0;
-    M.segN[x] = 0;
-    M.segS[x] = 0;
-  }
-  T.sync();
-  if (T.gtid() == 0) M.segN[0] = P;
-  const int nb = C->nbnd;
-  for (int d = 0; d < D; d++) {
-    const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
-    // alive arcs: crossing edges between unmarked vertices
-    for (int a = T.gtid(); a < C->nq; a += T.gsize()) M.qcnt[a] = 0;
-    T.sync();
-    for (int i = T.gtid(); i < nb; i += T.gsize()) {
-      const int v = M.bnd[i];
-      if (M.node_of[v] != -1) continue;
-      const int gv = M.gmap[v];
-      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-        const int u = M.gci[e];
-        if (M.node_of[u] != -1) continue;
-        const int gu = M.gmap[u];
-        if (gu == gv) continue;
-        const int a = arc_index(M, gv, gu);
-        if (a >= 0) atomicAdd(&M.qcnt[a], 1);
-      }
-    }
-    T.sync();
-    for (int t = lo + T.rank; t < hi; t += T.size) {
-      const int m = M.segN[t];
-      if (m >= 2)
-        wg_bisect(M, t, M.segS[t], m, sh);
-    }
-    T.sync();
-    // candidates on both sides
-    for (int i = T.gtid(); i < nb; i += T.gsize()) {
-      const int v = M.bnd[i];
-      M.cand[i] = 0;
-      if (M.node_of[v] != -1) continue;
-      const int c = M.pnode[M.gmap[v]];
-      if (c < hi) continue;  // patch not split at this level
-      const int sib = (c & 1) ? c + 1 : c - 1;
-      bool is = false;
-      for (int e = M.grp[v]; e < M.grp[v + 1] && !is; e++) {
-        const int u = M.gci[e];
-        is = (M.node_of[u] == -1 && M.pnode[M.gmap[u]] == sib);
-      }
-      if (is) {
-        M.cand[i] = 1;
-        atomicAdd((c & 1) ? &M.cntL[(c - 1) >> 1] : &M.cntR[(c - 1) >> 1], 1);
-      }
-    }
-    T.sync();
-    for (int i = T.gtid(); i < nb; i += T.gsize()) {
-      if (!M.cand[i]) continue;
-      const int v = M.bnd[i];
-      const int c = M.pnode[M.gmap[v]];
-      const int t = (c - 1) >> 1;
-      const bool left = c & 1;
-      const bool mark_left = M.cntL[t] <= M.cntR[t];
-      if (left == mark_left) {
-        M.node_of[v] = t;
-        atomicSub(&M.wp[M.gmap[v]], 1);
-      }
-    }
-    T.sync();
-  }
-  // leaves keep the remaining vertices of their patch
-  for (int v = T.gtid(); v < n; v += T.gsize())
-    if (M.node_of[v] == -1) M.node_of[v] = M.pnode[M.gmap[v]];
-  T.sync();
-  return true;
-}
-
-// --------------------------------------------------------------------------
-// Grouping (Alg. 3): node sizes, schedule offsets and vertices scattered into
-// their node's block (unordered inside a block; the local-order stage sorts
-// each block by vertex id).  Level order: depth descending, heap index
-// ascending.  Post order: left subtree, right subtree, node.
+// Schedule position of tree node t (Alg. 3, Sec. 5).  Level order: depth
+// descending, heap index ascending.  Post order: left subtree, right
+// subtree, node.
 // --------------------------------------------------------------------------
 __device__ __forceinline__ int sched_pos(int t, int D, int sched) {
   int d = 31 - __clz(t + 1);
@@ -335,28 +233,3 @@ __device__ __forceinline__ int sched_pos(int t, int D, int sched) {
   return start + (1 << (D - d + 1)) - 2;
 }
 
-__device__ void stage_group(const Team& T, const FpMesh& M, int* lds_tmp) {
-  FpCtl* C = M.ctl;
-  const int n = M.n, nn = C->nn, D = C->D;
-  for (int x = T.gtid(); x < nn; x += T.gsize()) M.nsize[x] = 0;
-  T.sync();
-  for (int v = T.gtid(); v < n; v += T.gsize()) {
-    if ((unsigned)M.node_of[v] >= (unsigned)nn) {  // never expected
-      atomicOr(&C->err, FP_E_INTERNAL);
-      M.node_of[v] = 0;
-    }
-    atomicAdd(&M.nsize[M.node_of[v]], 1);
-  }
-  T.sync();
-  for (int x = T.gtid(); x < nn; x += T.gsize()) M.sbuf[sched_pos(x, D, M.sched)] = M.nsize[x];
-  T.sync();
-  team_excl_scan(T, M.sbuf, M.sbuf, nn, C->part, &C->tot, lds_tmp);
-  for (int x = T.gtid(); x < nn; x += T.gsize()) {
-    const int b = M.sbuf[sched_pos(x, D, M.sched)];
-    M.nbegin[x] = b;
-    M.ncur[x] = b;
-  }
-  T.sync();
-  for (int v = T.gtid(); v < n; v += T.gsize()) M.gbuf[atomicAdd(&M.ncur[M.node_of[v]], 1)] = v;
-  T.sync();
-}

@@ -251,7 +251,7 @@ __device__ __forceinline__ void md_sp_carve(MdSp& S, char* mem, int m, int C) {
 
 // ---------------------------------------------------------------- driver
 // sort the node's vertex ids (LDS bitonic sort over the next power of two)
-__device__ void wave_sort_ids(int* a, int m, int np2) {
+__device__ __forceinline__ void wave_sort_ids(int* a, int m, int np2) {
   for (int i = m + lane_id(); i < np2; i += 64) a[i] = 0x7FFFFFFF;
   __threadfence_block();
   for (int k = 2; k <= np2; k <<= 1)
@@ -272,7 +272,7 @@ __device__ void wave_sort_ids(int* a, int m, int np2) {
 }
 
 // Build BIT rows for the vertices vmap[0..m) of node t straight from G.
-__device__ void md_bit_build(const FpMesh& M, MdBit& B, int t, const int* vmap) {
+__device__ __forceinline__ void md_bit_build(const FpMesh& M, MdBit& B, int t, const int* vmap) {
   const int m = B.m, W = B.W;
   for (long long i = lane_id(); i < (long long)m * W; i += 64) B.rows[i] = 0u;
   for (int w = lane_id(); w < W; w += 64) {
@@ -299,7 +299,7 @@ __device__ void md_bit_build(const FpMesh& M, MdBit& B, int t, const int* vmap) 
 }
 
 // One node, one wave.  slice/slice_bytes: this wave's LDS.
-__device__ void md_node(const FpMesh& M, int t, char* slice, long long slice_bytes) {
+__device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, long long slice_bytes) {
   const int m = M.nsize[t];
   const int pos0 = M.nbegin[t];
   int* V = M.gbuf + pos0;  // becomes the sorted vertex list
@@ -541,46 +541,10 @@ fail:
   }
 }
 
-// size class of a node: 0 = whole LDS, 1 = half, 2 = quarter, 3 = eighth
-__device__ __forceinline__ int md_class(int m, long long slice) {
-  if (m <= md_bit_max(slice / 8)) return 3;
-  if (m <= md_bit_max(slice / 4)) return 2;
-  if (m <= md_bit_max(slice / 2)) return 1;
+// size class of a node: 0 = whole LDS, 1 = half, 2 = quarter of the slice
+__device__ __forceinline__ int md_class(int m, long long lds) {
+  if (m <= md_bit_max((lds / 4) & ~15ll)) return 2;
+  if (m <= md_bit_max((lds / 2) & ~15ll)) return 1;
   return 0;
 }
 
-// Local orders of all nodes.  Each workgroup serves the classes from the
-// largest slice down; inside a class every participating wave pops nodes.
-__device__ void stage_local_orders(const Team& T, const FpMesh& M, char* lds) {
-  FpCtl* C = M.ctl;
-  const int nn = C->nn;
-  if (T.gtid() < 8) {
-    C->task_cnt[T.gtid()] = 0;
-    C->task_pop[T.gtid()] = 0;
-  }
-  T.sync();
-  for (int x = T.gtid(); x < nn; x += T.gsize()) {
-    const int m = M.nsize[x];
-    if (m == 0) continue;
-    const int c = md_class(m, M.lds_bytes);
-    M.tasks[c * M.NNcap + atomicAdd(&C->task_cnt[c], 1)] = x;
-  }
-  T.sync();
-  for (int c = 0; c < 4; c++) {
-    const int nsl = 1 << c;
-    const long long sb = (M.lds_bytes / nsl) & ~15ll;
-    const int cnt = C->task_cnt[c];
-    if (wave_id() < nsl) {
-      char* slice = lds + sb * wave_id();
-      while (true) {
-        int k = 0;
-        if (lane_id() == 0) k = atomicAdd(&C->task_pop[c], 1);
-        k = __shfl(k, 0, 64);
-        if (k >= cnt) break;
-        md_node(M, M.tasks[c * M.NNcap + k], slice, sb);
-      }
-    }
-    __syncthreads();
-  }
-  T.sync();
-}

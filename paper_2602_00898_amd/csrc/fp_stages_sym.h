@@ -50,7 +50,7 @@ __device__ __forceinline__ long long sym_bytes(int m, int ncand, int nent, int F
 
 // Process node t at depth d.  Returns false if the given memory was too
 // small (the caller retries with pool memory).
-__device__ bool sym_node_try(const FpMesh& M, int t, int d, char* mem, long long bytes,
+__device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char* mem, long long bytes,
                              bool full) {
   FpCtl* Cc = M.ctl;
   const int m = M.nsize[t];
@@ -374,7 +374,7 @@ __device__ bool sym_node_try(const FpMesh& M, int t, int d, char* mem, long long
   return true;
 }
 
-__device__ void sym_node(const FpMesh& M, int t, int d, char* slice, long long sb) {
+__device__ __forceinline__ void sym_node(const FpMesh& M, int t, int d, char* slice, long long sb) {
   if (sym_node_try(M, t, d, slice, sb, false)) return;
   // pool memory sized for the worst case of this node
   const int m = M.nsize[t];
@@ -407,41 +407,3 @@ __device__ void sym_node(const FpMesh& M, int t, int d, char* slice, long long s
     if (lane_id() == 0) atomicOr(&M.ctl->err, FP_E_INTERNAL);
 }
 
-// Bottom-up over the tree levels; nodes of one depth are independent.
-__device__ void stage_symbolic(const Team& T, const FpMesh& M, char* lds) {
-  FpCtl* C = M.ctl;
-  const int D = C->D;
-  for (int d = D; d >= 0; d--) {
-    if (T.gtid() == 0) C->arena_top[d & 1] = 0;
-    if (T.gtid() < 2) C->task_pop[T.gtid()] = 0;
-    T.sync();
-    const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
-    // big nodes: one wave with the whole LDS; small ones: eighth slices
-    for (int c = 0; c < 2; c++) {
-      const int nsl = c == 0 ? 1 : 8;
-      const long long sb = (M.lds_bytes / nsl) & ~15ll;
-      if (wave_id() < nsl) {
-        char* slice = lds + sb * wave_id();
-        while (true) {
-          int k = 0;
-          if (lane_id() == 0) k = atomicAdd(&C->task_pop[c], 1);
-          k = __shfl(k, 0, 64);
-          // node k of this depth belongs to class c when (m > 256) == (c == 0)
-          if (k >= hi - lo) break;
-          const int t = lo + k;
-          const bool big = M.nsize[t] > 256;
-          if (big != (c == 0)) continue;
-          sym_node(M, t, d, slice, sb);
-        }
-      }
-      __syncthreads();
-    }
-    T.sync();
-  }
-  // nnz(L) of the vertex graph
-  long long s = 0;
-  for (int i = T.gtid(); i < M.n; i += T.gsize()) s += M.vcc[i];
-  s = wave_sum_i64(s);
-  if (lane_id() == 0 && s) atomicAdd((unsigned long long*)&C->nnzL, (unsigned long long)s);
-  T.sync();
-}
