@@ -66,8 +66,12 @@ typedef struct {
   int32_t block_size;   /* DOFs per mesh vertex, >= 1 (default 1) */
   int32_t lloyd_iters;  /* Lloyd re-centre iterations of patching (default 1) */
   uint64_t seed;        /* seed of the patch-seed hash (default 0) */
-  uint32_t flags;       /* reserved, must be 0 */
+  uint32_t flags;       /* FP_FLAG_* bits, 0 by default */
 } fp_options;
+
+/* flags: record the device time of every stage of the call on its stream
+ * (read back with fp_stage_times) */
+#define FP_FLAG_TIMING 1u
 
 /* Pattern of A in CSR form (device arrays).  Exactly one of rowptr32 /
  * rowptr64 is non-NULL (n+1 entries); colind has nnz entries in [0, n).
@@ -127,6 +131,16 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
 /* Synchronise `stream` and translate the device error bits of the last
  * call that used `workspace`. */
 fp_status fp_last_error(fp_handle* h, void* workspace, void* stream);
+
+/* Stages of one ordering, in order (the paper's breakdown into patching,
+ * separators, local orders ... , Sec. 6.6): fp_stage_count() of them, named
+ * by fp_stage_name(i).  fp_stage_times waits for the last call made with
+ * FP_FLAG_TIMING on this handle and writes up to n stage times in
+ * milliseconds (device time between consecutive stage boundaries on the
+ * call's stream). */
+int fp_stage_count(void);
+const char* fp_stage_name(int i);
+fp_status fp_stage_times(fp_handle* h, float* ms, int32_t n);
 
 #ifdef __cplusplus
 }

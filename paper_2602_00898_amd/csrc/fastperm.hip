@@ -537,11 +537,17 @@ __global__ void k_finish(const FpMesh* __restrict__ Mp, int nn) {
 // ==========================================================================
 // host side
 // ==========================================================================
+#define FP_NSTAGE 8
+static const char* const kStageNames[FP_NSTAGE] = {
+    "ingest", "patches", "quotient", "septree", "group", "local_orders", "symbolic", "expand"};
+
 struct fp_handle {
   int device;
   int ncu;
   int lds_bytes;
   int* host;  // pinned: scalars read back between stages, and the job copy
+  hipEvent_t ev[FP_NSTAGE + 1];
+  bool timed;  // the last call recorded stage events
 };
 
 namespace {
@@ -555,7 +561,7 @@ fp_status check_opts(const fp_options* o) {
   if (o->patch_size < 1 || o->block_size < 1 || o->lloyd_iters < 0 || o->lloyd_iters > 64)
     return FP_ERR_ARG;
   if (o->schedule != FP_SCHED_LEVEL && o->schedule != FP_SCHED_POST) return FP_ERR_ARG;
-  if (o->nd_level != -1 || o->flags != 0) return FP_ERR_UNSUPPORTED;
+  if (o->nd_level != -1 || (o->flags & ~FP_FLAG_TIMING)) return FP_ERR_UNSUPPORTED;
   return FP_OK;
 }
 
@@ -585,7 +591,11 @@ struct Job {
   const FpMesh* dm;  // device copy
   FpCtl* ctl;
   bool hip_failed = false;
+  bool timing = false;
 
+  void mark(int i) {
+    if (timing && hipEventRecord(h->ev[i], st) != hipSuccess) hip_failed = true;
+  }
   int blocks(long long items, int per = FP_WG) const {
     long long b = (items + per - 1) / per;
     return (int)std::max(1ll, std::min(b, 8ll * h->ncu));
@@ -646,6 +656,7 @@ fp_status run_job(Job& J) {
   const dim3 T(FP_WG);
 
   // ingest
+  J.mark(0);
   hipLaunchKernelGGL(k_ingest, B(n), T, 0, st, dm, 0);
   J.scan(J.hm.pcnt, J.hm.grp, n, &C->nnz_g);
   J.read(&C->err, 8);
@@ -659,6 +670,7 @@ fp_status run_job(Job& J) {
   J.check();
 
   // patches
+  J.mark(1);
   int P = 0;
   if (J.hm.user_gmap) {
     hipLaunchKernelGGL(k_user_gmap, B(n), T, 0, st, dm);
@@ -704,6 +716,7 @@ fp_status run_job(Job& J) {
   if (P < 0 || P > std::max(n, 1)) return FP_ERR_DEVICE;
 
   // quotient graph
+  J.mark(2);
   hipLaunchKernelGGL(k_fill, B(P + 1), T, 0, st, J.hm.pcnt, P + 1, 0);
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, &C->nbnd, 1, 0);
   hipLaunchKernelGGL(k_patch_count, B(n), T, 0, st, dm);
@@ -724,6 +737,7 @@ fp_status run_job(Job& J) {
   J.check();
 
   // separator tree
+  J.mark(3);
   int D = 0;
   while ((1ll << D) < P) D++;
   const int nn = (1 << (D + 1)) - 1;
@@ -740,6 +754,7 @@ fp_status run_job(Job& J) {
   hipLaunchKernelGGL(k_leaves, B(n), T, 0, st, dm);
 
   // grouping in schedule order
+  J.mark(4);
   hipLaunchKernelGGL(k_fill, B(nn), T, 0, st, J.hm.nsize, nn, 0);
   hipLaunchKernelGGL(k_nsize, B(n), T, 0, st, dm, nn);
   hipLaunchKernelGGL(k_sched_place, B(nn), T, 0, st, dm, nn, D);
@@ -750,6 +765,7 @@ fp_status run_job(Job& J) {
   J.check();
 
   // local orders
+  J.mark(5);
   hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
   hipLaunchKernelGGL(k_md_tasks, B(nn), T, 0, st, dm, nn);
   for (int c = 0; c < 3; c++)
@@ -757,6 +773,7 @@ fp_status run_job(Job& J) {
   J.check();
 
   // elimination tree and column counts
+  J.mark(6);
   for (int d = D; d >= 0; d--) {
     hipLaunchKernelGGL(k_sym_level_init, dim3(1), dim3(64), 0, st, dm, d);
     hipLaunchKernelGGL(k_sym, dim3(std::min(1 << d, 2 * J.h->ncu)), T, J.h->lds_bytes, st, dm, d,
@@ -768,8 +785,10 @@ fp_status run_job(Job& J) {
   hipLaunchKernelGGL(k_nnzl, B(n), T, 0, st, dm);
 
   // outputs
+  J.mark(7);
   hipLaunchKernelGGL(k_expand, B(std::max<long long>(J.hm.n_dof, nn)), T, 0, st, dm, nn);
   hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, dm, nn);
+  J.mark(8);
   J.check();
   return J.hip_failed ? FP_ERR_HIP : FP_OK;
 }
@@ -822,12 +841,20 @@ fp_status fp_create(fp_handle** h) {
   }
   H->ncu = std::max(1, ncu);
   H->lds_bytes = FP_LDS_BYTES;
+  for (int i = 0; i <= FP_NSTAGE; i++)
+    if (hipEventCreate(&H->ev[i]) != hipSuccess) {
+      for (int j = 0; j < i; j++) (void)hipEventDestroy(H->ev[j]);
+      (void)hipHostFree(H->host);
+      delete H;
+      return FP_ERR_HIP;
+    }
   *h = H;
   return FP_OK;
 }
 
 fp_status fp_destroy(fp_handle* h) {
   if (!h) return FP_OK;
+  for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
   return FP_OK;
@@ -888,6 +915,8 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   M.lds_bytes = h->lds_bytes;
   J.ctl = M.ctl;
   J.dm = (const FpMesh*)(ws + P.o_mesh);
+  J.timing = (opts->flags & FP_FLAG_TIMING) != 0;
+  h->timed = false;
   // control block cleared, job description copied in
   const int words = (int)(sizeof(FpCtl) / 4);
   hipLaunchKernelGGL(k_fill, dim3((words + FP_WG - 1) / FP_WG), dim3(FP_WG), 0, J.st, (int*)M.ctl,
@@ -897,12 +926,26 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
       hipStreamSynchronize(J.st) != hipSuccess)
     return FP_ERR_HIP;
   s = run_job(J);
+  h->timed = J.timing && s == FP_OK;
   if (s != FP_OK) {
     // leave the status word and error bits where the caller looks for them
     if (out->status && s != FP_ERR_HIP)
       hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, J.st, J.dm, 1);
     return s;
   }
+  return FP_OK;
+}
+
+int fp_stage_count(void) { return FP_NSTAGE; }
+
+const char* fp_stage_name(int i) { return (i >= 0 && i < FP_NSTAGE) ? kStageNames[i] : ""; }
+
+fp_status fp_stage_times(fp_handle* h, float* ms, int32_t n) {
+  if (!h || !ms || n < 0) return FP_ERR_ARG;
+  if (!h->timed) return FP_ERR_ARG;
+  if (hipEventSynchronize(h->ev[FP_NSTAGE]) != hipSuccess) return FP_ERR_HIP;
+  for (int i = 0; i < std::min(n, FP_NSTAGE); i++)
+    if (hipEventElapsedTime(&ms[i], h->ev[i], h->ev[i + 1]) != hipSuccess) return FP_ERR_HIP;
   return FP_OK;
 }
 

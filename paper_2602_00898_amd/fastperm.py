@@ -71,6 +71,10 @@ def lib():
         L.fp_order.argtypes = [vp, C.POINTER(Csr), vp, C.POINTER(Options), vp, C.c_size_t,
                                C.POINTER(Result), vp]
         L.fp_last_error.argtypes = [vp, vp, vp]
+        L.fp_stage_count.restype = C.c_int
+        L.fp_stage_name.restype = C.c_char_p
+        L.fp_stage_name.argtypes = [C.c_int]
+        L.fp_stage_times.argtypes = [vp, C.POINTER(C.c_float), C.c_int32]
         _lib = L
     return _lib
 
@@ -104,7 +108,10 @@ class Handle:
         return self._ws
 
 
-def options(patch_size=512, schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, seed=0):
+FLAG_TIMING = 1
+
+
+def options(patch_size=512, schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, seed=0, flags=0):
     o = Options()
     lib().fp_options_default(C.byref(o))
     o.patch_size = patch_size
@@ -112,6 +119,7 @@ def options(patch_size=512, schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, s
     o.block_size = block_size
     o.lloyd_iters = lloyd_iters
     o.seed = seed & 0xFFFFFFFFFFFFFFFF
+    o.flags = flags
     return o
 
 
@@ -138,13 +146,14 @@ def query(handle, n, rowptr, colind, opts):
 
 def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size=1,
           lloyd_iters=1, seed=0, user_gmap=None, handle=None, out=None, stream=None,
-          check=True):
+          check=True, timing=False):
     """Order one matrix on the GPU.  rowptr (int32/int64) and colind (int32)
     are device tensors.  Returns a dict of device tensors; with check=True
     the call synchronises and raises on device-reported errors."""
     dev = colind.device if colind.numel() else rowptr.device
     handle = handle or Handle()
-    opts = options(patch_size, schedule, block_size, lloyd_iters, seed)
+    opts = options(patch_size, schedule, block_size, lloyd_iters, seed,
+                   FLAG_TIMING if timing else 0)
     A = make_csr(n, rowptr, colind)
     ws_bytes, max_nodes = query(handle, n, rowptr, colind, opts)
     ws = handle.workspace(ws_bytes, dev)
@@ -166,3 +175,12 @@ def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size
     if check:
         _check(lib().fp_last_error(handle.h, _ptr(ws), C.c_void_p(s)), "device")
     return out
+
+
+def stage_times(handle):
+    """Per-stage device milliseconds of the handle's last timed call."""
+    L = lib()
+    k = L.fp_stage_count()
+    ms = (C.c_float * k)()
+    _check(L.fp_stage_times(handle.h, ms, k), "fp_stage_times")
+    return {L.fp_stage_name(i).decode(): float(ms[i]) for i in range(k)}
