@@ -15,9 +15,12 @@
  *     owned by the caller; the library never frees them.  Server calls take
  *     host arrays (documented there).
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
- *     fp_order and fp_order_batch only enqueue work; results are ready when
- *     the stream reaches that point.  Errors found by the device are read
- *     with fp_last_error after the stream is synchronised.
+ *     Every kernel runs on `stream`.  fp_order reads a few scalars back
+ *     between stages (patch count, BFS frontier sizes, the error bits after
+ *     the local orders), so it synchronises `stream` at those points; the
+ *     last stages are only enqueued, and the results are ready when the
+ *     stream reaches the end of the call.  Errors found by the device are
+ *     read with fp_last_error / fp_error_detail after that.
  *   - perm[new] = old, iperm[old] = new.  parent[j] is the elimination-tree
  *     parent of column j of A(perm,perm), -1 for a root.  colcount[j] counts
  *     the nonzeros of column j of L including the diagonal; nnzL is their sum.
@@ -131,6 +134,13 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
 /* Synchronise `stream` and translate the device error bits of the last
  * call that used `workspace`. */
 fp_status fp_last_error(fp_handle* h, void* workspace, void* stream);
+
+/* Same, with the raw device error bits, the code of the first device check
+ * that failed (0 if none; the FP_SITE_* values of the library's sources)
+ * and one value it recorded (a node or vertex id).  Any output pointer may
+ * be NULL. */
+fp_status fp_error_detail(fp_handle* h, void* workspace, void* stream, uint32_t* bits,
+                          int32_t* site, int32_t* arg);
 
 /* Stages of one ordering, in order (the paper's breakdown into patching,
  * separators, local orders ... , Sec. 6.6): fp_stage_count() of them, named

@@ -86,7 +86,7 @@ __global__ void k_ingest(const FpMesh* __restrict__ Mp, int fill) {
     else
       M.pcnt[v] = gather_vertex_row(M, v, nullptr, &eb);
   }
-  if (eb) atomicOr(&C->err, eb);
+  if (eb) fp_fail(C, eb, FP_SITE_INGEST, 0);
 }
 
 // ==========================================================================
@@ -246,7 +246,7 @@ __global__ void k_gmap_final(const FpMesh* __restrict__ Mp, int P) {
   for (int v = gtid(); v < M.n; v += gsize()) {
     const unsigned long long k = M.key[v];
     const int g = k == FP_UNSET ? -1 : (int)(k & 0xFFFFFFFFu);
-    if (g < 0 || g >= P) atomicOr(&C->err, FP_E_INTERNAL);
+    if (g < 0 || g >= P) fp_fail(C, FP_E_INTERNAL, FP_SITE_GMAP_LABEL, v);
     M.gmap[v] = (g < 0 || g >= P) ? 0 : g;
   }
   if (gtid() == 0) C->P = P;
@@ -257,7 +257,7 @@ __global__ void k_user_gmap(const FpMesh* __restrict__ Mp) {
   for (int v = gtid(); v < M.n; v += gsize()) {
     int g = M.user_gmap[v];
     if (g < 0 || g >= M.n) {
-      atomicOr(&C->err, FP_E_GMAP);
+      fp_fail(C, FP_E_GMAP, FP_SITE_USER_GMAP, v);
       g = 0;
     }
     M.gmap[v] = g;
@@ -414,7 +414,7 @@ __global__ void k_nsize(const FpMesh* __restrict__ Mp, int nn) {
   MESH;
   for (int v = gtid(); v < M.n; v += gsize()) {
     if ((unsigned)M.node_of[v] >= (unsigned)nn) {  // never expected
-      atomicOr(&C->err, FP_E_INTERNAL);
+      fp_fail(C, FP_E_INTERNAL, FP_SITE_NODE_OF, v);
       M.node_of[v] = 0;
     }
     atomicAdd(&M.nsize[M.node_of[v]], 1);
@@ -528,7 +528,8 @@ __global__ void k_expand(const FpMesh* __restrict__ Mp, int nn) {
 __global__ void k_finish(const FpMesh* __restrict__ Mp, int nn) {
   MESH;
   if (gtid() != 0) return;
-  if ((M.node_begin_out || M.node_size_out) && nn > M.max_nodes_out) atomicOr(&C->err, FP_E_SCRATCH);
+  if ((M.node_begin_out || M.node_size_out) && nn > M.max_nodes_out)
+    fp_fail(C, FP_E_SCRATCH, FP_SITE_OUT_NODES, nn);
   *M.nnzL = (long long)M.b * M.b * C->nnzL - (long long)M.n * M.b * (M.b - 1) / 2;
   if (M.n_nodes_out) *M.n_nodes_out = nn;
   if (M.status_out) *M.status_out = C->err;
@@ -771,6 +772,12 @@ fp_status run_job(Job& J) {
   for (int c = 0; c < 3; c++)
     hipLaunchKernelGGL(k_md, dim3(2 * J.h->ncu), T, J.h->lds_bytes, st, dm, c);
   J.check();
+  // a node whose local order failed leaves its positions unset: stop here
+  {
+    const unsigned e = J.err();
+    if (J.hip_failed) return FP_ERR_HIP;
+    if (e) return map_err(e);
+  }
 
   // elimination tree and column counts
   J.mark(6);
@@ -946,6 +953,22 @@ fp_status fp_stage_times(fp_handle* h, float* ms, int32_t n) {
   if (hipEventSynchronize(h->ev[FP_NSTAGE]) != hipSuccess) return FP_ERR_HIP;
   for (int i = 0; i < std::min(n, FP_NSTAGE); i++)
     if (hipEventElapsedTime(&ms[i], h->ev[i], h->ev[i + 1]) != hipSuccess) return FP_ERR_HIP;
+  return FP_OK;
+}
+
+fp_status fp_error_detail(fp_handle* h, void* workspace, void* stream, uint32_t* bits,
+                          int32_t* site, int32_t* arg) {
+  if (!h || !workspace) return FP_ERR_ARG;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return FP_ERR_HIP;
+  const FpCtl* C = (const FpCtl*)workspace;
+  unsigned e = 0;
+  int s[2] = {0, 0};
+  if (hipMemcpy(&e, &C->err, sizeof(e), hipMemcpyDeviceToHost) != hipSuccess ||
+      hipMemcpy(s, &C->site, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess)
+    return FP_ERR_HIP;
+  if (bits) *bits = e;
+  if (site) *site = s[0];
+  if (arg) *arg = s[1];
   return FP_OK;
 }
 

@@ -15,6 +15,27 @@
 #define FP_E_GMAP 0x8u        // user group id out of range
 #define FP_E_INTERNAL 0x10u   // an internal consistency check failed
 
+// where a failure was raised (the first one is kept with one value)
+enum {
+  FP_SITE_NONE = 0,
+  FP_SITE_INGEST = 1,       // column index / row pointer out of range
+  FP_SITE_GMAP_LABEL = 2,   // a vertex left without a patch
+  FP_SITE_USER_GMAP = 3,    // user group id out of range
+  FP_SITE_BISECT_PATCH = 4, // patch id out of range in a node's list
+  FP_SITE_BISECT_SPLIT = 5, // split counts disagree with the split point
+  FP_SITE_NODE_OF = 6,      // vertex assigned to no valid node
+  FP_SITE_MD_VERTEX = 7,    // node vertex list holds a foreign vertex
+  FP_SITE_MD_POOL = 8,      // fallback pool exhausted
+  FP_SITE_MD_MAXM = 9,      // node beyond 16-bit local ids
+  FP_SITE_MD_PIVOT = 10,    // no valid pivot (dense layout)
+  FP_SITE_MD_PIVOT_SP = 11, // no valid pivot (sparse layout)
+  FP_SITE_SYM_VERTEX = 12,  // position list holds a vertex out of range
+  FP_SITE_SYM_RECORD = 13,  // child element record out of range
+  FP_SITE_SYM_ARENA = 14,   // element arena full
+  FP_SITE_SYM_SLOTS = 15,   // element slots exhausted even in the pool
+  FP_SITE_OUT_NODES = 16,   // node_begin/node_size capacity too small
+};
+
 #ifndef FP_DBGP
 #define FP_DBGP(...)
 #endif

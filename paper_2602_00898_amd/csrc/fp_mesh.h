@@ -24,6 +24,8 @@ struct FpCtl {
   int arena_top[2];      // element arena bump pointers (ping-pong per level)
   unsigned long long pool_top;  // global fallback pool bump pointer (words)
   long long nnzL;        // sum of vertex column counts
+  int site;              // FP_SITE_* of the first failure raised, 0 = none
+  int site_arg;          // a value that failure recorded (node, count ...)
   int part[1040];        // scan partials
 };
 

@@ -7,6 +7,12 @@
 
 #define FP_UNSET 0xFFFFFFFFFFFFFFFFull
 
+// raise error bits; the first failing site and one value are kept
+__device__ __forceinline__ void fp_fail(FpCtl* C, unsigned bits, int site, int arg) {
+  atomicOr(&C->err, bits);
+  if (atomicCAS(&C->site, 0, site) == 0) atomicExch(&C->site_arg, arg);
+}
+
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): output i+1 of the generator
 // seeded with `seed` -- the seed-selection hash of the patching stage.
 __device__ __forceinline__ uint64_t fp_mix64(uint64_t seed, uint64_t i) {

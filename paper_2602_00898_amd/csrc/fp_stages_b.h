@@ -88,7 +88,7 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
   for (int i = threadIdx.x; i < m; i += FP_WG) {
     int p = M.plist[s + i];
     if (p < 0 || p >= P) {  // never expected: keep every later index in range
-      atomicOr(&M.ctl->err, FP_E_INTERNAL);
+      fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_BISECT_PATCH, p);
       p = 0;
     }
     pid[i] = p;
@@ -206,7 +206,7 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
     rr += tr;
   }
   if (threadIdx.x == 0) {
-    if (rl != k || rr != m - k) atomicOr(&M.ctl->err, FP_E_INTERNAL);
+    if (rl != k || rr != m - k) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_BISECT_SPLIT, t);
     M.segS[2 * t + 1] = s;
     M.segN[2 * t + 1] = k;
     M.segS[2 * t + 2] = s + k;

@@ -35,7 +35,7 @@ __device__ __forceinline__ unsigned* pool_alloc(const FpMesh& M, unsigned long l
     words = (words + 63) & ~63ull;
     off = atomicAdd(&M.ctl->pool_top, words);
     if (off + words > M.pool_words) {
-      atomicOr(&M.ctl->err, FP_E_SCRATCH);
+      fp_fail(M.ctl, FP_E_SCRATCH, FP_SITE_MD_POOL, (int)(words >> 6));
       off = ~0ull;
     }
   }
@@ -150,7 +150,7 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
     const uint32_t km = md_argmin(B.gmin, B.G);
     const int p = (int)(km & 0xFFFFu);
     if (km == FP_KEY_INF || p >= B.m) {  // never expected: stop before any wild index
-      if (lane == 0) atomicOr(&M.ctl->err, FP_E_INTERNAL);
+      if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT, pos0);
       return;
     }
     if (lane == 0) {
@@ -245,7 +245,7 @@ __device__ __forceinline__ void md_sp_carve(MdSp& S, char* mem, int m, int C) {
   p += 8 * S.G;
   S.len = (uint16_t*)p;
   p += 2ll * m;
-  p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+  p = mem + ((p - mem + 15) & ~15ll);  // mem is 16-byte aligned; keeps the LDS address space
   S.rows = (uint16_t*)p;
 }
 
@@ -299,14 +299,57 @@ __device__ __forceinline__ void md_bit_build(const FpMesh& M, MdBit& B, int t, c
 }
 
 // One node, one wave.  slice/slice_bytes: this wave's LDS.
+// Re-index the na remaining vertices of a sparse state (rows srows/slen,
+// new index ni[i] or -1 if ordered) into a BIT layout carved from mem and
+// finish the node there.
+__device__ __forceinline__ void md_sp_to_bit(const FpMesh& M, char* mem, int na, int m, int C,
+                                             const uint16_t* srows, const uint16_t* slen,
+                                             const int* ni, const int* vm2, int pos) {
+  MdBit B;
+  md_bit_carve(B, mem, na);
+  for (long long i = lane_id(); i < (long long)na * B.W; i += 64) B.rows[i] = 0u;
+  for (int w = lane_id(); w < B.W; w += 64) {
+    const int hi = min(32, na - w * 32);
+    B.alive[w] = hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
+  }
+  for (int g = lane_id(); g < 2 * B.G; g += 64) B.dl[g] = 0;
+  __threadfence_block();
+  for (int i = lane_id(); i < m; i += 64) {
+    const int r = ni[i];
+    if (r < 0) continue;
+    uint32_t* rr = B.rows + (long long)r * B.W;
+    const int l = slen[i];
+    for (int q = 0; q < l; q++) {
+      const int x = ni[srows[(long long)i * C + q]];
+      if (x >= 0) rr[x >> 5] |= 1u << (x & 31);
+    }
+    B.key[r] = ((uint32_t)l << 16) | (uint32_t)r;
+  }
+  __threadfence_block();
+  md_refresh_all_groups(B);
+  md_bit_run(M, B, vm2, pos, na);
+}
+
 __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, long long slice_bytes) {
   const int m = M.nsize[t];
   const int pos0 = M.nbegin[t];
   int* V = M.gbuf + pos0;  // becomes the sorted vertex list
   if (m == 0) return;
+  // the node's vertex list must hold vertices of this node only
+  {
+    bool bad = pos0 < 0 || m < 0 || (long long)pos0 + m > M.n;
+    for (int i = lane_id(); i < m && !bad; i += 64) {
+      const int v = V[i];
+      bad = (unsigned)v >= (unsigned)M.n || M.node_of[v] != t;
+    }
+    if (ballot64(bad)) {
+      if (lane_id() == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_VERTEX, t);
+      return;
+    }
+  }
   if (m > FP_MD_MAXM) {
     // beyond 16-bit local ids: keep id order (flagged as unsupported)
-    if (lane_id() == 0) atomicOr(&M.ctl->err, FP_E_SCRATCH);
+    if (lane_id() == 0) fp_fail(M.ctl, FP_E_SCRATCH, FP_SITE_MD_MAXM, t);
     for (int i = lane_id(); i < m; i += 64) {
       M.vperm[pos0 + i] = V[i];
       M.viperm[V[i]] = pos0 + i;
@@ -391,7 +434,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       const uint32_t km = md_argmin(S.gmin, S.G);
       const int p = (int)(km & 0xFFFFu);
       if (km == FP_KEY_INF || p >= m) {
-        if (lane_id() == 0) atomicOr(&M.ctl->err, FP_E_INTERNAL);
+        if (lane_id() == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
         goto fail;
       }
       const int kp = S.len[p];
@@ -473,38 +516,16 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       if (!vm2) goto fail;
       for (int i = lane_id(); i < m; i += 64)
         if (ni[i] >= 0) vm2[ni[i]] = vmap[i];
-      MdBit B;
-      char* mem;
+      __threadfence_block();
+      // two call sites, so each keeps one address space (LDS or global)
       if (na <= mbit) {
-        mem = slice;
+        md_sp_to_bit(M, slice, na, m, C, srows, slen, ni, vm2, pos0 + done);
       } else {
         const long long bytes = md_bit_bytes(na);
-        mem = (char*)pool_alloc(M, (bytes + 3) / 4);
+        char* mem = (char*)pool_alloc(M, (bytes + 3) / 4);
         if (!mem) goto fail;
+        md_sp_to_bit(M, mem, na, m, C, srows, slen, ni, vm2, pos0 + done);
       }
-      __threadfence_block();
-      md_bit_carve(B, mem, na);
-      for (long long i = lane_id(); i < (long long)na * B.W; i += 64) B.rows[i] = 0u;
-      for (int w = lane_id(); w < B.W; w += 64) {
-        const int hi = min(32, na - w * 32);
-        B.alive[w] = hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
-      }
-      for (int g = lane_id(); g < 2 * B.G; g += 64) B.dl[g] = 0;
-      __threadfence_block();
-      for (int i = lane_id(); i < m; i += 64) {
-        const int r = ni[i];
-        if (r < 0) continue;
-        uint32_t* rr = B.rows + (long long)r * B.W;
-        const int l = slen[i];
-        for (int q = 0; q < l; q++) {
-          const int x = ni[srows[(long long)i * C + q]];
-          if (x >= 0) rr[x >> 5] |= 1u << (x & 31);
-        }
-        B.key[r] = ((uint32_t)l << 16) | (uint32_t)r;
-      }
-      __threadfence_block();
-      md_refresh_all_groups(B);
-      md_bit_run(M, B, vm2, pos0 + done, na);
       return;
     }
   } else {

@@ -68,6 +68,52 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
     }
   }
   const int nce = crec[0] + crec[1];
+  // inputs in range: t's positions hold vertices placed there by the local
+  // orders, child records hold positions of t or later.  An earlier failure
+  // can leave them unset; then t is skipped instead of indexing wildly.
+  {
+    bool bad = b0 < 0 || m < 0 || e0 > M.n;
+    for (int k = lane_id(); k < m && !bad; k += 64) {
+      const int v = M.vperm[b0 + k];
+      bad = (unsigned)v >= (unsigned)M.n || M.viperm[v] != b0 + k;
+    }
+    bad = ballot64(bad) != 0;
+    int site = bad ? FP_SITE_SYM_VERTEX : 0;
+    for (int c = 0; c < 2 && !bad; c++) {
+      site = FP_SITE_SYM_RECORD;
+      if (cst[c] < 0 || cin[c] < 0 || (long long)cst[c] + cin[c] > M.acap || crec[c] < 0) {
+        bad = true;
+        break;
+      }
+      int off = cst[c];
+      const int end = cst[c] + cin[c];
+      int nrec = 0;
+      while (off < end) {  // uniform: every lane walks the same records
+        const int len = src[off];
+        if (len < 0 || off + 1 + len > end) {
+          bad = true;
+          break;
+        }
+        for (int i = lane_id(); i < len; i += 64) {
+          const int q = src[off + 1 + i];
+          if (q < b0 || q >= M.n) bad = true;
+        }
+        off += 1 + len;
+        nrec++;
+      }
+      if (nrec != crec[c]) bad = true;
+      bad = ballot64(bad) != 0;
+    }
+    if (bad) {
+      if (lane_id() == 0) {
+        fp_fail(Cc, FP_E_INTERNAL, site, t);
+        M.eoff[3 * t] = 0;
+        M.eoff[3 * t + 1] = 0;
+        M.eoff[3 * t + 2] = 0;
+      }
+      return true;
+    }
+  }
   // count forward neighbours and later (ancestor) candidates
   int nfw = 0, nanc = 0;
   for (int k = lane_id(); k < m; k += 64) {
@@ -115,7 +161,7 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
     p += 4ll * nslot;
     L.freel = (int*)p;
     p += 4ll * nslot;
-    p = (char*)(((uintptr_t)p + 15) & ~(uintptr_t)15);
+    p = mem + ((p - mem + 15) & ~15ll);  // mem is 16-byte aligned; keeps the LDS address space
     L.slots = (uint32_t*)p;
   }
   L.m = m;
@@ -332,7 +378,7 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
   if (lane_id() == 0) {
     base = atomicAdd(&Cc->arena_top[d & 1], total);
     if ((long long)base + total > M.acap) {
-      atomicOr(&Cc->err, FP_E_SCRATCH);
+      fp_fail(Cc, FP_E_SCRATCH, FP_SITE_SYM_ARENA, t);
       base = -1;
     }
   }
@@ -404,6 +450,6 @@ __device__ __forceinline__ void sym_node(const FpMesh& M, int t, int d, char* sl
   char* mem = (char*)pool_alloc(M, words);
   if (!mem) return;
   if (!sym_node_try(M, t, d, mem, words * 4, true))
-    if (lane_id() == 0) atomicOr(&M.ctl->err, FP_E_INTERNAL);
+    if (lane_id() == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_SLOTS, t);
 }
 

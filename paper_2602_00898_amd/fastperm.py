@@ -25,9 +25,13 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "pattern not symmetric", 3: "index 
 
 
 class FpError(RuntimeError):
-    def __init__(self, code, what):
-        super().__init__(f"{what}: {STATUS.get(code, code)} (fp_status {code})")
+    def __init__(self, code, what, detail=None):
+        msg = f"{what}: {STATUS.get(code, code)} (fp_status {code})"
+        if detail:
+            msg += " [device bits 0x%x, check %d, value %d]" % detail
+        super().__init__(msg)
         self.code = code
+        self.detail = detail
 
 
 class Options(C.Structure):
@@ -71,6 +75,8 @@ def lib():
         L.fp_order.argtypes = [vp, C.POINTER(Csr), vp, C.POINTER(Options), vp, C.c_size_t,
                                C.POINTER(Result), vp]
         L.fp_last_error.argtypes = [vp, vp, vp]
+        L.fp_error_detail.argtypes = [vp, vp, vp, C.POINTER(C.c_uint32), C.POINTER(C.c_int32),
+                                      C.POINTER(C.c_int32)]
         L.fp_stage_count.restype = C.c_int
         L.fp_stage_name.restype = C.c_char_p
         L.fp_stage_name.argtypes = [C.c_int]
@@ -170,11 +176,24 @@ def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size
                _ptr(out.get("gmap")), _ptr(out.get("n_nodes")), _ptr(out.get("status")),
                int(out["node_begin"].numel()) if out.get("node_begin") is not None else 0)
     s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-    _check(lib().fp_order(handle.h, C.byref(A), _ptr(user_gmap), C.byref(opts), _ptr(ws),
-                          ws_bytes, C.byref(R), C.c_void_p(s)), "fp_order")
+    rc = lib().fp_order(handle.h, C.byref(A), _ptr(user_gmap), C.byref(opts), _ptr(ws),
+                        ws_bytes, C.byref(R), C.c_void_p(s))
+    if rc != 0:
+        device_side = rc in (3, 4, 9)
+        raise FpError(rc, "fp_order", error_detail(handle, ws, s) if device_side else None)
     if check:
-        _check(lib().fp_last_error(handle.h, _ptr(ws), C.c_void_p(s)), "device")
+        rc = lib().fp_last_error(handle.h, _ptr(ws), C.c_void_p(s))
+        if rc != 0:
+            raise FpError(rc, "device", error_detail(handle, ws, s))
     return out
+
+
+def error_detail(handle, ws, stream=0):
+    """(device error bits, first failing check, its value) of the last call."""
+    bits, site, arg = C.c_uint32(), C.c_int32(), C.c_int32()
+    rc = lib().fp_error_detail(handle.h, _ptr(ws), C.c_void_p(stream), C.byref(bits),
+                               C.byref(site), C.byref(arg))
+    return None if rc != 0 else (bits.value, site.value, arg.value)
 
 
 def stage_times(handle):
