@@ -34,6 +34,10 @@ enum {
   FP_SITE_SYM_ARENA = 14,   // element arena full
   FP_SITE_SYM_SLOTS = 15,   // element slots exhausted even in the pool
   FP_SITE_OUT_NODES = 16,   // node_begin/node_size capacity too small
+  FP_SITE_SYM_LOOKUP = 17,  // a later position missing from the node's list
+  FP_SITE_SYM_ROWS = 18,    // forward-row pointers out of order
+  FP_SITE_SYM_LIVE = 19,    // element slot or list index out of range
+  FP_SITE_SYM_PIVOT = 20,   // parent position outside the node's index space
 };
 
 #ifndef FP_DBGP

@@ -43,6 +43,26 @@ __device__ __forceinline__ int lower_bound_i(const int* a, int n, int x) {
   return lo;
 }
 
+// F-local index of position q (t's own range first, then the sorted list of
+// later positions); -1 if q is in neither, which the callers report
+__device__ __forceinline__ int sym_findex(int q, int b0, int e0, int m, const int* bd, int nbd) {
+  if (q >= b0 && q < e0) return q - b0;
+  if (q < e0) return -1;
+  const int i = lower_bound_i(bd, nbd, q);
+  return (i < nbd && bd[i] == q) ? m + i : -1;
+}
+
+// a failed internal check: record it, leave no elements for the parent
+__device__ __forceinline__ bool sym_abort(const FpMesh& M, int t, int site) {
+  if (lane_id() == 0) {
+    fp_fail(M.ctl, FP_E_INTERNAL, site, t);
+    M.eoff[3 * t] = 0;
+    M.eoff[3 * t + 1] = 0;
+    M.eoff[3 * t + 2] = 0;
+  }
+  return true;
+}
+
 // returns bytes needed (0 if nslot would be < 1)
 __device__ __forceinline__ long long sym_bytes(int m, int ncand, int nent, int FW, int nslot) {
   return 4ll * ncand + 4ll * (m + 1) + 4ll * nent + 4ll * FW + (4ll * FW + 8) * nslot + 512 + 64;
@@ -130,6 +150,7 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
   nanc = wave_sum_i32(nanc);
   const int nchild_ents = cin[0] + cin[1] - nce;
   int ncand = nanc + nchild_ents;
+  if (ncand < 0 || ncand > (1 << 29)) return sym_abort(M, t, FP_SITE_SYM_RECORD);
   int np2 = 1;
   while (np2 < ncand) np2 <<= 1;
   ncand = max(np2, 64);
@@ -226,6 +247,7 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
   L.FW = FW;
   // 2. forward rows in F-local indices
   {
+    bool bad = nbd > ncand;
     int run = 0;
     for (int k0 = 0; k0 < m; k0 += 64) {
       const int k = k0 + lane_id();
@@ -241,16 +263,22 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
         const int v = M.vperm[b0 + k];
         for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
           const int q = M.viperm[M.gci[e]];
-          if (q > b0 + k) L.oent[o++] = q < e0 ? q - b0 : m + lower_bound_i(L.bd, nbd, q);
+          if (q > b0 + k) {
+            const int f = sym_findex(q, b0, e0, m, L.bd, nbd);
+            bad |= f < 0;
+            L.oent[o++] = f < 0 ? m : f;
+          }
         }
       }
       run += __shfl(inc, 63, 64);
     }
     if (lane_id() == 0) L.optr[m] = run;
+    if (ballot64(bad) || run != nfw) return sym_abort(M, t, FP_SITE_SYM_LOOKUP);
   }
   // 3. child elements become slots
   int nlive = 0;
-  for (int c = 0; c < 2; c++) {
+  bool bad3 = nce > nslot;
+  for (int c = 0; c < 2 && !bad3; c++) {
     int off = cst[c];
     const int end = cst[c] + cin[c];
     while (off < end) {
@@ -260,14 +288,18 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
       __threadfence_block();
       for (int i = lane_id(); i < len; i += 64) {
         const int q = src[off + 1 + i];
-        const int f = q < e0 ? q - b0 : m + lower_bound_i(L.bd, nbd, q);
-        atomicOr(&sl[f >> 5], 1u << (f & 31));
+        const int f = sym_findex(q, b0, e0, m, L.bd, nbd);
+        if (f < 0)
+          bad3 = true;
+        else
+          atomicOr(&sl[f >> 5], 1u << (f & 31));
       }
       if (lane_id() == 0) L.live[nlive] = nlive;
       nlive++;
       off += 1 + len;
     }
   }
+  if (ballot64(bad3) || nlive != nce) return sym_abort(M, t, FP_SITE_SYM_LOOKUP);
   int nfree = 0;
   for (int i = nlive + lane_id(); i < nslot; i += 64) L.freel[i - nlive] = i;
   nfree = nslot - nlive;
@@ -275,11 +307,17 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
   // 4. eliminate t's positions in order
   for (int k = 0; k < m; k++) {
     const int kw = k >> 5;
+    if (nlive < 0 || nlive > nslot || nfree < 0 || nfree > nslot) return sym_abort(M, t, FP_SITE_SYM_LIVE);
+    bool bad4 = false;
     // live elements containing k
     int nab = 0;
     for (int j0 = 0; j0 < nlive; j0 += 64) {
       const int j = j0 + lane_id();
-      const int sidx = j < nlive ? L.live[j] : 0;
+      int sidx = j < nlive ? L.live[j] : 0;
+      if ((unsigned)sidx >= (unsigned)nslot) {
+        bad4 = true;
+        sidx = 0;
+      }
       const bool has = j < nlive && ((L.slots[(long long)sidx * FW + kw] >> (k & 31)) & 1u);
       const uint64_t bal = ballot64(has);
       if (has) L.tmp[nab + popc64(bal & lanemask_lt())] = j;  // live-list slot index
@@ -290,7 +328,14 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
     // struct = union of absorbed boundaries and the forward row, bits > k
     for (int w = kw + lane_id(); w < FW; w += 64) {
       uint32_t x = 0;
-      for (int a = 0; a < min(nab, 48); a++) x |= L.slots[(long long)L.live[L.tmp[a]] * FW + w];
+      for (int a = 0; a < min(nab, 48); a++) {
+        const int j = L.tmp[a];
+        const int sj = (unsigned)j < (unsigned)nlive ? L.live[j] : -1;
+        if ((unsigned)sj < (unsigned)nslot)
+          x |= L.slots[(long long)sj * FW + w];
+        else
+          bad4 = true;
+      }
       L.sw[w] = x;
     }
     __threadfence_block();
@@ -299,17 +344,27 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
       for (int w = kw + lane_id(); w < FW; w += 64) {
         uint32_t x = L.sw[w];
         for (int j = 0; j < nlive; j++) {
-          const uint32_t* sl = L.slots + (long long)L.live[j] * FW;
+          const int s = L.live[j];
+          if ((unsigned)s >= (unsigned)nslot) {
+            bad4 = true;
+            continue;
+          }
+          const uint32_t* sl = L.slots + (long long)s * FW;
           if ((sl[kw] >> (k & 31)) & 1u) x |= sl[w];
         }
         L.sw[w] = x;
       }
       __threadfence_block();
     }
-    for (int e = L.optr[k] + lane_id(); e < L.optr[k + 1]; e += 64) {
+    const int r0 = L.optr[k], r1 = L.optr[k + 1];
+    bad4 |= r0 < 0 || r1 < r0 || r1 > nfw;
+    if (ballot64(bad4)) return sym_abort(M, t, FP_SITE_SYM_LIVE);
+    for (int e = r0 + lane_id(); e < r1; e += 64) {
       const int f = L.oent[e];
-      atomicOr(&L.sw[f >> 5], 1u << (f & 31));
+      if (f > k && f < F) atomicOr(&L.sw[f >> 5], 1u << (f & 31));
+      else bad4 = true;
     }
+    if (ballot64(bad4)) return sym_abort(M, t, FP_SITE_SYM_ROWS);
     __threadfence_block();
     if (lane_id() == 0) {
       const uint32_t msk = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
@@ -325,6 +380,8 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
     }
     cnt = wave_sum_i32(cnt);
     first = wave_min_u32(first);
+    if (first != 0xFFFFFFFFu && (first <= (uint32_t)k || first >= (uint32_t)F))
+      return sym_abort(M, t, FP_SITE_SYM_PIVOT);
     if (lane_id() == 0) {
       M.vcc[b0 + k] = 1 + cnt;
       int par = -1;
@@ -341,6 +398,10 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
         int sidx = 0;
         if (j < nlive) {
           sidx = L.live[j];
+          if ((unsigned)sidx >= (unsigned)nslot) {
+            bad4 = true;
+            sidx = 0;
+          }
           absorbed = (L.slots[(long long)sidx * FW + kw] >> (k & 31)) & 1u;
         }
         const uint64_t bk = ballot64(j < nlive && !absorbed);
@@ -355,10 +416,12 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
       nlive = nl;
       nfree += nf_add;
     }
+    if (ballot64(bad4) || nlive + nfree != nslot) return sym_abort(M, t, FP_SITE_SYM_LIVE);
     if (cnt > 0) {
       if (nfree == 0) return false;  // out of slots
       const int sidx = L.freel[nfree - 1];
       nfree--;
+      if ((unsigned)sidx >= (unsigned)nslot) return sym_abort(M, t, FP_SITE_SYM_LIVE);
       uint32_t* sl = L.slots + (long long)sidx * FW;
       for (int w = lane_id(); w < FW; w += 64) sl[w] = w >= kw ? L.sw[w] : 0u;
       if (lane_id() == 0) L.live[nlive] = sidx;
