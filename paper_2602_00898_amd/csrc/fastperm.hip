@@ -469,31 +469,27 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
 // ==========================================================================
 // elimination tree and column counts, bottom-up over the tree levels
 // ==========================================================================
-__global__ void k_sym_level_init(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_sym_init(const FpMesh* __restrict__ Mp, int d) {
   MESH;
   if (gtid() == 0) {
     C->arena_top[d & 1] = 0;
-    C->task_pop[0] = 0;
-    C->task_pop[1] = 0;
+    C->pool_top = 0;  // the pool holds one level's node scratch at a time
   }
 }
-__global__ void __launch_bounds__(FP_WG) k_sym(const FpMesh* __restrict__ Mp, int d, int big) {
+__global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ Mp, int d) {
   MESH;
-  FP_LDS_DECL;
-  const int nsl = big ? 1 : FP_WAVES;
-  const long long sb = (M.lds_bytes / nsl) & ~15ll;
-  if (wave_id() >= nsl) return;
-  char* slice = fp_lds + sb * wave_id();
-  const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
-  while (true) {
-    int k = 0;
-    if (lane_id() == 0) k = atomicAdd(&C->task_pop[big ? 0 : 1], 1);
-    k = __shfl(k, 0, 64);
-    if (k >= hi - lo) break;
-    const int t = lo + k;
-    if ((M.nsize[t] > 256) != (big != 0)) continue;
-    sym_node(M, t, d, slice, sb);
-  }
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  for (int x = gwave(); x < cnt; x += nwaves()) sym_prep(M, lo + x, d);
+}
+__global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  for (int x = gwave(); x < cnt; x += nwaves()) sym_elim(M, lo + x);
+}
+__global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  for (int x = gwave(); x < cnt; x += nwaves()) sym_emit(M, lo + x, d);
 }
 __global__ void k_nnzl(const FpMesh* __restrict__ Mp) {
   MESH;
@@ -779,14 +775,15 @@ fp_status run_job(Job& J) {
     if (e) return map_err(e);
   }
 
-  // elimination tree and column counts
+  // elimination tree and column counts, bottom-up over the tree levels
   J.mark(6);
   for (int d = D; d >= 0; d--) {
-    hipLaunchKernelGGL(k_sym_level_init, dim3(1), dim3(64), 0, st, dm, d);
-    hipLaunchKernelGGL(k_sym, dim3(std::min(1 << d, 2 * J.h->ncu)), T, J.h->lds_bytes, st, dm, d,
-                       1);
-    hipLaunchKernelGGL(k_sym, dim3(std::min(1 << d, 2 * J.h->ncu)), T, J.h->lds_bytes, st, dm, d,
-                       0);
+    const int cnt = 1 << d;
+    const dim3 G(std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * J.h->ncu)));
+    hipLaunchKernelGGL(k_sym_init, dim3(1), dim3(64), 0, st, dm, d);
+    hipLaunchKernelGGL(k_sym_prep, G, T, 0, st, dm, d);
+    hipLaunchKernelGGL(k_sym_elim, G, T, 0, st, dm, d);
+    hipLaunchKernelGGL(k_sym_emit, G, T, 0, st, dm, d);
     J.check();
   }
   hipLaunchKernelGGL(k_nnzl, B(n), T, 0, st, dm);
@@ -874,7 +871,7 @@ fp_status fp_query(fp_handle* h, const fp_csr* A, const fp_options* opts, size_t
   if (s) return s;
   if ((s = check_csr(A, opts->block_size))) return s;
   Plan P;
-  if (!make_plan(A->n, opts->block_size, A->nnz, &P)) return FP_ERR_ARG;
+  if (!make_plan(A->n, opts->block_size, A->nnz, opts->patch_size, &P)) return FP_ERR_ARG;
   *ws_bytes = P.total;
   if (max_nodes) *max_nodes = P.NNcap;
   return FP_OK;
@@ -890,7 +887,7 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   if (!out->perm || !out->iperm || !out->parent || !out->colcount || !out->nnzL) return FP_ERR_ARG;
   if ((out->node_begin || out->node_size) && out->max_nodes < 1) return FP_ERR_ARG;
   Plan P;
-  if (!make_plan(A->n, opts->block_size, A->nnz, &P)) return FP_ERR_ARG;
+  if (!make_plan(A->n, opts->block_size, A->nnz, opts->patch_size, &P)) return FP_ERR_ARG;
   if (ws_bytes < P.total) return FP_ERR_SIZE;
   Job J;
   J.h = h;

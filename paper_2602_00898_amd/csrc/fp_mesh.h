@@ -105,6 +105,7 @@ struct FpMesh {
   int* vcc;       // n
   int* arena[2];  // element arenas, acap each
   long long acap;
+  long long* sdesc;  // NNcap: pool word offset of a node's symbolic scratch, -1 if none
   unsigned* pool; // fallback pool (32-bit words)
   unsigned long long pool_words;
 };

@@ -29,12 +29,13 @@ struct Plan {
   size_t o_ctl, o_mesh, o_fcnt, o_grp, o_gci, o_key, o_best, o_fa, o_fb, o_gmap, o_seeds, o_pcnt, o_pptr, o_pvtx,
       o_bnd, o_qptr, o_qci, o_qcnt, o_wp, o_pnode, o_plist, o_ploc, o_node_of, o_cand, o_bs[10],
       o_nsize, o_nbegin, o_ncur, o_segS, o_segN, o_cntL, o_cntR, o_sbuf, o_eoff, o_tasks, o_gbuf,
-      o_lidx, o_vperm, o_viperm, o_vpar, o_vcc, o_arena[2], o_pool;
+      o_lidx, o_vperm, o_viperm, o_vpar, o_vcc, o_arena[2], o_sdesc, o_pool;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
-bool make_plan(long long n_dof, int b, long long nnz, Plan* P) {
+// S: target patch size (bounds the per-level scratch of the symbolic stage)
+bool make_plan(long long n_dof, int b, long long nnz, int S, Plan* P) {
   if (b < 1 || n_dof < 0 || n_dof % b) return false;
   const long long n = n_dof / b;
   if (n >= (1ll << 31) - 2) return false;
@@ -47,7 +48,12 @@ bool make_plan(long long n_dof, int b, long long nnz, Plan* P) {
   while ((1ll << d) < std::max(n, 1ll)) d++;
   P->NNcap = (int)std::min((1ll << (d + 1)) + 2, (1ll << 31) - 1);
   P->acap = P->Ecap + 3 * n + 4096;
-  P->pool_words = std::max(1ull << 24, (unsigned long long)(16 * n + 2 * P->Ecap));
+  // one pool serves the local orders, then each level of the symbolic stage
+  // in turn: per vertex of a level a bitset row over the node's positions
+  // and later positions (about 2S + 1024 bits for patch-sized nodes)
+  const long long Se = std::max(1ll, std::min((long long)std::max(S, 1), n));
+  P->pool_words = std::max(1ull << 24, (unsigned long long)(16 * n + 4 * P->Ecap +
+                                                            n * ((2 * Se + 1024) / 32) + (1 << 20)));
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
@@ -99,6 +105,7 @@ bool make_plan(long long n_dof, int b, long long nnz, Plan* P) {
   P->o_vcc = take(4 * N1);
   P->o_arena[0] = take(4 * (size_t)P->acap);
   P->o_arena[1] = take(4 * (size_t)P->acap);
+  P->o_sdesc = take(8 * NN);
   P->o_pool = take(4 * (size_t)P->pool_words);
   P->total = o;
   return true;
@@ -154,6 +161,7 @@ void fill_mesh(const Plan& P, char* ws, FpMesh* M) {
   M->vcc = (int*)(ws + P.o_vcc);
   M->arena[0] = (int*)(ws + P.o_arena[0]);
   M->arena[1] = (int*)(ws + P.o_arena[1]);
+  M->sdesc = (long long*)(ws + P.o_sdesc);
   M->pool = (unsigned*)(ws + P.o_pool);
 }
 

@@ -4,32 +4,77 @@
 //
 // Node t owns the contiguous positions [b, b+m) of perm; every vertex that
 // precedes it and touches it lies in t's subtree, every later neighbour in
-// t or an ancestor.  The children summarise their eliminated subtrees as
-// *elements*: one per connected component, carrying its boundary (later
-// positions adjacent to the component).  Eliminating position k of t:
-//   struct(k) = (later neighbours of k in A)  U  (boundaries of live elements
-//               that contain k), minus positions <= k,
-//   colcount(k) = 1 + |struct(k)|,  parent(k) = min struct(k) (or -1),
-// the absorbed elements die and struct(k) becomes a new element.  This is
-// symbolic elimination in quotient-graph form (George & Liu), exact for any
-// order, so it agrees with the row-subtree definition of the column counts.
-// Boundaries are bitsets over F = t's positions followed by the sorted later
-// positions t can reach, held in the wave's LDS slice (pool when larger).
+// t or an ancestor.  Column k of L has the structure
+//   struct(k) = adj+(k)  U  (struct(j) for the columns j whose etree parent
+//               is k)  minus positions <= k,
+// parent(k) = min struct(k) (-1 if empty) and colcount(k) = 1 + |struct(k)|
+// (the column-structure recurrence of the elimination tree, Liu 1990).
+// Columns of t's subtree whose parent lies beyond t reach t as *elements*:
+// records [len, positions...] written by the children into an arena.
+//
+// Per tree level, three kernels, one wave per node, all scratch in a global
+// pool (reset per level):
+//   prep -- the node's index space F = t's positions followed by the sorted
+//           later positions it can reach; forward rows in F indices; every
+//           incoming element as a bitset row, queued on the column that
+//           absorbs it (its least position) or passed through;
+//   elim -- columns in order: OR of the rows queued on k and k's forward
+//           row; the new row is queued on its parent or leaves t;
+//   emit -- the rows that leave t become the parent's element records.
 #pragma once
 
 #include "fp_stages_md.h"
 
-struct SymLay {
-  int* bd;        // sorted later positions, capacity ncand
-  int* optr;      // m+1
-  int* oent;      // forward neighbours, F-local
-  uint32_t* sw;   // struct work bitset, FW words
-  uint32_t* slots;  // nslot x FW
-  int* live;      // nslot
-  int* freel;     // nslot
-  int* tmp;       // 128 ints
-  int m, FW, nslot, ncand, nent;
+// node scratch header (32-bit words at the start of the node's pool block)
+enum {
+  SH_M = 0,
+  SH_NBD,     // later positions in the index space
+  SH_NFW,     // forward entries
+  SH_FW,      // words of a row in use
+  SH_ROWS,    // m + incoming elements
+  SH_NCE,     // incoming elements
+  SH_NP2,     // capacity of the later-position list
+  SH_STRIDE,  // words per row
+  SH_NOUT,    // rows leaving t
+  SH_OK,      // 1 when prep finished
+  SH_WORDS = 16
 };
+
+struct SymView {
+  int* hdr;
+  int* bd;      // np2: sorted later positions
+  int* optr;    // m+1
+  int* oent;    // nfw: forward entries, F indices
+  int* head;    // m: first row queued on column k, -1 if none
+  int* next;    // rows: next row in the same queue
+  int* outl;    // rows: rows that leave t
+  uint32_t* rows;  // rows x stride words
+};
+
+__device__ __forceinline__ long long sym_words(int m, int np2, int nfw, int rows, int stride) {
+  return SH_WORDS + (long long)np2 + (m + 1) + nfw + m + 2ll * rows + (long long)rows * stride + 4;
+}
+
+__device__ __forceinline__ SymView sym_view(unsigned* base, int m, int np2, int nfw, int rows) {
+  SymView V;
+  int* p = (int*)base;
+  V.hdr = p;
+  p += SH_WORDS;
+  V.bd = p;
+  p += np2;
+  V.optr = p;
+  p += m + 1;
+  V.oent = p;
+  p += nfw;
+  V.head = p;
+  p += m;
+  V.next = p;
+  p += rows;
+  V.outl = p;
+  p += rows;
+  V.rows = (uint32_t*)p;
+  return V;
+}
 
 __device__ __forceinline__ int lower_bound_i(const int* a, int n, int x) {
   int lo = 0, hi = n;
@@ -43,8 +88,8 @@ __device__ __forceinline__ int lower_bound_i(const int* a, int n, int x) {
   return lo;
 }
 
-// F-local index of position q (t's own range first, then the sorted list of
-// later positions); -1 if q is in neither, which the callers report
+// F index of position q (t's own range first, then the sorted list of later
+// positions); -1 if q is in neither, which the callers report
 __device__ __forceinline__ int sym_findex(int q, int b0, int e0, int m, const int* bd, int nbd) {
   if (q >= b0 && q < e0) return q - b0;
   if (q < e0) return -1;
@@ -52,30 +97,24 @@ __device__ __forceinline__ int sym_findex(int q, int b0, int e0, int m, const in
   return (i < nbd && bd[i] == q) ? m + i : -1;
 }
 
-// a failed internal check: record it, leave no elements for the parent
-__device__ __forceinline__ bool sym_abort(const FpMesh& M, int t, int site) {
+// node t produces no elements for its parent and no scratch for the later
+// kernels of this level; `site` != 0 also records a failed check
+__device__ __forceinline__ void sym_drop(const FpMesh& M, int t, int site) {
   if (lane_id() == 0) {
-    fp_fail(M.ctl, FP_E_INTERNAL, site, t);
+    if (site) fp_fail(M.ctl, FP_E_INTERNAL, site, t);
+    M.sdesc[t] = -1;
     M.eoff[3 * t] = 0;
     M.eoff[3 * t + 1] = 0;
     M.eoff[3 * t + 2] = 0;
   }
-  return true;
 }
 
-// returns bytes needed (0 if nslot would be < 1)
-__device__ __forceinline__ long long sym_bytes(int m, int ncand, int nent, int FW, int nslot) {
-  return 4ll * ncand + 4ll * (m + 1) + 4ll * nent + 4ll * FW + (4ll * FW + 8) * nslot + 512 + 64;
-}
-
-// Process node t at depth d.  Returns false if the given memory was too
-// small (the caller retries with pool memory).
-__device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char* mem, long long bytes,
-                             bool full) {
-  FpCtl* Cc = M.ctl;
+// ---------------------------------------------------------------- prep
+__device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
+  FpCtl* C = M.ctl;
   const int m = M.nsize[t];
   const int b0 = M.nbegin[t], e0 = b0 + m;
-  const int nn = Cc->nn;
+  const int nn = C->nn;
   const int* src = M.arena[(d + 1) & 1];
   // child element records: [len, pos...] ...
   int cst[2] = {0, 0}, cin[2] = {0, 0}, crec[2] = {0, 0};
@@ -89,8 +128,7 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
   }
   const int nce = crec[0] + crec[1];
   // inputs in range: t's positions hold vertices placed there by the local
-  // orders, child records hold positions of t or later.  An earlier failure
-  // can leave them unset; then t is skipped instead of indexing wildly.
+  // orders, child records hold positions of t or later
   {
     bool bad = b0 < 0 || m < 0 || e0 > M.n;
     for (int k = lane_id(); k < m && !bad; k += 64) {
@@ -125,16 +163,11 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
       bad = ballot64(bad) != 0;
     }
     if (bad) {
-      if (lane_id() == 0) {
-        fp_fail(Cc, FP_E_INTERNAL, site, t);
-        M.eoff[3 * t] = 0;
-        M.eoff[3 * t + 1] = 0;
-        M.eoff[3 * t + 2] = 0;
-      }
-      return true;
+      sym_drop(M, t, site);
+      return;
     }
   }
-  // count forward neighbours and later (ancestor) candidates
+  // forward entries and later positions
   int nfw = 0, nanc = 0;
   for (int k = lane_id(); k < m; k += 64) {
     const int v = M.vperm[b0 + k];
@@ -148,47 +181,22 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
   }
   nfw = wave_sum_i32(nfw);
   nanc = wave_sum_i32(nanc);
-  const int nchild_ents = cin[0] + cin[1] - nce;
-  int ncand = nanc + nchild_ents;
-  if (ncand < 0 || ncand > (1 << 29)) return sym_abort(M, t, FP_SITE_SYM_RECORD);
-  int np2 = 1;
+  const int ncand = nanc + (cin[0] + cin[1] - nce);
+  if (ncand < 0 || ncand > (1 << 29)) {
+    sym_drop(M, t, FP_SITE_SYM_RECORD);
+    return;
+  }
+  int np2 = 64;
   while (np2 < ncand) np2 <<= 1;
-  ncand = max(np2, 64);
-  // F is at most m + ncand
-  const int FWmax = (m + ncand + 31) >> 5;
-  int nslot = full ? (nce + m + 1) : 0;
-  if (!full) {
-    const long long fixed = sym_bytes(m, ncand, nfw, FWmax, 0);
-    if (fixed > bytes) return false;
-    nslot = (int)min((long long)(nce + m + 1), (bytes - fixed) / (4ll * FWmax + 8));
-    if (nslot < nce + 1) return false;
-  } else if (sym_bytes(m, ncand, nfw, FWmax, nslot) > bytes) {
-    return false;
+  const int stride = (m + np2 + 31) >> 5;
+  const int rows = m + nce;
+  unsigned* base = pool_alloc(M, (unsigned long long)sym_words(m, np2, nfw, rows, stride));
+  if (!base) {  // pool_alloc raised the error
+    sym_drop(M, t, 0);
+    return;
   }
-  SymLay L;
-  {
-    char* p = mem;
-    L.tmp = (int*)p;
-    p += 512;
-    L.bd = (int*)p;
-    p += 4ll * ncand;
-    L.optr = (int*)p;
-    p += 4ll * (m + 1);
-    L.oent = (int*)p;
-    p += 4ll * nfw;
-    L.sw = (uint32_t*)p;
-    p += 4ll * FWmax;
-    L.live = (int*)p;
-    p += 4ll * nslot;
-    L.freel = (int*)p;
-    p += 4ll * nslot;
-    p = mem + ((p - mem + 15) & ~15ll);  // mem is 16-byte aligned; keeps the LDS address space
-    L.slots = (uint32_t*)p;
-  }
-  L.m = m;
-  L.nslot = nslot;
-  L.ncand = ncand;
-  // 1. later positions reachable from t: child boundaries and t's own rows
+  const SymView V = sym_view(base, m, np2, nfw, rows);
+  // 1. later positions: child boundaries and t's own rows, sorted, unique
   int nc = 0;
   for (int c = 0; c < 2; c++) {
     int off = cst[c];
@@ -197,57 +205,50 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
       const int len = src[off];
       for (int i = lane_id(); i < len; i += 64) {
         const int q = src[off + 1 + i];
-        L.bd[nc + i] = q >= e0 ? q : 0x7FFFFFFF;
+        V.bd[nc + i] = q >= e0 ? q : 0x7FFFFFFF;
       }
       nc += len;
       off += 1 + len;
     }
   }
-  {
-    int run = nc;
-    for (int k0 = 0; k0 < m; k0 += 64) {
-      const int k = k0 + lane_id();
-      int cnt = 0;
-      if (k < m) {
-        const int v = M.vperm[b0 + k];
-        for (int e = M.grp[v]; e < M.grp[v + 1]; e++) cnt += (M.viperm[M.gci[e]] >= e0);
-      }
-      const int inc = wave_incl_scan(cnt);
-      int o = run + inc - cnt;
-      if (k < m) {
-        const int v = M.vperm[b0 + k];
-        for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-          const int q = M.viperm[M.gci[e]];
-          if (q >= e0) L.bd[o++] = q;
-        }
-      }
-      run += __shfl(inc, 63, 64);
+  for (int k0 = 0; k0 < m; k0 += 64) {
+    const int k = k0 + lane_id();
+    int cnt = 0;
+    if (k < m) {
+      const int v = M.vperm[b0 + k];
+      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) cnt += (M.viperm[M.gci[e]] >= e0);
     }
-    nc = run;
+    const int inc = wave_incl_scan(cnt);
+    int o = nc + inc - cnt;
+    if (k < m) {
+      const int v = M.vperm[b0 + k];
+      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+        const int q = M.viperm[M.gci[e]];
+        if (q >= e0) V.bd[o++] = q;
+      }
+    }
+    nc += __shfl(inc, 63, 64);
   }
-  for (int i = nc + lane_id(); i < ncand; i += 64) L.bd[i] = 0x7FFFFFFF;
+  for (int i = nc + lane_id(); i < np2; i += 64) V.bd[i] = 0x7FFFFFFF;
   __threadfence_block();
-  wave_sort_ids(L.bd, ncand, ncand);
-  // unique
+  wave_sort_ids(V.bd, np2, np2);
   int nbd = 0;
-  for (int i0 = 0; i0 < ncand; i0 += 64) {
+  for (int i0 = 0; i0 < np2; i0 += 64) {
     const int i = i0 + lane_id();
-    const int x = i < ncand ? L.bd[i] : 0x7FFFFFFF;
-    const bool keep = x != 0x7FFFFFFF && (i == 0 || L.bd[i - 1] != x);
+    const int x = V.bd[i];
+    const bool keep = x != 0x7FFFFFFF && (i == 0 || V.bd[i - 1] != x);
     const uint64_t bal = ballot64(keep);
-    // compaction in place is safe: writes go to index <= read index
-    const int dst = nbd + popc64(bal & lanemask_lt());
+    const int dst = nbd + popc64(bal & lanemask_lt());  // dst <= i: in place
     __threadfence_block();
-    if (keep) L.bd[dst] = x;
+    if (keep) V.bd[dst] = x;
     __threadfence_block();
     nbd += popc64(bal);
   }
   const int F = m + nbd;
   const int FW = (F + 31) >> 5;
-  L.FW = FW;
-  // 2. forward rows in F-local indices
+  // 2. forward rows in F indices
   {
-    bool bad = nbd > ncand;
+    bool bad = false;
     int run = 0;
     for (int k0 = 0; k0 < m; k0 += 64) {
       const int k = k0 + lane_id();
@@ -259,260 +260,237 @@ __device__ __forceinline__ bool sym_node_try(const FpMesh& M, int t, int d, char
       const int inc = wave_incl_scan(cnt);
       int o = run + inc - cnt;
       if (k < m) {
-        L.optr[k] = o;
+        V.optr[k] = o;
         const int v = M.vperm[b0 + k];
         for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
           const int q = M.viperm[M.gci[e]];
           if (q > b0 + k) {
-            const int f = sym_findex(q, b0, e0, m, L.bd, nbd);
-            bad |= f < 0;
-            L.oent[o++] = f < 0 ? m : f;
+            const int f = sym_findex(q, b0, e0, m, V.bd, nbd);
+            const bool ok = f > k && f < F;
+            bad |= !ok;
+            V.oent[o++] = ok ? f : k + 1;
           }
         }
       }
       run += __shfl(inc, 63, 64);
     }
-    if (lane_id() == 0) L.optr[m] = run;
-    if (ballot64(bad) || run != nfw) return sym_abort(M, t, FP_SITE_SYM_LOOKUP);
+    if (lane_id() == 0) V.optr[m] = run;
+    if (ballot64(bad) || run != nfw) {
+      sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+      return;
+    }
   }
-  // 3. child elements become slots
-  int nlive = 0;
-  bool bad3 = nce > nslot;
-  for (int c = 0; c < 2 && !bad3; c++) {
+  for (int k = lane_id(); k < m; k += 64) V.head[k] = -1;
+  __threadfence_block();
+  // 3. incoming elements: one row each, queued on their least position
+  int npass = 0, e = 0;
+  bool bad3 = false;
+  for (int c = 0; c < 2; c++) {
     int off = cst[c];
     const int end = cst[c] + cin[c];
     while (off < end) {
       const int len = src[off];
-      uint32_t* sl = L.slots + (long long)nlive * FW;
-      for (int w = lane_id(); w < FW; w += 64) sl[w] = 0u;
+      const int r = m + e;
+      uint32_t* row = V.rows + (long long)r * stride;
+      for (int w = lane_id(); w < FW; w += 64) row[w] = 0u;
       __threadfence_block();
+      uint32_t fmin = 0xFFFFFFFFu;
       for (int i = lane_id(); i < len; i += 64) {
-        const int q = src[off + 1 + i];
-        const int f = sym_findex(q, b0, e0, m, L.bd, nbd);
-        if (f < 0)
+        const int f = sym_findex(src[off + 1 + i], b0, e0, m, V.bd, nbd);
+        if (f < 0) {
           bad3 = true;
-        else
-          atomicOr(&sl[f >> 5], 1u << (f & 31));
+        } else {
+          atomicOr(&row[f >> 5], 1u << (f & 31));
+          fmin = min(fmin, (uint32_t)f);
+        }
       }
-      if (lane_id() == 0) L.live[nlive] = nlive;
-      nlive++;
+      fmin = wave_min_u32(fmin);
+      __threadfence_block();
+      if (fmin != 0xFFFFFFFFu) {
+        if ((int)fmin < m) {
+          if (lane_id() == 0) {
+            V.next[r] = V.head[fmin];
+            V.head[fmin] = r;
+          }
+        } else {
+          if (lane_id() == 0) V.outl[npass] = r;
+          npass++;
+        }
+      }
+      __threadfence_block();
+      e++;
       off += 1 + len;
     }
   }
-  if (ballot64(bad3) || nlive != nce) return sym_abort(M, t, FP_SITE_SYM_LOOKUP);
-  int nfree = 0;
-  for (int i = nlive + lane_id(); i < nslot; i += 64) L.freel[i - nlive] = i;
-  nfree = nslot - nlive;
-  __threadfence_block();
-  // 4. eliminate t's positions in order
+  if (ballot64(bad3) || e != nce) {
+    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+    return;
+  }
+  if (lane_id() == 0) {
+    V.hdr[SH_M] = m;
+    V.hdr[SH_NBD] = nbd;
+    V.hdr[SH_NFW] = nfw;
+    V.hdr[SH_FW] = FW;
+    V.hdr[SH_ROWS] = rows;
+    V.hdr[SH_NCE] = nce;
+    V.hdr[SH_NP2] = np2;
+    V.hdr[SH_STRIDE] = stride;
+    V.hdr[SH_NOUT] = npass;
+    V.hdr[SH_OK] = 1;
+    M.sdesc[t] = (long long)(base - M.pool);
+  }
+}
+
+// scratch of node t after prep, or false if it has none
+__device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int* h) {
+  const long long so = M.sdesc[t];
+  if (so < 0 || (unsigned long long)so >= M.pool_words) return false;
+  unsigned* base = M.pool + so;
+  for (int i = 0; i < SH_WORDS; i++) h[i] = ((const int*)base)[i];
+  if (h[SH_OK] != 1) return false;
+  *V = sym_view(base, h[SH_M], h[SH_NP2], h[SH_NFW], h[SH_ROWS]);
+  return true;
+}
+
+// ---------------------------------------------------------------- elim
+__device__ __forceinline__ void sym_elim(const FpMesh& M, int t) {
+  SymView V;
+  int h[SH_WORDS];
+  if (!sym_load(M, t, &V, h)) return;
+  const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
+  const int stride = h[SH_STRIDE];
+  const int F = m + nbd;
+  const int b0 = M.nbegin[t];
+  int nout = h[SH_NOUT];
   for (int k = 0; k < m; k++) {
     const int kw = k >> 5;
-    if (nlive < 0 || nlive > nslot || nfree < 0 || nfree > nslot) return sym_abort(M, t, FP_SITE_SYM_LIVE);
-    bool bad4 = false;
-    // live elements containing k
-    int nab = 0;
-    for (int j0 = 0; j0 < nlive; j0 += 64) {
-      const int j = j0 + lane_id();
-      int sidx = j < nlive ? L.live[j] : 0;
-      if ((unsigned)sidx >= (unsigned)nslot) {
-        bad4 = true;
-        sidx = 0;
-      }
-      const bool has = j < nlive && ((L.slots[(long long)sidx * FW + kw] >> (k & 31)) & 1u);
-      const uint64_t bal = ballot64(has);
-      if (has) L.tmp[nab + popc64(bal & lanemask_lt())] = j;  // live-list slot index
-      nab += popc64(bal);
-      if (nab > 48) break;  // many absorptions: handled below in chunks
-    }
-    __threadfence_block();
-    // struct = union of absorbed boundaries and the forward row, bits > k
-    for (int w = kw + lane_id(); w < FW; w += 64) {
-      uint32_t x = 0;
-      for (int a = 0; a < min(nab, 48); a++) {
-        const int j = L.tmp[a];
-        const int sj = (unsigned)j < (unsigned)nlive ? L.live[j] : -1;
-        if ((unsigned)sj < (unsigned)nslot)
-          x |= L.slots[(long long)sj * FW + w];
-        else
-          bad4 = true;
-      }
-      L.sw[w] = x;
-    }
-    __threadfence_block();
-    if (nab > 48) {
-      // rare: scan every live element directly
-      for (int w = kw + lane_id(); w < FW; w += 64) {
-        uint32_t x = L.sw[w];
-        for (int j = 0; j < nlive; j++) {
-          const int s = L.live[j];
-          if ((unsigned)s >= (unsigned)nslot) {
-            bad4 = true;
-            continue;
-          }
-          const uint32_t* sl = L.slots + (long long)s * FW;
-          if ((sl[kw] >> (k & 31)) & 1u) x |= sl[w];
-        }
-        L.sw[w] = x;
-      }
-      __threadfence_block();
-    }
-    const int r0 = L.optr[k], r1 = L.optr[k + 1];
-    bad4 |= r0 < 0 || r1 < r0 || r1 > nfw;
-    if (ballot64(bad4)) return sym_abort(M, t, FP_SITE_SYM_LIVE);
-    for (int e = r0 + lane_id(); e < r1; e += 64) {
-      const int f = L.oent[e];
-      if (f > k && f < F) atomicOr(&L.sw[f >> 5], 1u << (f & 31));
-      else bad4 = true;
-    }
-    if (ballot64(bad4)) return sym_abort(M, t, FP_SITE_SYM_ROWS);
-    __threadfence_block();
-    if (lane_id() == 0) {
-      const uint32_t msk = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
-      L.sw[kw] &= msk;
-    }
-    __threadfence_block();
+    const int r0 = V.optr[k], r1 = V.optr[k + 1];
+    const int q0 = V.head[k];
+    uint32_t* rk = V.rows + (long long)k * stride;
     int cnt = 0;
     uint32_t first = 0xFFFFFFFFu;
-    for (int w = kw + lane_id(); w < FW; w += 64) {
-      const uint32_t x = L.sw[w];
+    bool bad = false;
+    for (int w = lane_id(); w < FW; w += 64) {
+      uint32_t x = 0u;
+      if (w >= kw) {
+        int j = q0, steps = 0;
+        while (j >= 0 && j < rows && steps < rows) {
+          x |= V.rows[(long long)j * stride + w];
+          j = V.next[j];
+          steps++;
+        }
+        bad |= j >= 0;  // a queue that leaves the rows or does not end
+        for (int e = r0; e < r1; e++) {
+          const int f = V.oent[e];
+          if ((f >> 5) == w) x |= 1u << (f & 31);
+        }
+        if (w == kw) x &= (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
+      }
+      rk[w] = x;
       cnt += popc32(x);
       if (x && first == 0xFFFFFFFFu) first = (uint32_t)(w * 32 + __ffs(x) - 1);
     }
     cnt = wave_sum_i32(cnt);
     first = wave_min_u32(first);
-    if (first != 0xFFFFFFFFu && (first <= (uint32_t)k || first >= (uint32_t)F))
-      return sym_abort(M, t, FP_SITE_SYM_PIVOT);
+    if (ballot64(bad) || (first != 0xFFFFFFFFu && first >= (uint32_t)F)) {
+      if (lane_id() == 0) {
+        fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_LIVE, t);
+        V.hdr[SH_OK] = 0;
+      }
+      return;
+    }
     if (lane_id() == 0) {
       M.vcc[b0 + k] = 1 + cnt;
       int par = -1;
-      if (first != 0xFFFFFFFFu) par = (int)first < m ? b0 + (int)first : L.bd[first - m];
+      if (first != 0xFFFFFFFFu) {
+        if ((int)first < m) {
+          par = b0 + (int)first;
+          V.next[k] = V.head[first];
+          V.head[first] = k;
+        } else {
+          par = V.bd[first - m];
+          V.outl[nout] = k;
+        }
+      }
       M.vpar[b0 + k] = par;
     }
-    // remove absorbed elements from the live list, recycle their slots
-    {
-      int nl = 0;
-      int nf_add = 0;
-      for (int j0 = 0; j0 < nlive; j0 += 64) {
-        const int j = j0 + lane_id();
-        bool absorbed = false;
-        int sidx = 0;
-        if (j < nlive) {
-          sidx = L.live[j];
-          if ((unsigned)sidx >= (unsigned)nslot) {
-            bad4 = true;
-            sidx = 0;
-          }
-          absorbed = (L.slots[(long long)sidx * FW + kw] >> (k & 31)) & 1u;
-        }
-        const uint64_t bk = ballot64(j < nlive && !absorbed);
-        const uint64_t ba = ballot64(absorbed);
-        __threadfence_block();
-        if (j < nlive && !absorbed) L.live[nl + popc64(bk & lanemask_lt())] = sidx;
-        if (absorbed) L.freel[nfree + nf_add + popc64(ba & lanemask_lt())] = sidx;
-        __threadfence_block();
-        nl += popc64(bk);
-        nf_add += popc64(ba);
-      }
-      nlive = nl;
-      nfree += nf_add;
-    }
-    if (ballot64(bad4) || nlive + nfree != nslot) return sym_abort(M, t, FP_SITE_SYM_LIVE);
-    if (cnt > 0) {
-      if (nfree == 0) return false;  // out of slots
-      const int sidx = L.freel[nfree - 1];
-      nfree--;
-      if ((unsigned)sidx >= (unsigned)nslot) return sym_abort(M, t, FP_SITE_SYM_LIVE);
-      uint32_t* sl = L.slots + (long long)sidx * FW;
-      for (int w = lane_id(); w < FW; w += 64) sl[w] = w >= kw ? L.sw[w] : 0u;
-      if (lane_id() == 0) L.live[nlive] = sidx;
-      nlive++;
-    }
-    __threadfence_block();
+    if (first != 0xFFFFFFFFu && (int)first >= m) nout++;
+    __threadfence_block();  // the row, the queue links and outl reach every lane
   }
-  // 5. surviving elements (boundaries beyond t) go to the parent
+  if (lane_id() == 0) V.hdr[SH_NOUT] = nout;
+}
+
+// ---------------------------------------------------------------- emit
+__device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
+  SymView V;
+  int h[SH_WORDS];
+  if (!sym_load(M, t, &V, h)) {
+    if (M.sdesc[t] >= 0) sym_drop(M, t, 0);  // elim failed after prep
+    return;
+  }
+  const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
+  const int stride = h[SH_STRIDE], nout = h[SH_NOUT];
+  if (nout < 0 || nout > rows) {
+    sym_drop(M, t, FP_SITE_SYM_LIVE);
+    return;
+  }
   int total = 0;
-  for (int j = 0; j < nlive; j++) {
-    const uint32_t* sl = L.slots + (long long)L.live[j] * FW;
+  for (int i = 0; i < nout; i++) {
+    const int r = V.outl[i];
+    if ((unsigned)r >= (unsigned)rows) {
+      sym_drop(M, t, FP_SITE_SYM_LIVE);
+      return;
+    }
+    const uint32_t* row = V.rows + (long long)r * stride;
     int c = 0;
-    for (int w = lane_id(); w < FW; w += 64) c += popc32(sl[w]);
+    for (int w = lane_id(); w < FW; w += 64) c += popc32(row[w]);
     total += 1 + wave_sum_i32(c);
   }
   int base = 0;
   if (lane_id() == 0) {
-    base = atomicAdd(&Cc->arena_top[d & 1], total);
+    base = atomicAdd(&M.ctl->arena_top[d & 1], total);
     if ((long long)base + total > M.acap) {
-      fp_fail(Cc, FP_E_SCRATCH, FP_SITE_SYM_ARENA, t);
+      fp_fail(M.ctl, FP_E_SCRATCH, FP_SITE_SYM_ARENA, t);
       base = -1;
     }
   }
   base = __shfl(base, 0, 64);
   if (base < 0) {
-    if (lane_id() == 0) {
-      M.eoff[3 * t] = 0;
-      M.eoff[3 * t + 1] = 0;
-      M.eoff[3 * t + 2] = 0;
-    }
-    return true;
+    sym_drop(M, t, 0);
+    return;
   }
   int* dst = M.arena[d & 1];
+  const int b0 = M.nbegin[t];
   int off = base;
-  for (int j = 0; j < nlive; j++) {
-    const uint32_t* sl = L.slots + (long long)L.live[j] * FW;
+  bool bad = false;
+  for (int i = 0; i < nout; i++) {
+    const uint32_t* row = V.rows + (long long)V.outl[i] * stride;
     int len = 0;
     for (int w0 = 0; w0 < FW; w0 += 64) {
       const int w = w0 + lane_id();
-      uint32_t x = w < FW ? sl[w] : 0u;
+      uint32_t x = w < FW ? row[w] : 0u;
       const int c = popc32(x);
       const int inc = wave_incl_scan(c);
       int o = off + 1 + len + inc - c;
       while (x) {
         const int f = w * 32 + __ffs(x) - 1;
         x &= x - 1;
-        dst[o++] = f < m ? b0 + f : L.bd[f - m];
+        const bool ok = f >= m && f < m + nbd;  // elements only hold later positions
+        bad |= !ok;
+        dst[o++] = ok ? V.bd[f - m] : b0;
       }
       len += __shfl(inc, 63, 64);
     }
     if (lane_id() == 0) dst[off] = len;
     off += 1 + len;
   }
+  if (ballot64(bad)) {
+    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+    return;
+  }
   if (lane_id() == 0) {
     M.eoff[3 * t] = base;
     M.eoff[3 * t + 1] = total;
-    M.eoff[3 * t + 2] = nlive;
+    M.eoff[3 * t + 2] = nout;
   }
-  return true;
 }
-
-__device__ __forceinline__ void sym_node(const FpMesh& M, int t, int d, char* slice, long long sb) {
-  if (sym_node_try(M, t, d, slice, sb, false)) return;
-  // pool memory sized for the worst case of this node
-  const int m = M.nsize[t];
-  long long words = 0;
-  {
-    // generous bound: F <= m + later candidates; nslot = children + m + 1
-    int cin = 0, crec = 0;
-    for (int c = 0; c < 2; c++) {
-      const int ch = 2 * t + 1 + c;
-      if (ch < M.ctl->nn) {
-        cin += M.eoff[3 * ch + 1];
-        crec += M.eoff[3 * ch + 2];
-      }
-    }
-    int nfw = 0;
-    for (int k = lane_id(); k < m; k += 64) {
-      const int v = M.vperm[M.nbegin[t] + k];
-      nfw += M.grp[v + 1] - M.grp[v];
-    }
-    nfw = wave_sum_i32(nfw);
-    long long nc = 1;
-    while (nc < (long long)nfw + cin) nc <<= 1;
-    nc = max(nc, 64ll);
-    const long long FW = (m + nc + 31) / 32;
-    words = (sym_bytes(m, (int)nc, nfw, (int)FW, crec + m + 1) + 3) / 4 + 64;
-  }
-  char* mem = (char*)pool_alloc(M, words);
-  if (!mem) return;
-  if (!sym_node_try(M, t, d, mem, words * 4, true))
-    if (lane_id() == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_SLOTS, t);
-}
-
