@@ -89,15 +89,19 @@ def run_gpu(args):
         return fpm.order(rp, ci, n, patch_size=PATCH, seed=MESH_SEED, handle=h, out=out,
                          timing=True)
 
-    for _ in range(args.warmup):
+    for i in range(args.warmup):
+        t = time.perf_counter()
         step()
-    torch.cuda.synchronize(dev)
+        torch.cuda.synchronize(dev)
+        print(f"[bench] warmup {i}: {1e3 * (time.perf_counter() - t):.2f} ms", file=sys.stderr, flush=True)
     stages = {}
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         step()
         for k, v in fpm.stage_times(h).items():
             stages.setdefault(k, []).append(v)
+        if i % 5 == 0:
+            print(f"[bench] step {i}", file=sys.stderr, flush=True)
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t0
     nnzL = int(out["nnzL"].item())
@@ -117,6 +121,7 @@ def run_cpu(A, budget_s=15.0):
     import oracle
 
     oracle.build()
+    print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
     times = []
     t_all = time.perf_counter()
     while True:
