@@ -128,19 +128,33 @@ __global__ void k_seed_push(const FpMesh* __restrict__ Mp, int nseeds) {
   }
   if (gtid() == 0) M.fcnt[0] = nseeds;
 }
+// one frontier level: a lane per frontier vertex, its neighbours visited in
+// lock step so that the new frontier is appended with one atomic per wave
 __global__ void k_bfs_level(const FpMesh* __restrict__ Mp, int lvl) {
   MESH;
   const int nf = M.fcnt[lvl];
   const int* cur = (lvl & 1) ? M.fb : M.fa;
   int* nxt = (lvl & 1) ? M.fa : M.fb;
-  for (int f = gtid(); f < nf; f += gsize()) {
-    const int v = cur[f];
-    const unsigned long long kv = M.key[v] + (1ull << 32);
-    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-      const int u = M.gci[e];
-      if (M.key[u] <= kv) continue;
-      const unsigned long long old = atomicMin(&M.key[u], kv);
-      if (old == FP_UNSET) nxt[atomicAdd(&M.fcnt[lvl + 1], 1)] = u;
+  for (int f0 = gwave() * 64; f0 < nf; f0 += nwaves() * 64) {
+    const int f = f0 + lane_id();
+    int e0 = 0, deg = 0;
+    unsigned long long kv = 0;
+    if (f < nf) {
+      const int v = cur[f];
+      kv = M.key[v] + (1ull << 32);
+      e0 = M.grp[v];
+      deg = M.grp[v + 1] - e0;
+    }
+    const int dmax = (int)wave_max_u32((uint32_t)deg);
+    for (int j = 0; j < dmax; j++) {
+      bool claim = false;
+      int u = 0;
+      if (j < deg) {
+        u = M.gci[e0 + j];
+        if (M.key[u] > kv) claim = atomicMin(&M.key[u], kv) == FP_UNSET;
+      }
+      const int slot = wave_append(&M.fcnt[lvl + 1], claim);
+      if (claim) nxt[slot] = u;
     }
   }
 }
@@ -216,12 +230,16 @@ __global__ void k_lloyd_gmap(const FpMesh* __restrict__ Mp, int P) {
 }
 __global__ void k_lloyd_bnd(const FpMesh* __restrict__ Mp) {
   MESH;
-  for (int v = gtid(); v < M.n; v += gsize()) {
-    const int g = M.gmap[v];
+  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+    const int v = v0 + lane_id();
     bool isb = false;
-    for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
-    M.key[v] = isb ? 0ull : FP_UNSET;
-    if (isb) M.fa[atomicAdd(&M.fcnt[0], 1)] = v;
+    if (v < M.n) {
+      const int g = M.gmap[v];
+      for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
+      M.key[v] = isb ? 0ull : FP_UNSET;
+    }
+    const int slot = wave_append(&M.fcnt[0], isb);
+    if (isb) M.fa[slot] = v;
   }
 }
 __global__ void k_lloyd_best(const FpMesh* __restrict__ Mp) {
@@ -272,17 +290,26 @@ __global__ void k_user_gmap(const FpMesh* __restrict__ Mp) {
 // ==========================================================================
 __global__ void k_patch_count(const FpMesh* __restrict__ Mp) {
   MESH;
-  for (int v = gtid(); v < M.n; v += gsize()) {
-    const int g = M.gmap[v];
-    atomicAdd(&M.pcnt[g], 1);
+  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+    const int v = v0 + lane_id();
+    const bool act = v < M.n;
+    const int g = act ? M.gmap[v] : 0;
     bool isb = false;
-    for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
-    if (isb) M.bnd[atomicAdd(&C->nbnd, 1)] = v;
+    if (act)
+      for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
+    (void)wave_append_keyed(M.pcnt, g, act);
+    const int slot = wave_append(&C->nbnd, isb);
+    if (isb) M.bnd[slot] = v;
   }
 }
 __global__ void k_patch_scatter(const FpMesh* __restrict__ Mp) {
   MESH;
-  for (int v = gtid(); v < M.n; v += gsize()) M.pvtx[atomicAdd(&M.pcnt[M.gmap[v]], 1)] = v;
+  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+    const int v = v0 + lane_id();
+    const bool act = v < M.n;
+    const int slot = wave_append_keyed(M.pcnt, act ? M.gmap[v] : 0, act);
+    if (act) M.pvtx[slot] = v;
+  }
 }
 // distinct neighbour patches of patch p, ascending, by repeated wave-wide
 // minimum over the foreign neighbours of its members
@@ -417,7 +444,14 @@ __global__ void k_nsize(const FpMesh* __restrict__ Mp, int nn) {
       fp_fail(C, FP_E_INTERNAL, FP_SITE_NODE_OF, v);
       M.node_of[v] = 0;
     }
-    atomicAdd(&M.nsize[M.node_of[v]], 1);
+  }
+}
+__global__ void k_nsize_count(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+    const int v = v0 + lane_id();
+    const bool act = v < M.n;
+    (void)wave_append_keyed(M.nsize, act ? M.node_of[v] : 0, act);
   }
 }
 __global__ void k_sched_place(const FpMesh* __restrict__ Mp, int nn, int D) {
@@ -434,7 +468,12 @@ __global__ void k_nbegin(const FpMesh* __restrict__ Mp, int nn, int D) {
 }
 __global__ void k_scatter(const FpMesh* __restrict__ Mp) {
   MESH;
-  for (int v = gtid(); v < M.n; v += gsize()) M.gbuf[atomicAdd(&M.ncur[M.node_of[v]], 1)] = v;
+  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+    const int v = v0 + lane_id();
+    const bool act = v < M.n;
+    const int slot = wave_append_keyed(M.ncur, act ? M.node_of[v] : 0, act);
+    if (act) M.gbuf[slot] = v;
+  }
 }
 
 // ==========================================================================
@@ -754,6 +793,7 @@ fp_status run_job(Job& J) {
   J.mark(4);
   hipLaunchKernelGGL(k_fill, B(nn), T, 0, st, J.hm.nsize, nn, 0);
   hipLaunchKernelGGL(k_nsize, B(n), T, 0, st, dm, nn);
+  hipLaunchKernelGGL(k_nsize_count, B(n), T, 0, st, dm);
   hipLaunchKernelGGL(k_sched_place, B(nn), T, 0, st, dm, nn, D);
   J.check();
   J.scan(J.hm.sbuf, J.hm.sbuf, nn, &C->tot);

@@ -52,6 +52,12 @@ enum {
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
+// Orders memory operations between the lanes of one wave (code where a wave
+// owns its data: the per-node stages).  The lanes of a wave issue their
+// memory operations together and in program order, so this scope needs no
+// wait for outstanding stores, unlike a workgroup fence.
+__device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
+
 // ---------------------------------------------------------------- wave64
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
 #pragma unroll
@@ -102,6 +108,41 @@ __device__ __forceinline__ int wave_incl_scan(int x) {
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 __device__ __forceinline__ int popc32(uint32_t x) { return __popc(x); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const int l = lane_id();
+  return l ? (~0ull >> (64 - l)) : 0ull;
+}
+
+// Append to a list whose length is *ctr: one atomic per wave instead of one
+// per item.  Call with the whole wave; returns the slot of a lane with `pred`.
+__device__ __forceinline__ int wave_append(int* ctr, bool pred) {
+  const uint64_t bal = ballot64(pred);
+  int base = 0;
+  if (bal) {
+    const int leader = __builtin_ctzll(bal);
+    if (lane_id() == leader) base = atomicAdd(ctr, popc64(bal));
+    base = __shfl(base, leader, 64);
+  }
+  return base + popc64(bal & lanemask_lt());
+}
+
+// Same for per-key counters ctr[key]: one atomic per distinct key present
+// in the wave (mesh vertices of a wave mostly share a few patches or nodes).
+__device__ __forceinline__ int wave_append_keyed(int* ctr, int key, bool pred) {
+  uint64_t pending = ballot64(pred);
+  int slot = 0;
+  while (pending) {
+    const int leader = __builtin_ctzll(pending);
+    const int lk = __shfl(key, leader, 64);
+    const uint64_t grp = ballot64(pred && key == lk) & pending;
+    int base = 0;
+    if (lane_id() == leader) base = atomicAdd(&ctr[lk], popc64(grp));
+    base = __shfl(base, leader, 64);
+    if ((grp >> lane_id()) & 1ull) slot = base + popc64(grp & lanemask_lt());
+    pending &= ~grp;
+  }
+  return slot;
+}
 
 // ---------------------------------------------------------------- workgroup
 // exclusive scan of one value per thread over the workgroup; returns the

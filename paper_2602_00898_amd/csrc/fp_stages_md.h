@@ -23,11 +23,6 @@
 #define FP_KEY_INF 0xFFFFFFFFu
 #define FP_MD_MAXM 65535  // 16-bit local ids
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  const int l = lane_id();
-  return l ? (~0ull >> (64 - l)) : 0ull;
-}
-
 // device-wide bump allocation from the fallback pool (32-bit words)
 __device__ __forceinline__ unsigned* pool_alloc(const FpMesh& M, unsigned long long words) {
   unsigned long long off = 0;
@@ -105,7 +100,7 @@ __device__ __forceinline__ void md_refresh_all_groups(MdBit& B) {
     if (lane_id() == 0) B.gmin[g] = k;
     if (lane_id() == 0) B.dl[g] = 0;
   }
-  __threadfence_block();
+  wave_fence();
 }
 
 __device__ __forceinline__ uint32_t md_argmin(const uint32_t* gmin, int G) {
@@ -128,7 +123,7 @@ __device__ __forceinline__ void md_refresh_dirty(uint32_t* key, uint32_t* gmin, 
     }
     nd += popc64(bal);
   }
-  __threadfence_block();
+  wave_fence();
   for (int j = 0; j < nd; j++) {
     const int g = dl[G + j];
     const int i = g * 64 + lane_id();
@@ -136,7 +131,7 @@ __device__ __forceinline__ void md_refresh_dirty(uint32_t* key, uint32_t* gmin, 
     k = wave_min_u32(k);
     if (lane_id() == 0) gmin[g] = k;
   }
-  __threadfence_block();
+  wave_fence();
 }
 
 // Run minimum degree steps on a BIT layout until every vertex is ordered.
@@ -161,7 +156,7 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
       B.key[p] = FP_KEY_INF;
       B.dl[p >> 6] = 1;
     }
-    __threadfence_block();
+    wave_fence();
     // neighbours of p among the remaining vertices, word by word
     int nnzw = 0;
     const uint32_t* rp = B.rows + (long long)p * W;
@@ -173,7 +168,7 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
       if (x) B.nzw[nnzw + popc64(bal & lanemask_lt())] = w;
       nnzw += popc64(bal);
     }
-    __threadfence_block();
+    wave_fence();
     int k = 0;
     for (int j0 = 0; j0 < nnzw; j0 += 64) {
       const int j = j0 + lane;
@@ -189,7 +184,7 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
       }
       k += __shfl(inc, 63, 64);
     }
-    __threadfence_block();
+    wave_fence();
     // the neighbours become a clique: OR the pivot row into theirs
     for (int i = lane; i < k; i += 64) {
       const int u = B.nbl[i];
@@ -209,7 +204,7 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
       B.key[u] = (deg << 16) | (uint32_t)u;
       B.dl[u >> 6] = 1;
     }
-    __threadfence_block();
+    wave_fence();
     md_refresh_dirty(B.key, B.gmin, B.dl, B.m, B.G);
   }
 }
@@ -253,7 +248,7 @@ __device__ __forceinline__ void md_sp_carve(MdSp& S, char* mem, int m, int C) {
 // sort the node's vertex ids (LDS bitonic sort over the next power of two)
 __device__ __forceinline__ void wave_sort_ids(int* a, int m, int np2) {
   for (int i = m + lane_id(); i < np2; i += 64) a[i] = 0x7FFFFFFF;
-  __threadfence_block();
+  wave_fence();
   for (int k = 2; k <= np2; k <<= 1)
     for (int j = k >> 1; j > 0; j >>= 1) {
       for (int i = lane_id(); i < np2; i += 64) {
@@ -267,7 +262,7 @@ __device__ __forceinline__ void wave_sort_ids(int* a, int m, int np2) {
           }
         }
       }
-      __threadfence_block();
+      wave_fence();
     }
 }
 
@@ -280,7 +275,7 @@ __device__ __forceinline__ void md_bit_build(const FpMesh& M, MdBit& B, int t, c
     B.alive[w] = hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
   }
   for (int g = lane_id(); g < 2 * B.G; g += 64) B.dl[g] = 0;
-  __threadfence_block();
+  wave_fence();
   for (int i = lane_id(); i < m; i += 64) {
     const int v = vmap[i];
     uint32_t* ri = B.rows + (long long)i * W;
@@ -294,7 +289,7 @@ __device__ __forceinline__ void md_bit_build(const FpMesh& M, MdBit& B, int t, c
     for (int w = 0; w < W; w++) d += popc32(ri[w]);
     B.key[i] = ((uint32_t)d << 16) | (uint32_t)i;
   }
-  __threadfence_block();
+  wave_fence();
   md_refresh_all_groups(B);
 }
 
@@ -313,7 +308,7 @@ __device__ __forceinline__ void md_sp_to_bit(const FpMesh& M, char* mem, int na,
     B.alive[w] = hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
   }
   for (int g = lane_id(); g < 2 * B.G; g += 64) B.dl[g] = 0;
-  __threadfence_block();
+  wave_fence();
   for (int i = lane_id(); i < m; i += 64) {
     const int r = ni[i];
     if (r < 0) continue;
@@ -325,7 +320,7 @@ __device__ __forceinline__ void md_sp_to_bit(const FpMesh& M, char* mem, int na,
     }
     B.key[r] = ((uint32_t)l << 16) | (uint32_t)r;
   }
-  __threadfence_block();
+  wave_fence();
   md_refresh_all_groups(B);
   md_bit_run(M, B, vm2, pos, na);
 }
@@ -362,20 +357,20 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
   if (4ll * np2 <= slice_bytes) {
     int* a = (int*)slice;
     for (int i = lane_id(); i < m; i += 64) a[i] = V[i];
-    __threadfence_block();
+    wave_fence();
     wave_sort_ids(a, m, np2);
     for (int i = lane_id(); i < m; i += 64) V[i] = a[i];
   } else {
     int* a = (int*)pool_alloc(M, np2);
     if (!a) return;
     for (int i = lane_id(); i < m; i += 64) a[i] = V[i];
-    __threadfence_block();
+    wave_fence();
     wave_sort_ids(a, m, np2);
     for (int i = lane_id(); i < m; i += 64) V[i] = a[i];
   }
-  __threadfence_block();
+  wave_fence();
   for (int i = lane_id(); i < m; i += 64) M.lidx[V[i]] = i;
-  __threadfence_block();
+  wave_fence();
 
   const int mbit = md_bit_max(slice_bytes);
   if (m <= mbit) {
@@ -416,7 +411,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       S.len[i] = (uint16_t)min(len, C);
       S.key[i] = ((uint32_t)len << 16) | (uint32_t)i;
     }
-    __threadfence_block();
+    wave_fence();
     sparse_ok = !ballot64(over);
   }
   int done = 0;           // vertices already ordered
@@ -429,7 +424,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       k = wave_min_u32(k);
       if (lane_id() == 0) S.gmin[g] = k;
     }
-    __threadfence_block();
+    wave_fence();
     while (na > 0 && na > mbit) {
       const uint32_t km = md_argmin(S.gmin, S.G);
       const int p = (int)(km & 0xFFFFu);
@@ -464,7 +459,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         S.dl[p >> 6] = 1;
       }
       for (int i = lane_id(); i < kp; i += 64) S.nbl[i] = rpv[i];
-      __threadfence_block();
+      wave_fence();
       for (int i = lane_id(); i < kp; i += 64) {
         const int u = S.nbl[i];
         uint16_t* ru = S.rows + (long long)u * C;
@@ -486,7 +481,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         S.key[u] = ((uint32_t)lu << 16) | (uint32_t)u;
         S.dl[u >> 6] = 1;
       }
-      __threadfence_block();
+      wave_fence();
       md_refresh_dirty(S.key, S.gmin, S.dl, m, S.G);
       done++;
       na--;
@@ -511,12 +506,12 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         if (i < m) ni[i] = al ? run + popc64(bal & lanemask_lt()) : -1;
         run += popc64(bal);
       }
-      __threadfence_block();
+      wave_fence();
       int* vm2 = (int*)pool_alloc(M, na);
       if (!vm2) goto fail;
       for (int i = lane_id(); i < m; i += 64)
         if (ni[i] >= 0) vm2[ni[i]] = vmap[i];
-      __threadfence_block();
+      wave_fence();
       // two call sites, so each keeps one address space (LDS or global)
       if (na <= mbit) {
         md_sp_to_bit(M, slice, na, m, C, srows, slen, ni, vm2, pos0 + done);

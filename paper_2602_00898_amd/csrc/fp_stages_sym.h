@@ -230,7 +230,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     nc += __shfl(inc, 63, 64);
   }
   for (int i = nc + lane_id(); i < np2; i += 64) V.bd[i] = 0x7FFFFFFF;
-  __threadfence_block();
+  wave_fence();
   wave_sort_ids(V.bd, np2, np2);
   int nbd = 0;
   for (int i0 = 0; i0 < np2; i0 += 64) {
@@ -239,9 +239,9 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     const bool keep = x != 0x7FFFFFFF && (i == 0 || V.bd[i - 1] != x);
     const uint64_t bal = ballot64(keep);
     const int dst = nbd + popc64(bal & lanemask_lt());  // dst <= i: in place
-    __threadfence_block();
+    wave_fence();
     if (keep) V.bd[dst] = x;
-    __threadfence_block();
+    wave_fence();
     nbd += popc64(bal);
   }
   const int F = m + nbd;
@@ -281,7 +281,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     }
   }
   for (int k = lane_id(); k < m; k += 64) V.head[k] = -1;
-  __threadfence_block();
+  wave_fence();
   // 3. incoming elements: one row each, queued on their least position
   int npass = 0, e = 0;
   bool bad3 = false;
@@ -293,7 +293,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
       const int r = m + e;
       uint32_t* row = V.rows + (long long)r * stride;
       for (int w = lane_id(); w < FW; w += 64) row[w] = 0u;
-      __threadfence_block();
+      wave_fence();
       uint32_t fmin = 0xFFFFFFFFu;
       for (int i = lane_id(); i < len; i += 64) {
         const int f = sym_findex(src[off + 1 + i], b0, e0, m, V.bd, nbd);
@@ -305,7 +305,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
         }
       }
       fmin = wave_min_u32(fmin);
-      __threadfence_block();
+      wave_fence();
       if (fmin != 0xFFFFFFFFu) {
         if ((int)fmin < m) {
           if (lane_id() == 0) {
@@ -317,7 +317,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
           npass++;
         }
       }
-      __threadfence_block();
+      wave_fence();
       e++;
       off += 1 + len;
     }
@@ -415,7 +415,7 @@ __device__ __forceinline__ void sym_elim(const FpMesh& M, int t) {
       M.vpar[b0 + k] = par;
     }
     if (first != 0xFFFFFFFFu && (int)first >= m) nout++;
-    __threadfence_block();  // the row, the queue links and outl reach every lane
+    wave_fence();  // the row, the queue links and outl reach every lane
   }
   if (lane_id() == 0) V.hdr[SH_NOUT] = nout;
 }
