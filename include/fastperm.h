@@ -152,6 +152,63 @@ int fp_stage_count(void);
 const char* fp_stage_name(int i);
 fp_status fp_stage_times(fp_handle* h, float* ms, int32_t n);
 
+/* ---------------------------------------------------------------------
+ * Batches: many independent matrices (the paper orders meshes of very
+ * different sizes, Sec. 6).  Matrix i is A[i] with options opts[i],
+ * optional user grouping user_gmap[i] (user_gmap itself may be NULL) and
+ * outputs out[i]; its result is exactly what fp_order gives for it alone.
+ * The matrices run concurrently on `lanes` streams owned by the handle
+ * (1 <= lanes <= 64; one host worker thread per lane, largest matrices
+ * first).  All pointers in A/out/user_gmap are device pointers owned by the
+ * caller.
+ * fp_query_batch: workspace size for `lanes` lanes (lanes slices of
+ * *lane_bytes each, enough for the largest matrix) and the largest
+ * node_begin/node_size capacity among the matrices.
+ * fp_order_batch: runs after prior work on `stream`; `stream` waits for the
+ * whole batch.  Returns when every matrix is done, with the first failing
+ * status; out[i].status holds each matrix's device error bits. */
+fp_status fp_query_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A, const fp_options* opts,
+                         int32_t lanes, size_t* workspace_bytes, size_t* lane_bytes,
+                         int32_t* max_nodes);
+fp_status fp_order_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A,
+                         const int32_t* const* user_gmap, const fp_options* opts, void* workspace,
+                         size_t ws_bytes, fp_result* out, int32_t lanes, void* stream);
+
+/* ---------------------------------------------------------------------
+ * Serving: a request loop that admits ordering requests of any size while
+ * others run.  A request is admitted (first come, first served) when one of
+ * max_slots worker slots is free and its device footprint (input copy,
+ * workspace, outputs) fits in what is left of hbm_budget bytes of device
+ * memory, which the server allocates once at creation and keeps; the
+ * requests in flight overlap on the device, each on its own stream.
+ * Inputs are HOST arrays; they must stay valid until fp_server_wait returns
+ * for the ticket.  Results are the same as fp_order's for the matrix alone.
+ */
+typedef struct fp_server fp_server;
+
+typedef struct {
+  int64_t n;
+  int64_t nnz;
+  const int64_t* rowptr; /* host, n+1 entries */
+  const int32_t* colind; /* host, nnz entries */
+} fp_host_csr;
+
+/* FP_ERR_OOM if hbm_budget cannot be allocated. */
+fp_status fp_server_create(fp_handle* h, size_t hbm_budget, int32_t max_slots, fp_server** s);
+/* Queue a request; FP_ERR_BUSY if its footprint exceeds the whole budget. */
+fp_status fp_server_submit(fp_server* s, const fp_host_csr* A, const fp_options* opts,
+                           uint64_t* ticket);
+/* *done = 1 once the request has finished (no wait). */
+fp_status fp_server_test(fp_server* s, uint64_t ticket, int32_t* done);
+/* Wait for a request, copy its results to host arrays (n entries each; any
+ * output pointer may be NULL) and release the ticket.  latency_s is the
+ * time from submission to completion.  Returns the request's status. */
+fp_status fp_server_wait(fp_server* s, uint64_t ticket, int32_t* perm, int32_t* iperm,
+                         int32_t* parent, int32_t* colcount, int64_t* nnzL, double* latency_s);
+/* Finish the requests in flight, release the device memory and threads.
+ * Tickets not yet waited for are dropped. */
+fp_status fp_server_destroy(fp_server* s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,6 +16,7 @@
 #include <new>
 
 #include "../../include/fastperm.h"
+#include "fp_handle.h"
 #include "fp_plan.h"
 #include "fp_stages_sym.h"
 
@@ -573,18 +574,8 @@ __global__ void k_finish(const FpMesh* __restrict__ Mp, int nn) {
 // ==========================================================================
 // host side
 // ==========================================================================
-#define FP_NSTAGE 8
 static const char* const kStageNames[FP_NSTAGE] = {
     "ingest", "patches", "quotient", "septree", "group", "local_orders", "symbolic", "expand"};
-
-struct fp_handle {
-  int device;
-  int ncu;
-  int lds_bytes;
-  int* host;  // pinned: scalars read back between stages, and the job copy
-  hipEvent_t ev[FP_NSTAGE + 1];
-  bool timed;  // the last call recorded stage events
-};
 
 namespace {
 
@@ -898,6 +889,12 @@ fp_status fp_create(fp_handle** h) {
 
 fp_status fp_destroy(fp_handle* h) {
   if (!h) return FP_OK;
+  for (FpLane& L : h->lanes) {
+    (void)hipStreamSynchronize(L.st);
+    (void)hipStreamDestroy(L.st);
+    (void)fp_destroy(L.h);
+  }
+  h->lanes.clear();
   for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);
   if (h->host) (void)hipHostFree(h->host);
   delete h;

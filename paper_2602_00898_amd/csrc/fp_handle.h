@@ -1,0 +1,31 @@
+// fp_handle.h -- the handle behind the C ABI (host side): device properties,
+// the pinned buffer scalars are read through, stage timing events, and the
+// lanes (internal streams with their own handles) of the batched and served
+// calls.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <vector>
+
+#define FP_NSTAGE 8
+
+struct fp_handle;
+
+// one lane: a handle of its own (pinned buffer, events) and a stream
+struct FpLane {
+  fp_handle* h;
+  hipStream_t st;
+};
+
+struct fp_handle {
+  int device;
+  int ncu;
+  int lds_bytes;
+  int* host;  // pinned: scalars read back between stages, and the job copy
+  hipEvent_t ev[FP_NSTAGE + 1];
+  bool timed;  // the last call recorded stage events
+  std::mutex lanes_mu;
+  std::vector<FpLane> lanes;  // created on demand by the batched calls
+};

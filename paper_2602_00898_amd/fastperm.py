@@ -52,6 +52,11 @@ class Result(C.Structure):
                 ("status", C.c_void_p), ("max_nodes", C.c_int32)]
 
 
+class HostCsr(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
+                ("colind", C.c_void_p)]
+
+
 _lib = None
 
 
@@ -81,6 +86,19 @@ def lib():
         L.fp_stage_name.restype = C.c_char_p
         L.fp_stage_name.argtypes = [C.c_int]
         L.fp_stage_times.argtypes = [vp, C.POINTER(C.c_float), C.c_int32]
+        L.fp_query_batch.argtypes = [vp, C.c_int32, C.POINTER(Csr), C.POINTER(Options), C.c_int32,
+                                     C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
+                                     C.POINTER(C.c_int32)]
+        L.fp_order_batch.argtypes = [vp, C.c_int32, C.POINTER(Csr), C.POINTER(vp),
+                                     C.POINTER(Options), vp, C.c_size_t, C.POINTER(Result),
+                                     C.c_int32, vp]
+        L.fp_server_create.argtypes = [vp, C.c_size_t, C.c_int32, C.POINTER(vp)]
+        L.fp_server_submit.argtypes = [vp, C.POINTER(HostCsr), C.POINTER(Options),
+                                       C.POINTER(C.c_uint64)]
+        L.fp_server_test.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int32)]
+        L.fp_server_wait.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, C.POINTER(C.c_int64),
+                                     C.POINTER(C.c_double)]
+        L.fp_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -203,3 +221,111 @@ def stage_times(handle):
     ms = (C.c_float * k)()
     _check(L.fp_stage_times(handle.h, ms, k), "fp_stage_times")
     return {L.fp_stage_name(i).decode(): float(ms[i]) for i in range(k)}
+
+
+def _alloc_out(n, max_nodes, block_size, dev):
+    i32 = dict(dtype=torch.int32, device=dev)
+    return dict(perm=torch.empty(n, **i32), iperm=torch.empty(n, **i32),
+                parent=torch.empty(n, **i32), colcount=torch.empty(n, **i32),
+                nnzL=torch.zeros(1, dtype=torch.int64, device=dev),
+                node_begin=torch.empty(max_nodes, **i32), node_size=torch.empty(max_nodes, **i32),
+                gmap=torch.empty(max(n // block_size, 1), **i32),
+                n_nodes=torch.zeros(1, **i32), status=torch.zeros(1, dtype=torch.int32, device=dev))
+
+
+def _result(out):
+    return Result(_ptr(out["perm"]), _ptr(out["iperm"]), _ptr(out["parent"]), _ptr(out["colcount"]),
+                  _ptr(out["nnzL"]), _ptr(out["node_begin"]), _ptr(out["node_size"]),
+                  _ptr(out["gmap"]), _ptr(out["n_nodes"]), _ptr(out["status"]),
+                  int(out["node_begin"].numel()))
+
+
+def order_batch(meshes, *, lanes=8, handle=None, stream=None):
+    """Order many matrices in one call (fp_order_batch).  `meshes` is a list
+    of dicts with device tensors rowptr, colind, the size n and optional
+    patch_size, seed, schedule, block_size, lloyd_iters, user_gmap.  Returns
+    one output dict per matrix, as order() does."""
+    L = lib()
+    k = len(meshes)
+    handle = handle or Handle()
+    if k == 0:
+        return []
+    A = (Csr * k)()
+    O = (Options * k)()
+    R = (Result * k)()
+    G = (C.c_void_p * k)()
+    keep, outs = [], []
+    for i, m in enumerate(meshes):
+        A[i] = make_csr(m["n"], m["rowptr"], m["colind"])
+        O[i] = options(m.get("patch_size", 512), m.get("schedule", SCHED_LEVEL),
+                       m.get("block_size", 1), m.get("lloyd_iters", 1), m.get("seed", 0))
+        ug = m.get("user_gmap")
+        G[i] = None if ug is None else ug.data_ptr()
+        keep.append(ug)
+    ws, lane_bytes, mx = C.c_size_t(), C.c_size_t(), C.c_int32()
+    _check(L.fp_query_batch(handle.h, k, A, O, lanes, C.byref(ws), C.byref(lane_bytes),
+                            C.byref(mx)), "fp_query_batch")
+    dev = meshes[0]["colind"].device
+    for i, m in enumerate(meshes):
+        outs.append(_alloc_out(m["n"], mx.value, m.get("block_size", 1), dev))
+        R[i] = _result(outs[i])
+    wbuf = handle.workspace(ws.value, dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    rc = L.fp_order_batch(handle.h, k, A, G, O, _ptr(wbuf), ws.value, R, lanes, C.c_void_p(s))
+    if rc != 0:
+        raise FpError(rc, "fp_order_batch")
+    return outs
+
+
+class Server:
+    """Request server (fp_server_*): host CSR in, host results out."""
+
+    def __init__(self, hbm_budget, max_slots, handle=None):
+        self.handle = handle or Handle()
+        s = C.c_void_p()
+        _check(lib().fp_server_create(self.handle.h, int(hbm_budget), int(max_slots), C.byref(s)),
+               "fp_server_create")
+        self.s = s
+        self._keep = {}
+
+    def submit(self, rowptr, colind, n, **kw):
+        import numpy as np
+        rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+        ci = np.ascontiguousarray(colind, dtype=np.int32)
+        A = HostCsr(n, ci.size, rp.ctypes.data, ci.ctypes.data if ci.size else None)
+        o = options(kw.get("patch_size", 512), kw.get("schedule", SCHED_LEVEL),
+                    kw.get("block_size", 1), kw.get("lloyd_iters", 1), kw.get("seed", 0))
+        t = C.c_uint64()
+        _check(lib().fp_server_submit(self.s, C.byref(A), C.byref(o), C.byref(t)),
+               "fp_server_submit")
+        self._keep[t.value] = (rp, ci, n)
+        return t.value
+
+    def test(self, ticket):
+        d = C.c_int32()
+        _check(lib().fp_server_test(self.s, ticket, C.byref(d)), "fp_server_test")
+        return bool(d.value)
+
+    def wait(self, ticket):
+        import numpy as np
+        n = self._keep[ticket][2]
+        r = {k: np.empty(n, np.int32) for k in ("perm", "iperm", "parent", "colcount")}
+        nz, lat = C.c_int64(), C.c_double()
+        rc = lib().fp_server_wait(self.s, ticket, r["perm"].ctypes.data, r["iperm"].ctypes.data,
+                                  r["parent"].ctypes.data, r["colcount"].ctypes.data,
+                                  C.byref(nz), C.byref(lat))
+        self._keep.pop(ticket, None)
+        if rc != 0:
+            raise FpError(rc, "fp_server_wait")
+        r["nnzL"] = nz.value
+        r["latency_s"] = lat.value
+        return r
+
+    def close(self):
+        if getattr(self, "s", None) is not None and _lib is not None:
+            _lib.fp_server_destroy(self.s)
+            self.s = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,119 @@
+"""GPU: batched and served orderings through the C ABI.
+
+A matrix ordered inside a batch, or by the server next to other requests,
+must give exactly the result it gets alone, which is the oracle's.
+"""
+
+import numpy as np
+import pytest
+
+from paper_2602_00898_amd import meshgen as mg
+from tests.gpu_util import compare, cpu_order, gpu_order, mesh, say
+
+pytestmark = pytest.mark.gpu
+
+# (H, W, torus, seed, flip, S): mixed sizes, shapes and patch targets
+MIX = [(20, 20, True, 3, 0.05, 40), (9, 30, False, 4, 0.0, 16), (33, 33, True, 5, 0.05, 64),
+       (5, 5, False, 6, 0.0, 3), (64, 48, True, 7, 0.05, 128), (3, 3, True, 8, 0.0, 2),
+       (100, 90, False, 9, 0.05, 256), (41, 17, True, 10, 0.0, 50)]
+
+
+def _to_dict(out, A, block_size=1):
+    r = {k: v.cpu().numpy() for k, v in out.items()}
+    nn = int(r["n_nodes"][0])
+    r["node_begin"] = r["node_begin"][:nn]
+    r["node_size"] = r["node_size"][:nn]
+    r["gmap"] = r["gmap"][: A.n // block_size]
+    r["nnzL"] = int(r["nnzL"][0])
+    return r
+
+
+def _device_meshes(cases):
+    import torch
+    dev = torch.device("cuda:0")
+    return [dict(rowptr=torch.from_numpy(A.rowptr).to(dev), colind=torch.from_numpy(A.colind).to(dev),
+                 n=A.n, patch_size=S, seed=s) for A, S, s in cases]
+
+
+@pytest.mark.parametrize("lanes", [1, 3, 8])
+def test_batch_matches_oracle_and_single(lanes):
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+    cases = [(mesh(H, W, t, s, f), S, s) for H, W, t, s, f, S in MIX]
+    say(f"[batch] {len(cases)} meshes, lanes={lanes}")
+    outs = fpm.order_batch(_device_meshes(cases), lanes=lanes)
+    torch.cuda.synchronize()
+    for (A, S, s), out in zip(cases, outs):
+        g = _to_dict(out, A)
+        compare(g, cpu_order(A, patch_size=S, seed=s), f"batch n={A.n}")
+        compare(g, gpu_order(A, patch_size=S, seed=s), f"batch vs single n={A.n}")
+
+
+def test_batch_blocks_user_groups_and_options():
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+    dev = torch.device("cuda:0")
+    B = mg.block_expand(mesh(16, 16, True, 11), 3)
+    P = mesh(30, 30, False, 12)
+    g = (np.arange(P.n) // 37).astype(np.int32)
+    Q = mesh(24, 20, True, 13, 0.05)
+    meshes = [
+        dict(rowptr=torch.from_numpy(B.rowptr).to(dev), colind=torch.from_numpy(B.colind).to(dev),
+             n=B.n, patch_size=40, seed=11, block_size=3),
+        dict(rowptr=torch.from_numpy(P.rowptr).to(dev), colind=torch.from_numpy(P.colind).to(dev),
+             n=P.n, patch_size=64, user_gmap=torch.from_numpy(g).to(dev)),
+        dict(rowptr=torch.from_numpy(Q.rowptr).to(dev), colind=torch.from_numpy(Q.colind).to(dev),
+             n=Q.n, patch_size=30, seed=13, schedule=1, lloyd_iters=2),
+    ]
+    say("[batch] block / user groups / post order")
+    outs = fpm.order_batch(meshes, lanes=3)
+    torch.cuda.synchronize()
+    compare(_to_dict(outs[0], B, 3), cpu_order(B, patch_size=40, seed=11, block_size=3), "block3")
+    compare(_to_dict(outs[1], P), cpu_order(P, patch_size=64, user_gmap=g), "user groups")
+    compare(_to_dict(outs[2], Q), cpu_order(Q, patch_size=30, seed=13, schedule=1, lloyd_iters=2),
+            "post order, lloyd 2")
+
+
+def test_server_same_alone_and_in_mix():
+    from paper_2602_00898_amd import fastperm as fpm
+    target = mesh(70, 60, True, 21, 0.05)
+    S = 100
+    srv = fpm.Server(hbm_budget=1 << 30, max_slots=4)
+    try:
+        say("[server] target alone")
+        t = srv.submit(target.rowptr, target.colind, target.n, patch_size=S, seed=21)
+        alone = srv.wait(t)
+        say("[server] target among 11 other requests")
+        mix = [(mesh(H, W, tt, s, f), SS, s) for H, W, tt, s, f, SS in MIX]
+        tickets = [srv.submit(A.rowptr, A.colind, A.n, patch_size=SS, seed=s) for A, SS, s in mix[:4]]
+        tt_target = srv.submit(target.rowptr, target.colind, target.n, patch_size=S, seed=21)
+        tickets += [srv.submit(A.rowptr, A.colind, A.n, patch_size=SS, seed=s) for A, SS, s in mix[4:]]
+        inmix = srv.wait(tt_target)
+        for (A, SS, s), tk in zip(mix, tickets):
+            r = srv.wait(tk)
+            c = cpu_order(A, patch_size=SS, seed=s)
+            for k in ("perm", "iperm", "parent", "colcount"):
+                assert np.array_equal(r[k], c[k]), f"server n={A.n}: {k}"
+            assert r["nnzL"] == c["nnzL"]
+            assert r["latency_s"] > 0
+    finally:
+        srv.close()
+    c = cpu_order(target, patch_size=S, seed=21)
+    for k in ("perm", "iperm", "parent", "colcount"):
+        assert np.array_equal(alone[k], c[k]), f"alone: {k}"
+        assert np.array_equal(inmix[k], alone[k]), f"in the mix: {k}"
+    assert alone["nnzL"] == inmix["nnzL"] == c["nnzL"]
+
+
+def test_server_refuses_oversize_request():
+    from paper_2602_00898_amd import fastperm as fpm
+    A = mesh(64, 64, True, 22)
+    srv = fpm.Server(hbm_budget=1 << 16, max_slots=1)
+    try:
+        with pytest.raises(fpm.FpError) as e:
+            srv.submit(A.rowptr, A.colind, A.n, patch_size=64)
+        assert e.value.code == 7  # FP_ERR_BUSY
+    finally:
+        srv.close()
