@@ -152,6 +152,14 @@ int fp_stage_count(void);
 const char* fp_stage_name(int i);
 fp_status fp_stage_times(fp_handle* h, float* ms, int32_t n);
 
+/* Time one kernel of the pipeline: every launch of the kernel named `name`
+ * (e.g. "k_md"; NULL or "" stops) in later fp_order calls on this handle is
+ * bracketed by events on the call's stream.  fp_kernel_time waits for the
+ * last call's events and returns the summed device time and the number of
+ * launches of that kernel in it. */
+fp_status fp_time_kernel(fp_handle* h, const char* name);
+fp_status fp_kernel_time(fp_handle* h, float* total_ms, int32_t* launches);
+
 /* ---------------------------------------------------------------------
  * Batches: many independent matrices (the paper orders meshes of very
  * different sizes, Sec. 6).  Matrix i is A[i] with options opts[i],

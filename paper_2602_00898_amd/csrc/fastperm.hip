@@ -611,6 +611,18 @@ fp_status map_err(unsigned e) {
 
 // one ordering job: launches in stream order, reads scalars through the
 // handle's pinned buffer
+// every launch of the pipeline goes through these, so that one kernel can be
+// timed with events on the call's stream (fp_time_kernel)
+#define FP_LAUNCH_(JOB, k, g, b, l, s, ...)                 \
+  do {                                                     \
+    const bool tk_ = (JOB).tk(#k);                         \
+    if (tk_) (JOB).tk_begin();                             \
+    hipLaunchKernelGGL(k, g, b, l, s, __VA_ARGS__);        \
+    if (tk_) (JOB).tk_end();                               \
+  } while (0)
+#define FPLM(...) FP_LAUNCH_(*this, __VA_ARGS__)
+#define FPL(...) FP_LAUNCH_(J, __VA_ARGS__)
+
 struct Job {
   fp_handle* h;
   hipStream_t st;
@@ -619,6 +631,26 @@ struct Job {
   FpCtl* ctl;
   bool hip_failed = false;
   bool timing = false;
+
+  // timing of one kernel (fp_time_kernel): events around each of its launches
+  bool tk(const char* name) const { return h->tk_name[0] && strcmp(h->tk_name, name) == 0; }
+  void tk_begin() {
+    if ((int)h->tk_ev.size() < 2 * (h->tk_n + 1)) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+        h->tk_failed = true;
+        return;
+      }
+      h->tk_ev.push_back(a);
+      h->tk_ev.push_back(b);
+    }
+    if (hipEventRecord(h->tk_ev[2 * h->tk_n], st) != hipSuccess) h->tk_failed = true;
+  }
+  void tk_end() {
+    if ((int)h->tk_ev.size() < 2 * (h->tk_n + 1)) return;
+    if (hipEventRecord(h->tk_ev[2 * h->tk_n + 1], st) != hipSuccess) h->tk_failed = true;
+    h->tk_n++;
+  }
 
   void mark(int i) {
     if (timing && hipEventRecord(h->ev[i], st) != hipSuccess) hip_failed = true;
@@ -647,9 +679,9 @@ struct Job {
   void scan(const int* in, int* out, int n, int* total) {
     const int np = std::max(1, std::min(1024, (n + 4095) / 4096));
     const int chunk = std::max(1, (n + np - 1) / np);
-    hipLaunchKernelGGL(k_scan_part, dim3(np), dim3(FP_WG), 0, st, in, n, chunk, ctl->part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(FP_WG), 0, st, ctl->part, np, total);
-    hipLaunchKernelGGL(k_scan_apply, dim3(np), dim3(FP_WG), 0, st, in, out, n, chunk, ctl->part);
+    FPLM(k_scan_part, dim3(np), dim3(FP_WG), 0, st, in, n, chunk, ctl->part);
+    FPLM(k_scan_top, dim3(1), dim3(FP_WG), 0, st, ctl->part, np, total);
+    FPLM(k_scan_apply, dim3(np), dim3(FP_WG), 0, st, in, out, n, chunk, ctl->part);
     check();
   }
   // frontier BFS from the level-0 frontier already in place; levels are
@@ -660,15 +692,15 @@ struct Job {
     // zero (the counter array holds n+16 entries)
     for (int lvl = 0;; lvl += 8) {
       for (int k = 0; k < 8; k++)
-        hipLaunchKernelGGL(k_bfs_level, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, lvl + k);
+        FPLM(k_bfs_level, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, lvl + k);
       check();
       if (lvl + 8 > n || hip_failed || read1(&hm.fcnt[lvl + 8]) == 0) break;
     }
   }
   void grow(int nseeds) {
     const int n = hm.n;
-    hipLaunchKernelGGL(k_key_unset, dim3(blocks(n)), dim3(FP_WG), 0, st, dm);
-    hipLaunchKernelGGL(k_seed_push, dim3(blocks(nseeds)), dim3(FP_WG), 0, st, dm, nseeds);
+    FPLM(k_key_unset, dim3(blocks(n)), dim3(FP_WG), 0, st, dm);
+    FPLM(k_seed_push, dim3(blocks(nseeds)), dim3(FP_WG), 0, st, dm, nseeds);
     check();
     bfs();
   }
@@ -684,7 +716,7 @@ fp_status run_job(Job& J) {
 
   // ingest
   J.mark(0);
-  hipLaunchKernelGGL(k_ingest, B(n), T, 0, st, dm, 0);
+  FPL(k_ingest, B(n), T, 0, st, dm, 0);
   J.scan(J.hm.pcnt, J.hm.grp, n, &C->nnz_g);
   J.read(&C->err, 8);
   if (J.hip_failed) return FP_ERR_HIP;
@@ -692,51 +724,51 @@ fp_status run_job(Job& J) {
   const int nnz_g = J.h->host[5];
   if (e0) return map_err(e0);
   if (nnz_g < 0 || nnz_g > J.hm.Ecap) return FP_ERR_SIZE;
-  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, st, J.hm.grp + n, &C->nnz_g);
-  hipLaunchKernelGGL(k_ingest, B(n), T, 0, st, dm, 1);
+  FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.grp + n, &C->nnz_g);
+  FPL(k_ingest, B(n), T, 0, st, dm, 1);
   J.check();
 
   // patches
   J.mark(1);
   int P = 0;
   if (J.hm.user_gmap) {
-    hipLaunchKernelGGL(k_user_gmap, B(n), T, 0, st, dm);
+    FPL(k_user_gmap, B(n), T, 0, st, dm);
     J.check();
     P = J.read1(&C->P);
   } else if (n > 0) {
     const int P0 = (int)(((long long)n + J.hm.S - 1) / J.hm.S);
-    hipLaunchKernelGGL(k_seeds, dim3(J.blocks(P0, FP_WAVES)), T, 0, st, dm, P0);
+    FPL(k_seeds, dim3(J.blocks(P0, FP_WAVES)), T, 0, st, dm, P0);
     J.check();
     J.grow(P0);
-    hipLaunchKernelGGL(k_count_unset, B(n), T, 0, st, dm);
+    FPL(k_count_unset, B(n), T, 0, st, dm);
     J.check();
     P = P0;
     if (J.read1(&C->norphan) > 0) {
-      hipLaunchKernelGGL(k_cc_init, B(n), T, 0, st, dm);
+      FPL(k_cc_init, B(n), T, 0, st, dm);
       for (int it = 0; it < n + 1; it++) {
-        hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, &C->chg, 1, 0);
-        hipLaunchKernelGGL(k_cc_hook, B(n), T, 0, st, dm);
-        hipLaunchKernelGGL(k_cc_jump, B(n), T, 0, st, dm);
+        FPL(k_fill, dim3(1), dim3(64), 0, st, &C->chg, 1, 0);
+        FPL(k_cc_hook, B(n), T, 0, st, dm);
+        FPL(k_cc_jump, B(n), T, 0, st, dm);
         J.check();
         if (J.read1(&C->chg) == 0 || J.hip_failed) break;
       }
-      hipLaunchKernelGGL(k_cc_flags, B(n), T, 0, st, dm);
+      FPL(k_cc_flags, B(n), T, 0, st, dm);
       J.scan(J.hm.pcnt, J.hm.pcnt, n, &C->nroot);
-      hipLaunchKernelGGL(k_cc_label, B(n), T, 0, st, dm, P0);
+      FPL(k_cc_label, B(n), T, 0, st, dm, P0);
       J.check();
       P = P0 + J.read1(&C->nroot);
     }
     for (int it = 0; it < J.hm.lloyd; it++) {
-      hipLaunchKernelGGL(k_lloyd_gmap, B(n), T, 0, st, dm, P);
-      hipLaunchKernelGGL(k_lloyd_bnd, B(n), T, 0, st, dm);
+      FPL(k_lloyd_gmap, B(n), T, 0, st, dm, P);
+      FPL(k_lloyd_bnd, B(n), T, 0, st, dm);
       J.check();
       J.bfs();
-      hipLaunchKernelGGL(k_lloyd_best, B(n), T, 0, st, dm);
-      hipLaunchKernelGGL(k_lloyd_seed, B(P), T, 0, st, dm, P);
+      FPL(k_lloyd_best, B(n), T, 0, st, dm);
+      FPL(k_lloyd_seed, B(P), T, 0, st, dm, P);
       J.check();
       J.grow(P);
     }
-    hipLaunchKernelGGL(k_gmap_final, B(n), T, 0, st, dm, P);
+    FPL(k_gmap_final, B(n), T, 0, st, dm, P);
     J.check();
   }
   if (J.hip_failed) return FP_ERR_HIP;
@@ -744,23 +776,23 @@ fp_status run_job(Job& J) {
 
   // quotient graph
   J.mark(2);
-  hipLaunchKernelGGL(k_fill, B(P + 1), T, 0, st, J.hm.pcnt, P + 1, 0);
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, &C->nbnd, 1, 0);
-  hipLaunchKernelGGL(k_patch_count, B(n), T, 0, st, dm);
-  hipLaunchKernelGGL(k_copy, B(P), T, 0, st, J.hm.wp, J.hm.pcnt, P);
+  FPL(k_fill, B(P + 1), T, 0, st, J.hm.pcnt, P + 1, 0);
+  FPL(k_fill, dim3(1), dim3(64), 0, st, &C->nbnd, 1, 0);
+  FPL(k_patch_count, B(n), T, 0, st, dm);
+  FPL(k_copy, B(P), T, 0, st, J.hm.wp, J.hm.pcnt, P);
   J.check();
   J.scan(J.hm.pcnt, J.hm.pptr, P, &C->tot);
-  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, st, J.hm.pptr + P, &C->tot);
-  hipLaunchKernelGGL(k_copy, B(P), T, 0, st, J.hm.pcnt, J.hm.pptr, P);
-  hipLaunchKernelGGL(k_patch_scatter, B(n), T, 0, st, dm);
-  hipLaunchKernelGGL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, 0, st, dm, P, 0);
+  FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.pptr + P, &C->tot);
+  FPL(k_copy, B(P), T, 0, st, J.hm.pcnt, J.hm.pptr, P);
+  FPL(k_patch_scatter, B(n), T, 0, st, dm);
+  FPL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, 0, st, dm, P, 0);
   J.check();
   J.scan(J.hm.pcnt, J.hm.qptr, P, &C->nq);
-  hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, st, J.hm.qptr + P, &C->nq);
+  FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.qptr + P, &C->nq);
   const int nq = J.read1(&C->nq);
   if (J.hip_failed) return FP_ERR_HIP;
   if (nq < 0 || nq > J.hm.Ecap) return FP_ERR_SIZE;
-  hipLaunchKernelGGL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, 0, st, dm, P, 1);
+  FPL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, 0, st, dm, P, 1);
   J.check();
 
   // separator tree
@@ -769,35 +801,35 @@ fp_status run_job(Job& J) {
   while ((1ll << D) < P) D++;
   const int nn = (1 << (D + 1)) - 1;
   if (nn > J.hm.NNcap) return FP_ERR_SIZE;
-  hipLaunchKernelGGL(k_sep_init, B(std::max(n, nn)), T, 0, st, dm, P, D, nn);
+  FPL(k_sep_init, B(std::max(n, nn)), T, 0, st, dm, P, D, nn);
   for (int d = 0; d < D; d++) {
-    hipLaunchKernelGGL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
-    hipLaunchKernelGGL(k_arcs, B(n), T, 0, st, dm);
-    hipLaunchKernelGGL(k_bisect, dim3(std::min(1 << d, 4 * J.h->ncu)), T, 0, st, dm, d);
-    hipLaunchKernelGGL(k_cand, B(n), T, 0, st, dm, d);
-    hipLaunchKernelGGL(k_mark, B(n), T, 0, st, dm);
+    FPL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
+    FPL(k_arcs, B(n), T, 0, st, dm);
+    FPL(k_bisect, dim3(std::min(1 << d, 4 * J.h->ncu)), T, 0, st, dm, d);
+    FPL(k_cand, B(n), T, 0, st, dm, d);
+    FPL(k_mark, B(n), T, 0, st, dm);
     J.check();
   }
-  hipLaunchKernelGGL(k_leaves, B(n), T, 0, st, dm);
+  FPL(k_leaves, B(n), T, 0, st, dm);
 
   // grouping in schedule order
   J.mark(4);
-  hipLaunchKernelGGL(k_fill, B(nn), T, 0, st, J.hm.nsize, nn, 0);
-  hipLaunchKernelGGL(k_nsize, B(n), T, 0, st, dm, nn);
-  hipLaunchKernelGGL(k_nsize_count, B(n), T, 0, st, dm);
-  hipLaunchKernelGGL(k_sched_place, B(nn), T, 0, st, dm, nn, D);
+  FPL(k_fill, B(nn), T, 0, st, J.hm.nsize, nn, 0);
+  FPL(k_nsize, B(n), T, 0, st, dm, nn);
+  FPL(k_nsize_count, B(n), T, 0, st, dm);
+  FPL(k_sched_place, B(nn), T, 0, st, dm, nn, D);
   J.check();
   J.scan(J.hm.sbuf, J.hm.sbuf, nn, &C->tot);
-  hipLaunchKernelGGL(k_nbegin, B(nn), T, 0, st, dm, nn, D);
-  hipLaunchKernelGGL(k_scatter, B(n), T, 0, st, dm);
+  FPL(k_nbegin, B(nn), T, 0, st, dm, nn, D);
+  FPL(k_scatter, B(n), T, 0, st, dm);
   J.check();
 
   // local orders
   J.mark(5);
-  hipLaunchKernelGGL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
-  hipLaunchKernelGGL(k_md_tasks, B(nn), T, 0, st, dm, nn);
+  FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
+  FPL(k_md_tasks, B(nn), T, 0, st, dm, nn);
   for (int c = 0; c < 3; c++)
-    hipLaunchKernelGGL(k_md, dim3(2 * J.h->ncu), T, J.h->lds_bytes, st, dm, c);
+    FPL(k_md, dim3(2 * J.h->ncu), T, J.h->lds_bytes, st, dm, c);
   J.check();
   // a node whose local order failed leaves its positions unset: stop here
   {
@@ -811,18 +843,18 @@ fp_status run_job(Job& J) {
   for (int d = D; d >= 0; d--) {
     const int cnt = 1 << d;
     const dim3 G(std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * J.h->ncu)));
-    hipLaunchKernelGGL(k_sym_init, dim3(1), dim3(64), 0, st, dm, d);
-    hipLaunchKernelGGL(k_sym_prep, G, T, 0, st, dm, d);
-    hipLaunchKernelGGL(k_sym_elim, G, T, 0, st, dm, d);
-    hipLaunchKernelGGL(k_sym_emit, G, T, 0, st, dm, d);
+    FPL(k_sym_init, dim3(1), dim3(64), 0, st, dm, d);
+    FPL(k_sym_prep, G, T, 0, st, dm, d);
+    FPL(k_sym_elim, G, T, 0, st, dm, d);
+    FPL(k_sym_emit, G, T, 0, st, dm, d);
     J.check();
   }
-  hipLaunchKernelGGL(k_nnzl, B(n), T, 0, st, dm);
+  FPL(k_nnzl, B(n), T, 0, st, dm);
 
   // outputs
   J.mark(7);
-  hipLaunchKernelGGL(k_expand, B(std::max<long long>(J.hm.n_dof, nn)), T, 0, st, dm, nn);
-  hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, st, dm, nn);
+  FPL(k_expand, B(std::max<long long>(J.hm.n_dof, nn)), T, 0, st, dm, nn);
+  FPL(k_finish, dim3(1), dim3(64), 0, st, dm, nn);
   J.mark(8);
   J.check();
   return J.hip_failed ? FP_ERR_HIP : FP_OK;
@@ -876,6 +908,9 @@ fp_status fp_create(fp_handle** h) {
   }
   H->ncu = std::max(1, ncu);
   H->lds_bytes = FP_LDS_BYTES;
+  H->tk_name[0] = 0;
+  H->tk_n = 0;
+  H->tk_failed = false;
   for (int i = 0; i <= FP_NSTAGE; i++)
     if (hipEventCreate(&H->ev[i]) != hipSuccess) {
       for (int j = 0; j < i; j++) (void)hipEventDestroy(H->ev[j]);
@@ -895,6 +930,7 @@ fp_status fp_destroy(fp_handle* h) {
     (void)fp_destroy(L.h);
   }
   h->lanes.clear();
+  for (hipEvent_t e : h->tk_ev) (void)hipEventDestroy(e);
   for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
@@ -958,6 +994,8 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   J.dm = (const FpMesh*)(ws + P.o_mesh);
   J.timing = (opts->flags & FP_FLAG_TIMING) != 0;
   h->timed = false;
+  h->tk_n = 0;
+  h->tk_failed = false;
   // control block cleared, job description copied in
   const int words = (int)(sizeof(FpCtl) / 4);
   hipLaunchKernelGGL(k_fill, dim3((words + FP_WG - 1) / FP_WG), dim3(FP_WG), 0, J.st, (int*)M.ctl,
@@ -974,6 +1012,31 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
       hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, J.st, J.dm, 1);
     return s;
   }
+  return FP_OK;
+}
+
+fp_status fp_time_kernel(fp_handle* h, const char* name) {
+  if (!h) return FP_ERR_ARG;
+  if (!name) name = "";
+  if (strlen(name) >= sizeof(h->tk_name)) return FP_ERR_ARG;
+  strcpy(h->tk_name, name);
+  h->tk_n = 0;
+  return FP_OK;
+}
+
+fp_status fp_kernel_time(fp_handle* h, float* total_ms, int32_t* launches) {
+  if (!h || !total_ms) return FP_ERR_ARG;
+  if (h->tk_failed) return FP_ERR_HIP;
+  float tot = 0.f;
+  for (int i = 0; i < h->tk_n; i++) {
+    float ms = 0.f;
+    if (hipEventSynchronize(h->tk_ev[2 * i + 1]) != hipSuccess ||
+        hipEventElapsedTime(&ms, h->tk_ev[2 * i], h->tk_ev[2 * i + 1]) != hipSuccess)
+      return FP_ERR_HIP;
+    tot += ms;
+  }
+  *total_ms = tot;
+  if (launches) *launches = h->tk_n;
   return FP_OK;
 }
 

@@ -28,4 +28,9 @@ struct fp_handle {
   bool timed;  // the last call recorded stage events
   std::mutex lanes_mu;
   std::vector<FpLane> lanes;  // created on demand by the batched calls
+  // kernel timing: events around every launch of the kernel named tk_name
+  char tk_name[64];
+  std::vector<hipEvent_t> tk_ev;  // pairs (begin, end)
+  int tk_n;                       // launches timed in the last call
+  bool tk_failed;
 };

@@ -86,6 +86,8 @@ def lib():
         L.fp_stage_name.restype = C.c_char_p
         L.fp_stage_name.argtypes = [C.c_int]
         L.fp_stage_times.argtypes = [vp, C.POINTER(C.c_float), C.c_int32]
+        L.fp_time_kernel.argtypes = [vp, C.c_char_p]
+        L.fp_kernel_time.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
         L.fp_query_batch.argtypes = [vp, C.c_int32, C.POINTER(Csr), C.POINTER(Options), C.c_int32,
                                      C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
                                      C.POINTER(C.c_int32)]
@@ -329,3 +331,15 @@ class Server:
 
     def __del__(self):
         self.close()
+
+
+def time_kernel(handle, name):
+    """Time every launch of kernel `name` in later calls on `handle`."""
+    _check(lib().fp_time_kernel(handle.h, (name or "").encode()), "fp_time_kernel")
+
+
+def kernel_time(handle):
+    """(total ms, launches) of the timed kernel in the handle's last call."""
+    ms, k = C.c_float(), C.c_int32()
+    _check(lib().fp_kernel_time(handle.h, C.byref(ms), C.byref(k)), "fp_kernel_time")
+    return ms.value, k.value

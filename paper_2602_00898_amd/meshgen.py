@@ -154,6 +154,68 @@ def grid_mesh(H: int, W: int, torus: bool, seed: int, flip_frac: float = 0.0,
     return edges_to_csr(H * W, u, v, diag=diag, index64=index64)
 
 
+def grid_mesh_direct(H: int, W: int, torus: bool, seed: int, index64: bool = False) -> CSR:
+    """Same pattern as ``grid_mesh(H, W, torus, seed)`` (no flips), built row
+    by row from the grid geometry instead of from an edge list: each vertex
+    lists itself, its axis neighbours and the diagonals of its four quads
+    that pass through it.  Used where many large requests are generated."""
+    if torus and (H < 3 or W < 3):
+        raise ValueError("torus needs H, W >= 3")
+    n = H * W
+    r = np.repeat(np.arange(H, dtype=np.int64), W)
+    c = np.tile(np.arange(W, dtype=np.int64), H)
+
+    def vid(rr, cc):
+        if torus:
+            return (rr % H) * W + (cc % W), np.ones(rr.shape, dtype=bool)
+        ok = (rr >= 0) & (rr < H) & (cc >= 0) & (cc < W)
+        return np.where(ok, rr * W + cc, -1), ok
+
+    bits = (_mix64(seed, np.arange(n, dtype=np.int64)) & np.uint64(1)).astype(bool)
+
+    def quad(qr, qc):
+        """(exists, anti-diagonal) of quad (qr, qc); quad ids are qr * W + qc."""
+        if torus:
+            qr, qc = qr % H, qc % W
+            ok = np.ones(qr.shape, dtype=bool)
+        else:
+            ok = (qr >= 0) & (qr < H - 1) & (qc >= 0) & (qc < W - 1)
+        return ok, bits[np.where(ok, qr * W + qc, 0)]
+
+    cols = []
+    for dr, dc in ((0, 0), (0, -1), (0, 1), (-1, 0), (1, 0)):
+        v, ok = vid(r + dr, c + dc)
+        cols.append(np.where(ok, v, -1))
+    # quad above-left: diagonal (r-1,c-1)-(r,c) when not anti
+    ok, anti = quad(r - 1, c - 1)
+    v, vok = vid(r - 1, c - 1)
+    cols.append(np.where(ok & ~anti & vok, v, -1))
+    # quad below-right: (r,c)-(r+1,c+1) when not anti
+    ok, anti = quad(r, c)
+    v, vok = vid(r + 1, c + 1)
+    cols.append(np.where(ok & ~anti & vok, v, -1))
+    # quad above-right: (r-1,c+1)-(r,c) when anti
+    ok, anti = quad(r - 1, c)
+    v, vok = vid(r - 1, c + 1)
+    cols.append(np.where(ok & anti & vok, v, -1))
+    # quad below-left: (r,c)-(r+1,c-1) when anti
+    ok, anti = quad(r, c - 1)
+    v, vok = vid(r + 1, c - 1)
+    cols.append(np.where(ok & anti & vok, v, -1))
+    M = np.stack(cols, axis=1)
+    M = np.where(M < 0, np.int64(1) << 62, M)
+    M.sort(axis=1)
+    keep = M < (np.int64(1) << 62)
+    keep[:, 1:] &= M[:, 1:] != M[:, :-1]
+    counts = keep.sum(axis=1)
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=rowptr[1:])
+    colind = M[keep].astype(np.int32)
+    if not index64:
+        rowptr = rowptr.astype(np.int32)
+    return CSR(n, rowptr, colind)
+
+
 def block_expand(A: CSR, b: int, index64: bool = True) -> CSR:
     """Dense b x b block pattern: DOF b*k+r couples with DOF b*l+s iff A_kl != 0.
 
