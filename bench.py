@@ -7,11 +7,16 @@ diagonals, scalar int32 CSR pattern + diagonal) with target patch size 512,
 inputs resident in device memory before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+                    [--no-batch] [--no-serve] [--serve-requests R] [--lanes L]
 
 Prints one JSON line.  `value` is mesh vertices ordered per second (whole
-job), `roofline` rates the dominant kernel against MI355X's HBM peak with
-algorithmic bytes, `cpu_baseline` times the serial CPU oracle on one core
-over a bounded sample of the same workload.
+job), `roofline` rates the dominant kernel (its launches timed with HIP
+events on the call's stream during the timed steps) against MI355X's HBM
+peak with algorithmic bytes, `cpu_baseline` times the serial CPU oracle on
+one core over a bounded sample of the same workload.  `batch` compares
+ordering 256 meshes of uneven size one at a time with the batched call;
+`serving` drives the request server with Poisson arrivals and reports
+p50/p99 latency.
 """
 
 from __future__ import annotations
@@ -33,55 +38,95 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 H = W = 1024
 MESH_SEED = 2
 PATCH = 512
+# 256-mesh batch, seed 3, 5% edge flips; Poisson serving stream, seed 5
+BATCH_SEED = 3
+SERVE_SEED = 5
+SERVE_RATE = 200.0
+KERNELS = ("k_bfs_level", "k_md", "k_sym_elim", "k_sym_prep", "k_bisect")
 
 
-def kernel_bytes(name, n, nnz, P, D, lloyd):
-    """Algorithmic bytes one launch of a dominant kernel must move (int32).
-
-    Per-vertex figures: a CSR pass reads rowptr (4 B) and the row (4 B per
-    entry); state arrays are read or written once at 4 B a vertex.
-    """
-    csr = 4 * (n + 1) + 4 * nnz
-    if name == "local_orders":
-        # gather every node's induced rows once (CSR + node_of + local index),
-        # write the local order
-        return csr + 4 * n * 3
-    if name == "symbolic":
-        # read the permuted pattern once (CSR + iperm + node_of), write parent
-        # and colcount
-        return csr + 4 * n * 4
-    if name == "patches":
-        # (1 + 2 * lloyd) growth passes over the CSR, plus labels
-        return (1 + 2 * lloyd) * (csr + 8 * n)
-    if name == "septree":
-        # D levels over the CSR of boundary vertices (at most the whole CSR)
-        return D * (csr + 8 * n)
-    return csr + 8 * n
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_gpu(args):
-    import numpy as np  # noqa: F401
+def patch_size_for(n):
+    """Target patch size by mesh size for the batch (larger meshes, larger
+    patches: fewer tree levels)."""
+    if n < 8192:
+        return 128
+    if n < 32768:
+        return 256
+    return 512
+
+
+def kernel_bytes(name, n, nnz_g):
+    """Algorithmic bytes of all launches of a kernel in one ordering (int32
+    arrays, 64-bit BFS keys; deg = graph entries per vertex)."""
+    deg = nnz_g / max(n, 1)
+    if name == "k_bfs_level":
+        # three BFS passes (growth, Lloyd distance, regrowth); per vertex:
+        # frontier 4 + own key 8 + row pointers 8 + deg x (column 4 +
+        # neighbour key 8) + claim (key 8 + frontier 4)
+        return 3 * n * (4 + 8 + 8 + deg * 12 + 12)
+    if name == "k_md":
+        # each node's induced rows once (row pointers 8, deg x (column 4,
+        # node 4, local index 4)), vertex list 4, order and inverse 8, index 4
+        return n * (8 + deg * 12 + 16)
+    if name in ("k_sym_elim", "k_sym_prep"):
+        # the permuted pattern once (row pointers 8, deg x (column 4 +
+        # inverse permutation 4)), parent and column count 8
+        return n * (8 + deg * 8 + 8)
+    if name == "k_bisect":
+        return 0
+    return n * (8 + deg * 4)
+
+
+# ------------------------------------------------------------------ inputs
+def _gen_batch_mesh(spec):
+    from paper_2602_00898_amd import meshgen as mg
+    return mg.grid_mesh(spec.side, spec.side, spec.torus, spec.seed, 0.05)
+
+
+def _gen_serve_mesh(spec):
+    from paper_2602_00898_amd import meshgen as mg
+    A = mg.grid_mesh_direct(spec.side, spec.side, spec.torus, spec.seed, index64=True)
+    return A
+
+
+def make_inputs(args):
+    """Generate every input before the GPU is touched (forked pool)."""
+    import multiprocessing as mp
+
+    from paper_2602_00898_amd import meshgen as mg
+    t = time.perf_counter()
+    A = mg.grid_mesh(H, W, True, MESH_SEED)
+    batch = serve = None
+    procs = min(16, os.cpu_count() or 1)
+    with mp.get_context("fork").Pool(procs) as pool:
+        if not args.no_batch:
+            batch = pool.map(_gen_batch_mesh, mg.batch_specs(BATCH_SEED), chunksize=4)
+        if not args.no_serve:
+            stream = mg.serving_stream(SERVE_SEED, args.serve_requests, rate=SERVE_RATE)
+            meshes = pool.map(_gen_serve_mesh, [s for _, s in stream], chunksize=2)
+            serve = [(t_arr, m) for (t_arr, _), m in zip(stream, meshes)]
+    log(f"inputs generated in {time.perf_counter() - t:.1f} s with {procs} processes")
+    return A, batch, serve
+
+
+# ------------------------------------------------------------------ plain
+def run_plain(args, A):
     import torch
 
     from paper_2602_00898_amd import fastperm as fpm
-    from paper_2602_00898_amd import meshgen as mg
 
     dev = torch.device("cuda:0")
-    torch.cuda.set_device(dev)
-    A = mg.grid_mesh(H, W, True, MESH_SEED)
     n, nnz = A.n, A.nnz
     rp = torch.from_numpy(A.rowptr).to(dev)
     ci = torch.from_numpy(A.colind).to(dev)
     h = fpm.Handle()
     opts = fpm.options(PATCH, fpm.SCHED_LEVEL, 1, 1, MESH_SEED, fpm.FLAG_TIMING)
     ws_bytes, max_nodes = fpm.query(h, n, rp, ci, opts)
-    i32 = dict(dtype=torch.int32, device=dev)
-    out = dict(perm=torch.empty(n, **i32), iperm=torch.empty(n, **i32),
-               parent=torch.empty(n, **i32), colcount=torch.empty(n, **i32),
-               nnzL=torch.zeros(1, dtype=torch.int64, device=dev),
-               node_begin=torch.empty(max_nodes, **i32), node_size=torch.empty(max_nodes, **i32),
-               gmap=torch.empty(n, **i32), n_nodes=torch.zeros(1, **i32),
-               status=torch.zeros(1, dtype=torch.int32, device=dev))
+    out = fpm._alloc_out(n, max_nodes, 1, dev)
     h.workspace(ws_bytes, dev)
     torch.cuda.synchronize(dev)
 
@@ -89,39 +134,131 @@ def run_gpu(args):
         return fpm.order(rp, ci, n, patch_size=PATCH, seed=MESH_SEED, handle=h, out=out,
                          timing=True)
 
-    for i in range(args.warmup):
+    # warmup; the first warmups also time the candidate kernels one by one
+    totals = {}
+    for i in range(max(args.warmup, 1)):
+        cand = KERNELS[i] if i < len(KERNELS) else None
+        fpm.time_kernel(h, cand)
         t = time.perf_counter()
         step()
         torch.cuda.synchronize(dev)
-        print(f"[bench] warmup {i}: {1e3 * (time.perf_counter() - t):.2f} ms", file=sys.stderr, flush=True)
+        if cand:
+            totals[cand] = fpm.kernel_time(h)[0]
+        log(f"warmup {i}: {1e3 * (time.perf_counter() - t):.2f} ms")
+    dom = max(totals, key=totals.get)
+    fpm.time_kernel(h, dom)
     stages = {}
+    kt_ms, kt_launch = 0.0, 0
     t0 = time.perf_counter()
     for i in range(args.steps):
         step()
         for k, v in fpm.stage_times(h).items():
             stages.setdefault(k, []).append(v)
+        ms, nl = fpm.kernel_time(h)
+        kt_ms += ms
+        kt_launch += nl
         if i % 5 == 0:
-            print(f"[bench] step {i}", file=sys.stderr, flush=True)
+            log(f"step {i}")
     torch.cuda.synchronize(dev)
     dt = time.perf_counter() - t0
+    fpm.time_kernel(h, None)
     nnzL = int(out["nnzL"].item())
     P = int(out["gmap"].max().item()) + 1
     nn = int(out["n_nodes"].item())
     D = max(0, (nn + 1).bit_length() - 2)
-    mean_ms = {k: sum(v) / len(v) for k, v in stages.items()}
-    dom = max(mean_ms, key=mean_ms.get)
-    byts = kernel_bytes(dom, n, nnz, P, D, 1)
-    achieved = byts / (mean_ms[dom] * 1e-3) / 1e9
-    ms = dt * 1e3 / args.steps
-    return dict(n=n, nnz=nnz, nnzL=nnzL, P=P, D=D, ms=ms, dt=dt, stage_ms=mean_ms, dom=dom,
-                dom_bytes=byts, achieved=achieved, A=A)
+    nnz_g = nnz - n  # the diagonal is not a graph entry
+    per_launch_bytes = kernel_bytes(dom, n, nnz_g) * args.steps / max(kt_launch, 1)
+    avg_ms = kt_ms / max(kt_launch, 1)
+    achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    return dict(n=n, nnz=nnz, nnzL=nnzL, P=P, D=D, ms=dt * 1e3 / args.steps,
+                stage_ms={k: sum(v) / len(v) for k, v in stages.items()}, dom=dom,
+                dom_bytes=per_launch_bytes, dom_avg_ms=avg_ms, dom_launches=kt_launch / args.steps,
+                achieved=achieved, warm_kernel_ms=totals)
 
 
+# ------------------------------------------------------------------ batch
+def run_batch(args, meshes):
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+
+    dev = torch.device("cuda:0")
+    dm = [dict(rowptr=torch.from_numpy(A.rowptr).to(dev), colind=torch.from_numpy(A.colind).to(dev),
+               n=A.n, patch_size=patch_size_for(A.n), seed=BATCH_SEED * 1000 + i)
+          for i, A in enumerate(meshes)]
+    nv = sum(A.n for A in meshes)
+    h = fpm.Handle()
+    torch.cuda.synchronize(dev)
+    # plain: one call per mesh, one stream
+    plain_out = [fpm.order(m["rowptr"], m["colind"], m["n"], patch_size=m["patch_size"],
+                           seed=m["seed"], handle=h) for m in dm[:2]]  # warm
+    torch.cuda.synchronize(dev)
+    t = time.perf_counter()
+    plain_out = [fpm.order(m["rowptr"], m["colind"], m["n"], patch_size=m["patch_size"],
+                           seed=m["seed"], handle=h) for m in dm]
+    torch.cuda.synchronize(dev)
+    t_plain = time.perf_counter() - t
+    log(f"batch plain: {t_plain:.2f} s")
+    hb = fpm.Handle()
+    fpm.order_batch(dm[:8], lanes=args.lanes, handle=hb)  # warm the lanes
+    torch.cuda.synchronize(dev)
+    t = time.perf_counter()
+    bout = fpm.order_batch(dm, lanes=args.lanes, handle=hb)
+    torch.cuda.synchronize(dev)
+    t_batch = time.perf_counter() - t
+    log(f"batch batched: {t_batch:.2f} s")
+    same = all(torch.equal(a[k], b[k]) for a, b in zip(plain_out, bout)
+               for k in ("perm", "iperm", "parent", "colcount", "nnzL"))
+    return {"workload": "256 grid/torus meshes, sides log-uniform 45..447, 5% edge flips, "
+                        "S by size (128/256/512)",
+            "meshes": len(meshes), "vertices": nv, "lanes": args.lanes,
+            "plain_value": round(nv / t_plain / 1e6, 4), "batched_value": round(nv / t_batch / 1e6, 4),
+            "unit": "M vertices/s", "speedup": round(t_plain / t_batch, 3),
+            "identical_to_plain": bool(same)}
+
+
+# ------------------------------------------------------------------ serving
+def run_serve(args, reqs):
+    from paper_2602_00898_amd import fastperm as fpm
+
+    srv = fpm.Server(hbm_budget=args.serve_budget_gb << 30, max_slots=args.lanes)
+    try:
+        # warm the slots on a small request
+        A0 = reqs[0][1]
+        srv.wait(srv.submit(A0.rowptr, A0.colind, A0.n, patch_size=PATCH, seed=1))
+        t0 = time.perf_counter()
+        tickets = []
+        for t_arr, A in reqs:  # open loop: submit at the arrival time
+            delay = t0 + t_arr - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(srv.submit(A.rowptr, A.colind, A.n, patch_size=PATCH, seed=7))
+        lat = []
+        for tk in tickets:
+            lat.append(srv.wait(tk)["latency_s"])
+        wall = time.perf_counter() - t0
+    finally:
+        srv.close()
+    lat.sort()
+    nv = sum(A.n for _, A in reqs)
+
+    def pct(p):
+        return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
+
+    return {"workload": f"Poisson arrivals {SERVE_RATE:.0f}/s, grid/torus sides log-uniform "
+                        "100..1414 (1e4..2e6 vertices), fresh diagonals per request, S=512",
+            "requests": len(reqs), "vertices": nv, "slots": args.lanes,
+            "value": round(nv / wall / 1e6, 4), "unit": "M vertices/s",
+            "p50_ms": round(1e3 * pct(50), 2), "p99_ms": round(1e3 * pct(99), 2),
+            "offered_M_vertices_per_s": round(nv / reqs[-1][0] / 1e6, 2)}
+
+
+# ------------------------------------------------------------------ oracle
 def run_cpu(A, budget_s=15.0):
     import oracle
 
     oracle.build()
-    print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+    log("CPU oracle baseline")
     times = []
     t_all = time.perf_counter()
     while True:
@@ -140,15 +277,23 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-mesh batch")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving sample")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-budget-gb", type=int, default=64)
+    ap.add_argument("--lanes", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the ordering of one mesh is not sharded across "
               "GPUs in this library (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
-    g = run_gpu(args)
-    cpu = None if args.no_cpu else run_cpu(g["A"])
+    A, batch_meshes, serve_reqs = make_inputs(args)
+    g = run_plain(args, A)
+    batch = None if batch_meshes is None else run_batch(args, batch_meshes)
+    serving = None if serve_reqs is None else run_serve(args, serve_reqs)
+    cpu = None if args.no_cpu else run_cpu(A)
     if cpu is not None and cpu.pop("nnzL") != g["nnzL"]:
         print(f"nnz(L) differs from the oracle: {g['nnzL']} vs oracle", file=sys.stderr)
         sys.exit(1)
@@ -171,9 +316,13 @@ def main():
         "roofline": {"bound": "hbm", "kernel": g["dom"], "achieved": round(g["achieved"], 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(g["achieved"] / HBM_PEAK_GBS, 6), "traffic": None,
-                     "bytes_per_launch": g["dom_bytes"],
-                     "launch_ms": round(g["stage_ms"][g["dom"]], 4)},
+                     "bytes_per_launch": round(g["dom_bytes"]),
+                     "avg_launch_ms": round(g["dom_avg_ms"], 5),
+                     "launches_per_step": g["dom_launches"]},
         "stage_ms": {k: round(v, 4) for k, v in g["stage_ms"].items()},
+        "kernel_ms_per_ordering": {k: round(v, 3) for k, v in g["warm_kernel_ms"].items()},
+        "batch": batch,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
