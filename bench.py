@@ -50,13 +50,9 @@ def log(msg):
 
 
 def patch_size_for(n):
-    """Target patch size by mesh size for the batch (larger meshes, larger
-    patches: fewer tree levels)."""
-    if n < 8192:
-        return 128
-    if n < 32768:
-        return 256
-    return 512
+    """Target patch size of a batch mesh: the committed autotune table."""
+    from paper_2602_00898_amd.autotune import patch_size_for as ps
+    return ps(n)
 
 
 def kernel_bytes(name, n, nnz_g):
@@ -210,7 +206,7 @@ def run_batch(args, meshes):
     same = all(torch.equal(a[k], b[k]) for a, b in zip(plain_out, bout)
                for k in ("perm", "iperm", "parent", "colcount", "nnzL"))
     return {"workload": "256 grid/torus meshes, sides log-uniform 45..447, 5% edge flips, "
-                        "S by size (128/256/512)",
+                        "S from the autotune table",
             "meshes": len(meshes), "vertices": nv, "lanes": args.lanes,
             "plain_value": round(nv / t_plain / 1e6, 4), "batched_value": round(nv / t_batch / 1e6, 4),
             "unit": "M vertices/s", "speedup": round(t_plain / t_batch, 3),
