@@ -353,42 +353,97 @@ __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int
 }
 
 // ---------------------------------------------------------------- elim
-__device__ __forceinline__ void sym_elim(const FpMesh& M, int t) {
-  SymView V;
-  int h[SH_WORDS];
-  if (!sym_load(M, t, &V, h)) return;
+// The columns of a node are a sequential chain of dependent steps, so their
+// latency decides the time of the top tree levels.  The queue links and the
+// forward rows are copied into the wave's LDS slice when they fit (kLds),
+// and every lane keeps its words of the last column computed in registers:
+// the next column is most often that column's parent, and then its row
+// needs no memory read at all.
+#define FP_SYM_REGW 4  // words per lane kept in registers (rows up to 256 words)
+
+template <bool kLds>
+__device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymView& V,
+                                             const int* h, int* lds) {
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
-  const int stride = h[SH_STRIDE];
+  const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
   const int F = m + nbd;
   const int b0 = M.nbegin[t];
   int nout = h[SH_NOUT];
+  int* head = V.head;
+  int* next = V.next;
+  const int* optr = V.optr;
+  const int* oent = V.oent;
+  if (kLds) {
+    head = lds;
+    next = head + m;
+    int* lo = next + rows;
+    int* le = lo + (m + 1);
+    for (int i = lane_id(); i < m; i += 64) head[i] = V.head[i];
+    for (int i = lane_id(); i < rows; i += 64) next[i] = V.next[i];
+    for (int i = lane_id(); i <= m; i += 64) lo[i] = V.optr[i];
+    for (int i = lane_id(); i < nfw; i += 64) le[i] = V.oent[i];
+    optr = lo;
+    oent = le;
+    wave_fence();
+  }
+  const bool regs = FW <= 64 * FP_SYM_REGW;
+  uint32_t prev[FP_SYM_REGW];
+#pragma unroll
+  for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = 0u;
   for (int k = 0; k < m; k++) {
     const int kw = k >> 5;
-    const int r0 = V.optr[k], r1 = V.optr[k + 1];
-    const int q0 = V.head[k];
+    const int r0 = optr[k], r1 = optr[k + 1];
+    const int q0 = head[k];
     uint32_t* rk = V.rows + (long long)k * stride;
     int cnt = 0;
     uint32_t first = 0xFFFFFFFFu;
     bool bad = false;
-    for (int w = lane_id(); w < FW; w += 64) {
+#pragma unroll
+    for (int i = 0; i < FP_SYM_REGW; i++) {
+      const int w = lane_id() + 64 * i;
+      if (i * 64 >= FW) break;
+      if (w >= FW) continue;
       uint32_t x = 0u;
       if (w >= kw) {
         int j = q0, steps = 0;
         while (j >= 0 && j < rows && steps < rows) {
-          x |= V.rows[(long long)j * stride + w];
-          j = V.next[j];
+          x |= (regs && j == k - 1) ? prev[i] : V.rows[(long long)j * stride + w];
+          j = next[j];
           steps++;
         }
         bad |= j >= 0;  // a queue that leaves the rows or does not end
         for (int e = r0; e < r1; e++) {
-          const int f = V.oent[e];
+          const int f = oent[e];
           if ((f >> 5) == w) x |= 1u << (f & 31);
         }
         if (w == kw) x &= (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
       }
       rk[w] = x;
+      prev[i] = x;
       cnt += popc32(x);
       if (x && first == 0xFFFFFFFFu) first = (uint32_t)(w * 32 + __ffs(x) - 1);
+    }
+    if (!regs) {  // rows wider than the register window: the rest from memory
+      for (int w = lane_id() + 64 * FP_SYM_REGW; w < FW; w += 64) {
+        uint32_t x = 0u;
+        if (w >= kw) {
+          int j = q0, steps = 0;
+          while (j >= 0 && j < rows && steps < rows) {
+            x |= V.rows[(long long)j * stride + w];
+            j = next[j];
+            steps++;
+          }
+          bad |= j >= 0;
+          for (int e = r0; e < r1; e++) {
+            const int f = oent[e];
+            if ((f >> 5) == w) x |= 1u << (f & 31);
+          }
+          if (w == kw) x &= (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
+        }
+        rk[w] = x;
+        cnt += popc32(x);
+        if (x && first == 0xFFFFFFFFu) first = (uint32_t)(w * 32 + __ffs(x) - 1);
+      }
     }
     cnt = wave_sum_i32(cnt);
     first = wave_min_u32(first);
@@ -405,8 +460,8 @@ __device__ __forceinline__ void sym_elim(const FpMesh& M, int t) {
       if (first != 0xFFFFFFFFu) {
         if ((int)first < m) {
           par = b0 + (int)first;
-          V.next[k] = V.head[first];
-          V.head[first] = k;
+          next[k] = head[first];
+          head[first] = k;
         } else {
           par = V.bd[first - m];
           V.outl[nout] = k;
@@ -415,9 +470,23 @@ __device__ __forceinline__ void sym_elim(const FpMesh& M, int t) {
       M.vpar[b0 + k] = par;
     }
     if (first != 0xFFFFFFFFu && (int)first >= m) nout++;
-    wave_fence();  // the row, the queue links and outl reach every lane
+    wave_fence();  // queue links and outl reach every lane of the wave
   }
   if (lane_id() == 0) V.hdr[SH_NOUT] = nout;
+}
+
+// LDS words a node's queue links and forward rows need
+__device__ __forceinline__ long long sym_elim_lds_words(const int* h) {
+  return 2ll * h[SH_M] + 1 + h[SH_ROWS] + h[SH_NFW];
+}
+
+// kLds: only nodes whose links fit in lds_words; otherwise only the others
+template <bool kLds>
+__device__ __forceinline__ void sym_elim(const FpMesh& M, int t, int* lds, long long lds_words) {
+  SymView V;
+  int h[SH_WORDS];
+  if (!sym_load(M, t, &V, h)) return;
+  if ((sym_elim_lds_words(h) <= lds_words) == kLds) sym_elim_run<kLds>(M, t, V, h, lds);
 }
 
 // ---------------------------------------------------------------- emit
