@@ -521,32 +521,25 @@ __global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ M
   const int lo = (1 << d) - 1, cnt = 1 << d;
   for (int x = gwave(); x < cnt; x += nwaves()) sym_prep(M, lo + x, d);
 }
-// Nodes whose queue links and forward rows fit in an LDS slice: big = 1
-// for nodes with more than 256 columns, one wave per workgroup owning the
-// whole LDS; big = 0 for the others, four waves sharing it.
-__global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ Mp, int d, int big) {
+// Elimination of the nodes whose queue links and forward rows fit in an LDS
+// slice: cls 0 with four waves per workgroup (a quarter of the LDS each),
+// cls 1 with one wave owning the whole LDS.
+__global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ Mp, int d, int cls) {
   MESH;
   FP_LDS_DECL;
-  const int nsl = big ? 1 : FP_WAVES;
+  const int nsl = cls == 0 ? FP_WAVES : 1;
   if (wave_id() >= nsl) return;
-  const long long words = (M.lds_bytes / nsl) / 4;
-  int* slice = (int*)fp_lds + words * wave_id();
+  const long long lds_words = M.lds_bytes / 4;
+  int* slice = (int*)fp_lds + (lds_words / nsl) * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
   const int wv = (int)blockIdx.x * nsl + wave_id(), nw = (int)gridDim.x * nsl;
-  for (int x = wv; x < cnt; x += nw) {
-    const int t = lo + x;
-    if ((M.nsize[t] > 256) == (big != 0)) sym_elim<true>(M, t, slice, words);
-  }
+  for (int x = wv; x < cnt; x += nw) sym_elim<true>(M, lo + x, cls, slice, lds_words);
 }
 // nodes too large for the whole LDS: links and rows in global memory
 __global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(const FpMesh* __restrict__ Mp, int d) {
   MESH;
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  const long long words = M.lds_bytes / 4;  // the largest slice of k_sym_elim
-  for (int x = gwave(); x < cnt; x += nwaves()) {
-    const int t = lo + x;
-    sym_elim<false>(M, t, nullptr, M.nsize[t] > 256 ? words : words / FP_WAVES);
-  }
+  for (int x = gwave(); x < cnt; x += nwaves()) sym_elim<false>(M, lo + x, 2, nullptr, M.lds_bytes / 4);
 }
 __global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ Mp, int d) {
   MESH;
@@ -868,8 +861,8 @@ fp_status run_job(Job& J) {
     FPL(k_sym_init, dim3(1), dim3(64), 0, st, dm, d);
     FPL(k_sym_prep, G, T, 0, st, dm, d);
     const dim3 G1(std::max(1, std::min(cnt, 4 * J.h->ncu)));
-    FPL(k_sym_elim, G1, T, J.h->lds_bytes, st, dm, d, 1);
     FPL(k_sym_elim, G, T, J.h->lds_bytes, st, dm, d, 0);
+    FPL(k_sym_elim, G1, T, J.h->lds_bytes, st, dm, d, 1);
     FPL(k_sym_elim_glb, G, T, 0, st, dm, d);
     FPL(k_sym_emit, G, T, 0, st, dm, d);
     J.check();

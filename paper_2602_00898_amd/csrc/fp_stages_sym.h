@@ -354,12 +354,36 @@ __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int
 
 // ---------------------------------------------------------------- elim
 // The columns of a node are a sequential chain of dependent steps, so their
-// latency decides the time of the top tree levels.  The queue links and the
-// forward rows are copied into the wave's LDS slice when they fit (kLds),
-// and every lane keeps its words of the last column computed in registers:
-// the next column is most often that column's parent, and then its row
-// needs no memory read at all.
+// latency decides the time of the top tree levels.  A step only builds the
+// column's row and finds its least entry, the parent, to queue the row on;
+// column counts and parents are read off the rows afterwards, in parallel
+// (sym_counts).  The queue links and the forward rows are copied into the
+// wave's LDS slice when they fit (kLds), and every lane keeps its words of
+// the last column in registers: the next column is most often that column's
+// parent, and then its row needs no memory read.
 #define FP_SYM_REGW 4  // words per lane kept in registers (rows up to 256 words)
+
+// the row of column k, word w: queued rows OR forward entries, bits > k
+__device__ __forceinline__ uint32_t sym_word(const SymView& V, const int* next, const int* oent,
+                                             int k, int w, int q0, int r0, int r1, int rows,
+                                             int stride, bool use_prev, uint32_t prev, bool* bad) {
+  uint32_t x = 0u;
+  const int kw = k >> 5;
+  if (w < kw) return 0u;
+  int j = q0, steps = 0;
+  while (j >= 0 && j < rows && steps < rows) {
+    x |= (use_prev && j == k - 1) ? prev : V.rows[(long long)j * stride + w];
+    j = next[j];
+    steps++;
+  }
+  *bad |= j >= 0;  // a queue that leaves the rows or does not end
+  for (int e = r0; e < r1; e++) {
+    const int f = oent[e];
+    if ((f >> 5) == w) x |= 1u << (f & 31);
+  }
+  if (w == kw) x &= (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
+  return x;
+}
 
 template <bool kLds>
 __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymView& V,
@@ -367,7 +391,6 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
   const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
   const int F = m + nbd;
-  const int b0 = M.nbegin[t];
   int nout = h[SH_NOUT];
   int* head = V.head;
   int* next = V.next;
@@ -391,83 +414,54 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
 #pragma unroll
   for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = 0u;
   for (int k = 0; k < m; k++) {
-    const int kw = k >> 5;
     const int r0 = optr[k], r1 = optr[k + 1];
     const int q0 = head[k];
     uint32_t* rk = V.rows + (long long)k * stride;
-    int cnt = 0;
-    uint32_t first = 0xFFFFFFFFu;
     bool bad = false;
+    uint32_t first = 0xFFFFFFFFu;
 #pragma unroll
     for (int i = 0; i < FP_SYM_REGW; i++) {
-      const int w = lane_id() + 64 * i;
-      if (i * 64 >= FW) break;
-      if (w >= FW) continue;
-      uint32_t x = 0u;
-      if (w >= kw) {
-        int j = q0, steps = 0;
-        while (j >= 0 && j < rows && steps < rows) {
-          x |= (regs && j == k - 1) ? prev[i] : V.rows[(long long)j * stride + w];
-          j = next[j];
-          steps++;
+      if (i * 64 < FW) {
+        const int w = lane_id() + 64 * i;
+        uint32_t x = 0u;
+        if (w < FW) {
+          x = sym_word(V, next, oent, k, w, q0, r0, r1, rows, stride, regs, prev[i], &bad);
+          rk[w] = x;
         }
-        bad |= j >= 0;  // a queue that leaves the rows or does not end
-        for (int e = r0; e < r1; e++) {
-          const int f = oent[e];
-          if ((f >> 5) == w) x |= 1u << (f & 31);
+        prev[i] = x;
+        // least set bit: lowest word with a bit, found by ballot
+        const uint64_t b = ballot64(x != 0u);
+        if (first == 0xFFFFFFFFu && b) {
+          const int l = __builtin_ctzll(b);
+          const uint32_t xv = (uint32_t)__shfl((int)x, l, 64);
+          first = (uint32_t)((l + 64 * i) * 32 + __ffs(xv) - 1);
         }
-        if (w == kw) x &= (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
       }
-      rk[w] = x;
-      prev[i] = x;
-      cnt += popc32(x);
-      if (x && first == 0xFFFFFFFFu) first = (uint32_t)(w * 32 + __ffs(x) - 1);
     }
     if (!regs) {  // rows wider than the register window: the rest from memory
+      uint32_t f2 = 0xFFFFFFFFu;
       for (int w = lane_id() + 64 * FP_SYM_REGW; w < FW; w += 64) {
-        uint32_t x = 0u;
-        if (w >= kw) {
-          int j = q0, steps = 0;
-          while (j >= 0 && j < rows && steps < rows) {
-            x |= V.rows[(long long)j * stride + w];
-            j = next[j];
-            steps++;
-          }
-          bad |= j >= 0;
-          for (int e = r0; e < r1; e++) {
-            const int f = oent[e];
-            if ((f >> 5) == w) x |= 1u << (f & 31);
-          }
-          if (w == kw) x &= (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
-        }
+        const uint32_t x = sym_word(V, next, oent, k, w, q0, r0, r1, rows, stride, false, 0u, &bad);
         rk[w] = x;
-        cnt += popc32(x);
-        if (x && first == 0xFFFFFFFFu) first = (uint32_t)(w * 32 + __ffs(x) - 1);
+        if (x && f2 == 0xFFFFFFFFu) f2 = (uint32_t)(w * 32 + __ffs(x) - 1);
       }
+      f2 = wave_min_u32(f2);
+      if (first == 0xFFFFFFFFu) first = f2;
     }
-    cnt = wave_sum_i32(cnt);
-    first = wave_min_u32(first);
-    if (ballot64(bad) || (first != 0xFFFFFFFFu && first >= (uint32_t)F)) {
+    if (ballot64(bad) || (first != 0xFFFFFFFFu && (first <= (uint32_t)k || first >= (uint32_t)F))) {
       if (lane_id() == 0) {
         fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_LIVE, t);
         V.hdr[SH_OK] = 0;
       }
       return;
     }
-    if (lane_id() == 0) {
-      M.vcc[b0 + k] = 1 + cnt;
-      int par = -1;
-      if (first != 0xFFFFFFFFu) {
-        if ((int)first < m) {
-          par = b0 + (int)first;
-          next[k] = head[first];
-          head[first] = k;
-        } else {
-          par = V.bd[first - m];
-          V.outl[nout] = k;
-        }
+    if (lane_id() == 0 && first != 0xFFFFFFFFu) {
+      if ((int)first < m) {
+        next[k] = head[first];
+        head[first] = k;
+      } else {
+        V.outl[nout] = k;
       }
-      M.vpar[b0 + k] = par;
     }
     if (first != 0xFFFFFFFFu && (int)first >= m) nout++;
     wave_fence();  // queue links and outl reach every lane of the wave
@@ -480,13 +474,40 @@ __device__ __forceinline__ long long sym_elim_lds_words(const int* h) {
   return 2ll * h[SH_M] + 1 + h[SH_ROWS] + h[SH_NFW];
 }
 
-// kLds: only nodes whose links fit in lds_words; otherwise only the others
+// 0: the links fit a quarter of the LDS (four waves per workgroup), 1: the
+// whole LDS (one wave), 2: neither (global memory)
+__device__ __forceinline__ int sym_elim_class(const int* h, long long lds_words) {
+  const long long need = sym_elim_lds_words(h);
+  if (need <= lds_words / FP_WAVES) return 0;
+  if (need <= lds_words) return 1;
+  return 2;
+}
+
 template <bool kLds>
-__device__ __forceinline__ void sym_elim(const FpMesh& M, int t, int* lds, long long lds_words) {
+__device__ __forceinline__ void sym_elim(const FpMesh& M, int t, int cls, int* lds,
+                                         long long lds_words) {
   SymView V;
   int h[SH_WORDS];
   if (!sym_load(M, t, &V, h)) return;
-  if ((sym_elim_lds_words(h) <= lds_words) == kLds) sym_elim_run<kLds>(M, t, V, h, lds);
+  if (sym_elim_class(h, lds_words) == cls) sym_elim_run<kLds>(M, t, V, h, lds);
+}
+
+// column counts and parents of a node's columns from their rows
+__device__ __forceinline__ void sym_counts(const FpMesh& M, int t, const SymView& V, const int* h) {
+  const int m = h[SH_M], FW = h[SH_FW], stride = h[SH_STRIDE];
+  const int b0 = M.nbegin[t];
+  for (int k = lane_id(); k < m; k += 64) {
+    const uint32_t* row = V.rows + (long long)k * stride;
+    int c = 0;
+    int f = -1;
+    for (int w = k >> 5; w < FW; w++) {
+      const uint32_t x = row[w];
+      c += popc32(x);
+      if (x && f < 0) f = w * 32 + __ffs(x) - 1;
+    }
+    M.vcc[b0 + k] = 1 + c;
+    M.vpar[b0 + k] = f < 0 ? -1 : (f < m ? b0 + f : V.bd[f - m]);
+  }
 }
 
 // ---------------------------------------------------------------- emit
@@ -503,6 +524,7 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
     sym_drop(M, t, FP_SITE_SYM_LIVE);
     return;
   }
+  sym_counts(M, t, V, h);
   int total = 0;
   for (int i = 0; i < nout; i++) {
     const int r = V.outl[i];
