@@ -134,6 +134,22 @@ __device__ __forceinline__ void md_refresh_dirty(uint32_t* key, uint32_t* gmin, 
   wave_fence();
 }
 
+// The pivot steps store the pivot's local index into vperm (a store that
+// waits for nothing); md_map_order then turns the positions
+// [pos0, pos0 + count) into vertex ids through vmap (local index -> vertex,
+// mlim entries) and fills viperm, all lanes at once.
+__device__ __forceinline__ void md_map_order(const FpMesh& M, const int* vmap, int mlim, int pos0,
+                                             int count) {
+  wave_fence();
+  for (int s = lane_id(); s < count; s += 64) {
+    const int p = M.vperm[pos0 + s];
+    const int v = (unsigned)p < (unsigned)mlim ? vmap[p] : -1;
+    M.vperm[pos0 + s] = v;
+    if ((unsigned)v < (unsigned)M.n) M.viperm[v] = pos0 + s;
+  }
+  wave_fence();
+}
+
 // Run minimum degree steps on a BIT layout until every vertex is ordered.
 // vmap[i] = vertex id of current index i; outputs go to positions
 // pos0, pos0+1, ...
@@ -146,12 +162,11 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
     const int p = (int)(km & 0xFFFFu);
     if (km == FP_KEY_INF || p >= B.m) {  // never expected: stop before any wild index
       if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT, pos0);
+      md_map_order(M, vmap, B.m, pos0, s);
       return;
     }
     if (lane == 0) {
-      const int v = vmap[p];
-      M.vperm[pos0 + s] = v;
-      if ((unsigned)v < (unsigned)M.n) M.viperm[v] = pos0 + s;
+      M.vperm[pos0 + s] = p;
       B.alive[p >> 5] &= ~(1u << (p & 31));
       B.key[p] = FP_KEY_INF;
       B.dl[p >> 6] = 1;
@@ -207,6 +222,7 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
     wave_fence();
     md_refresh_dirty(B.key, B.gmin, B.dl, B.m, B.G);
   }
+  md_map_order(M, vmap, B.m, pos0, nsteps);
 }
 
 // ---------------------------------------------------------------- SPARSE
@@ -430,6 +446,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       const int p = (int)(km & 0xFFFFu);
       if (km == FP_KEY_INF || p >= m) {
         if (lane_id() == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
+        md_map_order(M, vmap, m, pos0, done);
         goto fail;
       }
       const int kp = S.len[p];
@@ -452,9 +469,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       }
       if (ballot64(over)) break;  // convert with p still present
       if (lane_id() == 0) {
-        const int v = vmap[p];
-        M.vperm[pos0 + done] = v;
-        M.viperm[v] = pos0 + done;
+        M.vperm[pos0 + done] = p;  // local index; mapped below
         S.key[p] = FP_KEY_INF;
         S.dl[p >> 6] = 1;
       }
@@ -486,6 +501,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       done++;
       na--;
     }
+    md_map_order(M, vmap, m, pos0, done);
     if (na == 0) return;
     // re-index the remaining vertices (rank order) into BIT form; stage the
     // sparse state in the pool first since the BIT layout reuses the slice

@@ -98,6 +98,14 @@ def test_degenerate_sizes():
     check(mesh(12, 12, False, 16), "S=1", patch_size=1, seed=1)
 
 
+def test_large_nodes_sparse_local_order():
+    """Nodes of thousands of vertices: the local order starts in the sparse
+    layout and finishes in the dense one."""
+    check(mesh(50, 50, True, 3, 0.05), "one 2500-vertex node", patch_size=10 ** 6, seed=3)
+    check(mesh(40, 70, False, 4, 0.05), "one 2800-vertex node", patch_size=10 ** 6, seed=4)
+    check(mesh(64, 64, True, 5, 0.05), "two patches", patch_size=2048, seed=5)
+
+
 def test_determinism():
     A = mesh(64, 64, True, 17, 0.05)
     a = gpu_order(A, patch_size=64, seed=3)
