@@ -500,7 +500,7 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
   while (true) {
     int k = 0;
     if (lane_id() == 0) k = atomicAdd(&C->task_pop[c], 1);
-    k = __shfl(k, 0, 64);
+    k = wave_bcast(k, 0);
     if (k >= cnt) break;
     md_node(M, M.tasks[c * M.NNcap + k], slice, sb);
   }

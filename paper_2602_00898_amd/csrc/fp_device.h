@@ -59,15 +59,42 @@ __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
 // ---------------------------------------------------------------- wave64
+// Reductions and scans run on DPP row shifts (within each 16-lane row,
+// register to register) and combine the four rows through readlane, instead
+// of LDS-routed lane permutes.  All lanes of the wave must be active.
+// Value of `x` in lane `l` (l the same in every lane), broadcast to all.
+__device__ __forceinline__ int wave_bcast(int x, int l) { return __builtin_amdgcn_readlane(x, l); }
+__device__ __forceinline__ uint32_t wave_bcast_u32(uint32_t x, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, l);
+}
+// row_shr:n of x, `fill` where the source lane is before the row start
+__device__ __forceinline__ int dpp_shr(int x, int fill, int n) {
+  switch (n) {
+    case 1: return __builtin_amdgcn_update_dpp(fill, x, 0x111, 0xf, 0xf, false);
+    case 2: return __builtin_amdgcn_update_dpp(fill, x, 0x112, 0xf, 0xf, false);
+    case 4: return __builtin_amdgcn_update_dpp(fill, x, 0x114, 0xf, 0xf, false);
+    default: return __builtin_amdgcn_update_dpp(fill, x, 0x118, 0xf, 0xf, false);
+  }
+}
 __device__ __forceinline__ uint32_t wave_min_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = min(x, (uint32_t)__shfl_xor((int)x, o, 64));
-  return x;
+  const int I = -1;  // 0xFFFFFFFF, the identity of the unsigned minimum
+  x = min(x, (uint32_t)dpp_shr((int)x, I, 1));
+  x = min(x, (uint32_t)dpp_shr((int)x, I, 2));
+  x = min(x, (uint32_t)dpp_shr((int)x, I, 4));
+  x = min(x, (uint32_t)dpp_shr((int)x, I, 8));
+  // lane 15 of each row now holds the row's minimum
+  const uint32_t a = min(wave_bcast_u32(x, 15), wave_bcast_u32(x, 31));
+  const uint32_t b = min(wave_bcast_u32(x, 47), wave_bcast_u32(x, 63));
+  return min(a, b);
 }
 __device__ __forceinline__ uint32_t wave_max_u32(uint32_t x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = max(x, (uint32_t)__shfl_xor((int)x, o, 64));
-  return x;
+  x = max(x, (uint32_t)dpp_shr((int)x, 0, 1));
+  x = max(x, (uint32_t)dpp_shr((int)x, 0, 2));
+  x = max(x, (uint32_t)dpp_shr((int)x, 0, 4));
+  x = max(x, (uint32_t)dpp_shr((int)x, 0, 8));
+  const uint32_t a = max(wave_bcast_u32(x, 15), wave_bcast_u32(x, 31));
+  const uint32_t b = max(wave_bcast_u32(x, 47), wave_bcast_u32(x, 63));
+  return max(a, b);
 }
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t x) {
 #pragma unroll
@@ -86,24 +113,27 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t x) {
   return x;
 }
 __device__ __forceinline__ int wave_sum_i32(int x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  x += dpp_shr(x, 0, 1);
+  x += dpp_shr(x, 0, 2);
+  x += dpp_shr(x, 0, 4);
+  x += dpp_shr(x, 0, 8);
+  return (wave_bcast(x, 15) + wave_bcast(x, 31)) + (wave_bcast(x, 47) + wave_bcast(x, 63));
 }
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t x) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) x += (int64_t)__shfl_xor((long long)x, o, 64);
   return x;
 }
-// inclusive prefix sum over the wave
+// inclusive prefix sum over the wave: scans of the 16-lane rows, then the
+// totals of the rows before
 __device__ __forceinline__ int wave_incl_scan(int x) {
-  const int l = lane_id();
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    int y = __shfl_up(x, o, 64);
-    if (l >= o) x += y;
-  }
-  return x;
+  x += dpp_shr(x, 0, 1);
+  x += dpp_shr(x, 0, 2);
+  x += dpp_shr(x, 0, 4);
+  x += dpp_shr(x, 0, 8);
+  const int t0 = wave_bcast(x, 15), t1 = wave_bcast(x, 31), t2 = wave_bcast(x, 47);
+  const int row = lane_id() >> 4;
+  return x + (row > 0 ? t0 : 0) + (row > 1 ? t1 : 0) + (row > 2 ? t2 : 0);
 }
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
@@ -121,7 +151,7 @@ __device__ __forceinline__ int wave_append(int* ctr, bool pred) {
   if (bal) {
     const int leader = __builtin_ctzll(bal);
     if (lane_id() == leader) base = atomicAdd(ctr, popc64(bal));
-    base = __shfl(base, leader, 64);
+    base = wave_bcast(base, leader);
   }
   return base + popc64(bal & lanemask_lt());
 }
@@ -133,11 +163,11 @@ __device__ __forceinline__ int wave_append_keyed(int* ctr, int key, bool pred) {
   int slot = 0;
   while (pending) {
     const int leader = __builtin_ctzll(pending);
-    const int lk = __shfl(key, leader, 64);
+    const int lk = wave_bcast(key, leader);
     const uint64_t grp = ballot64(pred && key == lk) & pending;
     int base = 0;
     if (lane_id() == leader) base = atomicAdd(&ctr[lk], popc64(grp));
-    base = __shfl(base, leader, 64);
+    base = wave_bcast(base, leader);
     if ((grp >> lane_id()) & 1ull) slot = base + popc64(grp & lanemask_lt());
     pending &= ~grp;
   }

@@ -197,7 +197,7 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
         x &= x - 1;
         B.nbl[off++] = w * 32 + bit;
       }
-      k += __shfl(inc, 63, 64);
+      k += wave_bcast(inc, 63);
     }
     wave_fence();
     // the neighbours become a clique: OR the pivot row into theirs

@@ -227,7 +227,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
         if (q >= e0) V.bd[o++] = q;
       }
     }
-    nc += __shfl(inc, 63, 64);
+    nc += wave_bcast(inc, 63);
   }
   for (int i = nc + lane_id(); i < np2; i += 64) V.bd[i] = 0x7FFFFFFF;
   wave_fence();
@@ -272,7 +272,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
           }
         }
       }
-      run += __shfl(inc, 63, 64);
+      run += wave_bcast(inc, 63);
     }
     if (lane_id() == 0) V.optr[m] = run;
     if (ballot64(bad) || run != nfw) {
@@ -433,7 +433,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
         const uint64_t b = ballot64(x != 0u);
         if (first == 0xFFFFFFFFu && b) {
           const int l = __builtin_ctzll(b);
-          const uint32_t xv = (uint32_t)__shfl((int)x, l, 64);
+          const uint32_t xv = wave_bcast_u32(x, l);
           first = (uint32_t)((l + 64 * i) * 32 + __ffs(xv) - 1);
         }
       }
@@ -545,7 +545,7 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
       base = -1;
     }
   }
-  base = __shfl(base, 0, 64);
+  base = wave_bcast(base, 0);
   if (base < 0) {
     sym_drop(M, t, 0);
     return;
@@ -570,7 +570,7 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
         bad |= !ok;
         dst[o++] = ok ? V.bd[f - m] : b0;
       }
-      len += __shfl(inc, 63, 64);
+      len += wave_bcast(inc, 63);
     }
     if (lane_id() == 0) dst[off] = len;
     off += 1 + len;
