@@ -186,18 +186,74 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     sym_drop(M, t, FP_SITE_SYM_RECORD);
     return;
   }
-  int np2 = 64;
-  while (np2 < ncand) np2 <<= 1;
-  const int stride = (m + np2 + 31) >> 5;
+  // Every later position lies in an ancestor of t (the separator property),
+  // and t's ancestors, nearest first, occupy increasing positions.  Marking
+  // the positions in a bitmap over the ancestors' ranges, concatenated in
+  // that order, and reading the bitmap back gives them sorted and unique.
+  int na = 0;
+  long long B = 0;
+  for (int a = t; a > 0;) {
+    a = (a - 1) >> 1;
+    const int sz = M.nsize[a];
+    if (sz > 0) {
+      na++;
+      B += sz;
+    }
+  }
+  if (na > 32 || B > (1 << 29)) {
+    sym_drop(M, t, FP_SITE_SYM_RECORD);
+    return;
+  }
+  const int cap = (int)min((long long)max(ncand, 1), max(B, 1ll));  // later positions at most
+  const int BW = (int)((B + 31) >> 5);
+  const int stride = (m + cap + 31) >> 5;
   const int rows = m + nce;
-  unsigned* base = pool_alloc(M, (unsigned long long)sym_words(m, np2, nfw, rows, stride));
+  const long long words = sym_words(m, cap, nfw, rows, stride);
+  unsigned* base = pool_alloc(M, (unsigned long long)(words + BW + 96));
   if (!base) {  // pool_alloc raised the error
     sym_drop(M, t, 0);
     return;
   }
+  const int np2 = cap;  // capacity of the later-position list
   const SymView V = sym_view(base, m, np2, nfw, rows);
-  // 1. later positions: child boundaries and t's own rows, sorted, unique
-  int nc = 0;
+  uint32_t* bm = (uint32_t*)base + words;  // the bitmap
+  int* anc = (int*)(bm + BW);              // per ancestor: begin, size, bit offset
+  if (lane_id() == 0) {
+    int i = 0, off = 0;
+    for (int a = t; a > 0;) {
+      a = (a - 1) >> 1;
+      const int sz = M.nsize[a];
+      if (sz > 0) {
+        anc[3 * i] = M.nbegin[a];
+        anc[3 * i + 1] = sz;
+        anc[3 * i + 2] = off;
+        off += sz;
+        i++;
+      }
+    }
+  }
+  for (int w = lane_id(); w < BW; w += 64) bm[w] = 0u;
+  wave_fence();
+  // 1. mark the later positions of the child records and of t's own rows
+  bool bad1 = false;
+  auto mark = [&](int q) {
+    int lo = 0, hi = na - 1, f = -1;
+    while (lo <= hi) {  // nearest ancestor range starting at or before q
+      const int mid = (lo + hi) >> 1;
+      if (anc[3 * mid] <= q) {
+        f = mid;
+        lo = mid + 1;
+      } else {
+        hi = mid - 1;
+      }
+    }
+    if (f < 0 || q >= anc[3 * f] + anc[3 * f + 1]) {
+      bad1 = true;
+      return;
+    }
+    const int b = anc[3 * f + 2] + (q - anc[3 * f]);
+    atomicOr(&bm[b >> 5], 1u << (b & 31));
+  };
   for (int c = 0; c < 2; c++) {
     int off = cst[c];
     const int end = cst[c] + cin[c];
@@ -205,45 +261,54 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
       const int len = src[off];
       for (int i = lane_id(); i < len; i += 64) {
         const int q = src[off + 1 + i];
-        V.bd[nc + i] = q >= e0 ? q : 0x7FFFFFFF;
+        if (q >= e0) mark(q);
       }
-      nc += len;
       off += 1 + len;
     }
   }
-  for (int k0 = 0; k0 < m; k0 += 64) {
-    const int k = k0 + lane_id();
-    int cnt = 0;
-    if (k < m) {
-      const int v = M.vperm[b0 + k];
-      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) cnt += (M.viperm[M.gci[e]] >= e0);
+  for (int k = lane_id(); k < m; k += 64) {
+    const int v = M.vperm[b0 + k];
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+      const int q = M.viperm[M.gci[e]];
+      if (q >= e0) mark(q);
     }
-    const int inc = wave_incl_scan(cnt);
-    int o = nc + inc - cnt;
-    if (k < m) {
-      const int v = M.vperm[b0 + k];
-      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-        const int q = M.viperm[M.gci[e]];
-        if (q >= e0) V.bd[o++] = q;
-      }
-    }
-    nc += wave_bcast(inc, 63);
   }
-  for (int i = nc + lane_id(); i < np2; i += 64) V.bd[i] = 0x7FFFFFFF;
+  if (ballot64(bad1)) {
+    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+    return;
+  }
   wave_fence();
-  wave_sort_ids(V.bd, np2, np2);
+  // read the bitmap back: positions in increasing order
   int nbd = 0;
-  for (int i0 = 0; i0 < np2; i0 += 64) {
-    const int i = i0 + lane_id();
-    const int x = V.bd[i];
-    const bool keep = x != 0x7FFFFFFF && (i == 0 || V.bd[i - 1] != x);
-    const uint64_t bal = ballot64(keep);
-    const int dst = nbd + popc64(bal & lanemask_lt());  // dst <= i: in place
-    wave_fence();
-    if (keep) V.bd[dst] = x;
-    wave_fence();
-    nbd += popc64(bal);
+  for (int w0 = 0; w0 < BW; w0 += 64) {
+    const int w = w0 + lane_id();
+    uint32_t x = w < BW ? bm[w] : 0u;
+    const int c = popc32(x);
+    const int inc = wave_incl_scan(c);
+    int o = nbd + inc - c;
+    while (x) {
+      const int b = w * 32 + __ffs(x) - 1;
+      x &= x - 1;
+      int lo = 0, hi = na - 1, f = 0;
+      while (lo <= hi) {  // the ancestor whose bit range holds b
+        const int mid = (lo + hi) >> 1;
+        if (anc[3 * mid + 2] <= b) {
+          f = mid;
+          lo = mid + 1;
+        } else {
+          hi = mid - 1;
+        }
+      }
+      if (o < np2) V.bd[o] = anc[3 * f] + (b - anc[3 * f + 2]);
+      o++;
+    }
+    nbd += wave_bcast(inc, 63);
   }
+  if (nbd > np2) {
+    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+    return;
+  }
+  wave_fence();
   const int F = m + nbd;
   const int FW = (F + 31) >> 5;
   // 2. forward rows in F indices
@@ -354,10 +419,10 @@ __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int
 
 // ---------------------------------------------------------------- elim
 // The columns of a node are a sequential chain of dependent steps, so their
-// latency decides the time of the top tree levels.  A step only builds the
-// column's row and finds its least entry, the parent, to queue the row on;
-// column counts and parents are read off the rows afterwards, in parallel
-// (sym_counts).  The queue links and the forward rows are copied into the
+// latency decides the time of the top tree levels.  A step builds the
+// column's row, finds its least entry (the parent, found by ballot) to queue
+// the row on, and counts its entries (one DPP reduction).  The queue links
+// and the forward rows are copied into the
 // wave's LDS slice when they fit (kLds), and every lane keeps its words of
 // the last column in registers: the next column is most often that column's
 // parent, and then its row needs no memory read.
@@ -410,6 +475,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     wave_fence();
   }
   const bool regs = FW <= 64 * FP_SYM_REGW;
+  const int b0 = M.nbegin[t];
   uint32_t prev[FP_SYM_REGW];
 #pragma unroll
   for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = 0u;
@@ -419,6 +485,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     uint32_t* rk = V.rows + (long long)k * stride;
     bool bad = false;
     uint32_t first = 0xFFFFFFFFu;
+    int cnt = 0;
 #pragma unroll
     for (int i = 0; i < FP_SYM_REGW; i++) {
       if (i * 64 < FW) {
@@ -429,6 +496,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
           rk[w] = x;
         }
         prev[i] = x;
+        cnt += popc32(x);
         // least set bit: lowest word with a bit, found by ballot
         const uint64_t b = ballot64(x != 0u);
         if (first == 0xFFFFFFFFu && b) {
@@ -443,6 +511,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
       for (int w = lane_id() + 64 * FP_SYM_REGW; w < FW; w += 64) {
         const uint32_t x = sym_word(V, next, oent, k, w, q0, r0, r1, rows, stride, false, 0u, &bad);
         rk[w] = x;
+        cnt += popc32(x);
         if (x && f2 == 0xFFFFFFFFu) f2 = (uint32_t)(w * 32 + __ffs(x) - 1);
       }
       f2 = wave_min_u32(f2);
@@ -455,13 +524,21 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
       }
       return;
     }
-    if (lane_id() == 0 && first != 0xFFFFFFFFu) {
-      if ((int)first < m) {
-        next[k] = head[first];
-        head[first] = k;
-      } else {
-        V.outl[nout] = k;
+    cnt = wave_sum_i32(cnt);
+    if (lane_id() == 0) {
+      M.vcc[b0 + k] = 1 + cnt;
+      int par = -1;
+      if (first != 0xFFFFFFFFu) {
+        if ((int)first < m) {
+          par = b0 + (int)first;
+          next[k] = head[first];
+          head[first] = k;
+        } else {
+          par = V.bd[first - m];
+          V.outl[nout] = k;
+        }
       }
+      M.vpar[b0 + k] = par;
     }
     if (first != 0xFFFFFFFFu && (int)first >= m) nout++;
     wave_fence();  // queue links and outl reach every lane of the wave
@@ -492,24 +569,6 @@ __device__ __forceinline__ void sym_elim(const FpMesh& M, int t, int cls, int* l
   if (sym_elim_class(h, lds_words) == cls) sym_elim_run<kLds>(M, t, V, h, lds);
 }
 
-// column counts and parents of a node's columns from their rows
-__device__ __forceinline__ void sym_counts(const FpMesh& M, int t, const SymView& V, const int* h) {
-  const int m = h[SH_M], FW = h[SH_FW], stride = h[SH_STRIDE];
-  const int b0 = M.nbegin[t];
-  for (int k = lane_id(); k < m; k += 64) {
-    const uint32_t* row = V.rows + (long long)k * stride;
-    int c = 0;
-    int f = -1;
-    for (int w = k >> 5; w < FW; w++) {
-      const uint32_t x = row[w];
-      c += popc32(x);
-      if (x && f < 0) f = w * 32 + __ffs(x) - 1;
-    }
-    M.vcc[b0 + k] = 1 + c;
-    M.vpar[b0 + k] = f < 0 ? -1 : (f < m ? b0 + f : V.bd[f - m]);
-  }
-}
-
 // ---------------------------------------------------------------- emit
 __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
   SymView V;
@@ -524,7 +583,6 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
     sym_drop(M, t, FP_SITE_SYM_LIVE);
     return;
   }
-  sym_counts(M, t, V, h);
   int total = 0;
   for (int i = 0; i < nout; i++) {
     const int r = V.outl[i];
