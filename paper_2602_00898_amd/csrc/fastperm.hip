@@ -493,7 +493,7 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
   MESH;
   FP_LDS_DECL;
   const int nsl = 1 << c;
-  const long long sb = (M.lds_bytes / nsl) & ~15ll;
+  const long long sb = c == 0 ? (long long)M.lds_big : (M.lds_bytes / nsl) & ~15ll;
   const int cnt = C->task_cnt[c];
   if (wave_id() >= nsl) return;
   char* slice = fp_lds + sb * wave_id();
@@ -522,24 +522,23 @@ __global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ M
   for (int x = gwave(); x < cnt; x += nwaves()) sym_prep(M, lo + x, d);
 }
 // Elimination of the nodes whose queue links and forward rows fit in an LDS
-// slice: cls 0 with four waves per workgroup (a quarter of the LDS each),
-// cls 1 with one wave owning the whole LDS.
+// slice: cls 0 with four waves per workgroup (a quarter of the per-node LDS
+// each), cls 1 with one wave owning the large slice.
 __global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ Mp, int d, int cls) {
   MESH;
   FP_LDS_DECL;
   const int nsl = cls == 0 ? FP_WAVES : 1;
   if (wave_id() >= nsl) return;
-  const long long lds_words = M.lds_bytes / 4;
-  int* slice = (int*)fp_lds + (lds_words / nsl) * wave_id();
+  int* slice = (int*)fp_lds + (M.lds_bytes / 4 / nsl) * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
   const int wv = (int)blockIdx.x * nsl + wave_id(), nw = (int)gridDim.x * nsl;
-  for (int x = wv; x < cnt; x += nw) sym_elim<true>(M, lo + x, cls, slice, lds_words);
+  for (int x = wv; x < cnt; x += nw) sym_elim<true>(M, lo + x, cls, slice);
 }
 // nodes too large for the whole LDS: links and rows in global memory
 __global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(const FpMesh* __restrict__ Mp, int d) {
   MESH;
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  for (int x = gwave(); x < cnt; x += nwaves()) sym_elim<false>(M, lo + x, 2, nullptr, M.lds_bytes / 4);
+  for (int x = gwave(); x < cnt; x += nwaves()) sym_elim<false>(M, lo + x, 2, nullptr);
 }
 __global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ Mp, int d) {
   MESH;
@@ -844,7 +843,7 @@ fp_status run_job(Job& J) {
   FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
   FPL(k_md_tasks, B(nn), T, 0, st, dm, nn);
   for (int c = 0; c < 3; c++)
-    FPL(k_md, dim3(2 * J.h->ncu), T, J.h->lds_bytes, st, dm, c);
+    FPL(k_md, dim3(2 * J.h->ncu), T, c == 0 ? J.h->lds_big : J.h->lds_bytes, st, dm, c);
   J.check();
   // a node whose local order failed leaves its positions unset: stop here
   {
@@ -862,7 +861,7 @@ fp_status run_job(Job& J) {
     FPL(k_sym_prep, G, T, 0, st, dm, d);
     const dim3 G1(std::max(1, std::min(cnt, 4 * J.h->ncu)));
     FPL(k_sym_elim, G, T, J.h->lds_bytes, st, dm, d, 0);
-    FPL(k_sym_elim, G1, T, J.h->lds_bytes, st, dm, d, 1);
+    FPL(k_sym_elim, G1, T, J.h->lds_big, st, dm, d, 1);
     FPL(k_sym_elim_glb, G, T, 0, st, dm, d);
     FPL(k_sym_emit, G, T, 0, st, dm, d);
     J.check();
@@ -911,6 +910,27 @@ void fp_options_default(fp_options* o) {
   o->flags = 0;
 }
 
+// LDS of the one-wave kernels for large nodes: what one workgroup may hold
+// on this device (160 KB on gfx950), at least the per-node size
+static int big_lds(int device) {
+  int lim = 0;
+  if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    return FP_LDS_BYTES;
+  }
+  const int big = std::min(lim, 160 * 1024) & ~15;
+  if (big <= FP_LDS_BYTES) return FP_LDS_BYTES;
+  if (hipFuncSetAttribute((const void*)k_md, hipFuncAttributeMaxDynamicSharedMemorySize, big) !=
+          hipSuccess ||
+      hipFuncSetAttribute((const void*)k_sym_elim, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          big) != hipSuccess) {
+    (void)hipGetLastError();
+    return FP_LDS_BYTES;
+  }
+  return big;
+}
+
 fp_status fp_create(fp_handle** h) {
   if (!h) return FP_ERR_ARG;
   *h = nullptr;
@@ -926,6 +946,7 @@ fp_status fp_create(fp_handle** h) {
   }
   H->ncu = std::max(1, ncu);
   H->lds_bytes = FP_LDS_BYTES;
+  H->lds_big = big_lds(H->device);
   H->tk_name[0] = 0;
   H->tk_n = 0;
   H->tk_failed = false;
@@ -1008,6 +1029,7 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   M.status_out = out->status;
   M.max_nodes_out = out->max_nodes;
   M.lds_bytes = h->lds_bytes;
+  M.lds_big = h->lds_big;
   J.ctl = M.ctl;
   J.dm = (const FpMesh*)(ws + P.o_mesh);
   J.timing = (opts->flags & FP_FLAG_TIMING) != 0;

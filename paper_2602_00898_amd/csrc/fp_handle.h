@@ -23,6 +23,7 @@ struct fp_handle {
   int device;
   int ncu;
   int lds_bytes;
+  int lds_big;
   int* host;  // pinned: scalars read back between stages, and the job copy
   hipEvent_t ev[FP_NSTAGE + 1];
   bool timed;  // the last call recorded stage events

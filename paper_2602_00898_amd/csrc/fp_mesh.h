@@ -62,6 +62,7 @@ struct FpMesh {
   long long Ecap; // capacity of the vertex graph
   int NNcap;      // capacity of heap arrays
   int lds_bytes;  // dynamic LDS of the per-node kernels
+  int lds_big;    // LDS of the one-wave kernels for large nodes (>= lds_bytes)
   // workspace
   FpCtl* ctl;
   int* grp;       // n+1

@@ -226,34 +226,38 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int*
 }
 
 // ---------------------------------------------------------------- SPARSE
+// The pivot of the sparse layout is found through degree buckets: bucket d
+// is a bitmap of the remaining vertices of degree d (degrees stay <= C here),
+// cnt[d] its population; the pivot is the lowest vertex of the lowest
+// non-empty bucket, the (degree, index) minimum, found with two ballots.
 struct MdSp {
-  uint16_t* rows;  // m*C
-  uint16_t* len;   // m
-  uint32_t* key;   // m
-  uint32_t* gmin;  // G
-  int* dl;         // 2G
-  int* nbl;        // m
-  int m, C, G;
+  uint16_t* rows;   // m*C
+  uint16_t* len;    // m: degree = row length
+  uint32_t* alive;  // MW: remaining vertices
+  uint32_t* bk;     // (C+1) x MW: vertices by degree
+  int* cnt;         // C+1
+  int* nbl;         // 64: the pivot's neighbours
+  int m, C, MW;
 };
 
 __device__ __forceinline__ long long md_sp_bytes(int m, int C) {
-  const long long G = md_groups(m);
-  return 2ll * m * C + 2ll * m + 4ll * m + 4 * G + 8 * G + 4ll * m + 64;
+  const long long MW = (m + 31) / 32;
+  return 2ll * m * C + 2ll * m + 4 * MW + 4 * (C + 1) * MW + 4ll * (C + 1) + 4 * 64 + 64;
 }
 
 __device__ __forceinline__ void md_sp_carve(MdSp& S, char* mem, int m, int C) {
   S.m = m;
   S.C = C;
-  S.G = md_groups(m);
+  S.MW = (m + 31) >> 5;
   char* p = mem;
-  S.key = (uint32_t*)p;
-  p += 4ll * m;
+  S.bk = (uint32_t*)p;
+  p += 4ll * (C + 1) * S.MW;
+  S.alive = (uint32_t*)p;
+  p += 4ll * S.MW;
+  S.cnt = (int*)p;
+  p += 4ll * (C + 1);
   S.nbl = (int*)p;
-  p += 4ll * m;
-  S.gmin = (uint32_t*)p;
-  p += 4 * S.G;
-  S.dl = (int*)p;
-  p += 8 * S.G;
+  p += 4 * 64;
   S.len = (uint16_t*)p;
   p += 2ll * m;
   p = mem + ((p - mem + 15) & ~15ll);  // mem is 16-byte aligned; keeps the LDS address space
@@ -399,15 +403,22 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
   // SPARSE when the rows fit with a useful capacity
   int C = 0;
   {
+    const long long MW = (m + 31) / 32;
     const long long fixed = md_sp_bytes(m, 0) + 16;
-    C = (int)min(64ll, (slice_bytes - fixed) / (2ll * m));
+    C = (int)min(64ll, (slice_bytes - fixed) / (2ll * m + 4 * MW + 4));
   }
   bool sparse_ok = C >= 6;
   MdSp S;
   if (sparse_ok) {
     md_sp_carve(S, slice, m, C);
     int over = 0;
-    for (int g = lane_id(); g < 2 * S.G; g += 64) S.dl[g] = 0;
+    for (long long i = lane_id(); i < (long long)(C + 1) * S.MW; i += 64) S.bk[i] = 0u;
+    for (int i = lane_id(); i <= C; i += 64) S.cnt[i] = 0;
+    for (int w = lane_id(); w < S.MW; w += 64) {
+      const int hi = min(32, m - w * 32);
+      S.alive[w] = hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
+    }
+    wave_fence();
     for (int i = lane_id(); i < m; i += 64) {
       const int v = V[i];
       uint16_t* ri = S.rows + (long long)i * C;
@@ -424,8 +435,10 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         len++;
       }
       if (len > C) over = 1;
-      S.len[i] = (uint16_t)min(len, C);
-      S.key[i] = ((uint32_t)len << 16) | (uint32_t)i;
+      const int d = min(len, C);
+      S.len[i] = (uint16_t)d;
+      atomicOr(&S.bk[(long long)d * S.MW + (i >> 5)], 1u << (i & 31));
+      atomicAdd(&S.cnt[d], 1);
     }
     wave_fence();
     sparse_ok = !ballot64(over);
@@ -434,22 +447,37 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
   int na = m;             // vertices remaining
   const int* vmap = V;
   if (sparse_ok) {
-    for (int g = 0; g < S.G; g++) {
-      const int i = g * 64 + lane_id();
-      uint32_t k = i < m ? S.key[i] : FP_KEY_INF;
-      k = wave_min_u32(k);
-      if (lane_id() == 0) S.gmin[g] = k;
-    }
-    wave_fence();
     while (na > 0 && na > mbit) {
-      const uint32_t km = md_argmin(S.gmin, S.G);
-      const int p = (int)(km & 0xFFFFu);
-      if (km == FP_KEY_INF || p >= m) {
+      // pivot: lowest vertex of the lowest non-empty degree bucket
+      int d = -1;
+      for (int c0 = 0; c0 <= C; c0 += 64) {
+        const int dd = c0 + lane_id();
+        const uint64_t b = ballot64(dd <= C && S.cnt[dd] > 0);
+        if (b) {
+          d = c0 + __builtin_ctzll(b);
+          break;
+        }
+      }
+      int p = -1;
+      if (d >= 0) {
+        const uint32_t* row = S.bk + (long long)d * S.MW;
+        for (int w0 = 0; w0 < S.MW; w0 += 64) {
+          const int w = w0 + lane_id();
+          const uint32_t x = w < S.MW ? row[w] : 0u;
+          const uint64_t b = ballot64(x != 0u);
+          if (b) {
+            const int l = __builtin_ctzll(b);
+            p = (w0 + l) * 32 + __ffs(wave_bcast_u32(x, l)) - 1;
+            break;
+          }
+        }
+      }
+      if (p < 0 || p >= m || S.len[p] != d) {  // never expected: stop before any wild index
         if (lane_id() == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
         md_map_order(M, vmap, m, pos0, done);
         goto fail;
       }
-      const int kp = S.len[p];
+      const int kp = d;
       const uint16_t* rpv = S.rows + (long long)p * C;
       // dry run: would any neighbour row overflow?
       int over = 0;
@@ -470,15 +498,18 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       if (ballot64(over)) break;  // convert with p still present
       if (lane_id() == 0) {
         M.vperm[pos0 + done] = p;  // local index; mapped below
-        S.key[p] = FP_KEY_INF;
-        S.dl[p >> 6] = 1;
+        S.alive[p >> 5] &= ~(1u << (p & 31));
+        S.bk[(long long)d * S.MW + (p >> 5)] &= ~(1u << (p & 31));
+        S.cnt[d] -= 1;
       }
       for (int i = lane_id(); i < kp; i += 64) S.nbl[i] = rpv[i];
       wave_fence();
+      // the neighbours become a clique; their degrees move between buckets
       for (int i = lane_id(); i < kp; i += 64) {
         const int u = S.nbl[i];
         uint16_t* ru = S.rows + (long long)u * C;
-        int lu = S.len[u];
+        const int d1 = S.len[u];
+        int lu = d1;
         for (int q = 0; q < lu; q++)
           if (ru[q] == p) {
             ru[q] = ru[lu - 1];
@@ -493,11 +524,15 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
           if (!f) ru[lu++] = (uint16_t)x;
         }
         S.len[u] = (uint16_t)lu;
-        S.key[u] = ((uint32_t)lu << 16) | (uint32_t)u;
-        S.dl[u >> 6] = 1;
+        if (lu != d1) {
+          const uint32_t bit = 1u << (u & 31);
+          atomicAnd(&S.bk[(long long)d1 * S.MW + (u >> 5)], ~bit);
+          atomicOr(&S.bk[(long long)lu * S.MW + (u >> 5)], bit);
+          atomicSub(&S.cnt[d1], 1);
+          atomicAdd(&S.cnt[lu], 1);
+        }
       }
       wave_fence();
-      md_refresh_dirty(S.key, S.gmin, S.dl, m, S.G);
       done++;
       na--;
     }
@@ -516,7 +551,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
       int run = 0;
       for (int i0 = 0; i0 < m; i0 += 64) {
         const int i = i0 + lane_id();
-        const bool al = i < m && S.key[i] != FP_KEY_INF;
+        const bool al = i < m && ((S.alive[i >> 5] >> (i & 31)) & 1u);
         if (i < m) slen[i] = S.len[i];
         const uint64_t bal = ballot64(al);
         if (i < m) ni[i] = al ? run + popc64(bal & lanemask_lt()) : -1;

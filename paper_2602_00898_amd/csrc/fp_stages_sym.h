@@ -551,22 +551,21 @@ __device__ __forceinline__ long long sym_elim_lds_words(const int* h) {
   return 2ll * h[SH_M] + 1 + h[SH_ROWS] + h[SH_NFW];
 }
 
-// 0: the links fit a quarter of the LDS (four waves per workgroup), 1: the
-// whole LDS (one wave), 2: neither (global memory)
-__device__ __forceinline__ int sym_elim_class(const int* h, long long lds_words) {
+// 0: the links fit a quarter of the per-node LDS (four waves per workgroup),
+// 1: the large one-wave slice, 2: neither (global memory)
+__device__ __forceinline__ int sym_elim_class(const FpMesh& M, const int* h) {
   const long long need = sym_elim_lds_words(h);
-  if (need <= lds_words / FP_WAVES) return 0;
-  if (need <= lds_words) return 1;
+  if (need <= (long long)M.lds_bytes / 4 / FP_WAVES) return 0;
+  if (need <= (long long)M.lds_big / 4) return 1;
   return 2;
 }
 
 template <bool kLds>
-__device__ __forceinline__ void sym_elim(const FpMesh& M, int t, int cls, int* lds,
-                                         long long lds_words) {
+__device__ __forceinline__ void sym_elim(const FpMesh& M, int t, int cls, int* lds) {
   SymView V;
   int h[SH_WORDS];
   if (!sym_load(M, t, &V, h)) return;
-  if (sym_elim_class(h, lds_words) == cls) sym_elim_run<kLds>(M, t, V, h, lds);
+  if (sym_elim_class(M, h) == cls) sym_elim_run<kLds>(M, t, V, h, lds);
 }
 
 // ---------------------------------------------------------------- emit
