@@ -8,11 +8,17 @@ inputs resident in device memory before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
                     [--no-batch] [--no-serve] [--serve-requests R] [--lanes L]
+                    [--copy-probe-mib M]
+    python bench.py --traffic-from FETCH.csv WRITE.csv [--copy-probe-mib M]
 
 Prints one JSON line.  `value` is mesh vertices ordered per second (whole
 job), `roofline` rates the dominant kernel (its launches timed with HIP
 events on the call's stream during the timed steps) against MI355X's HBM
-peak with algorithmic bytes, `cpu_baseline` times the serial CPU oracle on
+peak with algorithmic bytes; its `traffic` is the HBM bytes per launch that
+two rocprofv3 counter runs measured (FETCH_SIZE, WRITE_SIZE, each scaled by
+what the counter reads for a plain device copy of known size), kept in
+profiles/traffic.json with a digest of the kernel sources and reported only
+while the sources still match.  `cpu_baseline` times the serial CPU oracle on
 one core over a bounded sample of the same workload.  `batch` compares
 ordering 256 meshes of uneven size one at a time with the batched call;
 `serving` drives the request server with Poisson arrivals and reports
@@ -22,6 +28,8 @@ p50/p99 latency.
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import statistics
@@ -53,6 +61,90 @@ def patch_size_for(n):
     """Target patch size of a batch mesh: the committed autotune table."""
     from paper_2602_00898_amd.autotune import patch_size_for as ps
     return ps(n)
+
+
+def csrc_digest():
+    """sha256 over the HIP sources (names and contents) of the library."""
+    d = os.path.join(ROOT, "paper_2602_00898_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def traffic_for(kernel):
+    """Measured HBM bytes per launch of a kernel, or None when there is no
+    measurement for the current sources."""
+    try:
+        with open(TRAFFIC) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("csrc_sha256") != csrc_digest():
+        return None
+    k = t.get("kernels", {}).get(kernel)
+    return None if k is None else k["bytes_per_launch"]
+
+
+def copy_probe(mib):
+    """A plain device copy of known size, for calibrating the byte counters
+    (an elementwise kernel rather than a DMA copy, so the counters see it)."""
+    import torch
+    dev = torch.device("cuda:0")
+    src = torch.ones(mib << 18, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1, out=dst)  # an elementwise kernel: reads and writes mib MiB
+    torch.cuda.synchronize(dev)
+    log(f"copy probe: 3 x {mib} MiB")
+
+
+def _counter_rows(path, counter):
+    """(kernel name, value) of every dispatch row of one counter."""
+    out = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if r.get("Counter_Name") == counter:
+                out.append((r["Kernel_Name"], float(r["Counter_Value"])))
+    return out
+
+
+def traffic_from(fetch_csv, write_csv, mib):
+    """Write profiles/traffic.json from a FETCH_SIZE run and a WRITE_SIZE run
+    of `bench.py --copy-probe-mib M` (counter values in KiB per dispatch)."""
+    known = float(mib << 20)
+    res = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rows = _counter_rows(path, counter)
+        cp = [v * 1024.0 for k, v in rows if "copy" in k.lower() or "elementwise" in k.lower()]
+        cp = [v for v in cp if v > 0.5 * known]
+        if not cp:
+            raise SystemExit(f"no copy-probe dispatch in {path}")
+        factor = known / statistics.median(cp)
+        per = {}
+        for k, v in rows:
+            name = k.split("(")[0].strip()
+            if name in KERNELS:
+                per.setdefault(name, []).append(v * 1024.0 * factor)
+        res[key] = (factor, per)
+    kernels = {}
+    for name in set(res["fetch"][1]) & set(res["write"][1]):
+        f, w = res["fetch"][1][name], res["write"][1][name]
+        kernels[name] = {"fetch_bytes_per_launch": round(sum(f) / len(f)),
+                         "write_bytes_per_launch": round(sum(w) / len(w)),
+                         "bytes_per_launch": round(sum(f) / len(f) + sum(w) / len(w)),
+                         "launches": len(f)}
+    out = {"csrc_sha256": csrc_digest(), "copy_probe_mib": mib,
+           "fetch_factor": round(res["fetch"][0], 4), "write_factor": round(res["write"][0], 4),
+           "kernels": kernels}
+    with open(TRAFFIC, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def kernel_bytes(name, n, nnz_g):
@@ -280,12 +372,21 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--lanes", type=int, default=8)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run a plain device copy of this size first (counter calibration)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="summarise two counter runs into profiles/traffic.json and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from, args.copy_probe_mib or 256)
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the ordering of one mesh is not sharded across "
               "GPUs in this library (--gpus must be 1)", file=sys.stderr)
         sys.exit(2)
     A, batch_meshes, serve_reqs = make_inputs(args)
+    if args.copy_probe_mib:
+        copy_probe(args.copy_probe_mib)
     g = run_plain(args, A)
     batch = None if batch_meshes is None else run_batch(args, batch_meshes)
     serving = None if serve_reqs is None else run_serve(args, serve_reqs)
@@ -311,7 +412,8 @@ def main():
                    "depth": g["D"], "nnzL": g["nnzL"]},
         "roofline": {"bound": "hbm", "kernel": g["dom"], "achieved": round(g["achieved"], 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(g["achieved"] / HBM_PEAK_GBS, 6), "traffic": None,
+                     "frac": round(g["achieved"] / HBM_PEAK_GBS, 6),
+                     "traffic": traffic_for(g["dom"]),
                      "bytes_per_launch": round(g["dom_bytes"]),
                      "avg_launch_ms": round(g["dom_avg_ms"], 5),
                      "launches_per_step": g["dom_launches"]},

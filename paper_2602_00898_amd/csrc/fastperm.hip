@@ -22,7 +22,7 @@
 
 #define MESH                  \
   const FpMesh& M = *Mp;      \
-  FpCtl* C = M.ctl;           \
+  gptr<FpCtl> C = M.ctl;      \
   (void)C
 
 // ==========================================================================
@@ -85,7 +85,7 @@ __global__ void k_ingest(const FpMesh* __restrict__ Mp, int fill) {
     if (fill)
       gather_vertex_row(M, v, M.gci + M.grp[v], &eb);
     else
-      M.pcnt[v] = gather_vertex_row(M, v, nullptr, &eb);
+      M.pcnt[v] = gather_vertex_row(M, v, gptr<int>(nullptr), &eb);
   }
   if (eb) fp_fail(C, eb, FP_SITE_INGEST, 0);
 }
@@ -134,8 +134,8 @@ __global__ void k_seed_push(const FpMesh* __restrict__ Mp, int nseeds) {
 __global__ void k_bfs_level(const FpMesh* __restrict__ Mp, int lvl) {
   MESH;
   const int nf = M.fcnt[lvl];
-  const int* cur = (lvl & 1) ? M.fb : M.fa;
-  int* nxt = (lvl & 1) ? M.fa : M.fb;
+  gptr<const int> cur = (lvl & 1) ? M.fb : M.fa;
+  gptr<int> nxt = (lvl & 1) ? M.fa : M.fb;
   for (int f0 = gwave() * 64; f0 < nf; f0 += nwaves() * 64) {
     const int f = f0 + lane_id();
     int e0 = 0, deg = 0;
@@ -174,7 +174,7 @@ __global__ void k_cc_init(const FpMesh* __restrict__ Mp) {
 }
 __global__ void k_cc_hook(const FpMesh* __restrict__ Mp) {
   MESH;
-  int* comp = M.fb;
+  gptr<int> comp = M.fb;
   int ch = 0;
   for (int v = gtid(); v < M.n; v += gsize()) {
     const int cv = comp[v];
@@ -192,7 +192,7 @@ __global__ void k_cc_hook(const FpMesh* __restrict__ Mp) {
 }
 __global__ void k_cc_jump(const FpMesh* __restrict__ Mp) {
   MESH;
-  int* comp = M.fb;
+  gptr<int> comp = M.fb;
   int ch = 0;
   for (int v = gtid(); v < M.n; v += gsize()) {
     if (comp[v] < 0) continue;
@@ -319,7 +319,7 @@ __global__ void k_qrow(const FpMesh* __restrict__ Mp, int P, int fill) {
   for (int p = gwave(); p < P; p += nwaves()) {
     const int a0 = M.pptr[p], a1 = M.pptr[p + 1];
     int last = -1, cnt = 0;
-    int* out = fill ? M.qci + M.qptr[p] : nullptr;
+    gptr<int> out = fill ? M.qci + M.qptr[p] : gptr<int>(nullptr);
     while (true) {
       uint32_t m = 0xFFFFFFFFu;
       for (int i = a0 + lane_id(); i < a1; i += 64) {
@@ -1038,7 +1038,7 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   h->tk_failed = false;
   // control block cleared, job description copied in
   const int words = (int)(sizeof(FpCtl) / 4);
-  hipLaunchKernelGGL(k_fill, dim3((words + FP_WG - 1) / FP_WG), dim3(FP_WG), 0, J.st, (int*)M.ctl,
+  hipLaunchKernelGGL(k_fill, dim3((words + FP_WG - 1) / FP_WG), dim3(FP_WG), 0, J.st, (int*)(FpCtl*)M.ctl,
                      words, 0);
   memcpy(h->host, &M, sizeof(M));
   if (hipMemcpyAsync((void*)J.dm, h->host, sizeof(M), hipMemcpyHostToDevice, J.st) != hipSuccess ||

@@ -145,12 +145,13 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 // Append to a list whose length is *ctr: one atomic per wave instead of one
 // per item.  Call with the whole wave; returns the slot of a lane with `pred`.
-__device__ __forceinline__ int wave_append(int* ctr, bool pred) {
+template <class P>
+__device__ __forceinline__ int wave_append(P ctr, bool pred) {
   const uint64_t bal = ballot64(pred);
   int base = 0;
   if (bal) {
     const int leader = __builtin_ctzll(bal);
-    if (lane_id() == leader) base = atomicAdd(ctr, popc64(bal));
+    if (lane_id() == leader) base = atomicAdd(ctr, (int)popc64(bal));
     base = wave_bcast(base, leader);
   }
   return base + popc64(bal & lanemask_lt());
@@ -158,7 +159,8 @@ __device__ __forceinline__ int wave_append(int* ctr, bool pred) {
 
 // Same for per-key counters ctr[key]: one atomic per distinct key present
 // in the wave (mesh vertices of a wave mostly share a few patches or nodes).
-__device__ __forceinline__ int wave_append_keyed(int* ctr, int key, bool pred) {
+template <class P>
+__device__ __forceinline__ int wave_append_keyed(P ctr, int key, bool pred) {
   uint64_t pending = ballot64(pred);
   int slot = 0;
   while (pending) {
@@ -166,7 +168,7 @@ __device__ __forceinline__ int wave_append_keyed(int* ctr, int key, bool pred) {
     const int lk = wave_bcast(key, leader);
     const uint64_t grp = ballot64(pred && key == lk) & pending;
     int base = 0;
-    if (lane_id() == leader) base = atomicAdd(&ctr[lk], popc64(grp));
+    if (lane_id() == leader) base = atomicAdd(&ctr[lk], (int)popc64(grp));
     base = wave_bcast(base, leader);
     if ((grp >> lane_id()) & 1ull) slot = base + popc64(grp & lanemask_lt());
     pending &= ~grp;

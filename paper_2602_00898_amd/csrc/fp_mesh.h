@@ -2,7 +2,92 @@
 // host API and the device stages.
 #pragma once
 
+#include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <type_traits>
+
+#ifndef FP_GLOBAL
+#define FP_GLOBAL __attribute__((address_space(1)))
+#define FP_GLOBAL_ATOMICS 1
+#endif
+
+// A pointer into device global memory.  Element access through it compiles
+// to global (not flat) loads and stores: a flat access also counts against
+// the LDS counter, so every wait for an LDS result would wait for the
+// outstanding global stores as well.  It converts to a plain pointer where
+// one is needed.
+template <class T>
+struct gptr {
+  T* p;
+  gptr() = default;
+  __host__ __device__ constexpr gptr(T* q) : p(q) {}
+  template <class U>  // int -> const int and the like
+  __host__ __device__ constexpr gptr(gptr<U> o) : p(o.p) {}
+  template <class U>  // the same memory seen as another element type
+  __host__ __device__ constexpr gptr<U> as() const {
+    return gptr<U>((U*)p);
+  }
+  __host__ __device__ constexpr operator T*() const { return p; }
+  __device__ __forceinline__ FP_GLOBAL T& operator[](long long i) const {
+    return ((FP_GLOBAL T*)p)[i];
+  }
+  __device__ __forceinline__ FP_GLOBAL T& operator*() const { return *(FP_GLOBAL T*)p; }
+  __device__ __forceinline__ FP_GLOBAL T* operator->() const { return (FP_GLOBAL T*)p; }
+  template <class I, class = typename std::enable_if<std::is_integral<I>::value>::type>
+  __host__ __device__ constexpr gptr operator+(I i) const {
+    return gptr(p + i);
+  }
+  template <class I, class = typename std::enable_if<std::is_integral<I>::value>::type>
+  __host__ __device__ constexpr gptr operator-(I i) const {
+    return gptr(p - i);
+  }
+  __host__ __device__ constexpr long long operator-(gptr o) const { return p - o.p; }
+  template <class I>
+  __host__ __device__ gptr& operator+=(I i) {
+    p += i;
+    return *this;
+  }
+};
+
+#ifdef FP_GLOBAL_ATOMICS
+// device-scope relaxed atomics on global memory (the semantics of HIP's
+// atomicAdd family), taking the pointers that gptr element access yields
+template <class T>
+__device__ __forceinline__ T atomicAdd(FP_GLOBAL T* p, T v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T atomicSub(FP_GLOBAL T* p, T v) {
+  return __hip_atomic_fetch_add(p, (T)(0 - v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T atomicOr(FP_GLOBAL T* p, T v) {
+  return __hip_atomic_fetch_or(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T atomicAnd(FP_GLOBAL T* p, T v) {
+  return __hip_atomic_fetch_and(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T atomicMin(FP_GLOBAL T* p, T v) {
+  return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T atomicMax(FP_GLOBAL T* p, T v) {
+  return __hip_atomic_fetch_max(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T atomicExch(FP_GLOBAL T* p, T v) {
+  return __hip_atomic_exchange(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <class T>
+__device__ __forceinline__ T atomicCAS(FP_GLOBAL T* p, T cmp, T v) {
+  __hip_atomic_compare_exchange_strong(p, &cmp, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+  return cmp;
+}
+#endif
 
 // control block at the start of every mesh workspace (device memory,
 // cleared by fp_ctl_init before the pipeline starts)
@@ -35,27 +120,27 @@ struct FpMesh {
   // input pattern (device)
   long long n_dof;
   int b;
-  const int* rp32;
-  const long long* rp64;
-  const int* ci_in;
+  gptr<const int> rp32;
+  gptr<const long long> rp64;
+  gptr<const int> ci_in;
   long long nnz_in;
-  const int* user_gmap;
+  gptr<const int> user_gmap;
   // options
   int S;
   int lloyd;
   int sched;
   unsigned long long seed;
   // outputs (device; optional ones may be null)
-  int* perm;
-  int* iperm;
-  int* parent;
-  int* colcount;
-  long long* nnzL;
-  int* node_begin_out;
-  int* node_size_out;
-  int* gmap_out;
-  int* n_nodes_out;
-  unsigned* status_out;
+  gptr<int> perm;
+  gptr<int> iperm;
+  gptr<int> parent;
+  gptr<int> colcount;
+  gptr<long long> nnzL;
+  gptr<int> node_begin_out;
+  gptr<int> node_size_out;
+  gptr<int> gmap_out;
+  gptr<int> n_nodes_out;
+  gptr<unsigned> status_out;
   int max_nodes_out;
   // sizes
   int n;          // vertices
@@ -64,49 +149,49 @@ struct FpMesh {
   int lds_bytes;  // dynamic LDS of the per-node kernels
   int lds_big;    // LDS of the one-wave kernels for large nodes (>= lds_bytes)
   // workspace
-  FpCtl* ctl;
-  int* grp;       // n+1
-  int* gci;       // Ecap
-  unsigned long long* key;  // n
-  unsigned long long* best; // n
-  int* fa;        // n
-  int* fcnt;      // n+16: frontier size of every BFS level
-  int* fb;        // n
-  int* gmap;      // n
-  int* seeds;     // n
-  int* pcnt;      // n+1
-  int* pptr;      // n+1
-  int* pvtx;      // n
-  int* bnd;       // n
-  int* qptr;      // n+1
-  int* qci;       // Ecap
-  int* qcnt;      // Ecap
-  int* wp;        // n
-  int* pnode;     // n
-  int* plist;     // n
-  int* ploc;      // n
-  int* node_of;   // n
-  int* cand;      // n
-  int* bs[10];    // bisection scratch, 2n+2 each
-  int* nsize;     // NNcap
-  int* nbegin;    // NNcap
-  int* ncur;      // NNcap
-  int* segS;      // NNcap
-  int* segN;      // NNcap
-  int* cntL;      // NNcap
-  int* cntR;      // NNcap
-  int* sbuf;      // NNcap
-  int* eoff;      // 3*NNcap: element records: start, ints, records
-  int* tasks;     // 8*NNcap
-  int* gbuf;      // n
-  int* lidx;      // n
-  int* vperm;     // n
-  int* viperm;    // n
-  int* vpar;      // n
-  int* vcc;       // n
-  int* arena[2];  // element arenas, acap each
+  gptr<FpCtl> ctl;
+  gptr<int> grp;       // n+1
+  gptr<int> gci;       // Ecap
+  gptr<unsigned long long> key;  // n
+  gptr<unsigned long long> best; // n
+  gptr<int> fa;        // n
+  gptr<int> fcnt;      // n+16: frontier size of every BFS level
+  gptr<int> fb;        // n
+  gptr<int> gmap;      // n
+  gptr<int> seeds;     // n
+  gptr<int> pcnt;      // n+1
+  gptr<int> pptr;      // n+1
+  gptr<int> pvtx;      // n
+  gptr<int> bnd;       // n
+  gptr<int> qptr;      // n+1
+  gptr<int> qci;       // Ecap
+  gptr<int> qcnt;      // Ecap
+  gptr<int> wp;        // n
+  gptr<int> pnode;     // n
+  gptr<int> plist;     // n
+  gptr<int> ploc;      // n
+  gptr<int> node_of;   // n
+  gptr<int> cand;      // n
+  gptr<int> bs[10];    // bisection scratch, 2n+2 each
+  gptr<int> nsize;     // NNcap
+  gptr<int> nbegin;    // NNcap
+  gptr<int> ncur;      // NNcap
+  gptr<int> segS;      // NNcap
+  gptr<int> segN;      // NNcap
+  gptr<int> cntL;      // NNcap
+  gptr<int> cntR;      // NNcap
+  gptr<int> sbuf;      // NNcap
+  gptr<int> eoff;      // 3*NNcap: element records: start, ints, records
+  gptr<int> tasks;     // 8*NNcap
+  gptr<int> gbuf;      // n
+  gptr<int> lidx;      // n
+  gptr<int> vperm;     // n
+  gptr<int> viperm;    // n
+  gptr<int> vpar;      // n
+  gptr<int> vcc;       // n
+  gptr<int> arena[2];  // element arenas, acap each
   long long acap;
-  long long* sdesc;  // NNcap: pool word offset of a node's symbolic scratch, -1 if none
-  unsigned* pool; // fallback pool (32-bit words)
+  gptr<long long> sdesc;  // NNcap: pool word offset of a node's symbolic scratch, -1 if none
+  gptr<unsigned> pool; // fallback pool (32-bit words)
   unsigned long long pool_words;
 };

@@ -8,7 +8,7 @@
 #define FP_UNSET 0xFFFFFFFFFFFFFFFFull
 
 // raise error bits; the first failing site and one value are kept
-__device__ __forceinline__ void fp_fail(FpCtl* C, unsigned bits, int site, int arg) {
+__device__ __forceinline__ void fp_fail(gptr<FpCtl> C, unsigned bits, int site, int arg) {
   atomicOr(&C->err, bits);
   if (atomicCAS(&C->site, 0, site) == 0) atomicExch(&C->site_arg, arg);
 }
@@ -32,7 +32,7 @@ __device__ __forceinline__ long long rp_at(const FpMesh& M, long long r) {
 // rows up to 512 entries; every later stage treats rows as sets, so longer
 // rows may keep duplicates.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ int gather_vertex_row(const FpMesh& M, int v, int* out, unsigned* eb) {
+__device__ __forceinline__ int gather_vertex_row(const FpMesh& M, int v, gptr<int> out, unsigned* eb) {
   const int b = M.b;
   const long long r0 = (long long)v * b;
   long long e0 = rp_at(M, r0), e1 = rp_at(M, r0 + b);

@@ -18,8 +18,8 @@ struct BisectLds {
   unsigned long long red[FP_WAVES];
 };
 
-__device__ __forceinline__ int wg_bfs(const FpMesh& M, int t, const int* pid, int src, int* lev, int* queue,
-                      int* ls, int* ecc_out, BisectLds* sh) {
+__device__ __forceinline__ int wg_bfs(const FpMesh& M, int t, gptr<const int> pid, int src, gptr<int> lev,
+                                      gptr<int> queue, gptr<int> ls, int* ecc_out, BisectLds* sh) {
   if (threadIdx.x == 0) {
     lev[src] = 0;
     queue[0] = src;
@@ -71,19 +71,19 @@ __device__ __forceinline__ unsigned long long wg_min_u64(unsigned long long x, B
 // segments back into plist (left ascending, then right ascending) and moves
 // each patch to its child in pnode.
 __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, BisectLds* sh) {
-  int* pid = M.bs[0] + s;
-  int* deg = M.bs[1] + s;
-  int* levA = M.bs[2] + s;
-  int* levB = M.bs[3] + s;
-  int* qA = M.bs[4] + s;
-  int* qB = M.bs[5] + s;
+  gptr<int> pid = M.bs[0] + s;
+  gptr<int> deg = M.bs[1] + s;
+  gptr<int> levA = M.bs[2] + s;
+  gptr<int> levB = M.bs[3] + s;
+  gptr<int> qA = M.bs[4] + s;
+  gptr<int> qB = M.bs[5] + s;
   // level starts need up to m+1 entries: node t's region is shifted by its
   // rank inside its depth, so regions of one depth stay disjoint
   const int rank_in_depth = t - ((1 << (31 - __clz(t + 1))) - 1);
-  int* lsA = M.bs[6] + s + rank_in_depth;
-  int* lsB = M.bs[7] + s + rank_in_depth;
-  int* Q = M.bs[8] + s;
-  int* flag = M.bs[9] + s;
+  gptr<int> lsA = M.bs[6] + s + rank_in_depth;
+  gptr<int> lsB = M.bs[7] + s + rank_in_depth;
+  gptr<int> Q = M.bs[8] + s;
+  gptr<int> flag = M.bs[9] + s;
   const int P = M.ctl->P;
   for (int i = threadIdx.x; i < m; i += FP_WG) {
     int p = M.plist[s + i];
@@ -129,12 +129,12 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
       const int c = (int)(wg_min_u64(best, sh) & 0xFFFFFFFFu);
       wg_bfs(M, t, pid, c, levB, qB, lsB, &eccB, sh);
       const bool accept = eccB > eccA;
-      int* clr_lev = accept ? levA : levB;
-      int* clr_q = accept ? qA : qB;
+      gptr<int> clr_lev = accept ? levA : levB;
+      gptr<int> clr_q = accept ? qA : qB;
       for (int i = threadIdx.x; i < cnt; i += FP_WG) clr_lev[clr_q[i]] = -1;
       __syncthreads();
       if (!accept) break;
-      int* tp;
+      gptr<int> tp;
       tp = levA; levA = levB; levB = tp;
       tp = qA; qA = qB; qB = tp;
       tp = lsA; lsA = lsB; lsB = tp;

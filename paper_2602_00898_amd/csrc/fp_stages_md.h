@@ -24,7 +24,7 @@
 #define FP_MD_MAXM 65535  // 16-bit local ids
 
 // device-wide bump allocation from the fallback pool (32-bit words)
-__device__ __forceinline__ unsigned* pool_alloc(const FpMesh& M, unsigned long long words) {
+__device__ __forceinline__ gptr<unsigned> pool_alloc(const FpMesh& M, unsigned long long words) {
   unsigned long long off = 0;
   if (lane_id() == 0) {
     words = (words + 63) & ~63ull;
@@ -35,7 +35,7 @@ __device__ __forceinline__ unsigned* pool_alloc(const FpMesh& M, unsigned long l
     }
   }
   off = __shfl((unsigned long long)off, 0, 64);
-  return off == ~0ull ? nullptr : M.pool + off;
+  return off == ~0ull ? gptr<unsigned>(nullptr) : M.pool + off;
 }
 
 __device__ __forceinline__ int md_words(int m) { return (m + 31) >> 5; }
@@ -138,7 +138,7 @@ __device__ __forceinline__ void md_refresh_dirty(uint32_t* key, uint32_t* gmin, 
 // waits for nothing); md_map_order then turns the positions
 // [pos0, pos0 + count) into vertex ids through vmap (local index -> vertex,
 // mlim entries) and fills viperm, all lanes at once.
-__device__ __forceinline__ void md_map_order(const FpMesh& M, const int* vmap, int mlim, int pos0,
+__device__ __forceinline__ void md_map_order(const FpMesh& M, gptr<const int> vmap, int mlim, int pos0,
                                              int count) {
   wave_fence();
   for (int s = lane_id(); s < count; s += 64) {
@@ -153,7 +153,7 @@ __device__ __forceinline__ void md_map_order(const FpMesh& M, const int* vmap, i
 // Run minimum degree steps on a BIT layout until every vertex is ordered.
 // vmap[i] = vertex id of current index i; outputs go to positions
 // pos0, pos0+1, ...
-__device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, const int* vmap, int pos0,
+__device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, gptr<const int> vmap, int pos0,
                                            int nsteps) {
   const int lane = lane_id();
   const int W = B.W;
@@ -266,7 +266,8 @@ __device__ __forceinline__ void md_sp_carve(MdSp& S, char* mem, int m, int C) {
 
 // ---------------------------------------------------------------- driver
 // sort the node's vertex ids (LDS bitonic sort over the next power of two)
-__device__ __forceinline__ void wave_sort_ids(int* a, int m, int np2) {
+template <class P>  // an LDS or a global int array
+__device__ __forceinline__ void wave_sort_ids(P a, int m, int np2) {
   for (int i = m + lane_id(); i < np2; i += 64) a[i] = 0x7FFFFFFF;
   wave_fence();
   for (int k = 2; k <= np2; k <<= 1)
@@ -287,7 +288,7 @@ __device__ __forceinline__ void wave_sort_ids(int* a, int m, int np2) {
 }
 
 // Build BIT rows for the vertices vmap[0..m) of node t straight from G.
-__device__ __forceinline__ void md_bit_build(const FpMesh& M, MdBit& B, int t, const int* vmap) {
+__device__ __forceinline__ void md_bit_build(const FpMesh& M, MdBit& B, int t, gptr<const int> vmap) {
   const int m = B.m, W = B.W;
   for (long long i = lane_id(); i < (long long)m * W; i += 64) B.rows[i] = 0u;
   for (int w = lane_id(); w < W; w += 64) {
@@ -318,8 +319,8 @@ __device__ __forceinline__ void md_bit_build(const FpMesh& M, MdBit& B, int t, c
 // new index ni[i] or -1 if ordered) into a BIT layout carved from mem and
 // finish the node there.
 __device__ __forceinline__ void md_sp_to_bit(const FpMesh& M, char* mem, int na, int m, int C,
-                                             const uint16_t* srows, const uint16_t* slen,
-                                             const int* ni, const int* vm2, int pos) {
+                                             gptr<const uint16_t> srows, gptr<const uint16_t> slen,
+                                             gptr<const int> ni, gptr<const int> vm2, int pos) {
   MdBit B;
   md_bit_carve(B, mem, na);
   for (long long i = lane_id(); i < (long long)na * B.W; i += 64) B.rows[i] = 0u;
@@ -348,7 +349,7 @@ __device__ __forceinline__ void md_sp_to_bit(const FpMesh& M, char* mem, int na,
 __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, long long slice_bytes) {
   const int m = M.nsize[t];
   const int pos0 = M.nbegin[t];
-  int* V = M.gbuf + pos0;  // becomes the sorted vertex list
+  gptr<int> V = M.gbuf + pos0;  // becomes the sorted vertex list
   if (m == 0) return;
   // the node's vertex list must hold vertices of this node only
   {
@@ -381,7 +382,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
     wave_sort_ids(a, m, np2);
     for (int i = lane_id(); i < m; i += 64) V[i] = a[i];
   } else {
-    int* a = (int*)pool_alloc(M, np2);
+    gptr<int> a = pool_alloc(M, np2).as<int>();
     if (!a) return;
     for (int i = lane_id(); i < m; i += 64) a[i] = V[i];
     wave_fence();
@@ -445,7 +446,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
   }
   int done = 0;           // vertices already ordered
   int na = m;             // vertices remaining
-  const int* vmap = V;
+  gptr<const int> vmap = V;
   if (sparse_ok) {
     while (na > 0 && na > mbit) {
       // pivot: lowest vertex of the lowest non-empty degree bucket
@@ -540,13 +541,13 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
     if (na == 0) return;
     // re-index the remaining vertices (rank order) into BIT form; stage the
     // sparse state in the pool first since the BIT layout reuses the slice
-    unsigned* st = pool_alloc(M, (unsigned long long)m * C / 2 + 2ull * m + 64);
+    gptr<unsigned> st = pool_alloc(M, (unsigned long long)m * C / 2 + 2ull * m + 64);
     if (!st) goto fail;
     {
       const long long wrows = ((long long)m * C + 1) / 2, wlen = (m + 1) / 2;
-      uint16_t* srows = (uint16_t*)st;
-      uint16_t* slen = (uint16_t*)(st + wrows);
-      int* ni = (int*)(st + wrows + wlen);
+      gptr<uint16_t> srows = st.as<uint16_t>();
+      gptr<uint16_t> slen = (st + wrows).as<uint16_t>();
+      gptr<int> ni = (st + wrows + wlen).as<int>();
       for (long long i = lane_id(); i < (long long)m * C; i += 64) srows[i] = S.rows[i];
       int run = 0;
       for (int i0 = 0; i0 < m; i0 += 64) {
@@ -558,7 +559,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         run += popc64(bal);
       }
       wave_fence();
-      int* vm2 = (int*)pool_alloc(M, na);
+      gptr<int> vm2 = pool_alloc(M, na).as<int>();
       if (!vm2) goto fail;
       for (int i = lane_id(); i < m; i += 64)
         if (ni[i] >= 0) vm2[ni[i]] = vmap[i];
@@ -568,7 +569,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         md_sp_to_bit(M, slice, na, m, C, srows, slen, ni, vm2, pos0 + done);
       } else {
         const long long bytes = md_bit_bytes(na);
-        char* mem = (char*)pool_alloc(M, (bytes + 3) / 4);
+        char* mem = (char*)(unsigned*)pool_alloc(M, (bytes + 3) / 4);
         if (!mem) goto fail;
         md_sp_to_bit(M, mem, na, m, C, srows, slen, ni, vm2, pos0 + done);
       }
@@ -577,7 +578,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
   } else {
     // too large for LDS: BIT layout in the pool
     const long long bytes = md_bit_bytes(m);
-    char* mem = (char*)pool_alloc(M, (bytes + 3) / 4);
+    char* mem = (char*)(unsigned*)pool_alloc(M, (bytes + 3) / 4);
     if (!mem) goto fail;
     MdBit B;
     md_bit_carve(B, mem, m);

@@ -23,6 +23,8 @@
 //   emit -- the rows that leave t become the parent's element records.
 #pragma once
 
+#include <type_traits>
+
 #include "fp_stages_md.h"
 
 // node scratch header (32-bit words at the start of the node's pool block)
@@ -41,23 +43,23 @@ enum {
 };
 
 struct SymView {
-  int* hdr;
-  int* bd;      // np2: sorted later positions
-  int* optr;    // m+1
-  int* oent;    // nfw: forward entries, F indices
-  int* head;    // m: first row queued on column k, -1 if none
-  int* next;    // rows: next row in the same queue
-  int* outl;    // rows: rows that leave t
-  uint32_t* rows;  // rows x stride words
+  gptr<int> hdr;
+  gptr<int> bd;      // np2: sorted later positions
+  gptr<int> optr;    // m+1
+  gptr<int> oent;    // nfw: forward entries, F indices
+  gptr<int> head;    // m: first row queued on column k, -1 if none
+  gptr<int> next;    // rows: next row in the same queue
+  gptr<int> outl;    // rows: rows that leave t
+  gptr<uint32_t> rows;  // rows x stride words
 };
 
 __device__ __forceinline__ long long sym_words(int m, int np2, int nfw, int rows, int stride) {
   return SH_WORDS + (long long)np2 + (m + 1) + nfw + m + 2ll * rows + (long long)rows * stride + 4;
 }
 
-__device__ __forceinline__ SymView sym_view(unsigned* base, int m, int np2, int nfw, int rows) {
+__device__ __forceinline__ SymView sym_view(gptr<unsigned> base, int m, int np2, int nfw, int rows) {
   SymView V;
-  int* p = (int*)base;
+  gptr<int> p = base.as<int>();
   V.hdr = p;
   p += SH_WORDS;
   V.bd = p;
@@ -72,11 +74,12 @@ __device__ __forceinline__ SymView sym_view(unsigned* base, int m, int np2, int 
   p += rows;
   V.outl = p;
   p += rows;
-  V.rows = (uint32_t*)p;
+  V.rows = p.as<uint32_t>();
   return V;
 }
 
-__device__ __forceinline__ int lower_bound_i(const int* a, int n, int x) {
+template <class P>
+__device__ __forceinline__ int lower_bound_i(P a, int n, int x) {
   int lo = 0, hi = n;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
@@ -90,7 +93,8 @@ __device__ __forceinline__ int lower_bound_i(const int* a, int n, int x) {
 
 // F index of position q (t's own range first, then the sorted list of later
 // positions); -1 if q is in neither, which the callers report
-__device__ __forceinline__ int sym_findex(int q, int b0, int e0, int m, const int* bd, int nbd) {
+template <class P>
+__device__ __forceinline__ int sym_findex(int q, int b0, int e0, int m, P bd, int nbd) {
   if (q >= b0 && q < e0) return q - b0;
   if (q < e0) return -1;
   const int i = lower_bound_i(bd, nbd, q);
@@ -111,11 +115,11 @@ __device__ __forceinline__ void sym_drop(const FpMesh& M, int t, int site) {
 
 // ---------------------------------------------------------------- prep
 __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
-  FpCtl* C = M.ctl;
+  gptr<FpCtl> C = M.ctl;
   const int m = M.nsize[t];
   const int b0 = M.nbegin[t], e0 = b0 + m;
   const int nn = C->nn;
-  const int* src = M.arena[(d + 1) & 1];
+  gptr<const int> src = M.arena[(d + 1) & 1];
   // child element records: [len, pos...] ...
   int cst[2] = {0, 0}, cin[2] = {0, 0}, crec[2] = {0, 0};
   for (int c = 0; c < 2; c++) {
@@ -209,15 +213,15 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
   const int stride = (m + cap + 31) >> 5;
   const int rows = m + nce;
   const long long words = sym_words(m, cap, nfw, rows, stride);
-  unsigned* base = pool_alloc(M, (unsigned long long)(words + BW + 96));
+  gptr<unsigned> base = pool_alloc(M, (unsigned long long)(words + BW + 96));
   if (!base) {  // pool_alloc raised the error
     sym_drop(M, t, 0);
     return;
   }
   const int np2 = cap;  // capacity of the later-position list
   const SymView V = sym_view(base, m, np2, nfw, rows);
-  uint32_t* bm = (uint32_t*)base + words;  // the bitmap
-  int* anc = (int*)(bm + BW);              // per ancestor: begin, size, bit offset
+  gptr<uint32_t> bm = base.as<uint32_t>() + words;  // the bitmap
+  gptr<int> anc = (bm + BW).as<int>();              // per ancestor: begin, size, bit offset
   if (lane_id() == 0) {
     int i = 0, off = 0;
     for (int a = t; a > 0;) {
@@ -356,7 +360,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     while (off < end) {
       const int len = src[off];
       const int r = m + e;
-      uint32_t* row = V.rows + (long long)r * stride;
+      gptr<uint32_t> row = V.rows + (long long)r * stride;
       for (int w = lane_id(); w < FW; w += 64) row[w] = 0u;
       wave_fence();
       uint32_t fmin = 0xFFFFFFFFu;
@@ -410,8 +414,8 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
 __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int* h) {
   const long long so = M.sdesc[t];
   if (so < 0 || (unsigned long long)so >= M.pool_words) return false;
-  unsigned* base = M.pool + so;
-  for (int i = 0; i < SH_WORDS; i++) h[i] = ((const int*)base)[i];
+  gptr<unsigned> base = M.pool + so;
+  for (int i = 0; i < SH_WORDS; i++) h[i] = base.as<int>()[i];
   if (h[SH_OK] != 1) return false;
   *V = sym_view(base, h[SH_M], h[SH_NP2], h[SH_NFW], h[SH_ROWS]);
   return true;
@@ -429,7 +433,8 @@ __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int
 #define FP_SYM_REGW 4  // words per lane kept in registers (rows up to 256 words)
 
 // the row of column k, word w: queued rows OR forward entries, bits > k
-__device__ __forceinline__ uint32_t sym_word(const SymView& V, const int* next, const int* oent,
+template <class NP, class OP>
+__device__ __forceinline__ uint32_t sym_word(const SymView& V, NP next, OP oent,
                                              int k, int w, int q0, int r0, int r1, int rows,
                                              int stride, bool use_prev, uint32_t prev, bool* bad) {
   uint32_t x = 0u;
@@ -457,10 +462,12 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
   const int F = m + nbd;
   int nout = h[SH_NOUT];
-  int* head = V.head;
-  int* next = V.next;
-  const int* optr = V.optr;
-  const int* oent = V.oent;
+  // queue links and forward rows: the wave's LDS slice, or global memory
+  using IP = typename std::conditional<kLds, int*, gptr<int>>::type;
+  IP head = V.head;
+  IP next = V.next;
+  IP optr = V.optr;
+  IP oent = V.oent;
   if (kLds) {
     head = lds;
     next = head + m;
@@ -479,10 +486,11 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   uint32_t prev[FP_SYM_REGW];
 #pragma unroll
   for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = 0u;
+  int my_cc = 0, my_par = -1;  // column count and parent of column k with k % 64 == lane
   for (int k = 0; k < m; k++) {
     const int r0 = optr[k], r1 = optr[k + 1];
     const int q0 = head[k];
-    uint32_t* rk = V.rows + (long long)k * stride;
+    gptr<uint32_t> rk = V.rows + (long long)k * stride;
     bool bad = false;
     uint32_t first = 0xFFFFFFFFu;
     int cnt = 0;
@@ -493,7 +501,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
         uint32_t x = 0u;
         if (w < FW) {
           x = sym_word(V, next, oent, k, w, q0, r0, r1, rows, stride, regs, prev[i], &bad);
-          rk[w] = x;
+          if (!regs) rk[w] = x;
         }
         prev[i] = x;
         cnt += popc32(x);
@@ -524,23 +532,41 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
       }
       return;
     }
-    cnt = wave_sum_i32(cnt);
-    if (lane_id() == 0) {
-      M.vcc[b0 + k] = 1 + cnt;
-      int par = -1;
-      if (first != 0xFFFFFFFFu) {
-        if ((int)first < m) {
-          par = b0 + (int)first;
-          next[k] = head[first];
-          head[first] = k;
-        } else {
-          par = V.bd[first - m];
-          V.outl[nout] = k;
-        }
+    // The row is read again only by its parent: from registers when that is
+    // the next column, else from memory (a later column, or the parent node
+    // for a row that leaves t).  Skipping the store keeps a chain of columns
+    // free of global stores, so no wait for a later load has to drain them.
+    if (regs && first != 0xFFFFFFFFu && !(first == (uint32_t)(k + 1) && (int)first < m)) {
+#pragma unroll
+      for (int i = 0; i < FP_SYM_REGW; i++) {
+        const int w = lane_id() + 64 * i;
+        if (i * 64 < FW && w < FW) rk[w] = prev[i];
       }
-      M.vpar[b0 + k] = par;
+    }
+    cnt = wave_sum_i32(cnt);
+    int par = -1;
+    if (first != 0xFFFFFFFFu) par = (int)first < m ? b0 + (int)first : V.bd[first - m];
+    if (lane_id() == 0 && first != 0xFFFFFFFFu) {
+      if ((int)first < m) {
+        next[k] = head[first];
+        head[first] = k;
+      } else {
+        V.outl[nout] = k;
+      }
     }
     if (first != 0xFFFFFFFFu && (int)first >= m) nout++;
+    // counts and parents leave in one 64-column store
+    if (lane_id() == (k & 63)) {
+      my_cc = 1 + cnt;
+      my_par = par;
+    }
+    if ((k & 63) == 63 || k == m - 1) {
+      const int c = (k & ~63) + lane_id();
+      if (c <= k) {
+        M.vcc[b0 + c] = my_cc;
+        M.vpar[b0 + c] = my_par;
+      }
+    }
     wave_fence();  // queue links and outl reach every lane of the wave
   }
   if (lane_id() == 0) V.hdr[SH_NOUT] = nout;
@@ -589,7 +615,7 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
       sym_drop(M, t, FP_SITE_SYM_LIVE);
       return;
     }
-    const uint32_t* row = V.rows + (long long)r * stride;
+    gptr<const uint32_t> row = V.rows + (long long)r * stride;
     int c = 0;
     for (int w = lane_id(); w < FW; w += 64) c += popc32(row[w]);
     total += 1 + wave_sum_i32(c);
@@ -607,12 +633,12 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
     sym_drop(M, t, 0);
     return;
   }
-  int* dst = M.arena[d & 1];
+  gptr<int> dst = M.arena[d & 1];
   const int b0 = M.nbegin[t];
   int off = base;
   bool bad = false;
   for (int i = 0; i < nout; i++) {
-    const uint32_t* row = V.rows + (long long)V.outl[i] * stride;
+    gptr<const uint32_t> row = V.rows + (long long)V.outl[i] * stride;
     int len = 0;
     for (int w0 = 0; w0 < FW; w0 += 64) {
       const int w = w0 + lane_id();
