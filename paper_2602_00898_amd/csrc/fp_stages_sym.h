@@ -431,6 +431,11 @@ __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int
 // the last column in registers: the next column is most often that column's
 // parent, and then its row needs no memory read.
 #define FP_SYM_REGW 4  // words per lane kept in registers (rows up to 256 words)
+#define FP_SYM_ENTW 4  // forward entries per lane kept for a block of 64 columns
+
+__device__ __forceinline__ int sym_sel(const int (&a)[FP_SYM_ENTW], int q) {
+  return q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
+}
 
 // the row of column k, word w: queued rows OR forward entries, bits > k
 template <class NP, class OP>
@@ -455,32 +460,15 @@ __device__ __forceinline__ uint32_t sym_word(const SymView& V, NP next, OP oent,
   return x;
 }
 
-template <bool kLds>
-__device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymView& V,
-                                             const int* h, int* lds) {
+// Rows wider than the register window (F > 64 * 32 * FP_SYM_REGW): every row
+// goes through memory.
+template <class IP>
+__device__ __forceinline__ void sym_elim_wide(const FpMesh& M, int t, const SymView& V, const int* h,
+                                              IP head, IP next, IP optr, IP oent) {
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
   const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
   const int F = m + nbd;
   int nout = h[SH_NOUT];
-  // queue links and forward rows: the wave's LDS slice, or global memory
-  using IP = typename std::conditional<kLds, int*, gptr<int>>::type;
-  IP head = V.head;
-  IP next = V.next;
-  IP optr = V.optr;
-  IP oent = V.oent;
-  if (kLds) {
-    head = lds;
-    next = head + m;
-    int* lo = next + rows;
-    int* le = lo + (m + 1);
-    for (int i = lane_id(); i < m; i += 64) head[i] = V.head[i];
-    for (int i = lane_id(); i < rows; i += 64) next[i] = V.next[i];
-    for (int i = lane_id(); i <= m; i += 64) lo[i] = V.optr[i];
-    for (int i = lane_id(); i < nfw; i += 64) le[i] = V.oent[i];
-    optr = lo;
-    oent = le;
-    wave_fence();
-  }
   const bool regs = FW <= 64 * FP_SYM_REGW;
   const int b0 = M.nbegin[t];
   uint32_t prev[FP_SYM_REGW];
@@ -570,6 +558,168 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     wave_fence();  // queue links and outl reach every lane of the wave
   }
   if (lane_id() == 0) V.hdr[SH_NOUT] = nout;
+}
+
+template <bool kLds>
+__device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymView& V,
+                                             const int* h, int* lds) {
+  const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
+  const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
+  const int F = m + nbd;
+  int nout = h[SH_NOUT];
+  // queue links and forward rows: the wave's LDS slice, or global memory
+  using IP = typename std::conditional<kLds, int*, gptr<int>>::type;
+  IP head = V.head;
+  IP next = V.next;
+  IP optr = V.optr;
+  IP oent = V.oent;
+  if (kLds) {
+    head = lds;
+    next = head + m;
+    int* lo = next + rows;
+    int* le = lo + (m + 1);
+    for (int i = lane_id(); i < m; i += 64) head[i] = V.head[i];
+    for (int i = lane_id(); i < rows; i += 64) next[i] = V.next[i];
+    for (int i = lane_id(); i <= m; i += 64) lo[i] = V.optr[i];
+    for (int i = lane_id(); i < nfw; i += 64) le[i] = V.oent[i];
+    optr = lo;
+    oent = le;
+    wave_fence();
+  }
+  if (FW > 64 * FP_SYM_REGW) {
+    sym_elim_wide(M, t, V, h, head, next, optr, oent);
+    return;
+  }
+  // Columns go in blocks of 64.  A block's queue heads, row pointers and
+  // forward entries are read once into registers (lane i holds column k0+i),
+  // and a column whose parent is the next column hands its row over in
+  // registers instead of a queue: a chain of such columns, the common case
+  // in separators, runs without any LDS or global round trip.
+  const int lane = lane_id();
+  const int b0 = M.nbegin[t];
+  uint32_t prev[FP_SYM_REGW];
+#pragma unroll
+  for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = 0u;
+  bool chain = false;          // the previous column's parent is this column
+  int my_cc = 0, my_par = -1;  // results of column k0 + lane, stored per block
+  for (int k0 = 0; k0 < m; k0 += 64) {
+    const int kn = min(64, m - k0);
+    int hreg = lane < kn ? head[k0 + lane] : -1;
+    const int oreg = lane < kn ? optr[k0 + lane] : 0;
+    const int e0 = optr[k0], e1 = optr[k0 + kn];
+    const bool ereg = e1 - e0 <= 64 * FP_SYM_ENTW;
+    int ent[FP_SYM_ENTW];
+#pragma unroll
+    for (int q = 0; q < FP_SYM_ENTW; q++) {
+      const int e = e0 + lane + 64 * q;
+      ent[q] = ereg && e < e1 ? oent[e] : 0;
+    }
+    for (int kk = 0; kk < kn; kk++) {
+      const int k = k0 + kk;
+      const int r0 = wave_bcast(oreg, kk);
+      const int r1 = kk + 1 < kn ? wave_bcast(oreg, kk + 1) : e1;
+      uint32_t x[FP_SYM_REGW];
+#pragma unroll
+      for (int i = 0; i < FP_SYM_REGW; i++) x[i] = chain ? prev[i] : 0u;
+      // rows queued on k (columns other than k-1, and rows from below)
+      bool bad = false;
+      {
+        int j = wave_bcast(hreg, kk), steps = 0;
+        while (j >= 0 && j < rows && steps < rows) {
+          const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
+#pragma unroll
+          for (int i = 0; i < FP_SYM_REGW; i++) {
+            const int w = lane + 64 * i;
+            if (i * 64 < FW && w < FW) x[i] |= rj[w];
+          }
+          j = next[j];
+          steps++;
+        }
+        bad = j >= 0;  // a queue that leaves the rows or does not end
+      }
+      // forward entries of column k
+      for (int e = r0; e < r1; e++) {
+        int f;
+        if (ereg) {
+          const int q = (e - e0) >> 6, l = (e - e0) & 63;
+          f = wave_bcast(sym_sel(ent, q), l);
+        } else {
+          f = oent[e];
+        }
+        const int fw = f >> 5;
+#pragma unroll
+        for (int i = 0; i < FP_SYM_REGW; i++)
+          if (fw == lane + 64 * i) x[i] |= 1u << (f & 31);
+      }
+      // keep entries > k; count; least entry by ballot
+      const int kw = k >> 5;
+      const uint32_t kmask = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
+      uint32_t first = 0xFFFFFFFFu;
+      int cnt = 0;
+#pragma unroll
+      for (int i = 0; i < FP_SYM_REGW; i++) {
+        if (i * 64 < FW) {
+          const int w = lane + 64 * i;
+          if (w < kw || w >= FW) x[i] = 0u;
+          if (w == kw) x[i] &= kmask;
+          cnt += popc32(x[i]);
+          const uint64_t b = ballot64(x[i] != 0u);
+          if (first == 0xFFFFFFFFu && b) {
+            const int l = __builtin_ctzll(b);
+            first = (uint32_t)((l + 64 * i) * 32 + __ffs(wave_bcast_u32(x[i], l)) - 1);
+          }
+        }
+      }
+      if (ballot64(bad) || (first != 0xFFFFFFFFu && (first <= (uint32_t)k || first >= (uint32_t)F))) {
+        if (lane == 0) {
+          fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_LIVE, t);
+          V.hdr[SH_OK] = 0;
+        }
+        return;
+      }
+      const bool to_next = first == (uint32_t)(k + 1) && (int)first < m;
+      // the row is read again by its parent only: stored unless that is the
+      // next column, which takes it from registers
+      if (first != 0xFFFFFFFFu && !to_next) {
+        const gptr<uint32_t> rk = V.rows + (long long)k * stride;
+#pragma unroll
+        for (int i = 0; i < FP_SYM_REGW; i++) {
+          const int w = lane + 64 * i;
+          if (i * 64 < FW && w < FW) rk[w] = x[i];
+        }
+      }
+      cnt = wave_sum_i32(cnt);
+      int par = -1;
+      if (first != 0xFFFFFFFFu) par = (int)first < m ? b0 + (int)first : V.bd[first - m];
+      if (first != 0xFFFFFFFFu && !to_next) {
+        if ((int)first < m) {
+          // queue k on its parent column, in LDS and in this block's registers
+          const int hf = (int)first < k0 + kn ? wave_bcast(hreg, (int)first - k0) : 0;
+          if (lane == 0) {
+            next[k] = (int)first < k0 + kn ? hf : head[first];
+            head[first] = k;
+          }
+          if (lane == (int)first - k0) hreg = k;
+        } else {
+          if (lane == 0) V.outl[nout] = k;
+          nout++;
+        }
+      }
+      chain = to_next;
+#pragma unroll
+      for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = x[i];
+      if (lane == kk) {
+        my_cc = 1 + cnt;
+        my_par = par;
+      }
+      wave_fence();  // queue links and outl reach every lane of the wave
+    }
+    if (lane < kn) {  // counts and parents leave in one store per block
+      M.vcc[b0 + k0 + lane] = my_cc;
+      M.vpar[b0 + k0 + lane] = my_par;
+    }
+  }
+  if (lane == 0) V.hdr[SH_NOUT] = nout;
 }
 
 // LDS words a node's queue links and forward rows need
