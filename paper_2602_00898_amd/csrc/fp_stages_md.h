@@ -406,7 +406,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
   {
     const long long MW = (m + 31) / 32;
     const long long fixed = md_sp_bytes(m, 0) + 16;
-    C = (int)min(64ll, (slice_bytes - fixed) / (2ll * m + 4 * MW + 4));
+    C = (int)min(63ll, (slice_bytes - fixed) / (2ll * m + 4 * MW + 4));
   }
   bool sparse_ok = C >= 6;
   MdSp S;
@@ -448,22 +448,18 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
   int na = m;             // vertices remaining
   gptr<const int> vmap = V;
   if (sparse_ok) {
+    // bucket sizes live in registers from here on: lane d counts degree d
+    int creg = lane_id() <= C ? S.cnt[lane_id()] : 0;
+    const int lane = lane_id();
     while (na > 0 && na > mbit) {
       // pivot: lowest vertex of the lowest non-empty degree bucket
-      int d = -1;
-      for (int c0 = 0; c0 <= C; c0 += 64) {
-        const int dd = c0 + lane_id();
-        const uint64_t b = ballot64(dd <= C && S.cnt[dd] > 0);
-        if (b) {
-          d = c0 + __builtin_ctzll(b);
-          break;
-        }
-      }
+      const uint64_t nz = ballot64(creg > 0);
+      const int d = nz ? __builtin_ctzll(nz) : -1;
       int p = -1;
       if (d >= 0) {
         const uint32_t* row = S.bk + (long long)d * S.MW;
         for (int w0 = 0; w0 < S.MW; w0 += 64) {
-          const int w = w0 + lane_id();
+          const int w = w0 + lane;
           const uint32_t x = w < S.MW ? row[w] : 0u;
           const uint64_t b = ballot64(x != 0u);
           if (b) {
@@ -474,66 +470,137 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         }
       }
       if (p < 0 || p >= m || S.len[p] != d) {  // never expected: stop before any wild index
-        if (lane_id() == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
+        if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
         md_map_order(M, vmap, m, pos0, done);
         goto fail;
       }
       const int kp = d;
       const uint16_t* rpv = S.rows + (long long)p * C;
-      // dry run: would any neighbour row overflow?
-      int over = 0;
-      for (int i = lane_id(); i < kp; i += 64) {
-        const int u = rpv[i];
+      if (kp <= 8) {
+        // One group of 8 lanes per neighbour u of p; a lane covers the slots
+        // q = lane % 8 + 8 s of u's row.  p's neighbours sit in registers.
+        const int rpl = lane < kp ? (int)rpv[lane] : -1;
+        int rp[8];
+#pragma unroll
+        for (int a = 0; a < 8; a++) rp[a] = wave_bcast(rpl, a);
+        const int g = lane >> 3, q0 = lane & 7;
+        int u = 0;
+#pragma unroll
+        for (int a = 0; a < 8; a++) u = g == a ? rp[a] : u;
+        const bool act = g < kp;
+        const int lu = act ? (int)S.len[u] : 0;
         const uint16_t* ru = S.rows + (long long)u * C;
-        const int lu = S.len[u];
-        int add = -1;  // p leaves the row
-        for (int a = 0; a < kp; a++) {
-          const int x = rpv[a];
-          if (x == u) continue;
-          bool f = false;
-          for (int q = 0; q < lu; q++) f |= (ru[q] == x);
-          add += !f;
-        }
-        if (lu + add > C) over = 1;
-      }
-      if (ballot64(over)) break;  // convert with p still present
-      if (lane_id() == 0) {
-        M.vperm[pos0 + done] = p;  // local index; mapped below
-        S.alive[p >> 5] &= ~(1u << (p & 31));
-        S.bk[(long long)d * S.MW + (p >> 5)] &= ~(1u << (p & 31));
-        S.cnt[d] -= 1;
-      }
-      for (int i = lane_id(); i < kp; i += 64) S.nbl[i] = rpv[i];
-      wave_fence();
-      // the neighbours become a clique; their degrees move between buckets
-      for (int i = lane_id(); i < kp; i += 64) {
-        const int u = S.nbl[i];
-        uint16_t* ru = S.rows + (long long)u * C;
-        const int d1 = S.len[u];
-        int lu = d1;
-        for (int q = 0; q < lu; q++)
-          if (ru[q] == p) {
-            ru[q] = ru[lu - 1];
-            lu--;
-            break;
+        // found bits (which neighbours of p u already has), the slot of p
+        // (+1) and the value in u's last slot, packed for one OR reduction
+        uint32_t pk = 0u;
+        for (int q = q0; q < C; q += 8) {
+          if (act && q < lu) {
+            const int x = ru[q];
+#pragma unroll
+            for (int a = 0; a < 8; a++)
+              if (a < kp && x == rp[a]) pk |= 1u << a;
+            if (x == p) pk |= (uint32_t)(q + 1) << 8;
+            if (q == lu - 1) pk |= (uint32_t)x << 16;
           }
+        }
+        pk |= (uint32_t)dpp_shr((int)pk, 0, 1);
+        pk |= (uint32_t)dpp_shr((int)pk, 0, 2);
+        pk |= (uint32_t)dpp_shr((int)pk, 0, 4);
+        const bool lead = act && q0 == 7;  // lane 8g+7 holds group g's result
+        const uint32_t missing = ((1u << kp) - 1u) & ~pk & ~(1u << g);
+        const int hole = (int)((pk >> 8) & 0xFFu) - 1;
+        const int nl = lu - 1 + __popc(missing);
+        if (ballot64(lead && hole < 0)) {  // p missing from a neighbour's row
+          if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
+          md_map_order(M, vmap, m, pos0, done);
+          goto fail;
+        }
+        if (ballot64(lead && nl > C)) break;  // convert with p still present
+        if (lane == 0) {
+          M.vperm[pos0 + done] = p;  // local index; mapped below
+          atomicAnd(&S.alive[p >> 5], ~(1u << (p & 31)));
+          atomicAnd(&S.bk[(long long)d * S.MW + (p >> 5)], ~(1u << (p & 31)));
+        }
+        if (lead) {
+          uint16_t* rw = S.rows + (long long)u * C;
+          if (hole != lu - 1) rw[hole] = (uint16_t)(pk >> 16);
+          int pos = lu - 1;
+#pragma unroll
+          for (int a = 0; a < 8; a++)
+            if ((missing >> a) & 1u) rw[pos++] = (uint16_t)rp[a];
+          S.len[u] = (uint16_t)nl;
+          if (nl != lu) {
+            const uint32_t bit = 1u << (u & 31);
+            atomicAnd(&S.bk[(long long)lu * S.MW + (u >> 5)], ~bit);
+            atomicOr(&S.bk[(long long)nl * S.MW + (u >> 5)], bit);
+          }
+        }
+        creg -= lane == d;
         for (int a = 0; a < kp; a++) {
-          const int x = S.nbl[a];
-          if (x == u) continue;
-          bool f = false;
-          for (int q = 0; q < lu; q++) f |= (ru[q] == x);
-          if (!f) ru[lu++] = (uint16_t)x;
+          const int o = wave_bcast(lu, 8 * a + 7), n2 = wave_bcast(nl, 8 * a + 7);
+          if (o != n2) creg += (lane == n2) - (lane == o);
         }
-        S.len[u] = (uint16_t)lu;
-        if (lu != d1) {
-          const uint32_t bit = 1u << (u & 31);
-          atomicAnd(&S.bk[(long long)d1 * S.MW + (u >> 5)], ~bit);
-          atomicOr(&S.bk[(long long)lu * S.MW + (u >> 5)], bit);
-          atomicSub(&S.cnt[d1], 1);
-          atomicAdd(&S.cnt[lu], 1);
+        wave_fence();
+      } else {
+        // dry run: would any neighbour row overflow?
+        int over = 0;
+        for (int i = lane; i < kp; i += 64) {
+          const int u = rpv[i];
+          const uint16_t* ru = S.rows + (long long)u * C;
+          const int lu = S.len[u];
+          int add = -1;  // p leaves the row
+          for (int a = 0; a < kp; a++) {
+            const int x = rpv[a];
+            if (x == u) continue;
+            bool f = false;
+            for (int q = 0; q < lu; q++) f |= (ru[q] == x);
+            add += !f;
+          }
+          if (lu + add > C) over = 1;
         }
+        if (ballot64(over)) break;  // convert with p still present
+        if (lane == 0) {
+          M.vperm[pos0 + done] = p;  // local index; mapped below
+          atomicAnd(&S.alive[p >> 5], ~(1u << (p & 31)));
+          atomicAnd(&S.bk[(long long)d * S.MW + (p >> 5)], ~(1u << (p & 31)));
+        }
+        for (int i = lane; i < kp; i += 64) S.nbl[i] = rpv[i];
+        wave_fence();
+        // the neighbours become a clique; their degrees move between buckets
+        int d1 = 0, d2 = 0;
+        for (int i = lane; i < kp; i += 64) {
+          const int u = S.nbl[i];
+          uint16_t* ru = S.rows + (long long)u * C;
+          d1 = S.len[u];
+          int lu = d1;
+          for (int q = 0; q < lu; q++)
+            if (ru[q] == p) {
+              ru[q] = ru[lu - 1];
+              lu--;
+              break;
+            }
+          for (int a = 0; a < kp; a++) {
+            const int x = S.nbl[a];
+            if (x == u) continue;
+            bool f = false;
+            for (int q = 0; q < lu; q++) f |= (ru[q] == x);
+            if (!f) ru[lu++] = (uint16_t)x;
+          }
+          d2 = lu;
+          S.len[u] = (uint16_t)lu;
+          if (lu != d1) {
+            const uint32_t bit = 1u << (u & 31);
+            atomicAnd(&S.bk[(long long)d1 * S.MW + (u >> 5)], ~bit);
+            atomicOr(&S.bk[(long long)lu * S.MW + (u >> 5)], bit);
+          }
+        }
+        creg -= lane == d;
+        for (int a = 0; a < kp; a++) {  // kp <= C < 64: one neighbour per lane
+          const int o = wave_bcast(d1, a), n2 = wave_bcast(d2, a);
+          if (o != n2) creg += (lane == n2) - (lane == o);
+        }
+        wave_fence();
       }
-      wave_fence();
       done++;
       na--;
     }

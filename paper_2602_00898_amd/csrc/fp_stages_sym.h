@@ -426,10 +426,9 @@ __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int
 // latency decides the time of the top tree levels.  A step builds the
 // column's row, finds its least entry (the parent, found by ballot) to queue
 // the row on, and counts its entries (one DPP reduction).  The queue links
-// and the forward rows are copied into the
-// wave's LDS slice when they fit (kLds), and every lane keeps its words of
-// the last column in registers: the next column is most often that column's
-// parent, and then its row needs no memory read.
+// are copied into the wave's LDS slice when they fit (kLds), and every lane
+// keeps its words of the last column in registers: the next column is most
+// often that column's parent, and then its row needs no memory read.
 #define FP_SYM_REGW 4  // words per lane kept in registers (rows up to 256 words)
 #define FP_SYM_ENTW 4  // forward entries per lane kept for a block of 64 columns
 
@@ -464,7 +463,7 @@ __device__ __forceinline__ uint32_t sym_word(const SymView& V, NP next, OP oent,
 // goes through memory.
 template <class IP>
 __device__ __forceinline__ void sym_elim_wide(const FpMesh& M, int t, const SymView& V, const int* h,
-                                              IP head, IP next, IP optr, IP oent) {
+                                              IP head, IP next, gptr<int> optr, gptr<int> oent) {
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
   const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
   const int F = m + nbd;
@@ -567,25 +566,21 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
   const int F = m + nbd;
   int nout = h[SH_NOUT];
-  // queue links and forward rows: the wave's LDS slice, or global memory
+  // queue links: the wave's LDS slice, or global memory; the forward rows
+  // are read from global memory once per block of 64 columns
   using IP = typename std::conditional<kLds, int*, gptr<int>>::type;
   IP head = V.head;
   IP next = V.next;
-  IP optr = V.optr;
-  IP oent = V.oent;
+  const gptr<int> optr = V.optr;
+  const gptr<int> oent = V.oent;
   if (kLds) {
     head = lds;
     next = head + m;
-    int* lo = next + rows;
-    int* le = lo + (m + 1);
     for (int i = lane_id(); i < m; i += 64) head[i] = V.head[i];
     for (int i = lane_id(); i < rows; i += 64) next[i] = V.next[i];
-    for (int i = lane_id(); i <= m; i += 64) lo[i] = V.optr[i];
-    for (int i = lane_id(); i < nfw; i += 64) le[i] = V.oent[i];
-    optr = lo;
-    oent = le;
     wave_fence();
   }
+  (void)nfw;
   if (FW > 64 * FP_SYM_REGW) {
     sym_elim_wide(M, t, V, h, head, next, optr, oent);
     return;
@@ -722,9 +717,9 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   if (lane == 0) V.hdr[SH_NOUT] = nout;
 }
 
-// LDS words a node's queue links and forward rows need
+// LDS words of a node's queue links (heads and next pointers)
 __device__ __forceinline__ long long sym_elim_lds_words(const int* h) {
-  return 2ll * h[SH_M] + 1 + h[SH_ROWS] + h[SH_NFW];
+  return (long long)h[SH_M] + h[SH_ROWS];
 }
 
 // 0: the links fit a quarter of the per-node LDS (four waves per workgroup),
