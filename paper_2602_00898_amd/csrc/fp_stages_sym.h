@@ -435,6 +435,9 @@ __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int
 __device__ __forceinline__ int sym_sel(const int (&a)[FP_SYM_ENTW], int q) {
   return q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
 }
+__device__ __forceinline__ uint32_t sym_selu(const uint32_t (&a)[FP_SYM_REGW], int q) {
+  return q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
+}
 
 // the row of column k, word w: queued rows OR forward entries, bits > k
 template <class NP, class OP>
@@ -592,9 +595,10 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   // in separators, runs without any LDS or global round trip.
   const int lane = lane_id();
   const int b0 = M.nbegin[t];
-  uint32_t prev[FP_SYM_REGW];
+  uint32_t x[FP_SYM_REGW];  // the row being built, word lane + 64 i in x[i]
 #pragma unroll
-  for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = 0u;
+  for (int i = 0; i < FP_SYM_REGW; i++) x[i] = 0u;
+  int cnt = 0;
   bool chain = false;          // the previous column's parent is this column
   int my_cc = 0, my_par = -1;  // results of column k0 + lane, stored per block
   for (int k0 = 0; k0 < m; k0 += 64) {
@@ -613,26 +617,45 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
       const int k = k0 + kk;
       const int r0 = wave_bcast(oreg, kk);
       const int r1 = kk + 1 < kn ? wave_bcast(oreg, kk + 1) : e1;
-      uint32_t x[FP_SYM_REGW];
+      // The carried row: after a chain step the previous column's row (its
+      // entries > k-1, k among them), else empty.  cnt counts its entries
+      // > k, and every bit added below is counted where it is set, so the
+      // row is never counted over again.
+      if (chain) {
+        cnt -= 1;  // k, the previous column's parent, is not an entry of k
+      } else {
 #pragma unroll
-      for (int i = 0; i < FP_SYM_REGW; i++) x[i] = chain ? prev[i] : 0u;
+        for (int i = 0; i < FP_SYM_REGW; i++) x[i] = 0u;
+        cnt = 0;
+      }
+      const int kw = k >> 5;
+      const uint32_t kmask = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
       // rows queued on k (columns other than k-1, and rows from below)
       bool bad = false;
       {
         int j = wave_bcast(hreg, kk), steps = 0;
-        while (j >= 0 && j < rows && steps < rows) {
-          const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
+        if (j >= 0) {
+          int add = 0;
+          while (j >= 0 && j < rows && steps < rows) {
+            const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
 #pragma unroll
-          for (int i = 0; i < FP_SYM_REGW; i++) {
-            const int w = lane + 64 * i;
-            if (i * 64 < FW && w < FW) x[i] |= rj[w];
+            for (int i = 0; i < FP_SYM_REGW; i++) {
+              const int w = lane + 64 * i;
+              if (i * 64 < FW && w < FW && w >= kw) {
+                uint32_t y = rj[w];
+                if (w == kw) y &= kmask;
+                add += popc32(y & ~x[i]);
+                x[i] |= y;
+              }
+            }
+            j = next[j];
+            steps++;
           }
-          j = next[j];
-          steps++;
+          bad = j >= 0;  // a queue that leaves the rows or does not end
+          cnt += wave_sum_i32(add);
         }
-        bad = j >= 0;  // a queue that leaves the rows or does not end
       }
-      // forward entries of column k
+      // forward entries of column k: a bit test in the owning lane
       for (int e = r0; e < r1; e++) {
         int f;
         if (ereg) {
@@ -641,23 +664,27 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
         } else {
           f = oent[e];
         }
-        const int fw = f >> 5;
+        if (f <= k || f >= F) {
+          bad = true;
+          break;
+        }
+        const int fw = f >> 5, owner = fw & 63, slot = fw >> 6;
+        const uint32_t bit = 1u << (f & 31);
+        if (!(wave_bcast_u32(sym_selu(x, slot), owner) & bit)) {
+          cnt++;
 #pragma unroll
-        for (int i = 0; i < FP_SYM_REGW; i++)
-          if (fw == lane + 64 * i) x[i] |= 1u << (f & 31);
+          for (int i = 0; i < FP_SYM_REGW; i++)
+            if (i == slot && lane == owner) x[i] |= bit;
+        }
       }
-      // keep entries > k; count; least entry by ballot
-      const int kw = k >> 5;
-      const uint32_t kmask = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
+      // keep entries > k; least entry by ballot
       uint32_t first = 0xFFFFFFFFu;
-      int cnt = 0;
 #pragma unroll
       for (int i = 0; i < FP_SYM_REGW; i++) {
         if (i * 64 < FW) {
           const int w = lane + 64 * i;
           if (w < kw || w >= FW) x[i] = 0u;
           if (w == kw) x[i] &= kmask;
-          cnt += popc32(x[i]);
           const uint64_t b = ballot64(x[i] != 0u);
           if (first == 0xFFFFFFFFu && b) {
             const int l = __builtin_ctzll(b);
@@ -683,7 +710,6 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
           if (i * 64 < FW && w < FW) rk[w] = x[i];
         }
       }
-      cnt = wave_sum_i32(cnt);
       int par = -1;
       if (first != 0xFFFFFFFFu) par = (int)first < m ? b0 + (int)first : V.bd[first - m];
       if (first != 0xFFFFFFFFu && !to_next) {
@@ -701,8 +727,6 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
         }
       }
       chain = to_next;
-#pragma unroll
-      for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = x[i];
       if (lane == kk) {
         my_cc = 1 + cnt;
         my_par = par;
