@@ -493,8 +493,8 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
   MESH;
   FP_LDS_DECL;
   const int nsl = 1 << c;
-  const long long sb = c == 0 ? (long long)M.lds_big : (M.lds_bytes / nsl) & ~15ll;
-  const int cnt = C->task_cnt[c];
+  const long long sb = uni(c == 0 ? M.lds_big : (M.lds_bytes / nsl) & ~15);
+  const int cnt = uni(C->task_cnt[c]);
   if (wave_id() >= nsl) return;
   char* slice = fp_lds + sb * wave_id();
   while (true) {
@@ -502,7 +502,7 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
     if (lane_id() == 0) k = atomicAdd(&C->task_pop[c], 1);
     k = wave_bcast(k, 0);
     if (k >= cnt) break;
-    md_node(M, M.tasks[c * M.NNcap + k], slice, sb);
+    md_node(M, uni(M.tasks[c * M.NNcap + k]), slice, sb);
   }
 }
 
@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ M
   if (wave_id() >= nsl) return;
   int* slice = (int*)fp_lds + (M.lds_bytes / 4 / nsl) * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  const int wv = (int)blockIdx.x * nsl + wave_id(), nw = (int)gridDim.x * nsl;
+  const int wv = uni((int)blockIdx.x * nsl + wave_id()), nw = (int)gridDim.x * nsl;
   for (int x = wv; x < cnt; x += nw) sym_elim<true>(M, lo + x, cls, slice);
 }
 // nodes too large for the whole LDS: links and rows in global memory

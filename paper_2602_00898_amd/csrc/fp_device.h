@@ -49,6 +49,21 @@ enum {
 #define FP_LDS_DECL extern __shared__ __align__(16) char fp_lds[]
 #endif
 
+// A value every lane of the wave holds alike (a node id, a size read from
+// memory at one address), moved into a scalar register.  The compiler treats
+// whatever a vector load returns as varying per lane; loops and branches on
+// such values then run under exec masks with vector counters.  Passing them
+// through readfirstlane makes them scalar, and the loops scalar too.
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ unsigned uni(unsigned x) {
+  return (unsigned)__builtin_amdgcn_readfirstlane((int)x);
+}
+__device__ __forceinline__ long long uni(long long x) {
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)x);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)((unsigned long long)x >> 32));
+  return (long long)(((unsigned long long)hi << 32) | lo);
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
@@ -209,5 +224,5 @@ __device__ __forceinline__ int64_t wg_sum_i64(int64_t x, int64_t* tmp) {
 // grid-stride helpers of the one-thread-per-item kernels
 __device__ __forceinline__ int gtid() { return (int)(blockIdx.x * blockDim.x + threadIdx.x); }
 __device__ __forceinline__ int gsize() { return (int)(gridDim.x * blockDim.x); }
-__device__ __forceinline__ int gwave() { return (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6); }
+__device__ __forceinline__ int gwave() { return uni((int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6)); }
 __device__ __forceinline__ int nwaves() { return (int)((gridDim.x * blockDim.x) >> 6); }

@@ -125,7 +125,7 @@ __device__ __forceinline__ void md_refresh_dirty(uint32_t* key, uint32_t* gmin, 
   }
   wave_fence();
   for (int j = 0; j < nd; j++) {
-    const int g = dl[G + j];
+    const int g = uni(dl[G + j]);
     const int i = g * 64 + lane_id();
     uint32_t k = i < m ? key[i] : FP_KEY_INF;
     k = wave_min_u32(k);
@@ -347,8 +347,8 @@ __device__ __forceinline__ void md_sp_to_bit(const FpMesh& M, char* mem, int na,
 }
 
 __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, long long slice_bytes) {
-  const int m = M.nsize[t];
-  const int pos0 = M.nbegin[t];
+  const int m = uni(M.nsize[t]);
+  const int pos0 = uni(M.nbegin[t]);
   gptr<int> V = M.gbuf + pos0;  // becomes the sorted vertex list
   if (m == 0) return;
   // the node's vertex list must hold vertices of this node only
@@ -469,7 +469,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
           }
         }
       }
-      if (p < 0 || p >= m || S.len[p] != d) {  // never expected: stop before any wild index
+      if (p < 0 || p >= m || uni((int)S.len[p]) != d) {  // never expected: stop before any wild index
         if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
         md_map_order(M, vmap, m, pos0, done);
         goto fail;

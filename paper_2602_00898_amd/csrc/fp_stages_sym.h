@@ -116,18 +116,18 @@ __device__ __forceinline__ void sym_drop(const FpMesh& M, int t, int site) {
 // ---------------------------------------------------------------- prep
 __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
   gptr<FpCtl> C = M.ctl;
-  const int m = M.nsize[t];
-  const int b0 = M.nbegin[t], e0 = b0 + m;
-  const int nn = C->nn;
+  const int m = uni(M.nsize[t]);
+  const int b0 = uni(M.nbegin[t]), e0 = b0 + m;
+  const int nn = uni(C->nn);
   gptr<const int> src = M.arena[(d + 1) & 1];
   // child element records: [len, pos...] ...
   int cst[2] = {0, 0}, cin[2] = {0, 0}, crec[2] = {0, 0};
   for (int c = 0; c < 2; c++) {
     const int ch = 2 * t + 1 + c;
     if (ch < nn) {
-      cst[c] = M.eoff[3 * ch];
-      cin[c] = M.eoff[3 * ch + 1];
-      crec[c] = M.eoff[3 * ch + 2];
+      cst[c] = uni(M.eoff[3 * ch]);
+      cin[c] = uni(M.eoff[3 * ch + 1]);
+      crec[c] = uni(M.eoff[3 * ch + 2]);
     }
   }
   const int nce = crec[0] + crec[1];
@@ -151,7 +151,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
       const int end = cst[c] + cin[c];
       int nrec = 0;
       while (off < end) {  // uniform: every lane walks the same records
-        const int len = src[off];
+        const int len = uni(src[off]);
         if (len < 0 || off + 1 + len > end) {
           bad = true;
           break;
@@ -198,7 +198,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
   long long B = 0;
   for (int a = t; a > 0;) {
     a = (a - 1) >> 1;
-    const int sz = M.nsize[a];
+    const int sz = uni(M.nsize[a]);
     if (sz > 0) {
       na++;
       B += sz;
@@ -262,7 +262,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     int off = cst[c];
     const int end = cst[c] + cin[c];
     while (off < end) {
-      const int len = src[off];
+      const int len = uni(src[off]);
       for (int i = lane_id(); i < len; i += 64) {
         const int q = src[off + 1 + i];
         if (q >= e0) mark(q);
@@ -358,7 +358,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     int off = cst[c];
     const int end = cst[c] + cin[c];
     while (off < end) {
-      const int len = src[off];
+      const int len = uni(src[off]);
       const int r = m + e;
       gptr<uint32_t> row = V.rows + (long long)r * stride;
       for (int w = lane_id(); w < FW; w += 64) row[w] = 0u;
@@ -412,10 +412,10 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
 
 // scratch of node t after prep, or false if it has none
 __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int* h) {
-  const long long so = M.sdesc[t];
+  const long long so = uni(M.sdesc[t]);
   if (so < 0 || (unsigned long long)so >= M.pool_words) return false;
   gptr<unsigned> base = M.pool + so;
-  for (int i = 0; i < SH_WORDS; i++) h[i] = base.as<int>()[i];
+  for (int i = 0; i < SH_WORDS; i++) h[i] = uni(base.as<int>()[i]);
   if (h[SH_OK] != 1) return false;
   *V = sym_view(base, h[SH_M], h[SH_NP2], h[SH_NFW], h[SH_ROWS]);
   return true;
@@ -605,7 +605,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     const int kn = min(64, m - k0);
     int hreg = lane < kn ? head[k0 + lane] : -1;
     const int oreg = lane < kn ? optr[k0 + lane] : 0;
-    const int e0 = optr[k0], e1 = optr[k0 + kn];
+    const int e0 = uni(optr[k0]), e1 = uni(optr[k0 + kn]);
     const bool ereg = e1 - e0 <= 64 * FP_SYM_ENTW;
     int ent[FP_SYM_ENTW];
 #pragma unroll
@@ -648,7 +648,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
                 x[i] |= y;
               }
             }
-            j = next[j];
+            j = uni(next[j]);
             steps++;
           }
           bad = j >= 0;  // a queue that leaves the rows or does not end
@@ -662,7 +662,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
           const int q = (e - e0) >> 6, l = (e - e0) & 63;
           f = wave_bcast(sym_sel(ent, q), l);
         } else {
-          f = oent[e];
+          f = uni(oent[e]);
         }
         if (f <= k || f >= F) {
           bad = true;
@@ -711,7 +711,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
         }
       }
       int par = -1;
-      if (first != 0xFFFFFFFFu) par = (int)first < m ? b0 + (int)first : V.bd[first - m];
+      if (first != 0xFFFFFFFFu) par = (int)first < m ? b0 + (int)first : uni(V.bd[first - m]);
       if (first != 0xFFFFFFFFu && !to_next) {
         if ((int)first < m) {
           // queue k on its parent column, in LDS and in this block's registers
@@ -750,8 +750,8 @@ __device__ __forceinline__ long long sym_elim_lds_words(const int* h) {
 // 1: the large one-wave slice, 2: neither (global memory)
 __device__ __forceinline__ int sym_elim_class(const FpMesh& M, const int* h) {
   const long long need = sym_elim_lds_words(h);
-  if (need <= (long long)M.lds_bytes / 4 / FP_WAVES) return 0;
-  if (need <= (long long)M.lds_big / 4) return 1;
+  if (need <= (long long)uni(M.lds_bytes) / 4 / FP_WAVES) return 0;
+  if (need <= (long long)uni(M.lds_big) / 4) return 1;
   return 2;
 }
 
@@ -779,7 +779,7 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
   }
   int total = 0;
   for (int i = 0; i < nout; i++) {
-    const int r = V.outl[i];
+    const int r = uni(V.outl[i]);
     if ((unsigned)r >= (unsigned)rows) {
       sym_drop(M, t, FP_SITE_SYM_LIVE);
       return;
@@ -803,11 +803,11 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
     return;
   }
   gptr<int> dst = M.arena[d & 1];
-  const int b0 = M.nbegin[t];
+  const int b0 = uni(M.nbegin[t]);
   int off = base;
   bool bad = false;
   for (int i = 0; i < nout; i++) {
-    gptr<const uint32_t> row = V.rows + (long long)V.outl[i] * stride;
+    gptr<const uint32_t> row = V.rows + (long long)uni(V.outl[i]) * stride;
     int len = 0;
     for (int w0 = 0; w0 < FW; w0 += 64) {
       const int w = w0 + lane_id();
