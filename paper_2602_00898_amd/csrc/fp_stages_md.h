@@ -454,7 +454,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
     while (na > 0 && na > mbit) {
       // pivot: lowest vertex of the lowest non-empty degree bucket
       const uint64_t nz = ballot64(creg > 0);
-      const int d = nz ? __builtin_ctzll(nz) : -1;
+      const int d = uni(nz ? (int)__builtin_ctzll(nz) : -1);
       int p = -1;
       if (d >= 0) {
         const uint32_t* row = S.bk + (long long)d * S.MW;
@@ -469,6 +469,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
           }
         }
       }
+      p = uni(p);
       if (p < 0 || p >= m || uni((int)S.len[p]) != d) {  // never expected: stop before any wild index
         if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
         md_map_order(M, vmap, m, pos0, done);
@@ -480,7 +481,7 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         // One group of 8 lanes per neighbour u of p; a lane covers the slots
         // q = lane % 8 + 8 s of u's row.  p's neighbours sit in registers.
         const int rpl = lane < kp ? (int)rpv[lane] : -1;
-        int rp[8];
+        int rp[8];  // p's neighbours (-1 past kp), in scalar registers
 #pragma unroll
         for (int a = 0; a < 8; a++) rp[a] = wave_bcast(rpl, a);
         const int g = lane >> 3, q0 = lane & 7;
@@ -488,20 +489,31 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
 #pragma unroll
         for (int a = 0; a < 8; a++) u = g == a ? rp[a] : u;
         const bool act = g < kp;
-        const int lu = act ? (int)S.len[u] : 0;
         const uint16_t* ru = S.rows + (long long)u * C;
+        // u's length and its slots q0 + 8 s, all loads issued at once
+        int lu = 0;
+        uint32_t xs[8];
+#pragma unroll
+        for (int s = 0; s < 8; s++) xs[s] = 0xFFFFFFFFu;
+        if (act) {
+          lu = S.len[u];
+#pragma unroll
+          for (int s = 0; s < 8; s++)
+            if (q0 + 8 * s < C) xs[s] = ru[q0 + 8 * s];
+        }
         // found bits (which neighbours of p u already has), the slot of p
         // (+1) and the value in u's last slot, packed for one OR reduction
         uint32_t pk = 0u;
-        for (int q = q0; q < C; q += 8) {
-          if (act && q < lu) {
-            const int x = ru[q];
 #pragma unroll
-            for (int a = 0; a < 8; a++)
-              if (a < kp && x == rp[a]) pk |= 1u << a;
-            if (x == p) pk |= (uint32_t)(q + 1) << 8;
-            if (q == lu - 1) pk |= (uint32_t)x << 16;
-          }
+        for (int s = 0; s < 8; s++) {
+          const int q = q0 + 8 * s;
+          const uint32_t x = xs[s];
+          uint32_t f = 0u;
+#pragma unroll
+          for (int a = 0; a < 8; a++) f |= x == (uint32_t)rp[a] ? 1u << a : 0u;
+          f |= x == (uint32_t)p ? (uint32_t)(q + 1) << 8 : 0u;
+          f |= q == lu - 1 ? x << 16 : 0u;
+          pk |= q < lu ? f : 0u;
         }
         pk |= (uint32_t)dpp_shr((int)pk, 0, 1);
         pk |= (uint32_t)dpp_shr((int)pk, 0, 2);
@@ -524,10 +536,9 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
         if (lead) {
           uint16_t* rw = S.rows + (long long)u * C;
           if (hole != lu - 1) rw[hole] = (uint16_t)(pk >> 16);
-          int pos = lu - 1;
 #pragma unroll
           for (int a = 0; a < 8; a++)
-            if ((missing >> a) & 1u) rw[pos++] = (uint16_t)rp[a];
+            if ((missing >> a) & 1u) rw[lu - 1 + __popc(missing & ((1u << a) - 1u))] = (uint16_t)rp[a];
           S.len[u] = (uint16_t)nl;
           if (nl != lu) {
             const uint32_t bit = 1u << (u & 31);
@@ -536,10 +547,12 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
           }
         }
         creg -= lane == d;
-        for (int a = 0; a < kp; a++) {
-          const int o = wave_bcast(lu, 8 * a + 7), n2 = wave_bcast(nl, 8 * a + 7);
-          if (o != n2) creg += (lane == n2) - (lane == o);
-        }
+#pragma unroll
+        for (int a = 0; a < 8; a++)
+          if (a < kp) {  // u of group a moves from bucket lu to bucket nl
+            const int o = wave_bcast(lu, 8 * a + 7), n2 = wave_bcast(nl, 8 * a + 7);
+            creg += (lane == n2) - (lane == o);
+          }
         wave_fence();
       } else {
         // dry run: would any neighbour row overflow?
