@@ -489,31 +489,18 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
 #pragma unroll
         for (int a = 0; a < 8; a++) u = g == a ? rp[a] : u;
         const bool act = g < kp;
+        const int lu = act ? (int)S.len[u] : 0;
         const uint16_t* ru = S.rows + (long long)u * C;
-        // u's length and its slots q0 + 8 s, all loads issued at once
-        int lu = 0;
-        uint32_t xs[8];
-#pragma unroll
-        for (int s = 0; s < 8; s++) xs[s] = 0xFFFFFFFFu;
-        if (act) {
-          lu = S.len[u];
-#pragma unroll
-          for (int s = 0; s < 8; s++)
-            if (q0 + 8 * s < C) xs[s] = ru[q0 + 8 * s];
-        }
         // found bits (which neighbours of p u already has), the slot of p
         // (+1) and the value in u's last slot, packed for one OR reduction
         uint32_t pk = 0u;
+        for (int q = q0; q < lu; q += 8) {
+          const int x = ru[q];
 #pragma unroll
-        for (int s = 0; s < 8; s++) {
-          const int q = q0 + 8 * s;
-          const uint32_t x = xs[s];
-          uint32_t f = 0u;
-#pragma unroll
-          for (int a = 0; a < 8; a++) f |= x == (uint32_t)rp[a] ? 1u << a : 0u;
-          f |= x == (uint32_t)p ? (uint32_t)(q + 1) << 8 : 0u;
-          f |= q == lu - 1 ? x << 16 : 0u;
-          pk |= q < lu ? f : 0u;
+          for (int a = 0; a < 8; a++)
+            if (a < kp && x == rp[a]) pk |= 1u << a;
+          if (x == p) pk |= (uint32_t)(q + 1) << 8;
+          if (q == lu - 1) pk |= (uint32_t)x << 16;
         }
         pk |= (uint32_t)dpp_shr((int)pk, 0, 1);
         pk |= (uint32_t)dpp_shr((int)pk, 0, 2);
