@@ -480,11 +480,11 @@ __global__ void k_scatter(const FpMesh* __restrict__ Mp) {
 // ==========================================================================
 // local orders (Sec. 4.3 Step 4): one wave per node, LDS slice per wave
 // ==========================================================================
-__global__ void k_md_tasks(const FpMesh* __restrict__ Mp, int nn) {
+__global__ void k_md_tasks(const FpMesh* __restrict__ Mp, int nn, int ntop) {
   MESH;
   for (int x = gtid(); x < nn; x += gsize()) {
     const int m = M.nsize[x];
-    if (m == 0) continue;
+    if (m == 0 || (x < ntop && C->tearly[x])) continue;  // top separators ordered already
     const int c = md_class(m, M.lds_bytes);
     M.tasks[c * M.NNcap + atomicAdd(&C->task_cnt[c], 1)] = x;
   }
@@ -504,6 +504,81 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
     if (k >= cnt) break;
     md_node(M, uni(M.tasks[c * M.NNcap + k]), slice, sb);
   }
+}
+
+// The top separators (depth < FP_TOP_LEVELS) are final as soon as their tree
+// level is marked, and their level-order ranges follow from the sizes of the
+// top levels alone: depth d fills the positions just before all shallower
+// nodes, in heap order.  Their local orders, the longest serial chains of
+// the stage, then run on a second stream while the rest of the tree and the
+// grouping proceed.
+__global__ void k_top_count(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  const int lo = (1 << d) - 1, hi = (2 << d) - 1;
+  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+    const int v = v0 + lane_id();
+    const int t = v < M.n ? M.node_of[v] : -1;
+    const bool act = t >= lo && t < hi;
+    (void)wave_append_keyed(&C->tcnt[0], act ? t : 0, act);
+  }
+}
+__global__ void k_top_place(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  if (gtid() != 0) return;
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  // A node that held a single patch at its level is a leaf: it gets that
+  // patch's unmarked vertices only after the tree is done, and it also
+  // shifts the ranges of all deeper levels.  Early orders stop there.
+  for (int i = 0; i < cnt; i++)
+    if (M.segN[lo + i] == 1) C->top_stop = 1;
+  if (C->top_stop) return;
+  int tot = 0;
+  for (int i = 0; i < cnt; i++) tot += C->tcnt[lo + i];
+  const int shallow = C->top_shallow;
+  int pos = M.n - shallow - tot, off = shallow;
+  for (int i = 0; i < cnt; i++) {
+    const int t = lo + i;
+    C->tpos[t] = pos;
+    C->toff[t] = off;
+    C->tcur[t] = off;
+    C->tearly[t] = 1;
+    pos += C->tcnt[t];
+    off += C->tcnt[t];
+  }
+  C->top_shallow = shallow + tot;
+}
+__global__ void k_top_scatter(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  if (C->top_stop) return;
+  const int lo = (1 << d) - 1, hi = (2 << d) - 1;
+  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+    const int v = v0 + lane_id();
+    const int t = v < M.n ? M.node_of[v] : -1;
+    const bool act = t >= lo && t < hi;
+    const int slot = wave_append_keyed(&C->tcur[0], act ? t : 0, act);
+    if (act) M.tbuf[slot] = v;
+  }
+}
+// one wave (and the whole LDS) per depth-d node
+__global__ void __launch_bounds__(64) k_md_top(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  FP_LDS_DECL;
+  const int t = uni((1 << d) - 1 + (int)blockIdx.x);
+  if (!uni(C->tearly[t])) return;
+  const int m = uni(C->tcnt[t]), off = uni(C->toff[t]), pos0 = uni(C->tpos[t]);
+  if (off < 0 || m < 0 || (long long)off + m > M.n) {
+    if (lane_id() == 0) fp_fail(C, FP_E_INTERNAL, FP_SITE_TOP, t);
+    return;
+  }
+  md_node_list(M, t, M.tbuf + off, m, pos0, fp_lds, uni(M.lds_big));
+}
+// the schedule's ranges must be the ones the early orders took
+__global__ void k_top_check(const FpMesh* __restrict__ Mp, int ntop) {
+  MESH;
+  for (int t = gtid(); t < ntop; t += gsize())
+    if (C->tearly[t] &&
+        (M.nsize[t] != C->tcnt[t] || (M.nsize[t] > 0 && M.nbegin[t] != C->tpos[t])))
+      fp_fail(C, FP_E_INTERNAL, FP_SITE_TOP, t);
 }
 
 // ==========================================================================
@@ -645,6 +720,16 @@ struct Job {
   FpCtl* ctl;
   bool hip_failed = false;
   bool timing = false;
+  bool side_open = false;  // work on the side stream not yet joined
+
+  // the call's stream waits for everything issued on the side stream
+  void join_side() {
+    if (!side_open) return;
+    side_open = false;
+    if (hipEventRecord(h->ev_join, h->side) != hipSuccess ||
+        hipStreamWaitEvent(st, h->ev_join, 0) != hipSuccess)
+      hip_failed = true;
+  }
 
   // timing of one kernel (fp_time_kernel): events around each of its launches
   bool tk(const char* name) const { return h->tk_name[0] && strcmp(h->tk_name, name) == 0; }
@@ -816,12 +901,26 @@ fp_status run_job(Job& J) {
   const int nn = (1 << (D + 1)) - 1;
   if (nn > J.hm.NNcap) return FP_ERR_SIZE;
   FPL(k_sep_init, B(std::max(n, nn)), T, 0, st, dm, P, D, nn);
+  // top separators ordered early on the side stream (level order only: there
+  // their ranges depend on the top levels alone)
+  const int TL = J.hm.sched == 0 ? std::min(FP_TOP_LEVELS, D) : 0;
+  const int ntop = (1 << TL) - 1;
   for (int d = 0; d < D; d++) {
     FPL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
     FPL(k_arcs, B(n), T, 0, st, dm);
     FPL(k_bisect, dim3(std::min(1 << d, 4 * J.h->ncu)), T, 0, st, dm, d);
     FPL(k_cand, B(n), T, 0, st, dm, d);
     FPL(k_mark, B(n), T, 0, st, dm);
+    if (d < TL) {
+      FPL(k_top_count, B(n), T, 0, st, dm, d);
+      FPL(k_top_place, dim3(1), dim3(64), 0, st, dm, d);
+      FPL(k_top_scatter, B(n), T, 0, st, dm, d);
+      if (hipEventRecord(J.h->ev_top[d], st) != hipSuccess ||
+          hipStreamWaitEvent(J.h->side, J.h->ev_top[d], 0) != hipSuccess)
+        J.hip_failed = true;
+      J.side_open = true;
+      FPL(k_md_top, dim3(1 << d), dim3(64), J.h->lds_big, J.h->side, dm, d);
+    }
     J.check();
   }
   FPL(k_leaves, B(n), T, 0, st, dm);
@@ -836,14 +935,16 @@ fp_status run_job(Job& J) {
   J.scan(J.hm.sbuf, J.hm.sbuf, nn, &C->tot);
   FPL(k_nbegin, B(nn), T, 0, st, dm, nn, D);
   FPL(k_scatter, B(n), T, 0, st, dm);
+  if (ntop) FPL(k_top_check, dim3(1), dim3(64), 0, st, dm, ntop);
   J.check();
 
   // local orders
   J.mark(5);
   FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
-  FPL(k_md_tasks, B(nn), T, 0, st, dm, nn);
+  FPL(k_md_tasks, B(nn), T, 0, st, dm, nn, ntop);
   for (int c = 0; c < 3; c++)
     FPL(k_md, dim3(2 * J.h->ncu), T, c == 0 ? J.h->lds_big : J.h->lds_bytes, st, dm, c);
+  J.join_side();
   J.check();
   // a node whose local order failed leaves its positions unset: stop here
   {
@@ -923,6 +1024,8 @@ static int big_lds(int device) {
   if (big <= FP_LDS_BYTES) return FP_LDS_BYTES;
   if (hipFuncSetAttribute((const void*)k_md, hipFuncAttributeMaxDynamicSharedMemorySize, big) !=
           hipSuccess ||
+      hipFuncSetAttribute((const void*)k_md_top, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          big) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_sym_elim, hipFuncAttributeMaxDynamicSharedMemorySize,
                           big) != hipSuccess) {
     (void)hipGetLastError();
@@ -957,6 +1060,19 @@ fp_status fp_create(fp_handle** h) {
       delete H;
       return FP_ERR_HIP;
     }
+  bool ok = hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking) == hipSuccess;
+  int ne = 0;
+  for (; ok && ne < 4; ne++)
+    ok = hipEventCreateWithFlags(ne < 3 ? &H->ev_top[ne] : &H->ev_join,
+                                 hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    for (int j = 0; j < ne - 1; j++) (void)hipEventDestroy(j < 3 ? H->ev_top[j] : H->ev_join);
+    if (H->side) (void)hipStreamDestroy(H->side);
+    for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(H->ev[i]);
+    (void)hipHostFree(H->host);
+    delete H;
+    return FP_ERR_HIP;
+  }
   *h = H;
   return FP_OK;
 }
@@ -969,6 +1085,10 @@ fp_status fp_destroy(fp_handle* h) {
     (void)fp_destroy(L.h);
   }
   h->lanes.clear();
+  (void)hipStreamSynchronize(h->side);
+  (void)hipStreamDestroy(h->side);
+  for (int i = 0; i < 3; i++) (void)hipEventDestroy(h->ev_top[i]);
+  (void)hipEventDestroy(h->ev_join);
   for (hipEvent_t e : h->tk_ev) (void)hipEventDestroy(e);
   for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);
   if (h->host) (void)hipHostFree(h->host);
@@ -1045,6 +1165,7 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
       hipStreamSynchronize(J.st) != hipSuccess)
     return FP_ERR_HIP;
   s = run_job(J);
+  J.join_side();  // a call that stopped early still leaves no work behind it
   h->timed = J.timing && s == FP_OK;
   if (s != FP_OK) {
     // leave the status word and error bits where the caller looks for them

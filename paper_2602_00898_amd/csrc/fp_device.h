@@ -8,6 +8,7 @@
 #define FP_WG 256                // threads per workgroup
 #define FP_WAVES (FP_WG / 64)    // waves per workgroup
 #define FP_LDS_BYTES (64 * 1024) // dynamic LDS of the per-node kernels
+#define FP_TOP_LEVELS 3          // tree levels whose separators are ordered early
 
 // error bits raised on the device; surfaced by fp_get_error
 #define FP_E_INDEX 0x1u       // column index out of range
@@ -38,6 +39,7 @@ enum {
   FP_SITE_SYM_ROWS = 18,    // forward-row pointers out of order
   FP_SITE_SYM_LIVE = 19,    // element slot or list index out of range
   FP_SITE_SYM_PIVOT = 20,   // parent position outside the node's index space
+  FP_SITE_TOP = 21,         // early top-separator range differs from the schedule's
 };
 
 #ifndef FP_DBGP

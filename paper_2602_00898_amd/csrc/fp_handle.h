@@ -25,6 +25,12 @@ struct fp_handle {
   int lds_bytes;
   int lds_big;
   int* host;  // pinned: scalars read back between stages, and the job copy
+  // second stream: local orders of the top separators, started while the
+  // separator tree is still being built; events order it after the call's
+  // stream and back
+  hipStream_t side;
+  hipEvent_t ev_top[3];
+  hipEvent_t ev_join;
   hipEvent_t ev[FP_NSTAGE + 1];
   bool timed;  // the last call recorded stage events
   std::mutex lanes_mu;

@@ -110,6 +110,15 @@ struct FpCtl {
   unsigned long long pool_top;  // global fallback pool bump pointer (words)
   long long nnzL;        // sum of vertex column counts
   int site;              // FP_SITE_* of the first failure raised, 0 = none
+  // top separators whose local orders start early: vertex counts, list
+  // offsets and cursors in tbuf, first positions (heap index < 8)
+  int tcnt[8];
+  int tcur[8];
+  int toff[8];
+  int tpos[8];
+  int top_shallow;       // vertices in the top levels placed so far
+  int top_stop;          // a top node kept a patch (a leaf): no early orders from its level on
+  int tearly[8];         // 1: this top node's local order runs early
   int site_arg;          // a value that failure recorded (node, count ...)
   int part[1040];        // scan partials
 };
@@ -192,6 +201,7 @@ struct FpMesh {
   gptr<int> arena[2];  // element arenas, acap each
   long long acap;
   gptr<long long> sdesc;  // NNcap: pool word offset of a node's symbolic scratch, -1 if none
+  gptr<int> tbuf;      // n: vertex lists of the top separators
   gptr<unsigned> pool; // fallback pool (32-bit words)
   unsigned long long pool_words;
 };

@@ -346,10 +346,10 @@ __device__ __forceinline__ void md_sp_to_bit(const FpMesh& M, char* mem, int na,
   md_bit_run(M, B, vm2, pos, na);
 }
 
-__device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, long long slice_bytes) {
-  const int m = uni(M.nsize[t]);
-  const int pos0 = uni(M.nbegin[t]);
-  gptr<int> V = M.gbuf + pos0;  // becomes the sorted vertex list
+// Local order of node t: its m vertices listed at V (sorted there in place)
+// take positions pos0 .. pos0+m-1.
+__device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V, int m, int pos0,
+                                             char* slice, long long slice_bytes) {
   if (m == 0) return;
   // the node's vertex list must hold vertices of this node only
   {
@@ -674,6 +674,13 @@ fail:
       run += popc64(bal);
     }
   }
+}
+
+// node t at its range in the schedule, vertices as the grouping listed them
+__device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, long long slice_bytes) {
+  const int m = uni(M.nsize[t]);
+  const int pos0 = uni(M.nbegin[t]);
+  md_node_list(M, t, M.gbuf + pos0, m, pos0, slice, slice_bytes);
 }
 
 // size class of a node: 0 = whole LDS, 1 = half, 2 = quarter of the slice
