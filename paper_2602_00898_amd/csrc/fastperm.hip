@@ -903,7 +903,7 @@ fp_status run_job(Job& J) {
   FPL(k_sep_init, B(std::max(n, nn)), T, 0, st, dm, P, D, nn);
   // top separators ordered early on the side stream (level order only: there
   // their ranges depend on the top levels alone)
-  const int TL = J.hm.sched == 0 ? std::min(FP_TOP_LEVELS, D) : 0;
+  const int TL = J.hm.sched == 0 && J.h->side_ok ? std::min(FP_TOP_LEVELS, D) : 0;
   const int ntop = (1 << TL) - 1;
   for (int d = 0; d < D; d++) {
     FPL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
@@ -1050,6 +1050,7 @@ fp_status fp_create(fp_handle** h) {
   H->ncu = std::max(1, ncu);
   H->lds_bytes = FP_LDS_BYTES;
   H->lds_big = big_lds(H->device);
+  H->side_ok = true;
   H->tk_name[0] = 0;
   H->tk_n = 0;
   H->tk_failed = false;

@@ -29,6 +29,7 @@ struct fp_handle {
   // separator tree is still being built; events order it after the call's
   // stream and back
   hipStream_t side;
+  bool side_ok;  // off for the lanes of batched and served calls: they overlap already
   hipEvent_t ev_top[3];
   hipEvent_t ev_join;
   hipEvent_t ev[FP_NSTAGE + 1];

@@ -34,6 +34,7 @@ fp_status new_lane(int device, FpLane* L) {
     fp_destroy(h);
     return FP_ERR_HIP;
   }
+  h->side_ok = false;  // lanes run side by side already
   L->h = h;
   L->st = st;
   return FP_OK;
