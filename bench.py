@@ -36,6 +36,11 @@ import statistics
 import sys
 import time
 
+# The batched and served runs keep 16 lanes (streams) busy; HIP maps streams
+# onto this many hardware queues (its default is 4, which serialises lanes).
+# Set before anything initialises HIP.
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -371,7 +376,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sample")
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
-    ap.add_argument("--lanes", type=int, default=8)
+    ap.add_argument("--lanes", type=int, default=16)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),

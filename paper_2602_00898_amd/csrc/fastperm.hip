@@ -805,6 +805,28 @@ struct Job {
   }
 };
 
+// The side stream and its events, created on first use: every stream takes
+// one of the device's hardware queues in turn, so a handle that never uses
+// it (a lane of the batched calls) should not hold one.
+bool ensure_side(fp_handle* h) {
+  if (h->side) return true;
+  hipStream_t s = nullptr;
+  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
+  int ne = 0;
+  bool ok = true;
+  for (; ok && ne < 4; ne++)
+    ok = hipEventCreateWithFlags(ne < 3 ? &h->ev_top[ne] : &h->ev_join, hipEventDisableTiming) ==
+         hipSuccess;
+  if (!ok) {
+    for (int j = 0; j < ne - 1; j++) (void)hipEventDestroy(j < 3 ? h->ev_top[j] : h->ev_join);
+    (void)hipStreamDestroy(s);
+    (void)hipGetLastError();
+    return false;
+  }
+  h->side = s;
+  return true;
+}
+
 fp_status run_job(Job& J) {
   const int n = J.hm.n;
   const FpMesh* dm = J.dm;
@@ -903,7 +925,8 @@ fp_status run_job(Job& J) {
   FPL(k_sep_init, B(std::max(n, nn)), T, 0, st, dm, P, D, nn);
   // top separators ordered early on the side stream (level order only: there
   // their ranges depend on the top levels alone)
-  const int TL = J.hm.sched == 0 && J.h->side_ok ? std::min(FP_TOP_LEVELS, D) : 0;
+  const int TL =
+      J.hm.sched == 0 && J.h->side_ok && ensure_side(J.h) ? std::min(FP_TOP_LEVELS, D) : 0;
   const int ntop = (1 << TL) - 1;
   for (int d = 0; d < D; d++) {
     FPL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
@@ -1061,22 +1084,11 @@ fp_status fp_create(fp_handle** h) {
       delete H;
       return FP_ERR_HIP;
     }
-  bool ok = hipStreamCreateWithFlags(&H->side, hipStreamNonBlocking) == hipSuccess;
-  int ne = 0;
-  for (; ok && ne < 4; ne++)
-    ok = hipEventCreateWithFlags(ne < 3 ? &H->ev_top[ne] : &H->ev_join,
-                                 hipEventDisableTiming) == hipSuccess;
-  if (!ok) {
-    for (int j = 0; j < ne - 1; j++) (void)hipEventDestroy(j < 3 ? H->ev_top[j] : H->ev_join);
-    if (H->side) (void)hipStreamDestroy(H->side);
-    for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(H->ev[i]);
-    (void)hipHostFree(H->host);
-    delete H;
-    return FP_ERR_HIP;
-  }
+  H->side = nullptr;  // created by the first call that uses it
   *h = H;
   return FP_OK;
 }
+
 
 fp_status fp_destroy(fp_handle* h) {
   if (!h) return FP_OK;
@@ -1086,10 +1098,12 @@ fp_status fp_destroy(fp_handle* h) {
     (void)fp_destroy(L.h);
   }
   h->lanes.clear();
-  (void)hipStreamSynchronize(h->side);
-  (void)hipStreamDestroy(h->side);
-  for (int i = 0; i < 3; i++) (void)hipEventDestroy(h->ev_top[i]);
-  (void)hipEventDestroy(h->ev_join);
+  if (h->side) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipStreamDestroy(h->side);
+    for (int i = 0; i < 3; i++) (void)hipEventDestroy(h->ev_top[i]);
+    (void)hipEventDestroy(h->ev_join);
+  }
   for (hipEvent_t e : h->tk_ev) (void)hipEventDestroy(e);
   for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);
   if (h->host) (void)hipHostFree(h->host);
