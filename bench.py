@@ -37,9 +37,10 @@ import sys
 import time
 
 # The batched and served runs keep 16 lanes (streams) busy; HIP maps streams
-# onto this many hardware queues (its default is 4, which serialises lanes).
-# Set before anything initialises HIP.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "16")
+# onto GPU_MAX_HW_QUEUES hardware queues (4 by default, which serialises the
+# lanes), so raise it to 16 before anything initialises HIP.
+if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
