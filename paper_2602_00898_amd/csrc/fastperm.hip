@@ -485,15 +485,15 @@ __global__ void k_md_tasks(const FpMesh* __restrict__ Mp, int nn, int ntop) {
   for (int x = gtid(); x < nn; x += gsize()) {
     const int m = M.nsize[x];
     if (m == 0 || (x < ntop && C->tearly[x])) continue;  // top separators ordered already
-    const int c = md_class(m, M.lds_bytes);
+    const int c = md_class(m, M.lds_bytes, M.lds_big);
     M.tasks[c * M.NNcap + atomicAdd(&C->task_cnt[c], 1)] = x;
   }
 }
 __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int c) {
   MESH;
   FP_LDS_DECL;
-  const int nsl = 1 << c;
-  const long long sb = uni(c == 0 ? M.lds_big : (M.lds_bytes / nsl) & ~15);
+  const int nsl = md_slice_waves(c);
+  const long long sb = uni(md_slice_bytes(c, M.lds_bytes, M.lds_big));
   const int cnt = uni(C->task_cnt[c]);
   if (wave_id() >= nsl) return;
   char* slice = fp_lds + sb * wave_id();
@@ -720,15 +720,23 @@ struct Job {
   FpCtl* ctl;
   bool hip_failed = false;
   bool timing = false;
-  bool side_open = false;  // work on the side stream not yet joined
+  bool side_open = false;   // work on the side stream not yet joined
+  bool side2_open = false;  // same for the second side stream
 
-  // the call's stream waits for everything issued on the side stream
+  // the call's stream waits for everything issued on the side streams
   void join_side() {
-    if (!side_open) return;
-    side_open = false;
-    if (hipEventRecord(h->ev_join, h->side) != hipSuccess ||
-        hipStreamWaitEvent(st, h->ev_join, 0) != hipSuccess)
-      hip_failed = true;
+    if (side_open) {
+      side_open = false;
+      if (hipEventRecord(h->ev_join, h->side) != hipSuccess ||
+          hipStreamWaitEvent(st, h->ev_join, 0) != hipSuccess)
+        hip_failed = true;
+    }
+    if (side2_open) {
+      side2_open = false;
+      if (hipEventRecord(h->ev_join2, h->side2) != hipSuccess ||
+          hipStreamWaitEvent(st, h->ev_join2, 0) != hipSuccess)
+        hip_failed = true;
+    }
   }
 
   // timing of one kernel (fp_time_kernel): events around each of its launches
@@ -810,20 +818,26 @@ struct Job {
 // it (a lane of the batched calls) should not hold one.
 bool ensure_side(fp_handle* h) {
   if (h->side) return true;
-  hipStream_t s = nullptr;
+  hipStream_t s = nullptr, s2 = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
+  if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipStreamDestroy(s);
+    return false;
+  }
+  hipEvent_t* ev[6] = {&h->ev_top[0], &h->ev_top[1], &h->ev_top[2], &h->ev_join, &h->ev_md,
+                       &h->ev_join2};
   int ne = 0;
   bool ok = true;
-  for (; ok && ne < 4; ne++)
-    ok = hipEventCreateWithFlags(ne < 3 ? &h->ev_top[ne] : &h->ev_join, hipEventDisableTiming) ==
-         hipSuccess;
+  for (; ok && ne < 6; ne++) ok = hipEventCreateWithFlags(ev[ne], hipEventDisableTiming) == hipSuccess;
   if (!ok) {
-    for (int j = 0; j < ne - 1; j++) (void)hipEventDestroy(j < 3 ? h->ev_top[j] : h->ev_join);
+    for (int j = 0; j < ne - 1; j++) (void)hipEventDestroy(*ev[j]);
     (void)hipStreamDestroy(s);
+    (void)hipStreamDestroy(s2);
     (void)hipGetLastError();
     return false;
   }
   h->side = s;
+  h->side2 = s2;
   return true;
 }
 
@@ -965,8 +979,20 @@ fp_status run_job(Job& J) {
   J.mark(5);
   FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
   FPL(k_md_tasks, B(nn), T, 0, st, dm, nn, ntop);
-  for (int c = 0; c < 3; c++)
-    FPL(k_md, dim3(2 * J.h->ncu), T, c == 0 ? J.h->lds_big : J.h->lds_bytes, st, dm, c);
+  {
+    // the two large classes on the second side stream, the two small ones
+    // here: the classes' tails overlap
+    const bool two = J.h->side_ok && ensure_side(J.h);
+    if (two) {
+      if (hipEventRecord(J.h->ev_md, st) != hipSuccess ||
+          hipStreamWaitEvent(J.h->side2, J.h->ev_md, 0) != hipSuccess)
+        J.hip_failed = true;
+      J.side2_open = true;
+    }
+    for (int c = 0; c < FP_MD_CLASSES; c++)
+      FPL(k_md, dim3(2 * J.h->ncu), T, c == 3 ? J.h->lds_bytes : J.h->lds_big,
+          two && c < 2 ? J.h->side2 : st, dm, c);
+  }
   J.join_side();
   J.check();
   // a node whose local order failed leaves its positions unset: stop here
@@ -1085,6 +1111,7 @@ fp_status fp_create(fp_handle** h) {
       return FP_ERR_HIP;
     }
   H->side = nullptr;  // created by the first call that uses it
+  H->side2 = nullptr;
   *h = H;
   return FP_OK;
 }
@@ -1100,9 +1127,13 @@ fp_status fp_destroy(fp_handle* h) {
   h->lanes.clear();
   if (h->side) {
     (void)hipStreamSynchronize(h->side);
+    (void)hipStreamSynchronize(h->side2);
     (void)hipStreamDestroy(h->side);
+    (void)hipStreamDestroy(h->side2);
     for (int i = 0; i < 3; i++) (void)hipEventDestroy(h->ev_top[i]);
     (void)hipEventDestroy(h->ev_join);
+    (void)hipEventDestroy(h->ev_md);
+    (void)hipEventDestroy(h->ev_join2);
   }
   for (hipEvent_t e : h->tk_ev) (void)hipEventDestroy(e);
   for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);

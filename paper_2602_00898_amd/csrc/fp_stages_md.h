@@ -683,10 +683,19 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
   md_node_list(M, t, M.gbuf + pos0, m, pos0, slice, slice_bytes);
 }
 
-// size class of a node: 0 = whole LDS, 1 = half, 2 = quarter of the slice
-__device__ __forceinline__ int md_class(int m, long long lds) {
-  if (m <= md_bit_max((lds / 4) & ~15ll)) return 2;
-  if (m <= md_bit_max((lds / 2) & ~15ll)) return 1;
+// Size classes of the local orders, by the LDS the dense layout needs:
+//   3: a quarter of the per-node LDS (four waves per workgroup),
+//   2: a quarter of the large LDS, 1: half of it, 0: all of it (one wave;
+//      also every node too large for the dense layout).
+// Slices sized to the node keep several waves per CU on the mid-size nodes.
+#define FP_MD_CLASSES 4
+__device__ __forceinline__ int md_slice_waves(int c) { return c == 0 ? 1 : c == 1 ? 2 : 4; }
+__device__ __forceinline__ long long md_slice_bytes(int c, long long lds, long long big) {
+  return ((c == 3 ? lds : big) / md_slice_waves(c)) & ~15ll;
+}
+__device__ __forceinline__ int md_class(int m, long long lds, long long big) {
+  for (int c = 3; c >= 1; c--)
+    if (m <= md_bit_max(md_slice_bytes(c, lds, big))) return c;
   return 0;
 }
 
