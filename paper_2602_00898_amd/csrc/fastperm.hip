@@ -731,10 +731,12 @@ struct Job {
           hipStreamWaitEvent(st, h->ev_join, 0) != hipSuccess)
         hip_failed = true;
     }
-    if (side2_open) {
+    if (side2_open) {  // both large-class streams
       side2_open = false;
       if (hipEventRecord(h->ev_join2, h->side2) != hipSuccess ||
-          hipStreamWaitEvent(st, h->ev_join2, 0) != hipSuccess)
+          hipEventRecord(h->ev_join3, h->side3) != hipSuccess ||
+          hipStreamWaitEvent(st, h->ev_join2, 0) != hipSuccess ||
+          hipStreamWaitEvent(st, h->ev_join3, 0) != hipSuccess)
         hip_failed = true;
     }
   }
@@ -818,26 +820,23 @@ struct Job {
 // it (a lane of the batched calls) should not hold one.
 bool ensure_side(fp_handle* h) {
   if (h->side) return true;
-  hipStream_t s = nullptr, s2 = nullptr;
-  if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return false;
-  if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
-    (void)hipStreamDestroy(s);
-    return false;
-  }
-  hipEvent_t* ev[6] = {&h->ev_top[0], &h->ev_top[1], &h->ev_top[2], &h->ev_join, &h->ev_md,
-                       &h->ev_join2};
+  hipStream_t s[3] = {nullptr, nullptr, nullptr};
+  int ns = 0;
+  while (ns < 3 && hipStreamCreateWithFlags(&s[ns], hipStreamNonBlocking) == hipSuccess) ns++;
+  hipEvent_t* ev[7] = {&h->ev_top[0], &h->ev_top[1], &h->ev_top[2], &h->ev_join,
+                       &h->ev_md,     &h->ev_join2,  &h->ev_join3};
   int ne = 0;
-  bool ok = true;
-  for (; ok && ne < 6; ne++) ok = hipEventCreateWithFlags(ev[ne], hipEventDisableTiming) == hipSuccess;
-  if (!ok) {
-    for (int j = 0; j < ne - 1; j++) (void)hipEventDestroy(*ev[j]);
-    (void)hipStreamDestroy(s);
-    (void)hipStreamDestroy(s2);
+  while (ns == 3 && ne < 7 && hipEventCreateWithFlags(ev[ne], hipEventDisableTiming) == hipSuccess)
+    ne++;
+  if (ns < 3 || ne < 7) {
+    for (int j = 0; j < ne; j++) (void)hipEventDestroy(*ev[j]);
+    for (int j = 0; j < ns; j++) (void)hipStreamDestroy(s[j]);
     (void)hipGetLastError();
     return false;
   }
-  h->side = s;
-  h->side2 = s2;
+  h->side = s[0];
+  h->side2 = s[1];
+  h->side3 = s[2];
   return true;
 }
 
@@ -980,18 +979,20 @@ fp_status run_job(Job& J) {
   FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
   FPL(k_md_tasks, B(nn), T, 0, st, dm, nn, ntop);
   {
-    // the two large classes on the second side stream, the two small ones
-    // here: the classes' tails overlap
+    // the two large classes on streams of their own, the two small ones
+    // here one after the other: the classes' tails overlap
     const bool two = J.h->side_ok && ensure_side(J.h);
     if (two) {
       if (hipEventRecord(J.h->ev_md, st) != hipSuccess ||
-          hipStreamWaitEvent(J.h->side2, J.h->ev_md, 0) != hipSuccess)
+          hipStreamWaitEvent(J.h->side2, J.h->ev_md, 0) != hipSuccess ||
+          hipStreamWaitEvent(J.h->side3, J.h->ev_md, 0) != hipSuccess)
         J.hip_failed = true;
       J.side2_open = true;
     }
-    for (int c = 0; c < FP_MD_CLASSES; c++)
-      FPL(k_md, dim3(2 * J.h->ncu), T, c == 3 ? J.h->lds_bytes : J.h->lds_big,
-          two && c < 2 ? J.h->side2 : st, dm, c);
+    for (int c = 0; c < FP_MD_CLASSES; c++) {
+      hipStream_t sc = !two || c >= 2 ? st : c == 0 ? J.h->side2 : J.h->side3;
+      FPL(k_md, dim3(2 * J.h->ncu), T, c == 3 ? J.h->lds_bytes : J.h->lds_big, sc, dm, c);
+    }
   }
   J.join_side();
   J.check();
@@ -1112,6 +1113,7 @@ fp_status fp_create(fp_handle** h) {
     }
   H->side = nullptr;  // created by the first call that uses it
   H->side2 = nullptr;
+  H->side3 = nullptr;
   *h = H;
   return FP_OK;
 }
@@ -1126,14 +1128,12 @@ fp_status fp_destroy(fp_handle* h) {
   }
   h->lanes.clear();
   if (h->side) {
-    (void)hipStreamSynchronize(h->side);
-    (void)hipStreamSynchronize(h->side2);
-    (void)hipStreamDestroy(h->side);
-    (void)hipStreamDestroy(h->side2);
+    for (hipStream_t s : {h->side, h->side2, h->side3}) {
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
     for (int i = 0; i < 3; i++) (void)hipEventDestroy(h->ev_top[i]);
-    (void)hipEventDestroy(h->ev_join);
-    (void)hipEventDestroy(h->ev_md);
-    (void)hipEventDestroy(h->ev_join2);
+    for (hipEvent_t e : {h->ev_join, h->ev_md, h->ev_join2, h->ev_join3}) (void)hipEventDestroy(e);
   }
   for (hipEvent_t e : h->tk_ev) (void)hipEventDestroy(e);
   for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);

@@ -29,9 +29,11 @@ struct fp_handle {
   // separator tree is still being built; events order it after the call's
   // stream and back
   hipStream_t side;
-  hipStream_t side2;  // the large size classes of the local orders
+  hipStream_t side2;  // the two large size classes of the local orders,
+  hipStream_t side3;  // one stream each
   hipEvent_t ev_md;
   hipEvent_t ev_join2;
+  hipEvent_t ev_join3;
   bool side_ok;  // off for the lanes of batched and served calls: they overlap already
   hipEvent_t ev_top[3];
   hipEvent_t ev_join;
