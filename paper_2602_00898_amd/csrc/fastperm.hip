@@ -620,6 +620,26 @@ __global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ M
   const int lo = (1 << d) - 1, cnt = 1 << d;
   for (int x = gwave(); x < cnt; x += nwaves()) sym_emit(M, lo + x, d);
 }
+// The permuted pattern by position, for the symbolic stage: row p lists the
+// positions of the neighbours of vertex vperm[p].  One pass with a thread per
+// position; the symbolic kernels then read contiguous rows instead of
+// chasing vperm -> row pointers -> columns -> viperm per entry.
+__global__ void k_prow_deg(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int p = gtid(); p < M.n; p += gsize()) {
+    const int v = M.vperm[p];
+    M.pcnt[p] = (unsigned)v < (unsigned)M.n ? M.grp[v + 1] - M.grp[v] : 0;
+  }
+}
+__global__ void k_prow_fill(const FpMesh* __restrict__ Mp) {
+  MESH;
+  for (int p = gtid(); p < M.n; p += gsize()) {
+    const int v = M.vperm[p];
+    if ((unsigned)v >= (unsigned)M.n) continue;
+    int o = M.prow[p];
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) M.pent[o++] = M.viperm[M.gci[e]];
+  }
+}
 __global__ void k_nnzl(const FpMesh* __restrict__ Mp) {
   MESH;
   long long s = 0;
@@ -1005,6 +1025,10 @@ fp_status run_job(Job& J) {
 
   // elimination tree and column counts, bottom-up over the tree levels
   J.mark(6);
+  FPL(k_prow_deg, B(n), T, 0, st, dm);
+  J.scan(J.hm.pcnt, J.hm.prow, n, &C->tot);
+  FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.prow + n, &C->tot);
+  FPL(k_prow_fill, B(n), T, 0, st, dm);
   for (int d = D; d >= 0; d--) {
     const int cnt = 1 << d;
     const dim3 G(std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * J.h->ncu)));

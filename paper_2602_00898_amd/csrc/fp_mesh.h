@@ -202,6 +202,8 @@ struct FpMesh {
   long long acap;
   gptr<long long> sdesc;  // NNcap: pool word offset of a node's symbolic scratch, -1 if none
   gptr<int> tbuf;      // n: vertex lists of the top separators
+  gptr<int> prow;      // n+1: the permuted pattern by position: row pointers
+  gptr<int> pent;      // Ecap: its entries, as positions
   gptr<unsigned> pool; // fallback pool (32-bit words)
   unsigned long long pool_words;
 };

@@ -29,7 +29,7 @@ struct Plan {
   size_t o_ctl, o_mesh, o_fcnt, o_grp, o_gci, o_key, o_best, o_fa, o_fb, o_gmap, o_seeds, o_pcnt, o_pptr, o_pvtx,
       o_bnd, o_qptr, o_qci, o_qcnt, o_wp, o_pnode, o_plist, o_ploc, o_node_of, o_cand, o_bs[10],
       o_nsize, o_nbegin, o_ncur, o_segS, o_segN, o_cntL, o_cntR, o_sbuf, o_eoff, o_tasks, o_gbuf,
-      o_lidx, o_vperm, o_viperm, o_vpar, o_vcc, o_arena[2], o_sdesc, o_tbuf, o_pool;
+      o_lidx, o_vperm, o_viperm, o_vpar, o_vcc, o_arena[2], o_sdesc, o_tbuf, o_prow, o_pent, o_pool;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -107,6 +107,8 @@ bool make_plan(long long n_dof, int b, long long nnz, int S, Plan* P) {
   P->o_arena[1] = take(4 * (size_t)P->acap);
   P->o_sdesc = take(8 * NN);
   P->o_tbuf = take(4 * N1);
+  P->o_prow = take(4 * (N1 + 1));
+  P->o_pent = take(4 * (size_t)P->Ecap);
   P->o_pool = take(4 * (size_t)P->pool_words);
   P->total = o;
   return true;
@@ -164,6 +166,8 @@ void fill_mesh(const Plan& P, char* ws, FpMesh* M) {
   M->arena[1] = (int*)(ws + P.o_arena[1]);
   M->sdesc = (long long*)(ws + P.o_sdesc);
   M->tbuf = (int*)(ws + P.o_tbuf);
+  M->prow = (int*)(ws + P.o_prow);
+  M->pent = (int*)(ws + P.o_pent);
   M->pool = (unsigned*)(ws + P.o_pool);
 }
 

@@ -174,10 +174,10 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
   // forward entries and later positions
   int nfw = 0, nanc = 0;
   for (int k = lane_id(); k < m; k += 64) {
-    const int v = M.vperm[b0 + k];
-    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-      const int q = M.viperm[M.gci[e]];
-      if (q > b0 + k) {
+    const int p = b0 + k;
+    for (int e = M.prow[p]; e < M.prow[p + 1]; e++) {
+      const int q = M.pent[e];
+      if (q > p) {
         nfw++;
         nanc += (q >= e0);
       }
@@ -271,9 +271,9 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     }
   }
   for (int k = lane_id(); k < m; k += 64) {
-    const int v = M.vperm[b0 + k];
-    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-      const int q = M.viperm[M.gci[e]];
+    const int p = b0 + k;
+    for (int e = M.prow[p]; e < M.prow[p + 1]; e++) {
+      const int q = M.pent[e];
       if (q >= e0) mark(q);
     }
   }
@@ -323,17 +323,17 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
       const int k = k0 + lane_id();
       int cnt = 0;
       if (k < m) {
-        const int v = M.vperm[b0 + k];
-        for (int e = M.grp[v]; e < M.grp[v + 1]; e++) cnt += (M.viperm[M.gci[e]] > b0 + k);
+        const int p = b0 + k;
+        for (int e = M.prow[p]; e < M.prow[p + 1]; e++) cnt += (M.pent[e] > p);
       }
       const int inc = wave_incl_scan(cnt);
       int o = run + inc - cnt;
       if (k < m) {
         V.optr[k] = o;
-        const int v = M.vperm[b0 + k];
-        for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-          const int q = M.viperm[M.gci[e]];
-          if (q > b0 + k) {
+        const int p = b0 + k;
+        for (int e = M.prow[p]; e < M.prow[p + 1]; e++) {
+          const int q = M.pent[e];
+          if (q > p) {
             const int f = sym_findex(q, b0, e0, m, V.bd, nbd);
             const bool ok = f > k && f < F;
             bad |= !ok;
