@@ -311,6 +311,48 @@ def run_batch(args, meshes):
             "identical_to_plain": bool(same)}
 
 
+# ------------------------------------------------------------------ block
+BLOCK_SIDE, BLOCK_SEED, BLOCK_B = 2048, 4, 3
+
+
+def run_block(args):
+    """2048x2048 torus expanded to dense 3x3 blocks (12.6M DOF, 264M entries,
+    int64 row pointers), ordered on the vertex graph and expanded back."""
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+    from paper_2602_00898_amd import meshgen as mg
+
+    t = time.perf_counter()
+    A = mg.grid_mesh(BLOCK_SIDE, BLOCK_SIDE, True, BLOCK_SEED)
+    B = mg.block_expand(A, BLOCK_B)
+    log(f"block pattern generated in {time.perf_counter() - t:.1f} s")
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(B.rowptr).to(dev)
+    ci = torch.from_numpy(B.colind).to(dev)
+    del B
+    h = fpm.Handle()
+
+    def step():
+        return fpm.order(rp, ci, rp.numel() - 1, patch_size=PATCH, seed=BLOCK_SEED,
+                         block_size=BLOCK_B, handle=h)
+
+    for _ in range(2):
+        out = step()
+    torch.cuda.synchronize(dev)
+    steps = max(1, min(args.steps, 5))
+    t = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize(dev)
+    ms = (time.perf_counter() - t) * 1e3 / steps
+    return {"workload": "2048x2048 torus, seeded diagonals, dense 3x3 blocks, int64 row pointers, S=512",
+            "vertices": A.n, "dof": A.n * BLOCK_B, "nnz": int(ci.numel()), "steps": steps,
+            "ms_per_ordering": round(ms, 3), "value": round(A.n / ms / 1e3, 4),
+            "dof_per_s_M": round(A.n * BLOCK_B / ms / 1e3, 4), "unit": "M vertices/s",
+            "nnzL": int(out["nnzL"].item())}
+
+
 # ------------------------------------------------------------------ serving
 def run_serve(args, reqs):
     from paper_2602_00898_amd import fastperm as fpm
@@ -378,6 +420,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--lanes", type=int, default=16)
+    ap.add_argument("--block", action="store_true",
+                    help="also time the 2048x2048 torus in 3x3 blocks (12.6M DOF)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -396,6 +440,7 @@ def main():
     g = run_plain(args, A)
     batch = None if batch_meshes is None else run_batch(args, batch_meshes)
     serving = None if serve_reqs is None else run_serve(args, serve_reqs)
+    block = run_block(args) if args.block else None
     cpu = None if args.no_cpu else run_cpu(A)
     if cpu is not None and cpu.pop("nnzL") != g["nnzL"]:
         print(f"nnz(L) differs from the oracle: {g['nnzL']} vs oracle", file=sys.stderr)
@@ -427,6 +472,7 @@ def main():
         "kernel_ms_per_ordering": {k: round(v, 3) for k, v in g["warm_kernel_ms"].items()},
         "batch": batch,
         "serving": serving,
+        "block": block,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
