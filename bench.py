@@ -56,7 +56,7 @@ PATCH = 512
 BATCH_SEED = 3
 SERVE_SEED = 5
 SERVE_RATE = 200.0
-KERNELS = ("k_sym_elim", "k_md", "k_sym_prep", "k_bfs_up", "k_bisect")
+KERNELS = ("k_bfs_level", "k_md", "k_sym_elim", "k_sym_prep", "k_bisect")
 
 
 def log(msg):
@@ -153,16 +153,15 @@ def traffic_from(fetch_csv, write_csv, mib):
     print(json.dumps(out))
 
 
-def kernel_bytes(name, n, nnz_g, launches):
+def kernel_bytes(name, n, nnz_g):
     """Algorithmic bytes of all launches of a kernel in one ordering (int32
-    arrays, 64-bit BFS keys; deg = graph entries per vertex; launches = its
-    launches per ordering)."""
+    arrays, 64-bit BFS keys; deg = graph entries per vertex)."""
     deg = nnz_g / max(n, 1)
-    if name == "k_bfs_up":
-        # every level sweeps the keys (8 B per vertex); in each of the three
-        # BFS passes (growth, Lloyd distance, regrowth) a vertex reads its row
-        # pointers, columns and neighbour keys and writes its key once
-        return launches * n * 8 + 3 * n * (8 + deg * 12 + 8)
+    if name == "k_bfs_level":
+        # three BFS passes (growth, Lloyd distance, regrowth); per vertex:
+        # frontier 4 + own key 8 + row pointers 8 + deg x (column 4 +
+        # neighbour key 8) + claim (key 8 + frontier 4)
+        return 3 * n * (4 + 8 + 8 + deg * 12 + 12)
     if name == "k_md":
         # each node's induced rows once (row pointers 8, deg x (column 4,
         # node 4, local index 4)), vertex list 4, order and inverse 8, index 4
@@ -262,8 +261,7 @@ def run_plain(args, A):
     nn = int(out["n_nodes"].item())
     D = max(0, (nn + 1).bit_length() - 2)
     nnz_g = nnz - n  # the diagonal is not a graph entry
-    lpo = kt_launch / max(args.steps, 1)  # launches per ordering
-    per_launch_bytes = kernel_bytes(dom, n, nnz_g, lpo) / max(lpo, 1e-9)
+    per_launch_bytes = kernel_bytes(dom, n, nnz_g) * args.steps / max(kt_launch, 1)
     avg_ms = kt_ms / max(kt_launch, 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     return dict(n=n, nnz=nnz, nnzL=nnzL, P=P, D=D, ms=dt * 1e3 / args.steps,

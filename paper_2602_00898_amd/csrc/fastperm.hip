@@ -129,30 +129,34 @@ __global__ void k_seed_push(const FpMesh* __restrict__ Mp, int nseeds) {
   }
   if (gtid() == 0) M.fcnt[0] = nseeds;
 }
-// One BFS level, pulled: every vertex not yet reached looks at its
-// neighbours, and if some were reached at level lvl it takes (lvl + 1, the
-// smallest of their labels).  That is the push rule (a vertex first reached
-// at level lvl + 1 takes the minimum label over its level-lvl neighbours), as
-// a coalesced sweep over the vertices with no atomic per edge.  Keys written
-// in this sweep carry level lvl + 1, so they are never mistaken for level lvl.
-__global__ void k_bfs_up(const FpMesh* __restrict__ Mp, int lvl) {
+// one frontier level: a lane per frontier vertex, its neighbours visited in
+// lock step so that the new frontier is appended with one atomic per wave
+__global__ void k_bfs_level(const FpMesh* __restrict__ Mp, int lvl) {
   MESH;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
-    const int v = v0 + lane_id();
-    bool set = false;
-    if (v < M.n && M.key[v] == FP_UNSET) {
-      uint32_t best = 0xFFFFFFFFu;
-      const int e1 = M.grp[v + 1];
-      for (int e = M.grp[v]; e < e1; e++) {
-        const unsigned long long k = M.key[M.gci[e]];
-        if ((k >> 32) == (unsigned long long)lvl) best = min(best, (uint32_t)k);
-      }
-      if (best != 0xFFFFFFFFu) {
-        M.key[v] = ((unsigned long long)(lvl + 1) << 32) | best;
-        set = true;
-      }
+  const int nf = M.fcnt[lvl];
+  gptr<const int> cur = (lvl & 1) ? M.fb : M.fa;
+  gptr<int> nxt = (lvl & 1) ? M.fa : M.fb;
+  for (int f0 = gwave() * 64; f0 < nf; f0 += nwaves() * 64) {
+    const int f = f0 + lane_id();
+    int e0 = 0, deg = 0;
+    unsigned long long kv = 0;
+    if (f < nf) {
+      const int v = cur[f];
+      kv = M.key[v] + (1ull << 32);
+      e0 = M.grp[v];
+      deg = M.grp[v + 1] - e0;
     }
-    (void)wave_append(&M.fcnt[lvl + 1], set);  // the level's size, for the stop test
+    const int dmax = (int)wave_max_u32((uint32_t)deg);
+    for (int j = 0; j < dmax; j++) {
+      bool claim = false;
+      int u = 0;
+      if (j < deg) {
+        u = M.gci[e0 + j];
+        if (M.key[u] > kv) claim = atomicMin(&M.key[u], kv) == FP_UNSET;
+      }
+      const int slot = wave_append(&M.fcnt[lvl + 1], claim);
+      if (claim) nxt[slot] = u;
+    }
   }
 }
 __global__ void k_count_unset(const FpMesh* __restrict__ Mp) {
@@ -809,15 +813,15 @@ struct Job {
     FPLM(k_scan_apply, dim3(np), dim3(FP_WG), 0, st, in, out, n, chunk, ctl->part);
     check();
   }
-  // BFS from the level-0 keys already in place; levels are launched in
-  // batches of 8, then the size of the next level is read back
+  // frontier BFS from the level-0 frontier already in place; levels are
+  // launched in batches of 8, then the next frontier size is read back
   void bfs() {
     const int n = hm.n;
-    // a BFS has fewer than n levels: levels up to n+7 write counters that stay
+    // a BFS has fewer than n levels: levels up to n+7 read counters that stay
     // zero (the counter array holds n+16 entries)
     for (int lvl = 0;; lvl += 8) {
       for (int k = 0; k < 8; k++)
-        FPLM(k_bfs_up, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, lvl + k);
+        FPLM(k_bfs_level, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, lvl + k);
       check();
       if (lvl + 8 > n || hip_failed || read1(&hm.fcnt[lvl + 8]) == 0) break;
     }
