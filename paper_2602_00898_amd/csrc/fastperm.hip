@@ -381,13 +381,15 @@ __global__ void k_arcs(const FpMesh* __restrict__ Mp) {
     }
   }
 }
-__global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ Mp, int d) {
+__global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ Mp, int d,
+                                                   int lds_bytes) {
   MESH;
   __shared__ BisectLds sh;
+  FP_LDS_DECL;
   const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
   for (int t = lo + (int)blockIdx.x; t < hi; t += (int)gridDim.x) {
     const int m = M.segN[t];
-    if (m >= 2) wg_bisect(M, t, M.segS[t], m, &sh);
+    if (m >= 2) wg_bisect(M, t, M.segS[t], m, &sh, fp_lds, lds_bytes);
   }
 }
 __global__ void k_cand(const FpMesh* __restrict__ Mp, int d) {
@@ -964,7 +966,15 @@ fp_status run_job(Job& J) {
   for (int d = 0; d < D; d++) {
     FPL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
     FPL(k_arcs, B(n), T, 0, st, dm);
-    FPL(k_bisect, dim3(std::min(1 << d, 4 * J.h->ncu)), T, 0, st, dm, d);
+    {
+      // LDS for the local quotient subgraphs: a node at depth d holds at most
+      // 2^(D-d) patches; about 8 alive arcs per patch, capped below the large
+      // LDS (the kernel's static LDS comes on top)
+      const long long cap = 1ll << (D - d);
+      const int lb =
+          (int)std::min<long long>(J.h->lds_big - 1024, (4 * (13 * cap + 1) + 255) & ~255ll);
+      FPL(k_bisect, dim3(std::min(1 << d, 4 * J.h->ncu)), T, lb, st, dm, d, lb);
+    }
     FPL(k_cand, B(n), T, 0, st, dm, d);
     FPL(k_mark, B(n), T, 0, st, dm);
     if (d < TL) {
@@ -1099,6 +1109,8 @@ static int big_lds(int device) {
   if (hipFuncSetAttribute((const void*)k_md, hipFuncAttributeMaxDynamicSharedMemorySize, big) !=
           hipSuccess ||
       hipFuncSetAttribute((const void*)k_md_top, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          big) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_bisect, hipFuncAttributeMaxDynamicSharedMemorySize,
                           big) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_sym_elim, hipFuncAttributeMaxDynamicSharedMemorySize,
                           big) != hipSuccess) {

@@ -55,6 +55,42 @@ __device__ __forceinline__ int wg_bfs(const FpMesh& M, int t, gptr<const int> pi
   return tail;
 }
 
+// The same BFS on the node's quotient subgraph held as a local CSR (lrow,
+// lcol: local indices) with its levels and queue in LDS: a level costs a few
+// LDS round trips instead of a chain of global loads per arc.
+__device__ __forceinline__ int wg_bfs_lds(const int* lrow, const int* lcol, int src, int* lev,
+                                          int* queue, gptr<int> ls, int* ecc_out, BisectLds* sh) {
+  if (threadIdx.x == 0) {
+    lev[src] = 0;
+    queue[0] = src;
+    ls[0] = 0;
+    sh->tail = 1;
+  }
+  __syncthreads();
+  int head = 0, tail = 1, L = 0;
+  while (true) {
+    for (int i = head + (int)threadIdx.x; i < tail; i += FP_WG) {
+      const int x = queue[i];
+      for (int a = lrow[x]; a < lrow[x + 1]; a++) {
+        const int y = lcol[a];
+        if (lev[y] == -1 && atomicCAS(&lev[y], -1, L + 1) == -1) queue[atomicAdd(&sh->tail, 1)] = y;
+      }
+    }
+    __syncthreads();
+    const int nt = sh->tail;
+    __syncthreads();
+    if (nt == tail) break;
+    L++;
+    if (threadIdx.x == 0) ls[L] = tail;
+    head = tail;
+    tail = nt;
+  }
+  if (threadIdx.x == 0) ls[L + 1] = tail;
+  __syncthreads();
+  *ecc_out = L;
+  return tail;
+}
+
 __device__ __forceinline__ unsigned long long wg_min_u64(unsigned long long x, BisectLds* sh) {
   x = wave_min_u64(x);
   if (lane_id() == 0) sh->red[wave_id()] = x;
@@ -70,13 +106,15 @@ __device__ __forceinline__ unsigned long long wg_min_u64(unsigned long long x, B
 // node's patches are plist[s..s+m), ascending ids.  Writes the two child
 // segments back into plist (left ascending, then right ascending) and moves
 // each patch to its child in pnode.
-__device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, BisectLds* sh) {
+//
+// When the node's local CSR, two level arrays and two queues fit in the
+// workgroup's dynamic LDS (lds, lds_bytes), the BFS sweeps run there.
+template <bool kLds, class PT>
+__device__ __forceinline__ void wg_bisect_body(const FpMesh& M, int t, int s, int m, BisectLds* sh,
+                                               PT levA, PT levB, PT qA, PT qB, const int* lrow,
+                                               const int* lcol) {
   gptr<int> pid = M.bs[0] + s;
   gptr<int> deg = M.bs[1] + s;
-  gptr<int> levA = M.bs[2] + s;
-  gptr<int> levB = M.bs[3] + s;
-  gptr<int> qA = M.bs[4] + s;
-  gptr<int> qB = M.bs[5] + s;
   // level starts need up to m+1 entries: node t's region is shifted by its
   // rank inside its depth, so regions of one depth stay disjoint
   const int rank_in_depth = t - ((1 << (31 - __clz(t + 1))) - 1);
@@ -84,28 +122,6 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
   gptr<int> lsB = M.bs[7] + s + rank_in_depth;
   gptr<int> Q = M.bs[8] + s;
   gptr<int> flag = M.bs[9] + s;
-  const int P = M.ctl->P;
-  for (int i = threadIdx.x; i < m; i += FP_WG) {
-    int p = M.plist[s + i];
-    if (p < 0 || p >= P) {  // never expected: keep every later index in range
-      fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_BISECT_PATCH, p);
-      p = 0;
-    }
-    pid[i] = p;
-    M.ploc[p] = i;
-    levA[i] = -1;
-    levB[i] = -1;
-    flag[i] = 0;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < m; i += FP_WG) {
-    const int p = pid[i];
-    int d = 0;
-    for (int a = M.qptr[p]; a < M.qptr[p + 1]; a++)
-      d += (M.qcnt[a] > 0 && M.pnode[M.qci[a]] == t);
-    deg[i] = d;
-  }
-  __syncthreads();
   int base = 0, r0 = 0;
   while (base < m) {
     // the next component starts at its lowest unseen local index
@@ -117,7 +133,8 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
       }
     r0 = (int)wg_min_u64(cand, sh);
     int eccA, eccB;
-    int cnt = wg_bfs(M, t, pid, r0, levA, qA, lsA, &eccA, sh);
+    int cnt = kLds ? wg_bfs_lds(lrow, lcol, r0, (int*)levA, (int*)qA, lsA, &eccA, sh)
+                   : wg_bfs(M, t, pid, r0, (gptr<int>)levA, (gptr<int>)qA, lsA, &eccA, sh);
     for (int round = 0; round < 8; round++) {
       // least (degree, index) on the last level
       unsigned long long best = 0xFFFFFFFFFFFFFFFFull;
@@ -127,17 +144,20 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
         best = k < best ? k : best;
       }
       const int c = (int)(wg_min_u64(best, sh) & 0xFFFFFFFFu);
-      wg_bfs(M, t, pid, c, levB, qB, lsB, &eccB, sh);
+      if (kLds)
+        wg_bfs_lds(lrow, lcol, c, (int*)levB, (int*)qB, lsB, &eccB, sh);
+      else
+        wg_bfs(M, t, pid, c, (gptr<int>)levB, (gptr<int>)qB, lsB, &eccB, sh);
       const bool accept = eccB > eccA;
-      gptr<int> clr_lev = accept ? levA : levB;
-      gptr<int> clr_q = accept ? qA : qB;
+      PT clr_lev = accept ? levA : levB;
+      PT clr_q = accept ? qA : qB;
       for (int i = threadIdx.x; i < cnt; i += FP_WG) clr_lev[clr_q[i]] = -1;
       __syncthreads();
       if (!accept) break;
-      gptr<int> tp;
+      PT tp;
       tp = levA; levA = levB; levB = tp;
       tp = qA; qA = qB; qB = tp;
-      tp = lsA; lsA = lsB; lsB = tp;
+      gptr<int> tl = lsA; lsA = lsB; lsB = tl;
       eccA = eccB;
     }
     // order by (level, index): rank inside the level by counting smaller ids
@@ -213,6 +233,76 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
     M.segN[2 * t + 2] = m - k;
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, BisectLds* sh,
+                                          char* lds, long long lds_bytes) {
+  gptr<int> pid = M.bs[0] + s;
+  gptr<int> deg = M.bs[1] + s;
+  gptr<int> levA = M.bs[2] + s;
+  gptr<int> levB = M.bs[3] + s;
+  gptr<int> qA = M.bs[4] + s;
+  gptr<int> qB = M.bs[5] + s;
+  gptr<int> flag = M.bs[9] + s;
+  const int P = M.ctl->P;
+  for (int i = threadIdx.x; i < m; i += FP_WG) {
+    int p = M.plist[s + i];
+    if (p < 0 || p >= P) {  // never expected: keep every later index in range
+      fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_BISECT_PATCH, p);
+      p = 0;
+    }
+    pid[i] = p;
+    M.ploc[p] = i;
+    levA[i] = -1;
+    levB[i] = -1;
+    flag[i] = 0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < m; i += FP_WG) {
+    const int p = pid[i];
+    int d = 0;
+    for (int a = M.qptr[p]; a < M.qptr[p + 1]; a++)
+      d += (M.qcnt[a] > 0 && M.pnode[M.qci[a]] == t);
+    deg[i] = d;
+  }
+  __syncthreads();
+  // the node's quotient subgraph as a local CSR in LDS, with two level
+  // arrays and two queues, when it fits
+  if (4ll * (5ll * m + 1) <= lds_bytes) {
+    int* lrow = (int*)lds;
+    int run = 0;
+    for (int c0 = 0; c0 < m; c0 += FP_WG) {
+      const int i = c0 + (int)threadIdx.x;
+      const int dd = i < m ? deg[i] : 0;
+      int tot;
+      const int ex = wg_excl_scan(dd, sh->tmp, &tot);
+      if (i < m) lrow[i] = run + ex;
+      run += tot;
+    }
+    if (threadIdx.x == 0) lrow[m] = run;
+    __syncthreads();
+    if (4ll * (5ll * m + 1 + run) <= lds_bytes) {
+      int* lcol = lrow + (m + 1);
+      int* lA = lcol + run;
+      int* lB = lA + m;
+      int* qa = lB + m;
+      int* qb = qa + m;
+      for (int i = threadIdx.x; i < m; i += FP_WG) {
+        const int p = pid[i];
+        int o = lrow[i];
+        for (int a = M.qptr[p]; a < M.qptr[p + 1]; a++) {
+          const int q = M.qci[a];
+          if (M.qcnt[a] > 0 && M.pnode[q] == t) lcol[o++] = M.ploc[q];
+        }
+        lA[i] = -1;
+        lB[i] = -1;
+      }
+      __syncthreads();
+      wg_bisect_body<true, int*>(M, t, s, m, sh, lA, lB, qa, qb, lrow, lcol);
+      return;
+    }
+  }
+  wg_bisect_body<false, gptr<int>>(M, t, s, m, sh, levA, levB, qA, qB, nullptr, nullptr);
 }
 
 // --------------------------------------------------------------------------
