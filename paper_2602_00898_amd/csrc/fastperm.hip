@@ -595,8 +595,11 @@ __global__ void k_sym_init(const FpMesh* __restrict__ Mp, int d) {
 }
 __global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ Mp, int d) {
   MESH;
+  FP_LDS_DECL;
+  const int lw = M.lds_bytes / 4 / FP_WAVES;
+  int* slice = (int*)fp_lds + lw * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  for (int x = gwave(); x < cnt; x += nwaves()) sym_prep(M, lo + x, d);
+  for (int x = gwave(); x < cnt; x += nwaves()) sym_prep(M, lo + x, d, slice, lw);
 }
 // Elimination of the nodes whose queue links and forward rows fit in an LDS
 // slice: cls 0 with four waves per workgroup (a quarter of the per-node LDS
@@ -1043,7 +1046,7 @@ fp_status run_job(Job& J) {
     const int cnt = 1 << d;
     const dim3 G(std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * J.h->ncu)));
     FPL(k_sym_init, dim3(1), dim3(64), 0, st, dm, d);
-    FPL(k_sym_prep, G, T, 0, st, dm, d);
+    FPL(k_sym_prep, G, T, J.h->lds_bytes, st, dm, d);
     const dim3 G1(std::max(1, std::min(cnt, 4 * J.h->ncu)));
     FPL(k_sym_elim, G, T, J.h->lds_bytes, st, dm, d, 0);
     FPL(k_sym_elim, G1, T, J.h->lds_big, st, dm, d, 1);

@@ -114,7 +114,9 @@ __device__ __forceinline__ void sym_drop(const FpMesh& M, int t, int site) {
 }
 
 // ---------------------------------------------------------------- prep
-__device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
+// lds / lwords: this wave's LDS slice, which holds the ancestor table and,
+// when it fits, the sorted later positions for the index lookups
+__device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds, int lwords) {
   gptr<FpCtl> C = M.ctl;
   const int m = uni(M.nsize[t]);
   const int b0 = uni(M.nbegin[t]), e0 = b0 + m;
@@ -221,7 +223,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
   const int np2 = cap;  // capacity of the later-position list
   const SymView V = sym_view(base, m, np2, nfw, rows);
   gptr<uint32_t> bm = base.as<uint32_t>() + words;  // the bitmap
-  gptr<int> anc = (bm + BW).as<int>();              // per ancestor: begin, size, bit offset
+  int* anc = lds;  // per ancestor: begin, size, bit offset (at most 32 ancestors)
   if (lane_id() == 0) {
     int i = 0, off = 0;
     for (int a = t; a > 0;) {
@@ -313,6 +315,12 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
     return;
   }
   wave_fence();
+  // the later positions again in LDS, for the binary searches below
+  int* lbd = lds + 96;
+  const bool bd_lds = nbd <= lwords - 96;
+  if (bd_lds)
+    for (int i = lane_id(); i < nbd; i += 64) lbd[i] = V.bd[i];
+  wave_fence();
   const int F = m + nbd;
   const int FW = (F + 31) >> 5;
   // 2. forward rows in F indices
@@ -334,7 +342,8 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
         for (int e = M.prow[p]; e < M.prow[p + 1]; e++) {
           const int q = M.pent[e];
           if (q > p) {
-            const int f = sym_findex(q, b0, e0, m, V.bd, nbd);
+            const int f = bd_lds ? sym_findex(q, b0, e0, m, (const int*)lbd, nbd)
+                                 : sym_findex(q, b0, e0, m, V.bd, nbd);
             const bool ok = f > k && f < F;
             bad |= !ok;
             V.oent[o++] = ok ? f : k + 1;
@@ -365,7 +374,9 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d) {
       wave_fence();
       uint32_t fmin = 0xFFFFFFFFu;
       for (int i = lane_id(); i < len; i += 64) {
-        const int f = sym_findex(src[off + 1 + i], b0, e0, m, V.bd, nbd);
+        const int q = src[off + 1 + i];
+        const int f = bd_lds ? sym_findex(q, b0, e0, m, (const int*)lbd, nbd)
+                             : sym_findex(q, b0, e0, m, V.bd, nbd);
         if (f < 0) {
           bad3 = true;
         } else {
