@@ -114,6 +114,39 @@ __device__ __forceinline__ void sym_drop(const FpMesh& M, int t, int site) {
 }
 
 // ---------------------------------------------------------------- prep
+// The permuted rows of a node's columns, 256 columns per step: lane l takes
+// columns k0 + l + 64 u (u < 4) and holds the first FP_PREP_ROW entries of
+// each row in registers, every load of the step issued at once (mesh rows
+// have 4 to 8 entries), so a step costs two memory round trips; entries past
+// FP_PREP_ROW are read from memory when visited.
+#define FP_PREP_ROW 8
+#define FP_PREP_COLS 4
+struct PrepRows {
+  int e0[FP_PREP_COLS], deg[FP_PREP_COLS];
+  int q[FP_PREP_COLS][FP_PREP_ROW];
+};
+__device__ __forceinline__ void prep_rows(const FpMesh& M, int b0, int m, int k0, PrepRows& r) {
+#pragma unroll
+  for (int u = 0; u < FP_PREP_COLS; u++) {
+    const int k = k0 + lane_id() + 64 * u;
+    const bool act = k < m;
+    r.e0[u] = act ? M.prow[b0 + k] : 0;
+    r.deg[u] = act ? M.prow[b0 + k + 1] - r.e0[u] : 0;
+  }
+#pragma unroll
+  for (int u = 0; u < FP_PREP_COLS; u++)
+#pragma unroll
+    for (int j = 0; j < FP_PREP_ROW; j++) r.q[u][j] = j < r.deg[u] ? M.pent[r.e0[u] + j] : 0;
+}
+// fn(q) for every entry q of the row of column k0 + lane + 64 u
+template <class Fn>
+__device__ __forceinline__ void prep_each(const FpMesh& M, const PrepRows& r, int u, Fn fn) {
+#pragma unroll
+  for (int j = 0; j < FP_PREP_ROW; j++)
+    if (j < r.deg[u]) fn(r.q[u][j]);
+  for (int j = FP_PREP_ROW; j < r.deg[u]; j++) fn((int)M.pent[r.e0[u] + j]);
+}
+
 // lds / lwords: this wave's LDS slice, which holds the ancestor table and,
 // when it fits, the sorted later positions for the index lookups
 __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds, int lwords) {
@@ -175,14 +208,18 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
   }
   // forward entries and later positions
   int nfw = 0, nanc = 0;
-  for (int k = lane_id(); k < m; k += 64) {
-    const int p = b0 + k;
-    for (int e = M.prow[p]; e < M.prow[p + 1]; e++) {
-      const int q = M.pent[e];
-      if (q > p) {
-        nfw++;
-        nanc += (q >= e0);
-      }
+  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
+    PrepRows R;
+    prep_rows(M, b0, m, k0, R);
+#pragma unroll
+    for (int u = 0; u < FP_PREP_COLS; u++) {
+      const int p = b0 + k0 + lane_id() + 64 * u;
+      prep_each(M, R, u, [&](int q) {
+        if (q > p) {
+          nfw++;
+          nanc += (q >= e0);
+        }
+      });
     }
   }
   nfw = wave_sum_i32(nfw);
@@ -272,12 +309,14 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
       off += 1 + len;
     }
   }
-  for (int k = lane_id(); k < m; k += 64) {
-    const int p = b0 + k;
-    for (int e = M.prow[p]; e < M.prow[p + 1]; e++) {
-      const int q = M.pent[e];
-      if (q >= e0) mark(q);
-    }
+  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
+    PrepRows R;
+    prep_rows(M, b0, m, k0, R);
+#pragma unroll
+    for (int u = 0; u < FP_PREP_COLS; u++)
+      prep_each(M, R, u, [&](int q) {
+        if (q >= e0) mark(q);
+      });
   }
   if (ballot64(bad1)) {
     sym_drop(M, t, FP_SITE_SYM_LOOKUP);
@@ -327,30 +366,32 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
   {
     bool bad = false;
     int run = 0;
-    for (int k0 = 0; k0 < m; k0 += 64) {
-      const int k = k0 + lane_id();
-      int cnt = 0;
-      if (k < m) {
+    for (int k1 = 0; k1 < m; k1 += 64 * FP_PREP_COLS) {
+      PrepRows R;
+      prep_rows(M, b0, m, k1, R);
+#pragma unroll
+      for (int u = 0; u < FP_PREP_COLS; u++) {
+        if (k1 + 64 * u >= m) break;
+        const int k = k1 + 64 * u + lane_id();
         const int p = b0 + k;
-        for (int e = M.prow[p]; e < M.prow[p + 1]; e++) cnt += (M.pent[e] > p);
-      }
-      const int inc = wave_incl_scan(cnt);
-      int o = run + inc - cnt;
-      if (k < m) {
-        V.optr[k] = o;
-        const int p = b0 + k;
-        for (int e = M.prow[p]; e < M.prow[p + 1]; e++) {
-          const int q = M.pent[e];
-          if (q > p) {
-            const int f = bd_lds ? sym_findex(q, b0, e0, m, (const int*)lbd, nbd)
-                                 : sym_findex(q, b0, e0, m, V.bd, nbd);
-            const bool ok = f > k && f < F;
-            bad |= !ok;
-            V.oent[o++] = ok ? f : k + 1;
-          }
+        int cnt = 0;
+        prep_each(M, R, u, [&](int q) { cnt += q > p; });
+        const int inc = wave_incl_scan(cnt);
+        int o = run + inc - cnt;
+        if (k < m) {
+          V.optr[k] = o;
+          prep_each(M, R, u, [&](int q) {
+            if (q > p) {
+              const int f = bd_lds ? sym_findex(q, b0, e0, m, (const int*)lbd, nbd)
+                                   : sym_findex(q, b0, e0, m, V.bd, nbd);
+              const bool ok = f > k && f < F;
+              bad |= !ok;
+              V.oent[o++] = ok ? f : k + 1;
+            }
+          });
         }
+        run += wave_bcast(inc, 63);
       }
-      run += wave_bcast(inc, 63);
     }
     if (lane_id() == 0) V.optr[m] = run;
     if (ballot64(bad) || run != nfw) {
