@@ -129,8 +129,10 @@ __global__ void k_seed_push(const FpMesh* __restrict__ Mp, int nseeds) {
   }
   if (gtid() == 0) M.fcnt[0] = nseeds;
 }
-// one frontier level: a lane per frontier vertex, its neighbours visited in
-// lock step so that the new frontier is appended with one atomic per wave
+// One frontier level: a lane per frontier vertex.  The loads of its first
+// FP_BFS_ROW neighbours (columns, then keys) go out together, and the wave's
+// claims are appended with one atomic.
+#define FP_BFS_ROW 8
 __global__ void k_bfs_level(const FpMesh* __restrict__ Mp, int lvl) {
   MESH;
   const int nf = M.fcnt[lvl];
@@ -146,16 +148,42 @@ __global__ void k_bfs_level(const FpMesh* __restrict__ Mp, int lvl) {
       e0 = M.grp[v];
       deg = M.grp[v + 1] - e0;
     }
+    // the first FP_BFS_ROW neighbours: columns, then keys, then claims, each
+    // round of loads issued at once; longer rows continue one by one
+    int u[FP_BFS_ROW];
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) u[j] = j < deg ? (int)M.gci[e0 + j] : -1;
+    unsigned long long ku[FP_BFS_ROW];
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) ku[j] = u[j] >= 0 ? (unsigned long long)M.key[u[j]] : 0ull;
+    unsigned claims = 0u;
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++)
+      if (u[j] >= 0 && ku[j] > kv && atomicMin(&M.key[u[j]], kv) == FP_UNSET) claims |= 1u << j;
+    // one slot range per wave for all these claims
+    const int c = __popc(claims);
+    const int inc = wave_incl_scan(c);
+    const int tot = wave_bcast(inc, 63);
+    int base = 0;
+    if (tot) {
+      if (lane_id() == 0) base = atomicAdd(&M.fcnt[lvl + 1], tot);
+      base = wave_bcast(base, 0);
+    }
+    int o = base + inc - c;
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++)
+      if ((claims >> j) & 1u) nxt[o++] = u[j];
+    // the rare longer rows: the remaining neighbours in lock step
     const int dmax = (int)wave_max_u32((uint32_t)deg);
-    for (int j = 0; j < dmax; j++) {
+    for (int j = FP_BFS_ROW; j < dmax; j++) {
       bool claim = false;
-      int u = 0;
+      int w = 0;
       if (j < deg) {
-        u = M.gci[e0 + j];
-        if (M.key[u] > kv) claim = atomicMin(&M.key[u], kv) == FP_UNSET;
+        w = M.gci[e0 + j];
+        if (M.key[w] > kv) claim = atomicMin(&M.key[w], kv) == FP_UNSET;
       }
       const int slot = wave_append(&M.fcnt[lvl + 1], claim);
-      if (claim) nxt[slot] = u;
+      if (claim) nxt[slot] = w;
     }
   }
 }
