@@ -342,26 +342,70 @@ __global__ void k_patch_scatter(const FpMesh* __restrict__ Mp) {
 }
 // distinct neighbour patches of patch p, ascending, by repeated wave-wide
 // minimum over the foreign neighbours of its members
-__global__ void k_qrow(const FpMesh* __restrict__ Mp, int P, int fill) {
+// Quotient row of patch p: the sorted distinct patches next to it.  With an
+// LDS bitmap over the patch ids (bm_words words per wave) one pass over the
+// members marks the neighbours, their loads issued a row at a time, and the
+// bitmap is read back in order; without it, one pass per neighbour.
+__global__ void k_qrow(const FpMesh* __restrict__ Mp, int P, int fill, int bm_words) {
   MESH;
+  FP_LDS_DECL;
+  uint32_t* bm = (uint32_t*)fp_lds + (long long)bm_words * wave_id();
   for (int p = gwave(); p < P; p += nwaves()) {
     const int a0 = M.pptr[p], a1 = M.pptr[p + 1];
-    int last = -1, cnt = 0;
     gptr<int> out = fill ? M.qci + M.qptr[p] : gptr<int>(nullptr);
-    while (true) {
-      uint32_t m = 0xFFFFFFFFu;
+    int cnt = 0;
+    if (bm_words) {
+      for (int w = lane_id(); w < bm_words; w += 64) bm[w] = 0u;
+      wave_fence();
       for (int i = a0 + lane_id(); i < a1; i += 64) {
         const int v = M.pvtx[i];
-        for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-          const int q = M.gmap[M.gci[e]];
-          if (q != p && q > last && (uint32_t)q < m) m = (uint32_t)q;
+        const int e0 = M.grp[v], deg = M.grp[v + 1] - e0;
+        int u[FP_BFS_ROW];
+#pragma unroll
+        for (int j = 0; j < FP_BFS_ROW; j++) u[j] = j < deg ? (int)M.gci[e0 + j] : -1;
+#pragma unroll
+        for (int j = 0; j < FP_BFS_ROW; j++) {
+          const int q = u[j] >= 0 ? (int)M.gmap[u[j]] : p;
+          if (q != p) atomicOr(&bm[q >> 5], 1u << (q & 31));
+        }
+        for (int j = FP_BFS_ROW; j < deg; j++) {
+          const int q = M.gmap[M.gci[e0 + j]];
+          if (q != p) atomicOr(&bm[q >> 5], 1u << (q & 31));
         }
       }
-      m = wave_min_u32(m);
-      if (m == 0xFFFFFFFFu) break;
-      if (out && lane_id() == 0) out[cnt] = (int)m;
-      cnt++;
-      last = (int)m;
+      wave_fence();
+      for (int w0 = 0; w0 < bm_words; w0 += 64) {
+        const int w = w0 + lane_id();
+        uint32_t x = w < bm_words ? bm[w] : 0u;
+        const int c = popc32(x);
+        const int inc = wave_incl_scan(c);
+        if (out) {
+          int o = cnt + inc - c;
+          while (x) {
+            out[o++] = w * 32 + __ffs(x) - 1;
+            x &= x - 1;
+          }
+        }
+        cnt += wave_bcast(inc, 63);
+      }
+      wave_fence();
+    } else {
+      int last = -1;
+      while (true) {
+        uint32_t m = 0xFFFFFFFFu;
+        for (int i = a0 + lane_id(); i < a1; i += 64) {
+          const int v = M.pvtx[i];
+          for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+            const int q = M.gmap[M.gci[e]];
+            if (q != p && q > last && (uint32_t)q < m) m = (uint32_t)q;
+          }
+        }
+        m = wave_min_u32(m);
+        if (m == 0xFFFFFFFFu) break;
+        if (out && lane_id() == 0) out[cnt] = (int)m;
+        cnt++;
+        last = (int)m;
+      }
     }
     if (!fill && lane_id() == 0) M.pcnt[p] = cnt;
   }
@@ -399,12 +443,28 @@ __global__ void k_arcs(const FpMesh* __restrict__ Mp) {
     const int v = M.bnd[i];
     if (M.node_of[v] != -1) continue;
     const int gv = M.gmap[v];
-    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
-      const int u = M.gci[e];
-      if (M.node_of[u] != -1) continue;
-      const int gu = M.gmap[u];
-      if (gu == gv) continue;
-      const int a = arc_index(M, gv, gu);
+    const int e0 = M.grp[v], deg = M.grp[v + 1] - e0;
+    // the first FP_BFS_ROW neighbours' columns, marks and patches at once
+    int u[FP_BFS_ROW], nu[FP_BFS_ROW], gu[FP_BFS_ROW];
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) u[j] = j < deg ? (int)M.gci[e0 + j] : -1;
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) {
+      nu[j] = u[j] >= 0 ? (int)M.node_of[u[j]] : 0;
+      gu[j] = u[j] >= 0 ? (int)M.gmap[u[j]] : gv;
+    }
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) {
+      if (nu[j] != -1 || gu[j] == gv) continue;
+      const int a = arc_index(M, gv, gu[j]);
+      if (a >= 0) atomicAdd(&M.qcnt[a], 1);
+    }
+    for (int e = e0 + FP_BFS_ROW; e < e0 + deg; e++) {
+      const int w = M.gci[e];
+      if (M.node_of[w] != -1) continue;
+      const int gw = M.gmap[w];
+      if (gw == gv) continue;
+      const int a = arc_index(M, gv, gw);
       if (a >= 0) atomicAdd(&M.qcnt[a], 1);
     }
   }
@@ -431,10 +491,22 @@ __global__ void k_cand(const FpMesh* __restrict__ Mp, int d) {
     const int c = M.pnode[M.gmap[v]];
     if (c < hi) continue;  // patch not split at this level
     const int sib = (c & 1) ? c + 1 : c - 1;
+    const int e0 = M.grp[v], deg = M.grp[v + 1] - e0;
+    // the first FP_BFS_ROW neighbours' columns, marks and patches at once
+    int u[FP_BFS_ROW], nu[FP_BFS_ROW], gu[FP_BFS_ROW];
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) u[j] = j < deg ? (int)M.gci[e0 + j] : -1;
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) {
+      nu[j] = u[j] >= 0 ? (int)M.node_of[u[j]] : 0;
+      gu[j] = u[j] >= 0 ? (int)M.gmap[u[j]] : 0;
+    }
     bool is = false;
-    for (int e = M.grp[v]; e < M.grp[v + 1] && !is; e++) {
-      const int u = M.gci[e];
-      is = (M.node_of[u] == -1 && M.pnode[M.gmap[u]] == sib);
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) is |= nu[j] == -1 && M.pnode[gu[j]] == sib;
+    for (int e = e0 + FP_BFS_ROW; e < e0 + deg && !is; e++) {
+      const int w = M.gci[e];
+      is = (M.node_of[w] == -1 && M.pnode[M.gmap[w]] == sib);
     }
     if (is) {
       M.cand[i] = 1;
@@ -972,14 +1044,16 @@ fp_status run_job(Job& J) {
   FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.pptr + P, &C->tot);
   FPL(k_copy, B(P), T, 0, st, J.hm.pcnt, J.hm.pptr, P);
   FPL(k_patch_scatter, B(n), T, 0, st, dm);
-  FPL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, 0, st, dm, P, 0);
+  // a patch-id bitmap per wave when four of them fit in 64 KB of LDS
+  const int qbw = (long long)(P + 31) / 32 * 4 * FP_WAVES <= 65536 ? (P + 31) / 32 : 0;
+  FPL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, qbw * 4 * FP_WAVES, st, dm, P, 0, qbw);
   J.check();
   J.scan(J.hm.pcnt, J.hm.qptr, P, &C->nq);
   FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.qptr + P, &C->nq);
   const int nq = J.read1(&C->nq);
   if (J.hip_failed) return FP_ERR_HIP;
   if (nq < 0 || nq > J.hm.Ecap) return FP_ERR_SIZE;
-  FPL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, 0, st, dm, P, 1);
+  FPL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, qbw * 4 * FP_WAVES, st, dm, P, 1, qbw);
   J.check();
 
   // separator tree
