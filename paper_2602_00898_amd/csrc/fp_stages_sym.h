@@ -614,6 +614,116 @@ __device__ __forceinline__ void sym_elim_wide(const FpMesh& M, int t, const SymV
   if (lane_id() == 0) V.hdr[SH_NOUT] = nout;
 }
 
+// ---------------------------------------------------------------- chain
+// Most separator nodes eliminate as one chain: column k's parent is k + 1.
+// In a chain, column k's structure is every index b > k that some column
+// j <= k holds among its forward entries or incoming rows (an incoming row
+// joins at its least entry).  With intro(b) the least such column, the count
+// of column k is the number of b with intro(b) <= k < b: a difference array
+// and a prefix sum, all lanes at once.  The node is a chain exactly when
+// intro(k + 1) <= k for every k < m - 1 (by induction over k: then column
+// k's only child is k - 1), which is checked before anything is written; a
+// node that fails it takes the sequential elimination.
+#define FP_CHAIN_MIN 32
+template <class IP>
+__device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const SymView& V,
+                                               const int* h, IP head, IP next) {
+  const int m = h[SH_M], nbd = h[SH_NBD], rows = h[SH_ROWS], FW = h[SH_FW];
+  const int stride = h[SH_STRIDE];
+  const int F = m + nbd;
+  if (m < FP_CHAIN_MIN) return false;
+  const gptr<unsigned> sc = pool_alloc(M, (unsigned long long)F + m + 64);
+  if (!sc) return false;  // pool_alloc raised the error
+  const gptr<int> intro = sc.as<int>(), diff = intro + F;
+  const gptr<const int> optr = V.optr, oent = V.oent;
+  const int lane = lane_id();
+  for (int b = lane; b < F; b += 64) intro[b] = 0x7FFFFFFF;
+  for (int k = lane; k < m; k += 64) diff[k] = 0;
+  wave_fence();
+  // forward entries, and incoming rows at the column they are queued on
+  bool bad = false;
+  for (int k = lane; k < m; k += 64) {
+    const int r0 = optr[k], r1 = optr[k + 1];
+    for (int e = r0; e < r1; e++) {
+      const int f = oent[e];
+      if (f <= k || f >= F) {
+        bad = true;
+        break;
+      }
+      atomicMin(&intro[f], k);
+    }
+    int j = head[k], steps = 0;
+    while (j >= m && j < rows && steps < rows) {
+      const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
+      for (int w = k >> 5; w < FW; w++) {
+        uint32_t x = rj[w];
+        while (x) {
+          const int b = w * 32 + __ffs(x) - 1;
+          x &= x - 1;
+          if (b > k && b < F) atomicMin(&intro[b], k);
+        }
+      }
+      j = next[j];
+      steps++;
+    }
+    bad |= j >= 0;  // only incoming rows are queued before the elimination
+  }
+  if (ballot64(bad)) {
+    if (lane == 0) {
+      fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_LIVE, t);
+      V.hdr[SH_OK] = 0;
+    }
+    return true;
+  }
+  wave_fence();
+  // the chain test
+  for (int k = lane; k + 1 < m; k += 64) bad |= intro[k + 1] > k;
+  if (ballot64(bad)) return false;
+  // every b holds on the columns intro(b) .. b - 1 (the node's last column
+  // for a later position); the least later position held is the parent of
+  // the last column
+  uint32_t pl = 0xFFFFFFFFu;
+  for (int b = lane; b < F; b += 64) {
+    const int i = intro[b];
+    if (i < m) {
+      atomicAdd(&diff[i], 1);
+      if (b < m)
+        atomicAdd(&diff[b], -1);
+      else
+        pl = min(pl, (uint32_t)b);
+    }
+  }
+  pl = wave_min_u32(pl);
+  wave_fence();
+  const int b0 = M.nbegin[t];
+  const int plast = pl != 0xFFFFFFFFu ? uni(V.bd[pl - m]) : -1;
+  int run = 0;
+  for (int k0 = 0; k0 < m; k0 += 64) {
+    const int k = k0 + lane;
+    const int c = k < m ? (int)diff[k] : 0;
+    const int inc = wave_incl_scan(c);
+    if (k < m) {
+      M.vcc[b0 + k] = 1 + run + inc;
+      M.vpar[b0 + k] = k + 1 < m ? b0 + k + 1 : plast;
+    }
+    run += wave_bcast(inc, 63);
+  }
+  // the last column's row leaves t when its parent is above
+  int nout = h[SH_NOUT];
+  if (pl != 0xFFFFFFFFu) {
+    const gptr<uint32_t> rl = V.rows + (long long)(m - 1) * stride;
+    for (int w = lane; w < FW; w += 64) rl[w] = 0u;
+    wave_fence();
+    for (int b = m + lane; b < F; b += 64)
+      if (intro[b] < m) atomicOr(&rl[b >> 5], 1u << (b & 31));
+    if (lane == 0) V.outl[nout] = m - 1;
+    nout++;
+  }
+  wave_fence();
+  if (lane == 0) V.hdr[SH_NOUT] = nout;
+  return true;
+}
+
 template <bool kLds>
 __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymView& V,
                                              const int* h, int* lds) {
@@ -636,6 +746,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     wave_fence();
   }
   (void)nfw;
+  if (sym_elim_chain(M, t, V, h, head, next)) return;
   if (FW > 64 * FP_SYM_REGW) {
     sym_elim_wide(M, t, V, h, head, next, optr, oent);
     return;
