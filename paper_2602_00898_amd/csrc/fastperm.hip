@@ -712,13 +712,14 @@ __global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ M
   int* slice = (int*)fp_lds + (M.lds_bytes / 4 / nsl) * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
   const int wv = uni((int)blockIdx.x * nsl + wave_id()), nw = (int)gridDim.x * nsl;
-  for (int x = wv; x < cnt; x += nw) sym_elim<true>(M, lo + x, cls, slice);
+  const long long lw = cls == 0 ? M.lds_bytes / 4 / nsl : M.lds_big / 4;
+  for (int x = wv; x < cnt; x += nw) sym_elim<true>(M, lo + x, cls, slice, lw);
 }
 // nodes too large for the whole LDS: links and rows in global memory
 __global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(const FpMesh* __restrict__ Mp, int d) {
   MESH;
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  for (int x = gwave(); x < cnt; x += nwaves()) sym_elim<false>(M, lo + x, 2, nullptr);
+  for (int x = gwave(); x < cnt; x += nwaves()) sym_elim<false>(M, lo + x, 2, nullptr, 0);
 }
 __global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ Mp, int d) {
   MESH;

@@ -625,17 +625,15 @@ __device__ __forceinline__ void sym_elim_wide(const FpMesh& M, int t, const SymV
 // k's only child is k - 1), which is checked before anything is written; a
 // node that fails it takes the sequential elimination.
 #define FP_CHAIN_MIN 32
-template <class IP>
+// intro (F words) and diff (m words): the wave's LDS slice or global scratch
+template <class SP>
 __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const SymView& V,
-                                               const int* h, IP head, IP next) {
+                                               const int* h, SP intro, SP diff) {
   const int m = h[SH_M], nbd = h[SH_NBD], rows = h[SH_ROWS], FW = h[SH_FW];
   const int stride = h[SH_STRIDE];
   const int F = m + nbd;
-  if (m < FP_CHAIN_MIN) return false;
-  const gptr<unsigned> sc = pool_alloc(M, (unsigned long long)F + m + 64);
-  if (!sc) return false;  // pool_alloc raised the error
-  const gptr<int> intro = sc.as<int>(), diff = intro + F;
   const gptr<const int> optr = V.optr, oent = V.oent;
+  const gptr<const int> head = V.head, next = V.next;
   const int lane = lane_id();
   for (int b = lane; b < F; b += 64) intro[b] = 0x7FFFFFFF;
   for (int k = lane; k < m; k += 64) diff[k] = 0;
@@ -726,11 +724,22 @@ __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const Sym
 
 template <bool kLds>
 __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymView& V,
-                                             const int* h, int* lds) {
+                                             const int* h, int* lds, long long lds_words) {
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
   const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
   const int F = m + nbd;
   int nout = h[SH_NOUT];
+  // a chain node first (section above): its arrays in the LDS slice when they
+  // fit, else in pool scratch
+  if (m >= FP_CHAIN_MIN) {
+    if (kLds && (long long)F + m <= lds_words) {
+      if (sym_elim_chain(M, t, V, h, lds, lds + F)) return;
+    } else {
+      const gptr<unsigned> sc = pool_alloc(M, (unsigned long long)F + m + 64);
+      if (!sc) return;  // pool_alloc raised the error
+      if (sym_elim_chain(M, t, V, h, sc.as<int>(), sc.as<int>() + F)) return;
+    }
+  }
   // queue links: the wave's LDS slice, or global memory; the forward rows
   // are read from global memory once per block of 64 columns
   using IP = typename std::conditional<kLds, int*, gptr<int>>::type;
@@ -746,7 +755,6 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     wave_fence();
   }
   (void)nfw;
-  if (sym_elim_chain(M, t, V, h, head, next)) return;
   if (FW > 64 * FP_SYM_REGW) {
     sym_elim_wide(M, t, V, h, head, next, optr, oent);
     return;
@@ -919,11 +927,12 @@ __device__ __forceinline__ int sym_elim_class(const FpMesh& M, const int* h) {
 }
 
 template <bool kLds>
-__device__ __forceinline__ void sym_elim(const FpMesh& M, int t, int cls, int* lds) {
+__device__ __forceinline__ void sym_elim(const FpMesh& M, int t, int cls, int* lds,
+                                         long long lds_words) {
   SymView V;
   int h[SH_WORDS];
   if (!sym_load(M, t, &V, h)) return;
-  if (sym_elim_class(M, h) == cls) sym_elim_run<kLds>(M, t, V, h, lds);
+  if (sym_elim_class(M, h) == cls) sym_elim_run<kLds>(M, t, V, h, lds, lds_words);
 }
 
 // ---------------------------------------------------------------- emit
