@@ -125,26 +125,35 @@ struct PrepRows {
   int e0[FP_PREP_COLS], deg[FP_PREP_COLS];
   int q[FP_PREP_COLS][FP_PREP_ROW];
 };
-__device__ __forceinline__ void prep_rows(const FpMesh& M, int b0, int m, int k0, PrepRows& r) {
+// rows k of a CSR (rp, ent), k = k0 + lane + 64 u < m, position base + k
+__device__ __forceinline__ void csr_rows(gptr<const int> rp, gptr<const int> ent, int base, int m,
+                                         int k0, PrepRows& r) {
 #pragma unroll
   for (int u = 0; u < FP_PREP_COLS; u++) {
     const int k = k0 + lane_id() + 64 * u;
     const bool act = k < m;
-    r.e0[u] = act ? M.prow[b0 + k] : 0;
-    r.deg[u] = act ? M.prow[b0 + k + 1] - r.e0[u] : 0;
+    r.e0[u] = act ? rp[base + k] : 0;
+    r.deg[u] = act ? rp[base + k + 1] - r.e0[u] : 0;
   }
 #pragma unroll
   for (int u = 0; u < FP_PREP_COLS; u++)
 #pragma unroll
-    for (int j = 0; j < FP_PREP_ROW; j++) r.q[u][j] = j < r.deg[u] ? M.pent[r.e0[u] + j] : 0;
+    for (int j = 0; j < FP_PREP_ROW; j++) r.q[u][j] = j < r.deg[u] ? ent[r.e0[u] + j] : 0;
+}
+__device__ __forceinline__ void prep_rows(const FpMesh& M, int b0, int m, int k0, PrepRows& r) {
+  csr_rows(M.prow, M.pent, b0, m, k0, r);
 }
 // fn(q) for every entry q of the row of column k0 + lane + 64 u
 template <class Fn>
-__device__ __forceinline__ void prep_each(const FpMesh& M, const PrepRows& r, int u, Fn fn) {
+__device__ __forceinline__ void csr_each(gptr<const int> ent, const PrepRows& r, int u, Fn fn) {
 #pragma unroll
   for (int j = 0; j < FP_PREP_ROW; j++)
     if (j < r.deg[u]) fn(r.q[u][j]);
-  for (int j = FP_PREP_ROW; j < r.deg[u]; j++) fn((int)M.pent[r.e0[u] + j]);
+  for (int j = FP_PREP_ROW; j < r.deg[u]; j++) fn((int)ent[r.e0[u] + j]);
+}
+template <class Fn>
+__device__ __forceinline__ void prep_each(const FpMesh& M, const PrepRows& r, int u, Fn fn) {
+  csr_each(M.pent, r, u, fn);
 }
 
 // lds / lwords: this wave's LDS slice, which holds the ancestor table and,
@@ -640,16 +649,21 @@ __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const Sym
   wave_fence();
   // forward entries, and incoming rows at the column they are queued on
   bool bad = false;
-  for (int k = lane; k < m; k += 64) {
-    const int r0 = optr[k], r1 = optr[k + 1];
-    for (int e = r0; e < r1; e++) {
-      const int f = oent[e];
-      if (f <= k || f >= F) {
-        bad = true;
-        break;
-      }
-      atomicMin(&intro[f], k);
+  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
+    PrepRows R;
+    csr_rows(optr, oent, 0, m, k0, R);
+#pragma unroll
+    for (int u = 0; u < FP_PREP_COLS; u++) {
+      const int k = k0 + lane + 64 * u;
+      csr_each(oent, R, u, [&](int f) {
+        if (f <= k || f >= F)
+          bad = true;
+        else
+          atomicMin(&intro[f], k);
+      });
     }
+  }
+  for (int k = lane; k < m; k += 64) {
     int j = head[k], steps = 0;
     while (j >= m && j < rows && steps < rows) {
       const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
