@@ -75,6 +75,13 @@ __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 // wait for outstanding stores, unlike a workgroup fence.
 __device__ __forceinline__ void wave_fence() { __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront"); }
 
+// Waits until every vector memory operation the wave has issued is done
+// (vmcnt 0; expcnt and lgkmcnt left alone).  Placed right after loads whose
+// registers a loop reads many times: the compiler then knows they have
+// arrived, instead of waiting for every outstanding load and store (a
+// store's completion takes hundreds of cycles) at each use in the loop.
+__device__ __forceinline__ void vm_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // ---------------------------------------------------------------- wave64
 // Reductions and scans run on DPP row shifts (within each 16-lane row,
 // register to register) and combine the four rows through readlane, instead

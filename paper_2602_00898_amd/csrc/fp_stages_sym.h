@@ -491,13 +491,21 @@ __device__ __forceinline__ bool sym_load(const FpMesh& M, int t, SymView* V, int
 // keeps its words of the last column in registers: the next column is most
 // often that column's parent, and then its row needs no memory read.
 #define FP_SYM_REGW 4  // words per lane kept in registers (rows up to 256 words)
-#define FP_SYM_ENTW 4  // forward entries per lane kept for a block of 64 columns
+#ifndef FP_SYM_ENTW
+#define FP_SYM_ENTW 4  // forward entries per lane in the register window
+#endif
 
-__device__ __forceinline__ int sym_sel(const int (&a)[FP_SYM_ENTW], int q) {
-  return q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
-}
-__device__ __forceinline__ uint32_t sym_selu(const uint32_t (&a)[FP_SYM_REGW], int q) {
-  return q == 0 ? a[0] : q == 1 ? a[1] : q == 2 ? a[2] : a[3];
+// entry q * 64 + l of the window, q and l wave-uniform: one readlane per
+// register and a scalar select, so the window is never indexed dynamically
+// (which would move it to scratch memory)
+__device__ __forceinline__ int sym_ent(const int (&a)[FP_SYM_ENTW], int q, int l) {
+  int r = __builtin_amdgcn_readlane(a[0], l);
+#pragma unroll
+  for (int i = 1; i < FP_SYM_ENTW; i++) {
+    const int v = __builtin_amdgcn_readlane(a[i], l);
+    r = q == i ? v : r;
+  }
+  return r;
 }
 
 // the row of column k, word w: queued rows OR forward entries, bits > k
@@ -529,7 +537,7 @@ template <class IP>
 __device__ __forceinline__ void sym_elim_wide(const FpMesh& M, int t, const SymView& V, const int* h,
                                               IP head, IP next, gptr<int> optr, gptr<int> oent) {
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
-  const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
+  const int stride = h[SH_STRIDE];
   const int F = m + nbd;
   int nout = h[SH_NOUT];
   const bool regs = FW <= 64 * FP_SYM_REGW;
@@ -736,43 +744,16 @@ __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const Sym
   return true;
 }
 
-template <bool kLds>
-__device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymView& V,
-                                             const int* h, int* lds, long long lds_words) {
+// The sequential walk over a node's columns, rows of up to 64 NW words
+// held NW words per lane.
+template <int NW, class IP>
+__device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymView& V,
+                                              const int* h, IP head, IP next,
+                                              const gptr<int> optr, const gptr<int> oent) {
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
-  const int nfw = h[SH_NFW], stride = h[SH_STRIDE];
+  const int stride = h[SH_STRIDE];
   const int F = m + nbd;
   int nout = h[SH_NOUT];
-  // a chain node first (section above): its arrays in the LDS slice when they
-  // fit, else in pool scratch
-  if (m >= FP_CHAIN_MIN) {
-    if (kLds && (long long)F + m <= lds_words) {
-      if (sym_elim_chain(M, t, V, h, lds, lds + F)) return;
-    } else {
-      const gptr<unsigned> sc = pool_alloc(M, (unsigned long long)F + m + 64);
-      if (!sc) return;  // pool_alloc raised the error
-      if (sym_elim_chain(M, t, V, h, sc.as<int>(), sc.as<int>() + F)) return;
-    }
-  }
-  // queue links: the wave's LDS slice, or global memory; the forward rows
-  // are read from global memory once per block of 64 columns
-  using IP = typename std::conditional<kLds, int*, gptr<int>>::type;
-  IP head = V.head;
-  IP next = V.next;
-  const gptr<int> optr = V.optr;
-  const gptr<int> oent = V.oent;
-  if (kLds) {
-    head = lds;
-    next = head + m;
-    for (int i = lane_id(); i < m; i += 64) head[i] = V.head[i];
-    for (int i = lane_id(); i < rows; i += 64) next[i] = V.next[i];
-    wave_fence();
-  }
-  (void)nfw;
-  if (FW > 64 * FP_SYM_REGW) {
-    sym_elim_wide(M, t, V, h, head, next, optr, oent);
-    return;
-  }
   // Columns go in blocks of 64.  A block's queue heads, row pointers and
   // forward entries are read once into registers (lane i holds column k0+i),
   // and a column whose parent is the next column hands its row over in
@@ -780,9 +761,9 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   // in separators, runs without any LDS or global round trip.
   const int lane = lane_id();
   const int b0 = M.nbegin[t];
-  uint32_t x[FP_SYM_REGW];  // the row being built, word lane + 64 i in x[i]
+  uint32_t x[NW];  // the row being built, word lane + 64 i in x[i]
 #pragma unroll
-  for (int i = 0; i < FP_SYM_REGW; i++) x[i] = 0u;
+  for (int i = 0; i < NW; i++) x[i] = 0u;
   int cnt = 0;
   bool chain = false;          // the previous column's parent is this column
   int my_cc = 0, my_par = -1;  // results of column k0 + lane, stored per block
@@ -790,14 +771,18 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     const int kn = min(64, m - k0);
     int hreg = lane < kn ? head[k0 + lane] : -1;
     const int oreg = lane < kn ? optr[k0 + lane] : 0;
-    const int e0 = uni(optr[k0]), e1 = uni(optr[k0 + kn]);
-    const bool ereg = e1 - e0 <= 64 * FP_SYM_ENTW;
+    const int e1 = uni(optr[k0 + kn]);
+    // a window of the block's forward entries in registers: entries wb ..
+    // wb + 64 FP_SYM_ENTW - 1, moved up to a column's first entry when that
+    // column's entries run past it
+    int wb = uni(optr[k0]);
     int ent[FP_SYM_ENTW];
 #pragma unroll
     for (int q = 0; q < FP_SYM_ENTW; q++) {
-      const int e = e0 + lane + 64 * q;
-      ent[q] = ereg && e < e1 ? oent[e] : 0;
+      const int e = wb + lane + 64 * q;
+      ent[q] = e < e1 ? oent[e] : 0;
     }
+    vm_wait();
     for (int kk = 0; kk < kn; kk++) {
       const int k = k0 + kk;
       const int r0 = wave_bcast(oreg, kk);
@@ -810,21 +795,21 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
         cnt -= 1;  // k, the previous column's parent, is not an entry of k
       } else {
 #pragma unroll
-        for (int i = 0; i < FP_SYM_REGW; i++) x[i] = 0u;
+        for (int i = 0; i < NW; i++) x[i] = 0u;
         cnt = 0;
       }
       const int kw = k >> 5;
       const uint32_t kmask = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
       // rows queued on k (columns other than k-1, and rows from below)
       bool bad = false;
+      int add = 0;  // bits set in x below, summed over the wave once
       {
         int j = wave_bcast(hreg, kk), steps = 0;
         if (j >= 0) {
-          int add = 0;
           while (j >= 0 && j < rows && steps < rows) {
             const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
 #pragma unroll
-            for (int i = 0; i < FP_SYM_REGW; i++) {
+            for (int i = 0; i < NW; i++) {
               const int w = lane + 64 * i;
               if (i * 64 < FW && w < FW && w >= kw) {
                 uint32_t y = rj[w];
@@ -837,35 +822,48 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
             steps++;
           }
           bad = j >= 0;  // a queue that leaves the rows or does not end
-          cnt += wave_sum_i32(add);
         }
       }
       // forward entries of column k: a bit test in the owning lane
+      if (r1 > wb + 64 * FP_SYM_ENTW && r1 - r0 <= 64 * FP_SYM_ENTW) {
+        wb = r0;
+#pragma unroll
+        for (int q = 0; q < FP_SYM_ENTW; q++) {
+          const int e = wb + lane + 64 * q;
+          ent[q] = e < e1 ? oent[e] : 0;
+        }
+        vm_wait();
+      }
+      // every entry is broadcast and each lane keeps the bits of its own
+      // words: straight-line vector work, merged into x once
+      const bool ereg = r1 <= wb + 64 * FP_SYM_ENTW;
+      uint32_t fm[NW];
+#pragma unroll
+      for (int i = 0; i < NW; i++) fm[i] = 0u;
       for (int e = r0; e < r1; e++) {
         int f;
         if (ereg) {
-          const int q = (e - e0) >> 6, l = (e - e0) & 63;
-          f = wave_bcast(sym_sel(ent, q), l);
+          const int q = (e - wb) >> 6, l = (e - wb) & 63;
+          f = sym_ent(ent, q, l);
         } else {
           f = uni(oent[e]);
         }
-        if (f <= k || f >= F) {
-          bad = true;
-          break;
-        }
-        const int fw = f >> 5, owner = fw & 63, slot = fw >> 6;
+        bad |= f <= k || f >= F;
+        const int fw = f >> 5;
         const uint32_t bit = 1u << (f & 31);
-        if (!(wave_bcast_u32(sym_selu(x, slot), owner) & bit)) {
-          cnt++;
 #pragma unroll
-          for (int i = 0; i < FP_SYM_REGW; i++)
-            if (i == slot && lane == owner) x[i] |= bit;
-        }
+        for (int i = 0; i < NW; i++) fm[i] |= lane + 64 * i == fw ? bit : 0u;
       }
+#pragma unroll
+      for (int i = 0; i < NW; i++) {
+        add += popc32(fm[i] & ~x[i]);
+        x[i] |= fm[i];
+      }
+      cnt += wave_sum_i32(add);
       // keep entries > k; least entry by ballot
       uint32_t first = 0xFFFFFFFFu;
 #pragma unroll
-      for (int i = 0; i < FP_SYM_REGW; i++) {
+      for (int i = 0; i < NW; i++) {
         if (i * 64 < FW) {
           const int w = lane + 64 * i;
           if (w < kw || w >= FW) x[i] = 0u;
@@ -890,7 +888,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
       if (first != 0xFFFFFFFFu && !to_next) {
         const gptr<uint32_t> rk = V.rows + (long long)k * stride;
 #pragma unroll
-        for (int i = 0; i < FP_SYM_REGW; i++) {
+        for (int i = 0; i < NW; i++) {
           const int w = lane + 64 * i;
           if (i * 64 < FW && w < FW) rk[w] = x[i];
         }
@@ -924,6 +922,48 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     }
   }
   if (lane == 0) V.hdr[SH_NOUT] = nout;
+}
+
+template <bool kLds>
+__device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymView& V,
+                                             const int* h, int* lds, long long lds_words) {
+  const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
+  const int F = m + nbd;
+  // a chain node first (section above): its arrays in the LDS slice when they
+  // fit, else in pool scratch
+  if (m >= FP_CHAIN_MIN) {
+    if (kLds && (long long)F + m <= lds_words) {
+      if (sym_elim_chain(M, t, V, h, lds, lds + F)) return;
+    } else {
+      const gptr<unsigned> sc = pool_alloc(M, (unsigned long long)F + m + 64);
+      if (!sc) return;  // pool_alloc raised the error
+      if (sym_elim_chain(M, t, V, h, sc.as<int>(), sc.as<int>() + F)) return;
+    }
+  }
+  // queue links: the wave's LDS slice, or global memory; the forward rows
+  // are read from global memory once per block of 64 columns
+  using IP = typename std::conditional<kLds, int*, gptr<int>>::type;
+  IP head = V.head;
+  IP next = V.next;
+  const gptr<int> optr = V.optr;
+  const gptr<int> oent = V.oent;
+  if (kLds) {
+    head = lds;
+    next = head + m;
+    for (int i = lane_id(); i < m; i += 64) head[i] = V.head[i];
+    for (int i = lane_id(); i < rows; i += 64) next[i] = V.next[i];
+    wave_fence();
+  }
+  if (FW > 64 * FP_SYM_REGW) {
+    sym_elim_wide(M, t, V, h, head, next, optr, oent);
+    return;
+  }
+  if (FW <= 64)
+    sym_elim_cols<1>(M, t, V, h, head, next, optr, oent);
+  else if (FW <= 128)
+    sym_elim_cols<2>(M, t, V, h, head, next, optr, oent);
+  else
+    sym_elim_cols<4>(M, t, V, h, head, next, optr, oent);
 }
 
 // LDS words of a node's queue links (heads and next pointers)
