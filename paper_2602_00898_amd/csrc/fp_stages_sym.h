@@ -746,10 +746,14 @@ __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const Sym
 
 // The sequential walk over a node's columns, rows of up to 64 NW words
 // held NW words per lane.
+// With the links in LDS (IP a plain pointer), rb is an LDS buffer of FW
+// zero words that gathers each column's forward entries.
 template <int NW, class IP>
 __device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymView& V,
                                               const int* h, IP head, IP next,
-                                              const gptr<int> optr, const gptr<int> oent) {
+                                              const gptr<int> optr, const gptr<int> oent,
+                                              uint32_t* rb) {
+  constexpr bool kRb = std::is_same<IP, int*>::value;
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
   const int stride = h[SH_STRIDE];
   const int F = m + nbd;
@@ -834,25 +838,61 @@ __device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymV
         }
         vm_wait();
       }
-      // every entry is broadcast and each lane keeps the bits of its own
-      // words: straight-line vector work, merged into x once
       const bool ereg = r1 <= wb + 64 * FP_SYM_ENTW;
       uint32_t fm[NW];
 #pragma unroll
       for (int i = 0; i < NW; i++) fm[i] = 0u;
-      for (int e = r0; e < r1; e++) {
-        int f;
-        if (ereg) {
-          const int q = (e - wb) >> 6, l = (e - wb) & 63;
-          f = sym_ent(ent, q, l);
-        } else {
-          f = uni(oent[e]);
-        }
-        bad |= f <= k || f >= F;
-        const int fw = f >> 5;
-        const uint32_t bit = 1u << (f & 31);
+      if (kRb) {
+        // the lanes that hold the column's entries set their bits in the
+        // LDS row buffer; each lane then takes (and clears) its own words
+        if (r1 > r0) {
+          if (ereg) {
+            const int p0 = r0 - wb, p1 = r1 - wb;
 #pragma unroll
-        for (int i = 0; i < NW; i++) fm[i] |= lane + 64 * i == fw ? bit : 0u;
+            for (int q = 0; q < FP_SYM_ENTW; q++) {
+              if (64 * q < p1 && 64 * q + 64 > p0) {
+                const int p = lane + 64 * q;
+                const int f = ent[q];
+                if (p >= p0 && p < p1) {
+                  bad |= f <= k || f >= F;
+                  if (f > k && f < F) atomicOr(&rb[f >> 5], 1u << (f & 31));
+                }
+              }
+            }
+          } else {
+            for (int e = r0 + lane; e < r1; e += 64) {
+              const int f = oent[e];
+              bad |= f <= k || f >= F;
+              if (f > k && f < F) atomicOr(&rb[f >> 5], 1u << (f & 31));
+            }
+          }
+          wave_fence();
+#pragma unroll
+          for (int i = 0; i < NW; i++) {
+            const int w = lane + 64 * i;
+            if (i * 64 < FW && w < FW) {
+              fm[i] = rb[w];
+              rb[w] = 0u;
+            }
+          }
+        }
+      } else {
+        // every entry is broadcast and each lane keeps the bits of its own
+        // words: straight-line vector work
+        for (int e = r0; e < r1; e++) {
+          int f;
+          if (ereg) {
+            const int q = (e - wb) >> 6, l = (e - wb) & 63;
+            f = sym_ent(ent, q, l);
+          } else {
+            f = uni(oent[e]);
+          }
+          bad |= f <= k || f >= F;
+          const int fw = f >> 5;
+          const uint32_t bit = 1u << (f & 31);
+#pragma unroll
+          for (int i = 0; i < NW; i++) fm[i] |= lane + 64 * i == fw ? bit : 0u;
+        }
       }
 #pragma unroll
       for (int i = 0; i < NW; i++) {
@@ -947,11 +987,14 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   IP next = V.next;
   const gptr<int> optr = V.optr;
   const gptr<int> oent = V.oent;
-  if (kLds) {
+  uint32_t* rb = nullptr;
+  if constexpr (kLds) {
     head = lds;
     next = head + m;
+    rb = (uint32_t*)(lds + m + rows);
     for (int i = lane_id(); i < m; i += 64) head[i] = V.head[i];
     for (int i = lane_id(); i < rows; i += 64) next[i] = V.next[i];
+    for (int i = lane_id(); i < FW; i += 64) rb[i] = 0u;
     wave_fence();
   }
   if (FW > 64 * FP_SYM_REGW) {
@@ -959,16 +1002,17 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     return;
   }
   if (FW <= 64)
-    sym_elim_cols<1>(M, t, V, h, head, next, optr, oent);
+    sym_elim_cols<1>(M, t, V, h, head, next, optr, oent, rb);
   else if (FW <= 128)
-    sym_elim_cols<2>(M, t, V, h, head, next, optr, oent);
+    sym_elim_cols<2>(M, t, V, h, head, next, optr, oent, rb);
   else
-    sym_elim_cols<4>(M, t, V, h, head, next, optr, oent);
+    sym_elim_cols<4>(M, t, V, h, head, next, optr, oent, rb);
 }
 
-// LDS words of a node's queue links (heads and next pointers)
+// LDS words of a node's sequential walk: queue links (heads and next
+// pointers) and the forward-entry row buffer
 __device__ __forceinline__ long long sym_elim_lds_words(const int* h) {
-  return (long long)h[SH_M] + h[SH_ROWS];
+  return (long long)h[SH_M] + h[SH_ROWS] + h[SH_FW];
 }
 
 // 0: the links fit a quarter of the per-node LDS (four waves per workgroup),
