@@ -653,7 +653,6 @@ __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const Sym
   const gptr<const int> head = V.head, next = V.next;
   const int lane = lane_id();
   for (int b = lane; b < F; b += 64) intro[b] = 0x7FFFFFFF;
-  for (int k = lane; k < m; k += 64) diff[k] = 0;
   wave_fence();
   // forward entries, and incoming rows at the column they are queued on
   bool bad = false;
@@ -671,23 +670,48 @@ __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const Sym
       });
     }
   }
-  for (int k = lane; k < m; k += 64) {
-    int j = head[k], steps = 0;
+  // Incoming rows are few but wide (a child's last row holds most of its
+  // structure), so each is taken by the whole wave.  The columns with a
+  // queue are listed in diff first (cleared afterwards).
+  int nq = 0;
+  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
+    int hj[FP_PREP_COLS];
+#pragma unroll
+    for (int u = 0; u < FP_PREP_COLS; u++) {
+      const int k = k0 + lane + 64 * u;
+      hj[u] = k < m ? head[k] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < FP_PREP_COLS; u++) {
+      const uint64_t bal = ballot64(hj[u] >= 0);
+      if (hj[u] >= 0) diff[nq + popc64(bal & lanemask_lt())] = k0 + lane + 64 * u;
+      nq += popc64(bal);
+    }
+  }
+  wave_fence();
+  for (int q = 0; q < nq; q++) {
+    const int k = uni(diff[q]);
+    const int kw = k >> 5;
+    const uint32_t kmask = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
+    int j = uni(head[k]), steps = 0;
     while (j >= m && j < rows && steps < rows) {
       const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
-      for (int w = k >> 5; w < FW; w++) {
+      for (int w = kw + lane; w < FW; w += 64) {
         uint32_t x = rj[w];
+        if (w == kw) x &= kmask;
         while (x) {
           const int b = w * 32 + __ffs(x) - 1;
           x &= x - 1;
-          if (b > k && b < F) atomicMin(&intro[b], k);
+          if (b < F) atomicMin(&intro[b], k);
         }
       }
-      j = next[j];
+      j = uni(next[j]);
       steps++;
     }
     bad |= j >= 0;  // only incoming rows are queued before the elimination
   }
+  wave_fence();
+  for (int k = lane; k < m; k += 64) diff[k] = 0;
   if (ballot64(bad)) {
     if (lane == 0) {
       fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_LIVE, t);
@@ -771,6 +795,10 @@ __device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymV
   int cnt = 0;
   bool chain = false;          // the previous column's parent is this column
   int my_cc = 0, my_par = -1;  // results of column k0 + lane, stored per block
+  uint32_t pf[NW];             // row pfj, loaded one column ahead
+  int pfj = -1;
+#pragma unroll
+  for (int i = 0; i < NW; i++) pf[i] = 0u;
   for (int k0 = 0; k0 < m; k0 += 64) {
     const int kn = min(64, m - k0);
     int hreg = lane < kn ? head[k0 + lane] : -1;
@@ -804,30 +832,51 @@ __device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymV
       }
       const int kw = k >> 5;
       const uint32_t kmask = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
-      // rows queued on k (columns other than k-1, and rows from below)
+      // rows queued on k (columns other than k-1, and rows from below); the
+      // first of them was loaded into pf at the previous column
       bool bad = false;
       int add = 0;  // bits set in x below, summed over the wave once
-      {
-        int j = wave_bcast(hreg, kk), steps = 0;
-        if (j >= 0) {
-          while (j >= 0 && j < rows && steps < rows) {
-            const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
+      int j = wave_bcast(hreg, kk), steps = 0;
+      if (j >= 0 && j == pfj) {
 #pragma unroll
-            for (int i = 0; i < NW; i++) {
-              const int w = lane + 64 * i;
-              if (i * 64 < FW && w < FW && w >= kw) {
-                uint32_t y = rj[w];
-                if (w == kw) y &= kmask;
-                add += popc32(y & ~x[i]);
-                x[i] |= y;
-              }
-            }
-            j = uni(next[j]);
-            steps++;
-          }
-          bad = j >= 0;  // a queue that leaves the rows or does not end
+        for (int i = 0; i < NW; i++) {
+          const int w = lane + 64 * i;
+          uint32_t y = w >= kw && w < FW ? pf[i] : 0u;
+          if (w == kw) y &= kmask;
+          add += popc32(y & ~x[i]);
+          x[i] |= y;
+        }
+        j = uni(next[j]);
+        steps = 1;
+      }
+      // the first row queued on k + 1 (that queue is complete: this column
+      // hands its own row to k + 1 in registers), loaded while k goes on
+      {
+        const int jn = kk + 1 < kn ? wave_bcast(hreg, kk + 1) : (k + 1 < m ? uni(head[k + 1]) : -1);
+        pfj = -1;
+        if (jn >= 0 && jn < rows) {
+          pfj = jn;
+          const gptr<const uint32_t> rn = V.rows + (long long)jn * stride;
+#pragma unroll
+          for (int i = 0; i < NW; i++) pf[i] = rn[min(lane + 64 * i, FW - 1)];
         }
       }
+      while (j >= 0 && j < rows && steps < rows) {
+        const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
+#pragma unroll
+        for (int i = 0; i < NW; i++) {
+          const int w = lane + 64 * i;
+          if (i * 64 < FW && w < FW && w >= kw) {
+            uint32_t y = rj[w];
+            if (w == kw) y &= kmask;
+            add += popc32(y & ~x[i]);
+            x[i] |= y;
+          }
+        }
+        j = uni(next[j]);
+        steps++;
+      }
+      bad = j >= 0;  // a queue that leaves the rows or does not end
       // forward entries of column k: a bit test in the owning lane
       if (r1 > wb + 64 * FP_SYM_ENTW && r1 - r0 <= 64 * FP_SYM_ENTW) {
         wb = r0;
@@ -900,14 +949,22 @@ __device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymV
         x[i] |= fm[i];
       }
       cnt += wave_sum_i32(add);
-      // keep entries > k; least entry by ballot
+      // keep entries > k; the row is stored at once (its parent, unless that
+      // is the next column, reads it back from memory), so the store is done
+      // by the time a later column waits for its loads
+      const gptr<uint32_t> rk = V.rows + (long long)k * stride;
+#pragma unroll
+      for (int i = 0; i < NW; i++) {
+        const int w = lane + 64 * i;
+        if (w < kw || w >= FW) x[i] = 0u;
+        if (w == kw) x[i] &= kmask;
+        if (i * 64 < FW && w < FW) rk[w] = x[i];
+      }
+      // least entry by ballot
       uint32_t first = 0xFFFFFFFFu;
 #pragma unroll
       for (int i = 0; i < NW; i++) {
         if (i * 64 < FW) {
-          const int w = lane + 64 * i;
-          if (w < kw || w >= FW) x[i] = 0u;
-          if (w == kw) x[i] &= kmask;
           const uint64_t b = ballot64(x[i] != 0u);
           if (first == 0xFFFFFFFFu && b) {
             const int l = __builtin_ctzll(b);
@@ -923,16 +980,6 @@ __device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymV
         return;
       }
       const bool to_next = first == (uint32_t)(k + 1) && (int)first < m;
-      // the row is read again by its parent only: stored unless that is the
-      // next column, which takes it from registers
-      if (first != 0xFFFFFFFFu && !to_next) {
-        const gptr<uint32_t> rk = V.rows + (long long)k * stride;
-#pragma unroll
-        for (int i = 0; i < NW; i++) {
-          const int w = lane + 64 * i;
-          if (i * 64 < FW && w < FW) rk[w] = x[i];
-        }
-      }
       int par = -1;
       if (first != 0xFFFFFFFFu) par = (int)first < m ? b0 + (int)first : uni(V.bd[first - m]);
       if (first != 0xFFFFFFFFu && !to_next) {
