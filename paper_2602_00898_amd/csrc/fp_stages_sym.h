@@ -726,15 +726,21 @@ __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const Sym
   // every b holds on the columns intro(b) .. b - 1 (the node's last column
   // for a later position); the least later position held is the parent of
   // the last column
+  // The +1 side aggregates runs of equal intro over consecutive lanes: the
+  // bits of one incoming row share their intro, and one atomic per run
+  // replaces up to 64 on the same LDS word.
   uint32_t pl = 0xFFFFFFFFu;
-  for (int b = lane; b < F; b += 64) {
-    const int i = intro[b];
-    if (i < m) {
-      atomicAdd(&diff[i], 1);
-      if (b < m)
-        atomicAdd(&diff[b], -1);
-      else
-        pl = min(pl, (uint32_t)b);
+  for (int g = 0; g < F; g += 64) {
+    const int b = g + lane;
+    const int i = b < F ? intro[b] : 0x7FFFFFFF;
+    const bool v = i < m;
+    if (v && b < m) atomicAdd(&diff[b], -1);
+    if (v && b >= m) pl = min(pl, (uint32_t)b);
+    const int ip = __shfl_up(i, 1, 64);
+    const uint64_t heads = ballot64(lane == 0 || i != ip);
+    if (v && ((heads >> lane) & 1)) {
+      const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
+      atomicAdd(&diff[i], after ? __builtin_ctzll(after) + 1 : 64 - lane);
     }
   }
   pl = wave_min_u32(pl);
@@ -755,11 +761,16 @@ __device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const Sym
   // the last column's row leaves t when its parent is above
   int nout = h[SH_NOUT];
   if (pl != 0xFFFFFFFFu) {
+    // 64 bits at a time from one ballot: words 2g and 2g + 1 of the row
     const gptr<uint32_t> rl = V.rows + (long long)(m - 1) * stride;
-    for (int w = lane; w < FW; w += 64) rl[w] = 0u;
-    wave_fence();
-    for (int b = m + lane; b < F; b += 64)
-      if (intro[b] < m) atomicOr(&rl[b >> 5], 1u << (b & 31));
+    const int g0 = m >> 6;
+    for (int w = lane; w < 2 * g0 && w < FW; w += 64) rl[w] = 0u;
+    for (int g = g0; 64 * g < F; g++) {
+      const int b = 64 * g + lane;
+      const uint64_t bal = ballot64(b >= m && b < F && intro[b] < m);
+      const int w = 2 * g + lane;
+      if (lane < 2 && w < FW) rl[w] = lane == 0 ? (uint32_t)bal : (uint32_t)(bal >> 32);
+    }
     if (lane == 0) V.outl[nout] = m - 1;
     nout++;
   }
@@ -1018,7 +1029,7 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
   const int F = m + nbd;
   // a chain node first (section above): its arrays in the LDS slice when they
   // fit, else in pool scratch
-  if (m >= FP_CHAIN_MIN) {
+  if (m >= FP_CHAIN_MIN && rows > m) {  // a node with no incoming rows is a leaf
     if (kLds && (long long)F + m <= lds_words) {
       if (sym_elim_chain(M, t, V, h, lds, lds + F)) return;
     } else {
@@ -1056,10 +1067,13 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     sym_elim_cols<4>(M, t, V, h, head, next, optr, oent, rb);
 }
 
-// LDS words of a node's sequential walk: queue links (heads and next
-// pointers) and the forward-entry row buffer
+// LDS words of a node's elimination: the chain form's intro and diff
+// arrays, or the sequential walk's queue links (heads and next pointers)
+// and forward-entry row buffer
 __device__ __forceinline__ long long sym_elim_lds_words(const int* h) {
-  return (long long)h[SH_M] + h[SH_ROWS] + h[SH_FW];
+  const long long chain = 2ll * h[SH_M] + h[SH_NBD];
+  const long long walk = (long long)h[SH_M] + h[SH_ROWS] + h[SH_FW];
+  return chain > walk ? chain : walk;
 }
 
 // 0: the links fit a quarter of the per-node LDS (four waves per workgroup),
