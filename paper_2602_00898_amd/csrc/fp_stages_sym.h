@@ -78,29 +78,6 @@ __device__ __forceinline__ SymView sym_view(gptr<unsigned> base, int m, int np2,
   return V;
 }
 
-template <class P>
-__device__ __forceinline__ int lower_bound_i(P a, int n, int x) {
-  int lo = 0, hi = n;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (a[mid] < x)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  return lo;
-}
-
-// F index of position q (t's own range first, then the sorted list of later
-// positions); -1 if q is in neither, which the callers report
-template <class P>
-__device__ __forceinline__ int sym_findex(int q, int b0, int e0, int m, P bd, int nbd) {
-  if (q >= b0 && q < e0) return q - b0;
-  if (q < e0) return -1;
-  const int i = lower_bound_i(bd, nbd, q);
-  return (i < nbd && bd[i] == q) ? m + i : -1;
-}
-
 // node t produces no elements for its parent and no scratch for the later
 // kernels of this level; `site` != 0 also records a failed check
 __device__ __forceinline__ void sym_drop(const FpMesh& M, int t, int site) {
@@ -156,8 +133,238 @@ __device__ __forceinline__ void prep_each(const FpMesh& M, const PrepRows& r, in
   csr_each(M.pent, r, u, fn);
 }
 
+// Sizes and child records of a node, for the second half of the prep.
+struct PrepIn {
+  int m, b0, e0, na, BW, np2, nfw, nce, rows, stride;
+  int cst[2], cin[2];
+};
+
+// Second half of the prep: the later positions (marked in a bitmap over the
+// ancestors' ranges and read back in order), the forward rows in F
+// indices, and the incoming element rows.  bm and pre (BW words each) and
+// rbuf (stride words) live in LDS or in the pool (P a plain or a global
+// pointer).  The F index of a later position is m plus its rank in the
+// bitmap: the prefix count of its word plus the set bits below it.
+template <class P>
+__device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymView& V,
+                                              gptr<unsigned> base, gptr<const int> src,
+                                              const int* anc, const PrepIn& in, P bm, P pre,
+                                              P rbuf) {
+  const int m = in.m, b0 = in.b0, e0 = in.e0, na = in.na, BW = in.BW, np2 = in.np2;
+  const int lane = lane_id();
+  for (int w = lane; w < BW; w += 64) bm[w] = 0u;
+  wave_fence();
+  // the ancestor whose range holds position q, or -1
+  auto anc_of = [&](int q) -> int {
+    int lo = 0, hi = na - 1, f = -1;
+    while (lo <= hi) {  // nearest ancestor range starting at or before q
+      const int mid = (lo + hi) >> 1;
+      if (anc[3 * mid] <= q) {
+        f = mid;
+        lo = mid + 1;
+      } else {
+        hi = mid - 1;
+      }
+    }
+    return f >= 0 && q < anc[3 * f] + anc[3 * f + 1] ? f : -1;
+  };
+  // every position of the child records, four per lane loaded together
+  auto each_record_pos = [&](int off, int len, auto fn) {
+    for (int i0 = 0; i0 < len; i0 += 64 * FP_PREP_COLS) {
+      int q[FP_PREP_COLS];
+#pragma unroll
+      for (int u = 0; u < FP_PREP_COLS; u++) {
+        const int i = i0 + lane + 64 * u;
+        q[u] = i < len ? src[off + 1 + i] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < FP_PREP_COLS; u++)
+        if (i0 + lane + 64 * u < len) fn(q[u]);
+    }
+  };
+  // 1. mark the later positions of the child records and of t's own rows
+  bool bad1 = false;
+  auto mark = [&](int q) {
+    const int f = anc_of(q);
+    if (f < 0) {
+      bad1 = true;
+      return;
+    }
+    const int b = anc[3 * f + 2] + (q - anc[3 * f]);
+    atomicOr(&bm[b >> 5], 1u << (b & 31));
+  };
+  for (int c = 0; c < 2; c++) {
+    int off = in.cst[c];
+    const int end = in.cst[c] + in.cin[c];
+    while (off < end) {
+      const int len = uni(src[off]);
+      each_record_pos(off, len, [&](int q) {
+        if (q >= e0) mark(q);
+      });
+      off += 1 + len;
+    }
+  }
+  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
+    PrepRows R;
+    prep_rows(M, b0, m, k0, R);
+#pragma unroll
+    for (int u = 0; u < FP_PREP_COLS; u++)
+      prep_each(M, R, u, [&](int q) {
+        if (q >= e0) mark(q);
+      });
+  }
+  if (ballot64(bad1)) {
+    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+    return;
+  }
+  wave_fence();
+  // read the bitmap back: positions in increasing order, and the rank
+  // prefix of every word
+  int nbd = 0;
+  for (int w0 = 0; w0 < BW; w0 += 64) {
+    const int w = w0 + lane;
+    uint32_t x = w < BW ? bm[w] : 0u;
+    const int c = popc32(x);
+    const int inc = wave_incl_scan(c);
+    int o = nbd + inc - c;
+    if (w < BW) pre[w] = o;
+    while (x) {
+      const int b = w * 32 + __ffs(x) - 1;
+      x &= x - 1;
+      int lo = 0, hi = na - 1, f = 0;
+      while (lo <= hi) {  // the ancestor whose bit range holds b
+        const int mid = (lo + hi) >> 1;
+        if (anc[3 * mid + 2] <= b) {
+          f = mid;
+          lo = mid + 1;
+        } else {
+          hi = mid - 1;
+        }
+      }
+      if (o < np2) V.bd[o] = anc[3 * f] + (b - anc[3 * f + 2]);
+      o++;
+    }
+    nbd += wave_bcast(inc, 63);
+  }
+  if (nbd > np2) {
+    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+    return;
+  }
+  wave_fence();
+  const int F = m + nbd;
+  const int FW = (F + 31) >> 5;
+  // F index of position q: t's own range first, then the later positions
+  // in order; -1 if q is in neither, which the callers report
+  auto findex = [&](int q) -> int {
+    if (q >= b0 && q < e0) return q - b0;
+    if (q < e0) return -1;
+    const int f = anc_of(q);
+    if (f < 0) return -1;
+    const int b = anc[3 * f + 2] + (q - anc[3 * f]);
+    const uint32_t x = bm[b >> 5], bit = 1u << (b & 31);
+    return (x & bit) ? m + (int)pre[b >> 5] + popc32(x & (bit - 1u)) : -1;
+  };
+  // 2. forward rows in F indices
+  {
+    bool bad = false;
+    int run = 0;
+    for (int k1 = 0; k1 < m; k1 += 64 * FP_PREP_COLS) {
+      PrepRows R;
+      prep_rows(M, b0, m, k1, R);
+#pragma unroll
+      for (int u = 0; u < FP_PREP_COLS; u++) {
+        if (k1 + 64 * u >= m) break;
+        const int k = k1 + 64 * u + lane;
+        const int p = b0 + k;
+        int cnt = 0;
+        prep_each(M, R, u, [&](int q) { cnt += q > p; });
+        const int inc = wave_incl_scan(cnt);
+        int o = run + inc - cnt;
+        if (k < m) {
+          V.optr[k] = o;
+          prep_each(M, R, u, [&](int q) {
+            if (q > p) {
+              const int f = findex(q);
+              const bool ok = f > k && f < F;
+              bad |= !ok;
+              V.oent[o++] = ok ? f : k + 1;
+            }
+          });
+        }
+        run += wave_bcast(inc, 63);
+      }
+    }
+    if (lane == 0) V.optr[m] = run;
+    if (ballot64(bad) || run != in.nfw) {
+      sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+      return;
+    }
+  }
+  for (int k = lane; k < m; k += 64) V.head[k] = -1;
+  wave_fence();
+  // 3. incoming elements: one row each, gathered in rbuf and stored whole,
+  // queued on their least position
+  int npass = 0, e = 0;
+  bool bad3 = false;
+  for (int c = 0; c < 2; c++) {
+    int off = in.cst[c];
+    const int end = in.cst[c] + in.cin[c];
+    while (off < end) {
+      const int len = uni(src[off]);
+      const int r = m + e;
+      for (int w = lane; w < FW; w += 64) rbuf[w] = 0u;
+      wave_fence();
+      uint32_t fmin = 0xFFFFFFFFu;
+      each_record_pos(off, len, [&](int q) {
+        const int f = findex(q);
+        if (f < 0) {
+          bad3 = true;
+        } else {
+          atomicOr(&rbuf[f >> 5], 1u << (f & 31));
+          fmin = min(fmin, (uint32_t)f);
+        }
+      });
+      fmin = wave_min_u32(fmin);
+      wave_fence();
+      const gptr<uint32_t> row = V.rows + (long long)r * in.stride;
+      for (int w = lane; w < FW; w += 64) row[w] = rbuf[w];
+      if (fmin != 0xFFFFFFFFu) {
+        if ((int)fmin < m) {
+          if (lane == 0) {
+            V.next[r] = V.head[fmin];
+            V.head[fmin] = r;
+          }
+        } else {
+          if (lane == 0) V.outl[npass] = r;
+          npass++;
+        }
+      }
+      wave_fence();
+      e++;
+      off += 1 + len;
+    }
+  }
+  if (ballot64(bad3) || e != in.nce) {
+    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
+    return;
+  }
+  if (lane == 0) {
+    V.hdr[SH_M] = m;
+    V.hdr[SH_NBD] = nbd;
+    V.hdr[SH_NFW] = in.nfw;
+    V.hdr[SH_FW] = FW;
+    V.hdr[SH_ROWS] = in.rows;
+    V.hdr[SH_NCE] = in.nce;
+    V.hdr[SH_NP2] = np2;
+    V.hdr[SH_STRIDE] = in.stride;
+    V.hdr[SH_NOUT] = npass;
+    V.hdr[SH_OK] = 1;
+    M.sdesc[t] = (long long)(base - M.pool);
+  }
+}
+
 // lds / lwords: this wave's LDS slice, which holds the ancestor table and,
-// when it fits, the sorted later positions for the index lookups
+// when they fit, the later-position bitmap, its rank prefix and a row buffer
 __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds, int lwords) {
   gptr<FpCtl> C = M.ctl;
   const int m = uni(M.nsize[t]);
@@ -261,14 +468,17 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
   const int stride = (m + cap + 31) >> 5;
   const int rows = m + nce;
   const long long words = sym_words(m, cap, nfw, rows, stride);
-  gptr<unsigned> base = pool_alloc(M, (unsigned long long)(words + BW + 96));
+  // the bitmap, its rank prefix and a row buffer: in the LDS slice after
+  // the ancestor table when they fit, else in the pool after the scratch
+  const bool lmode = 96 + 2ll * BW + stride <= lwords;
+  const long long extra = lmode ? 0 : 2ll * BW + stride;
+  gptr<unsigned> base = pool_alloc(M, (unsigned long long)(words + extra + 96));
   if (!base) {  // pool_alloc raised the error
     sym_drop(M, t, 0);
     return;
   }
   const int np2 = cap;  // capacity of the later-position list
   const SymView V = sym_view(base, m, np2, nfw, rows);
-  gptr<uint32_t> bm = base.as<uint32_t>() + words;  // the bitmap
   int* anc = lds;  // per ancestor: begin, size, bit offset (at most 32 ancestors)
   if (lane_id() == 0) {
     int i = 0, off = 0;
@@ -284,190 +494,14 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
       }
     }
   }
-  for (int w = lane_id(); w < BW; w += 64) bm[w] = 0u;
   wave_fence();
-  // 1. mark the later positions of the child records and of t's own rows
-  bool bad1 = false;
-  auto mark = [&](int q) {
-    int lo = 0, hi = na - 1, f = -1;
-    while (lo <= hi) {  // nearest ancestor range starting at or before q
-      const int mid = (lo + hi) >> 1;
-      if (anc[3 * mid] <= q) {
-        f = mid;
-        lo = mid + 1;
-      } else {
-        hi = mid - 1;
-      }
-    }
-    if (f < 0 || q >= anc[3 * f] + anc[3 * f + 1]) {
-      bad1 = true;
-      return;
-    }
-    const int b = anc[3 * f + 2] + (q - anc[3 * f]);
-    atomicOr(&bm[b >> 5], 1u << (b & 31));
-  };
-  for (int c = 0; c < 2; c++) {
-    int off = cst[c];
-    const int end = cst[c] + cin[c];
-    while (off < end) {
-      const int len = uni(src[off]);
-      for (int i = lane_id(); i < len; i += 64) {
-        const int q = src[off + 1 + i];
-        if (q >= e0) mark(q);
-      }
-      off += 1 + len;
-    }
-  }
-  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
-    PrepRows R;
-    prep_rows(M, b0, m, k0, R);
-#pragma unroll
-    for (int u = 0; u < FP_PREP_COLS; u++)
-      prep_each(M, R, u, [&](int q) {
-        if (q >= e0) mark(q);
-      });
-  }
-  if (ballot64(bad1)) {
-    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
-    return;
-  }
-  wave_fence();
-  // read the bitmap back: positions in increasing order
-  int nbd = 0;
-  for (int w0 = 0; w0 < BW; w0 += 64) {
-    const int w = w0 + lane_id();
-    uint32_t x = w < BW ? bm[w] : 0u;
-    const int c = popc32(x);
-    const int inc = wave_incl_scan(c);
-    int o = nbd + inc - c;
-    while (x) {
-      const int b = w * 32 + __ffs(x) - 1;
-      x &= x - 1;
-      int lo = 0, hi = na - 1, f = 0;
-      while (lo <= hi) {  // the ancestor whose bit range holds b
-        const int mid = (lo + hi) >> 1;
-        if (anc[3 * mid + 2] <= b) {
-          f = mid;
-          lo = mid + 1;
-        } else {
-          hi = mid - 1;
-        }
-      }
-      if (o < np2) V.bd[o] = anc[3 * f] + (b - anc[3 * f + 2]);
-      o++;
-    }
-    nbd += wave_bcast(inc, 63);
-  }
-  if (nbd > np2) {
-    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
-    return;
-  }
-  wave_fence();
-  // the later positions again in LDS, for the binary searches below
-  int* lbd = lds + 96;
-  const bool bd_lds = nbd <= lwords - 96;
-  if (bd_lds)
-    for (int i = lane_id(); i < nbd; i += 64) lbd[i] = V.bd[i];
-  wave_fence();
-  const int F = m + nbd;
-  const int FW = (F + 31) >> 5;
-  // 2. forward rows in F indices
-  {
-    bool bad = false;
-    int run = 0;
-    for (int k1 = 0; k1 < m; k1 += 64 * FP_PREP_COLS) {
-      PrepRows R;
-      prep_rows(M, b0, m, k1, R);
-#pragma unroll
-      for (int u = 0; u < FP_PREP_COLS; u++) {
-        if (k1 + 64 * u >= m) break;
-        const int k = k1 + 64 * u + lane_id();
-        const int p = b0 + k;
-        int cnt = 0;
-        prep_each(M, R, u, [&](int q) { cnt += q > p; });
-        const int inc = wave_incl_scan(cnt);
-        int o = run + inc - cnt;
-        if (k < m) {
-          V.optr[k] = o;
-          prep_each(M, R, u, [&](int q) {
-            if (q > p) {
-              const int f = bd_lds ? sym_findex(q, b0, e0, m, (const int*)lbd, nbd)
-                                   : sym_findex(q, b0, e0, m, V.bd, nbd);
-              const bool ok = f > k && f < F;
-              bad |= !ok;
-              V.oent[o++] = ok ? f : k + 1;
-            }
-          });
-        }
-        run += wave_bcast(inc, 63);
-      }
-    }
-    if (lane_id() == 0) V.optr[m] = run;
-    if (ballot64(bad) || run != nfw) {
-      sym_drop(M, t, FP_SITE_SYM_LOOKUP);
-      return;
-    }
-  }
-  for (int k = lane_id(); k < m; k += 64) V.head[k] = -1;
-  wave_fence();
-  // 3. incoming elements: one row each, queued on their least position
-  int npass = 0, e = 0;
-  bool bad3 = false;
-  for (int c = 0; c < 2; c++) {
-    int off = cst[c];
-    const int end = cst[c] + cin[c];
-    while (off < end) {
-      const int len = uni(src[off]);
-      const int r = m + e;
-      gptr<uint32_t> row = V.rows + (long long)r * stride;
-      for (int w = lane_id(); w < FW; w += 64) row[w] = 0u;
-      wave_fence();
-      uint32_t fmin = 0xFFFFFFFFu;
-      for (int i = lane_id(); i < len; i += 64) {
-        const int q = src[off + 1 + i];
-        const int f = bd_lds ? sym_findex(q, b0, e0, m, (const int*)lbd, nbd)
-                             : sym_findex(q, b0, e0, m, V.bd, nbd);
-        if (f < 0) {
-          bad3 = true;
-        } else {
-          atomicOr(&row[f >> 5], 1u << (f & 31));
-          fmin = min(fmin, (uint32_t)f);
-        }
-      }
-      fmin = wave_min_u32(fmin);
-      wave_fence();
-      if (fmin != 0xFFFFFFFFu) {
-        if ((int)fmin < m) {
-          if (lane_id() == 0) {
-            V.next[r] = V.head[fmin];
-            V.head[fmin] = r;
-          }
-        } else {
-          if (lane_id() == 0) V.outl[npass] = r;
-          npass++;
-        }
-      }
-      wave_fence();
-      e++;
-      off += 1 + len;
-    }
-  }
-  if (ballot64(bad3) || e != nce) {
-    sym_drop(M, t, FP_SITE_SYM_LOOKUP);
-    return;
-  }
-  if (lane_id() == 0) {
-    V.hdr[SH_M] = m;
-    V.hdr[SH_NBD] = nbd;
-    V.hdr[SH_NFW] = nfw;
-    V.hdr[SH_FW] = FW;
-    V.hdr[SH_ROWS] = rows;
-    V.hdr[SH_NCE] = nce;
-    V.hdr[SH_NP2] = np2;
-    V.hdr[SH_STRIDE] = stride;
-    V.hdr[SH_NOUT] = npass;
-    V.hdr[SH_OK] = 1;
-    M.sdesc[t] = (long long)(base - M.pool);
+  const PrepIn in{m, b0, e0, na, BW, np2, nfw, nce, rows, stride, {cst[0], cst[1]}, {cin[0], cin[1]}};
+  if (lmode) {
+    uint32_t* l = (uint32_t*)(lds + 96);
+    sym_prep_tail(M, t, V, base, src, anc, in, l, l + BW, l + 2 * BW);
+  } else {
+    const gptr<uint32_t> g = base.as<uint32_t>() + words;
+    sym_prep_tail(M, t, V, base, src, anc, in, g, g + BW, g + 2 * BW);
   }
 }
 
