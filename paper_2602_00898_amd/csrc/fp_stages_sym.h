@@ -569,18 +569,18 @@ __device__ __forceinline__ uint32_t sym_word(const SymView& V, NP next, OP oent,
 // goes through memory.
 template <class IP>
 __device__ __forceinline__ void sym_elim_wide(const FpMesh& M, int t, const SymView& V, const int* h,
-                                              IP head, IP next, gptr<int> optr, gptr<int> oent) {
+                                              IP head, IP next, gptr<int> optr, gptr<int> oent,
+                                              int s0, int nout) {
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
   const int stride = h[SH_STRIDE];
   const int F = m + nbd;
-  int nout = h[SH_NOUT];
   const bool regs = FW <= 64 * FP_SYM_REGW;
   const int b0 = M.nbegin[t];
   uint32_t prev[FP_SYM_REGW];
 #pragma unroll
   for (int i = 0; i < FP_SYM_REGW; i++) prev[i] = 0u;
   int my_cc = 0, my_par = -1;  // column count and parent of column k with k % 64 == lane
-  for (int k = 0; k < m; k++) {
+  for (int k = s0; k < m; k++) {
     const int r0 = optr[k], r1 = optr[k + 1];
     const int q0 = head[k];
     gptr<uint32_t> rk = V.rows + (long long)k * stride;
@@ -655,7 +655,7 @@ __device__ __forceinline__ void sym_elim_wide(const FpMesh& M, int t, const SymV
     }
     if ((k & 63) == 63 || k == m - 1) {
       const int c = (k & ~63) + lane_id();
-      if (c <= k) {
+      if (c >= s0 && c <= k) {
         M.vcc[b0 + c] = my_cc;
         M.vpar[b0 + c] = my_par;
       }
@@ -666,151 +666,180 @@ __device__ __forceinline__ void sym_elim_wide(const FpMesh& M, int t, const SymV
 }
 
 // ---------------------------------------------------------------- chain
-// Most separator nodes eliminate as one chain: column k's parent is k + 1.
-// In a chain, column k's structure is every index b > k that some column
-// j <= k holds among its forward entries or incoming rows (an incoming row
-// joins at its least entry).  With intro(b) the least such column, the count
-// of column k is the number of b with intro(b) <= k < b: a difference array
-// and a prefix sum, all lanes at once.  The node is a chain exactly when
-// intro(k + 1) <= k for every k < m - 1 (by induction over k: then column
-// k's only child is k - 1), which is checked before anything is written; a
-// node that fails it takes the sequential elimination.
+// Most separator nodes eliminate as chains: column k's parent is k + 1.
+// Take a run of columns s.. that starts with nothing carried in (s = 0, or
+// column s - 1 has another parent).  While the run is a chain, column k's
+// structure is every index b > k that some column j in s..k holds among
+// its forward entries or queued rows (a row joins at the column it is
+// queued on).  With intro(b) the least such column, the run goes on through
+// column k + 1 exactly when intro(k + 1) <= k (by induction over k: column
+// k's parent is its least index above k), so the run ends at the first
+// column e whose test fails, or at m - 1.  The count of column k in s..e is
+// one plus the number of b with intro(b) <= k < b: a difference array and a
+// prefix sum, all lanes at once.  Column e's structure, the b > e with
+// intro(b) <= e, goes to its parent as a queued row (or leaves t), and the
+// next run starts at e + 1.  A node with many breaks hands the columns left
+// after FP_CHAIN_RUNS runs to the sequential walk.
 #define FP_CHAIN_MIN 32
-// intro (F words) and diff (m words): the wave's LDS slice or global scratch
+#ifndef FP_CHAIN_RUNS
+#define FP_CHAIN_RUNS 8
+#endif
+// intro (F words) and diff (m words): the wave's LDS slice or global scratch.
+// Returns the first column left for the sequential walk (m when done), or
+// -1 after raising an error; *nout receives the count of rows leaving t.
 template <class SP>
-__device__ __forceinline__ bool sym_elim_chain(const FpMesh& M, int t, const SymView& V,
-                                               const int* h, SP intro, SP diff) {
+__device__ __forceinline__ int sym_elim_chain(const FpMesh& M, int t, const SymView& V,
+                                              const int* h, SP intro, SP diff, int* nout_out) {
   const int m = h[SH_M], nbd = h[SH_NBD], rows = h[SH_ROWS], FW = h[SH_FW];
   const int stride = h[SH_STRIDE];
   const int F = m + nbd;
   const gptr<const int> optr = V.optr, oent = V.oent;
-  const gptr<const int> head = V.head, next = V.next;
+  const gptr<int> head = V.head, next = V.next;
   const int lane = lane_id();
-  for (int b = lane; b < F; b += 64) intro[b] = 0x7FFFFFFF;
-  wave_fence();
-  // forward entries, and incoming rows at the column they are queued on
-  bool bad = false;
-  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
-    PrepRows R;
-    csr_rows(optr, oent, 0, m, k0, R);
-#pragma unroll
-    for (int u = 0; u < FP_PREP_COLS; u++) {
-      const int k = k0 + lane + 64 * u;
-      csr_each(oent, R, u, [&](int f) {
-        if (f <= k || f >= F)
-          bad = true;
-        else
-          atomicMin(&intro[f], k);
-      });
-    }
-  }
-  // Incoming rows are few but wide (a child's last row holds most of its
-  // structure), so each is taken by the whole wave.  The columns with a
-  // queue are listed in diff first (cleared afterwards).
-  int nq = 0;
-  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
-    int hj[FP_PREP_COLS];
-#pragma unroll
-    for (int u = 0; u < FP_PREP_COLS; u++) {
-      const int k = k0 + lane + 64 * u;
-      hj[u] = k < m ? head[k] : -1;
-    }
-#pragma unroll
-    for (int u = 0; u < FP_PREP_COLS; u++) {
-      const uint64_t bal = ballot64(hj[u] >= 0);
-      if (hj[u] >= 0) diff[nq + popc64(bal & lanemask_lt())] = k0 + lane + 64 * u;
-      nq += popc64(bal);
-    }
-  }
-  wave_fence();
-  for (int q = 0; q < nq; q++) {
-    const int k = uni(diff[q]);
-    const int kw = k >> 5;
-    const uint32_t kmask = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
-    int j = uni(head[k]), steps = 0;
-    while (j >= m && j < rows && steps < rows) {
-      const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
-      for (int w = kw + lane; w < FW; w += 64) {
-        uint32_t x = rj[w];
-        if (w == kw) x &= kmask;
-        while (x) {
-          const int b = w * 32 + __ffs(x) - 1;
-          x &= x - 1;
-          if (b < F) atomicMin(&intro[b], k);
-        }
-      }
-      j = uni(next[j]);
-      steps++;
-    }
-    bad |= j >= 0;  // only incoming rows are queued before the elimination
-  }
-  wave_fence();
-  for (int k = lane; k < m; k += 64) diff[k] = 0;
-  if (ballot64(bad)) {
-    if (lane == 0) {
-      fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_LIVE, t);
-      V.hdr[SH_OK] = 0;
-    }
-    return true;
-  }
-  wave_fence();
-  // the chain test
-  for (int k = lane; k + 1 < m; k += 64) bad |= intro[k + 1] > k;
-  if (ballot64(bad)) return false;
-  // every b holds on the columns intro(b) .. b - 1 (the node's last column
-  // for a later position); the least later position held is the parent of
-  // the last column
-  // The +1 side aggregates runs of equal intro over consecutive lanes: the
-  // bits of one incoming row share their intro, and one atomic per run
-  // replaces up to 64 on the same LDS word.
-  uint32_t pl = 0xFFFFFFFFu;
-  for (int g = 0; g < F; g += 64) {
-    const int b = g + lane;
-    const int i = b < F ? intro[b] : 0x7FFFFFFF;
-    const bool v = i < m;
-    if (v && b < m) atomicAdd(&diff[b], -1);
-    if (v && b >= m) pl = min(pl, (uint32_t)b);
-    const int ip = __shfl_up(i, 1, 64);
-    const uint64_t heads = ballot64(lane == 0 || i != ip);
-    if (v && ((heads >> lane) & 1)) {
-      const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
-      atomicAdd(&diff[i], after ? __builtin_ctzll(after) + 1 : 64 - lane);
-    }
-  }
-  pl = wave_min_u32(pl);
-  wave_fence();
-  const int b0 = M.nbegin[t];
-  const int plast = pl != 0xFFFFFFFFu ? uni(V.bd[pl - m]) : -1;
-  int run = 0;
-  for (int k0 = 0; k0 < m; k0 += 64) {
-    const int k = k0 + lane;
-    const int c = k < m ? (int)diff[k] : 0;
-    const int inc = wave_incl_scan(c);
-    if (k < m) {
-      M.vcc[b0 + k] = 1 + run + inc;
-      M.vpar[b0 + k] = k + 1 < m ? b0 + k + 1 : plast;
-    }
-    run += wave_bcast(inc, 63);
-  }
-  // the last column's row leaves t when its parent is above
+  const int b0 = uni(M.nbegin[t]);
   int nout = h[SH_NOUT];
-  if (pl != 0xFFFFFFFFu) {
-    // 64 bits at a time from one ballot: words 2g and 2g + 1 of the row
-    const gptr<uint32_t> rl = V.rows + (long long)(m - 1) * stride;
-    const int g0 = m >> 6;
-    for (int w = lane; w < 2 * g0 && w < FW; w += 64) rl[w] = 0u;
-    for (int g = g0; 64 * g < F; g++) {
-      const int b = 64 * g + lane;
-      const uint64_t bal = ballot64(b >= m && b < F && intro[b] < m);
-      const int w = 2 * g + lane;
-      if (lane < 2 && w < FW) rl[w] = lane == 0 ? (uint32_t)bal : (uint32_t)(bal >> 32);
+  int s = 0;
+  for (int run_no = 0; run_no < FP_CHAIN_RUNS && s < m; run_no++) {
+    for (int b = s + lane; b < F; b += 64) intro[b] = 0x7FFFFFFF;
+    wave_fence();
+    // forward entries of the columns s..
+    bool bad = false;
+    for (int k0 = s; k0 < m; k0 += 64 * FP_PREP_COLS) {
+      PrepRows R;
+      csr_rows(optr, oent, 0, m, k0, R);
+#pragma unroll
+      for (int u = 0; u < FP_PREP_COLS; u++) {
+        const int k = k0 + lane + 64 * u;
+        csr_each(oent, R, u, [&](int f) {
+          if (f <= k || f >= F)
+            bad = true;
+          else
+            atomicMin(&intro[f], k);
+        });
+      }
     }
-    if (lane == 0) V.outl[nout] = m - 1;
-    nout++;
+    // Queued rows are few but wide (a child's last row holds most of its
+    // structure), so each is taken by the whole wave.  The columns with a
+    // queue are listed in diff first (cleared afterwards).
+    int nq = 0;
+    for (int k0 = s; k0 < m; k0 += 64 * FP_PREP_COLS) {
+      int hj[FP_PREP_COLS];
+#pragma unroll
+      for (int u = 0; u < FP_PREP_COLS; u++) {
+        const int k = k0 + lane + 64 * u;
+        hj[u] = k < m ? head[k] : -1;
+      }
+#pragma unroll
+      for (int u = 0; u < FP_PREP_COLS; u++) {
+        const uint64_t bal = ballot64(hj[u] >= 0);
+        if (hj[u] >= 0) diff[nq + popc64(bal & lanemask_lt())] = k0 + lane + 64 * u;
+        nq += popc64(bal);
+      }
+    }
+    wave_fence();
+    for (int q = 0; q < nq; q++) {
+      const int k = uni(diff[q]);
+      const int kw = k >> 5;
+      const uint32_t kmask = (k & 31) == 31 ? 0u : (0xFFFFFFFFu << ((k & 31) + 1));
+      int j = uni(head[k]), steps = 0;
+      while (j >= 0 && j < rows && steps < rows) {
+        const gptr<const uint32_t> rj = V.rows + (long long)j * stride;
+        for (int w = kw + lane; w < FW; w += 64) {
+          uint32_t x = rj[w];
+          if (w == kw) x &= kmask;
+          while (x) {
+            const int b = w * 32 + __ffs(x) - 1;
+            x &= x - 1;
+            if (b < F) atomicMin(&intro[b], k);
+          }
+        }
+        j = uni(next[j]);
+        steps++;
+      }
+      bad |= j >= 0;  // a queue that leaves the rows or does not end
+    }
+    wave_fence();
+    for (int k = lane; k < m; k += 64) diff[k] = 0;
+    if (ballot64(bad)) {
+      if (lane == 0) {
+        fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_SYM_LIVE, t);
+        V.hdr[SH_OK] = 0;
+      }
+      return -1;
+    }
+    wave_fence();
+    // the run's last column: the first k >= s with intro(k + 1) > k
+    int e = m - 1;
+    for (int k0 = s; k0 + 1 < m; k0 += 64) {
+      const int k = k0 + lane;
+      const uint64_t br = ballot64(k + 1 < m && intro[k + 1] > k);
+      if (br) {
+        e = k0 + __builtin_ctzll(br);
+        break;
+      }
+    }
+    // every b with intro(b) in s..e holds on the columns intro(b) .. b - 1,
+    // or up to e; the least such b above e is the parent of e.  The +1 side
+    // aggregates runs of equal intro over consecutive lanes: the bits of one
+    // queued row share their intro, and one atomic per run replaces up to 64
+    // on the same LDS word.
+    uint32_t pl = 0xFFFFFFFFu;
+    for (int g = s; g < F; g += 64) {
+      const int b = g + lane;
+      const int i = b < F ? intro[b] : 0x7FFFFFFF;
+      const bool v = i <= e;  // intro(b) >= s for every b marked in this run
+      if (v && b <= e) atomicAdd(&diff[b], -1);
+      if (v && b > e) pl = min(pl, (uint32_t)b);
+      const int ip = __shfl_up(i, 1, 64);
+      const uint64_t heads = ballot64(lane == 0 || i != ip);
+      if (v && ((heads >> lane) & 1)) {
+        const uint64_t after = lane == 63 ? 0ull : heads >> (lane + 1);
+        atomicAdd(&diff[i], after ? __builtin_ctzll(after) + 1 : 64 - lane);
+      }
+    }
+    pl = wave_min_u32(pl);
+    wave_fence();
+    const int pe = pl == 0xFFFFFFFFu ? -1 : (int)pl < m ? b0 + (int)pl : uni(V.bd[pl - m]);
+    int acc = 0;
+    for (int k0 = s; k0 <= e; k0 += 64) {
+      const int k = k0 + lane;
+      const int c = k <= e ? (int)diff[k] : 0;
+      const int inc = wave_incl_scan(c);
+      if (k <= e) {
+        M.vcc[b0 + k] = 1 + acc + inc;
+        M.vpar[b0 + k] = k < e ? b0 + k + 1 : pe;
+      }
+      acc += wave_bcast(inc, 63);
+    }
+    if (pl != 0xFFFFFFFFu) {
+      // the row of e, 64 bits at a time from one ballot: words 2g, 2g + 1
+      const gptr<uint32_t> rl = V.rows + (long long)e * stride;
+      const int g0 = (e + 1) >> 6;
+      for (int w = lane; w < 2 * g0 && w < FW; w += 64) rl[w] = 0u;
+      for (int g = g0; 64 * g < F; g++) {
+        const int b = 64 * g + lane;
+        const uint64_t bal = ballot64(b > e && b < F && intro[b] <= e);
+        const int w = 2 * g + lane;
+        if (lane < 2 && w < FW) rl[w] = lane == 0 ? (uint32_t)bal : (uint32_t)(bal >> 32);
+      }
+      if ((int)pl < m) {
+        if (lane == 0) {  // queued on its parent, a column of a later run
+          next[e] = head[pl];
+          head[pl] = e;
+        }
+      } else {
+        if (lane == 0) V.outl[nout] = e;
+        nout++;
+      }
+    }
+    // the queue links and the row reach every lane (the next run, or the
+    // sequential walk, reads them)
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+    s = e + 1;
   }
-  wave_fence();
+  *nout_out = nout;
   if (lane == 0) V.hdr[SH_NOUT] = nout;
-  return true;
+  return s;
 }
 
 // The sequential walk over a node's columns, rows of up to 64 NW words
@@ -821,12 +850,11 @@ template <int NW, class IP>
 __device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymView& V,
                                               const int* h, IP head, IP next,
                                               const gptr<int> optr, const gptr<int> oent,
-                                              uint32_t* rb) {
+                                              uint32_t* rb, int s0, int nout) {
   constexpr bool kRb = std::is_same<IP, int*>::value;
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
   const int stride = h[SH_STRIDE];
   const int F = m + nbd;
-  int nout = h[SH_NOUT];
   // Columns go in blocks of 64.  A block's queue heads, row pointers and
   // forward entries are read once into registers (lane i holds column k0+i),
   // and a column whose parent is the next column hands its row over in
@@ -844,7 +872,7 @@ __device__ __forceinline__ void sym_elim_cols(const FpMesh& M, int t, const SymV
   int pfj = -1;
 #pragma unroll
   for (int i = 0; i < NW; i++) pf[i] = 0u;
-  for (int k0 = 0; k0 < m; k0 += 64) {
+  for (int k0 = s0; k0 < m; k0 += 64) {
     const int kn = min(64, m - k0);
     int hreg = lane < kn ? head[k0 + lane] : -1;
     const int oreg = lane < kn ? optr[k0 + lane] : 0;
@@ -1061,16 +1089,19 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
                                              const int* h, int* lds, long long lds_words) {
   const int m = h[SH_M], nbd = h[SH_NBD], FW = h[SH_FW], rows = h[SH_ROWS];
   const int F = m + nbd;
-  // a chain node first (section above): its arrays in the LDS slice when they
-  // fit, else in pool scratch
+  // chain runs first (section above): their arrays in the LDS slice when
+  // they fit, else in pool scratch; the sequential walk takes the columns
+  // they leave
+  int s0 = 0, nout = h[SH_NOUT];
   if (m >= FP_CHAIN_MIN && rows > m) {  // a node with no incoming rows is a leaf
     if (kLds && (long long)F + m <= lds_words) {
-      if (sym_elim_chain(M, t, V, h, lds, lds + F)) return;
+      s0 = sym_elim_chain(M, t, V, h, lds, lds + F, &nout);
     } else {
       const gptr<unsigned> sc = pool_alloc(M, (unsigned long long)F + m + 64);
       if (!sc) return;  // pool_alloc raised the error
-      if (sym_elim_chain(M, t, V, h, sc.as<int>(), sc.as<int>() + F)) return;
+      s0 = sym_elim_chain(M, t, V, h, sc.as<int>(), sc.as<int>() + F, &nout);
     }
+    if (s0 < 0 || s0 >= m) return;
   }
   // queue links: the wave's LDS slice, or global memory; the forward rows
   // are read from global memory once per block of 64 columns
@@ -1090,15 +1121,15 @@ __device__ __forceinline__ void sym_elim_run(const FpMesh& M, int t, const SymVi
     wave_fence();
   }
   if (FW > 64 * FP_SYM_REGW) {
-    sym_elim_wide(M, t, V, h, head, next, optr, oent);
+    sym_elim_wide(M, t, V, h, head, next, optr, oent, s0, nout);
     return;
   }
   if (FW <= 64)
-    sym_elim_cols<1>(M, t, V, h, head, next, optr, oent, rb);
+    sym_elim_cols<1>(M, t, V, h, head, next, optr, oent, rb, s0, nout);
   else if (FW <= 128)
-    sym_elim_cols<2>(M, t, V, h, head, next, optr, oent, rb);
+    sym_elim_cols<2>(M, t, V, h, head, next, optr, oent, rb, s0, nout);
   else
-    sym_elim_cols<4>(M, t, V, h, head, next, optr, oent, rb);
+    sym_elim_cols<4>(M, t, V, h, head, next, optr, oent, rb, s0, nout);
 }
 
 // LDS words of a node's elimination: the chain form's intro and diff
