@@ -1087,11 +1087,17 @@ fp_status run_job(Job& J) {
       FPL(k_top_count, B(n), T, 0, st, dm, d);
       FPL(k_top_place, dim3(1), dim3(64), 0, st, dm, d);
       FPL(k_top_scatter, B(n), T, 0, st, dm, d);
+      // one stream per level, so a level does not wait for the one above;
+      // the large local-order classes follow on the second and third
+      hipStream_t sd = d == 0 ? J.h->side : d == 1 ? J.h->side2 : J.h->side3;
       if (hipEventRecord(J.h->ev_top[d], st) != hipSuccess ||
-          hipStreamWaitEvent(J.h->side, J.h->ev_top[d], 0) != hipSuccess)
+          hipStreamWaitEvent(sd, J.h->ev_top[d], 0) != hipSuccess)
         J.hip_failed = true;
-      J.side_open = true;
-      FPL(k_md_top, dim3(1 << d), dim3(64), J.h->lds_big, J.h->side, dm, d);
+      if (d == 0)
+        J.side_open = true;
+      else
+        J.side2_open = true;
+      FPL(k_md_top, dim3(1 << d), dim3(64), J.h->lds_big, sd, dm, d);
     }
     J.check();
   }
@@ -1115,8 +1121,10 @@ fp_status run_job(Job& J) {
   FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
   FPL(k_md_tasks, B(nn), T, 0, st, dm, nn, ntop);
   {
-    // the two large classes on streams of their own, the two small ones
-    // here one after the other: the classes' tails overlap
+    // The largest class (one wave per CU, the longest nodes) goes first on
+    // this stream, so its workgroups take their CUs before the others fill
+    // the rest; class 1 follows the depth-1 orders on the second side
+    // stream, classes 2 and 3 the depth-2 orders on the third.
     const bool two = J.h->side_ok && ensure_side(J.h);
     if (two) {
       if (hipEventRecord(J.h->ev_md, st) != hipSuccess ||
@@ -1126,7 +1134,7 @@ fp_status run_job(Job& J) {
       J.side2_open = true;
     }
     for (int c = 0; c < FP_MD_CLASSES; c++) {
-      hipStream_t sc = !two || c >= 2 ? st : c == 0 ? J.h->side2 : J.h->side3;
+      hipStream_t sc = !two || c == 0 ? st : c == 1 ? J.h->side2 : J.h->side3;
       FPL(k_md, dim3(2 * J.h->ncu), T, c == 3 ? J.h->lds_bytes : J.h->lds_big, sc, dm, c);
     }
   }

@@ -8,7 +8,7 @@
 #define FP_WG 256                // threads per workgroup
 #define FP_WAVES (FP_WG / 64)    // waves per workgroup
 #define FP_LDS_BYTES (64 * 1024) // dynamic LDS of the per-node kernels
-#define FP_TOP_LEVELS 1          // tree levels whose separators are ordered early (at most 3)
+#define FP_TOP_LEVELS 3          // tree levels whose separators are ordered early (at most 3)
 
 // error bits raised on the device; surfaced by fp_get_error
 #define FP_E_INDEX 0x1u       // column index out of range
