@@ -831,9 +831,9 @@ fp_status map_err(unsigned e) {
 #define FP_LAUNCH_(JOB, k, g, b, l, s, ...)                 \
   do {                                                     \
     const bool tk_ = (JOB).tk(#k);                         \
-    if (tk_) (JOB).tk_begin();                             \
+    if (tk_) (JOB).tk_begin(s);                            \
     hipLaunchKernelGGL(k, g, b, l, s, __VA_ARGS__);        \
-    if (tk_) (JOB).tk_end();                               \
+    if (tk_) (JOB).tk_end(s);                              \
   } while (0)
 #define FPLM(...) FP_LAUNCH_(*this, __VA_ARGS__)
 #define FPL(...) FP_LAUNCH_(J, __VA_ARGS__)
@@ -869,7 +869,8 @@ struct Job {
 
   // timing of one kernel (fp_time_kernel): events around each of its launches
   bool tk(const char* name) const { return h->tk_name[0] && strcmp(h->tk_name, name) == 0; }
-  void tk_begin() {
+  // the events go on the launch's own stream
+  void tk_begin(hipStream_t ls) {
     if ((int)h->tk_ev.size() < 2 * (h->tk_n + 1)) {
       hipEvent_t a, b;
       if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
@@ -879,11 +880,11 @@ struct Job {
       h->tk_ev.push_back(a);
       h->tk_ev.push_back(b);
     }
-    if (hipEventRecord(h->tk_ev[2 * h->tk_n], st) != hipSuccess) h->tk_failed = true;
+    if (hipEventRecord(h->tk_ev[2 * h->tk_n], ls) != hipSuccess) h->tk_failed = true;
   }
-  void tk_end() {
+  void tk_end(hipStream_t ls) {
     if ((int)h->tk_ev.size() < 2 * (h->tk_n + 1)) return;
-    if (hipEventRecord(h->tk_ev[2 * h->tk_n + 1], st) != hipSuccess) h->tk_failed = true;
+    if (hipEventRecord(h->tk_ev[2 * h->tk_n + 1], ls) != hipSuccess) h->tk_failed = true;
     h->tk_n++;
   }
 
