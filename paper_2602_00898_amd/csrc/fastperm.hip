@@ -587,7 +587,7 @@ __global__ void k_md_tasks(const FpMesh* __restrict__ Mp, int nn, int ntop) {
   for (int x = gtid(); x < nn; x += gsize()) {
     const int m = M.nsize[x];
     if (m == 0 || (x < ntop && C->tearly[x])) continue;  // top separators ordered already
-    const int c = md_class(m, M.lds_bytes, M.lds_big);
+    const int c = md_class(m, M.lds_bytes, M.lds_md);
     M.tasks[c * M.NNcap + atomicAdd(&C->task_cnt[c], 1)] = x;
   }
 }
@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
   MESH;
   FP_LDS_DECL;
   const int nsl = md_slice_waves(c);
-  const long long sb = uni(md_slice_bytes(c, M.lds_bytes, M.lds_big));
+  const long long sb = uni(md_slice_bytes(c, M.lds_bytes, M.lds_md));
   const int cnt = uni(C->task_cnt[c]);
   if (wave_id() >= nsl) return;
   char* slice = fp_lds + sb * wave_id();
@@ -672,7 +672,7 @@ __global__ void __launch_bounds__(64) k_md_top(const FpMesh* __restrict__ Mp, in
     if (lane_id() == 0) fp_fail(C, FP_E_INTERNAL, FP_SITE_TOP, t);
     return;
   }
-  md_node_list(M, t, M.tbuf + off, m, pos0, fp_lds, uni(M.lds_big));
+  md_node_list(M, t, M.tbuf + off, m, pos0, fp_lds, uni(M.lds_md));
 }
 // the schedule's ranges must be the ones the early orders took
 __global__ void k_top_check(const FpMesh* __restrict__ Mp, int ntop) {
@@ -1075,11 +1075,14 @@ fp_status run_job(Job& J) {
     FPL(k_arcs, B(n), T, 0, st, dm);
     {
       // LDS for the local quotient subgraphs: a node at depth d holds at most
-      // 2^(D-d) patches; about 8 alive arcs per patch, capped below the large
-      // LDS (the kernel's static LDS comes on top)
+      // 2^(D-d) patches.  While the level has no more nodes than CUs, each
+      // workgroup takes the large LDS (quotient degrees can pass 8); deeper,
+      // about 8 alive arcs per patch, so several workgroups share a CU.  The
+      // kernel's static LDS comes on top.
       const long long cap = 1ll << (D - d);
-      const int lb =
-          (int)std::min<long long>(J.h->lds_big - 1024, (4 * (13 * cap + 1) + 255) & ~255ll);
+      const long long want =
+          (1ll << d) <= J.h->ncu ? J.h->lds_big : (4 * (13 * cap + 1) + 255) & ~255ll;
+      const int lb = (int)std::min<long long>(J.h->lds_big - 1024, want);
       FPL(k_bisect, dim3(std::min(1 << d, 4 * J.h->ncu)), T, lb, st, dm, d, lb);
     }
     FPL(k_cand, B(n), T, 0, st, dm, d);
@@ -1098,7 +1101,7 @@ fp_status run_job(Job& J) {
         J.side_open = true;
       else
         J.side2_open = true;
-      FPL(k_md_top, dim3(1 << d), dim3(64), J.h->lds_big, sd, dm, d);
+      FPL(k_md_top, dim3(1 << d), dim3(64), J.h->lds_md, sd, dm, d);
     }
     J.check();
   }
@@ -1136,7 +1139,7 @@ fp_status run_job(Job& J) {
     }
     for (int c = 0; c < FP_MD_CLASSES; c++) {
       hipStream_t sc = !two || c == 0 ? st : c == 1 ? J.h->side2 : J.h->side3;
-      FPL(k_md, dim3(2 * J.h->ncu), T, c == 3 ? J.h->lds_bytes : J.h->lds_big, sc, dm, c);
+      FPL(k_md, dim3(2 * J.h->ncu), T, c == 3 ? J.h->lds_bytes : J.h->lds_md, sc, dm, c);
     }
   }
   J.join_side();
@@ -1213,20 +1216,28 @@ void fp_options_default(fp_options* o) {
 // LDS of the one-wave kernels for large nodes: what one workgroup may hold
 // on this device (160 KB on gfx950), at least the per-node size
 static int big_lds(int device) {
-  int lim = 0;
+  // the default per-workgroup limit, or more where a kernel opts in (CDNA4:
+  // 160 KB of LDS per CU, all of it to one workgroup)
+  int lim = 0, optin = 0;
   if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, device) !=
       hipSuccess) {
     (void)hipGetLastError();
     return FP_LDS_BYTES;
   }
+  if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, device) ==
+      hipSuccess)
+    lim = std::max(lim, optin);
+  else
+    (void)hipGetLastError();
   const int big = std::min(lim, 160 * 1024) & ~15;
   if (big <= FP_LDS_BYTES) return FP_LDS_BYTES;
   if (hipFuncSetAttribute((const void*)k_md, hipFuncAttributeMaxDynamicSharedMemorySize, big) !=
           hipSuccess ||
       hipFuncSetAttribute((const void*)k_md_top, hipFuncAttributeMaxDynamicSharedMemorySize,
                           big) != hipSuccess ||
+      // the bisection keeps 1 KB for its static LDS
       hipFuncSetAttribute((const void*)k_bisect, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          big) != hipSuccess ||
+                          big - 1024) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_sym_elim, hipFuncAttributeMaxDynamicSharedMemorySize,
                           big) != hipSuccess) {
     (void)hipGetLastError();
@@ -1251,6 +1262,7 @@ fp_status fp_create(fp_handle** h) {
   H->ncu = std::max(1, ncu);
   H->lds_bytes = FP_LDS_BYTES;
   H->lds_big = big_lds(H->device);
+  H->lds_md = std::min(H->lds_big, FP_MD_LDS);
   H->side_ok = true;
   H->tk_name[0] = 0;
   H->tk_n = 0;
@@ -1347,6 +1359,7 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   M.max_nodes_out = out->max_nodes;
   M.lds_bytes = h->lds_bytes;
   M.lds_big = h->lds_big;
+  M.lds_md = h->lds_md;
   J.ctl = M.ctl;
   J.dm = (const FpMesh*)(ws + P.o_mesh);
   J.timing = (opts->flags & FP_FLAG_TIMING) != 0;

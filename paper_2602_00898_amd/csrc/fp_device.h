@@ -8,6 +8,9 @@
 #define FP_WG 256                // threads per workgroup
 #define FP_WAVES (FP_WG / 64)    // waves per workgroup
 #define FP_LDS_BYTES (64 * 1024) // dynamic LDS of the per-node kernels
+// large LDS of the local orders: two such workgroups share a CU, which
+// measured faster than one wave per CU holding the whole 160 KB
+#define FP_MD_LDS (64 * 1024)
 #define FP_TOP_LEVELS 3          // tree levels whose separators are ordered early (at most 3)
 
 // error bits raised on the device; surfaced by fp_get_error

@@ -24,6 +24,7 @@ struct fp_handle {
   int ncu;
   int lds_bytes;
   int lds_big;
+  int lds_md;  // the local orders' large LDS (at most FP_MD_LDS)
   int* host;  // pinned: scalars read back between stages, and the job copy
   // second stream: local orders of the top separators, started while the
   // separator tree is still being built; events order it after the call's

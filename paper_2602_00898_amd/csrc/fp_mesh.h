@@ -157,6 +157,7 @@ struct FpMesh {
   int NNcap;      // capacity of heap arrays
   int lds_bytes;  // dynamic LDS of the per-node kernels
   int lds_big;    // LDS of the one-wave kernels for large nodes (>= lds_bytes)
+  int lds_md;     // LDS of the local orders' large classes (<= lds_big)
   // workspace
   gptr<FpCtl> ctl;
   gptr<int> grp;       // n+1
