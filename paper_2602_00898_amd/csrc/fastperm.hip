@@ -582,13 +582,39 @@ __global__ void k_scatter(const FpMesh* __restrict__ Mp) {
 // ==========================================================================
 // local orders (Sec. 4.3 Step 4): one wave per node, LDS slice per wave
 // ==========================================================================
-__global__ void k_md_tasks(const FpMesh* __restrict__ Mp, int nn, int ntop) {
+// Task lists of the local orders, one per size class, largest nodes first
+// (a counting sort on size / 16, one workgroup): a class with more nodes
+// than resident slots then ends with its smallest nodes, not its largest.
+#define FP_TASK_BUCKETS 256
+__global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ Mp, int nn, int ntop) {
   MESH;
-  for (int x = gtid(); x < nn; x += gsize()) {
+  __shared__ int hist[FP_MD_CLASSES * FP_TASK_BUCKETS];
+  for (int i = threadIdx.x; i < FP_MD_CLASSES * FP_TASK_BUCKETS; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  auto key = [&](int x) -> int {  // class * buckets + bucket, or -1
     const int m = M.nsize[x];
-    if (m == 0 || (x < ntop && C->tearly[x])) continue;  // top separators ordered already
+    if (m == 0 || (x < ntop && C->tearly[x])) return -1;  // top separators ordered already
     const int c = md_class(m, M.lds_bytes, M.lds_md);
-    M.tasks[c * M.NNcap + atomicAdd(&C->task_cnt[c], 1)] = x;
+    return c * FP_TASK_BUCKETS + (FP_TASK_BUCKETS - 1) - min(m >> 4, FP_TASK_BUCKETS - 1);
+  };
+  for (int x = threadIdx.x; x < nn; x += blockDim.x) {
+    const int k = key(x);
+    if (k >= 0) atomicAdd(&hist[k], 1);
+  }
+  __syncthreads();
+  if (threadIdx.x < FP_MD_CLASSES) {
+    int run = 0;
+    for (int b = 0; b < FP_TASK_BUCKETS; b++) {
+      const int v = hist[threadIdx.x * FP_TASK_BUCKETS + b];
+      hist[threadIdx.x * FP_TASK_BUCKETS + b] = run;
+      run += v;
+    }
+    C->task_cnt[threadIdx.x] = run;
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < nn; x += blockDim.x) {
+    const int k = key(x);
+    if (k >= 0) M.tasks[(k / FP_TASK_BUCKETS) * M.NNcap + atomicAdd(&hist[k], 1)] = x;
   }
 }
 __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int c) {
@@ -1123,7 +1149,7 @@ fp_status run_job(Job& J) {
   // local orders
   J.mark(5);
   FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
-  FPL(k_md_tasks, B(nn), T, 0, st, dm, nn, ntop);
+  FPL(k_md_tasks, dim3(1), dim3(1024), 0, st, dm, nn, ntop);
   {
     // The largest class (one wave per CU, the longest nodes) goes first on
     // this stream, so its workgroups take their CUs before the others fill
