@@ -947,16 +947,33 @@ struct Job {
     check();
   }
   // frontier BFS from the level-0 frontier already in place; levels are
-  // launched in batches of 8, then the next frontier size is read back
+  // launched in batches of 8.  The next batch is queued before the host
+  // looks at the frontier size the previous one left, so the GPU never
+  // waits for that round trip; a batch queued past the last level finds
+  // empty frontiers and returns at once.
   void bfs() {
     const int n = hm.n;
-    // a BFS has fewer than n levels: levels up to n+7 read counters that stay
-    // zero (the counter array holds n+16 entries)
-    for (int lvl = 0;; lvl += 8) {
+    // a BFS has fewer than n levels: levels up to n+15 read counters that
+    // stay zero (the counter array holds n+16 entries)
+    auto batch = [&](int lvl) {
       for (int k = 0; k < 8; k++)
         FPLM(k_bfs_level, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, lvl + k);
       check();
-      if (lvl + 8 > n || hip_failed || read1(&hm.fcnt[lvl + 8]) == 0) break;
+    };
+    batch(0);
+    for (int lvl = 0; lvl + 8 <= n && !hip_failed; lvl += 8) {
+      if (hipMemcpyAsync(h->host + 1, hm.fcnt + lvl + 8, 4, hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
+          hipEventRecord(h->ev_bfs, st) != hipSuccess) {
+        hip_failed = true;
+        break;
+      }
+      batch(lvl + 8);
+      if (hipEventSynchronize(h->ev_bfs) != hipSuccess) {
+        hip_failed = true;
+        break;
+      }
+      if (h->host[1] == 0) break;
     }
   }
   void grow(int nseeds) {
@@ -1300,6 +1317,12 @@ fp_status fp_create(fp_handle** h) {
       delete H;
       return FP_ERR_HIP;
     }
+  if (hipEventCreateWithFlags(&H->ev_bfs, hipEventDisableTiming) != hipSuccess) {
+    for (int j = 0; j <= FP_NSTAGE; j++) (void)hipEventDestroy(H->ev[j]);
+    (void)hipHostFree(H->host);
+    delete H;
+    return FP_ERR_HIP;
+  }
   H->side = nullptr;  // created by the first call that uses it
   H->side2 = nullptr;
   H->side3 = nullptr;
@@ -1326,6 +1349,7 @@ fp_status fp_destroy(fp_handle* h) {
   }
   for (hipEvent_t e : h->tk_ev) (void)hipEventDestroy(e);
   for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);
+  (void)hipEventDestroy(h->ev_bfs);
   if (h->host) (void)hipHostFree(h->host);
   delete h;
   return FP_OK;

@@ -39,6 +39,7 @@ struct fp_handle {
   hipEvent_t ev_top[3];
   hipEvent_t ev_join;
   hipEvent_t ev[FP_NSTAGE + 1];
+  hipEvent_t ev_bfs;  // a BFS frontier size has reached the host buffer
   bool timed;  // the last call recorded stage events
   std::mutex lanes_mu;
   std::vector<FpLane> lanes;  // created on demand by the batched calls
