@@ -257,28 +257,45 @@ __global__ void k_lloyd_gmap(const FpMesh* __restrict__ Mp, int P) {
   for (int p = gtid(); p < P; p += gsize()) M.best[p] = 0;
   for (int i = gtid(); i < M.n + 16; i += gsize()) M.fcnt[i] = 0;
 }
+// (the loops below step a whole workgroup at a time: wg_append holds a
+// barrier, and a single list counter takes one atomic per workgroup)
 __global__ void k_lloyd_bnd(const FpMesh* __restrict__ Mp) {
   MESH;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
-    const int v = v0 + lane_id();
+  __shared__ int lds2[2];
+  for (int v0 = (int)(blockIdx.x * blockDim.x); v0 < M.n; v0 += (int)(gridDim.x * blockDim.x)) {
+    const int v = v0 + (int)threadIdx.x;
     bool isb = false;
     if (v < M.n) {
       const int g = M.gmap[v];
       for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
       M.key[v] = isb ? 0ull : FP_UNSET;
     }
-    const int slot = wave_append(&M.fcnt[0], isb);
+    const int slot = wg_append(&M.fcnt[0], isb, lds2);
     if (isb) M.fa[slot] = v;
   }
 }
+// per patch, the candidate of largest distance (least vertex on ties); the
+// lanes of a wave that share a patch take their maximum first, so a patch
+// gets one atomic per wave instead of one per vertex
 __global__ void k_lloyd_best(const FpMesh* __restrict__ Mp) {
   MESH;
-  for (int v = gtid(); v < M.n; v += gsize()) {
-    const unsigned long long k = M.key[v];
-    if (k == FP_UNSET) continue;
+  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+    const int v = v0 + lane_id();
+    const unsigned long long k = v < M.n ? M.key[v] : FP_UNSET;
+    const bool act = k != FP_UNSET;
     const unsigned long long cand =
-        ((k >> 32) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)v) | (1ull << 63);
-    atomicMax(&M.best[M.gmap[v]], cand);
+        act ? (((k >> 32) << 32) | (unsigned long long)(0xFFFFFFFFu - (unsigned)v) | (1ull << 63))
+            : 0ull;
+    const int g = act ? M.gmap[v] : -1;
+    uint64_t pend = ballot64(act);
+    while (pend) {
+      const int l = __builtin_ctzll(pend);
+      const int kg = wave_bcast(g, l);
+      const uint64_t same = ballot64(g == kg) & pend;
+      const unsigned long long mx = wave_max_u64(((same >> lane_id()) & 1ull) ? cand : 0ull);
+      if (lane_id() == l) atomicMax(&M.best[kg], mx);
+      pend &= ~same;
+    }
   }
 }
 __global__ void k_lloyd_seed(const FpMesh* __restrict__ Mp, int P) {
@@ -319,15 +336,16 @@ __global__ void k_user_gmap(const FpMesh* __restrict__ Mp) {
 // ==========================================================================
 __global__ void k_patch_count(const FpMesh* __restrict__ Mp) {
   MESH;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
-    const int v = v0 + lane_id();
+  __shared__ int lds2[2];
+  for (int v0 = (int)(blockIdx.x * blockDim.x); v0 < M.n; v0 += (int)(gridDim.x * blockDim.x)) {
+    const int v = v0 + (int)threadIdx.x;
     const bool act = v < M.n;
     const int g = act ? M.gmap[v] : 0;
     bool isb = false;
     if (act)
       for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
     (void)wave_append_keyed(M.pcnt, g, act);
-    const int slot = wave_append(&C->nbnd, isb);
+    const int slot = wg_append(&C->nbnd, isb, lds2);
     if (isb) M.bnd[slot] = v;
   }
 }

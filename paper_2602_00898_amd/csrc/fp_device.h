@@ -184,6 +184,26 @@ __device__ __forceinline__ int wave_append(P ctr, bool pred) {
   return base + popc64(bal & lanemask_lt());
 }
 
+// Append for a whole workgroup: one global atomic per workgroup and call.
+// Every thread of the workgroup must call it (a barrier inside); lds2 is two
+// ints of LDS the workgroup owns.
+template <class P>
+__device__ __forceinline__ int wg_append(P ctr, bool pred, int* lds2) {
+  const uint64_t bal = ballot64(pred);
+  const int c = popc64(bal);
+  if (threadIdx.x == 0) lds2[0] = 0;
+  __syncthreads();
+  int off = 0;
+  if (lane_id() == 0 && c) off = atomicAdd(&lds2[0], c);
+  off = wave_bcast(off, 0);
+  __syncthreads();
+  if (threadIdx.x == 0) lds2[1] = lds2[0] ? atomicAdd(ctr, lds2[0]) : 0;
+  __syncthreads();
+  const int base = lds2[1];
+  __syncthreads();  // lds2 is free again for the next call
+  return base + off + popc64(bal & lanemask_lt());
+}
+
 // Same for per-key counters ctr[key]: one atomic per distinct key present
 // in the wave (mesh vertices of a wave mostly share a few patches or nodes).
 template <class P>
