@@ -790,12 +790,20 @@ __global__ void k_prow_fill(const FpMesh* __restrict__ Mp) {
     for (int e = M.grp[v]; e < M.grp[v + 1]; e++) M.pent[o++] = M.viperm[M.gci[e]];
   }
 }
-__global__ void k_nnzl(const FpMesh* __restrict__ Mp) {
+// nnz(L): the column counts summed per workgroup, one atomic each
+__global__ void __launch_bounds__(FP_WG) k_nnzl(const FpMesh* __restrict__ Mp) {
   MESH;
+  __shared__ long long part[FP_WAVES];
   long long s = 0;
   for (int i = gtid(); i < M.n; i += gsize()) s += M.vcc[i];
   s = wave_sum_i64(s);
-  if (lane_id() == 0 && s) atomicAdd((unsigned long long*)&C->nnzL, (unsigned long long)s);
+  if (lane_id() == 0) part[wave_id()] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long t = 0;
+    for (int w = 0; w < FP_WAVES; w++) t += part[w];
+    if (t) atomicAdd((unsigned long long*)&C->nnzL, (unsigned long long)t);
+  }
 }
 
 // ==========================================================================
@@ -1230,7 +1238,7 @@ fp_status run_job(Job& J) {
     FPL(k_sym_emit, G, T, 0, st, dm, d);
     J.check();
   }
-  FPL(k_nnzl, B(n), T, 0, st, dm);
+  FPL(k_nnzl, dim3(std::min(J.blocks(n), 2 * J.h->ncu)), T, 0, st, dm);
 
   // outputs
   J.mark(7);
