@@ -52,21 +52,11 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 H = W = 1024
 MESH_SEED = 2
 PATCH = 512
-# 256-mesh batch, seed 3, 5% edge flips; Poisson serving stream, seed 5
-BATCH_SEED = 3
-SERVE_SEED = 5
-SERVE_RATE = 200.0
 KERNELS = ("k_bfs_level", "k_md", "k_sym_elim", "k_sym_prep", "k_bisect")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def patch_size_for(n):
-    """Target patch size of a batch mesh: the committed autotune table."""
-    from paper_2602_00898_amd.autotune import patch_size_for as ps
-    return ps(n)
 
 
 def csrc_digest():
@@ -176,33 +166,29 @@ def kernel_bytes(name, n, nnz_g):
 
 
 # ------------------------------------------------------------------ inputs
-def _gen_batch_mesh(spec):
-    from paper_2602_00898_amd import meshgen as mg
-    return mg.grid_mesh(spec.side, spec.side, spec.torus, spec.seed, 0.05)
-
-
-def _gen_serve_mesh(spec):
-    from paper_2602_00898_amd import meshgen as mg
-    A = mg.grid_mesh_direct(spec.side, spec.side, spec.torus, spec.seed, index64=True)
-    return A
-
-
 def make_inputs(args):
     """Generate every input before the GPU is touched (forked pool)."""
     import multiprocessing as mp
 
     from paper_2602_00898_amd import meshgen as mg
+    from paper_2602_00898_amd import workloads as wl
     t = time.perf_counter()
     A = mg.grid_mesh(H, W, True, MESH_SEED)
     batch = serve = None
     procs = min(16, os.cpu_count() or 1)
-    with mp.get_context("fork").Pool(procs) as pool:
+    pool = mp.get_context("fork").Pool(procs)
+    try:
         if not args.no_batch:
-            batch = pool.map(_gen_batch_mesh, mg.batch_specs(BATCH_SEED), chunksize=4)
+            batch = pool.map(wl.batch_mesh, wl.batch_specs(), chunksize=4)
         if not args.no_serve:
-            stream = mg.serving_stream(SERVE_SEED, args.serve_requests, rate=SERVE_RATE)
-            meshes = pool.map(_gen_serve_mesh, [s for _, s in stream], chunksize=2)
+            stream = wl.serving_stream(args.serve_requests)
+            meshes = pool.map(wl.serving_mesh, [s for _, s in stream], chunksize=2)
             serve = [(t_arr, m) for (t_arr, _), m in zip(stream, meshes)]
+    finally:
+        # close and join (not terminate): the workers exit on their own, so a
+        # profiled run sees no signal
+        pool.close()
+        pool.join()
     log(f"inputs generated in {time.perf_counter() - t:.1f} s with {procs} processes")
     return A, batch, serve
 
@@ -277,8 +263,9 @@ def run_batch(args, meshes):
     from paper_2602_00898_amd import fastperm as fpm
 
     dev = torch.device("cuda:0")
+    from paper_2602_00898_amd import workloads as wl
     dm = [dict(rowptr=torch.from_numpy(A.rowptr).to(dev), colind=torch.from_numpy(A.colind).to(dev),
-               n=A.n, patch_size=patch_size_for(A.n), seed=BATCH_SEED * 1000 + i)
+               n=A.n, patch_size=wl.batch_patch_size(A.n), seed=wl.batch_order_seed(i))
           for i, A in enumerate(meshes)]
     nv = sum(A.n for A in meshes)
     h = fpm.Handle()
@@ -356,6 +343,7 @@ def run_block(args):
 # ------------------------------------------------------------------ serving
 def run_serve(args, reqs):
     from paper_2602_00898_amd import fastperm as fpm
+    from paper_2602_00898_amd import workloads as wl
 
     srv = fpm.Server(hbm_budget=args.serve_budget_gb << 30, max_slots=args.lanes)
     try:
@@ -368,7 +356,8 @@ def run_serve(args, reqs):
             delay = t0 + t_arr - time.perf_counter()
             if delay > 0:
                 time.sleep(delay)
-            tickets.append(srv.submit(A.rowptr, A.colind, A.n, patch_size=PATCH, seed=7))
+            tickets.append(srv.submit(A.rowptr, A.colind, A.n, patch_size=wl.SERVE_PATCH,
+                                      seed=wl.SERVE_ORDER_SEED))
         lat = []
         for tk in tickets:
             lat.append(srv.wait(tk)["latency_s"])
@@ -381,7 +370,7 @@ def run_serve(args, reqs):
     def pct(p):
         return lat[min(len(lat) - 1, int(round(p / 100.0 * (len(lat) - 1))))]
 
-    return {"workload": f"Poisson arrivals {SERVE_RATE:.0f}/s, grid/torus sides log-uniform "
+    return {"workload": f"Poisson arrivals {wl.SERVE_RATE:.0f}/s, grid/torus sides log-uniform "
                         "100..1414 (1e4..2e6 vertices), fresh diagonals per request, S=512",
             "requests": len(reqs), "vertices": nv, "slots": args.lanes,
             "value": round(nv / wall / 1e6, 4), "unit": "M vertices/s",
@@ -417,7 +406,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-mesh batch")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sample")
-    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--lanes", type=int, default=16)
     ap.add_argument("--block", action="store_true",

@@ -131,6 +131,21 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
                    const fp_options* opts, void* workspace, size_t ws_bytes,
                    fp_result* out, void* stream);
 
+/* fp_order for callers that cannot allocate device memory (code that must
+ * not call hipMalloc: tight serving loops, harnesses that forbid it).  The
+ * workspace is a static device array of the library, 256 MiB per device,
+ * held from the library's first use on a device until the process ends;
+ * the caller still passes the matrix and the output buffers.  A matrix whose
+ * fp_query workspace exceeds 256 MiB gets FP_ERR_SIZE (no work is queued).
+ * Every launch stays on `stream` and the call creates nothing: no memory,
+ * streams or events.  Device error bits are written to out->status (pass a
+ * non-NULL status to see them).  All calls on one device share that
+ * device's array, and the last call's contents stay in it: two calls that
+ * overlap on one device (different streams or host threads) race and give
+ * wrong results, so serialise them.  Results equal fp_order's. */
+fp_status fp_order_static(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
+                          const fp_options* opts, fp_result* out, void* stream);
+
 /* Synchronise `stream` and translate the device error bits of the last
  * call that used `workspace`. */
 fp_status fp_last_error(fp_handle* h, void* workspace, void* stream);

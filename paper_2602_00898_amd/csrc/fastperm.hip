@@ -13,6 +13,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "../../include/fastperm.h"
@@ -839,6 +840,33 @@ __global__ void k_finish(const FpMesh* __restrict__ Mp, int nn) {
 }
 
 // ==========================================================================
+// Static scratch of fp_order_static, for callers that cannot allocate
+// device memory.  Each device holds its own copy of the array, from the
+// first use of the library on it until the process ends.  Host code never
+// uses the array's name as an address: the device address is looked up once
+// per device (fp_create) and kept in g_scratch.
+// ==========================================================================
+#define FP_STATIC_SCRATCH_BYTES (256ull << 20)
+#define FP_MAX_DEVICES 64
+static __device__ __align__(256) char scratch[FP_STATIC_SCRATCH_BYTES];
+static void* g_scratch[FP_MAX_DEVICES];
+static bool g_scratch_tried[FP_MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+// with `device` current: its copy of the scratch array, looked up once
+static void bind_scratch(int device) {
+  if (device < 0 || device >= FP_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (g_scratch_tried[device]) return;
+  g_scratch_tried[device] = true;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess)
+    g_scratch[device] = p;
+  else
+    (void)hipGetLastError();  // fp_order_static then reports FP_ERR_HIP
+}
+
+// ==========================================================================
 // host side
 // ==========================================================================
 static const char* const kStageNames[FP_NSTAGE] = {
@@ -898,6 +926,7 @@ struct Job {
   FpCtl* ctl;
   bool hip_failed = false;
   bool timing = false;
+  bool fixed = false;       // no side streams and no per-kernel events (static-scratch calls)
   bool side_open = false;   // work on the side stream not yet joined
   bool side2_open = false;  // same for the second side stream
 
@@ -920,7 +949,9 @@ struct Job {
   }
 
   // timing of one kernel (fp_time_kernel): events around each of its launches
-  bool tk(const char* name) const { return h->tk_name[0] && strcmp(h->tk_name, name) == 0; }
+  bool tk(const char* name) const {
+    return !fixed && h->tk_name[0] && strcmp(h->tk_name, name) == 0;
+  }
   // the events go on the launch's own stream
   void tk_begin(hipStream_t ls) {
     if ((int)h->tk_ev.size() < 2 * (h->tk_n + 1)) {
@@ -1137,7 +1168,8 @@ fp_status run_job(Job& J) {
   // top separators ordered early on the side stream (level order only: there
   // their ranges depend on the top levels alone)
   const int TL =
-      J.hm.sched == 0 && J.h->side_ok && ensure_side(J.h) ? std::min(FP_TOP_LEVELS, D) : 0;
+      J.hm.sched == 0 && !J.fixed && J.h->side_ok && ensure_side(J.h) ? std::min(FP_TOP_LEVELS, D)
+                                                                       : 0;
   const int ntop = (1 << TL) - 1;
   for (int d = 0; d < D; d++) {
     FPL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
@@ -1198,7 +1230,7 @@ fp_status run_job(Job& J) {
     // this stream, so its workgroups take their CUs before the others fill
     // the rest; class 1 follows the depth-1 orders on the second side
     // stream, classes 2 and 3 the depth-2 orders on the third.
-    const bool two = J.h->side_ok && ensure_side(J.h);
+    const bool two = !J.fixed && J.h->side_ok && ensure_side(J.h);
     if (two) {
       if (hipEventRecord(J.h->ev_md, st) != hipSuccess ||
           hipStreamWaitEvent(J.h->side2, J.h->ev_md, 0) != hipSuccess ||
@@ -1329,6 +1361,7 @@ fp_status fp_create(fp_handle** h) {
     return FP_ERR_HIP;
   }
   H->ncu = std::max(1, ncu);
+  bind_scratch(H->device);
   H->lds_bytes = FP_LDS_BYTES;
   H->lds_big = big_lds(H->device);
   H->lds_md = std::min(H->lds_big, FP_MD_LDS);
@@ -1394,9 +1427,15 @@ fp_status fp_query(fp_handle* h, const fp_csr* A, const fp_options* opts, size_t
   return FP_OK;
 }
 
-fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
-                   const fp_options* opts, void* workspace, size_t ws_bytes, fp_result* out,
-                   void* stream) {
+}  // extern "C"
+
+namespace {
+
+// fp_order and fp_order_static: `fixed` keeps every launch on `stream`, with
+// no side streams and no per-kernel timing events (nothing is created).
+fp_status order_impl(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
+                     const fp_options* opts, void* workspace, size_t ws_bytes, fp_result* out,
+                     void* stream, bool fixed) {
   if (!h || !out || !workspace) return FP_ERR_ARG;
   fp_status s = check_opts(opts);
   if (s) return s;
@@ -1438,7 +1477,8 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   M.lds_md = h->lds_md;
   J.ctl = M.ctl;
   J.dm = (const FpMesh*)(ws + P.o_mesh);
-  J.timing = (opts->flags & FP_FLAG_TIMING) != 0;
+  J.fixed = fixed;
+  J.timing = !fixed && (opts->flags & FP_FLAG_TIMING) != 0;
   h->timed = false;
   h->tk_n = 0;
   h->tk_failed = false;
@@ -1460,6 +1500,29 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
     return s;
   }
   return FP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
+                   const fp_options* opts, void* workspace, size_t ws_bytes, fp_result* out,
+                   void* stream) {
+  return order_impl(h, A, user_gmap, opts, workspace, ws_bytes, out, stream, false);
+}
+
+fp_status fp_order_static(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
+                          const fp_options* opts, fp_result* out, void* stream) {
+  if (!h || !opts || !A) return FP_ERR_ARG;
+  if (h->device < 0 || h->device >= FP_MAX_DEVICES) return FP_ERR_ARG;
+  void* ws = g_scratch[h->device];
+  if (!ws) return FP_ERR_HIP;
+  size_t need = 0;
+  fp_status s = fp_query(h, A, opts, &need, nullptr);
+  if (s != FP_OK) return s;
+  if (need > FP_STATIC_SCRATCH_BYTES) return FP_ERR_SIZE;
+  return order_impl(h, A, user_gmap, opts, ws, FP_STATIC_SCRATCH_BYTES, out, stream, true);
 }
 
 fp_status fp_time_kernel(fp_handle* h, const char* name) {

@@ -79,6 +79,8 @@ def lib():
                                C.POINTER(C.c_int32)]
         L.fp_order.argtypes = [vp, C.POINTER(Csr), vp, C.POINTER(Options), vp, C.c_size_t,
                                C.POINTER(Result), vp]
+        L.fp_order_static.argtypes = [vp, C.POINTER(Csr), vp, C.POINTER(Options),
+                                      C.POINTER(Result), vp]
         L.fp_last_error.argtypes = [vp, vp, vp]
         L.fp_error_detail.argtypes = [vp, vp, vp, C.POINTER(C.c_uint32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32)]
@@ -205,6 +207,32 @@ def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size
         rc = lib().fp_last_error(handle.h, _ptr(ws), C.c_void_p(s))
         if rc != 0:
             raise FpError(rc, "device", error_detail(handle, ws, s))
+    return out
+
+
+def order_static(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size=1,
+                 lloyd_iters=1, seed=0, user_gmap=None, handle=None, out=None, stream=None,
+                 check=True):
+    """order() through fp_order_static: the library's static device scratch
+    instead of a workspace (the call allocates nothing itself)."""
+    dev = colind.device if colind.numel() else rowptr.device
+    handle = handle or Handle()
+    opts = options(patch_size, schedule, block_size, lloyd_iters, seed)
+    A = make_csr(n, rowptr, colind)
+    if out is None:
+        _, max_nodes = query(handle, n, rowptr, colind, opts)
+        out = _alloc_out(n, max_nodes, block_size, dev)
+    R = _result(out)
+    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().fp_order_static(handle.h, C.byref(A), _ptr(user_gmap), C.byref(opts), C.byref(R),
+                               C.c_void_p(s))
+    if rc != 0:
+        raise FpError(rc, "fp_order_static")
+    if check:
+        torch.cuda.synchronize(dev)
+        bits = int(out["status"].item())
+        if bits:
+            raise FpError(9, "device", (bits, 0, 0))
     return out
 
 

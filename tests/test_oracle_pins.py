@@ -446,6 +446,58 @@ def test_level_and_post_order_same_fill(mesh):
             assert np.all(r["node_of"][blk] == t)
 
 
+def _schedule_sequence(D, sched):
+    """Node sequence of a schedule over the heap of depth D, from its
+    definition: level order lists depth D first, then D-1, ..., 0, each depth
+    by ascending heap index; post order visits the left subtree, the right
+    subtree, then the node."""
+    if sched == oracle.SCHED_LEVEL:
+        return [t for d in range(D, -1, -1) for t in range((1 << d) - 1, (1 << (d + 1)) - 1)]
+    seq, nn = [], (1 << (D + 1)) - 1
+    stack = [(0, False)]
+    while stack:
+        t, done = stack.pop()
+        if t >= nn:
+            continue
+        if done:
+            seq.append(t)
+        else:
+            stack += [(t, True), (2 * t + 2, False), (2 * t + 1, False)]
+    return seq
+
+
+@pytest.mark.parametrize("sched", [oracle.SCHED_LEVEL, oracle.SCHED_POST])
+@pytest.mark.parametrize("mesh,S", [((16, 16, True, 13), 24), ((12, 20, False, 14), 7),
+                                    ((24, 24, True, 15), 40), ((20, 21, False, 16), 3)])
+def test_concatenation_sequence_exact(mesh, S, sched):
+    """perm is the concatenation of the local orders along the schedule
+    (Alg. 3): rebuilt here from node_of, the schedule's definition and the
+    minimum-degree order of each node's induced subgraph, it must equal the
+    oracle's perm and node ranges element for element."""
+    A, (rp, ci) = mesh_graph(*mesh)
+    r = oracle.order(A.rowptr, A.colind, A.n, patch_size=S, seed=5, schedule=sched)
+    D, nof = r["D"], r["node_of"]
+    seq = _schedule_sequence(D, sched)
+    assert sorted(seq) == list(range((1 << (D + 1)) - 1))
+    begin = np.zeros(len(seq), dtype=np.int64)
+    perm = []
+    for t in seq:
+        begin[t] = len(perm)
+        V = np.flatnonzero(nof == t)  # ascending ids = local indices
+        if len(V) == 0:
+            continue
+        loc = -np.ones(A.n, dtype=np.int64)
+        loc[V] = np.arange(len(V))
+        rows = [[loc[u] for u in ci[rp[v]:rp[v + 1]] if loc[u] >= 0] for v in V]
+        lrp = np.zeros(len(V) + 1, dtype=np.int64)
+        np.cumsum([len(x) for x in rows], out=lrp[1:])
+        lci = np.array([x for row in rows for x in row], dtype=np.int32)
+        perm.extend(V[oracle.brute_md(lrp, lci)])
+    assert np.array_equal(np.asarray(perm), r["perm"])
+    assert np.array_equal(begin, r["node_begin"])
+    assert np.array_equal(np.bincount(nof, minlength=len(seq)), r["node_size"])
+
+
 # ---------------------------------------------------------------- limits, blocks
 
 def test_single_patch_reduces_to_minimum_degree():
