@@ -66,6 +66,7 @@ def lib():
         L.fpo_etree.argtypes = [C.c_int32, vp, vp, vp, vp, vp]
         L.fpo_colcount.argtypes = [C.c_int32, vp, vp, vp, vp, vp, vp, vp]
         L.fpo_brute_symbolic.argtypes = [C.c_int32, vp, vp, vp, vp, vp, vp]
+        L.fpo_supernodes.argtypes = [C.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fpo_order.argtypes = [C.c_int64, vp, vp, vp, C.POINTER(_Opts), C.POINTER(_Out)]
         _lib = L
     return _lib
@@ -202,6 +203,26 @@ def brute_symbolic(grp, gci, perm):
     _check(lib().fpo_brute_symbolic(n, _p(_i64(grp)), _p(_i32(gci)), _p(_i32(perm)), _p(parent),
                                     _p(cc), _p(nnz)), "brute_symbolic")
     return parent, cc, int(nnz[0])
+
+
+def supernodes(parent, colcount):
+    """F1: fundamental supernodes of L from the elimination tree and column
+    counts; returns a dict (Lp, super_of, super_ptr, super_parent, Lx_ptr,
+    n_super)."""
+    parent = _i32(parent)
+    colcount = _i32(colcount)
+    n = len(parent)
+    Lp = np.zeros(n + 1, dtype=np.int64)
+    sof = np.zeros(max(n, 1), dtype=np.int32)
+    sptr = np.zeros(n + 1, dtype=np.int32)
+    spar = np.zeros(max(n, 1), dtype=np.int32)
+    lx = np.zeros(n + 1, dtype=np.int64)
+    ns = np.zeros(1, dtype=np.int32)
+    _check(lib().fpo_supernodes(n, _p(parent), _p(colcount), _p(Lp), _p(sof), _p(sptr), _p(spar),
+                                _p(lx), _p(ns)), "supernodes")
+    k = int(ns[0])
+    return dict(Lp=Lp, super_of=sof[:n].copy(), super_ptr=sptr[:k + 1].copy(),
+                super_parent=spar[:k].copy(), Lx_ptr=lx[:k + 1].copy(), n_super=k)
 
 
 def order(rowptr, colind, n_dof: int, patch_size: int = 512, lloyd_iters: int = 1,

@@ -776,6 +776,68 @@ int fpo_brute_symbolic(int32_t n, const int64_t* rp, const int32_t* ci,
 }
 
 /* ------------------------------------------------------------------ */
+/* F1: supernodal symbolic analysis.  The solver that consumes the       */
+/* ordering needs the elimination tree for its symbolic analysis         */
+/* (Sec. 1); a supernodal factorization groups columns into fundamental  */
+/* supernodes (Liu, Ng and Peyton, SIAM J. Matrix Anal. Appl. 14(1),     */
+/* 1993): column j+1 continues the supernode of column j exactly when    */
+/* j is the only child of j+1 in the elimination tree and the structure  */
+/* of column j is that of column j+1 plus j itself, which, given that    */
+/* struct(L_j) minus j lies inside struct(L_parent(j)), is               */
+/* colcount[j] == colcount[j+1] + 1 with parent[j] == j+1.               */
+/* ------------------------------------------------------------------ */
+
+int fpo_supernodes(int32_t n, const int32_t* parent, const int32_t* colcount, int64_t* Lp,
+                   int32_t* super_of, int32_t* super_ptr, int32_t* super_parent, int64_t* Lx_ptr,
+                   int32_t* n_super) {
+  if (n < 0 || !parent || !colcount) return FPO_ERR_ARG;
+  /* column pointers of L: column j occupies Lp[j] .. Lp[j+1]-1 */
+  if (Lp) {
+    Lp[0] = 0;
+    for (int32_t j = 0; j < n; j++) Lp[j + 1] = Lp[j] + colcount[j];
+  }
+  /* number of children of every column in the elimination tree */
+  int32_t* nchild = NEWZ(int32_t, n > 0 ? n : 1);
+  for (int32_t j = 0; j < n; j++) {
+    if (parent[j] < -1 || parent[j] >= n || (parent[j] >= 0 && parent[j] <= j)) {
+      free(nchild);
+      return FPO_ERR_INDEX;
+    }
+    if (parent[j] >= 0) nchild[parent[j]]++;
+  }
+  /* walk the columns: a new supernode starts wherever column j cannot
+   * continue the supernode of column j-1 */
+  int32_t ns = 0;
+  for (int32_t j = 0; j < n; j++) {
+    int cont = j > 0 && parent[j - 1] == j && nchild[j] == 1 && colcount[j - 1] == colcount[j] + 1;
+    if (!cont) {
+      if (super_ptr) super_ptr[ns] = j;
+      ns++;
+    }
+    if (super_of) super_of[j] = ns - 1;
+  }
+  if (super_ptr) super_ptr[ns] = n;
+  /* supernodal elimination tree: the parent of a supernode is the supernode
+   * holding the etree parent of its last column */
+  if (super_parent && super_ptr && super_of)
+    for (int32_t s = 0; s < ns; s++) {
+      int32_t last = super_ptr[s + 1] - 1;
+      super_parent[s] = parent[last] < 0 ? -1 : super_of[parent[last]];
+    }
+  /* dense storage of a supernode: its first column's rows times its width */
+  if (Lx_ptr && super_ptr) {
+    Lx_ptr[0] = 0;
+    for (int32_t s = 0; s < ns; s++) {
+      int32_t f = super_ptr[s], w = super_ptr[s + 1] - f;
+      Lx_ptr[s + 1] = Lx_ptr[s] + (int64_t)colcount[f] * w;
+    }
+  }
+  *n_super = ns;
+  free(nchild);
+  return FPO_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* O8 and the whole pipeline (Alg. 1; Alg. 3; Sec. 5 schedules).        */
 /* ------------------------------------------------------------------ */
 

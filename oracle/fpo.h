@@ -23,6 +23,8 @@
  *                                 node, heap capacity, candidate definition
  *   schedules                  -- equal fill for level and post order
  *   block expansion            -- symbolic analysis of the expanded DOF pattern
+ *   fpo_supernodes             -- column structures of a dense symbolic
+ *                                 elimination compared set by set
  */
 #ifndef FPO_H
 #define FPO_H
@@ -129,6 +131,19 @@ int fpo_brute_symbolic(int32_t n, const int64_t* rp, const int32_t* ci,
 /* Pin: minimum degree with every degree recomputed from a dense adjacency
  * matrix at every step (m <= 2048). */
 int fpo_brute_md(int32_t m, const int64_t* rp, const int32_t* ci, int32_t* order);
+
+/* F1: supernodal symbolic analysis from the elimination tree and column
+ * counts (the solver's symbolic phase, Sec. 1): fundamental supernodes
+ * (Liu, Ng, Peyton 1993).  Lp[n+1]: column pointers of L; super_of[n]:
+ * supernode of every column; super_ptr[ns+1]: first column of every
+ * supernode, then n; super_parent[ns]: supernodal elimination tree (-1 for
+ * roots); Lx_ptr[ns+1]: offsets of the dense supernode blocks (first column's
+ * row count times width).  Any output may be NULL (super_parent and Lx_ptr
+ * need super_ptr and super_of).  Capacities: n+1 for super_ptr and Lx_ptr,
+ * n for super_parent. */
+int fpo_supernodes(int32_t n, const int32_t* parent, const int32_t* colcount, int64_t* Lp,
+                   int32_t* super_of, int32_t* super_ptr, int32_t* super_parent, int64_t* Lx_ptr,
+                   int32_t* n_super);
 
 /* The whole ordering (Alg. 1).  A is the matrix pattern (diagonal optional,
  * duplicates and column order irrelevant).  user_gmap (nullable, n_v entries)
