@@ -52,7 +52,8 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
 H = W = 1024
 MESH_SEED = 2
 PATCH = 512
-KERNELS = ("k_bfs_level", "k_md", "k_sym_elim", "k_sym_prep", "k_bisect")
+# kernels timed one by one with HIP events during the warm-up orderings
+KERNELS = ("k_md_top", "k_md", "k_sym_elim", "k_sym_prep", "k_bfs_level", "k_bisect")
 
 
 def log(msg):
@@ -143,26 +144,50 @@ def traffic_from(fetch_csv, write_csv, mib):
     print(json.dumps(out))
 
 
-def kernel_bytes(name, n, nnz_g):
-    """Algorithmic bytes of all launches of a kernel in one ordering (int32
-    arrays, 64-bit BFS keys; deg = graph entries per vertex)."""
-    deg = nnz_g / max(n, 1)
+def csr_pass_bytes(n, nnz):
+    """One pass over the CSR pattern per vertex: 4 B of row pointer plus 4 B
+    per stored entry (diagonal included): 32 B on a torus (7 entries)."""
+    return 4.0 + 4.0 * nnz / max(n, 1)
+
+
+def kernel_bytes(name, n, nnz, top_vertices, lloyd_iters=1):
+    """Algorithmic HBM bytes of all launches of a kernel in one ordering, by
+    the per-vertex figures of the path's byte budget (c = one CSR pass):
+    patching takes (1 + 2 I) passes (the BFS launches), each local order
+    gathers its node's rows once (one pass over the vertices it orders),
+    the symbolic stage reads the permuted pattern once plus 24 B of iperm
+    gathers and writes parent and column count (8 B).  The bisection works
+    on the quotient graph only (no per-vertex bytes)."""
+    c = csr_pass_bytes(n, nnz)
     if name == "k_bfs_level":
-        # three BFS passes (growth, Lloyd distance, regrowth); per vertex:
-        # frontier 4 + own key 8 + row pointers 8 + deg x (column 4 +
-        # neighbour key 8) + claim (key 8 + frontier 4)
-        return 3 * n * (4 + 8 + 8 + deg * 12 + 12)
+        return (1 + 2 * lloyd_iters) * c * n
     if name == "k_md":
-        # each node's induced rows once (row pointers 8, deg x (column 4,
-        # node 4, local index 4)), vertex list 4, order and inverse 8, index 4
-        return n * (8 + deg * 12 + 16)
-    if name in ("k_sym_elim", "k_sym_prep"):
-        # the permuted pattern once (row pointers 8, deg x (column 4 +
-        # inverse permutation 4)), parent and column count 8
-        return n * (8 + deg * 8 + 8)
-    if name == "k_bisect":
-        return 0
-    return n * (8 + deg * 4)
+        return c * (n - top_vertices)
+    if name == "k_md_top":
+        return c * top_vertices
+    if name == "k_sym_prep":
+        return (c + 24.0) * n
+    if name == "k_sym_elim":
+        return 8.0 * n
+    return 0.0
+
+
+def path_bytes_per_vertex(n, nnz, depth, beta, lloyd_iters=1):
+    """Algorithmic bytes per vertex of the whole path: (4 + 2 I) CSR passes
+    (patching, boundary detection, local-order gather, symbolic), the marking
+    passes over the boundary list (depth x beta passes, beta = boundary
+    fraction), and 64 B of state arrays and outputs."""
+    c = csr_pass_bytes(n, nnz)
+    return (4 + 2 * lloyd_iters) * c + depth * beta * c + 64.0
+
+
+def boundary_fraction(rowptr, colind, gmap):
+    """Fraction of vertices with a neighbour in another patch."""
+    import numpy as np
+    rows = np.repeat(np.arange(len(rowptr) - 1), np.diff(rowptr))
+    g = np.asarray(gmap)
+    cross = g[rows] != g[colind]
+    return float(np.unique(rows[cross]).size) / max(len(rowptr) - 1, 1)
 
 
 # ------------------------------------------------------------------ inputs
@@ -215,17 +240,19 @@ def run_plain(args, A):
                          timing=True)
 
     # warmup; the first warmups also time the candidate kernels one by one
-    totals = {}
-    for i in range(max(args.warmup, 1)):
+    # (HIP events around each launch, on the launch's own stream)
+    timed = {}
+    for i in range(max(args.warmup, len(KERNELS))):
         cand = KERNELS[i] if i < len(KERNELS) else None
         fpm.time_kernel(h, cand)
         t = time.perf_counter()
         step()
         torch.cuda.synchronize(dev)
         if cand:
-            totals[cand] = fpm.kernel_time(h)[0]
+            timed[cand] = fpm.kernel_time(h)
         log(f"warmup {i}: {1e3 * (time.perf_counter() - t):.2f} ms")
-    dom = max(totals, key=totals.get)
+    # the dominant kernel: the largest event-timed total per ordering
+    dom = max(timed, key=lambda k: timed[k][0])
     fpm.time_kernel(h, dom)
     stages = {}
     kt_ms, kt_launch = 0.0, 0
@@ -243,17 +270,30 @@ def run_plain(args, A):
     dt = time.perf_counter() - t0
     fpm.time_kernel(h, None)
     nnzL = int(out["nnzL"].item())
-    P = int(out["gmap"].max().item()) + 1
+    gmap = out["gmap"][:n].cpu().numpy()
+    P = int(gmap.max()) + 1
     nn = int(out["n_nodes"].item())
     D = max(0, (nn + 1).bit_length() - 2)
-    nnz_g = nnz - n  # the diagonal is not a graph entry
-    per_launch_bytes = kernel_bytes(dom, n, nnz_g) * args.steps / max(kt_launch, 1)
+    sizes = out["node_size"][:nn].cpu().numpy()
+    top_vertices = int(sizes[:min(nn, 7)].sum())  # separators of depths 0-2
+    beta = boundary_fraction(A.rowptr, A.colind, gmap)
+    kern = {}
+    for k, (ms, nl) in timed.items():
+        alg = kernel_bytes(k, n, nnz, top_vertices)
+        per = alg / max(nl, 1)
+        avg = ms / max(nl, 1)
+        gbs = per / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+        kern[k] = {"ms_per_ordering": round(ms, 4), "launches": nl, "avg_launch_ms": round(avg, 5),
+                   "alg_bytes_per_launch": round(per), "GBps": round(gbs, 4),
+                   "frac": round(gbs / HBM_PEAK_GBS, 7)}
+    per_launch_bytes = kernel_bytes(dom, n, nnz, top_vertices) * args.steps / max(kt_launch, 1)
     avg_ms = kt_ms / max(kt_launch, 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     return dict(n=n, nnz=nnz, nnzL=nnzL, P=P, D=D, ms=dt * 1e3 / args.steps,
                 stage_ms={k: sum(v) / len(v) for k, v in stages.items()}, dom=dom,
                 dom_bytes=per_launch_bytes, dom_avg_ms=avg_ms, dom_launches=kt_launch / args.steps,
-                achieved=achieved, warm_kernel_ms=totals)
+                achieved=achieved, kernels=kern, beta=beta,
+                path_bpv=path_bytes_per_vertex(n, nnz, D, beta))
 
 
 # ------------------------------------------------------------------ batch
@@ -379,11 +419,43 @@ def run_serve(args, reqs):
 
 
 # ------------------------------------------------------------------ oracle
-def run_cpu(A, budget_s=15.0):
+def host_cpu():
+    """Model name of the host CPU and the cores this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count() or 1
+    return model, cores
+
+
+def _oracle_batch_item(args):
     import oracle
+    A, S, seed = args
+    t = time.perf_counter()
+    oracle.order(A.rowptr, A.colind, A.n, patch_size=S, seed=seed)
+    return time.perf_counter() - t
+
+
+def run_cpu(A, batch_meshes, budget_s=15.0):
+    """The oracle as it stands: full orderings of the benchmark mesh on one
+    core (median), and the 256-mesh batch with one process per core."""
+    import multiprocessing as mp
+
+    import oracle
+    from paper_2602_00898_amd import workloads as wl
 
     oracle.build()
-    log("CPU oracle baseline")
+    model, cores = host_cpu()
+    log(f"CPU oracle baseline on {cores} cores of {model}")
     times = []
     t_all = time.perf_counter()
     while True:
@@ -393,9 +465,28 @@ def run_cpu(A, budget_s=15.0):
         if time.perf_counter() - t_all > budget_s or len(times) >= 5:
             break
     med = statistics.median(times)
-    return dict(value=A.n / med / 1e6, unit="M vertices/s", cores=1, kind="oracle",
-                sample=f"{len(times)} full orderings of the 1024x1024 torus (S=512) on one "
-                       f"host core, median {med:.3f} s", nnzL=r["nnzL"])
+    res = dict(value=A.n / med / 1e6, unit="M vertices/s", cores=1, kind="oracle",
+               host_cpu=model, host_cores=cores,
+               sample=f"{len(times)} full orderings of the 1024x1024 torus (S=512) on one "
+                      f"host core, median {med:.3f} s", nnzL=r["nnzL"])
+    if batch_meshes is not None:
+        items = [(M, wl.batch_patch_size(M.n), wl.batch_order_seed(i))
+                 for i, M in enumerate(batch_meshes)]
+        items.sort(key=lambda x: -x[0].n)
+        t = time.perf_counter()
+        pool = mp.get_context("fork").Pool(cores)
+        try:
+            pool.map(_oracle_batch_item, items, chunksize=1)
+        finally:
+            pool.close()
+            pool.join()
+        wall = time.perf_counter() - t
+        nv = sum(M.n for M in batch_meshes)
+        res["batch_all_cores"] = dict(value=round(nv / wall / 1e6, 4), unit="M vertices/s",
+                                      processes=cores, meshes=len(batch_meshes),
+                                      sample=f"the 256-mesh batch, one oracle process per core, "
+                                             f"{wall:.2f} s wall")
+    return res
 
 
 def main():
@@ -409,8 +500,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--lanes", type=int, default=16)
-    ap.add_argument("--block", action="store_true",
-                    help="also time the 2048x2048 torus in 3x3 blocks (12.6M DOF)")
+    ap.add_argument("--no-block", action="store_true",
+                    help="skip the 2048x2048 torus in 3x3 blocks (12.6M DOF)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run a plain device copy of this size first (counter calibration)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -429,8 +520,8 @@ def main():
     g = run_plain(args, A)
     batch = None if batch_meshes is None else run_batch(args, batch_meshes)
     serving = None if serve_reqs is None else run_serve(args, serve_reqs)
-    block = run_block(args) if args.block else None
-    cpu = None if args.no_cpu else run_cpu(A)
+    block = None if args.no_block else run_block(args)
+    cpu = None if args.no_cpu else run_cpu(A, batch_meshes)
     if cpu is not None and cpu.pop("nnzL") != g["nnzL"]:
         print(f"nnz(L) differs from the oracle: {g['nnzL']} vs oracle", file=sys.stderr)
         sys.exit(1)
@@ -457,8 +548,15 @@ def main():
                      "bytes_per_launch": round(g["dom_bytes"]),
                      "avg_launch_ms": round(g["dom_avg_ms"], 5),
                      "launches_per_step": g["dom_launches"]},
+        # the whole path at the algorithmic bytes per vertex, against the peak
+        "path_roofline": {"bytes_per_vertex": round(g["path_bpv"], 2),
+                          "boundary_fraction": round(g["beta"], 4),
+                          "achieved": round(g["n"] / (g["ms"] * 1e-3) * g["path_bpv"] / 1e9, 3),
+                          "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                          "frac": round(g["n"] / (g["ms"] * 1e-3) * g["path_bpv"] / 1e9
+                                        / HBM_PEAK_GBS, 6)},
         "stage_ms": {k: round(v, 4) for k, v in g["stage_ms"].items()},
-        "kernel_ms_per_ordering": {k: round(v, 3) for k, v in g["warm_kernel_ms"].items()},
+        "kernels": g["kernels"],
         "batch": batch,
         "serving": serving,
         "block": block,

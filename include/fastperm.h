@@ -15,12 +15,16 @@
  *     owned by the caller; the library never frees them.  Server calls take
  *     host arrays (documented there).
  *   - `stream` is a hipStream_t passed as void* (NULL = default stream).
- *     Every kernel runs on `stream`.  fp_order reads a few scalars back
- *     between stages (patch count, BFS frontier sizes, the error bits after
- *     the local orders), so it synchronises `stream` at those points; the
- *     last stages are only enqueued, and the results are ready when the
- *     stream reaches the end of the call.  Errors found by the device are
- *     read with fp_last_error / fp_error_detail after that.
+ *     fp_order, fp_order_static, fp_order_batch and fp_supernodes are
+ *     asynchronous: they queue their kernels on `stream` (fp_order also on
+ *     internal side streams that fork from `stream` with events and join
+ *     back into it) and return without waiting for the device or reading
+ *     anything back; the results are ready when `stream` reaches the end of
+ *     the call.  Counts that only the device knows (patches, tree depth,
+ *     frontier sizes) are read by the kernels themselves, so a call can be
+ *     captured into a hipGraph.  Errors found by the device are read with
+ *     fp_last_error / fp_error_detail (which synchronise `stream`) or from
+ *     the status output.
  *   - perm[new] = old, iperm[old] = new.  parent[j] is the elimination-tree
  *     parent of column j of A(perm,perm), -1 for a root.  colcount[j] counts
  *     the nonzeros of column j of L including the diagonal; nnzL is their sum.
@@ -69,12 +73,20 @@ typedef struct {
   int32_t block_size;   /* DOFs per mesh vertex, >= 1 (default 1) */
   int32_t lloyd_iters;  /* Lloyd re-centre iterations of patching (default 1) */
   uint64_t seed;        /* seed of the patch-seed hash (default 0) */
-  uint32_t flags;       /* FP_FLAG_* bits, 0 by default */
+  uint32_t flags;       /* FP_FLAG_* bits, FP_FLAG_VALIDATE by default */
 } fp_options;
 
 /* flags: record the device time of every stage of the call on its stream
  * (read back with fp_stage_times) */
 #define FP_FLAG_TIMING 1u
+/* flags: check on the device that the pattern is symmetric, as the method
+ * requires of its input (Sec. 4, "Inputs and outputs"): every entry (i, j)
+ * must have its mirror (j, i) (in block mode, every coupled vertex pair both
+ * ways).  A failure stops the ordering and is reported as
+ * FP_ERR_NOT_SYMMETRIC.  Set by fp_options_default; a caller that clears it
+ * saves one pass over the graph, and an asymmetric pattern then gives an
+ * unspecified ordering. */
+#define FP_FLAG_VALIDATE 2u
 
 /* Pattern of A in CSR form (device arrays).  Exactly one of rowptr32 /
  * rowptr64 is non-NULL (n+1 entries); colind has nnz entries in [0, n).
@@ -146,6 +158,42 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
 fp_status fp_order_static(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
                           const fp_options* opts, fp_result* out, void* stream);
 
+/* ---------------------------------------------------------------------
+ * Supernodal symbolic analysis of the ordering's result, the first step of
+ * the solver's symbolic phase, which needs the elimination tree (Sec. 1):
+ * fundamental supernodes (Liu, Ng, Peyton, SIAM J. Matrix Anal. Appl.
+ * 14(1), 1993).  Column j+1 continues the supernode of column j exactly when
+ * parent[j] == j+1, j is the only child of j+1, and colcount[j] ==
+ * colcount[j+1] + 1.  Inputs are the parent and colcount arrays that
+ * fp_order wrote (n columns; device arrays).  Outputs (device arrays owned
+ * by the caller):
+ *   Lp[n+1]            column pointers of L (exclusive sums of colcount);
+ *   super_ptr[n+1]     first column of every supernode, then n (the first
+ *                      n_super+1 entries are written);
+ *   n_super[1]         number of supernodes;
+ *   super_of[n]        supernode of every column (nullable);
+ *   super_parent[n]    supernodal elimination tree: the supernode of the
+ *                      parent of its last column, -1 for roots (nullable);
+ *   Lx_ptr[n+1]        offsets of dense supernode blocks, each the first
+ *                      column's row count times the width (nullable);
+ *   status[1]          1 if a parent entry is not -1 and not in (j, n)
+ *                      (nullable; the other outputs are then unspecified).
+ * Asynchronous on `stream`: nothing is read back to the host. */
+typedef struct {
+  int64_t* Lp;
+  int32_t* super_ptr;
+  int32_t* n_super;
+  int32_t* super_of;
+  int32_t* super_parent;
+  int64_t* Lx_ptr;
+  uint32_t* status;
+} fp_super_result;
+
+/* Bytes of device workspace fp_supernodes needs for n columns. */
+fp_status fp_supernodes_query(int64_t n, size_t* workspace_bytes);
+fp_status fp_supernodes(fp_handle* h, int64_t n, const int32_t* parent, const int32_t* colcount,
+                        void* workspace, size_t ws_bytes, fp_super_result* out, void* stream);
+
 /* Synchronise `stream` and translate the device error bits of the last
  * call that used `workspace`. */
 fp_status fp_last_error(fp_handle* h, void* workspace, void* stream);
@@ -181,15 +229,19 @@ fp_status fp_kernel_time(fp_handle* h, float* total_ms, int32_t* launches);
  * optional user grouping user_gmap[i] (user_gmap itself may be NULL) and
  * outputs out[i]; its result is exactly what fp_order gives for it alone.
  * The matrices run concurrently on `lanes` streams owned by the handle
- * (1 <= lanes <= 64; one host worker thread per lane, largest matrices
- * first).  All pointers in A/out/user_gmap are device pointers owned by the
+ * (1 <= lanes <= 64; one host thread per lane queues that lane's share).  All pointers in A/out/user_gmap are device pointers owned by the
  * caller.
  * fp_query_batch: workspace size for `lanes` lanes (lanes slices of
  * *lane_bytes each, enough for the largest matrix) and the largest
  * node_begin/node_size capacity among the matrices.
- * fp_order_batch: runs after prior work on `stream`; `stream` waits for the
- * whole batch.  Returns when every matrix is done, with the first failing
- * status; out[i].status holds each matrix's device error bits. */
+ * fp_order_batch: asynchronous like fp_order.  The lanes start after prior
+ * work on `stream` and `stream` waits for the whole batch (events); the call
+ * returns once everything is queued.  Matrices are assigned to lanes before
+ * anything is queued (largest first, each to the lane with the fewest
+ * vertices so far) and each lane's thread queues its matrices back to back.
+ * The return value reports argument and HIP errors; device errors of
+ * matrix i are its out[i].status bits (0 = success), valid when `stream`
+ * reaches the end of the batch. */
 fp_status fp_query_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A, const fp_options* opts,
                          int32_t lanes, size_t* workspace_bytes, size_t* lane_bytes,
                          int32_t* max_nodes);

@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfastperm.so")
-SOURCES = ["fastperm.hip", "fp_runtime.hip"]
+SOURCES = ["fastperm.hip", "fp_runtime.hip", "fp_super.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -21,10 +22,33 @@
 #include "fp_plan.h"
 #include "fp_stages_sym.h"
 
-#define MESH                  \
-  const FpMesh& M = *Mp;      \
-  gptr<FpCtl> C = M.ctl;      \
+#define FP_CC_ROUNDS 4  // launched rounds of the orphan-component pass
+
+#define MESH0            \
+  const FpMesh& M = *Mp; \
+  gptr<FpCtl> C = M.ctl; \
   (void)C
+
+// Every stage after ingest stops at once when an earlier one raised an
+// error (its inputs may be unset).  A kernel on another stream may raise it
+// while this one starts, so the error word is read once per wave (MESH:
+// kernels whose waves never meet at a barrier) or once per workgroup and
+// shared through LDS (MESH_WG: kernels with workgroup barriers, which a
+// workgroup must reach whole).  MESH adds no LDS, so the kernels that take
+// all of it keep it.
+__device__ __forceinline__ bool wave_failed(gptr<FpCtl> C) { return uni((unsigned)C->err) != 0u; }
+__device__ __forceinline__ bool wg_failed(gptr<FpCtl> C) {
+  __shared__ unsigned fp_err_seen;
+  if (threadIdx.x == 0) fp_err_seen = C->err;
+  __syncthreads();
+  return fp_err_seen != 0;
+}
+#define MESH \
+  MESH0;     \
+  if (wave_failed(C)) return
+#define MESH_WG \
+  MESH0;        \
+  if (wg_failed(C)) return
 
 // ==========================================================================
 // generic helpers
@@ -35,13 +59,38 @@ __global__ void k_fill(int* a, int n, int v) {
 __global__ void k_copy(int* dst, const int* src, int n) {
   for (int i = gtid(); i < n; i += gsize()) dst[i] = src[i];
 }
+__global__ void k_put_mesh(FpMesh m, FpMesh* dst) {
+  if (gtid() == 0) *dst = m;
+}
 __global__ void k_set(int* a, const int* v) {
   if (gtid() == 0) *a = *v;
 }
+// A count that only the device knows (a patch or arc count): the value at
+// n_dev plus `add`, clamped to [0, cap]; without n_dev, cap itself.  Launch
+// grids are sized on the host from capacities or expected values, and every
+// loop runs to the count read here.
+__device__ __forceinline__ int dcount(const int* n_dev, int add, int cap) {
+  if (!n_dev) return cap;
+  const int x = *n_dev + add;
+  return x < 0 ? 0 : (x > cap ? cap : x);
+}
+__global__ void k_fill_n(int* a, const int* n_dev, int add, int cap, int v) {
+  const int n = dcount(n_dev, add, cap);
+  for (int i = gtid(); i < n; i += gsize()) a[i] = v;
+}
+__global__ void k_copy_n(int* dst, const int* src, const int* n_dev, int cap) {
+  const int n = dcount(n_dev, 0, cap);
+  for (int i = gtid(); i < n; i += gsize()) dst[i] = src[i];
+}
+// base[*idx] = *v, with *idx in [0, cap]
+__global__ void k_set_at(int* base, const int* idx, int cap, const int* v) {
+  if (gtid() == 0) base[dcount(idx, 0, cap)] = *v;
+}
 
 // exclusive scan, three passes: chunk sums, scan of the sums, chunk scans
-__global__ void k_scan_part(const int* in, int n, int chunk, int* part) {
+__global__ void k_scan_part(const int* in, int cap, const int* n_dev, int chunk, int* part) {
   __shared__ int tmp[FP_WAVES + 2];
+  const int n = dcount(n_dev, 0, cap);
   const int lo = min(n, (int)blockIdx.x * chunk), hi = min(n, lo + chunk);
   int s = 0;
   for (int i = lo + (int)threadIdx.x; i < hi; i += FP_WG) s += in[i];
@@ -62,8 +111,10 @@ __global__ void k_scan_top(int* part, int np, int* total) {
   }
   if (threadIdx.x == 0) *total = base;
 }
-__global__ void k_scan_apply(const int* in, int* out, int n, int chunk, const int* part) {
+__global__ void k_scan_apply(const int* in, int* out, int cap, const int* n_dev, int chunk,
+                             const int* part) {
   __shared__ int tmp[FP_WAVES + 2];
+  const int n = dcount(n_dev, 0, cap);
   const int lo = min(n, (int)blockIdx.x * chunk), hi = min(n, lo + chunk);
   int base = part[blockIdx.x];
   for (int t0 = lo; t0 < hi; t0 += FP_WG) {
@@ -80,15 +131,52 @@ __global__ void k_scan_apply(const int* in, int* out, int n, int chunk, const in
 // ingest: graph of A without its diagonal (Sec. 4.1 Step 2, Sec. 6.5)
 // ==========================================================================
 __global__ void k_ingest(const FpMesh* __restrict__ Mp, int fill) {
-  MESH;
+  MESH0;
+  if (fill && wave_failed(C)) return;
   unsigned eb = 0;
   for (int v = gtid(); v < M.n; v += gsize()) {
-    if (fill)
+    if (fill) {
       gather_vertex_row(M, v, M.gci + M.grp[v], &eb);
-    else
-      M.pcnt[v] = gather_vertex_row(M, v, gptr<int>(nullptr), &eb);
+    } else {
+      const int c = gather_vertex_row(M, v, gptr<int>(nullptr), &eb);
+      M.pcnt[v] = c < 0 ? 0 : c;
+      if (c < 0) M.fb[atomicAdd(&C->nlong, 1)] = v;  // a long row: listed
+    }
   }
   if (eb) fp_fail(C, eb, FP_SITE_INGEST, 0);
+}
+// rows of more than FP_ROW_SHORT input entries, a workgroup each
+__global__ void k_ingest_long(const FpMesh* __restrict__ Mp, int fill) {
+  MESH0;
+  __shared__ int red;
+  if (fill && wg_failed(C)) return;
+  unsigned eb = 0;
+  const int nl = C->nlong;
+  for (int l = blockIdx.x; l < nl; l += gridDim.x) {
+    const int v = M.fb[l];
+    const int c = ingest_long_row(M, v, fill ? M.gci + M.grp[v] : gptr<int>(nullptr), &eb, &red);
+    if (!fill && threadIdx.x == 0) M.pcnt[v] = c;
+  }
+  if (eb) fp_fail(C, eb, FP_SITE_INGEST, 0);
+}
+// the vertex graph fits its capacity (an int32 count that overflowed reads
+// negative); the fill pass and every later stage are gated on this
+__global__ void k_check_graph(const FpMesh* __restrict__ Mp) {
+  MESH0;
+  if (gtid() == 0 && (C->nnz_g < 0 || (long long)C->nnz_g > M.Ecap))
+    fp_fail(C, FP_E_SCRATCH, FP_SITE_GRAPH, C->nnz_g);
+}
+// every entry (v, u) of the graph has its mirror (u, v): the pattern of A is
+// symmetric (Sec. 4, inputs), block by block in block mode
+__global__ void k_validate(const FpMesh* __restrict__ Mp) {
+  MESH0;
+  if (wave_failed(C)) return;
+  for (int v = gtid(); v < M.n; v += gsize())
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++)
+      if (!row_has(M, M.gci[e], v)) {
+        fp_fail(C, FP_E_ASYM, FP_SITE_ASYM, v);
+        break;
+      }
 }
 
 // ==========================================================================
@@ -115,14 +203,20 @@ __global__ void k_seeds(const FpMesh* __restrict__ Mp, int P0) {
     const uint32_t vm = wave_min_u32(bh == hm ? bv : 0xFFFFFFFFu);
     if (lane_id() == 0) M.seeds[blk] = (int)vm;
   }
+  if (gtid() == 0) {
+    C->P0 = P0;
+    C->P = P0;
+  }
 }
 __global__ void k_key_unset(const FpMesh* __restrict__ Mp) {
   MESH;
   for (int v = gtid(); v < M.n; v += gsize()) M.key[v] = FP_UNSET;
   for (int i = gtid(); i < M.n + 16; i += gsize()) M.fcnt[i] = 0;
 }
+// nseeds < 0: every patch seed (the count is on the device)
 __global__ void k_seed_push(const FpMesh* __restrict__ Mp, int nseeds) {
   MESH;
+  if (nseeds < 0) nseeds = min(C->P, M.n);
   for (int k = gtid(); k < nseeds; k += gsize()) {
     const int s = M.seeds[k];
     atomicMin(&M.key[s], (unsigned long long)k);
@@ -188,6 +282,37 @@ __global__ void k_bfs_level(const FpMesh* __restrict__ Mp, int lvl) {
     }
   }
 }
+// Levels past the last launched one, in one workgroup: a level at a time
+// with a barrier between levels, until a frontier comes out empty (a BFS has
+// fewer than n levels).  Only a BFS deeper than the launched levels does
+// any work here; late frontiers are small.  The agent-scope fences around
+// each barrier make the level's claims and appends (in L2) visible to every
+// lane's next loads, which would otherwise be served from this CU's L1.
+__device__ __forceinline__ void wg_level_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+__global__ void __launch_bounds__(1024) k_bfs_tail(const FpMesh* __restrict__ Mp, int lvl0) {
+  MESH_WG;
+  wg_level_barrier();
+  for (int lvl = lvl0; lvl < M.n + 15; lvl++) {
+    const int nf = M.fcnt[lvl];
+    if (nf == 0) break;
+    gptr<const int> cur = (lvl & 1) ? M.fb : M.fa;
+    gptr<int> nxt = (lvl & 1) ? M.fa : M.fb;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+      const int v = cur[f];
+      const unsigned long long kv = M.key[v] + (1ull << 32);
+      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+        const int u = M.gci[e];
+        if (M.key[u] > kv && atomicMin(&M.key[u], kv) == FP_UNSET)
+          nxt[atomicAdd(&M.fcnt[lvl + 1], 1)] = u;
+      }
+    }
+    wg_level_barrier();
+  }
+}
 __global__ void k_count_unset(const FpMesh* __restrict__ Mp) {
   MESH;
   int cnt = 0;
@@ -197,15 +322,21 @@ __global__ void k_count_unset(const FpMesh* __restrict__ Mp) {
 }
 // components without a seed: min-label fixed point, then ids P0 + rank of
 // the component's lowest vertex
+// Every kernel of this pass returns at once when growth left no vertex
+// unlabelled.  Rounds of hooking and pointer jumping run as separate
+// launches while the previous round changed a label; a one-workgroup tail
+// finishes any component the rounds did not settle.
 __global__ void k_cc_init(const FpMesh* __restrict__ Mp) {
   MESH;
+  const bool any = C->norphan > 0;
+  if (gtid() == 0) C->ccn = any ? M.n : 0;
+  if (!any) return;
   for (int v = gtid(); v < M.n; v += gsize()) M.fb[v] = (M.key[v] == FP_UNSET) ? v : -1;
 }
-__global__ void k_cc_hook(const FpMesh* __restrict__ Mp) {
-  MESH;
+__device__ __forceinline__ bool cc_hook_pass(const FpMesh& M, int i0, int di) {
   gptr<int> comp = M.fb;
-  int ch = 0;
-  for (int v = gtid(); v < M.n; v += gsize()) {
+  bool ch = false;
+  for (int v = i0; v < M.n; v += di) {
     const int cv = comp[v];
     if (cv < 0) continue;
     for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
@@ -213,33 +344,68 @@ __global__ void k_cc_hook(const FpMesh* __restrict__ Mp) {
       if (cu >= 0 && cu < cv) {
         atomicMin(&comp[cv], cu);  // hook the larger label under the smaller
         atomicMin(&comp[v], cu);
-        ch = 1;
+        ch = true;
       }
     }
   }
-  if (ch) atomicOr((unsigned*)&C->chg, 1u);
+  return ch;
 }
-__global__ void k_cc_jump(const FpMesh* __restrict__ Mp) {
-  MESH;
+__device__ __forceinline__ bool cc_jump_pass(const FpMesh& M, int i0, int di) {
   gptr<int> comp = M.fb;
-  int ch = 0;
-  for (int v = gtid(); v < M.n; v += gsize()) {
+  bool ch = false;
+  for (int v = i0; v < M.n; v += di) {
     if (comp[v] < 0) continue;
     int c = comp[v];
     while (comp[c] != c) c = comp[c];
     if (c != comp[v]) {
       comp[v] = c;
-      ch = 1;
+      ch = true;
     }
   }
-  if (ch) atomicOr((unsigned*)&C->chg, 1u);
+  return ch;
+}
+// round r runs while round r-1 changed something
+__device__ __forceinline__ bool cc_round_live(gptr<FpCtl> C, int r) {
+  return C->norphan > 0 && (r == 0 || C->ccchg[r - 1] != 0);
+}
+__global__ void k_cc_hook(const FpMesh* __restrict__ Mp, int r) {
+  MESH;
+  if (!cc_round_live(C, r)) return;
+  if (cc_hook_pass(M, gtid(), gsize())) atomicOr(&C->ccchg[r], 1);
+}
+__global__ void k_cc_jump(const FpMesh* __restrict__ Mp, int r) {
+  MESH;
+  if (!cc_round_live(C, r)) return;
+  if (cc_jump_pass(M, gtid(), gsize())) atomicOr(&C->ccchg[r], 1);
+}
+__global__ void __launch_bounds__(1024) k_cc_tail(const FpMesh* __restrict__ Mp, int r0) {
+  MESH_WG;
+  __shared__ int chg;
+  if (!cc_round_live(C, r0)) return;
+  if (threadIdx.x == 0) chg = 0;
+  wg_level_barrier();
+  while (true) {
+    bool ch = cc_hook_pass(M, threadIdx.x, blockDim.x);
+    wg_level_barrier();
+    ch |= cc_jump_pass(M, threadIdx.x, blockDim.x);
+    if (ch) atomicOr(&chg, 1);
+    wg_level_barrier();
+    const int c = chg;
+    __syncthreads();  // every lane has read the flag before it is cleared
+    if (threadIdx.x == 0) chg = 0;
+    if (!c) break;
+  }
 }
 __global__ void k_cc_flags(const FpMesh* __restrict__ Mp) {
   MESH;
+  if (C->norphan == 0) return;
   for (int v = gtid(); v < M.n; v += gsize()) M.pcnt[v] = (M.fb[v] == v) ? 1 : 0;
 }
-__global__ void k_cc_label(const FpMesh* __restrict__ Mp, int P0) {
+// ids P0 + rank of the component's lowest vertex; P grows by the count
+__global__ void k_cc_label(const FpMesh* __restrict__ Mp) {
   MESH;
+  if (C->norphan == 0) return;
+  const int P0 = C->P0;
   for (int v = gtid(); v < M.n; v += gsize()) {
     const int c = M.fb[v];
     if (c < 0) continue;
@@ -247,13 +413,15 @@ __global__ void k_cc_label(const FpMesh* __restrict__ Mp, int P0) {
     M.key[v] = (unsigned long long)id;
     if (c == v) M.seeds[id] = v;
   }
+  if (gtid() == 0) C->P = P0 + C->nroot;
 }
 // Lloyd re-centre: new seed = vertex farthest from the patch boundary (the
 // distance inside the patch equals the distance to the boundary set of the
 // whole graph, because any path out of a patch passes its own boundary
 // first), ties to the lowest id; patches without a boundary keep their seed.
-__global__ void k_lloyd_gmap(const FpMesh* __restrict__ Mp, int P) {
+__global__ void k_lloyd_gmap(const FpMesh* __restrict__ Mp) {
   MESH;
+  const int P = C->P;
   for (int v = gtid(); v < M.n; v += gsize()) M.gmap[v] = (int)(M.key[v] & 0xFFFFFFFFu);
   for (int p = gtid(); p < P; p += gsize()) M.best[p] = 0;
   for (int i = gtid(); i < M.n + 16; i += gsize()) M.fcnt[i] = 0;
@@ -261,7 +429,7 @@ __global__ void k_lloyd_gmap(const FpMesh* __restrict__ Mp, int P) {
 // (the loops below step a whole workgroup at a time: wg_append holds a
 // barrier, and a single list counter takes one atomic per workgroup)
 __global__ void k_lloyd_bnd(const FpMesh* __restrict__ Mp) {
-  MESH;
+  MESH_WG;
   __shared__ int lds2[2];
   for (int v0 = (int)(blockIdx.x * blockDim.x); v0 < M.n; v0 += (int)(gridDim.x * blockDim.x)) {
     const int v = v0 + (int)threadIdx.x;
@@ -299,22 +467,23 @@ __global__ void k_lloyd_best(const FpMesh* __restrict__ Mp) {
     }
   }
 }
-__global__ void k_lloyd_seed(const FpMesh* __restrict__ Mp, int P) {
+__global__ void k_lloyd_seed(const FpMesh* __restrict__ Mp) {
   MESH;
+  const int P = C->P;
   for (int p = gtid(); p < P; p += gsize()) {
     const unsigned long long bb = M.best[p];
     if (bb) M.seeds[p] = (int)(0xFFFFFFFFu - (unsigned)(bb & 0xFFFFFFFFu));
   }
 }
-__global__ void k_gmap_final(const FpMesh* __restrict__ Mp, int P) {
+__global__ void k_gmap_final(const FpMesh* __restrict__ Mp) {
   MESH;
+  const int P = C->P;
   for (int v = gtid(); v < M.n; v += gsize()) {
     const unsigned long long k = M.key[v];
     const int g = k == FP_UNSET ? -1 : (int)(k & 0xFFFFFFFFu);
     if (g < 0 || g >= P) fp_fail(C, FP_E_INTERNAL, FP_SITE_GMAP_LABEL, v);
     M.gmap[v] = (g < 0 || g >= P) ? 0 : g;
   }
-  if (gtid() == 0) C->P = P;
 }
 __global__ void k_user_gmap(const FpMesh* __restrict__ Mp) {
   MESH;
@@ -336,7 +505,7 @@ __global__ void k_user_gmap(const FpMesh* __restrict__ Mp) {
 // patch members, boundary list, quotient graph (Sec. 2; built once, Sec. 5)
 // ==========================================================================
 __global__ void k_patch_count(const FpMesh* __restrict__ Mp) {
-  MESH;
+  MESH_WG;
   __shared__ int lds2[2];
   for (int v0 = (int)(blockIdx.x * blockDim.x); v0 < M.n; v0 += (int)(gridDim.x * blockDim.x)) {
     const int v = v0 + (int)threadIdx.x;
@@ -365,9 +534,11 @@ __global__ void k_patch_scatter(const FpMesh* __restrict__ Mp) {
 // LDS bitmap over the patch ids (bm_words words per wave) one pass over the
 // members marks the neighbours, their loads issued a row at a time, and the
 // bitmap is read back in order; without it, one pass per neighbour.
-__global__ void k_qrow(const FpMesh* __restrict__ Mp, int P, int fill, int bm_words) {
+__global__ void k_qrow(const FpMesh* __restrict__ Mp, int fill, int lds_words) {
   MESH;
   FP_LDS_DECL;
+  const int P = C->P;
+  const int bm_words = (P + 31) / 32 <= lds_words ? (P + 31) / 32 : 0;
   uint32_t* bm = (uint32_t*)fp_lds + (long long)bm_words * wave_id();
   for (int p = gwave(); p < P; p += nwaves()) {
     const int a0 = M.pptr[p], a1 = M.pptr[p + 1];
@@ -430,14 +601,28 @@ __global__ void k_qrow(const FpMesh* __restrict__ Mp, int P, int fill, int bm_wo
   }
 }
 
+__global__ void k_check_arcs(const FpMesh* __restrict__ Mp) {
+  MESH;
+  if (gtid() == 0 && (C->nq < 0 || (long long)C->nq > M.Ecap))
+    fp_fail(C, FP_E_SCRATCH, FP_SITE_QARCS, C->nq);
+}
+
 // ==========================================================================
 // separator tree (Sec. 4.2 Step 3; Alg. 2; Sec. 5).  Level d: recount the
 // alive quotient arcs from the boundary list, bisect every node of depth d,
 // SuperSeparator (unmarked vertices with an unmarked neighbour across) and
 // RefineSeparator (keep the smaller side, ties to the left).
 // ==========================================================================
-__global__ void k_sep_init(const FpMesh* __restrict__ Mp, int P, int D, int nn) {
+__global__ void k_sep_init(const FpMesh* __restrict__ Mp) {
   MESH;
+  const int P = C->P;
+  int D = 0;
+  while ((1ll << D) < P) D++;
+  const int nn = (1 << (D + 1)) - 1;
+  if (nn > M.NNcap) {  // never expected: NNcap holds the tree of n patches
+    if (gtid() == 0) fp_fail(C, FP_E_SCRATCH, FP_SITE_TREE, nn);
+    return;
+  }
   if (gtid() == 0) {
     C->D = D;
     C->nn = nn;
@@ -455,8 +640,16 @@ __global__ void k_sep_init(const FpMesh* __restrict__ Mp, int P, int D, int nn) 
   }
   if (gtid() == 0) M.segN[0] = P;
 }
-__global__ void k_arcs(const FpMesh* __restrict__ Mp) {
+// level d of the tree: alive arcs recounted from zero
+__global__ void k_level_begin(const FpMesh* __restrict__ Mp, int d) {
   MESH;
+  if (d >= C->D) return;
+  const int nq = min(C->nq, (int)M.Ecap);
+  for (int a = gtid(); a < nq; a += gsize()) M.qcnt[a] = 0;
+}
+__global__ void k_arcs(const FpMesh* __restrict__ Mp, int d) {
+  MESH;
+  if (d >= C->D) return;
   const int nb = C->nbnd;
   for (int i = gtid(); i < nb; i += gsize()) {
     const int v = M.bnd[i];
@@ -490,9 +683,10 @@ __global__ void k_arcs(const FpMesh* __restrict__ Mp) {
 }
 __global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ Mp, int d,
                                                    int lds_bytes) {
-  MESH;
+  MESH_WG;
   __shared__ BisectLds sh;
   FP_LDS_DECL;
+  if (d >= C->D) return;
   const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
   for (int t = lo + (int)blockIdx.x; t < hi; t += (int)gridDim.x) {
     const int m = M.segN[t];
@@ -501,6 +695,7 @@ __global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ Mp,
 }
 __global__ void k_cand(const FpMesh* __restrict__ Mp, int d) {
   MESH;
+  if (d >= C->D) return;
   const int hi = (1 << (d + 1)) - 1;
   const int nb = C->nbnd;
   for (int i = gtid(); i < nb; i += gsize()) {
@@ -533,8 +728,9 @@ __global__ void k_cand(const FpMesh* __restrict__ Mp, int d) {
     }
   }
 }
-__global__ void k_mark(const FpMesh* __restrict__ Mp) {
+__global__ void k_mark(const FpMesh* __restrict__ Mp, int d) {
   MESH;
+  if (d >= C->D) return;
   const int nb = C->nbnd;
   for (int i = gtid(); i < nb; i += gsize()) {
     if (!M.cand[i]) continue;
@@ -559,8 +755,10 @@ __global__ void k_leaves(const FpMesh* __restrict__ Mp) {
 // ==========================================================================
 // grouping in schedule order (Alg. 3)
 // ==========================================================================
-__global__ void k_nsize(const FpMesh* __restrict__ Mp, int nn) {
+__global__ void k_nsize(const FpMesh* __restrict__ Mp) {
   MESH;
+  const int nn = C->nn;
+  for (int x = gtid(); x < nn; x += gsize()) M.nsize[x] = 0;
   for (int v = gtid(); v < M.n; v += gsize()) {
     if ((unsigned)M.node_of[v] >= (unsigned)nn) {  // never expected
       fp_fail(C, FP_E_INTERNAL, FP_SITE_NODE_OF, v);
@@ -576,12 +774,14 @@ __global__ void k_nsize_count(const FpMesh* __restrict__ Mp) {
     (void)wave_append_keyed(M.nsize, act ? M.node_of[v] : 0, act);
   }
 }
-__global__ void k_sched_place(const FpMesh* __restrict__ Mp, int nn, int D) {
+__global__ void k_sched_place(const FpMesh* __restrict__ Mp) {
   MESH;
+  const int nn = C->nn, D = C->D;
   for (int x = gtid(); x < nn; x += gsize()) M.sbuf[sched_pos(x, D, M.sched)] = M.nsize[x];
 }
-__global__ void k_nbegin(const FpMesh* __restrict__ Mp, int nn, int D) {
+__global__ void k_nbegin(const FpMesh* __restrict__ Mp) {
   MESH;
+  const int nn = C->nn, D = C->D;
   for (int x = gtid(); x < nn; x += gsize()) {
     const int b = M.sbuf[sched_pos(x, D, M.sched)];
     M.nbegin[x] = b;
@@ -605,8 +805,9 @@ __global__ void k_scatter(const FpMesh* __restrict__ Mp) {
 // (a counting sort on size / 16, one workgroup): a class with more nodes
 // than resident slots then ends with its smallest nodes, not its largest.
 #define FP_TASK_BUCKETS 256
-__global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ Mp, int nn, int ntop) {
-  MESH;
+__global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ Mp, int ntop) {
+  MESH_WG;
+  const int nn = C->nn;
   __shared__ int hist[FP_MD_CLASSES * FP_TASK_BUCKETS];
   for (int i = threadIdx.x; i < FP_MD_CLASSES * FP_TASK_BUCKETS; i += blockDim.x) hist[i] = 0;
   __syncthreads();
@@ -661,6 +862,7 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
 // grouping proceed.
 __global__ void k_top_count(const FpMesh* __restrict__ Mp, int d) {
   MESH;
+  if (d >= C->D) return;
   const int lo = (1 << d) - 1, hi = (2 << d) - 1;
   for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
     const int v = v0 + lane_id();
@@ -671,7 +873,7 @@ __global__ void k_top_count(const FpMesh* __restrict__ Mp, int d) {
 }
 __global__ void k_top_place(const FpMesh* __restrict__ Mp, int d) {
   MESH;
-  if (gtid() != 0) return;
+  if (gtid() != 0 || d >= C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
   // A node that held a single patch at its level is a leaf: it gets that
   // patch's unmarked vertices only after the tree is done, and it also
@@ -696,7 +898,7 @@ __global__ void k_top_place(const FpMesh* __restrict__ Mp, int d) {
 }
 __global__ void k_top_scatter(const FpMesh* __restrict__ Mp, int d) {
   MESH;
-  if (C->top_stop) return;
+  if (C->top_stop || d >= C->D) return;
   const int lo = (1 << d) - 1, hi = (2 << d) - 1;
   for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
     const int v = v0 + lane_id();
@@ -710,6 +912,7 @@ __global__ void k_top_scatter(const FpMesh* __restrict__ Mp, int d) {
 __global__ void __launch_bounds__(64) k_md_top(const FpMesh* __restrict__ Mp, int d) {
   MESH;
   FP_LDS_DECL;
+  if (d >= uni(C->D)) return;
   const int t = uni((1 << d) - 1 + (int)blockIdx.x);
   if (!uni(C->tearly[t])) return;
   const int m = uni(C->tcnt[t]), off = uni(C->toff[t]), pos0 = uni(C->tpos[t]);
@@ -722,6 +925,7 @@ __global__ void __launch_bounds__(64) k_md_top(const FpMesh* __restrict__ Mp, in
 // the schedule's ranges must be the ones the early orders took
 __global__ void k_top_check(const FpMesh* __restrict__ Mp, int ntop) {
   MESH;
+  ntop = min(ntop, C->nn);
   for (int t = gtid(); t < ntop; t += gsize())
     if (C->tearly[t] &&
         (M.nsize[t] != C->tcnt[t] || (M.nsize[t] > 0 && M.nbegin[t] != C->tpos[t])))
@@ -733,7 +937,7 @@ __global__ void k_top_check(const FpMesh* __restrict__ Mp, int ntop) {
 // ==========================================================================
 __global__ void k_sym_init(const FpMesh* __restrict__ Mp, int d) {
   MESH;
-  if (gtid() == 0) {
+  if (gtid() == 0 && d <= C->D) {
     C->arena_top[d & 1] = 0;
     C->pool_top = 0;  // the pool holds one level's node scratch at a time
   }
@@ -741,6 +945,7 @@ __global__ void k_sym_init(const FpMesh* __restrict__ Mp, int d) {
 __global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ Mp, int d) {
   MESH;
   FP_LDS_DECL;
+  if (d > C->D) return;
   const int lw = M.lds_bytes / 4 / FP_WAVES;
   int* slice = (int*)fp_lds + lw * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
@@ -752,6 +957,7 @@ __global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ M
 __global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ Mp, int d, int cls) {
   MESH;
   FP_LDS_DECL;
+  if (d > C->D) return;
   const int nsl = cls == 0 ? FP_WAVES : 1;
   if (wave_id() >= nsl) return;
   int* slice = (int*)fp_lds + (M.lds_bytes / 4 / nsl) * wave_id();
@@ -763,11 +969,13 @@ __global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ M
 // nodes too large for the whole LDS: links and rows in global memory
 __global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(const FpMesh* __restrict__ Mp, int d) {
   MESH;
+  if (d > C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
   for (int x = gwave(); x < cnt; x += nwaves()) sym_elim<false>(M, lo + x, 2, nullptr, 0);
 }
 __global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ Mp, int d) {
   MESH;
+  if (d > C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
   for (int x = gwave(); x < cnt; x += nwaves()) sym_emit(M, lo + x, d);
 }
@@ -793,7 +1001,7 @@ __global__ void k_prow_fill(const FpMesh* __restrict__ Mp) {
 }
 // nnz(L): the column counts summed per workgroup, one atomic each
 __global__ void __launch_bounds__(FP_WG) k_nnzl(const FpMesh* __restrict__ Mp) {
-  MESH;
+  MESH_WG;
   __shared__ long long part[FP_WAVES];
   long long s = 0;
   for (int i = gtid(); i < M.n; i += gsize()) s += M.vcc[i];
@@ -810,8 +1018,9 @@ __global__ void __launch_bounds__(FP_WG) k_nnzl(const FpMesh* __restrict__ Mp) {
 // ==========================================================================
 // block expansion and outputs (Sec. 6.5)
 // ==========================================================================
-__global__ void k_expand(const FpMesh* __restrict__ Mp, int nn) {
+__global__ void k_expand(const FpMesh* __restrict__ Mp) {
   MESH;
+  const int nn = C->nn;
   const int b = M.b;
   const long long nd = M.n_dof;
   for (long long j = gtid(); j < nd; j += gsize()) {
@@ -829,9 +1038,10 @@ __global__ void k_expand(const FpMesh* __restrict__ Mp, int nn) {
       if (M.node_size_out) M.node_size_out[x] = M.nsize[x] * b;
     }
 }
-__global__ void k_finish(const FpMesh* __restrict__ Mp, int nn) {
-  MESH;
+__global__ void k_finish(const FpMesh* __restrict__ Mp) {
+  MESH0;
   if (gtid() != 0) return;
+  const int nn = C->nn;
   if ((M.node_begin_out || M.node_size_out) && nn > M.max_nodes_out)
     fp_fail(C, FP_E_SCRATCH, FP_SITE_OUT_NODES, nn);
   *M.nnzL = (long long)M.b * M.b * C->nnzL - (long long)M.n * M.b * (M.b - 1) / 2;
@@ -883,7 +1093,8 @@ fp_status check_opts(const fp_options* o) {
   if (o->patch_size < 1 || o->block_size < 1 || o->lloyd_iters < 0 || o->lloyd_iters > 64)
     return FP_ERR_ARG;
   if (o->schedule != FP_SCHED_LEVEL && o->schedule != FP_SCHED_POST) return FP_ERR_ARG;
-  if (o->nd_level != -1 || (o->flags & ~FP_FLAG_TIMING)) return FP_ERR_UNSUPPORTED;
+  if (o->nd_level != -1 || (o->flags & ~(FP_FLAG_TIMING | FP_FLAG_VALIDATE)))
+    return FP_ERR_UNSUPPORTED;
   return FP_OK;
 }
 
@@ -899,6 +1110,7 @@ fp_status check_csr(const fp_csr* A, int b) {
 
 fp_status map_err(unsigned e) {
   if (e & (FP_E_INDEX | FP_E_GMAP)) return FP_ERR_INDEX;
+  if (e & FP_E_ASYM) return FP_ERR_NOT_SYMMETRIC;
   if (e & FP_E_SCRATCH) return FP_ERR_SIZE;
   if (e) return FP_ERR_DEVICE;
   return FP_OK;
@@ -926,6 +1138,7 @@ struct Job {
   FpCtl* ctl;
   bool hip_failed = false;
   bool timing = false;
+  bool validate = false;    // symmetry check of the pattern
   bool fixed = false;       // no side streams and no per-kernel events (static-scratch calls)
   bool side_open = false;   // work on the side stream not yet joined
   bool side2_open = false;  // same for the second side stream
@@ -995,50 +1208,34 @@ struct Job {
     read(&ctl->err, 1);
     return hip_failed ? 0xFFFFFFFFu : (unsigned)h->host[0];
   }
-  void scan(const int* in, int* out, int n, int* total) {
-    const int np = std::max(1, std::min(1024, (n + 4095) / 4096));
-    const int chunk = std::max(1, (n + np - 1) / np);
-    FPLM(k_scan_part, dim3(np), dim3(FP_WG), 0, st, in, n, chunk, ctl->part);
+  // exclusive scan of in[0..count) into out, total to *total; count is cap
+  // or, with n_dev, the device value clamped to cap
+  void scan(const int* in, int* out, int cap, int* total, const int* n_dev = nullptr) {
+    const int np = std::max(1, std::min(1024, (cap + 4095) / 4096));
+    const int chunk = std::max(1, (cap + np - 1) / np);
+    FPLM(k_scan_part, dim3(np), dim3(FP_WG), 0, st, in, cap, n_dev, chunk, ctl->part);
     FPLM(k_scan_top, dim3(1), dim3(FP_WG), 0, st, ctl->part, np, total);
-    FPLM(k_scan_apply, dim3(np), dim3(FP_WG), 0, st, in, out, n, chunk, ctl->part);
+    FPLM(k_scan_apply, dim3(np), dim3(FP_WG), 0, st, in, out, cap, n_dev, chunk, ctl->part);
     check();
   }
-  // frontier BFS from the level-0 frontier already in place; levels are
-  // launched in batches of 8.  The next batch is queued before the host
-  // looks at the frontier size the previous one left, so the GPU never
-  // waits for that round trip; a batch queued past the last level finds
-  // empty frontiers and returns at once.
-  void bfs() {
+  // Frontier BFS from the level-0 frontier already in place: `levels`
+  // launches of a level each (a launch past the last level finds an empty
+  // frontier and returns at once), then one workgroup continues from there
+  // until a frontier comes out empty.  Nothing is read back.
+  void bfs(int levels) {
     const int n = hm.n;
-    // a BFS has fewer than n levels: levels up to n+15 read counters that
-    // stay zero (the counter array holds n+16 entries)
-    auto batch = [&](int lvl) {
-      for (int k = 0; k < 8; k++)
-        FPLM(k_bfs_level, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, lvl + k);
-      check();
-    };
-    batch(0);
-    for (int lvl = 0; lvl + 8 <= n && !hip_failed; lvl += 8) {
-      if (hipMemcpyAsync(h->host + 1, hm.fcnt + lvl + 8, 4, hipMemcpyDeviceToHost, st) !=
-              hipSuccess ||
-          hipEventRecord(h->ev_bfs, st) != hipSuccess) {
-        hip_failed = true;
-        break;
-      }
-      batch(lvl + 8);
-      if (hipEventSynchronize(h->ev_bfs) != hipSuccess) {
-        hip_failed = true;
-        break;
-      }
-      if (h->host[1] == 0) break;
-    }
+    const int L = std::max(0, std::min(levels, n));
+    for (int k = 0; k < L; k++) FPLM(k_bfs_level, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, k);
+    FPLM(k_bfs_tail, dim3(1), dim3(1024), 0, st, dm, L);
+    check();
   }
-  void grow(int nseeds) {
+  // nseeds < 0: the device patch count
+  void grow(int nseeds, int nseeds_exp, int levels) {
     const int n = hm.n;
     FPLM(k_key_unset, dim3(blocks(n)), dim3(FP_WG), 0, st, dm);
-    FPLM(k_seed_push, dim3(blocks(nseeds)), dim3(FP_WG), 0, st, dm, nseeds);
+    FPLM(k_seed_push, dim3(blocks(nseeds_exp)), dim3(FP_WG), 0, st, dm, nseeds);
     check();
-    bfs();
+    bfs(levels);
   }
 };
 
@@ -1067,6 +1264,25 @@ bool ensure_side(fp_handle* h) {
   return true;
 }
 
+// Levels of a growth BFS launched one by one before the tail takes over:
+// about twice the radius of a patch of S vertices on a triangle mesh, at
+// most 64.  The distance BFS of Lloyd's step runs inside patches (half).
+static int bfs_levels(int S, bool inner) {
+  const int r = (int)std::ceil(std::sqrt((double)std::max(S, 1)));
+  return std::min(64, (inner ? r : 2 * r) + 4);
+}
+static int ceil_log2(long long x) {
+  int d = 0;
+  while ((1ll << d) < x) d++;
+  return d;
+}
+
+// Queue the whole pipeline on J.st (and the side streams, joined back).
+// Nothing is read back to the host: counts known only on the device (patches,
+// tree depth, arcs, frontier sizes) are read there, launch grids come from
+// capacities or expected values, and every kernel returns at once once an
+// earlier stage has raised an error.  The tree depth D is at most
+// ceil(log2 n); levels past the expected depth get small grids.
 fp_status run_job(Job& J) {
   const int n = J.hm.n;
   const FpMesh* dm = J.dm;
@@ -1074,120 +1290,113 @@ fp_status run_job(Job& J) {
   FpCtl* C = J.ctl;
   auto B = [&](long long items) { return dim3(J.blocks(items)); };
   const dim3 T(FP_WG);
+  const int P0 = n > 0 ? (int)(((long long)n + J.hm.S - 1) / J.hm.S) : 0;
+  const int Pexp = std::max(P0, 1);            // expected patch count (exact without orphans)
+  const int Dexp = ceil_log2(Pexp);             // expected tree depth
+  const int Dmax = ceil_log2(std::max(n, 1));   // P <= n
+  auto BL = [&](int d, long long items) {       // grid of a tree level
+    return d <= Dexp ? B(items) : dim3(1);
+  };
 
   // ingest
   J.mark(0);
   FPL(k_ingest, B(n), T, 0, st, dm, 0);
+  FPL(k_ingest_long, dim3(J.h->ncu), T, 0, st, dm, 0);
   J.scan(J.hm.pcnt, J.hm.grp, n, &C->nnz_g);
-  J.read(&C->err, 8);
-  if (J.hip_failed) return FP_ERR_HIP;
-  const unsigned e0 = (unsigned)J.h->host[0];
-  const int nnz_g = J.h->host[5];
-  if (e0) return map_err(e0);
-  if (nnz_g < 0 || nnz_g > J.hm.Ecap) return FP_ERR_SIZE;
+  FPL(k_check_graph, dim3(1), dim3(64), 0, st, dm);
   FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.grp + n, &C->nnz_g);
   FPL(k_ingest, B(n), T, 0, st, dm, 1);
+  FPL(k_ingest_long, dim3(J.h->ncu), T, 0, st, dm, 1);
+  if (J.validate) FPL(k_validate, B(n), T, 0, st, dm);
   J.check();
 
   // patches
   J.mark(1);
-  int P = 0;
   if (J.hm.user_gmap) {
     FPL(k_user_gmap, B(n), T, 0, st, dm);
     J.check();
-    P = J.read1(&C->P);
   } else if (n > 0) {
-    const int P0 = (int)(((long long)n + J.hm.S - 1) / J.hm.S);
+    const int Lg = bfs_levels(J.hm.S, false), Ld = bfs_levels(J.hm.S, true);
     FPL(k_seeds, dim3(J.blocks(P0, FP_WAVES)), T, 0, st, dm, P0);
     J.check();
-    J.grow(P0);
+    J.grow(P0, P0, Lg);
     FPL(k_count_unset, B(n), T, 0, st, dm);
-    J.check();
-    P = P0;
-    if (J.read1(&C->norphan) > 0) {
-      FPL(k_cc_init, B(n), T, 0, st, dm);
-      for (int it = 0; it < n + 1; it++) {
-        FPL(k_fill, dim3(1), dim3(64), 0, st, &C->chg, 1, 0);
-        FPL(k_cc_hook, B(n), T, 0, st, dm);
-        FPL(k_cc_jump, B(n), T, 0, st, dm);
-        J.check();
-        if (J.read1(&C->chg) == 0 || J.hip_failed) break;
-      }
-      FPL(k_cc_flags, B(n), T, 0, st, dm);
-      J.scan(J.hm.pcnt, J.hm.pcnt, n, &C->nroot);
-      FPL(k_cc_label, B(n), T, 0, st, dm, P0);
-      J.check();
-      P = P0 + J.read1(&C->nroot);
+    // components growth did not reach (none on a connected mesh: every
+    // kernel here then returns at once)
+    FPL(k_cc_init, B(n), T, 0, st, dm);
+    for (int r = 0; r < FP_CC_ROUNDS; r++) {
+      FPL(k_cc_hook, B(n), T, 0, st, dm, r);
+      FPL(k_cc_jump, B(n), T, 0, st, dm, r);
     }
+    FPL(k_cc_tail, dim3(1), dim3(1024), 0, st, dm, FP_CC_ROUNDS);
+    FPL(k_cc_flags, B(n), T, 0, st, dm);
+    J.scan(J.hm.pcnt, J.hm.pcnt, n, &C->nroot, &C->ccn);
+    FPL(k_cc_label, B(n), T, 0, st, dm);
+    J.check();
     for (int it = 0; it < J.hm.lloyd; it++) {
-      FPL(k_lloyd_gmap, B(n), T, 0, st, dm, P);
+      FPL(k_lloyd_gmap, B(n), T, 0, st, dm);
       FPL(k_lloyd_bnd, B(n), T, 0, st, dm);
       J.check();
-      J.bfs();
+      J.bfs(Ld);
       FPL(k_lloyd_best, B(n), T, 0, st, dm);
-      FPL(k_lloyd_seed, B(P), T, 0, st, dm, P);
+      FPL(k_lloyd_seed, B(Pexp), T, 0, st, dm);
       J.check();
-      J.grow(P);
+      J.grow(-1, Pexp, Lg);
     }
-    FPL(k_gmap_final, B(n), T, 0, st, dm, P);
+    FPL(k_gmap_final, B(n), T, 0, st, dm);
     J.check();
   }
-  if (J.hip_failed) return FP_ERR_HIP;
-  if (P < 0 || P > std::max(n, 1)) return FP_ERR_DEVICE;
 
-  // quotient graph
+  // quotient graph (P on the device)
   J.mark(2);
-  FPL(k_fill, B(P + 1), T, 0, st, J.hm.pcnt, P + 1, 0);
+  FPL(k_fill_n, B(Pexp + 1), T, 0, st, J.hm.pcnt, &C->P, 1, n + 1, 0);
   FPL(k_fill, dim3(1), dim3(64), 0, st, &C->nbnd, 1, 0);
   FPL(k_patch_count, B(n), T, 0, st, dm);
-  FPL(k_copy, B(P), T, 0, st, J.hm.wp, J.hm.pcnt, P);
+  FPL(k_copy_n, B(Pexp), T, 0, st, J.hm.wp, J.hm.pcnt, &C->P, n);
   J.check();
-  J.scan(J.hm.pcnt, J.hm.pptr, P, &C->tot);
-  FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.pptr + P, &C->tot);
-  FPL(k_copy, B(P), T, 0, st, J.hm.pcnt, J.hm.pptr, P);
+  J.scan(J.hm.pcnt, J.hm.pptr, n, &C->tot, &C->P);
+  FPL(k_set_at, dim3(1), dim3(1), 0, st, J.hm.pptr, &C->P, n, &C->tot);
+  FPL(k_copy_n, B(Pexp), T, 0, st, J.hm.pcnt, J.hm.pptr, &C->P, n);
   FPL(k_patch_scatter, B(n), T, 0, st, dm);
-  // a patch-id bitmap per wave when four of them fit in 64 KB of LDS
-  const int qbw = (long long)(P + 31) / 32 * 4 * FP_WAVES <= 65536 ? (P + 31) / 32 : 0;
-  FPL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, qbw * 4 * FP_WAVES, st, dm, P, 0, qbw);
+  // a patch-id bitmap per wave when four of them fit in 64 KB of LDS (for
+  // the expected patch count; the kernel checks the actual one)
+  const int qbw = (long long)(Pexp + 31) / 32 * 4 * FP_WAVES <= 65536 ? (Pexp + 31) / 32 : 0;
+  FPL(k_qrow, dim3(J.blocks(Pexp, FP_WAVES)), T, qbw * 4 * FP_WAVES, st, dm, 0, qbw);
   J.check();
-  J.scan(J.hm.pcnt, J.hm.qptr, P, &C->nq);
-  FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.qptr + P, &C->nq);
-  const int nq = J.read1(&C->nq);
-  if (J.hip_failed) return FP_ERR_HIP;
-  if (nq < 0 || nq > J.hm.Ecap) return FP_ERR_SIZE;
-  FPL(k_qrow, dim3(J.blocks(P, FP_WAVES)), T, qbw * 4 * FP_WAVES, st, dm, P, 1, qbw);
+  J.scan(J.hm.pcnt, J.hm.qptr, n, &C->nq, &C->P);
+  FPL(k_set_at, dim3(1), dim3(1), 0, st, J.hm.qptr, &C->P, n, &C->nq);
+  FPL(k_check_arcs, dim3(1), dim3(64), 0, st, dm);
+  FPL(k_qrow, dim3(J.blocks(Pexp, FP_WAVES)), T, qbw * 4 * FP_WAVES, st, dm, 1, qbw);
   J.check();
 
   // separator tree
   J.mark(3);
-  int D = 0;
-  while ((1ll << D) < P) D++;
-  const int nn = (1 << (D + 1)) - 1;
-  if (nn > J.hm.NNcap) return FP_ERR_SIZE;
-  FPL(k_sep_init, B(std::max(n, nn)), T, 0, st, dm, P, D, nn);
-  // top separators ordered early on the side stream (level order only: there
-  // their ranges depend on the top levels alone)
-  const int TL =
-      J.hm.sched == 0 && !J.fixed && J.h->side_ok && ensure_side(J.h) ? std::min(FP_TOP_LEVELS, D)
-                                                                       : 0;
+  FPL(k_sep_init, B(n), T, 0, st, dm);
+  // top separators ordered early on the side streams (level order only:
+  // there their ranges depend on the top levels alone)
+  const int TL = J.hm.sched == 0 && !J.fixed && J.h->side_ok && ensure_side(J.h)
+                     ? std::min(FP_TOP_LEVELS, Dmax)
+                     : 0;
   const int ntop = (1 << TL) - 1;
-  for (int d = 0; d < D; d++) {
-    FPL(k_fill, B(nq), T, 0, st, J.hm.qcnt, nq, 0);
-    FPL(k_arcs, B(n), T, 0, st, dm);
+  for (int d = 0; d < Dmax; d++) {
+    FPL(k_level_begin, BL(d, 8ll * Pexp), T, 0, st, dm, d);
+    FPL(k_arcs, BL(d, n), T, 0, st, dm, d);
     {
-      // LDS for the local quotient subgraphs: a node at depth d holds at most
-      // 2^(D-d) patches.  While the level has no more nodes than CUs, each
-      // workgroup takes the large LDS (quotient degrees can pass 8); deeper,
-      // about 8 alive arcs per patch, so several workgroups share a CU.  The
+      // LDS for the local quotient subgraphs: a node at depth d holds about
+      // 2^(Dexp-d) patches.  While the level has no more nodes than CUs,
+      // each workgroup takes the large LDS (quotient degrees can pass 8);
+      // deeper, about 8 alive arcs per patch, so several workgroups share a
+      // CU (a node that does not fit runs from global memory).  The
       // kernel's static LDS comes on top.
-      const long long cap = 1ll << (D - d);
+      const long long cap = 1ll << std::max(0, Dexp - d);
       const long long want =
           (1ll << d) <= J.h->ncu ? J.h->lds_big : (4 * (13 * cap + 1) + 255) & ~255ll;
       const int lb = (int)std::min<long long>(J.h->lds_big - 1024, want);
-      FPL(k_bisect, dim3(std::min(1 << d, 4 * J.h->ncu)), T, lb, st, dm, d, lb);
+      const dim3 gb = d <= Dexp ? dim3(std::min(1 << std::min(d, 30), 4 * J.h->ncu)) : dim3(1);
+      FPL(k_bisect, gb, T, lb, st, dm, d, lb);
     }
-    FPL(k_cand, B(n), T, 0, st, dm, d);
-    FPL(k_mark, B(n), T, 0, st, dm);
+    FPL(k_cand, BL(d, n), T, 0, st, dm, d);
+    FPL(k_mark, BL(d, n), T, 0, st, dm, d);
     if (d < TL) {
       FPL(k_top_count, B(n), T, 0, st, dm, d);
       FPL(k_top_place, dim3(1), dim3(64), 0, st, dm, d);
@@ -1208,15 +1417,15 @@ fp_status run_job(Job& J) {
   }
   FPL(k_leaves, B(n), T, 0, st, dm);
 
-  // grouping in schedule order
+  // grouping in schedule order (heap size nn on the device)
   J.mark(4);
-  FPL(k_fill, B(nn), T, 0, st, J.hm.nsize, nn, 0);
-  FPL(k_nsize, B(n), T, 0, st, dm, nn);
+  const int NNexp = (2 << Dexp) - 1;
+  FPL(k_nsize, B(n), T, 0, st, dm);
   FPL(k_nsize_count, B(n), T, 0, st, dm);
-  FPL(k_sched_place, B(nn), T, 0, st, dm, nn, D);
+  FPL(k_sched_place, B(NNexp), T, 0, st, dm);
   J.check();
-  J.scan(J.hm.sbuf, J.hm.sbuf, nn, &C->tot);
-  FPL(k_nbegin, B(nn), T, 0, st, dm, nn, D);
+  J.scan(J.hm.sbuf, J.hm.sbuf, J.hm.NNcap, &C->tot, &C->nn);
+  FPL(k_nbegin, B(NNexp), T, 0, st, dm);
   FPL(k_scatter, B(n), T, 0, st, dm);
   if (ntop) FPL(k_top_check, dim3(1), dim3(64), 0, st, dm, ntop);
   J.check();
@@ -1224,7 +1433,7 @@ fp_status run_job(Job& J) {
   // local orders
   J.mark(5);
   FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
-  FPL(k_md_tasks, dim3(1), dim3(1024), 0, st, dm, nn, ntop);
+  FPL(k_md_tasks, dim3(1), dim3(1024), 0, st, dm, ntop);
   {
     // The largest class (one wave per CU, the longest nodes) goes first on
     // this stream, so its workgroups take their CUs before the others fill
@@ -1245,25 +1454,21 @@ fp_status run_job(Job& J) {
   }
   J.join_side();
   J.check();
-  // a node whose local order failed leaves its positions unset: stop here
-  {
-    const unsigned e = J.err();
-    if (J.hip_failed) return FP_ERR_HIP;
-    if (e) return map_err(e);
-  }
 
-  // elimination tree and column counts, bottom-up over the tree levels
+  // elimination tree and column counts, bottom-up over the tree levels (a
+  // node whose local order failed raised an error: these kernels then return)
   J.mark(6);
   FPL(k_prow_deg, B(n), T, 0, st, dm);
   J.scan(J.hm.pcnt, J.hm.prow, n, &C->tot);
   FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.prow + n, &C->tot);
   FPL(k_prow_fill, B(n), T, 0, st, dm);
-  for (int d = D; d >= 0; d--) {
+  for (int d = Dmax; d >= 0; d--) {
     const int cnt = 1 << d;
-    const dim3 G(std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * J.h->ncu)));
+    const bool big = d <= Dexp;
+    const dim3 G(big ? std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * J.h->ncu)) : 1);
     FPL(k_sym_init, dim3(1), dim3(64), 0, st, dm, d);
     FPL(k_sym_prep, G, T, J.h->lds_bytes, st, dm, d);
-    const dim3 G1(std::max(1, std::min(cnt, 4 * J.h->ncu)));
+    const dim3 G1(big ? std::max(1, std::min(cnt, 4 * J.h->ncu)) : 1);
     FPL(k_sym_elim, G, T, J.h->lds_bytes, st, dm, d, 0);
     FPL(k_sym_elim, G1, T, J.h->lds_big, st, dm, d, 1);
     FPL(k_sym_elim_glb, G, T, 0, st, dm, d);
@@ -1274,8 +1479,8 @@ fp_status run_job(Job& J) {
 
   // outputs
   J.mark(7);
-  FPL(k_expand, B(std::max<long long>(J.hm.n_dof, nn)), T, 0, st, dm, nn);
-  FPL(k_finish, dim3(1), dim3(64), 0, st, dm, nn);
+  FPL(k_expand, B(std::max<long long>(J.hm.n_dof, NNexp)), T, 0, st, dm);
+  FPL(k_finish, dim3(1), dim3(64), 0, st, dm);
   J.mark(8);
   J.check();
   return J.hip_failed ? FP_ERR_HIP : FP_OK;
@@ -1311,7 +1516,7 @@ void fp_options_default(fp_options* o) {
   o->block_size = 1;
   o->lloyd_iters = 1;
   o->seed = 0;
-  o->flags = 0;
+  o->flags = FP_FLAG_VALIDATE;
 }
 
 // LDS of the one-wave kernels for large nodes: what one workgroup may hold
@@ -1479,27 +1684,21 @@ fp_status order_impl(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   J.dm = (const FpMesh*)(ws + P.o_mesh);
   J.fixed = fixed;
   J.timing = !fixed && (opts->flags & FP_FLAG_TIMING) != 0;
+  J.validate = (opts->flags & FP_FLAG_VALIDATE) != 0;
   h->timed = false;
   h->tk_n = 0;
   h->tk_failed = false;
-  // control block cleared, job description copied in
+  // control block cleared, job description copied in as a kernel argument
+  // (so no host buffer has to outlive the call)
   const int words = (int)(sizeof(FpCtl) / 4);
   hipLaunchKernelGGL(k_fill, dim3((words + FP_WG - 1) / FP_WG), dim3(FP_WG), 0, J.st, (int*)(FpCtl*)M.ctl,
                      words, 0);
-  memcpy(h->host, &M, sizeof(M));
-  if (hipMemcpyAsync((void*)J.dm, h->host, sizeof(M), hipMemcpyHostToDevice, J.st) != hipSuccess ||
-      hipStreamSynchronize(J.st) != hipSuccess)
-    return FP_ERR_HIP;
+  hipLaunchKernelGGL(k_put_mesh, dim3(1), dim3(64), 0, J.st, M, (FpMesh*)J.dm);
+  if (hipGetLastError() != hipSuccess) return FP_ERR_HIP;
   s = run_job(J);
   J.join_side();  // a call that stopped early still leaves no work behind it
   h->timed = J.timing && s == FP_OK;
-  if (s != FP_OK) {
-    // leave the status word and error bits where the caller looks for them
-    if (out->status && s != FP_ERR_HIP)
-      hipLaunchKernelGGL(k_finish, dim3(1), dim3(64), 0, J.st, J.dm, 1);
-    return s;
-  }
-  return FP_OK;
+  return s;
 }
 
 }  // namespace

@@ -18,6 +18,7 @@
 #define FP_E_SCRATCH 0x4u     // a workspace pool overflowed
 #define FP_E_GMAP 0x8u        // user group id out of range
 #define FP_E_INTERNAL 0x10u   // an internal consistency check failed
+#define FP_E_ASYM 0x20u       // the pattern is not symmetric (validation)
 
 // where a failure was raised (the first one is kept with one value)
 enum {
@@ -43,6 +44,10 @@ enum {
   FP_SITE_SYM_LIVE = 19,    // element slot or list index out of range
   FP_SITE_SYM_PIVOT = 20,   // parent position outside the node's index space
   FP_SITE_TOP = 21,         // early top-separator range differs from the schedule's
+  FP_SITE_ASYM = 22,        // entry (v, u) without its mirror (u, v); the value is v
+  FP_SITE_GRAPH = 23,       // vertex graph larger than its capacity
+  FP_SITE_QARCS = 24,       // quotient graph larger than its capacity
+  FP_SITE_TREE = 25,        // separator tree larger than its capacity
 };
 
 #ifndef FP_DBGP

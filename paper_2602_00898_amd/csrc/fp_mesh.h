@@ -102,6 +102,9 @@ struct FpCtl {
   int nq;                // quotient arcs
   int norphan;           // unlabelled vertices after growth
   int nroot;             // orphan components
+  int nlong;             // vertex rows of more than FP_ROW_SHORT input entries
+  int ccn;               // vertices the orphan-component pass covers (n, or 0 without orphans)
+  int ccchg[8];          // orphan components: 1 if round r changed a label
   int chg;               // fixed-point iteration flag
   int tot;               // scan total
   int task_cnt[8];       // local-order task counts per size class

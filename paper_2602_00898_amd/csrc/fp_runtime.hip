@@ -96,11 +96,25 @@ fp_status fp_order_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A,
   if (ws_bytes < need) return FP_ERR_SIZE;
   const int used = std::max(1, std::min(lanes, (int)n_mesh));
   if ((s = ensure_lanes(h, used)) != FP_OK) return s;
-  // largest matrices first, so that the tail of the batch is short
+  // Matrices go to lanes before anything is queued: largest first, each to
+  // the lane with the least work so far (vertices, a proxy for time), so the
+  // lanes finish together.  Each lane's host thread then queues its
+  // matrices back to back on the lane's stream; nothing waits for the
+  // device (fp_order reads nothing back), and a lane reuses its workspace
+  // slice in stream order.
   std::vector<int32_t> order(n_mesh);
   for (int32_t i = 0; i < n_mesh; i++) order[i] = i;
   std::stable_sort(order.begin(), order.end(),
                    [&](int32_t a, int32_t b) { return A[a].n > A[b].n; });
+  std::vector<std::vector<int32_t>> plan(used);
+  {
+    std::vector<long long> load(used, 0);
+    for (int32_t i : order) {
+      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      plan[l].push_back(i);
+      load[l] += std::max<long long>(A[i].n, 1);
+    }
+  }
   // the lanes start after the caller's prior work
   hipStream_t cs = (hipStream_t)stream;
   hipEvent_t start;
@@ -108,7 +122,6 @@ fp_status fp_order_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A,
   bool hip_ok = hipEventRecord(start, cs) == hipSuccess;
   for (int l = 0; l < used && hip_ok; l++)
     hip_ok = hipStreamWaitEvent(h->lanes[l].st, start, 0) == hipSuccess;
-  std::atomic<int32_t> next(0);
   std::atomic<int> first_err((int)FP_OK);
   auto worker = [&](int l) {
     FpLane& L = h->lanes[l];
@@ -118,13 +131,9 @@ fp_status fp_order_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A,
       return;
     }
     char* ws = (char*)workspace + (size_t)l * lb;
-    while (true) {
-      const int32_t k = next.fetch_add(1);
-      if (k >= n_mesh) break;
-      const int32_t i = order[k];
+    for (int32_t i : plan[l]) {
       const int32_t* ug = user_gmap ? user_gmap[i] : nullptr;
-      fp_status r = fp_order(L.h, &A[i], ug, &opts[i], ws, lb, &out[i], L.st);
-      if (r == FP_OK) r = fp_last_error(L.h, ws, L.st);
+      const fp_status r = fp_order(L.h, &A[i], ug, &opts[i], ws, lb, &out[i], L.st);
       if (r != FP_OK) {
         int ok = FP_OK;
         first_err.compare_exchange_strong(ok, (int)r);
@@ -374,7 +383,7 @@ fp_status fp_server_submit(fp_server* S, const fp_host_csr* A, const fp_options*
   if (!r) return FP_ERR_OOM;
   r->A = *A;
   r->o = *opts;
-  r->o.flags = 0;
+  r->o.flags &= FP_FLAG_VALIDATE;  // no per-stage timing inside the server
   r->ws_bytes = ws;
   r->bytes = request_bytes(*A, ws);
   r->done = false;

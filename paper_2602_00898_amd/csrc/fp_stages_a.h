@@ -28,42 +28,143 @@ __device__ __forceinline__ long long rp_at(const FpMesh& M, long long r) {
 
 // --------------------------------------------------------------------------
 // Ingest: graph of A without its diagonal; block rows b*v..b*v+b-1 merge
-// into vertex v (Sec. 4.1 Step 2, Sec. 6.5).  Duplicates are dropped for
-// rows up to 512 entries; every later stage treats rows as sets, so longer
-// rows may keep duplicates.
+// into vertex v (Sec. 4.1 Step 2, Sec. 6.5).  Every row of the graph comes
+// out sorted ascending and without duplicates, whatever the order and
+// multiplicity of the input entries.  A lane per vertex handles rows of up
+// to FP_ROW_SHORT input entries; longer rows are listed and handled by a
+// whole workgroup each (ingest_long_row).
 // --------------------------------------------------------------------------
+#define FP_ROW_SHORT 512
+
+// input entries of vertex v's block rows: [*e0, *e1); false on a bad range
+__device__ __forceinline__ bool vertex_row_range(const FpMesh& M, int v, long long* e0,
+                                                 long long* e1) {
+  const long long r0 = (long long)v * M.b;
+  *e0 = rp_at(M, r0);
+  *e1 = rp_at(M, r0 + M.b);
+  return *e0 >= 0 && *e1 >= *e0 && *e1 <= M.nnz_in;
+}
+
+// vertex of input entry e, or -1 for the diagonal block and bad indices
+__device__ __forceinline__ int entry_vertex(const FpMesh& M, long long e, int v, unsigned* eb) {
+  const int c = M.ci_in[e];
+  if (c < 0 || (long long)c >= M.n_dof) {
+    *eb |= FP_E_INDEX;
+    return -1;
+  }
+  const int u = c / M.b;
+  return u == v ? -1 : u;
+}
+
+// Short rows (one lane): the distinct neighbours of v; with `out`, written
+// there in ascending order.  Returns their count, or -1 for a long row.
 __device__ __forceinline__ int gather_vertex_row(const FpMesh& M, int v, gptr<int> out, unsigned* eb) {
-  const int b = M.b;
-  const long long r0 = (long long)v * b;
-  long long e0 = rp_at(M, r0), e1 = rp_at(M, r0 + b);
-  if (e0 < 0 || e1 < e0 || e1 > M.nnz_in) {
+  long long e0, e1;
+  if (!vertex_row_range(M, v, &e0, &e1)) {
     *eb |= FP_E_INDEX;
     return 0;
   }
-  const bool dedup = (e1 - e0) <= 512;
+  if (e1 - e0 > FP_ROW_SHORT) return -1;
   int cnt = 0;
   for (long long e = e0; e < e1; e++) {
-    int c = M.ci_in[e];
-    if (c < 0 || (long long)c >= M.n_dof) {
-      *eb |= FP_E_INDEX;
-      continue;
-    }
-    int u = c / b;
-    if (u == v) continue;
+    const int u = entry_vertex(M, e, v, eb);
+    if (u < 0) continue;
     bool dup = false;
-    if (dedup)
-      for (long long f = e0; f < e; f++) {
-        int c2 = M.ci_in[f];
-        if (c2 >= 0 && (long long)c2 < M.n_dof && c2 / b == u) {
-          dup = true;
-          break;
-        }
-      }
+    for (long long f = e0; f < e && !dup; f++) {
+      const int c2 = M.ci_in[f];
+      dup = c2 >= 0 && (long long)c2 < M.n_dof && c2 / M.b == u;
+    }
     if (dup) continue;
-    if (out) out[cnt] = u;
+    if (out) {
+      // insertion into the sorted prefix out[0..cnt)
+      int k = cnt;
+      while (k > 0 && out[k - 1] > u) {
+        out[k] = out[k - 1];
+        k--;
+      }
+      out[k] = u;
+    }
     cnt++;
   }
   return cnt;
+}
+
+// Long rows (one workgroup, blockDim.x threads): an entry counts if no
+// earlier entry of the row names the same vertex.  Without `out`, returns the
+// number of distinct vertices to every thread.  With `out`, the distinct
+// vertices are appended there and then sorted in place by a bitonic network
+// whose first step of every merge compares mirrored positions, so every
+// comparison puts the smaller value first and positions past the count act
+// as +infinity that never moves.  `red` is one LDS word.
+__device__ __forceinline__ int ingest_long_row(const FpMesh& M, int v, gptr<int> out, unsigned* eb,
+                                               int* red) {
+  long long e0, e1;
+  if (!vertex_row_range(M, v, &e0, &e1)) {
+    *eb |= FP_E_INDEX;
+    return 0;
+  }
+  if (threadIdx.x == 0) *red = 0;
+  __syncthreads();
+  for (long long e = e0 + threadIdx.x; e < e1; e += blockDim.x) {
+    const int u = entry_vertex(M, e, v, eb);
+    if (u < 0) continue;
+    bool first = true;
+    for (long long f = e0; f < e && first; f++) {
+      const int c2 = M.ci_in[f];
+      first = !(c2 >= 0 && (long long)c2 < M.n_dof && c2 / M.b == u);
+    }
+    if (!first) continue;
+    const int slot = atomicAdd(red, 1);
+    if (out) out[slot] = u;
+  }
+  __syncthreads();
+  const int cnt = *red;
+  if (out && cnt > 1) {
+    int pw = 1;
+    while (pw < cnt) pw <<= 1;
+    for (int k = 2; k <= pw; k <<= 1) {
+      const int h = k >> 1;
+      for (int i = threadIdx.x; i < pw / 2; i += blockDim.x) {
+        const int a = (i / h) * k + (i % h), b = (i / h) * k + (k - 1 - (i % h));
+        if (b < cnt) {
+          const int x = out[a], y = out[b];
+          if (x > y) {
+            out[a] = y;
+            out[b] = x;
+          }
+        }
+      }
+      __syncthreads();
+      for (int j = h >> 1; j >= 1; j >>= 1) {
+        for (int i = threadIdx.x; i < pw / 2; i += blockDim.x) {
+          const int a = (i / j) * 2 * j + (i % j), b = a + j;
+          if (b < cnt) {
+            const int x = out[a], y = out[b];
+            if (x > y) {
+              out[a] = y;
+              out[b] = x;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  __syncthreads();
+  return cnt;
+}
+
+// true if the sorted row of u holds v
+__device__ __forceinline__ bool row_has(const FpMesh& M, int u, int v) {
+  int lo = M.grp[u], hi = M.grp[u + 1];
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (M.gci[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo < M.grp[u + 1] && M.gci[lo] == v;
 }
 
 // arc index of (p, q) in the sorted quotient row of p, -1 if absent

@@ -52,6 +52,12 @@ class Result(C.Structure):
                 ("status", C.c_void_p), ("max_nodes", C.c_int32)]
 
 
+class SuperResult(C.Structure):
+    _fields_ = [("Lp", C.c_void_p), ("super_ptr", C.c_void_p), ("n_super", C.c_void_p),
+                ("super_of", C.c_void_p), ("super_parent", C.c_void_p), ("Lx_ptr", C.c_void_p),
+                ("status", C.c_void_p)]
+
+
 class HostCsr(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
                 ("colind", C.c_void_p)]
@@ -103,6 +109,9 @@ def lib():
         L.fp_server_wait.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, C.POINTER(C.c_int64),
                                      C.POINTER(C.c_double)]
         L.fp_server_destroy.argtypes = [vp]
+        L.fp_supernodes_query.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
+        L.fp_supernodes.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_size_t,
+                                    C.POINTER(SuperResult), vp]
         _lib = L
     return _lib
 
@@ -137,9 +146,11 @@ class Handle:
 
 
 FLAG_TIMING = 1
+FLAG_VALIDATE = 2
 
 
-def options(patch_size=512, schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, seed=0, flags=0):
+def options(patch_size=512, schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, seed=0,
+            flags=FLAG_VALIDATE):
     o = Options()
     lib().fp_options_default(C.byref(o))
     o.patch_size = patch_size
@@ -174,14 +185,15 @@ def query(handle, n, rowptr, colind, opts):
 
 def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size=1,
           lloyd_iters=1, seed=0, user_gmap=None, handle=None, out=None, stream=None,
-          check=True, timing=False):
+          check=True, timing=False, validate=True):
     """Order one matrix on the GPU.  rowptr (int32/int64) and colind (int32)
     are device tensors.  Returns a dict of device tensors; with check=True
-    the call synchronises and raises on device-reported errors."""
+    the call synchronises and raises on device-reported errors.  validate
+    checks on the device that the pattern is symmetric."""
     dev = colind.device if colind.numel() else rowptr.device
     handle = handle or Handle()
     opts = options(patch_size, schedule, block_size, lloyd_iters, seed,
-                   FLAG_TIMING if timing else 0)
+                   (FLAG_TIMING if timing else 0) | (FLAG_VALIDATE if validate else 0))
     A = make_csr(n, rowptr, colind)
     ws_bytes, max_nodes = query(handle, n, rowptr, colind, opts)
     ws = handle.workspace(ws_bytes, dev)
@@ -207,6 +219,37 @@ def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size
         rc = lib().fp_last_error(handle.h, _ptr(ws), C.c_void_p(s))
         if rc != 0:
             raise FpError(rc, "device", error_detail(handle, ws, s))
+    return out
+
+
+def supernodes(parent, colcount, *, handle=None, stream=None, check=True):
+    """Fundamental supernodes of L from an ordering's parent and colcount
+    (int32 device tensors of n entries) through fp_supernodes.  Returns a
+    dict of device tensors: Lp, super_ptr, n_super, super_of, super_parent,
+    Lx_ptr, status (super_ptr / super_parent / Lx_ptr hold capacity n+1;
+    their first n_super(+1) entries are written)."""
+    n = int(parent.numel())
+    dev = parent.device
+    handle = handle or Handle()
+    ws_bytes = C.c_size_t()
+    _check(lib().fp_supernodes_query(n, C.byref(ws_bytes)), "fp_supernodes_query")
+    ws = torch.empty(max(int(ws_bytes.value), 1), dtype=torch.uint8, device=dev)
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = dict(Lp=torch.empty(n + 1, dtype=torch.int64, device=dev),
+               super_ptr=torch.empty(n + 1, **i32), n_super=torch.zeros(1, **i32),
+               super_of=torch.empty(max(n, 1), **i32), super_parent=torch.empty(max(n, 1), **i32),
+               Lx_ptr=torch.empty(n + 1, dtype=torch.int64, device=dev),
+               status=torch.zeros(1, **i32))
+    R = SuperResult(*[_ptr(out[k]) for k in ("Lp", "super_ptr", "n_super", "super_of",
+                                              "super_parent", "Lx_ptr", "status")])
+    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    _check(lib().fp_supernodes(handle.h, n, _ptr(parent), _ptr(colcount), _ptr(ws),
+                               ws_bytes.value, C.byref(R), C.c_void_p(s)), "fp_supernodes")
+    out["_ws"] = ws  # the workspace lives until the results are read
+    if check:
+        torch.cuda.synchronize(dev)
+        if int(out["status"].item()):
+            raise FpError(9, "fp_supernodes: parent array is not an elimination tree")
     return out
 
 
@@ -270,7 +313,7 @@ def _result(out):
                   int(out["node_begin"].numel()))
 
 
-def order_batch(meshes, *, lanes=8, handle=None, stream=None):
+def order_batch(meshes, *, lanes=8, handle=None, stream=None, check=True):
     """Order many matrices in one call (fp_order_batch).  `meshes` is a list
     of dicts with device tensors rowptr, colind, the size n and optional
     patch_size, seed, schedule, block_size, lloyd_iters, user_gmap.  Returns
@@ -304,6 +347,12 @@ def order_batch(meshes, *, lanes=8, handle=None, stream=None):
     rc = L.fp_order_batch(handle.h, k, A, G, O, _ptr(wbuf), ws.value, R, lanes, C.c_void_p(s))
     if rc != 0:
         raise FpError(rc, "fp_order_batch")
+    if check:
+        torch.cuda.synchronize(dev)
+        st = torch.cat([o["status"] for o in outs]).cpu()
+        bad = torch.nonzero(st).flatten().tolist()
+        if bad:
+            raise FpError(9, f"fp_order_batch: matrix {bad[0]} device bits 0x{int(st[bad[0]]):x}")
     return outs
 
 

@@ -46,4 +46,11 @@ def test_block3_torus_2048_full_parity():
     B = mg.block_expand(A, 3)
     say(f"[block] DOF pattern n={B.n} nnz={B.nnz}: GPU")
     g = gpu_order(B, patch_size=512, seed=4, block_size=3, rowptr64=True)
-    compare(g, expand3(c, A.n), "C4 block 3x3")
+    e = expand3(c, A.n)
+    compare(g, e, "C4 block 3x3")
+    # supernodal analysis of the 12.6M-column factor, GPU against oracle
+    import oracle
+    from tests.test_gpu_supernodes import compare_super, gpu_super
+    say("[block] supernodes")
+    compare_super(gpu_super(g["parent"], g["colcount"]),
+                  oracle.supernodes(e["parent"], e["colcount"]), "C4 block 3x3 supernodes")

@@ -558,6 +558,29 @@ def test_input_order_and_duplicates_do_not_matter():
         assert np.array_equal(a[k], b[k])
 
 
+def test_long_rows_order_and_duplicates_do_not_matter():
+    """A vertex of degree 600 whose row is shuffled and every entry repeated
+    (1202 entries) gives the same ordering as the clean pattern."""
+    A = mg.grid_mesh(30, 30, True, 23)
+    hub, deg = A.n, 600
+    rp = A.rowptr.astype(np.int64)
+    rows = [np.append(A.colind[rp[i]:rp[i + 1]], hub) if i < deg else A.colind[rp[i]:rp[i + 1]]
+            for i in range(A.n)]
+    rows.append(np.append(np.arange(deg), hub))
+    rng = np.random.default_rng(3)
+    messy = [rng.permutation(np.concatenate([r, r])) for r in rows]
+
+    def csr(rr):
+        p = np.zeros(len(rr) + 1, dtype=np.int64)
+        np.cumsum([len(x) for x in rr], out=p[1:])
+        return p, np.concatenate(rr).astype(np.int32)
+
+    a = oracle.order(*csr(rows), A.n + 1, patch_size=64, seed=23)
+    b = oracle.order(*csr(messy), A.n + 1, patch_size=64, seed=23)
+    for k in ("perm", "parent", "colcount", "gmap", "node_of"):
+        assert np.array_equal(a[k], b[k])
+
+
 def test_errors():
     A = mg.grid_mesh(5, 5, False, 1)
     bad = A.colind.copy()
