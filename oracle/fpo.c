@@ -568,7 +568,7 @@ static int popc64(uint64_t x) { return __builtin_popcountll(x); }
 int fpo_md(int32_t m, const int64_t* rp, const int32_t* ci, int32_t* order) {
   if (m < 0) return FPO_ERR_ARG;
   if (m == 0) return FPO_OK;
-  if (m > 46340) return FPO_ERR_SIZE;
+  if (m > 65535) return FPO_ERR_SIZE;  /* the same node-size limit as the GPU library */
   int64_t W = (m + 63) / 64;
   uint64_t* adj = NEWZ(uint64_t, (int64_t)m * W);
   uint64_t* alive = NEWZ(uint64_t, W);

@@ -110,7 +110,8 @@ int fpo_bisect(int32_t m, const int64_t* w, const int64_t* arp, const int32_t* a
 
 /* O7: exact minimum-degree order of a graph on 0..m-1 (Sec. 4.3 Step 4,
  * LocalOrder): repeatedly eliminate the vertex of least current degree in the
- * elimination graph, ties to the lowest index.  order[k] = k-th vertex. */
+ * elimination graph, ties to the lowest index.  order[k] = k-th vertex.
+ * m <= 65535 (FPO_ERR_SIZE beyond), the GPU library's limit too. */
 int fpo_md(int32_t m, const int64_t* rp, const int32_t* ci, int32_t* order);
 
 /* O9: elimination tree of A(perm,perm) by Liu's algorithm with path
