@@ -7,7 +7,7 @@ diagonals, scalar int32 CSR pattern + diagonal) with target patch size 512,
 inputs resident in device memory before the timed region.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                    [--no-batch] [--no-serve] [--serve-requests R] [--lanes L]
+                    [--no-batch] [--no-serve] [--no-block] [--serve-requests R] [--slots L]
                     [--copy-probe-mib M]
     python bench.py --traffic-from FETCH.csv WRITE.csv [--copy-probe-mib M]
 
@@ -36,9 +36,9 @@ import statistics
 import sys
 import time
 
-# The batched and served runs keep 16 lanes (streams) busy; HIP maps streams
-# onto GPU_MAX_HW_QUEUES hardware queues (4 by default, which serialises the
-# lanes), so raise it to 16 before anything initialises HIP.
+# The served run keeps 16 slots (streams) busy; HIP maps streams onto
+# GPU_MAX_HW_QUEUES hardware queues (4 by default, which serialises the
+# slots), so raise it to 16 before anything initialises HIP.
 if int(os.environ.get("GPU_MAX_HW_QUEUES", "4")) < 16:
     os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
@@ -321,10 +321,10 @@ def run_batch(args, meshes):
     t_plain = time.perf_counter() - t
     log(f"batch plain: {t_plain:.2f} s")
     hb = fpm.Handle()
-    fpm.order_batch(dm[:8], lanes=args.lanes, handle=hb)  # warm the lanes
+    fpm.order_batch(dm[:8], handle=hb)  # warm-up
     torch.cuda.synchronize(dev)
     t = time.perf_counter()
-    bout = fpm.order_batch(dm, lanes=args.lanes, handle=hb)
+    bout = fpm.order_batch(dm, handle=hb)
     torch.cuda.synchronize(dev)
     t_batch = time.perf_counter() - t
     log(f"batch batched: {t_batch:.2f} s")
@@ -332,7 +332,7 @@ def run_batch(args, meshes):
                for k in ("perm", "iperm", "parent", "colcount", "nnzL"))
     return {"workload": "256 grid/torus meshes, sides log-uniform 45..447, 5% edge flips, "
                         "S from the autotune table",
-            "meshes": len(meshes), "vertices": nv, "lanes": args.lanes,
+            "meshes": len(meshes), "vertices": nv,
             "plain_value": round(nv / t_plain / 1e6, 4), "batched_value": round(nv / t_batch / 1e6, 4),
             "unit": "M vertices/s", "speedup": round(t_plain / t_batch, 3),
             "identical_to_plain": bool(same)}
@@ -385,7 +385,7 @@ def run_serve(args, reqs):
     from paper_2602_00898_amd import fastperm as fpm
     from paper_2602_00898_amd import workloads as wl
 
-    srv = fpm.Server(hbm_budget=args.serve_budget_gb << 30, max_slots=args.lanes)
+    srv = fpm.Server(hbm_budget=args.serve_budget_gb << 30, max_slots=args.slots)
     try:
         # warm the slots on a small request
         A0 = reqs[0][1]
@@ -412,7 +412,7 @@ def run_serve(args, reqs):
 
     return {"workload": f"Poisson arrivals {wl.SERVE_RATE:.0f}/s, grid/torus sides log-uniform "
                         "100..1414 (1e4..2e6 vertices), fresh diagonals per request, S=512",
-            "requests": len(reqs), "vertices": nv, "slots": args.lanes,
+            "requests": len(reqs), "vertices": nv, "slots": args.slots,
             "value": round(nv / wall / 1e6, 4), "unit": "M vertices/s",
             "p50_ms": round(1e3 * pct(50), 2), "p99_ms": round(1e3 * pct(99), 2),
             "offered_M_vertices_per_s": round(nv / reqs[-1][0] / 1e6, 2)}
@@ -499,7 +499,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving sample")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
-    ap.add_argument("--lanes", type=int, default=16)
+    ap.add_argument("--slots", type=int, default=16, help="request-server slots")
     ap.add_argument("--no-block", action="store_true",
                     help="skip the 2048x2048 torus in 3x3 blocks (12.6M DOF)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,

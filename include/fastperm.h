@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define FP_ABI_VERSION 1
+#define FP_ABI_VERSION 2
 
 typedef enum {
   FP_OK = 0,
@@ -66,6 +66,9 @@ typedef struct fp_handle fp_handle;
 #define FP_SCHED_LEVEL 0 /* level order: leaves first, then upward (Sec. 5) */
 #define FP_SCHED_POST 1  /* post order: left, right, node (Sec. 5) */
 
+/* Size limits: n < 2^31 vertices; every separator-tree node (a patch
+ * interior or a separator) holds at most 65535 vertices, or the call reports
+ * FP_ERR_SIZE (the oracle has the same limit). */
 typedef struct {
   int32_t patch_size;   /* target patch size S (Sec. 6 uses 256; default 512) */
   int32_t nd_level;     /* -1: full depth (each leaf one patch); others unsupported */
@@ -224,30 +227,54 @@ fp_status fp_time_kernel(fp_handle* h, const char* name);
 fp_status fp_kernel_time(fp_handle* h, float* total_ms, int32_t* launches);
 
 /* ---------------------------------------------------------------------
- * Batches: many independent matrices (the paper orders meshes of very
- * different sizes, Sec. 6).  Matrix i is A[i] with options opts[i],
- * optional user grouping user_gmap[i] (user_gmap itself may be NULL) and
- * outputs out[i]; its result is exactly what fp_order gives for it alone.
- * The matrices run concurrently on `lanes` streams owned by the handle
- * (1 <= lanes <= 64; one host thread per lane queues that lane's share).  All pointers in A/out/user_gmap are device pointers owned by the
- * caller.
- * fp_query_batch: workspace size for `lanes` lanes (lanes slices of
- * *lane_bytes each, enough for the largest matrix) and the largest
+ * Batches: many independent matrices of uneven size (the paper orders meshes
+ * from 1.5K to 1.8M vertices, Sec. 6) in one pass over the pipeline: every
+ * kernel launch covers all matrices at once (each matrix takes the blocks
+ * it would take alone, found by a block table the call uploads), and the
+ * local orders of all separator-tree nodes of all matrices run in the same
+ * launches.  Matrix i is A[i] with options opts[i], optional user grouping
+ * user_gmap[i] (user_gmap itself may be NULL) and outputs out[i]; its result
+ * is exactly what fp_order gives for it alone.  All pointers in A, out and
+ * user_gmap are device pointers owned by the caller.
+ * fp_query_batch: bytes of workspace for the batch (the matrices' own
+ * workspaces, their descriptions and the block tables) and the largest
  * node_begin/node_size capacity among the matrices.
- * fp_order_batch: asynchronous like fp_order.  The lanes start after prior
- * work on `stream` and `stream` waits for the whole batch (events); the call
- * returns once everything is queued.  Matrices are assigned to lanes before
- * anything is queued (largest first, each to the lane with the fewest
- * vertices so far) and each lane's thread queues its matrices back to back.
- * The return value reports argument and HIP errors; device errors of
- * matrix i are its out[i].status bits (0 = success), valid when `stream`
- * reaches the end of the batch. */
+ * fp_order_batch: asynchronous like fp_order: queued on `stream`, nothing
+ * read back; the descriptions and block tables are copied from pinned
+ * memory the handle keeps (a later batch call on the same handle first
+ * waits for that copy).  Device errors of matrix i are its out[i].status
+ * bits (0 = success), valid when `stream` reaches the end of the batch.
+ * The call can be captured into a hipGraph. */
 fp_status fp_query_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A, const fp_options* opts,
-                         int32_t lanes, size_t* workspace_bytes, size_t* lane_bytes,
+                         const int32_t* const* user_gmap, size_t* workspace_bytes,
                          int32_t* max_nodes);
 fp_status fp_order_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A,
                          const int32_t* const* user_gmap, const fp_options* opts, void* workspace,
-                         size_t ws_bytes, fp_result* out, int32_t lanes, void* stream);
+                         size_t ws_bytes, fp_result* out, void* stream);
+
+/* The same batch over concatenated arrays (device):
+ *   rowptr  int64, mesh i's n_i + 1 row pointers at rowptr[vtx_off[i] + i],
+ *           each mesh's starting at 0;
+ *   colind  int32, mesh i's entries at colind[nnz_off[i] ..], column indices
+ *           local to the mesh (0 .. n_i - 1);
+ *   vtx_off, nnz_off  HOST arrays of n_mesh + 1 offsets (rows and entries);
+ *   perm, iperm, parent, colcount  mesh i's local results at [vtx_off[i] ..];
+ *   nnzL[i], status[i]  one per mesh (status nullable);
+ *   node_begin, node_size  nullable; mesh i's separator tree at node_off[i]
+ *           with capacity node_off[i+1] - node_off[i] (node_off is a HOST
+ *           array that fp_query_batch_concat fills).
+ * Sizes are in DOF units for block patterns (opts[i].block_size). */
+fp_status fp_query_batch_concat(fp_handle* h, int32_t n_mesh, const int64_t* rowptr,
+                                const int32_t* colind, const int64_t* vtx_off,
+                                const int64_t* nnz_off, const fp_options* opts,
+                                size_t* workspace_bytes, int64_t* node_off);
+fp_status fp_order_batch_concat(fp_handle* h, int32_t n_mesh, const int64_t* rowptr,
+                                const int32_t* colind, const int64_t* vtx_off,
+                                const int64_t* nnz_off, const fp_options* opts, void* workspace,
+                                size_t ws_bytes, int32_t* perm, int32_t* iperm, int32_t* parent,
+                                int32_t* colcount, int64_t* nnzL, uint32_t* status,
+                                int32_t* node_begin, int32_t* node_size, const int64_t* node_off,
+                                void* stream);
 
 /* ---------------------------------------------------------------------
  * Serving: a request loop that admits ordering requests of any size while

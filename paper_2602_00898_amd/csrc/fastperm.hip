@@ -24,9 +24,43 @@
 
 #define FP_CC_ROUNDS 4  // launched rounds of the orphan-component pass
 
-#define MESH0            \
-  const FpMesh& M = *Mp; \
-  gptr<FpCtl> C = M.ctl; \
+// A launch can cover several meshes (a batch): the grid is the
+// concatenation of every mesh's own grid, and g.boff[i] is the first block
+// of mesh i (g.boff[nm] the total).  A block finds its mesh by binary search
+// and then works as if it ran alone: fp_s.bx / fp_s.gx are its block index
+// and grid size within that mesh.  A single mesh passes no table.
+struct FpGrid {
+  const FpMesh* ms;
+  const int* boff;
+  int nm;
+};
+struct FpSlot {
+  int mi, bx, gx;
+};
+__device__ __forceinline__ FpSlot fp_slot(const FpGrid& g) {
+  if (!g.boff) return FpSlot{0, (int)blockIdx.x, (int)gridDim.x};
+  int lo = 0, hi = g.nm - 1;  // the last mesh whose first block is <= blockIdx.x
+  const int b = (int)blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (g.boff[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  lo = uni(lo);
+  return FpSlot{lo, b - g.boff[lo], g.boff[lo + 1] - g.boff[lo]};
+}
+// grid-stride indices within the block's mesh
+__device__ __forceinline__ int vt(const FpSlot& s) { return s.bx * (int)blockDim.x + (int)threadIdx.x; }
+__device__ __forceinline__ int vs(const FpSlot& s) { return s.gx * (int)blockDim.x; }
+__device__ __forceinline__ int vw(const FpSlot& s) { return uni(vt(s) >> 6); }
+__device__ __forceinline__ int vn(const FpSlot& s) { return vs(s) >> 6; }
+
+#define MESH0                          \
+  const FpSlot fp_s = fp_slot(fp_g);   \
+  const FpMesh& M = fp_g.ms[fp_s.mi];  \
+  gptr<FpCtl> C = M.ctl;               \
   (void)C
 
 // Every stage after ingest stops at once when an earlier one raised an
@@ -128,13 +162,125 @@ __global__ void k_scan_apply(const int* in, int* out, int cap, const int* n_dev,
 }
 
 // ==========================================================================
+// per-mesh generic passes: arrays and counts named by selectors, so that one
+// launch serves every mesh of a batch
+// ==========================================================================
+enum : int { FA_PCNT, FA_GRP, FA_PPTR, FA_QPTR, FA_WP, FA_SBUF, FA_PROW };
+enum : int { FN_N, FN_NNCAP, FN_P, FN_NN, FN_CCN };
+enum : int { FT_NNZG, FT_TOT, FT_NQ, FT_NROOT };
+__device__ __forceinline__ gptr<int> fa_arr(const FpMesh& M, int a) {
+  switch (a) {
+    case FA_PCNT: return M.pcnt;
+    case FA_GRP: return M.grp;
+    case FA_PPTR: return M.pptr;
+    case FA_QPTR: return M.qptr;
+    case FA_WP: return M.wp;
+    case FA_SBUF: return M.sbuf;
+    default: return M.prow;
+  }
+}
+// capacity (host-known) and count (device) of a pass
+__device__ __forceinline__ int fn_cap(const FpMesh& M, int f) {
+  return f == FN_NNCAP || f == FN_NN ? M.NNcap : M.n;
+}
+__device__ __forceinline__ int fn_count(const FpMesh& M, int f) {
+  const int cap = fn_cap(M, f);
+  int x = cap;
+  if (f == FN_P) x = M.ctl->P;
+  if (f == FN_NN) x = M.ctl->nn;
+  if (f == FN_CCN) x = M.ctl->ccn;
+  return x < 0 ? 0 : (x > cap ? cap : x);
+}
+__device__ __forceinline__ gptr<int> ft_ptr(const FpMesh& M, int t) {
+  FpCtl* C = M.ctl.p;
+  switch (t) {
+    case FT_NNZG: return gptr<int>(&C->nnz_g);
+    case FT_NQ: return gptr<int>(&C->nq);
+    case FT_NROOT: return gptr<int>(&C->nroot);
+    default: return gptr<int>(&C->tot);
+  }
+}
+// scan blocks of a pass with capacity `cap` (the host uses the same rule)
+__host__ __device__ __forceinline__ int scan_blocks(int cap) {
+  const int b = (cap + 4095) / 4096;
+  return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+// exclusive scan of a per-mesh array, three launches: chunk sums, a scan of
+// the sums (one block per mesh), chunk rescans; the total goes to `tdst`
+__global__ void k_mscan_part(FpGrid fp_g, int ain, int fcnt) {
+  MESH;
+  __shared__ int tmp[FP_WAVES + 2];
+  const int cap = fn_cap(M, fcnt), n = fn_count(M, fcnt);
+  const int chunk = max(1, (cap + fp_s.gx - 1) / fp_s.gx);
+  gptr<const int> in = fa_arr(M, ain);
+  const int lo = min(n, fp_s.bx * chunk), hi = min(n, lo + chunk);
+  int sum = 0;
+  for (int i = lo + (int)threadIdx.x; i < hi; i += FP_WG) sum += in[i];
+  int tot;
+  wg_excl_scan(sum, tmp, &tot);
+  if (threadIdx.x == 0) C->part[fp_s.bx] = tot;
+}
+__global__ void k_mscan_top(FpGrid fp_g, int fcnt, int tdst) {
+  MESH;
+  __shared__ int tmp[FP_WAVES + 2];
+  const int np = scan_blocks(fn_cap(M, fcnt));
+  int base = 0;
+  for (int c0 = 0; c0 < np; c0 += FP_WG) {
+    const int i = c0 + (int)threadIdx.x;
+    const int x = i < np ? (int)C->part[i] : 0;
+    int tt;
+    const int ex = wg_excl_scan(x, tmp, &tt);
+    if (i < np) C->part[i] = base + ex;
+    base += tt;
+  }
+  if (threadIdx.x == 0) *ft_ptr(M, tdst) = base;
+}
+__global__ void k_mscan_apply(FpGrid fp_g, int ain, int aout, int fcnt) {
+  MESH;
+  __shared__ int tmp[FP_WAVES + 2];
+  const int cap = fn_cap(M, fcnt), n = fn_count(M, fcnt);
+  const int chunk = max(1, (cap + fp_s.gx - 1) / fp_s.gx);
+  gptr<const int> in = fa_arr(M, ain);
+  gptr<int> out = fa_arr(M, aout);
+  const int lo = min(n, fp_s.bx * chunk), hi = min(n, lo + chunk);
+  int base = C->part[fp_s.bx];
+  for (int t0 = lo; t0 < hi; t0 += FP_WG) {
+    const int i = t0 + (int)threadIdx.x;
+    const int x = i < hi ? (int)in[i] : 0;
+    int tt;
+    const int ex = wg_excl_scan(x, tmp, &tt);
+    if (i < hi) out[i] = base + ex;
+    base += tt;
+  }
+}
+// out[count] = total (the last row pointer)
+__global__ void k_mptr_end(FpGrid fp_g, int aout, int fcnt, int tsrc) {
+  MESH;
+  if (vt(fp_s) == 0) fa_arr(M, aout)[fn_count(M, fcnt)] = *ft_ptr(M, tsrc);
+}
+__global__ void k_mcopy(FpGrid fp_g, int adst, int asrc, int fcnt) {
+  MESH;
+  const int n = fn_count(M, fcnt);
+  gptr<int> d = fa_arr(M, adst);
+  gptr<const int> a = fa_arr(M, asrc);
+  for (int i = vt(fp_s); i < n; i += vs(fp_s)) d[i] = a[i];
+}
+// control block of every mesh of a batch cleared before its pipeline
+// starts: block i clears mesh i's
+__global__ void k_ctl_clear_all(const FpMesh* __restrict__ ms) {
+  gptr<int> w = ms[blockIdx.x].ctl.as<int>();
+  const int words = (int)(sizeof(FpCtl) / 4);
+  for (int i = (int)threadIdx.x; i < words; i += (int)blockDim.x) w[i] = 0;
+}
+
+// ==========================================================================
 // ingest: graph of A without its diagonal (Sec. 4.1 Step 2, Sec. 6.5)
 // ==========================================================================
-__global__ void k_ingest(const FpMesh* __restrict__ Mp, int fill) {
+__global__ void k_ingest(FpGrid fp_g, int fill) {
   MESH0;
   if (fill && wave_failed(C)) return;
   unsigned eb = 0;
-  for (int v = gtid(); v < M.n; v += gsize()) {
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) {
     if (fill) {
       gather_vertex_row(M, v, M.gci + M.grp[v], &eb);
     } else {
@@ -146,13 +292,13 @@ __global__ void k_ingest(const FpMesh* __restrict__ Mp, int fill) {
   if (eb) fp_fail(C, eb, FP_SITE_INGEST, 0);
 }
 // rows of more than FP_ROW_SHORT input entries, a workgroup each
-__global__ void k_ingest_long(const FpMesh* __restrict__ Mp, int fill) {
+__global__ void k_ingest_long(FpGrid fp_g, int fill) {
   MESH0;
   __shared__ int red;
   if (fill && wg_failed(C)) return;
   unsigned eb = 0;
   const int nl = C->nlong;
-  for (int l = blockIdx.x; l < nl; l += gridDim.x) {
+  for (int l = fp_s.bx; l < nl; l += fp_s.gx) {
     const int v = M.fb[l];
     const int c = ingest_long_row(M, v, fill ? M.gci + M.grp[v] : gptr<int>(nullptr), &eb, &red);
     if (!fill && threadIdx.x == 0) M.pcnt[v] = c;
@@ -161,17 +307,17 @@ __global__ void k_ingest_long(const FpMesh* __restrict__ Mp, int fill) {
 }
 // the vertex graph fits its capacity (an int32 count that overflowed reads
 // negative); the fill pass and every later stage are gated on this
-__global__ void k_check_graph(const FpMesh* __restrict__ Mp) {
+__global__ void k_check_graph(FpGrid fp_g) {
   MESH0;
-  if (gtid() == 0 && (C->nnz_g < 0 || (long long)C->nnz_g > M.Ecap))
+  if (vt(fp_s) == 0 && (C->nnz_g < 0 || (long long)C->nnz_g > M.Ecap))
     fp_fail(C, FP_E_SCRATCH, FP_SITE_GRAPH, C->nnz_g);
 }
 // every entry (v, u) of the graph has its mirror (u, v): the pattern of A is
 // symmetric (Sec. 4, inputs), block by block in block mode
-__global__ void k_validate(const FpMesh* __restrict__ Mp) {
+__global__ void k_validate(FpGrid fp_g) {
   MESH0;
-  if (wave_failed(C)) return;
-  for (int v = gtid(); v < M.n; v += gsize())
+  if (!M.validate || wave_failed(C)) return;
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s))
     for (int e = M.grp[v]; e < M.grp[v + 1]; e++)
       if (!row_has(M, M.gci[e], v)) {
         fp_fail(C, FP_E_ASYM, FP_SITE_ASYM, v);
@@ -185,10 +331,14 @@ __global__ void k_validate(const FpMesh* __restrict__ Mp) {
 // seed with ties to the lowest id) as the fixed point of 64-bit keys
 // (dist << 32 | id), one level per launch, atomicMin on the keys.
 // ==========================================================================
-__global__ void k_seeds(const FpMesh* __restrict__ Mp, int P0) {
+__host__ __device__ __forceinline__ int fp_p0(long long n, int S) {
+  return n > 0 ? (int)((n + S - 1) / S) : 0;
+}
+__global__ void k_seeds(FpGrid fp_g) {
   MESH;
+  const int P0 = fp_p0(M.n, M.S);
   const int n = M.n, S = M.S;
-  for (int blk = gwave(); blk < P0; blk += nwaves()) {
+  for (int blk = vw(fp_s); blk < P0; blk += vn(fp_s)) {
     const long long lo = (long long)blk * S, hi = min((long long)n, lo + S);
     uint64_t bh = FP_UNSET;
     uint32_t bv = 0xFFFFFFFFu;
@@ -203,37 +353,37 @@ __global__ void k_seeds(const FpMesh* __restrict__ Mp, int P0) {
     const uint32_t vm = wave_min_u32(bh == hm ? bv : 0xFFFFFFFFu);
     if (lane_id() == 0) M.seeds[blk] = (int)vm;
   }
-  if (gtid() == 0) {
+  if (vt(fp_s) == 0) {
     C->P0 = P0;
     C->P = P0;
   }
 }
-__global__ void k_key_unset(const FpMesh* __restrict__ Mp) {
+__global__ void k_key_unset(FpGrid fp_g) {
   MESH;
-  for (int v = gtid(); v < M.n; v += gsize()) M.key[v] = FP_UNSET;
-  for (int i = gtid(); i < M.n + 16; i += gsize()) M.fcnt[i] = 0;
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.key[v] = FP_UNSET;
+  for (int i = vt(fp_s); i < M.n + 16; i += vs(fp_s)) M.fcnt[i] = 0;
 }
-// nseeds < 0: every patch seed (the count is on the device)
-__global__ void k_seed_push(const FpMesh* __restrict__ Mp, int nseeds) {
+// all: every patch seed (the count is on the device); else the P0 seeds
+__global__ void k_seed_push(FpGrid fp_g, int all) {
   MESH;
-  if (nseeds < 0) nseeds = min(C->P, M.n);
-  for (int k = gtid(); k < nseeds; k += gsize()) {
+  const int nseeds = all ? min(C->P, M.n) : fp_p0(M.n, M.S);
+  for (int k = vt(fp_s); k < nseeds; k += vs(fp_s)) {
     const int s = M.seeds[k];
     atomicMin(&M.key[s], (unsigned long long)k);
     M.fa[k] = s;
   }
-  if (gtid() == 0) M.fcnt[0] = nseeds;
+  if (vt(fp_s) == 0) M.fcnt[0] = nseeds;
 }
 // One frontier level: a lane per frontier vertex.  The loads of its first
 // FP_BFS_ROW neighbours (columns, then keys) go out together, and the wave's
 // claims are appended with one atomic.
 #define FP_BFS_ROW 8
-__global__ void k_bfs_level(const FpMesh* __restrict__ Mp, int lvl) {
+__global__ void k_bfs_level(FpGrid fp_g, int lvl) {
   MESH;
   const int nf = M.fcnt[lvl];
   gptr<const int> cur = (lvl & 1) ? M.fb : M.fa;
   gptr<int> nxt = (lvl & 1) ? M.fa : M.fb;
-  for (int f0 = gwave() * 64; f0 < nf; f0 += nwaves() * 64) {
+  for (int f0 = vw(fp_s) * 64; f0 < nf; f0 += vn(fp_s) * 64) {
     const int f = f0 + lane_id();
     int e0 = 0, deg = 0;
     unsigned long long kv = 0;
@@ -293,8 +443,18 @@ __device__ __forceinline__ void wg_level_barrier() {
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
-__global__ void __launch_bounds__(1024) k_bfs_tail(const FpMesh* __restrict__ Mp, int lvl0) {
+// Levels of a BFS launched one by one before the tail takes over: about
+// twice the radius of a patch of S vertices on a triangle mesh, at most 64;
+// the distance BFS of Lloyd's step runs inside patches (half).
+__host__ __device__ __forceinline__ int fp_bfs_levels(int n, int S, bool inner) {
+  int r = 1;
+  while ((long long)r * r < (long long)S && r < 64) r++;
+  const int L = (inner ? r : 2 * r) + 4;
+  return L < 64 ? (L < n ? L : n) : (64 < n ? 64 : n);
+}
+__global__ void __launch_bounds__(1024) k_bfs_tail(FpGrid fp_g, int inner) {
   MESH_WG;
+  const int lvl0 = fp_bfs_levels(M.n, M.S, inner != 0);
   wg_level_barrier();
   for (int lvl = lvl0; lvl < M.n + 15; lvl++) {
     const int nf = M.fcnt[lvl];
@@ -313,10 +473,10 @@ __global__ void __launch_bounds__(1024) k_bfs_tail(const FpMesh* __restrict__ Mp
     wg_level_barrier();
   }
 }
-__global__ void k_count_unset(const FpMesh* __restrict__ Mp) {
+__global__ void k_count_unset(FpGrid fp_g) {
   MESH;
   int cnt = 0;
-  for (int v = gtid(); v < M.n; v += gsize()) cnt += (M.key[v] == FP_UNSET);
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) cnt += (M.key[v] == FP_UNSET);
   cnt = wave_sum_i32(cnt);
   if (lane_id() == 0 && cnt) atomicAdd(&C->norphan, cnt);
 }
@@ -326,12 +486,12 @@ __global__ void k_count_unset(const FpMesh* __restrict__ Mp) {
 // unlabelled.  Rounds of hooking and pointer jumping run as separate
 // launches while the previous round changed a label; a one-workgroup tail
 // finishes any component the rounds did not settle.
-__global__ void k_cc_init(const FpMesh* __restrict__ Mp) {
+__global__ void k_cc_init(FpGrid fp_g) {
   MESH;
   const bool any = C->norphan > 0;
-  if (gtid() == 0) C->ccn = any ? M.n : 0;
+  if (vt(fp_s) == 0) C->ccn = any ? M.n : 0;
   if (!any) return;
-  for (int v = gtid(); v < M.n; v += gsize()) M.fb[v] = (M.key[v] == FP_UNSET) ? v : -1;
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.fb[v] = (M.key[v] == FP_UNSET) ? v : -1;
 }
 __device__ __forceinline__ bool cc_hook_pass(const FpMesh& M, int i0, int di) {
   gptr<int> comp = M.fb;
@@ -368,17 +528,17 @@ __device__ __forceinline__ bool cc_jump_pass(const FpMesh& M, int i0, int di) {
 __device__ __forceinline__ bool cc_round_live(gptr<FpCtl> C, int r) {
   return C->norphan > 0 && (r == 0 || C->ccchg[r - 1] != 0);
 }
-__global__ void k_cc_hook(const FpMesh* __restrict__ Mp, int r) {
+__global__ void k_cc_hook(FpGrid fp_g, int r) {
   MESH;
   if (!cc_round_live(C, r)) return;
-  if (cc_hook_pass(M, gtid(), gsize())) atomicOr(&C->ccchg[r], 1);
+  if (cc_hook_pass(M, vt(fp_s), vs(fp_s))) atomicOr(&C->ccchg[r], 1);
 }
-__global__ void k_cc_jump(const FpMesh* __restrict__ Mp, int r) {
+__global__ void k_cc_jump(FpGrid fp_g, int r) {
   MESH;
   if (!cc_round_live(C, r)) return;
-  if (cc_jump_pass(M, gtid(), gsize())) atomicOr(&C->ccchg[r], 1);
+  if (cc_jump_pass(M, vt(fp_s), vs(fp_s))) atomicOr(&C->ccchg[r], 1);
 }
-__global__ void __launch_bounds__(1024) k_cc_tail(const FpMesh* __restrict__ Mp, int r0) {
+__global__ void __launch_bounds__(1024) k_cc_tail(FpGrid fp_g, int r0) {
   MESH_WG;
   __shared__ int chg;
   if (!cc_round_live(C, r0)) return;
@@ -396,42 +556,42 @@ __global__ void __launch_bounds__(1024) k_cc_tail(const FpMesh* __restrict__ Mp,
     if (!c) break;
   }
 }
-__global__ void k_cc_flags(const FpMesh* __restrict__ Mp) {
+__global__ void k_cc_flags(FpGrid fp_g) {
   MESH;
   if (C->norphan == 0) return;
-  for (int v = gtid(); v < M.n; v += gsize()) M.pcnt[v] = (M.fb[v] == v) ? 1 : 0;
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.pcnt[v] = (M.fb[v] == v) ? 1 : 0;
 }
 // ids P0 + rank of the component's lowest vertex; P grows by the count
-__global__ void k_cc_label(const FpMesh* __restrict__ Mp) {
+__global__ void k_cc_label(FpGrid fp_g) {
   MESH;
   if (C->norphan == 0) return;
   const int P0 = C->P0;
-  for (int v = gtid(); v < M.n; v += gsize()) {
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) {
     const int c = M.fb[v];
     if (c < 0) continue;
     const int id = P0 + M.pcnt[c];
     M.key[v] = (unsigned long long)id;
     if (c == v) M.seeds[id] = v;
   }
-  if (gtid() == 0) C->P = P0 + C->nroot;
+  if (vt(fp_s) == 0) C->P = P0 + C->nroot;
 }
 // Lloyd re-centre: new seed = vertex farthest from the patch boundary (the
 // distance inside the patch equals the distance to the boundary set of the
 // whole graph, because any path out of a patch passes its own boundary
 // first), ties to the lowest id; patches without a boundary keep their seed.
-__global__ void k_lloyd_gmap(const FpMesh* __restrict__ Mp) {
+__global__ void k_lloyd_gmap(FpGrid fp_g) {
   MESH;
   const int P = C->P;
-  for (int v = gtid(); v < M.n; v += gsize()) M.gmap[v] = (int)(M.key[v] & 0xFFFFFFFFu);
-  for (int p = gtid(); p < P; p += gsize()) M.best[p] = 0;
-  for (int i = gtid(); i < M.n + 16; i += gsize()) M.fcnt[i] = 0;
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.gmap[v] = (int)(M.key[v] & 0xFFFFFFFFu);
+  for (int p = vt(fp_s); p < P; p += vs(fp_s)) M.best[p] = 0;
+  for (int i = vt(fp_s); i < M.n + 16; i += vs(fp_s)) M.fcnt[i] = 0;
 }
 // (the loops below step a whole workgroup at a time: wg_append holds a
 // barrier, and a single list counter takes one atomic per workgroup)
-__global__ void k_lloyd_bnd(const FpMesh* __restrict__ Mp) {
+__global__ void k_lloyd_bnd(FpGrid fp_g) {
   MESH_WG;
   __shared__ int lds2[2];
-  for (int v0 = (int)(blockIdx.x * blockDim.x); v0 < M.n; v0 += (int)(gridDim.x * blockDim.x)) {
+  for (int v0 = (int)(fp_s.bx * blockDim.x); v0 < M.n; v0 += (int)(fp_s.gx * blockDim.x)) {
     const int v = v0 + (int)threadIdx.x;
     bool isb = false;
     if (v < M.n) {
@@ -446,9 +606,9 @@ __global__ void k_lloyd_bnd(const FpMesh* __restrict__ Mp) {
 // per patch, the candidate of largest distance (least vertex on ties); the
 // lanes of a wave that share a patch take their maximum first, so a patch
 // gets one atomic per wave instead of one per vertex
-__global__ void k_lloyd_best(const FpMesh* __restrict__ Mp) {
+__global__ void k_lloyd_best(FpGrid fp_g) {
   MESH;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
     const unsigned long long k = v < M.n ? M.key[v] : FP_UNSET;
     const bool act = k != FP_UNSET;
@@ -467,28 +627,28 @@ __global__ void k_lloyd_best(const FpMesh* __restrict__ Mp) {
     }
   }
 }
-__global__ void k_lloyd_seed(const FpMesh* __restrict__ Mp) {
+__global__ void k_lloyd_seed(FpGrid fp_g) {
   MESH;
   const int P = C->P;
-  for (int p = gtid(); p < P; p += gsize()) {
+  for (int p = vt(fp_s); p < P; p += vs(fp_s)) {
     const unsigned long long bb = M.best[p];
     if (bb) M.seeds[p] = (int)(0xFFFFFFFFu - (unsigned)(bb & 0xFFFFFFFFu));
   }
 }
-__global__ void k_gmap_final(const FpMesh* __restrict__ Mp) {
+__global__ void k_gmap_final(FpGrid fp_g) {
   MESH;
   const int P = C->P;
-  for (int v = gtid(); v < M.n; v += gsize()) {
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) {
     const unsigned long long k = M.key[v];
     const int g = k == FP_UNSET ? -1 : (int)(k & 0xFFFFFFFFu);
     if (g < 0 || g >= P) fp_fail(C, FP_E_INTERNAL, FP_SITE_GMAP_LABEL, v);
     M.gmap[v] = (g < 0 || g >= P) ? 0 : g;
   }
 }
-__global__ void k_user_gmap(const FpMesh* __restrict__ Mp) {
+__global__ void k_user_gmap(FpGrid fp_g) {
   MESH;
   int mx = 0;
-  for (int v = gtid(); v < M.n; v += gsize()) {
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) {
     int g = M.user_gmap[v];
     if (g < 0 || g >= M.n) {
       fp_fail(C, FP_E_GMAP, FP_SITE_USER_GMAP, v);
@@ -504,10 +664,16 @@ __global__ void k_user_gmap(const FpMesh* __restrict__ Mp) {
 // ==========================================================================
 // patch members, boundary list, quotient graph (Sec. 2; built once, Sec. 5)
 // ==========================================================================
-__global__ void k_patch_count(const FpMesh* __restrict__ Mp) {
+__global__ void k_quot_init(FpGrid fp_g) {
+  MESH;
+  const int P = min(C->P, M.n);
+  for (int p = vt(fp_s); p <= P; p += vs(fp_s)) M.pcnt[p] = 0;
+  if (vt(fp_s) == 0) C->nbnd = 0;
+}
+__global__ void k_patch_count(FpGrid fp_g) {
   MESH_WG;
   __shared__ int lds2[2];
-  for (int v0 = (int)(blockIdx.x * blockDim.x); v0 < M.n; v0 += (int)(gridDim.x * blockDim.x)) {
+  for (int v0 = (int)(fp_s.bx * blockDim.x); v0 < M.n; v0 += (int)(fp_s.gx * blockDim.x)) {
     const int v = v0 + (int)threadIdx.x;
     const bool act = v < M.n;
     const int g = act ? M.gmap[v] : 0;
@@ -519,9 +685,9 @@ __global__ void k_patch_count(const FpMesh* __restrict__ Mp) {
     if (isb) M.bnd[slot] = v;
   }
 }
-__global__ void k_patch_scatter(const FpMesh* __restrict__ Mp) {
+__global__ void k_patch_scatter(FpGrid fp_g) {
   MESH;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
     const bool act = v < M.n;
     const int slot = wave_append_keyed(M.pcnt, act ? M.gmap[v] : 0, act);
@@ -534,13 +700,13 @@ __global__ void k_patch_scatter(const FpMesh* __restrict__ Mp) {
 // LDS bitmap over the patch ids (bm_words words per wave) one pass over the
 // members marks the neighbours, their loads issued a row at a time, and the
 // bitmap is read back in order; without it, one pass per neighbour.
-__global__ void k_qrow(const FpMesh* __restrict__ Mp, int fill, int lds_words) {
+__global__ void k_qrow(FpGrid fp_g, int fill, int lds_words) {
   MESH;
   FP_LDS_DECL;
   const int P = C->P;
   const int bm_words = (P + 31) / 32 <= lds_words ? (P + 31) / 32 : 0;
   uint32_t* bm = (uint32_t*)fp_lds + (long long)bm_words * wave_id();
-  for (int p = gwave(); p < P; p += nwaves()) {
+  for (int p = vw(fp_s); p < P; p += vn(fp_s)) {
     const int a0 = M.pptr[p], a1 = M.pptr[p + 1];
     gptr<int> out = fill ? M.qci + M.qptr[p] : gptr<int>(nullptr);
     int cnt = 0;
@@ -601,9 +767,9 @@ __global__ void k_qrow(const FpMesh* __restrict__ Mp, int fill, int lds_words) {
   }
 }
 
-__global__ void k_check_arcs(const FpMesh* __restrict__ Mp) {
+__global__ void k_check_arcs(FpGrid fp_g) {
   MESH;
-  if (gtid() == 0 && (C->nq < 0 || (long long)C->nq > M.Ecap))
+  if (vt(fp_s) == 0 && (C->nq < 0 || (long long)C->nq > M.Ecap))
     fp_fail(C, FP_E_SCRATCH, FP_SITE_QARCS, C->nq);
 }
 
@@ -613,45 +779,45 @@ __global__ void k_check_arcs(const FpMesh* __restrict__ Mp) {
 // SuperSeparator (unmarked vertices with an unmarked neighbour across) and
 // RefineSeparator (keep the smaller side, ties to the left).
 // ==========================================================================
-__global__ void k_sep_init(const FpMesh* __restrict__ Mp) {
+__global__ void k_sep_init(FpGrid fp_g) {
   MESH;
   const int P = C->P;
   int D = 0;
   while ((1ll << D) < P) D++;
   const int nn = (1 << (D + 1)) - 1;
   if (nn > M.NNcap) {  // never expected: NNcap holds the tree of n patches
-    if (gtid() == 0) fp_fail(C, FP_E_SCRATCH, FP_SITE_TREE, nn);
+    if (vt(fp_s) == 0) fp_fail(C, FP_E_SCRATCH, FP_SITE_TREE, nn);
     return;
   }
-  if (gtid() == 0) {
+  if (vt(fp_s) == 0) {
     C->D = D;
     C->nn = nn;
   }
-  for (int v = gtid(); v < M.n; v += gsize()) M.node_of[v] = -1;
-  for (int p = gtid(); p < P; p += gsize()) {
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.node_of[v] = -1;
+  for (int p = vt(fp_s); p < P; p += vs(fp_s)) {
     M.pnode[p] = 0;
     M.plist[p] = p;
   }
-  for (int x = gtid(); x < nn; x += gsize()) {
+  for (int x = vt(fp_s); x < nn; x += vs(fp_s)) {
     M.cntL[x] = 0;
     M.cntR[x] = 0;
     M.segN[x] = 0;
     M.segS[x] = 0;
   }
-  if (gtid() == 0) M.segN[0] = P;
+  if (vt(fp_s) == 0) M.segN[0] = P;
 }
 // level d of the tree: alive arcs recounted from zero
-__global__ void k_level_begin(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_level_begin(FpGrid fp_g, int d) {
   MESH;
   if (d >= C->D) return;
   const int nq = min(C->nq, (int)M.Ecap);
-  for (int a = gtid(); a < nq; a += gsize()) M.qcnt[a] = 0;
+  for (int a = vt(fp_s); a < nq; a += vs(fp_s)) M.qcnt[a] = 0;
 }
-__global__ void k_arcs(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_arcs(FpGrid fp_g, int d) {
   MESH;
   if (d >= C->D) return;
   const int nb = C->nbnd;
-  for (int i = gtid(); i < nb; i += gsize()) {
+  for (int i = vt(fp_s); i < nb; i += vs(fp_s)) {
     const int v = M.bnd[i];
     if (M.node_of[v] != -1) continue;
     const int gv = M.gmap[v];
@@ -681,24 +847,24 @@ __global__ void k_arcs(const FpMesh* __restrict__ Mp, int d) {
     }
   }
 }
-__global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ Mp, int d,
+__global__ void __launch_bounds__(FP_WG) k_bisect(FpGrid fp_g, int d,
                                                    int lds_bytes) {
   MESH_WG;
   __shared__ BisectLds sh;
   FP_LDS_DECL;
   if (d >= C->D) return;
   const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
-  for (int t = lo + (int)blockIdx.x; t < hi; t += (int)gridDim.x) {
+  for (int t = lo + fp_s.bx; t < hi; t += fp_s.gx) {
     const int m = M.segN[t];
     if (m >= 2) wg_bisect(M, t, M.segS[t], m, &sh, fp_lds, lds_bytes);
   }
 }
-__global__ void k_cand(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_cand(FpGrid fp_g, int d) {
   MESH;
   if (d >= C->D) return;
   const int hi = (1 << (d + 1)) - 1;
   const int nb = C->nbnd;
-  for (int i = gtid(); i < nb; i += gsize()) {
+  for (int i = vt(fp_s); i < nb; i += vs(fp_s)) {
     const int v = M.bnd[i];
     M.cand[i] = 0;
     if (M.node_of[v] != -1) continue;
@@ -728,11 +894,11 @@ __global__ void k_cand(const FpMesh* __restrict__ Mp, int d) {
     }
   }
 }
-__global__ void k_mark(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_mark(FpGrid fp_g, int d) {
   MESH;
   if (d >= C->D) return;
   const int nb = C->nbnd;
-  for (int i = gtid(); i < nb; i += gsize()) {
+  for (int i = vt(fp_s); i < nb; i += vs(fp_s)) {
     if (!M.cand[i]) continue;
     const int v = M.bnd[i];
     const int c = M.pnode[M.gmap[v]];
@@ -746,51 +912,51 @@ __global__ void k_mark(const FpMesh* __restrict__ Mp, int d) {
   }
 }
 // leaves keep the remaining vertices of their patch
-__global__ void k_leaves(const FpMesh* __restrict__ Mp) {
+__global__ void k_leaves(FpGrid fp_g) {
   MESH;
-  for (int v = gtid(); v < M.n; v += gsize())
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s))
     if (M.node_of[v] == -1) M.node_of[v] = M.pnode[M.gmap[v]];
 }
 
 // ==========================================================================
 // grouping in schedule order (Alg. 3)
 // ==========================================================================
-__global__ void k_nsize(const FpMesh* __restrict__ Mp) {
+__global__ void k_nsize(FpGrid fp_g) {
   MESH;
   const int nn = C->nn;
-  for (int x = gtid(); x < nn; x += gsize()) M.nsize[x] = 0;
-  for (int v = gtid(); v < M.n; v += gsize()) {
+  for (int x = vt(fp_s); x < nn; x += vs(fp_s)) M.nsize[x] = 0;
+  for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) {
     if ((unsigned)M.node_of[v] >= (unsigned)nn) {  // never expected
       fp_fail(C, FP_E_INTERNAL, FP_SITE_NODE_OF, v);
       M.node_of[v] = 0;
     }
   }
 }
-__global__ void k_nsize_count(const FpMesh* __restrict__ Mp) {
+__global__ void k_nsize_count(FpGrid fp_g) {
   MESH;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
     const bool act = v < M.n;
     (void)wave_append_keyed(M.nsize, act ? M.node_of[v] : 0, act);
   }
 }
-__global__ void k_sched_place(const FpMesh* __restrict__ Mp) {
+__global__ void k_sched_place(FpGrid fp_g) {
   MESH;
   const int nn = C->nn, D = C->D;
-  for (int x = gtid(); x < nn; x += gsize()) M.sbuf[sched_pos(x, D, M.sched)] = M.nsize[x];
+  for (int x = vt(fp_s); x < nn; x += vs(fp_s)) M.sbuf[sched_pos(x, D, M.sched)] = M.nsize[x];
 }
-__global__ void k_nbegin(const FpMesh* __restrict__ Mp) {
+__global__ void k_nbegin(FpGrid fp_g) {
   MESH;
   const int nn = C->nn, D = C->D;
-  for (int x = gtid(); x < nn; x += gsize()) {
+  for (int x = vt(fp_s); x < nn; x += vs(fp_s)) {
     const int b = M.sbuf[sched_pos(x, D, M.sched)];
     M.nbegin[x] = b;
     M.ncur[x] = b;
   }
 }
-__global__ void k_scatter(const FpMesh* __restrict__ Mp) {
+__global__ void k_scatter(FpGrid fp_g) {
   MESH;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
     const bool act = v < M.n;
     const int slot = wave_append_keyed(M.ncur, act ? M.node_of[v] : 0, act);
@@ -805,11 +971,12 @@ __global__ void k_scatter(const FpMesh* __restrict__ Mp) {
 // (a counting sort on size / 16, one workgroup): a class with more nodes
 // than resident slots then ends with its smallest nodes, not its largest.
 #define FP_TASK_BUCKETS 256
-__global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ Mp, int ntop) {
+__global__ void __launch_bounds__(1024) k_md_tasks(FpGrid fp_g, int ntop) {
   MESH_WG;
   const int nn = C->nn;
   __shared__ int hist[FP_MD_CLASSES * FP_TASK_BUCKETS];
   for (int i = threadIdx.x; i < FP_MD_CLASSES * FP_TASK_BUCKETS; i += blockDim.x) hist[i] = 0;
+  if (threadIdx.x < 8) C->task_pop[threadIdx.x] = 0;
   __syncthreads();
   auto key = [&](int x) -> int {  // class * buckets + bucket, or -1
     const int m = M.nsize[x];
@@ -837,7 +1004,7 @@ __global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ Mp
     if (k >= 0) M.tasks[(k / FP_TASK_BUCKETS) * M.NNcap + atomicAdd(&hist[k], 1)] = x;
   }
 }
-__global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int c) {
+__global__ void __launch_bounds__(FP_WG) k_md(FpGrid fp_g, int c) {
   MESH;
   FP_LDS_DECL;
   const int nsl = md_slice_waves(c);
@@ -860,20 +1027,20 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ Mp, int
 // nodes, in heap order.  Their local orders, the longest serial chains of
 // the stage, then run on a second stream while the rest of the tree and the
 // grouping proceed.
-__global__ void k_top_count(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_top_count(FpGrid fp_g, int d) {
   MESH;
   if (d >= C->D) return;
   const int lo = (1 << d) - 1, hi = (2 << d) - 1;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
     const int t = v < M.n ? M.node_of[v] : -1;
     const bool act = t >= lo && t < hi;
     (void)wave_append_keyed(&C->tcnt[0], act ? t : 0, act);
   }
 }
-__global__ void k_top_place(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_top_place(FpGrid fp_g, int d) {
   MESH;
-  if (gtid() != 0 || d >= C->D) return;
+  if (vt(fp_s) != 0 || d >= C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
   // A node that held a single patch at its level is a leaf: it gets that
   // patch's unmarked vertices only after the tree is done, and it also
@@ -896,11 +1063,11 @@ __global__ void k_top_place(const FpMesh* __restrict__ Mp, int d) {
   }
   C->top_shallow = shallow + tot;
 }
-__global__ void k_top_scatter(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_top_scatter(FpGrid fp_g, int d) {
   MESH;
   if (C->top_stop || d >= C->D) return;
   const int lo = (1 << d) - 1, hi = (2 << d) - 1;
-  for (int v0 = gwave() * 64; v0 < M.n; v0 += nwaves() * 64) {
+  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
     const int t = v < M.n ? M.node_of[v] : -1;
     const bool act = t >= lo && t < hi;
@@ -909,11 +1076,11 @@ __global__ void k_top_scatter(const FpMesh* __restrict__ Mp, int d) {
   }
 }
 // one wave (and the whole LDS) per depth-d node
-__global__ void __launch_bounds__(64) k_md_top(const FpMesh* __restrict__ Mp, int d) {
+__global__ void __launch_bounds__(64) k_md_top(FpGrid fp_g, int d) {
   MESH;
   FP_LDS_DECL;
   if (d >= uni(C->D)) return;
-  const int t = uni((1 << d) - 1 + (int)blockIdx.x);
+  const int t = uni((1 << d) - 1 + fp_s.bx);
   if (!uni(C->tearly[t])) return;
   const int m = uni(C->tcnt[t]), off = uni(C->toff[t]), pos0 = uni(C->tpos[t]);
   if (off < 0 || m < 0 || (long long)off + m > M.n) {
@@ -923,10 +1090,10 @@ __global__ void __launch_bounds__(64) k_md_top(const FpMesh* __restrict__ Mp, in
   md_node_list(M, t, M.tbuf + off, m, pos0, fp_lds, uni(M.lds_md));
 }
 // the schedule's ranges must be the ones the early orders took
-__global__ void k_top_check(const FpMesh* __restrict__ Mp, int ntop) {
+__global__ void k_top_check(FpGrid fp_g, int ntop) {
   MESH;
   ntop = min(ntop, C->nn);
-  for (int t = gtid(); t < ntop; t += gsize())
+  for (int t = vt(fp_s); t < ntop; t += vs(fp_s))
     if (C->tearly[t] &&
         (M.nsize[t] != C->tcnt[t] || (M.nsize[t] > 0 && M.nbegin[t] != C->tpos[t])))
       fp_fail(C, FP_E_INTERNAL, FP_SITE_TOP, t);
@@ -935,26 +1102,26 @@ __global__ void k_top_check(const FpMesh* __restrict__ Mp, int ntop) {
 // ==========================================================================
 // elimination tree and column counts, bottom-up over the tree levels
 // ==========================================================================
-__global__ void k_sym_init(const FpMesh* __restrict__ Mp, int d) {
+__global__ void k_sym_init(FpGrid fp_g, int d) {
   MESH;
-  if (gtid() == 0 && d <= C->D) {
+  if (vt(fp_s) == 0 && d <= C->D) {
     C->arena_top[d & 1] = 0;
     C->pool_top = 0;  // the pool holds one level's node scratch at a time
   }
 }
-__global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ Mp, int d) {
+__global__ void __launch_bounds__(FP_WG) k_sym_prep(FpGrid fp_g, int d) {
   MESH;
   FP_LDS_DECL;
   if (d > C->D) return;
   const int lw = M.lds_bytes / 4 / FP_WAVES;
   int* slice = (int*)fp_lds + lw * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  for (int x = gwave(); x < cnt; x += nwaves()) sym_prep(M, lo + x, d, slice, lw);
+  for (int x = vw(fp_s); x < cnt; x += vn(fp_s)) sym_prep(M, lo + x, d, slice, lw);
 }
 // Elimination of the nodes whose queue links and forward rows fit in an LDS
 // slice: cls 0 with four waves per workgroup (a quarter of the per-node LDS
 // each), cls 1 with one wave owning the large slice.
-__global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ Mp, int d, int cls) {
+__global__ void __launch_bounds__(FP_WG) k_sym_elim(FpGrid fp_g, int d, int cls) {
   MESH;
   FP_LDS_DECL;
   if (d > C->D) return;
@@ -962,37 +1129,37 @@ __global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ M
   if (wave_id() >= nsl) return;
   int* slice = (int*)fp_lds + (M.lds_bytes / 4 / nsl) * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  const int wv = uni((int)blockIdx.x * nsl + wave_id()), nw = (int)gridDim.x * nsl;
+  const int wv = uni(fp_s.bx * nsl + wave_id()), nw = fp_s.gx * nsl;
   const long long lw = cls == 0 ? M.lds_bytes / 4 / nsl : M.lds_big / 4;
   for (int x = wv; x < cnt; x += nw) sym_elim<true>(M, lo + x, cls, slice, lw);
 }
 // nodes too large for the whole LDS: links and rows in global memory
-__global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(const FpMesh* __restrict__ Mp, int d) {
+__global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(FpGrid fp_g, int d) {
   MESH;
   if (d > C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  for (int x = gwave(); x < cnt; x += nwaves()) sym_elim<false>(M, lo + x, 2, nullptr, 0);
+  for (int x = vw(fp_s); x < cnt; x += vn(fp_s)) sym_elim<false>(M, lo + x, 2, nullptr, 0);
 }
-__global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ Mp, int d) {
+__global__ void __launch_bounds__(FP_WG) k_sym_emit(FpGrid fp_g, int d) {
   MESH;
   if (d > C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
-  for (int x = gwave(); x < cnt; x += nwaves()) sym_emit(M, lo + x, d);
+  for (int x = vw(fp_s); x < cnt; x += vn(fp_s)) sym_emit(M, lo + x, d);
 }
 // The permuted pattern by position, for the symbolic stage: row p lists the
 // positions of the neighbours of vertex vperm[p].  One pass with a thread per
 // position; the symbolic kernels then read contiguous rows instead of
 // chasing vperm -> row pointers -> columns -> viperm per entry.
-__global__ void k_prow_deg(const FpMesh* __restrict__ Mp) {
+__global__ void k_prow_deg(FpGrid fp_g) {
   MESH;
-  for (int p = gtid(); p < M.n; p += gsize()) {
+  for (int p = vt(fp_s); p < M.n; p += vs(fp_s)) {
     const int v = M.vperm[p];
     M.pcnt[p] = (unsigned)v < (unsigned)M.n ? M.grp[v + 1] - M.grp[v] : 0;
   }
 }
-__global__ void k_prow_fill(const FpMesh* __restrict__ Mp) {
+__global__ void k_prow_fill(FpGrid fp_g) {
   MESH;
-  for (int p = gtid(); p < M.n; p += gsize()) {
+  for (int p = vt(fp_s); p < M.n; p += vs(fp_s)) {
     const int v = M.vperm[p];
     if ((unsigned)v >= (unsigned)M.n) continue;
     int o = M.prow[p];
@@ -1000,11 +1167,11 @@ __global__ void k_prow_fill(const FpMesh* __restrict__ Mp) {
   }
 }
 // nnz(L): the column counts summed per workgroup, one atomic each
-__global__ void __launch_bounds__(FP_WG) k_nnzl(const FpMesh* __restrict__ Mp) {
+__global__ void __launch_bounds__(FP_WG) k_nnzl(FpGrid fp_g) {
   MESH_WG;
   __shared__ long long part[FP_WAVES];
   long long s = 0;
-  for (int i = gtid(); i < M.n; i += gsize()) s += M.vcc[i];
+  for (int i = vt(fp_s); i < M.n; i += vs(fp_s)) s += M.vcc[i];
   s = wave_sum_i64(s);
   if (lane_id() == 0) part[wave_id()] = s;
   __syncthreads();
@@ -1018,12 +1185,12 @@ __global__ void __launch_bounds__(FP_WG) k_nnzl(const FpMesh* __restrict__ Mp) {
 // ==========================================================================
 // block expansion and outputs (Sec. 6.5)
 // ==========================================================================
-__global__ void k_expand(const FpMesh* __restrict__ Mp) {
+__global__ void k_expand(FpGrid fp_g) {
   MESH;
   const int nn = C->nn;
   const int b = M.b;
   const long long nd = M.n_dof;
-  for (long long j = gtid(); j < nd; j += gsize()) {
+  for (long long j = vt(fp_s); j < nd; j += vs(fp_s)) {
     const int k = (int)(j / b), r = (int)(j - (long long)k * b);
     M.perm[j] = M.vperm[k] * b + r;
     M.iperm[j] = M.viperm[k] * b + r;
@@ -1031,16 +1198,16 @@ __global__ void k_expand(const FpMesh* __restrict__ Mp) {
     M.parent[j] = r < b - 1 ? (int)(j + 1) : (M.vpar[k] < 0 ? -1 : M.vpar[k] * b);
   }
   if (M.gmap_out)
-    for (int v = gtid(); v < M.n; v += gsize()) M.gmap_out[v] = M.gmap[v];
+    for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.gmap_out[v] = M.gmap[v];
   if ((M.node_begin_out || M.node_size_out) && nn <= M.max_nodes_out)
-    for (int x = gtid(); x < nn; x += gsize()) {
+    for (int x = vt(fp_s); x < nn; x += vs(fp_s)) {
       if (M.node_begin_out) M.node_begin_out[x] = M.nbegin[x] * b;
       if (M.node_size_out) M.node_size_out[x] = M.nsize[x] * b;
     }
 }
-__global__ void k_finish(const FpMesh* __restrict__ Mp) {
+__global__ void k_finish(FpGrid fp_g) {
   MESH0;
-  if (gtid() != 0) return;
+  if (vt(fp_s) != 0) return;
   const int nn = C->nn;
   if ((M.node_begin_out || M.node_size_out) && nn > M.max_nodes_out)
     fp_fail(C, FP_E_SCRATCH, FP_SITE_OUT_NODES, nn);
@@ -1087,6 +1254,7 @@ namespace {
 using fpplan::fill_mesh;
 using fpplan::make_plan;
 using fpplan::Plan;
+using fpplan::align_up;
 
 fp_status check_opts(const fp_options* o) {
   if (!o) return FP_ERR_ARG;
@@ -1116,56 +1284,85 @@ fp_status map_err(unsigned e) {
   return FP_OK;
 }
 
-// one ordering job: launches in stream order, reads scalars through the
-// handle's pinned buffer
-// every launch of the pipeline goes through these, so that one kernel can be
-// timed with events on the call's stream (fp_time_kernel)
-#define FP_LAUNCH_(JOB, k, g, b, l, s, ...)                 \
-  do {                                                     \
-    const bool tk_ = (JOB).tk(#k);                         \
-    if (tk_) (JOB).tk_begin(s);                            \
-    hipLaunchKernelGGL(k, g, b, l, s, __VA_ARGS__);        \
-    if (tk_) (JOB).tk_end(s);                              \
-  } while (0)
-#define FPLM(...) FP_LAUNCH_(*this, __VA_ARGS__)
-#define FPL(...) FP_LAUNCH_(J, __VA_ARGS__)
+// ==========================================================================
+// The pipeline on the host.  One Pipe queues Alg. 1 for one mesh or for a
+// batch of meshes: every launch covers all meshes at once (each mesh gets
+// the blocks it would get alone; a mesh with no part in a launch gets none).
+// The same code runs twice for a batch: a planning pass records the block
+// table of every launch (no HIP calls), then the launching pass reads it
+// back from device memory in the same order.  Nothing is read back to the
+// host: counts known only on the device (patches, tree depth, arcs,
+// frontier sizes) are read by the kernels, launch grids come from
+// capacities or expected values, and every kernel returns at once after an
+// earlier stage raised an error.
+// ==========================================================================
+static int ceil_log2(long long x) {
+  int d = 0;
+  while ((1ll << d) < x) d++;
+  return d;
+}
 
-struct Job {
+// host-known sizes of one mesh
+struct MeshPlan {
+  int n;
+  long long n_dof;
+  int S;
+  int lloyd;
+  bool user;      // user groups instead of patching
+  bool validate;  // symmetry check
+  int sched;      // FP_SCHED_LEVEL or FP_SCHED_POST
+  int P0, Pexp;   // seed blocks; expected patch count (exact without orphans)
+  int Dexp, Dmax; // expected and largest possible tree depth (P <= n)
+  int NNcap;
+  int Lg, Ld;     // launched levels of the growth and distance BFS
+};
+
+MeshPlan mesh_plan(const FpMesh& M, bool user) {
+  MeshPlan m;
+  m.n = M.n;
+  m.n_dof = M.n_dof;
+  m.S = M.S;
+  m.lloyd = M.lloyd;
+  m.user = user;
+  m.validate = M.validate != 0;
+  m.sched = M.sched;
+  m.P0 = fp_p0(M.n, M.S);
+  m.Pexp = std::max(m.P0, 1);
+  m.Dexp = ceil_log2(m.Pexp);
+  m.Dmax = ceil_log2(std::max(M.n, 1));
+  m.NNcap = M.NNcap;
+  m.Lg = fp_bfs_levels(M.n, M.S, false);
+  m.Ld = fp_bfs_levels(M.n, M.S, true);
+  return m;
+}
+
+struct Pipe {
   fp_handle* h;
   hipStream_t st;
-  FpMesh hm;         // host copy of the job description
-  const FpMesh* dm;  // device copy
-  FpCtl* ctl;
+  std::vector<MeshPlan> mp;
+  const FpMesh* dm = nullptr;  // device array of the meshes' descriptions
+  FpCtl* ctl0 = nullptr;       // control block of the single mesh
+  bool single = true;          // one mesh: no block table; side streams and timing allowed
+  bool plan = false;           // planning pass of a batch
+  std::vector<int> tab;        // block tables, launch after launch (nm + 1 ints each)
+  const int* dtab = nullptr;   // their device copy (launching pass)
+  size_t tpos = 0;
   bool hip_failed = false;
   bool timing = false;
-  bool validate = false;    // symmetry check of the pattern
-  bool fixed = false;       // no side streams and no per-kernel events (static-scratch calls)
-  bool side_open = false;   // work on the side stream not yet joined
-  bool side2_open = false;  // same for the second side stream
+  bool fixed = false;      // no side streams and no per-kernel events (static-scratch calls)
+  bool side_open = false;  // work on the side stream not yet joined
+  bool side2_open = false; // same for the second side stream
+  int nm() const { return (int)mp.size(); }
+  int ncu() const { return h->ncu; }
 
-  // the call's stream waits for everything issued on the side streams
-  void join_side() {
-    if (side_open) {
-      side_open = false;
-      if (hipEventRecord(h->ev_join, h->side) != hipSuccess ||
-          hipStreamWaitEvent(st, h->ev_join, 0) != hipSuccess)
-        hip_failed = true;
-    }
-    if (side2_open) {  // both large-class streams
-      side2_open = false;
-      if (hipEventRecord(h->ev_join2, h->side2) != hipSuccess ||
-          hipEventRecord(h->ev_join3, h->side3) != hipSuccess ||
-          hipStreamWaitEvent(st, h->ev_join2, 0) != hipSuccess ||
-          hipStreamWaitEvent(st, h->ev_join3, 0) != hipSuccess)
-        hip_failed = true;
-    }
+  long long blk(long long items, int per = FP_WG) const {
+    const long long b = (items + per - 1) / per;
+    return std::max(1ll, std::min(b, 8ll * h->ncu));
   }
-
   // timing of one kernel (fp_time_kernel): events around each of its launches
   bool tk(const char* name) const {
-    return !fixed && h->tk_name[0] && strcmp(h->tk_name, name) == 0;
+    return single && !fixed && h->tk_name[0] && strcmp(h->tk_name, name) == 0;
   }
-  // the events go on the launch's own stream
   void tk_begin(hipStream_t ls) {
     if ((int)h->tk_ev.size() < 2 * (h->tk_n + 1)) {
       hipEvent_t a, b;
@@ -1183,65 +1380,95 @@ struct Job {
     if (hipEventRecord(h->tk_ev[2 * h->tk_n + 1], ls) != hipSuccess) h->tk_failed = true;
     h->tk_n++;
   }
-
   void mark(int i) {
-    if (timing && hipEventRecord(h->ev[i], st) != hipSuccess) hip_failed = true;
+    if (single && timing && hipEventRecord(h->ev[i], st) != hipSuccess) hip_failed = true;
   }
-  int blocks(long long items, int per = FP_WG) const {
-    long long b = (items + per - 1) / per;
-    return (int)std::max(1ll, std::min(b, 8ll * h->ncu));
+  // One launch: bl(i) blocks for mesh i (<= 0: none).
+  template <class BL, class K, class... A>
+  void go(const char* name, K kern, BL bl, dim3 T, size_t lds, hipStream_t s, A... args) {
+    if (single) {
+      const long long b = bl(0);
+      if (b <= 0) return;
+      const bool t = tk(name);
+      if (t) tk_begin(s);
+      hipLaunchKernelGGL(kern, dim3((unsigned)b), T, lds, s, FpGrid{dm, nullptr, 1}, args...);
+      if (t) tk_end(s);
+      return;
+    }
+    const int n = nm();
+    if (plan) {
+      long long o = 0;
+      tab.push_back(0);
+      for (int i = 0; i < n; i++) {
+        o += std::max(0ll, (long long)bl(i));
+        tab.push_back((int)std::min(o, (long long)INT32_MAX));
+      }
+      return;
+    }
+    const size_t at = tpos;
+    tpos += n + 1;
+    if (at + n >= tab.size()) {
+      hip_failed = true;
+      return;
+    }
+    const int tot = tab[at + n];
+    if (tot <= 0) return;
+    hipLaunchKernelGGL(kern, dim3((unsigned)tot), T, lds, s, FpGrid{dm, dtab + at, n}, args...);
   }
   void check() {
-    if (hipGetLastError() != hipSuccess) hip_failed = true;
+    if (!plan && hipGetLastError() != hipSuccess) hip_failed = true;
   }
-  // read `count` ints of the control block starting at `field`
-  void read(const void* field, int count) {
-    if (hipMemcpyAsync(h->host, field, 4 * count, hipMemcpyDeviceToHost, st) != hipSuccess ||
-        hipStreamSynchronize(st) != hipSuccess)
-      hip_failed = true;
+  // the call's stream waits for everything issued on the side streams
+  void join_side() {
+    if (side_open) {
+      side_open = false;
+      if (hipEventRecord(h->ev_join, h->side) != hipSuccess ||
+          hipStreamWaitEvent(st, h->ev_join, 0) != hipSuccess)
+        hip_failed = true;
+    }
+    if (side2_open) {  // both large-class streams
+      side2_open = false;
+      if (hipEventRecord(h->ev_join2, h->side2) != hipSuccess ||
+          hipEventRecord(h->ev_join3, h->side3) != hipSuccess ||
+          hipStreamWaitEvent(st, h->ev_join2, 0) != hipSuccess ||
+          hipStreamWaitEvent(st, h->ev_join3, 0) != hipSuccess)
+        hip_failed = true;
+    }
   }
-  int read1(const int* field) {
-    read(field, 1);
-    return hip_failed ? 0 : h->host[0];
-  }
-  unsigned err() {
-    read(&ctl->err, 1);
-    return hip_failed ? 0xFFFFFFFFu : (unsigned)h->host[0];
-  }
-  // exclusive scan of in[0..count) into out, total to *total; count is cap
-  // or, with n_dev, the device value clamped to cap
-  void scan(const int* in, int* out, int cap, int* total, const int* n_dev = nullptr) {
-    const int np = std::max(1, std::min(1024, (cap + 4095) / 4096));
-    const int chunk = std::max(1, (cap + np - 1) / np);
-    FPLM(k_scan_part, dim3(np), dim3(FP_WG), 0, st, in, cap, n_dev, chunk, ctl->part);
-    FPLM(k_scan_top, dim3(1), dim3(FP_WG), 0, st, ctl->part, np, total);
-    FPLM(k_scan_apply, dim3(np), dim3(FP_WG), 0, st, in, out, cap, n_dev, chunk, ctl->part);
+  // exclusive scan of array `ain` into `aout` over count `fcnt`, total to `tdst`
+  void scan(int ain, int aout, int fcnt, int tdst) {
+    auto cap = [&](int i) { return fcnt == FN_NNCAP || fcnt == FN_NN ? mp[i].NNcap : mp[i].n; };
+    go("k_scan_part", k_mscan_part, [&](int i) { return scan_blocks(cap(i)); }, dim3(FP_WG), 0, st,
+       ain, fcnt);
+    go("k_scan_top", k_mscan_top, [&](int) { return 1; }, dim3(FP_WG), 0, st, fcnt, tdst);
+    go("k_scan_apply", k_mscan_apply, [&](int i) { return scan_blocks(cap(i)); }, dim3(FP_WG), 0,
+       st, ain, aout, fcnt);
     check();
   }
-  // Frontier BFS from the level-0 frontier already in place: `levels`
-  // launches of a level each (a launch past the last level finds an empty
-  // frontier and returns at once), then one workgroup continues from there
-  // until a frontier comes out empty.  Nothing is read back.
-  void bfs(int levels) {
-    const int n = hm.n;
-    const int L = std::max(0, std::min(levels, n));
-    for (int k = 0; k < L; k++) FPLM(k_bfs_level, dim3(blocks(n)), dim3(FP_WG), 0, st, dm, k);
-    FPLM(k_bfs_tail, dim3(1), dim3(1024), 0, st, dm, L);
+  // Frontier BFS from the level-0 frontier already in place: each mesh's
+  // launched levels (a launch past its last level finds an empty frontier
+  // and returns at once), then one workgroup per mesh continues until a
+  // frontier comes out empty.  `on(i)`: mesh i takes part.
+  template <class ON>
+  void bfs(bool inner, ON on) {
+    int L = 0;
+    for (int i = 0; i < nm(); i++)
+      if (on(i)) L = std::max(L, inner ? mp[i].Ld : mp[i].Lg);
+    for (int k = 0; k < L; k++)
+      go("k_bfs_level", k_bfs_level,
+         [&](int i) { return on(i) && k < (inner ? mp[i].Ld : mp[i].Lg) ? blk(mp[i].n) : 0; },
+         dim3(FP_WG), 0, st, k);
+    go("k_bfs_tail", k_bfs_tail, [&](int i) { return on(i) ? 1 : 0; }, dim3(1024), 0, st,
+       inner ? 1 : 0);
     check();
-  }
-  // nseeds < 0: the device patch count
-  void grow(int nseeds, int nseeds_exp, int levels) {
-    const int n = hm.n;
-    FPLM(k_key_unset, dim3(blocks(n)), dim3(FP_WG), 0, st, dm);
-    FPLM(k_seed_push, dim3(blocks(nseeds_exp)), dim3(FP_WG), 0, st, dm, nseeds);
-    check();
-    bfs(levels);
   }
 };
 
+#define FPG(...) P.go(__VA_ARGS__)
+
 // The side stream and its events, created on first use: every stream takes
 // one of the device's hardware queues in turn, so a handle that never uses
-// it (a lane of the batched calls) should not hold one.
+// it (a lane of the served calls) should not hold one.
 bool ensure_side(fp_handle* h) {
   if (h->side) return true;
   hipStream_t s[3] = {nullptr, nullptr, nullptr};
@@ -1264,123 +1491,144 @@ bool ensure_side(fp_handle* h) {
   return true;
 }
 
-// Levels of a growth BFS launched one by one before the tail takes over:
-// about twice the radius of a patch of S vertices on a triangle mesh, at
-// most 64.  The distance BFS of Lloyd's step runs inside patches (half).
-static int bfs_levels(int S, bool inner) {
-  const int r = (int)std::ceil(std::sqrt((double)std::max(S, 1)));
-  return std::min(64, (inner ? r : 2 * r) + 4);
-}
-static int ceil_log2(long long x) {
-  int d = 0;
-  while ((1ll << d) < x) d++;
-  return d;
-}
-
-// Queue the whole pipeline on J.st (and the side streams, joined back).
-// Nothing is read back to the host: counts known only on the device (patches,
-// tree depth, arcs, frontier sizes) are read there, launch grids come from
-// capacities or expected values, and every kernel returns at once once an
-// earlier stage has raised an error.  The tree depth D is at most
-// ceil(log2 n); levels past the expected depth get small grids.
-fp_status run_job(Job& J) {
-  const int n = J.hm.n;
-  const FpMesh* dm = J.dm;
-  hipStream_t st = J.st;
-  FpCtl* C = J.ctl;
-  auto B = [&](long long items) { return dim3(J.blocks(items)); };
+// Queue Alg. 1 for every mesh of the pipe.  Levels of the separator tree and
+// of the symbolic stage run to each mesh's largest possible depth
+// (ceil(log2 n)); levels past the expected depth get one block.
+fp_status run_pipe(Pipe& P) {
+  hipStream_t st = P.st;
+  const int nm = P.nm();
+  auto& mp = P.mp;
   const dim3 T(FP_WG);
-  const int P0 = n > 0 ? (int)(((long long)n + J.hm.S - 1) / J.hm.S) : 0;
-  const int Pexp = std::max(P0, 1);            // expected patch count (exact without orphans)
-  const int Dexp = ceil_log2(Pexp);             // expected tree depth
-  const int Dmax = ceil_log2(std::max(n, 1));   // P <= n
-  auto BL = [&](int d, long long items) {       // grid of a tree level
-    return d <= Dexp ? B(items) : dim3(1);
-  };
+  auto per_n = [&](int i) { return P.blk(mp[i].n); };
+  auto one = [&](int) { return 1ll; };
+  int Dmax = 0, Lloyd = 0;
+  bool any_patch = false, any_user = false;
+  for (int i = 0; i < nm; i++) {
+    Dmax = std::max(Dmax, mp[i].Dmax);
+    if (mp[i].user) any_user = true;
+    else if (mp[i].n > 0) {
+      any_patch = true;
+      Lloyd = std::max(Lloyd, mp[i].lloyd);
+    }
+  }
+  auto patching = [&](int i) { return !mp[i].user && mp[i].n > 0; };
 
   // ingest
-  J.mark(0);
-  FPL(k_ingest, B(n), T, 0, st, dm, 0);
-  FPL(k_ingest_long, dim3(J.h->ncu), T, 0, st, dm, 0);
-  J.scan(J.hm.pcnt, J.hm.grp, n, &C->nnz_g);
-  FPL(k_check_graph, dim3(1), dim3(64), 0, st, dm);
-  FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.grp + n, &C->nnz_g);
-  FPL(k_ingest, B(n), T, 0, st, dm, 1);
-  FPL(k_ingest_long, dim3(J.h->ncu), T, 0, st, dm, 1);
-  if (J.validate) FPL(k_validate, B(n), T, 0, st, dm);
-  J.check();
+  P.mark(0);
+  FPG("k_ingest", k_ingest, per_n, T, 0, st, 0);
+  FPG("k_ingest_long", k_ingest_long, [&](int) { return (long long)P.ncu(); }, T, 0, st, 0);
+  P.scan(FA_PCNT, FA_GRP, FN_N, FT_NNZG);
+  FPG("k_check_graph", k_check_graph, one, dim3(64), 0, st);
+  FPG("k_mptr_end", k_mptr_end, one, dim3(64), 0, st, (int)FA_GRP, (int)FN_N, (int)FT_NNZG);
+  FPG("k_ingest", k_ingest, per_n, T, 0, st, 1);
+  FPG("k_ingest_long", k_ingest_long, [&](int) { return (long long)P.ncu(); }, T, 0, st, 1);
+  FPG("k_validate", k_validate, [&](int i) { return mp[i].validate ? P.blk(mp[i].n) : 0; }, T, 0,
+      st);
+  P.check();
 
   // patches
-  J.mark(1);
-  if (J.hm.user_gmap) {
-    FPL(k_user_gmap, B(n), T, 0, st, dm);
-    J.check();
-  } else if (n > 0) {
-    const int Lg = bfs_levels(J.hm.S, false), Ld = bfs_levels(J.hm.S, true);
-    FPL(k_seeds, dim3(J.blocks(P0, FP_WAVES)), T, 0, st, dm, P0);
-    J.check();
-    J.grow(P0, P0, Lg);
-    FPL(k_count_unset, B(n), T, 0, st, dm);
+  P.mark(1);
+  if (any_user)
+    FPG("k_user_gmap", k_user_gmap, [&](int i) { return mp[i].user ? P.blk(mp[i].n) : 0; }, T, 0,
+        st);
+  if (any_patch) {
+    auto pn = [&](int i) { return patching(i) ? P.blk(mp[i].n) : 0; };
+    FPG("k_seeds", k_seeds, [&](int i) { return patching(i) ? P.blk(mp[i].P0, FP_WAVES) : 0; }, T,
+        0, st);
+    FPG("k_key_unset", k_key_unset, pn, T, 0, st);
+    FPG("k_seed_push", k_seed_push, [&](int i) { return patching(i) ? P.blk(mp[i].P0) : 0; }, T, 0,
+        st, 0);
+    P.bfs(false, patching);
+    FPG("k_count_unset", k_count_unset, pn, T, 0, st);
     // components growth did not reach (none on a connected mesh: every
     // kernel here then returns at once)
-    FPL(k_cc_init, B(n), T, 0, st, dm);
+    FPG("k_cc_init", k_cc_init, pn, T, 0, st);
     for (int r = 0; r < FP_CC_ROUNDS; r++) {
-      FPL(k_cc_hook, B(n), T, 0, st, dm, r);
-      FPL(k_cc_jump, B(n), T, 0, st, dm, r);
+      FPG("k_cc_hook", k_cc_hook, pn, T, 0, st, r);
+      FPG("k_cc_jump", k_cc_jump, pn, T, 0, st, r);
     }
-    FPL(k_cc_tail, dim3(1), dim3(1024), 0, st, dm, FP_CC_ROUNDS);
-    FPL(k_cc_flags, B(n), T, 0, st, dm);
-    J.scan(J.hm.pcnt, J.hm.pcnt, n, &C->nroot, &C->ccn);
-    FPL(k_cc_label, B(n), T, 0, st, dm);
-    J.check();
-    for (int it = 0; it < J.hm.lloyd; it++) {
-      FPL(k_lloyd_gmap, B(n), T, 0, st, dm);
-      FPL(k_lloyd_bnd, B(n), T, 0, st, dm);
-      J.check();
-      J.bfs(Ld);
-      FPL(k_lloyd_best, B(n), T, 0, st, dm);
-      FPL(k_lloyd_seed, B(Pexp), T, 0, st, dm);
-      J.check();
-      J.grow(-1, Pexp, Lg);
+    FPG("k_cc_tail", k_cc_tail, [&](int i) { return patching(i) ? 1 : 0; }, dim3(1024), 0, st,
+        FP_CC_ROUNDS);
+    FPG("k_cc_flags", k_cc_flags, pn, T, 0, st);
+    {
+      // only patching meshes take part in the scan of their component roots
+      auto cap = [&](int i) { return patching(i) ? scan_blocks(mp[i].n) : 0; };
+      FPG("k_scan_part", k_mscan_part, cap, T, 0, st, (int)FA_PCNT, (int)FN_CCN);
+      FPG("k_scan_top", k_mscan_top, [&](int i) { return patching(i) ? 1 : 0; }, T, 0, st,
+          (int)FN_CCN, (int)FT_NROOT);
+      FPG("k_scan_apply", k_mscan_apply, cap, T, 0, st, (int)FA_PCNT, (int)FA_PCNT, (int)FN_CCN);
     }
-    FPL(k_gmap_final, B(n), T, 0, st, dm);
-    J.check();
+    FPG("k_cc_label", k_cc_label, pn, T, 0, st);
+    P.check();
+    for (int it = 0; it < Lloyd; it++) {
+      auto on = [&](int i) { return patching(i) && it < mp[i].lloyd; };
+      auto ln = [&](int i) { return on(i) ? P.blk(mp[i].n) : 0; };
+      FPG("k_lloyd_gmap", k_lloyd_gmap, ln, T, 0, st);
+      FPG("k_lloyd_bnd", k_lloyd_bnd, ln, T, 0, st);
+      P.check();
+      P.bfs(true, on);
+      FPG("k_lloyd_best", k_lloyd_best, ln, T, 0, st);
+      FPG("k_lloyd_seed", k_lloyd_seed, [&](int i) { return on(i) ? P.blk(mp[i].Pexp) : 0; }, T, 0,
+          st);
+      FPG("k_key_unset", k_key_unset, ln, T, 0, st);
+      FPG("k_seed_push", k_seed_push, [&](int i) { return on(i) ? P.blk(mp[i].Pexp) : 0; }, T, 0,
+          st, 1);
+      P.bfs(false, on);
+    }
+    FPG("k_gmap_final", k_gmap_final, pn, T, 0, st);
+    P.check();
   }
 
   // quotient graph (P on the device)
-  J.mark(2);
-  FPL(k_fill_n, B(Pexp + 1), T, 0, st, J.hm.pcnt, &C->P, 1, n + 1, 0);
-  FPL(k_fill, dim3(1), dim3(64), 0, st, &C->nbnd, 1, 0);
-  FPL(k_patch_count, B(n), T, 0, st, dm);
-  FPL(k_copy_n, B(Pexp), T, 0, st, J.hm.wp, J.hm.pcnt, &C->P, n);
-  J.check();
-  J.scan(J.hm.pcnt, J.hm.pptr, n, &C->tot, &C->P);
-  FPL(k_set_at, dim3(1), dim3(1), 0, st, J.hm.pptr, &C->P, n, &C->tot);
-  FPL(k_copy_n, B(Pexp), T, 0, st, J.hm.pcnt, J.hm.pptr, &C->P, n);
-  FPL(k_patch_scatter, B(n), T, 0, st, dm);
+  P.mark(2);
+  FPG("k_quot_init", k_quot_init, [&](int i) { return P.blk(mp[i].Pexp + 1); }, T, 0, st);
+  FPG("k_patch_count", k_patch_count, per_n, T, 0, st);
+  FPG("k_copy", k_mcopy, [&](int i) { return P.blk(mp[i].Pexp); }, T, 0, st, (int)FA_WP,
+      (int)FA_PCNT, (int)FN_P);
+  P.check();
+  P.scan(FA_PCNT, FA_PPTR, FN_P, FT_TOT);
+  FPG("k_set", k_mptr_end, one, dim3(64), 0, st, (int)FA_PPTR, (int)FN_P, (int)FT_TOT);
+  FPG("k_copy", k_mcopy, [&](int i) { return P.blk(mp[i].Pexp); }, T, 0, st, (int)FA_PCNT,
+      (int)FA_PPTR, (int)FN_P);
+  FPG("k_patch_scatter", k_patch_scatter, per_n, T, 0, st);
   // a patch-id bitmap per wave when four of them fit in 64 KB of LDS (for
   // the expected patch count; the kernel checks the actual one)
-  const int qbw = (long long)(Pexp + 31) / 32 * 4 * FP_WAVES <= 65536 ? (Pexp + 31) / 32 : 0;
-  FPL(k_qrow, dim3(J.blocks(Pexp, FP_WAVES)), T, qbw * 4 * FP_WAVES, st, dm, 0, qbw);
-  J.check();
-  J.scan(J.hm.pcnt, J.hm.qptr, n, &C->nq, &C->P);
-  FPL(k_set_at, dim3(1), dim3(1), 0, st, J.hm.qptr, &C->P, n, &C->nq);
-  FPL(k_check_arcs, dim3(1), dim3(64), 0, st, dm);
-  FPL(k_qrow, dim3(J.blocks(Pexp, FP_WAVES)), T, qbw * 4 * FP_WAVES, st, dm, 1, qbw);
-  J.check();
+  int qbw = 0;
+  for (int i = 0; i < nm; i++) {
+    const int w = (mp[i].Pexp + 31) / 32;
+    if ((long long)w * 4 * FP_WAVES <= 65536) qbw = std::max(qbw, w);
+  }
+  auto qb = [&](int i) { return P.blk(mp[i].Pexp, FP_WAVES); };
+  FPG("k_qrow", k_qrow, qb, T, (size_t)qbw * 4 * FP_WAVES, st, 0, qbw);
+  P.check();
+  P.scan(FA_PCNT, FA_QPTR, FN_P, FT_NQ);
+  FPG("k_set", k_mptr_end, one, dim3(64), 0, st, (int)FA_QPTR, (int)FN_P, (int)FT_NQ);
+  FPG("k_check_arcs", k_check_arcs, one, dim3(64), 0, st);
+  FPG("k_qrow", k_qrow, qb, T, (size_t)qbw * 4 * FP_WAVES, st, 1, qbw);
+  P.check();
 
   // separator tree
-  J.mark(3);
-  FPL(k_sep_init, B(n), T, 0, st, dm);
-  // top separators ordered early on the side streams (level order only:
-  // there their ranges depend on the top levels alone)
-  const int TL = J.hm.sched == 0 && !J.fixed && J.h->side_ok && ensure_side(J.h)
-                     ? std::min(FP_TOP_LEVELS, Dmax)
+  P.mark(3);
+  FPG("k_sep_init", k_sep_init, per_n, T, 0, st);
+  // top separators ordered early on the side streams (one mesh, level
+  // order: there their ranges depend on the top levels alone)
+  const int TL = P.single && mp[0].n > 0 && mp[0].sched == FP_SCHED_LEVEL && P.h->side_ok &&
+                         !P.fixed && ensure_side(P.h)
+                     ? std::min(FP_TOP_LEVELS, mp[0].Dmax)
                      : 0;
-  const int ntop = (1 << TL) - 1;
+  auto lvl = [&](int d, long long items) {  // a tree level of mesh i: small past Dexp
+    return [&, d, items](int i) -> long long {
+      if (d >= mp[i].Dmax) return 0;
+      return d <= mp[i].Dexp ? P.blk(items > 0 ? items : mp[i].n) : 1;
+    };
+  };
   for (int d = 0; d < Dmax; d++) {
-    FPL(k_level_begin, BL(d, 8ll * Pexp), T, 0, st, dm, d);
-    FPL(k_arcs, BL(d, n), T, 0, st, dm, d);
+    FPG("k_level_begin", k_level_begin,
+        [&, d](int i) -> long long {
+          return d >= mp[i].Dmax ? 0 : d <= mp[i].Dexp ? P.blk(8ll * mp[i].Pexp) : 1;
+        },
+        T, 0, st, d);
+    FPG("k_arcs", k_arcs, lvl(d, 0), T, 0, st, d);
     {
       // LDS for the local quotient subgraphs: a node at depth d holds about
       // 2^(Dexp-d) patches.  While the level has no more nodes than CUs,
@@ -1388,102 +1636,128 @@ fp_status run_job(Job& J) {
       // deeper, about 8 alive arcs per patch, so several workgroups share a
       // CU (a node that does not fit runs from global memory).  The
       // kernel's static LDS comes on top.
-      const long long cap = 1ll << std::max(0, Dexp - d);
-      const long long want =
-          (1ll << d) <= J.h->ncu ? J.h->lds_big : (4 * (13 * cap + 1) + 255) & ~255ll;
-      const int lb = (int)std::min<long long>(J.h->lds_big - 1024, want);
-      const dim3 gb = d <= Dexp ? dim3(std::min(1 << std::min(d, 30), 4 * J.h->ncu)) : dim3(1);
-      FPL(k_bisect, gb, T, lb, st, dm, d, lb);
+      long long want = 0;
+      for (int i = 0; i < nm; i++) {
+        if (d >= mp[i].Dmax) continue;
+        const long long cap = 1ll << std::max(0, mp[i].Dexp - d);
+        want = std::max(want, (1ll << d) <= P.ncu() ? (long long)P.h->lds_big
+                                                     : (4 * (13 * cap + 1) + 255) & ~255ll);
+      }
+      const int lb = (int)std::min<long long>(P.h->lds_big - 1024, std::max(want, 256ll));
+      FPG("k_bisect", k_bisect,
+          [&, d](int i) -> long long {
+            if (d >= mp[i].Dmax) return 0;
+            return d <= mp[i].Dexp ? std::min(1 << std::min(d, 30), 4 * P.ncu()) : 1;
+          },
+          T, lb, st, d, lb);
     }
-    FPL(k_cand, BL(d, n), T, 0, st, dm, d);
-    FPL(k_mark, BL(d, n), T, 0, st, dm, d);
+    FPG("k_cand", k_cand, lvl(d, 0), T, 0, st, d);
+    FPG("k_mark", k_mark, lvl(d, 0), T, 0, st, d);
     if (d < TL) {
-      FPL(k_top_count, B(n), T, 0, st, dm, d);
-      FPL(k_top_place, dim3(1), dim3(64), 0, st, dm, d);
-      FPL(k_top_scatter, B(n), T, 0, st, dm, d);
+      const long long b = P.blk(mp[0].n);
+      FPG("k_top_count", k_top_count, [&](int) { return b; }, T, 0, st, d);
+      FPG("k_top_place", k_top_place, one, dim3(64), 0, st, d);
+      FPG("k_top_scatter", k_top_scatter, [&](int) { return b; }, T, 0, st, d);
       // one stream per level, so a level does not wait for the one above;
       // the large local-order classes follow on the second and third
-      hipStream_t sd = d == 0 ? J.h->side : d == 1 ? J.h->side2 : J.h->side3;
-      if (hipEventRecord(J.h->ev_top[d], st) != hipSuccess ||
-          hipStreamWaitEvent(sd, J.h->ev_top[d], 0) != hipSuccess)
-        J.hip_failed = true;
+      hipStream_t sd = d == 0 ? P.h->side : d == 1 ? P.h->side2 : P.h->side3;
+      if (hipEventRecord(P.h->ev_top[d], st) != hipSuccess ||
+          hipStreamWaitEvent(sd, P.h->ev_top[d], 0) != hipSuccess)
+        P.hip_failed = true;
       if (d == 0)
-        J.side_open = true;
+        P.side_open = true;
       else
-        J.side2_open = true;
-      FPL(k_md_top, dim3(1 << d), dim3(64), J.h->lds_md, sd, dm, d);
+        P.side2_open = true;
+      FPG("k_md_top", k_md_top, [&, d](int) { return 1ll << d; }, dim3(64), P.h->lds_md, sd, d);
     }
-    J.check();
+    P.check();
   }
-  FPL(k_leaves, B(n), T, 0, st, dm);
+  FPG("k_leaves", k_leaves, per_n, T, 0, st);
 
   // grouping in schedule order (heap size nn on the device)
-  J.mark(4);
-  const int NNexp = (2 << Dexp) - 1;
-  FPL(k_nsize, B(n), T, 0, st, dm);
-  FPL(k_nsize_count, B(n), T, 0, st, dm);
-  FPL(k_sched_place, B(NNexp), T, 0, st, dm);
-  J.check();
-  J.scan(J.hm.sbuf, J.hm.sbuf, J.hm.NNcap, &C->tot, &C->nn);
-  FPL(k_nbegin, B(NNexp), T, 0, st, dm);
-  FPL(k_scatter, B(n), T, 0, st, dm);
-  if (ntop) FPL(k_top_check, dim3(1), dim3(64), 0, st, dm, ntop);
-  J.check();
+  P.mark(4);
+  auto nnexp = [&](int i) { return P.blk((2ll << mp[i].Dexp) - 1); };
+  FPG("k_nsize", k_nsize, per_n, T, 0, st);
+  FPG("k_nsize_count", k_nsize_count, per_n, T, 0, st);
+  FPG("k_sched_place", k_sched_place, nnexp, T, 0, st);
+  P.check();
+  P.scan(FA_SBUF, FA_SBUF, FN_NN, FT_TOT);
+  FPG("k_nbegin", k_nbegin, nnexp, T, 0, st);
+  FPG("k_scatter", k_scatter, per_n, T, 0, st);
+  const int ntop = (1 << TL) - 1;
+  if (ntop) FPG("k_top_check", k_top_check, one, dim3(64), 0, st, ntop);
+  P.check();
 
   // local orders
-  J.mark(5);
-  FPL(k_fill, dim3(1), dim3(64), 0, st, C->task_cnt, 16, 0);
-  FPL(k_md_tasks, dim3(1), dim3(1024), 0, st, dm, ntop);
+  P.mark(5);
+  FPG("k_md_tasks", k_md_tasks, one, dim3(1024), 0, st, ntop);
   {
     // The largest class (one wave per CU, the longest nodes) goes first on
     // this stream, so its workgroups take their CUs before the others fill
-    // the rest; class 1 follows the depth-1 orders on the second side
-    // stream, classes 2 and 3 the depth-2 orders on the third.
-    const bool two = !J.fixed && J.h->side_ok && ensure_side(J.h);
+    // the rest; for one mesh, class 1 follows the depth-1 orders on the
+    // second side stream, classes 2 and 3 the depth-2 orders on the third.
+    const bool two = P.single && !P.fixed && P.h->side_ok && ensure_side(P.h);
     if (two) {
-      if (hipEventRecord(J.h->ev_md, st) != hipSuccess ||
-          hipStreamWaitEvent(J.h->side2, J.h->ev_md, 0) != hipSuccess ||
-          hipStreamWaitEvent(J.h->side3, J.h->ev_md, 0) != hipSuccess)
-        J.hip_failed = true;
-      J.side2_open = true;
+      if (hipEventRecord(P.h->ev_md, st) != hipSuccess ||
+          hipStreamWaitEvent(P.h->side2, P.h->ev_md, 0) != hipSuccess ||
+          hipStreamWaitEvent(P.h->side3, P.h->ev_md, 0) != hipSuccess)
+        P.hip_failed = true;
+      P.side2_open = true;
     }
     for (int c = 0; c < FP_MD_CLASSES; c++) {
-      hipStream_t sc = !two || c == 0 ? st : c == 1 ? J.h->side2 : J.h->side3;
-      FPL(k_md, dim3(2 * J.h->ncu), T, c == 3 ? J.h->lds_bytes : J.h->lds_md, sc, dm, c);
+      hipStream_t sc = !two || c == 0 ? st : c == 1 ? P.h->side2 : P.h->side3;
+      // one workgroup per CU twice over for one mesh; in a batch, a share
+      // of that in proportion to the mesh's expected node count
+      FPG("k_md", k_md,
+          [&](int i) -> long long {
+            if (P.single) return 2ll * P.ncu();
+            return std::max(1ll, std::min(2ll * P.ncu(), (2ll * mp[i].Pexp + FP_WAVES - 1) / FP_WAVES));
+          },
+          T, c == 3 ? P.h->lds_bytes : P.h->lds_md, sc, c);
     }
   }
-  J.join_side();
-  J.check();
+  if (P.single) P.join_side();
+  P.check();
 
   // elimination tree and column counts, bottom-up over the tree levels (a
   // node whose local order failed raised an error: these kernels then return)
-  J.mark(6);
-  FPL(k_prow_deg, B(n), T, 0, st, dm);
-  J.scan(J.hm.pcnt, J.hm.prow, n, &C->tot);
-  FPL(k_set, dim3(1), dim3(1), 0, st, J.hm.prow + n, &C->tot);
-  FPL(k_prow_fill, B(n), T, 0, st, dm);
+  P.mark(6);
+  FPG("k_prow_deg", k_prow_deg, per_n, T, 0, st);
+  P.scan(FA_PCNT, FA_PROW, FN_N, FT_TOT);
+  FPG("k_set", k_mptr_end, one, dim3(64), 0, st, (int)FA_PROW, (int)FN_N, (int)FT_TOT);
+  FPG("k_prow_fill", k_prow_fill, per_n, T, 0, st);
   for (int d = Dmax; d >= 0; d--) {
     const int cnt = 1 << d;
-    const bool big = d <= Dexp;
-    const dim3 G(big ? std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * J.h->ncu)) : 1);
-    FPL(k_sym_init, dim3(1), dim3(64), 0, st, dm, d);
-    FPL(k_sym_prep, G, T, J.h->lds_bytes, st, dm, d);
-    const dim3 G1(big ? std::max(1, std::min(cnt, 4 * J.h->ncu)) : 1);
-    FPL(k_sym_elim, G, T, J.h->lds_bytes, st, dm, d, 0);
-    FPL(k_sym_elim, G1, T, J.h->lds_big, st, dm, d, 1);
-    FPL(k_sym_elim_glb, G, T, 0, st, dm, d);
-    FPL(k_sym_emit, G, T, 0, st, dm, d);
-    J.check();
+    auto G = [&, d, cnt](int i) -> long long {
+      if (d > mp[i].Dmax) return 0;
+      return d <= mp[i].Dexp
+                 ? std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * P.ncu()))
+                 : 1;
+    };
+    auto G1 = [&, d, cnt](int i) -> long long {
+      if (d > mp[i].Dmax) return 0;
+      return d <= mp[i].Dexp ? std::max(1, std::min(cnt, 4 * P.ncu())) : 1;
+    };
+    auto G0 = [&, d](int i) -> long long { return d > mp[i].Dmax ? 0 : 1; };
+    FPG("k_sym_init", k_sym_init, G0, dim3(64), 0, st, d);
+    FPG("k_sym_prep", k_sym_prep, G, T, P.h->lds_bytes, st, d);
+    FPG("k_sym_elim", k_sym_elim, G, T, P.h->lds_bytes, st, d, 0);
+    FPG("k_sym_elim", k_sym_elim, G1, T, P.h->lds_big, st, d, 1);
+    FPG("k_sym_elim_glb", k_sym_elim_glb, G, T, 0, st, d);
+    FPG("k_sym_emit", k_sym_emit, G, T, 0, st, d);
+    P.check();
   }
-  FPL(k_nnzl, dim3(std::min(J.blocks(n), 2 * J.h->ncu)), T, 0, st, dm);
+  FPG("k_nnzl", k_nnzl, [&](int i) { return std::min(P.blk(mp[i].n), 2ll * P.ncu()); }, T, 0, st);
 
   // outputs
-  J.mark(7);
-  FPL(k_expand, B(std::max<long long>(J.hm.n_dof, NNexp)), T, 0, st, dm);
-  FPL(k_finish, dim3(1), dim3(64), 0, st, dm);
-  J.mark(8);
-  J.check();
-  return J.hip_failed ? FP_ERR_HIP : FP_OK;
+  P.mark(7);
+  FPG("k_expand", k_expand,
+      [&](int i) { return P.blk(std::max<long long>(mp[i].n_dof, (2ll << mp[i].Dexp) - 1)); }, T, 0,
+      st);
+  FPG("k_finish", k_finish, one, dim3(64), 0, st);
+  P.mark(8);
+  P.check();
+  return P.hip_failed ? FP_ERR_HIP : FP_OK;
 }
 
 }  // namespace
@@ -1560,8 +1834,7 @@ fp_status fp_create(fp_handle** h) {
   int ncu = 0;
   if (hipGetDevice(&H->device) != hipSuccess ||
       hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, H->device) !=
-          hipSuccess ||
-      hipHostMalloc((void**)&H->host, 8192, hipHostMallocDefault) != hipSuccess) {
+          hipSuccess) {
     delete H;
     return FP_ERR_HIP;
   }
@@ -1577,13 +1850,14 @@ fp_status fp_create(fp_handle** h) {
   for (int i = 0; i <= FP_NSTAGE; i++)
     if (hipEventCreate(&H->ev[i]) != hipSuccess) {
       for (int j = 0; j < i; j++) (void)hipEventDestroy(H->ev[j]);
-      (void)hipHostFree(H->host);
       delete H;
       return FP_ERR_HIP;
     }
-  if (hipEventCreateWithFlags(&H->ev_bfs, hipEventDisableTiming) != hipSuccess) {
+  H->bstage = nullptr;
+  H->bstage_cap = 0;
+  H->bstage_busy = false;
+  if (hipEventCreateWithFlags(&H->ev_bstage, hipEventDisableTiming) != hipSuccess) {
     for (int j = 0; j <= FP_NSTAGE; j++) (void)hipEventDestroy(H->ev[j]);
-    (void)hipHostFree(H->host);
     delete H;
     return FP_ERR_HIP;
   }
@@ -1597,12 +1871,6 @@ fp_status fp_create(fp_handle** h) {
 
 fp_status fp_destroy(fp_handle* h) {
   if (!h) return FP_OK;
-  for (FpLane& L : h->lanes) {
-    (void)hipStreamSynchronize(L.st);
-    (void)hipStreamDestroy(L.st);
-    (void)fp_destroy(L.h);
-  }
-  h->lanes.clear();
   if (h->side) {
     for (hipStream_t s : {h->side, h->side2, h->side3}) {
       (void)hipStreamSynchronize(s);
@@ -1613,8 +1881,9 @@ fp_status fp_destroy(fp_handle* h) {
   }
   for (hipEvent_t e : h->tk_ev) (void)hipEventDestroy(e);
   for (int i = 0; i <= FP_NSTAGE; i++) (void)hipEventDestroy(h->ev[i]);
-  (void)hipEventDestroy(h->ev_bfs);
-  if (h->host) (void)hipHostFree(h->host);
+  if (h->bstage_busy) (void)hipEventSynchronize(h->ev_bstage);
+  (void)hipEventDestroy(h->ev_bstage);
+  if (h->bstage) (void)hipHostFree(h->bstage);
   delete h;
   return FP_OK;
 }
@@ -1638,67 +1907,209 @@ namespace {
 
 // fp_order and fp_order_static: `fixed` keeps every launch on `stream`, with
 // no side streams and no per-kernel timing events (nothing is created).
+// the job description of one mesh: its workspace layout, input, options,
+// outputs (host copy; the kernels read a device copy)
+// (out == NULL: sizes only)
+fp_status describe(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
+                   const fp_options* opts, char* ws, size_t ws_bytes, const fp_result* out,
+                   FpMesh* M, size_t* need) {
+  if (!h) return FP_ERR_ARG;
+  fp_status s = check_opts(opts);
+  if (s) return s;
+  if ((s = check_csr(A, opts->block_size))) return s;
+  const fp_result none{};
+  if (out) {
+    if (!out->perm || !out->iperm || !out->parent || !out->colcount || !out->nnzL)
+      return FP_ERR_ARG;
+    if ((out->node_begin || out->node_size) && out->max_nodes < 1) return FP_ERR_ARG;
+  } else {
+    out = &none;
+  }
+  Plan P;
+  if (!make_plan(A->n, opts->block_size, A->nnz, opts->patch_size, &P)) return FP_ERR_ARG;
+  if (need) *need = P.total;
+  if (ws && ws_bytes < P.total) return FP_ERR_SIZE;
+  memset(M, 0, sizeof(*M));
+  fill_mesh(P, ws, M);
+  M->rp32 = A->rowptr32;
+  M->rp64 = (const long long*)A->rowptr64;
+  M->ci_in = A->colind;
+  M->nnz_in = A->nnz;
+  M->user_gmap = user_gmap;
+  M->S = opts->patch_size;
+  M->lloyd = opts->lloyd_iters;
+  M->sched = opts->schedule;
+  M->seed = opts->seed;
+  M->validate = (opts->flags & FP_FLAG_VALIDATE) != 0;
+  M->perm = out->perm;
+  M->iperm = out->iperm;
+  M->parent = out->parent;
+  M->colcount = out->colcount;
+  M->nnzL = (long long*)out->nnzL;
+  M->node_begin_out = out->node_begin;
+  M->node_size_out = out->node_size;
+  M->gmap_out = out->gmap;
+  M->n_nodes_out = out->n_nodes;
+  M->status_out = out->status;
+  M->max_nodes_out = out->max_nodes;
+  M->lds_bytes = h->lds_bytes;
+  M->lds_big = h->lds_big;
+  M->lds_md = h->lds_md;
+  return FP_OK;
+}
+
 fp_status order_impl(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
                      const fp_options* opts, void* workspace, size_t ws_bytes, fp_result* out,
                      void* stream, bool fixed) {
   if (!h || !out || !workspace) return FP_ERR_ARG;
-  fp_status s = check_opts(opts);
-  if (s) return s;
-  if ((s = check_csr(A, opts->block_size))) return s;
-  if (!out->perm || !out->iperm || !out->parent || !out->colcount || !out->nnzL) return FP_ERR_ARG;
-  if ((out->node_begin || out->node_size) && out->max_nodes < 1) return FP_ERR_ARG;
-  Plan P;
-  if (!make_plan(A->n, opts->block_size, A->nnz, opts->patch_size, &P)) return FP_ERR_ARG;
-  if (ws_bytes < P.total) return FP_ERR_SIZE;
-  Job J;
-  J.h = h;
-  J.st = (hipStream_t)stream;
-  FpMesh& M = J.hm;
-  memset(&M, 0, sizeof(M));
+  FpMesh M;
   char* ws = (char*)workspace;
-  fill_mesh(P, ws, &M);
-  M.rp32 = A->rowptr32;
-  M.rp64 = (const long long*)A->rowptr64;
-  M.ci_in = A->colind;
-  M.nnz_in = A->nnz;
-  M.user_gmap = user_gmap;
-  M.S = opts->patch_size;
-  M.lloyd = opts->lloyd_iters;
-  M.sched = opts->schedule;
-  M.seed = opts->seed;
-  M.perm = out->perm;
-  M.iperm = out->iperm;
-  M.parent = out->parent;
-  M.colcount = out->colcount;
-  M.nnzL = (long long*)out->nnzL;
-  M.node_begin_out = out->node_begin;
-  M.node_size_out = out->node_size;
-  M.gmap_out = out->gmap;
-  M.n_nodes_out = out->n_nodes;
-  M.status_out = out->status;
-  M.max_nodes_out = out->max_nodes;
-  M.lds_bytes = h->lds_bytes;
-  M.lds_big = h->lds_big;
-  M.lds_md = h->lds_md;
-  J.ctl = M.ctl;
-  J.dm = (const FpMesh*)(ws + P.o_mesh);
-  J.fixed = fixed;
-  J.timing = !fixed && (opts->flags & FP_FLAG_TIMING) != 0;
-  J.validate = (opts->flags & FP_FLAG_VALIDATE) != 0;
+  fp_status s = describe(h, A, user_gmap, opts, ws, ws_bytes, out, &M, nullptr);
+  if (s) return s;
+  Plan PL;
+  make_plan(A->n, opts->block_size, A->nnz, opts->patch_size, &PL);
+  Pipe P;
+  P.h = h;
+  P.st = (hipStream_t)stream;
+  P.mp.push_back(mesh_plan(M, user_gmap != nullptr));
+  P.dm = (const FpMesh*)(ws + PL.o_mesh);
+  P.single = true;
+  P.fixed = fixed;
+  P.timing = !fixed && (opts->flags & FP_FLAG_TIMING) != 0;
   h->timed = false;
   h->tk_n = 0;
   h->tk_failed = false;
   // control block cleared, job description copied in as a kernel argument
   // (so no host buffer has to outlive the call)
   const int words = (int)(sizeof(FpCtl) / 4);
-  hipLaunchKernelGGL(k_fill, dim3((words + FP_WG - 1) / FP_WG), dim3(FP_WG), 0, J.st, (int*)(FpCtl*)M.ctl,
-                     words, 0);
-  hipLaunchKernelGGL(k_put_mesh, dim3(1), dim3(64), 0, J.st, M, (FpMesh*)J.dm);
+  hipLaunchKernelGGL(k_fill, dim3((words + FP_WG - 1) / FP_WG), dim3(FP_WG), 0, P.st,
+                     (int*)(FpCtl*)M.ctl, words, 0);
+  hipLaunchKernelGGL(k_put_mesh, dim3(1), dim3(64), 0, P.st, M, (FpMesh*)P.dm);
   if (hipGetLastError() != hipSuccess) return FP_ERR_HIP;
-  s = run_job(J);
-  J.join_side();  // a call that stopped early still leaves no work behind it
-  h->timed = J.timing && s == FP_OK;
+  s = run_pipe(P);
+  P.join_side();  // a call that stopped early still leaves no work behind it
+  h->timed = P.timing && s == FP_OK;
   return s;
+}
+
+// ---------------------------------------------------------------- batches
+// Workspace of a batch: the meshes' descriptions (device array), the block
+// tables of every launch, then each mesh's own workspace.
+struct BatchLayout {
+  size_t o_desc, o_tab, total;
+  std::vector<size_t> o_ws, ws;
+  std::vector<FpMesh> desc;
+  std::vector<int> tab;
+};
+
+fp_status batch_layout(fp_handle* h, int32_t n_mesh, const fp_csr* A,
+                       const int32_t* const* user_gmap, const fp_options* opts,
+                       const fp_result* out, char* base, BatchLayout* L) {
+  L->o_ws.resize(n_mesh);
+  L->ws.resize(n_mesh);
+  L->desc.resize(n_mesh);
+  size_t o = align_up(sizeof(FpMesh) * (size_t)std::max(n_mesh, 1));
+  L->o_desc = 0;
+  std::vector<size_t> need(n_mesh);
+  for (int32_t i = 0; i < n_mesh; i++) {
+    Plan PL;
+    fp_status s = check_opts(&opts[i]);
+    if (s) return s;
+    if ((s = check_csr(&A[i], opts[i].block_size))) return s;
+    if (!make_plan(A[i].n, opts[i].block_size, A[i].nnz, opts[i].patch_size, &PL))
+      return FP_ERR_ARG;
+    need[i] = align_up(PL.total);
+  }
+  // the planning pass sizes the block tables (it needs only the sizes)
+  Pipe P;
+  P.h = h;
+  P.single = false;
+  P.plan = true;
+  for (int32_t i = 0; i < n_mesh; i++) {
+    const int32_t* ug = user_gmap ? user_gmap[i] : nullptr;
+    FpMesh M;
+    fp_status s = describe(h, &A[i], ug, &opts[i], nullptr, 0, nullptr, &M, nullptr);
+    if (s) return s;
+    P.mp.push_back(mesh_plan(M, ug != nullptr));
+  }
+  (void)run_pipe(P);
+  L->tab = std::move(P.tab);
+  L->o_tab = o;
+  o = align_up(o + 4 * L->tab.size());
+  for (int32_t i = 0; i < n_mesh; i++) {
+    L->o_ws[i] = o;
+    L->ws[i] = need[i];
+    o += need[i];
+  }
+  L->total = o;
+  if (base)
+    for (int32_t i = 0; i < n_mesh; i++) {
+      const int32_t* ug = user_gmap ? user_gmap[i] : nullptr;
+      fp_status s = describe(h, &A[i], ug, &opts[i], base + L->o_ws[i], L->ws[i], &out[i],
+                             &L->desc[i], nullptr);
+      if (s) return s;
+    }
+  return FP_OK;
+}
+
+// host staging of a batch's descriptions and block tables: pinned memory of
+// the handle, reused once the previous batch's copy has completed
+fp_status stage_batch(fp_handle* h, const void* a, size_t na, const void* b, size_t nb,
+                      hipStream_t st, void* dst_a, void* dst_b) {
+  if (h->bstage_busy && hipEventSynchronize(h->ev_bstage) != hipSuccess) return FP_ERR_HIP;
+  h->bstage_busy = false;
+  const size_t need = align_up(na) + nb;
+  if (need > h->bstage_cap) {
+    if (h->bstage) (void)hipHostFree(h->bstage);
+    h->bstage = nullptr;
+    h->bstage_cap = 0;
+    if (hipHostMalloc(&h->bstage, need, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return FP_ERR_OOM;
+    }
+    h->bstage_cap = need;
+  }
+  char* p = (char*)h->bstage;
+  memcpy(p, a, na);
+  memcpy(p + align_up(na), b, nb);
+  if (hipMemcpyAsync(dst_a, p, na, hipMemcpyHostToDevice, st) != hipSuccess ||
+      (nb && hipMemcpyAsync(dst_b, p + align_up(na), nb, hipMemcpyHostToDevice, st) !=
+                 hipSuccess) ||
+      hipEventRecord(h->ev_bstage, st) != hipSuccess)
+    return FP_ERR_HIP;
+  h->bstage_busy = true;
+  return FP_OK;
+}
+
+fp_status batch_impl(fp_handle* h, int32_t n_mesh, const fp_csr* A,
+                     const int32_t* const* user_gmap, const fp_options* opts, void* workspace,
+                     size_t ws_bytes, fp_result* out, void* stream) {
+  if (!h || n_mesh < 0) return FP_ERR_ARG;
+  if (n_mesh == 0) return FP_OK;
+  if (!A || !opts || !out || !workspace) return FP_ERR_ARG;
+  BatchLayout L;
+  char* base = (char*)workspace;
+  fp_status s = batch_layout(h, n_mesh, A, user_gmap, opts, nullptr, nullptr, &L);
+  if (s) return s;
+  if (ws_bytes < L.total) return FP_ERR_SIZE;
+  if ((s = batch_layout(h, n_mesh, A, user_gmap, opts, out, base, &L))) return s;
+  Pipe P;
+  P.h = h;
+  P.st = (hipStream_t)stream;
+  P.single = false;
+  for (int32_t i = 0; i < n_mesh; i++) {
+    P.mp.push_back(mesh_plan(L.desc[i], user_gmap && user_gmap[i]));
+  }
+  P.dm = (const FpMesh*)(base + L.o_desc);
+  P.tab = L.tab;
+  P.dtab = (const int*)(base + L.o_tab);
+  if ((s = stage_batch(h, L.desc.data(), sizeof(FpMesh) * n_mesh, L.tab.data(), 4 * L.tab.size(),
+                       P.st, base + L.o_desc, base + L.o_tab)))
+    return s;
+  // every mesh's control block cleared (one block each), then the pipeline
+  hipLaunchKernelGGL(k_ctl_clear_all, dim3((unsigned)n_mesh), dim3(FP_WG), 0, P.st, P.dm);
+  if (hipGetLastError() != hipSuccess) return FP_ERR_HIP;
+  return run_pipe(P);
 }
 
 }  // namespace
@@ -1722,6 +2133,97 @@ fp_status fp_order_static(fp_handle* h, const fp_csr* A, const int32_t* user_gma
   if (s != FP_OK) return s;
   if (need > FP_STATIC_SCRATCH_BYTES) return FP_ERR_SIZE;
   return order_impl(h, A, user_gmap, opts, ws, FP_STATIC_SCRATCH_BYTES, out, stream, true);
+}
+
+fp_status fp_query_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A, const fp_options* opts,
+                         const int32_t* const* user_gmap, size_t* workspace_bytes,
+                         int32_t* max_nodes) {
+  if (!h || n_mesh < 0 || (n_mesh > 0 && (!A || !opts)) || !workspace_bytes) return FP_ERR_ARG;
+  BatchLayout L;
+  fp_status s = batch_layout(h, n_mesh, A, user_gmap, opts, nullptr, nullptr, &L);
+  if (s) return s;
+  *workspace_bytes = std::max<size_t>(L.total, 256);
+  if (max_nodes) {
+    int32_t mx = 1;
+    for (int32_t i = 0; i < n_mesh; i++) {
+      Plan PL;
+      make_plan(A[i].n, opts[i].block_size, A[i].nnz, opts[i].patch_size, &PL);
+      mx = std::max(mx, PL.NNcap);
+    }
+    *max_nodes = mx;
+  }
+  return FP_OK;
+}
+
+fp_status fp_order_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A,
+                         const int32_t* const* user_gmap, const fp_options* opts, void* workspace,
+                         size_t ws_bytes, fp_result* out, void* stream) {
+  return batch_impl(h, n_mesh, A, user_gmap, opts, workspace, ws_bytes, out, stream);
+}
+
+// the concatenated form: per-mesh views into the caller's arrays
+static fp_status concat_views(int32_t n_mesh, const int64_t* rowptr, const int32_t* colind,
+                              const int64_t* vtx_off, const int64_t* nnz_off,
+                              const fp_options* opts, std::vector<fp_csr>* A) {
+  if (n_mesh < 0 || (n_mesh > 0 && (!rowptr || !vtx_off || !nnz_off || !opts))) return FP_ERR_ARG;
+  A->resize(n_mesh);
+  for (int32_t i = 0; i < n_mesh; i++) {
+    const int64_t n = vtx_off[i + 1] - vtx_off[i], nnz = nnz_off[i + 1] - nnz_off[i];
+    if (n < 0 || nnz < 0 || (nnz > 0 && !colind)) return FP_ERR_ARG;
+    (*A)[i] = fp_csr{n, nnz, nullptr, rowptr + vtx_off[i] + i, nnz ? colind + nnz_off[i] : nullptr};
+  }
+  return FP_OK;
+}
+
+fp_status fp_query_batch_concat(fp_handle* h, int32_t n_mesh, const int64_t* rowptr,
+                                const int32_t* colind, const int64_t* vtx_off,
+                                const int64_t* nnz_off, const fp_options* opts,
+                                size_t* workspace_bytes, int64_t* node_off) {
+  std::vector<fp_csr> A;
+  fp_status s = concat_views(n_mesh, rowptr, colind, vtx_off, nnz_off, opts, &A);
+  if (s) return s;
+  if ((s = fp_query_batch(h, n_mesh, A.data(), opts, nullptr, workspace_bytes, nullptr))) return s;
+  if (node_off) {
+    node_off[0] = 0;
+    for (int32_t i = 0; i < n_mesh; i++) {
+      Plan PL;
+      make_plan(A[i].n, opts[i].block_size, A[i].nnz, opts[i].patch_size, &PL);
+      node_off[i + 1] = node_off[i] + PL.NNcap;
+    }
+  }
+  return FP_OK;
+}
+
+fp_status fp_order_batch_concat(fp_handle* h, int32_t n_mesh, const int64_t* rowptr,
+                                const int32_t* colind, const int64_t* vtx_off,
+                                const int64_t* nnz_off, const fp_options* opts, void* workspace,
+                                size_t ws_bytes, int32_t* perm, int32_t* iperm, int32_t* parent,
+                                int32_t* colcount, int64_t* nnzL, uint32_t* status,
+                                int32_t* node_begin, int32_t* node_size, const int64_t* node_off,
+                                void* stream) {
+  std::vector<fp_csr> A;
+  fp_status s = concat_views(n_mesh, rowptr, colind, vtx_off, nnz_off, opts, &A);
+  if (s) return s;
+  if (n_mesh > 0 && (!perm || !iperm || !parent || !colcount || !nnzL)) return FP_ERR_ARG;
+  if ((node_begin || node_size) && !node_off) return FP_ERR_ARG;
+  std::vector<fp_result> R(n_mesh);
+  for (int32_t i = 0; i < n_mesh; i++) {
+    const int64_t o = vtx_off[i];
+    fp_result& r = R[i];
+    r = fp_result{};
+    r.perm = perm + o;
+    r.iperm = iperm + o;
+    r.parent = parent + o;
+    r.colcount = colcount + o;
+    r.nnzL = nnzL + i;
+    r.status = status ? status + i : nullptr;
+    if (node_begin || node_size) {
+      r.node_begin = node_begin ? node_begin + node_off[i] : nullptr;
+      r.node_size = node_size ? node_size + node_off[i] : nullptr;
+      r.max_nodes = (int32_t)(node_off[i + 1] - node_off[i]);
+    }
+  }
+  return batch_impl(h, n_mesh, A.data(), nullptr, opts, workspace, ws_bytes, R.data(), stream);
 }
 
 fp_status fp_time_kernel(fp_handle* h, const char* name) {

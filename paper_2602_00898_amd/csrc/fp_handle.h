@@ -1,7 +1,6 @@
 // fp_handle.h -- the handle behind the C ABI (host side): device properties,
-// the pinned buffer scalars are read through, stage timing events, and the
-// lanes (internal streams with their own handles) of the batched and served
-// calls.
+// side streams and their events, stage and kernel timing events, and the
+// pinned staging buffer of batched calls.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -13,7 +12,7 @@
 
 struct fp_handle;
 
-// one lane: a handle of its own (pinned buffer, events) and a stream
+// one lane of the request server: a handle of its own and a stream
 struct FpLane {
   fp_handle* h;
   hipStream_t st;
@@ -25,7 +24,6 @@ struct fp_handle {
   int lds_bytes;
   int lds_big;
   int lds_md;  // the local orders' large LDS (at most FP_MD_LDS)
-  int* host;  // pinned: scalars read back between stages, and the job copy
   // second stream: local orders of the top separators, started while the
   // separator tree is still being built; events order it after the call's
   // stream and back
@@ -39,13 +37,16 @@ struct fp_handle {
   hipEvent_t ev_top[3];
   hipEvent_t ev_join;
   hipEvent_t ev[FP_NSTAGE + 1];
-  hipEvent_t ev_bfs;  // a BFS frontier size has reached the host buffer
   bool timed;  // the last call recorded stage events
-  std::mutex lanes_mu;
-  std::vector<FpLane> lanes;  // created on demand by the batched calls
   // kernel timing: events around every launch of the kernel named tk_name
   char tk_name[64];
   std::vector<hipEvent_t> tk_ev;  // pairs (begin, end)
   int tk_n;                       // launches timed in the last call
   bool tk_failed;
+  // pinned staging of a batch's mesh descriptions and block tables, and the
+  // event after their copy (the buffer is reused once that copy is done)
+  void* bstage;
+  size_t bstage_cap;
+  bool bstage_busy;
+  hipEvent_t ev_bstage;
 };

@@ -142,6 +142,7 @@ struct FpMesh {
   int lloyd;
   int sched;
   unsigned long long seed;
+  int validate;   // check that the pattern is symmetric
   // outputs (device; optional ones may be null)
   gptr<int> perm;
   gptr<int> iperm;

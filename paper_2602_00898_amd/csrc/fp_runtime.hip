@@ -1,7 +1,7 @@
-// fp_runtime.hip -- host runtime of the batched and served calls declared in
-// include/fastperm.h: lanes (an internal stream with its own handle) driven
-// by host worker threads, and a request server with a device-memory arena.
-// No kernels here: every matrix goes through fp_order on some lane.
+// fp_runtime.hip -- host runtime of the request server declared in
+// include/fastperm.h: slots (an internal stream with its own handle) driven
+// by host worker threads, and a device-memory arena.  No kernels here:
+// every request goes through fp_order on its slot's stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,7 +34,7 @@ fp_status new_lane(int device, FpLane* L) {
     fp_destroy(h);
     return FP_ERR_HIP;
   }
-  h->side_ok = false;  // lanes run side by side already
+  h->side_ok = false;  // slots run side by side already
   L->h = h;
   L->st = st;
   return FP_OK;
@@ -46,127 +46,7 @@ void free_lane(FpLane& L) {
   (void)fp_destroy(L.h);
 }
 
-fp_status ensure_lanes(fp_handle* h, int lanes) {
-  std::lock_guard<std::mutex> g(h->lanes_mu);
-  while ((int)h->lanes.size() < lanes) {
-    FpLane L;
-    fp_status s = new_lane(h->device, &L);
-    if (s != FP_OK) return s;
-    h->lanes.push_back(L);
-  }
-  return FP_OK;
-}
-
 }  // namespace
-
-extern "C" {
-
-fp_status fp_query_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A, const fp_options* opts,
-                         int32_t lanes, size_t* workspace_bytes, size_t* lane_bytes,
-                         int32_t* max_nodes) {
-  if (!h || n_mesh < 0 || (n_mesh > 0 && (!A || !opts)) || lanes < 1 || lanes > 64 ||
-      !workspace_bytes)
-    return FP_ERR_ARG;
-  size_t lb = 256;
-  int32_t mx = 1;
-  for (int32_t i = 0; i < n_mesh; i++) {
-    size_t ws = 0;
-    int32_t m = 0;
-    fp_status s = fp_query(h, &A[i], &opts[i], &ws, &m);
-    if (s != FP_OK) return s;
-    lb = std::max(lb, align256(ws));
-    mx = std::max(mx, m);
-  }
-  const int used = std::max(1, std::min(lanes, n_mesh));
-  *workspace_bytes = lb * (size_t)used;
-  if (lane_bytes) *lane_bytes = lb;
-  if (max_nodes) *max_nodes = mx;
-  return FP_OK;
-}
-
-fp_status fp_order_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A,
-                         const int32_t* const* user_gmap, const fp_options* opts, void* workspace,
-                         size_t ws_bytes, fp_result* out, int32_t lanes, void* stream) {
-  if (!h || n_mesh < 0 || lanes < 1 || lanes > 64) return FP_ERR_ARG;
-  if (n_mesh == 0) return FP_OK;
-  if (!A || !opts || !out || !workspace) return FP_ERR_ARG;
-  size_t need = 0, lb = 0;
-  fp_status s = fp_query_batch(h, n_mesh, A, opts, lanes, &need, &lb, nullptr);
-  if (s != FP_OK) return s;
-  if (ws_bytes < need) return FP_ERR_SIZE;
-  const int used = std::max(1, std::min(lanes, (int)n_mesh));
-  if ((s = ensure_lanes(h, used)) != FP_OK) return s;
-  // Matrices go to lanes before anything is queued: largest first, each to
-  // the lane with the least work so far (vertices, a proxy for time), so the
-  // lanes finish together.  Each lane's host thread then queues its
-  // matrices back to back on the lane's stream; nothing waits for the
-  // device (fp_order reads nothing back), and a lane reuses its workspace
-  // slice in stream order.
-  std::vector<int32_t> order(n_mesh);
-  for (int32_t i = 0; i < n_mesh; i++) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int32_t a, int32_t b) { return A[a].n > A[b].n; });
-  std::vector<std::vector<int32_t>> plan(used);
-  {
-    std::vector<long long> load(used, 0);
-    for (int32_t i : order) {
-      const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      plan[l].push_back(i);
-      load[l] += std::max<long long>(A[i].n, 1);
-    }
-  }
-  // the lanes start after the caller's prior work
-  hipStream_t cs = (hipStream_t)stream;
-  hipEvent_t start;
-  if (hipEventCreateWithFlags(&start, hipEventDisableTiming) != hipSuccess) return FP_ERR_HIP;
-  bool hip_ok = hipEventRecord(start, cs) == hipSuccess;
-  for (int l = 0; l < used && hip_ok; l++)
-    hip_ok = hipStreamWaitEvent(h->lanes[l].st, start, 0) == hipSuccess;
-  std::atomic<int> first_err((int)FP_OK);
-  auto worker = [&](int l) {
-    FpLane& L = h->lanes[l];
-    if (hipSetDevice(h->device) != hipSuccess) {
-      int ok = FP_OK;
-      first_err.compare_exchange_strong(ok, (int)FP_ERR_HIP);
-      return;
-    }
-    char* ws = (char*)workspace + (size_t)l * lb;
-    for (int32_t i : plan[l]) {
-      const int32_t* ug = user_gmap ? user_gmap[i] : nullptr;
-      const fp_status r = fp_order(L.h, &A[i], ug, &opts[i], ws, lb, &out[i], L.st);
-      if (r != FP_OK) {
-        int ok = FP_OK;
-        first_err.compare_exchange_strong(ok, (int)r);
-      }
-    }
-  };
-  if (hip_ok) {
-    if (used == 1) {
-      worker(0);
-    } else {
-      std::vector<std::thread> th;
-      th.reserve(used);
-      for (int l = 0; l < used; l++) th.emplace_back(worker, l);
-      for (auto& t : th) t.join();
-    }
-  }
-  // the caller's stream waits for every lane
-  for (int l = 0; l < used && hip_ok; l++) {
-    hipEvent_t done;
-    if (hipEventCreateWithFlags(&done, hipEventDisableTiming) != hipSuccess) {
-      hip_ok = false;
-      break;
-    }
-    hip_ok = hipEventRecord(done, h->lanes[l].st) == hipSuccess &&
-             hipStreamWaitEvent(cs, done, 0) == hipSuccess;
-    (void)hipEventDestroy(done);
-  }
-  (void)hipEventDestroy(start);
-  if (!hip_ok) return FP_ERR_HIP;
-  return (fp_status)first_err.load();
-}
-
-}  // extern "C"
 
 // ===========================================================================
 // request server

@@ -96,12 +96,16 @@ def lib():
         L.fp_stage_times.argtypes = [vp, C.POINTER(C.c_float), C.c_int32]
         L.fp_time_kernel.argtypes = [vp, C.c_char_p]
         L.fp_kernel_time.argtypes = [vp, C.POINTER(C.c_float), C.POINTER(C.c_int32)]
-        L.fp_query_batch.argtypes = [vp, C.c_int32, C.POINTER(Csr), C.POINTER(Options), C.c_int32,
-                                     C.POINTER(C.c_size_t), C.POINTER(C.c_size_t),
-                                     C.POINTER(C.c_int32)]
+        L.fp_query_batch.argtypes = [vp, C.c_int32, C.POINTER(Csr), C.POINTER(Options),
+                                     C.POINTER(vp), C.POINTER(C.c_size_t), C.POINTER(C.c_int32)]
         L.fp_order_batch.argtypes = [vp, C.c_int32, C.POINTER(Csr), C.POINTER(vp),
-                                     C.POINTER(Options), vp, C.c_size_t, C.POINTER(Result),
-                                     C.c_int32, vp]
+                                     C.POINTER(Options), vp, C.c_size_t, C.POINTER(Result), vp]
+        i64p = C.POINTER(C.c_int64)
+        L.fp_query_batch_concat.argtypes = [vp, C.c_int32, vp, vp, i64p, i64p, C.POINTER(Options),
+                                            C.POINTER(C.c_size_t), i64p]
+        L.fp_order_batch_concat.argtypes = [vp, C.c_int32, vp, vp, i64p, i64p, C.POINTER(Options),
+                                            vp, C.c_size_t, vp, vp, vp, vp, vp, vp, vp, vp, i64p,
+                                            vp]
         L.fp_server_create.argtypes = [vp, C.c_size_t, C.c_int32, C.POINTER(vp)]
         L.fp_server_submit.argtypes = [vp, C.POINTER(HostCsr), C.POINTER(Options),
                                        C.POINTER(C.c_uint64)]
@@ -313,7 +317,7 @@ def _result(out):
                   int(out["node_begin"].numel()))
 
 
-def order_batch(meshes, *, lanes=8, handle=None, stream=None, check=True):
+def order_batch(meshes, *, handle=None, stream=None, check=True):
     """Order many matrices in one call (fp_order_batch).  `meshes` is a list
     of dicts with device tensors rowptr, colind, the size n and optional
     patch_size, seed, schedule, block_size, lloyd_iters, user_gmap.  Returns
@@ -335,16 +339,15 @@ def order_batch(meshes, *, lanes=8, handle=None, stream=None, check=True):
         ug = m.get("user_gmap")
         G[i] = None if ug is None else ug.data_ptr()
         keep.append(ug)
-    ws, lane_bytes, mx = C.c_size_t(), C.c_size_t(), C.c_int32()
-    _check(L.fp_query_batch(handle.h, k, A, O, lanes, C.byref(ws), C.byref(lane_bytes),
-                            C.byref(mx)), "fp_query_batch")
+    ws, mx = C.c_size_t(), C.c_int32()
+    _check(L.fp_query_batch(handle.h, k, A, O, G, C.byref(ws), C.byref(mx)), "fp_query_batch")
     dev = meshes[0]["colind"].device
     for i, m in enumerate(meshes):
         outs.append(_alloc_out(m["n"], mx.value, m.get("block_size", 1), dev))
         R[i] = _result(outs[i])
     wbuf = handle.workspace(ws.value, dev)
     s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-    rc = L.fp_order_batch(handle.h, k, A, G, O, _ptr(wbuf), ws.value, R, lanes, C.c_void_p(s))
+    rc = L.fp_order_batch(handle.h, k, A, G, O, _ptr(wbuf), ws.value, R, C.c_void_p(s))
     if rc != 0:
         raise FpError(rc, "fp_order_batch")
     if check:
@@ -354,6 +357,62 @@ def order_batch(meshes, *, lanes=8, handle=None, stream=None, check=True):
         if bad:
             raise FpError(9, f"fp_order_batch: matrix {bad[0]} device bits 0x{int(st[bad[0]]):x}")
     return outs
+
+
+def order_batch_concat(rowptr, colind, vtx_off, nnz_off, opts_list, *, handle=None, stream=None,
+                       check=True):
+    """fp_order_batch_concat: concatenated per-mesh CSR (rowptr int64 device
+    tensor holding each mesh's n_i+1 local row pointers, colind int32 device
+    tensor with local column indices; vtx_off / nnz_off host sequences of
+    n_mesh+1 offsets).  opts_list: one dict of options per mesh.  Returns a
+    dict of concatenated device tensors (perm, iperm, parent, colcount at the
+    vertex offsets; nnzL and status per mesh; node_begin/node_size at
+    node_off) and node_off itself."""
+    import numpy as np
+    L = lib()
+    k = len(opts_list)
+    handle = handle or Handle()
+    O = (Options * k)()
+    for i, o in enumerate(opts_list):
+        O[i] = options(o.get("patch_size", 512), o.get("schedule", SCHED_LEVEL),
+                       o.get("block_size", 1), o.get("lloyd_iters", 1), o.get("seed", 0))
+    vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
+    no = np.ascontiguousarray(nnz_off, dtype=np.int64)
+    node_off = np.zeros(k + 1, dtype=np.int64)
+    i64p = C.POINTER(C.c_int64)
+    ws = C.c_size_t()
+    _check(L.fp_query_batch_concat(handle.h, k, _ptr(rowptr), _ptr(colind),
+                                   vo.ctypes.data_as(i64p), no.ctypes.data_as(i64p), O,
+                                   C.byref(ws), node_off.ctypes.data_as(i64p)),
+           "fp_query_batch_concat")
+    dev = rowptr.device
+    ntot = int(vo[-1])
+    i32 = dict(dtype=torch.int32, device=dev)
+    out = dict(perm=torch.empty(ntot, **i32), iperm=torch.empty(ntot, **i32),
+               parent=torch.empty(ntot, **i32), colcount=torch.empty(ntot, **i32),
+               nnzL=torch.zeros(k, dtype=torch.int64, device=dev), status=torch.zeros(k, **i32),
+               node_begin=torch.empty(int(node_off[-1]), **i32),
+               node_size=torch.empty(int(node_off[-1]), **i32))
+    wbuf = handle.workspace(ws.value, dev)
+    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    rc = L.fp_order_batch_concat(handle.h, k, _ptr(rowptr), _ptr(colind),
+                                 vo.ctypes.data_as(i64p), no.ctypes.data_as(i64p), O, _ptr(wbuf),
+                                 ws.value, _ptr(out["perm"]), _ptr(out["iperm"]),
+                                 _ptr(out["parent"]), _ptr(out["colcount"]), _ptr(out["nnzL"]),
+                                 _ptr(out["status"]), _ptr(out["node_begin"]),
+                                 _ptr(out["node_size"]), node_off.ctypes.data_as(i64p),
+                                 C.c_void_p(s))
+    if rc != 0:
+        raise FpError(rc, "fp_order_batch_concat")
+    out["node_off"] = node_off
+    if check:
+        torch.cuda.synchronize(dev)
+        st = out["status"].cpu()
+        bad = torch.nonzero(st).flatten().tolist()
+        if bad:
+            raise FpError(9, f"fp_order_batch_concat: matrix {bad[0]} device bits "
+                             f"0x{int(st[bad[0]]):x}")
+    return out
 
 
 class Server:

@@ -38,10 +38,15 @@ def test_every_declared_symbol_is_exported(lib):
 
 def test_host_only_calls(lib):
     lib.fp_version.restype = ctypes.c_int
-    assert lib.fp_version() == 1
+    assert lib.fp_version() == 2
     lib.fp_status_str.restype = ctypes.c_char_p
     assert lib.fp_status_str(0) == b"ok"
     from paper_2602_00898_amd.fastperm import Options
     o = Options()
     lib.fp_options_default(ctypes.byref(o))
     assert o.patch_size == 512 and o.nd_level == -1 and o.block_size == 1 and o.lloyd_iters == 1
+    assert o.flags == 2  # FP_FLAG_VALIDATE
+    # sizing calls need no device memory: the supernode workspace grows with n
+    ws = ctypes.c_size_t()
+    assert lib.fp_supernodes_query(ctypes.c_int64(1000), ctypes.byref(ws)) == 0 and ws.value > 0
+    assert lib.fp_supernodes_query(ctypes.c_int64(-1), ctypes.byref(ws)) == 1

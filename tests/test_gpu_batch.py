@@ -1,7 +1,8 @@
 """GPU: batched and served orderings through the C ABI.
 
-A matrix ordered inside a batch, or by the server next to other requests,
-must give exactly the result it gets alone, which is the oracle's.
+A matrix ordered inside a batch (every launch covering all matrices), or by
+the server next to other requests, must give exactly the result it gets
+alone, which is the oracle's.
 """
 
 import numpy as np
@@ -35,14 +36,15 @@ def _device_meshes(cases):
                  n=A.n, patch_size=S, seed=s) for A, S, s in cases]
 
 
-@pytest.mark.parametrize("lanes", [1, 3, 8])
-def test_batch_matches_oracle_and_single(lanes):
+@pytest.mark.parametrize("pick", ["all", "reversed", "three"])
+def test_batch_matches_oracle_and_single(pick):
     import torch
 
     from paper_2602_00898_amd import fastperm as fpm
-    cases = [(mesh(H, W, t, s, f), S, s) for H, W, t, s, f, S in MIX]
-    say(f"[batch] {len(cases)} meshes, lanes={lanes}")
-    outs = fpm.order_batch(_device_meshes(cases), lanes=lanes)
+    mix = {"all": MIX, "reversed": MIX[::-1], "three": MIX[2:5]}[pick]
+    cases = [(mesh(H, W, t, s, f), S, s) for H, W, t, s, f, S in mix]
+    say(f"[batch] {len(cases)} meshes ({pick})")
+    outs = fpm.order_batch(_device_meshes(cases))
     torch.cuda.synchronize()
     for (A, S, s), out in zip(cases, outs):
         g = _to_dict(out, A)
@@ -68,12 +70,41 @@ def test_batch_blocks_user_groups_and_options():
              n=Q.n, patch_size=30, seed=13, schedule=1, lloyd_iters=2),
     ]
     say("[batch] block / user groups / post order")
-    outs = fpm.order_batch(meshes, lanes=3)
+    outs = fpm.order_batch(meshes)
     torch.cuda.synchronize()
     compare(_to_dict(outs[0], B, 3), cpu_order(B, patch_size=40, seed=11, block_size=3), "block3")
     compare(_to_dict(outs[1], P), cpu_order(P, patch_size=64, user_gmap=g), "user groups")
     compare(_to_dict(outs[2], Q), cpu_order(Q, patch_size=30, seed=13, schedule=1, lloyd_iters=2),
             "post order, lloyd 2")
+
+
+def test_batch_concatenated_arrays():
+    """fp_order_batch_concat over one concatenated CSR (local indices per
+    mesh) gives each mesh its own fp_order result, in the concatenated
+    outputs."""
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+    cases = [(mesh(H, W, t, s, f), S, s) for H, W, t, s, f, S in MIX]
+    rp = np.concatenate([A.rowptr.astype(np.int64) for A, _, _ in cases])
+    ci = np.concatenate([A.colind for A, _, _ in cases]).astype(np.int32)
+    vo = np.concatenate([[0], np.cumsum([A.n for A, _, _ in cases])])
+    no = np.concatenate([[0], np.cumsum([A.nnz for A, _, _ in cases])])
+    dev = torch.device("cuda:0")
+    say(f"[batch] concatenated: {len(cases)} meshes, {vo[-1]} vertices")
+    out = fpm.order_batch_concat(torch.from_numpy(rp).to(dev), torch.from_numpy(ci).to(dev), vo, no,
+                                 [dict(patch_size=S, seed=s) for _, S, s in cases])
+    r = {k: v.cpu().numpy() for k, v in out.items() if torch.is_tensor(v)}
+    for i, (A, S, s) in enumerate(cases):
+        c = cpu_order(A, patch_size=S, seed=s)
+        sl = slice(vo[i], vo[i + 1])
+        for k in ("perm", "iperm", "parent", "colcount"):
+            assert np.array_equal(r[k][sl], c[k]), f"concat mesh {i}: {k}"
+        assert int(r["nnzL"][i]) == c["nnzL"] and int(r["status"][i]) == 0
+        nn = len(c["node_begin"])
+        no_i = int(out["node_off"][i])
+        assert np.array_equal(r["node_begin"][no_i:no_i + nn], c["node_begin"])
+        assert np.array_equal(r["node_size"][no_i:no_i + nn], c["node_size"])
 
 
 def test_server_same_alone_and_in_mix():

@@ -46,7 +46,7 @@ def test_batch_workload_256_meshes_match_oracle():
     dev = torch.device("cuda:0")
     dm = [dict(rowptr=torch.from_numpy(A.rowptr).to(dev), colind=torch.from_numpy(A.colind).to(dev),
                n=A.n, patch_size=S, seed=s) for A, (S, s) in zip(meshes, cfg)]
-    outs = fpm.order_batch(dm, lanes=16)
+    outs = fpm.order_batch(dm)
     torch.cuda.synchronize()
     say("[batch] GPU done; oracle")
     with ThreadPoolExecutor(THREADS) as ex:
