@@ -146,6 +146,25 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
                    const fp_options* opts, void* workspace, size_t ws_bytes,
                    fp_result* out, void* stream);
 
+/* Order a matrix again after its pattern changed, on the same mesh
+ * vertices, keeping an earlier call's patches: the reuse of the nested-
+ * dissection hierarchy across pattern changes that the paper builds on
+ * (Sec. 2, related work: reordering when the sparsity pattern changes over
+ * time).  The result is exactly fp_order's with user_gmap = prev_gmap (the
+ * gmap output of the earlier call); separator-tree nodes whose vertex set and
+ * induced edges are unchanged take their local order (Sec. 4.3 Step 4) from
+ * the earlier call instead of recomputing it, which is exact because that
+ * order depends on nothing else.  prev_workspace is the earlier call's
+ * workspace, unchanged since that call finished on the device (and not the
+ * same buffer as `workspace`); a call whose sizes differ (another vertex
+ * count, block size or tree size) reuses nothing and is still correct.
+ * reused_vertices (device, 1 entry, nullable) receives the number of
+ * vertices whose local order was reused.  Asynchronous like fp_order. */
+fp_status fp_order_update(fp_handle* h, const fp_csr* A, const int32_t* prev_gmap,
+                          const void* prev_workspace, const fp_options* opts, void* workspace,
+                          size_t ws_bytes, fp_result* out, int32_t* reused_vertices,
+                          void* stream);
+
 /* fp_order for callers that cannot allocate device memory (code that must
  * not call hipMalloc: tight serving loops, harnesses that forbid it).  The
  * workspace is a static device array of the library, 256 MiB per device,

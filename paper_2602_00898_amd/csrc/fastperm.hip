@@ -965,6 +965,58 @@ __global__ void k_scatter(FpGrid fp_g) {
 }
 
 // ==========================================================================
+// Reuse of an earlier call's local orders (update calls, patches kept): the
+// local order of a node depends only on its vertex set and the edges among
+// them (minimum degree with ties to the lowest local index, the rank of the
+// vertex id), so a node whose vertex set and induced edges are both
+// unchanged takes the earlier order as it is.  One wave per node; flags in
+// segS (free once the tree is built) tell the task lists to skip it.
+// ==========================================================================
+__global__ void k_reuse(FpGrid fp_g) {
+  MESH;
+  const FpMesh* O = M.prev;
+  if (!O) return;
+  const int nn = C->nn;
+  const bool same = O->n == M.n && O->b == M.b && O->ctl->nn == nn && O->ctl->err == 0u;
+  for (int t = vw(fp_s); t < nn; t += vn(fp_s)) {
+    const int m = uni((int)M.nsize[t]);
+    bool ok = same && m > 0 && O->nsize[t] == m;
+    const int pos = uni((int)M.nbegin[t]);
+    // the same vertices: every member was in node t before, and as many
+    for (int k = lane_id(); ok && k < m; k += 64) ok = O->node_of[M.gbuf[pos + k]] == t;
+    ok = ballot64(!ok) == 0;
+    // the same induced edges: each member's row, restricted to the node, is
+    // the same sorted list in both graphs
+    for (int k = lane_id(); ok && k < m; k += 64) {
+      const int v = M.gbuf[pos + k];
+      int a = M.grp[v], ae = M.grp[v + 1], b = O->grp[v], be = O->grp[v + 1];
+      while (ok) {
+        while (a < ae && M.node_of[M.gci[a]] != t) a++;
+        while (b < be && O->node_of[O->gci[b]] != t) b++;
+        if (a == ae || b == be) {
+          ok = a == ae && b == be;
+          break;
+        }
+        ok = M.gci[a] == O->gci[b];
+        a++;
+        b++;
+      }
+    }
+    ok = ballot64(!ok) == 0;
+    if (ok) {
+      const int opos = O->nbegin[t];
+      for (int k = lane_id(); k < m; k += 64) {
+        const int v = O->vperm[opos + k];
+        M.vperm[pos + k] = v;
+        M.viperm[v] = pos + k;
+      }
+      if (lane_id() == 0) atomicAdd(&C->vreuse, m);
+    }
+    if (lane_id() == 0) M.segS[t] = ok ? 1 : 0;
+  }
+}
+
+// ==========================================================================
 // local orders (Sec. 4.3 Step 4): one wave per node, LDS slice per wave
 // ==========================================================================
 // Task lists of the local orders, one per size class, largest nodes first
@@ -981,6 +1033,7 @@ __global__ void __launch_bounds__(1024) k_md_tasks(FpGrid fp_g, int ntop) {
   auto key = [&](int x) -> int {  // class * buckets + bucket, or -1
     const int m = M.nsize[x];
     if (m == 0 || (x < ntop && C->tearly[x])) return -1;  // top separators ordered already
+    if (M.prev && M.segS[x]) return -1;                  // order reused
     const int c = md_class(m, M.lds_bytes, M.lds_md);
     return c * FP_TASK_BUCKETS + (FP_TASK_BUCKETS - 1) - min(m >> 4, FP_TASK_BUCKETS - 1);
   };
@@ -1214,6 +1267,7 @@ __global__ void k_finish(FpGrid fp_g) {
   *M.nnzL = (long long)M.b * M.b * C->nnzL - (long long)M.n * M.b * (M.b - 1) / 2;
   if (M.n_nodes_out) *M.n_nodes_out = nn;
   if (M.status_out) *M.status_out = C->err;
+  if (M.reused_out) *M.reused_out = C->vreuse;
 }
 
 // ==========================================================================
@@ -1349,6 +1403,7 @@ struct Pipe {
   size_t tpos = 0;
   bool hip_failed = false;
   bool timing = false;
+  bool update = false;     // an update call: local orders may be reused
   bool fixed = false;      // no side streams and no per-kernel events (static-scratch calls)
   bool side_open = false;  // work on the side stream not yet joined
   bool side2_open = false; // same for the second side stream
@@ -1612,8 +1667,8 @@ fp_status run_pipe(Pipe& P) {
   FPG("k_sep_init", k_sep_init, per_n, T, 0, st);
   // top separators ordered early on the side streams (one mesh, level
   // order: there their ranges depend on the top levels alone)
-  const int TL = P.single && mp[0].n > 0 && mp[0].sched == FP_SCHED_LEVEL && P.h->side_ok &&
-                         !P.fixed && ensure_side(P.h)
+  const int TL = P.single && !P.update && mp[0].n > 0 && mp[0].sched == FP_SCHED_LEVEL &&
+                         P.h->side_ok && !P.fixed && ensure_side(P.h)
                      ? std::min(FP_TOP_LEVELS, mp[0].Dmax)
                      : 0;
   auto lvl = [&](int d, long long items) {  // a tree level of mesh i: small past Dexp
@@ -1686,6 +1741,7 @@ fp_status run_pipe(Pipe& P) {
   FPG("k_scatter", k_scatter, per_n, T, 0, st);
   const int ntop = (1 << TL) - 1;
   if (ntop) FPG("k_top_check", k_top_check, one, dim3(64), 0, st, ntop);
+  if (P.update) FPG("k_reuse", k_reuse, [&](int i) { return P.blk((2ll << mp[i].Dexp) - 1, 64); }, T, 0, st);
   P.check();
 
   // local orders
@@ -1960,7 +2016,8 @@ fp_status describe(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
 
 fp_status order_impl(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
                      const fp_options* opts, void* workspace, size_t ws_bytes, fp_result* out,
-                     void* stream, bool fixed) {
+                     void* stream, bool fixed, const void* prev_ws = nullptr,
+                     int32_t* reused = nullptr) {
   if (!h || !out || !workspace) return FP_ERR_ARG;
   FpMesh M;
   char* ws = (char*)workspace;
@@ -1968,6 +2025,10 @@ fp_status order_impl(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   if (s) return s;
   Plan PL;
   make_plan(A->n, opts->block_size, A->nnz, opts->patch_size, &PL);
+  // the earlier call's description sits at the same offset of its workspace
+  // (the control block, then the description, lead every layout)
+  M.prev = prev_ws ? (const FpMesh*)((const char*)prev_ws + PL.o_mesh) : nullptr;
+  M.reused_out = reused;
   Pipe P;
   P.h = h;
   P.st = (hipStream_t)stream;
@@ -1975,6 +2036,7 @@ fp_status order_impl(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   P.dm = (const FpMesh*)(ws + PL.o_mesh);
   P.single = true;
   P.fixed = fixed;
+  P.update = prev_ws != nullptr;
   P.timing = !fixed && (opts->flags & FP_FLAG_TIMING) != 0;
   h->timed = false;
   h->tk_n = 0;
@@ -2120,6 +2182,16 @@ fp_status fp_order(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
                    const fp_options* opts, void* workspace, size_t ws_bytes, fp_result* out,
                    void* stream) {
   return order_impl(h, A, user_gmap, opts, workspace, ws_bytes, out, stream, false);
+}
+
+fp_status fp_order_update(fp_handle* h, const fp_csr* A, const int32_t* prev_gmap,
+                          const void* prev_workspace, const fp_options* opts, void* workspace,
+                          size_t ws_bytes, fp_result* out, int32_t* reused_vertices,
+                          void* stream) {
+  if (!h || !prev_gmap || !prev_workspace || !workspace || prev_workspace == workspace)
+    return FP_ERR_ARG;
+  return order_impl(h, A, prev_gmap, opts, workspace, ws_bytes, out, stream, false,
+                    prev_workspace, reused_vertices);
 }
 
 fp_status fp_order_static(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,

@@ -104,6 +104,7 @@ struct FpCtl {
   int nroot;             // orphan components
   int nlong;             // vertex rows of more than FP_ROW_SHORT input entries
   int ccn;               // vertices the orphan-component pass covers (n, or 0 without orphans)
+  int vreuse;            // vertices whose local order came from the previous call
   int ccchg[8];          // orphan components: 1 if round r changed a label
   int chg;               // fixed-point iteration flag
   int tot;               // scan total
@@ -154,6 +155,7 @@ struct FpMesh {
   gptr<int> gmap_out;
   gptr<int> n_nodes_out;
   gptr<unsigned> status_out;
+  gptr<int> reused_out;  // vertices whose local order was reused (update calls)
   int max_nodes_out;
   // sizes
   int n;          // vertices
@@ -210,5 +212,8 @@ struct FpMesh {
   gptr<int> prow;      // n+1: the permuted pattern by position: row pointers
   gptr<int> pent;      // Ecap: its entries, as positions
   gptr<unsigned> pool; // fallback pool (32-bit words)
+  // update calls: the description of the earlier call whose local orders
+  // may be reused (its workspace, unchanged since), else null
+  const FpMesh* prev;
   unsigned long long pool_words;
 };

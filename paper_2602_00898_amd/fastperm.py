@@ -87,6 +87,8 @@ def lib():
                                C.POINTER(Result), vp]
         L.fp_order_static.argtypes = [vp, C.POINTER(Csr), vp, C.POINTER(Options),
                                       C.POINTER(Result), vp]
+        L.fp_order_update.argtypes = [vp, C.POINTER(Csr), vp, vp, C.POINTER(Options), vp,
+                                      C.c_size_t, C.POINTER(Result), vp, vp]
         L.fp_last_error.argtypes = [vp, vp, vp]
         L.fp_error_detail.argtypes = [vp, vp, vp, C.POINTER(C.c_uint32), C.POINTER(C.c_int32),
                                       C.POINTER(C.c_int32)]
@@ -254,6 +256,39 @@ def supernodes(parent, colcount, *, handle=None, stream=None, check=True):
         torch.cuda.synchronize(dev)
         if int(out["status"].item()):
             raise FpError(9, "fp_supernodes: parent array is not an elimination tree")
+    return out
+
+
+def order_update(rowptr, colind, n, prev_gmap, prev_workspace, *, patch_size=512,
+                 schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, seed=0, handle=None, out=None,
+                 stream=None, check=True):
+    """fp_order_update: order a changed pattern on the same vertices keeping
+    an earlier call's patches (prev_gmap, its gmap output) and reusing the
+    local orders of unchanged nodes from its workspace (prev_workspace, a
+    device tensor that must not be the workspace of `handle`).  Returns the
+    output dict plus 'reused' (vertices whose local order was reused)."""
+    dev = colind.device if colind.numel() else rowptr.device
+    handle = handle or Handle()
+    opts = options(patch_size, schedule, block_size, lloyd_iters, seed)
+    A = make_csr(n, rowptr, colind)
+    ws_bytes, max_nodes = query(handle, n, rowptr, colind, opts)
+    ws = handle.workspace(ws_bytes, dev)
+    if ws.data_ptr() == prev_workspace.data_ptr():
+        raise ValueError("order_update needs a workspace other than the earlier call's")
+    if out is None:
+        out = _alloc_out(n, max_nodes, block_size, dev)
+    out["reused"] = torch.zeros(1, dtype=torch.int32, device=dev)
+    R = _result(out)
+    s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
+    rc = lib().fp_order_update(handle.h, C.byref(A), _ptr(prev_gmap), _ptr(prev_workspace),
+                               C.byref(opts), _ptr(ws), ws_bytes, C.byref(R), _ptr(out["reused"]),
+                               C.c_void_p(s))
+    if rc != 0:
+        raise FpError(rc, "fp_order_update")
+    if check:
+        rc = lib().fp_last_error(handle.h, _ptr(ws), C.c_void_p(s))
+        if rc != 0:
+            raise FpError(rc, "device", error_detail(handle, ws, s))
     return out
 
 
