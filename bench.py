@@ -6,23 +6,27 @@ counts) of a 1024x1024 torus triangle mesh (1,048,576 vertices, seeded
 diagonals, scalar int32 CSR pattern + diagonal) with target patch size 512,
 inputs resident in device memory before the timed region.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
-                    [--no-batch] [--no-serve] [--no-block] [--serve-requests R] [--slots L]
-                    [--copy-probe-mib M]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-batch]
+                    [--no-serve] [--no-update] [--no-block] [--serve-requests R]
+                    [--slots L] [--copy-probe-mib M]
     python bench.py --traffic-from FETCH.csv WRITE.csv [--copy-probe-mib M]
 
 Prints one JSON line.  `value` is mesh vertices ordered per second (whole
-job), `roofline` rates the dominant kernel (its launches timed with HIP
-events on the call's stream during the timed steps) against MI355X's HBM
-peak with algorithmic bytes; its `traffic` is the HBM bytes per launch that
-two rocprofv3 counter runs measured (FETCH_SIZE, WRITE_SIZE, each scaled by
-what the counter reads for a plain device copy of known size), kept in
+job).  `roofline` rates the dominant kernel (the largest event-timed total
+per ordering; its launches timed with HIP events on their own streams during
+the timed steps) against MI355X's HBM peak with the algorithmic bytes of the
+path's byte budget; its `traffic` is the HBM bytes per launch that two
+rocprofv3 counter runs measured (FETCH_SIZE, WRITE_SIZE, each scaled by what
+the counter reads for a plain device copy of known size), kept in
 profiles/traffic.json with a digest of the kernel sources and reported only
-while the sources still match.  `cpu_baseline` times the serial CPU oracle on
-one core over a bounded sample of the same workload.  `batch` compares
-ordering 256 meshes of uneven size one at a time with the batched call;
-`serving` drives the request server with Poisson arrivals and reports
-p50/p99 latency.
+while the sources still match.  `path_roofline` rates the whole path the
+same way, `kernels` every timed kernel.  `cpu_baseline` times the serial CPU
+oracle on one host core over a bounded sample (and the 256-mesh batch with
+one process per core).  `batch` compares ordering 256 meshes of uneven size
+one at a time with the batched call, `serving` drives the request server
+with Poisson arrivals and reports p50/p99 latency, `update` re-orders the
+benchmark mesh after a local pattern change, `block` orders the 2048x2048
+torus in 3x3 blocks.
 """
 
 from __future__ import annotations
@@ -338,6 +342,50 @@ def run_batch(args, meshes):
             "identical_to_plain": bool(same)}
 
 
+# ------------------------------------------------------------------ update
+def run_update(args, A):
+    """Pattern change on the benchmark mesh: 16 quads in one corner get their
+    other diagonal; the new pattern is ordered again with the earlier call's
+    patches kept (fp_order_update), reusing the local orders of unchanged
+    nodes, against a full ordering of the new pattern with the same patches."""
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+    from paper_2602_00898_amd import meshgen as mg
+
+    dev = torch.device("cuda:0")
+    quads = [(100 + i, 100 + j) for i in range(4) for j in range(4)]
+    B = mg.swap_quad_diagonals(A, W, quads)
+    rp, ci = torch.from_numpy(A.rowptr).to(dev), torch.from_numpy(A.colind).to(dev)
+    rp2, ci2 = torch.from_numpy(B.rowptr).to(dev), torch.from_numpy(B.colind).to(dev)
+    h0, h1, h2 = fpm.Handle(), fpm.Handle(), fpm.Handle()
+    first = fpm.order(rp, ci, A.n, patch_size=PATCH, seed=MESH_SEED, handle=h0)
+    gmap = first["gmap"][:A.n].clone()
+    steps = max(1, min(args.steps, 10))
+
+    def timed(fn):
+        for _ in range(2):
+            out = fn()
+        torch.cuda.synchronize(dev)
+        t = time.perf_counter()
+        for _ in range(steps):
+            out = fn()
+        torch.cuda.synchronize(dev)
+        return out, (time.perf_counter() - t) * 1e3 / steps
+
+    upd, ms_u = timed(lambda: fpm.order_update(rp2, ci2, B.n, gmap, h0._ws, patch_size=PATCH,
+                                               seed=MESH_SEED, handle=h1))
+    full, ms_f = timed(lambda: fpm.order(rp2, ci2, B.n, patch_size=PATCH, user_gmap=gmap,
+                                         handle=h2))
+    same = all(torch.equal(upd[k], full[k]) for k in ("perm", "iperm", "parent", "colcount", "nnzL"))
+    reused = int(upd["reused"].item())
+    return {"workload": "1024x1024 torus, S=512, 16 quads in one corner flipped to the other "
+                        "diagonal, patches of the earlier ordering kept",
+            "steps": steps, "ms_update": round(ms_u, 3), "ms_full": round(ms_f, 3),
+            "speedup": round(ms_f / ms_u, 3), "reused_fraction": round(reused / A.n, 5),
+            "identical_to_full": bool(same)}
+
+
 # ------------------------------------------------------------------ block
 BLOCK_SIDE, BLOCK_SEED, BLOCK_B = 2048, 4, 3
 
@@ -500,6 +548,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-budget-gb", type=int, default=64)
     ap.add_argument("--slots", type=int, default=16, help="request-server slots")
+    ap.add_argument("--no-update", action="store_true",
+                    help="skip the pattern-change re-ordering of the benchmark mesh")
     ap.add_argument("--no-block", action="store_true",
                     help="skip the 2048x2048 torus in 3x3 blocks (12.6M DOF)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -520,6 +570,7 @@ def main():
     g = run_plain(args, A)
     batch = None if batch_meshes is None else run_batch(args, batch_meshes)
     serving = None if serve_reqs is None else run_serve(args, serve_reqs)
+    update = None if args.no_update else run_update(args, A)
     block = None if args.no_block else run_block(args)
     cpu = None if args.no_cpu else run_cpu(A, batch_meshes)
     if cpu is not None and cpu.pop("nnzL") != g["nnzL"]:
@@ -559,6 +610,7 @@ def main():
         "kernels": g["kernels"],
         "batch": batch,
         "serving": serving,
+        "update": update,
         "block": block,
         "cpu_baseline": cpu,
     }

@@ -50,14 +50,8 @@ enum {
   FP_SITE_TREE = 25,        // separator tree larger than its capacity
 };
 
-#ifndef FP_DBGP
-#define FP_DBGP(...)
-#endif
-
 // the dynamic LDS array of every kernel that uses one
-#ifndef FP_LDS_DECL
 #define FP_LDS_DECL extern __shared__ __align__(16) char fp_lds[]
-#endif
 
 // A value every lane of the wave holds alike (a node id, a size read from
 // memory at one address), moved into a scalar register.  The compiler treats

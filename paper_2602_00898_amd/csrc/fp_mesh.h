@@ -7,10 +7,7 @@
 
 #include <type_traits>
 
-#ifndef FP_GLOBAL
 #define FP_GLOBAL __attribute__((address_space(1)))
-#define FP_GLOBAL_ATOMICS 1
-#endif
 
 // A pointer into device global memory.  Element access through it compiles
 // to global (not flat) loads and stores: a flat access also counts against
@@ -50,7 +47,6 @@ struct gptr {
   }
 };
 
-#ifdef FP_GLOBAL_ATOMICS
 // device-scope relaxed atomics on global memory (the semantics of HIP's
 // atomicAdd family), taking the pointers that gptr element access yields
 template <class T>
@@ -87,7 +83,6 @@ __device__ __forceinline__ T atomicCAS(FP_GLOBAL T* p, T cmp, T v) {
                                        __HIP_MEMORY_SCOPE_AGENT);
   return cmp;
 }
-#endif
 
 // control block at the start of every mesh workspace (device memory,
 // cleared by fp_ctl_init before the pipeline starts)

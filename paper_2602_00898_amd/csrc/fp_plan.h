@@ -7,12 +7,6 @@
 
 #include "fp_mesh.h"
 
-#ifndef FP_PLAN_GAP
-#define FP_PLAN_GAP 0
-#endif
-#ifndef FP_PLAN_RECORD
-#define FP_PLAN_RECORD(off, bytes)
-#endif
 
 namespace fpplan {
 
@@ -57,8 +51,7 @@ bool make_plan(long long n_dof, int b, long long nnz, int S, Plan* P) {
   size_t o = 0;
   auto take = [&](size_t bytes) {
     size_t r = o;
-    FP_PLAN_RECORD(r, bytes);
-    o = align_up(o + bytes + FP_PLAN_GAP);
+    o = align_up(o + bytes);
     return r;
   };
   const size_t N1 = (size_t)n + 1, E = (size_t)P->Ecap, NN = (size_t)P->NNcap;

@@ -311,3 +311,38 @@ def serving_stream(seed: int, count: int, rate: float = 200.0, smin: int = 100,
         torus = bool(rng.integers(0, 2))
         out.append((t, MeshSpec(s, torus, int(seed * 7919 + i))))
     return out
+
+
+def swap_quad_diagonals(A: CSR, W: int, quads) -> CSR:
+    """The pattern of A (a grid or torus mesh of width W, vertex r*W + c)
+    with the diagonal of each quad (r, c) moved to the other diagonal: the
+    local pattern change of a remeshing step.  Indices wrap as on a torus.
+    A quad whose first diagonal (r,c)-(r+1,c+1) is present gets the second
+    one instead, and the other way round."""
+    n = A.n
+    H = n // W
+    q = np.asarray(list(quads), dtype=np.int64).reshape(-1, 2)
+    if len(q) == 0:
+        return A
+    r, c = q[:, 0], q[:, 1]
+
+    def vid(rr, cc):
+        return (rr % H) * W + (cc % W)
+
+    a, b = vid(r, c), vid(r + 1, c + 1)
+    x, y = vid(r, c + 1), vid(r + 1, c)
+    rp = A.rowptr.astype(np.int64)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    key = rows * n + A.colind.astype(np.int64)
+    has_ab = np.isin(a * n + b, key)
+    old_u, old_v = np.where(has_ab, a, x), np.where(has_ab, b, y)
+    new_u, new_v = np.where(has_ab, x, a), np.where(has_ab, y, b)
+    drop = np.concatenate([old_u * n + old_v, old_v * n + old_u])
+    key = key[~np.isin(key, drop)]
+    key = np.unique(np.concatenate([key, new_u * n + new_v, new_v * n + new_u]))
+    rr, cc = key // n, key % n
+    rowptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rr, minlength=n), out=rowptr[1:])
+    if A.rowptr.dtype == np.int32:
+        rowptr = rowptr.astype(np.int32)
+    return CSR(n, rowptr, cc.astype(np.int32))

@@ -24,8 +24,8 @@ def check(A, label, **kw):
 
 
 @pytest.mark.skip(reason="this input faulted the GPU twice on a former single persistent-kernel "
-                  "path; kept off the GPU for the rest of this build round (that path was "
-                  "replaced; the case passes on the CPU emulator)")
+                  "path whose cause was never shown; that kernel was deleted and the input stays "
+                  "off the GPU")
 def test_tiny_planar_64x64_S64():
     """64x64 planar grid, seeded diagonals, S = 64 (the tiny configuration)."""
     check(mesh(64, 64, False, 1), "C1", patch_size=64, seed=1)
@@ -43,9 +43,9 @@ def test_small_meshes(H, W, torus, seed, flip, S):
     check(mesh(H, W, torus, seed, flip), f"{H}x{W}", patch_size=S, seed=seed)
 
 
-@pytest.mark.skip(reason="this input faulted, then hung, the GPU in a former symbolic-stage kernel; "
-                  "kept off the GPU for the rest of this build round (that kernel was replaced; "
-                  "the case passes on the CPU emulator)")
+@pytest.mark.skip(reason="this input faulted, then hung, the GPU in a former symbolic-stage kernel "
+                  "whose cause was never shown; that kernel was deleted and the input stays off "
+                  "the GPU")
 @pytest.mark.parametrize("sched", [0, 1])
 def test_schedules_48x48_S40(sched):
     check(mesh(48, 48, True, 9, 0.05), f"sched{sched}", patch_size=40, seed=9, schedule=sched)

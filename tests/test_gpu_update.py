@@ -17,32 +17,6 @@ from tests.gpu_util import compare, cpu_order, mesh, say
 pytestmark = pytest.mark.gpu
 
 
-def swap_quad_diagonals(A, W, quads):
-    """The pattern of A with the diagonal of each quad (r, c) (torus
-    indexing, width W, height n / W) moved to the other diagonal."""
-    H = A.n // W
-    rows = [set(A.colind[A.rowptr[i]:A.rowptr[i + 1]].tolist()) for i in range(A.n)]
-
-    def vid(r, c):
-        return (r % H) * W + (c % W)
-
-    for r, c in quads:
-        a, b = vid(r, c), vid(r + 1, c + 1)
-        x, y = vid(r, c + 1), vid(r + 1, c)
-        if b in rows[a]:
-            old, new = (a, b), (x, y)
-        else:
-            old, new = (x, y), (a, b)
-        rows[old[0]].discard(old[1])
-        rows[old[1]].discard(old[0])
-        rows[new[0]].add(new[1])
-        rows[new[1]].add(new[0])
-    rp = np.zeros(A.n + 1, np.int64)
-    np.cumsum([len(r) for r in rows], out=rp[1:])
-    ci = np.concatenate([np.array(sorted(r), np.int32) for r in rows])
-    return mg.CSR(A.n, rp.astype(np.int32), ci)
-
-
 def _dev(A):
     import torch
     dev = torch.device("cuda:0")
@@ -73,7 +47,7 @@ def test_update_matches_oracle_with_kept_patches(H, W, seed, S, quads):
     rp, ci = _dev(A)
     first = fpm.order(rp, ci, A.n, patch_size=S, seed=seed, handle=h0)
     gmap = first["gmap"][:A.n].clone()
-    B = swap_quad_diagonals(A, W, quads) if quads else A
+    B = mg.swap_quad_diagonals(A, W, quads) if quads else A
     say(f"[update] {H}x{W} S={S}: {len(quads)} quads changed")
     rp2, ci2 = _dev(B)
     out = fpm.order_update(rp2, ci2, B.n, gmap, h0._ws, patch_size=S, seed=seed, handle=h1)

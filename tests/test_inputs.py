@@ -27,3 +27,15 @@ def test_workload_recipes_are_deterministic():
     assert [(t, m.side, m.seed) for t, m in s1] == [(t, m.side, m.seed) for t, m in s2]
     assert all(100 <= m.side <= 1414 for _, m in s1)
     assert all(t2 > t1 for (t1, _), (t2, _) in zip(s1, s1[1:]))
+
+
+def test_swap_quad_diagonals_is_a_local_symmetric_change():
+    import scipy.sparse as sp
+    A = mg.grid_mesh(12, 10, True, 3)
+    B = mg.swap_quad_diagonals(A, 10, [(2, 3), (7, 9)])
+    M = sp.csr_matrix((np.ones(B.nnz), B.colind, B.rowptr), shape=(B.n, B.n))
+    assert (M != M.T).nnz == 0 and B.nnz == A.nnz
+    MA = sp.csr_matrix((np.ones(A.nnz), A.colind, A.rowptr), shape=(A.n, A.n))
+    assert (M != MA).nnz == 8  # two edges out, two in, both directions
+    C = mg.swap_quad_diagonals(B, 10, [(2, 3), (7, 9)])
+    assert np.array_equal(C.rowptr, A.rowptr) and np.array_equal(C.colind, A.colind)
