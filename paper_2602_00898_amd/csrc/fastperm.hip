@@ -57,10 +57,13 @@ __device__ __forceinline__ int vs(const FpSlot& s) { return s.gx * (int)blockDim
 __device__ __forceinline__ int vw(const FpSlot& s) { return uni(vt(s) >> 6); }
 __device__ __forceinline__ int vn(const FpSlot& s) { return vs(s) >> 6; }
 
-#define MESH0                          \
-  const FpSlot fp_s = fp_slot(fp_g);   \
-  const FpMesh& M = fp_g.ms[fp_s.mi];  \
-  gptr<FpCtl> C = M.ctl;               \
+// The meshes' descriptions come in as a __restrict__ kernel argument: the
+// kernels never write them, and without the qualifier the compiler would
+// reload a description field after every store in a loop.
+#define MESH0                                                  \
+  const FpSlot fp_s = fp_slot(FpGrid{fp_ms, fp_boff, fp_nm});  \
+  const FpMesh& M = fp_ms[fp_s.mi];                            \
+  gptr<FpCtl> C = M.ctl;                                       \
   (void)C
 
 // Every stage after ingest stops at once when an earlier one raised an
@@ -207,7 +210,7 @@ __host__ __device__ __forceinline__ int scan_blocks(int cap) {
 }
 // exclusive scan of a per-mesh array, three launches: chunk sums, a scan of
 // the sums (one block per mesh), chunk rescans; the total goes to `tdst`
-__global__ void k_mscan_part(FpGrid fp_g, int ain, int fcnt) {
+__global__ void k_mscan_part(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int ain, int fcnt) {
   MESH;
   __shared__ int tmp[FP_WAVES + 2];
   const int cap = fn_cap(M, fcnt), n = fn_count(M, fcnt);
@@ -220,7 +223,7 @@ __global__ void k_mscan_part(FpGrid fp_g, int ain, int fcnt) {
   wg_excl_scan(sum, tmp, &tot);
   if (threadIdx.x == 0) C->part[fp_s.bx] = tot;
 }
-__global__ void k_mscan_top(FpGrid fp_g, int fcnt, int tdst) {
+__global__ void k_mscan_top(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int fcnt, int tdst) {
   MESH;
   __shared__ int tmp[FP_WAVES + 2];
   const int np = scan_blocks(fn_cap(M, fcnt));
@@ -235,7 +238,7 @@ __global__ void k_mscan_top(FpGrid fp_g, int fcnt, int tdst) {
   }
   if (threadIdx.x == 0) *ft_ptr(M, tdst) = base;
 }
-__global__ void k_mscan_apply(FpGrid fp_g, int ain, int aout, int fcnt) {
+__global__ void k_mscan_apply(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int ain, int aout, int fcnt) {
   MESH;
   __shared__ int tmp[FP_WAVES + 2];
   const int cap = fn_cap(M, fcnt), n = fn_count(M, fcnt);
@@ -254,11 +257,11 @@ __global__ void k_mscan_apply(FpGrid fp_g, int ain, int aout, int fcnt) {
   }
 }
 // out[count] = total (the last row pointer)
-__global__ void k_mptr_end(FpGrid fp_g, int aout, int fcnt, int tsrc) {
+__global__ void k_mptr_end(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int aout, int fcnt, int tsrc) {
   MESH;
   if (vt(fp_s) == 0) fa_arr(M, aout)[fn_count(M, fcnt)] = *ft_ptr(M, tsrc);
 }
-__global__ void k_mcopy(FpGrid fp_g, int adst, int asrc, int fcnt) {
+__global__ void k_mcopy(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int adst, int asrc, int fcnt) {
   MESH;
   const int n = fn_count(M, fcnt);
   gptr<int> d = fa_arr(M, adst);
@@ -276,7 +279,7 @@ __global__ void k_ctl_clear_all(const FpMesh* __restrict__ ms) {
 // ==========================================================================
 // ingest: graph of A without its diagonal (Sec. 4.1 Step 2, Sec. 6.5)
 // ==========================================================================
-__global__ void k_ingest(FpGrid fp_g, int fill) {
+__global__ void k_ingest(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int fill) {
   MESH0;
   if (fill && wave_failed(C)) return;
   unsigned eb = 0;
@@ -292,7 +295,7 @@ __global__ void k_ingest(FpGrid fp_g, int fill) {
   if (eb) fp_fail(C, eb, FP_SITE_INGEST, 0);
 }
 // rows of more than FP_ROW_SHORT input entries, a workgroup each
-__global__ void k_ingest_long(FpGrid fp_g, int fill) {
+__global__ void k_ingest_long(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int fill) {
   MESH0;
   __shared__ int red;
   if (fill && wg_failed(C)) return;
@@ -307,14 +310,14 @@ __global__ void k_ingest_long(FpGrid fp_g, int fill) {
 }
 // the vertex graph fits its capacity (an int32 count that overflowed reads
 // negative); the fill pass and every later stage are gated on this
-__global__ void k_check_graph(FpGrid fp_g) {
+__global__ void k_check_graph(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH0;
   if (vt(fp_s) == 0 && (C->nnz_g < 0 || (long long)C->nnz_g > M.Ecap))
     fp_fail(C, FP_E_SCRATCH, FP_SITE_GRAPH, C->nnz_g);
 }
 // every entry (v, u) of the graph has its mirror (u, v): the pattern of A is
 // symmetric (Sec. 4, inputs), block by block in block mode
-__global__ void k_validate(FpGrid fp_g) {
+__global__ void k_validate(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH0;
   if (!M.validate || wave_failed(C)) return;
   for (int v = vt(fp_s); v < M.n; v += vs(fp_s))
@@ -334,7 +337,7 @@ __global__ void k_validate(FpGrid fp_g) {
 __host__ __device__ __forceinline__ int fp_p0(long long n, int S) {
   return n > 0 ? (int)((n + S - 1) / S) : 0;
 }
-__global__ void k_seeds(FpGrid fp_g) {
+__global__ void k_seeds(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int P0 = fp_p0(M.n, M.S);
   const int n = M.n, S = M.S;
@@ -358,13 +361,13 @@ __global__ void k_seeds(FpGrid fp_g) {
     C->P = P0;
   }
 }
-__global__ void k_key_unset(FpGrid fp_g) {
+__global__ void k_key_unset(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.key[v] = FP_UNSET;
   for (int i = vt(fp_s); i < M.n + 16; i += vs(fp_s)) M.fcnt[i] = 0;
 }
 // all: every patch seed (the count is on the device); else the P0 seeds
-__global__ void k_seed_push(FpGrid fp_g, int all) {
+__global__ void k_seed_push(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int all) {
   MESH;
   const int nseeds = all ? min(C->P, M.n) : fp_p0(M.n, M.S);
   for (int k = vt(fp_s); k < nseeds; k += vs(fp_s)) {
@@ -378,7 +381,7 @@ __global__ void k_seed_push(FpGrid fp_g, int all) {
 // FP_BFS_ROW neighbours (columns, then keys) go out together, and the wave's
 // claims are appended with one atomic.
 #define FP_BFS_ROW 8
-__global__ void k_bfs_level(FpGrid fp_g, int lvl) {
+__global__ void k_bfs_level(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int lvl) {
   MESH;
   const int nf = M.fcnt[lvl];
   gptr<const int> cur = (lvl & 1) ? M.fb : M.fa;
@@ -452,7 +455,7 @@ __host__ __device__ __forceinline__ int fp_bfs_levels(int n, int S, bool inner) 
   const int L = (inner ? r : 2 * r) + 4;
   return L < 64 ? (L < n ? L : n) : (64 < n ? 64 : n);
 }
-__global__ void __launch_bounds__(1024) k_bfs_tail(FpGrid fp_g, int inner) {
+__global__ void __launch_bounds__(1024) k_bfs_tail(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int inner) {
   MESH_WG;
   const int lvl0 = fp_bfs_levels(M.n, M.S, inner != 0);
   wg_level_barrier();
@@ -473,7 +476,7 @@ __global__ void __launch_bounds__(1024) k_bfs_tail(FpGrid fp_g, int inner) {
     wg_level_barrier();
   }
 }
-__global__ void k_count_unset(FpGrid fp_g) {
+__global__ void k_count_unset(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   int cnt = 0;
   for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) cnt += (M.key[v] == FP_UNSET);
@@ -486,7 +489,7 @@ __global__ void k_count_unset(FpGrid fp_g) {
 // unlabelled.  Rounds of hooking and pointer jumping run as separate
 // launches while the previous round changed a label; a one-workgroup tail
 // finishes any component the rounds did not settle.
-__global__ void k_cc_init(FpGrid fp_g) {
+__global__ void k_cc_init(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const bool any = C->norphan > 0;
   if (vt(fp_s) == 0) C->ccn = any ? M.n : 0;
@@ -528,17 +531,17 @@ __device__ __forceinline__ bool cc_jump_pass(const FpMesh& M, int i0, int di) {
 __device__ __forceinline__ bool cc_round_live(gptr<FpCtl> C, int r) {
   return C->norphan > 0 && (r == 0 || C->ccchg[r - 1] != 0);
 }
-__global__ void k_cc_hook(FpGrid fp_g, int r) {
+__global__ void k_cc_hook(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int r) {
   MESH;
   if (!cc_round_live(C, r)) return;
   if (cc_hook_pass(M, vt(fp_s), vs(fp_s))) atomicOr(&C->ccchg[r], 1);
 }
-__global__ void k_cc_jump(FpGrid fp_g, int r) {
+__global__ void k_cc_jump(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int r) {
   MESH;
   if (!cc_round_live(C, r)) return;
   if (cc_jump_pass(M, vt(fp_s), vs(fp_s))) atomicOr(&C->ccchg[r], 1);
 }
-__global__ void __launch_bounds__(1024) k_cc_tail(FpGrid fp_g, int r0) {
+__global__ void __launch_bounds__(1024) k_cc_tail(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int r0) {
   MESH_WG;
   __shared__ int chg;
   if (!cc_round_live(C, r0)) return;
@@ -556,13 +559,13 @@ __global__ void __launch_bounds__(1024) k_cc_tail(FpGrid fp_g, int r0) {
     if (!c) break;
   }
 }
-__global__ void k_cc_flags(FpGrid fp_g) {
+__global__ void k_cc_flags(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   if (C->norphan == 0) return;
   for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.pcnt[v] = (M.fb[v] == v) ? 1 : 0;
 }
 // ids P0 + rank of the component's lowest vertex; P grows by the count
-__global__ void k_cc_label(FpGrid fp_g) {
+__global__ void k_cc_label(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   if (C->norphan == 0) return;
   const int P0 = C->P0;
@@ -579,7 +582,7 @@ __global__ void k_cc_label(FpGrid fp_g) {
 // distance inside the patch equals the distance to the boundary set of the
 // whole graph, because any path out of a patch passes its own boundary
 // first), ties to the lowest id; patches without a boundary keep their seed.
-__global__ void k_lloyd_gmap(FpGrid fp_g) {
+__global__ void k_lloyd_gmap(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int P = C->P;
   for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) M.gmap[v] = (int)(M.key[v] & 0xFFFFFFFFu);
@@ -588,7 +591,7 @@ __global__ void k_lloyd_gmap(FpGrid fp_g) {
 }
 // (the loops below step a whole workgroup at a time: wg_append holds a
 // barrier, and a single list counter takes one atomic per workgroup)
-__global__ void k_lloyd_bnd(FpGrid fp_g) {
+__global__ void k_lloyd_bnd(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH_WG;
   __shared__ int lds2[2];
   for (int v0 = (int)(fp_s.bx * blockDim.x); v0 < M.n; v0 += (int)(fp_s.gx * blockDim.x)) {
@@ -606,7 +609,7 @@ __global__ void k_lloyd_bnd(FpGrid fp_g) {
 // per patch, the candidate of largest distance (least vertex on ties); the
 // lanes of a wave that share a patch take their maximum first, so a patch
 // gets one atomic per wave instead of one per vertex
-__global__ void k_lloyd_best(FpGrid fp_g) {
+__global__ void k_lloyd_best(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
@@ -627,7 +630,7 @@ __global__ void k_lloyd_best(FpGrid fp_g) {
     }
   }
 }
-__global__ void k_lloyd_seed(FpGrid fp_g) {
+__global__ void k_lloyd_seed(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int P = C->P;
   for (int p = vt(fp_s); p < P; p += vs(fp_s)) {
@@ -635,7 +638,7 @@ __global__ void k_lloyd_seed(FpGrid fp_g) {
     if (bb) M.seeds[p] = (int)(0xFFFFFFFFu - (unsigned)(bb & 0xFFFFFFFFu));
   }
 }
-__global__ void k_gmap_final(FpGrid fp_g) {
+__global__ void k_gmap_final(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int P = C->P;
   for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) {
@@ -645,7 +648,7 @@ __global__ void k_gmap_final(FpGrid fp_g) {
     M.gmap[v] = (g < 0 || g >= P) ? 0 : g;
   }
 }
-__global__ void k_user_gmap(FpGrid fp_g) {
+__global__ void k_user_gmap(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   int mx = 0;
   for (int v = vt(fp_s); v < M.n; v += vs(fp_s)) {
@@ -664,13 +667,13 @@ __global__ void k_user_gmap(FpGrid fp_g) {
 // ==========================================================================
 // patch members, boundary list, quotient graph (Sec. 2; built once, Sec. 5)
 // ==========================================================================
-__global__ void k_quot_init(FpGrid fp_g) {
+__global__ void k_quot_init(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int P = min(C->P, M.n);
   for (int p = vt(fp_s); p <= P; p += vs(fp_s)) M.pcnt[p] = 0;
   if (vt(fp_s) == 0) C->nbnd = 0;
 }
-__global__ void k_patch_count(FpGrid fp_g) {
+__global__ void k_patch_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH_WG;
   __shared__ int lds2[2];
   for (int v0 = (int)(fp_s.bx * blockDim.x); v0 < M.n; v0 += (int)(fp_s.gx * blockDim.x)) {
@@ -685,7 +688,7 @@ __global__ void k_patch_count(FpGrid fp_g) {
     if (isb) M.bnd[slot] = v;
   }
 }
-__global__ void k_patch_scatter(FpGrid fp_g) {
+__global__ void k_patch_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
@@ -700,7 +703,7 @@ __global__ void k_patch_scatter(FpGrid fp_g) {
 // LDS bitmap over the patch ids (bm_words words per wave) one pass over the
 // members marks the neighbours, their loads issued a row at a time, and the
 // bitmap is read back in order; without it, one pass per neighbour.
-__global__ void k_qrow(FpGrid fp_g, int fill, int lds_words) {
+__global__ void k_qrow(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int fill, int lds_words) {
   MESH;
   FP_LDS_DECL;
   const int P = C->P;
@@ -767,7 +770,7 @@ __global__ void k_qrow(FpGrid fp_g, int fill, int lds_words) {
   }
 }
 
-__global__ void k_check_arcs(FpGrid fp_g) {
+__global__ void k_check_arcs(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   if (vt(fp_s) == 0 && (C->nq < 0 || (long long)C->nq > M.Ecap))
     fp_fail(C, FP_E_SCRATCH, FP_SITE_QARCS, C->nq);
@@ -779,7 +782,7 @@ __global__ void k_check_arcs(FpGrid fp_g) {
 // SuperSeparator (unmarked vertices with an unmarked neighbour across) and
 // RefineSeparator (keep the smaller side, ties to the left).
 // ==========================================================================
-__global__ void k_sep_init(FpGrid fp_g) {
+__global__ void k_sep_init(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int P = C->P;
   int D = 0;
@@ -807,13 +810,13 @@ __global__ void k_sep_init(FpGrid fp_g) {
   if (vt(fp_s) == 0) M.segN[0] = P;
 }
 // level d of the tree: alive arcs recounted from zero
-__global__ void k_level_begin(FpGrid fp_g, int d) {
+__global__ void k_level_begin(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d >= C->D) return;
   const int nq = min(C->nq, (int)M.Ecap);
   for (int a = vt(fp_s); a < nq; a += vs(fp_s)) M.qcnt[a] = 0;
 }
-__global__ void k_arcs(FpGrid fp_g, int d) {
+__global__ void k_arcs(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d >= C->D) return;
   const int nb = C->nbnd;
@@ -847,7 +850,7 @@ __global__ void k_arcs(FpGrid fp_g, int d) {
     }
   }
 }
-__global__ void __launch_bounds__(FP_WG) k_bisect(FpGrid fp_g, int d,
+__global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d,
                                                    int lds_bytes) {
   MESH_WG;
   __shared__ BisectLds sh;
@@ -859,7 +862,7 @@ __global__ void __launch_bounds__(FP_WG) k_bisect(FpGrid fp_g, int d,
     if (m >= 2) wg_bisect(M, t, M.segS[t], m, &sh, fp_lds, lds_bytes);
   }
 }
-__global__ void k_cand(FpGrid fp_g, int d) {
+__global__ void k_cand(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d >= C->D) return;
   const int hi = (1 << (d + 1)) - 1;
@@ -894,7 +897,7 @@ __global__ void k_cand(FpGrid fp_g, int d) {
     }
   }
 }
-__global__ void k_mark(FpGrid fp_g, int d) {
+__global__ void k_mark(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d >= C->D) return;
   const int nb = C->nbnd;
@@ -912,7 +915,7 @@ __global__ void k_mark(FpGrid fp_g, int d) {
   }
 }
 // leaves keep the remaining vertices of their patch
-__global__ void k_leaves(FpGrid fp_g) {
+__global__ void k_leaves(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   for (int v = vt(fp_s); v < M.n; v += vs(fp_s))
     if (M.node_of[v] == -1) M.node_of[v] = M.pnode[M.gmap[v]];
@@ -921,7 +924,7 @@ __global__ void k_leaves(FpGrid fp_g) {
 // ==========================================================================
 // grouping in schedule order (Alg. 3)
 // ==========================================================================
-__global__ void k_nsize(FpGrid fp_g) {
+__global__ void k_nsize(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int nn = C->nn;
   for (int x = vt(fp_s); x < nn; x += vs(fp_s)) M.nsize[x] = 0;
@@ -932,7 +935,7 @@ __global__ void k_nsize(FpGrid fp_g) {
     }
   }
 }
-__global__ void k_nsize_count(FpGrid fp_g) {
+__global__ void k_nsize_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
@@ -940,12 +943,12 @@ __global__ void k_nsize_count(FpGrid fp_g) {
     (void)wave_append_keyed(M.nsize, act ? M.node_of[v] : 0, act);
   }
 }
-__global__ void k_sched_place(FpGrid fp_g) {
+__global__ void k_sched_place(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int nn = C->nn, D = C->D;
   for (int x = vt(fp_s); x < nn; x += vs(fp_s)) M.sbuf[sched_pos(x, D, M.sched)] = M.nsize[x];
 }
-__global__ void k_nbegin(FpGrid fp_g) {
+__global__ void k_nbegin(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int nn = C->nn, D = C->D;
   for (int x = vt(fp_s); x < nn; x += vs(fp_s)) {
@@ -954,7 +957,7 @@ __global__ void k_nbegin(FpGrid fp_g) {
     M.ncur[x] = b;
   }
 }
-__global__ void k_scatter(FpGrid fp_g) {
+__global__ void k_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
     const int v = v0 + lane_id();
@@ -972,7 +975,7 @@ __global__ void k_scatter(FpGrid fp_g) {
 // unchanged takes the earlier order as it is.  One wave per node; flags in
 // segS (free once the tree is built) tell the task lists to skip it.
 // ==========================================================================
-__global__ void k_reuse(FpGrid fp_g) {
+__global__ void k_reuse(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const FpMesh* O = M.prev;
   if (!O) return;
@@ -1023,7 +1026,7 @@ __global__ void k_reuse(FpGrid fp_g) {
 // (a counting sort on size / 16, one workgroup): a class with more nodes
 // than resident slots then ends with its smallest nodes, not its largest.
 #define FP_TASK_BUCKETS 256
-__global__ void __launch_bounds__(1024) k_md_tasks(FpGrid fp_g, int ntop) {
+__global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int ntop) {
   MESH_WG;
   const int nn = C->nn;
   __shared__ int hist[FP_MD_CLASSES * FP_TASK_BUCKETS];
@@ -1057,7 +1060,7 @@ __global__ void __launch_bounds__(1024) k_md_tasks(FpGrid fp_g, int ntop) {
     if (k >= 0) M.tasks[(k / FP_TASK_BUCKETS) * M.NNcap + atomicAdd(&hist[k], 1)] = x;
   }
 }
-__global__ void __launch_bounds__(FP_WG) k_md(FpGrid fp_g, int c) {
+__global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int c) {
   MESH;
   FP_LDS_DECL;
   const int nsl = md_slice_waves(c);
@@ -1080,7 +1083,7 @@ __global__ void __launch_bounds__(FP_WG) k_md(FpGrid fp_g, int c) {
 // nodes, in heap order.  Their local orders, the longest serial chains of
 // the stage, then run on a second stream while the rest of the tree and the
 // grouping proceed.
-__global__ void k_top_count(FpGrid fp_g, int d) {
+__global__ void k_top_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d >= C->D) return;
   const int lo = (1 << d) - 1, hi = (2 << d) - 1;
@@ -1091,7 +1094,7 @@ __global__ void k_top_count(FpGrid fp_g, int d) {
     (void)wave_append_keyed(&C->tcnt[0], act ? t : 0, act);
   }
 }
-__global__ void k_top_place(FpGrid fp_g, int d) {
+__global__ void k_top_place(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (vt(fp_s) != 0 || d >= C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
@@ -1116,7 +1119,7 @@ __global__ void k_top_place(FpGrid fp_g, int d) {
   }
   C->top_shallow = shallow + tot;
 }
-__global__ void k_top_scatter(FpGrid fp_g, int d) {
+__global__ void k_top_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (C->top_stop || d >= C->D) return;
   const int lo = (1 << d) - 1, hi = (2 << d) - 1;
@@ -1129,7 +1132,7 @@ __global__ void k_top_scatter(FpGrid fp_g, int d) {
   }
 }
 // one wave (and the whole LDS) per depth-d node
-__global__ void __launch_bounds__(64) k_md_top(FpGrid fp_g, int d) {
+__global__ void __launch_bounds__(64) k_md_top(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   FP_LDS_DECL;
   if (d >= uni(C->D)) return;
@@ -1143,7 +1146,7 @@ __global__ void __launch_bounds__(64) k_md_top(FpGrid fp_g, int d) {
   md_node_list(M, t, M.tbuf + off, m, pos0, fp_lds, uni(M.lds_md));
 }
 // the schedule's ranges must be the ones the early orders took
-__global__ void k_top_check(FpGrid fp_g, int ntop) {
+__global__ void k_top_check(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int ntop) {
   MESH;
   ntop = min(ntop, C->nn);
   for (int t = vt(fp_s); t < ntop; t += vs(fp_s))
@@ -1155,14 +1158,14 @@ __global__ void k_top_check(FpGrid fp_g, int ntop) {
 // ==========================================================================
 // elimination tree and column counts, bottom-up over the tree levels
 // ==========================================================================
-__global__ void k_sym_init(FpGrid fp_g, int d) {
+__global__ void k_sym_init(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (vt(fp_s) == 0 && d <= C->D) {
     C->arena_top[d & 1] = 0;
     C->pool_top = 0;  // the pool holds one level's node scratch at a time
   }
 }
-__global__ void __launch_bounds__(FP_WG) k_sym_prep(FpGrid fp_g, int d) {
+__global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   FP_LDS_DECL;
   if (d > C->D) return;
@@ -1174,7 +1177,7 @@ __global__ void __launch_bounds__(FP_WG) k_sym_prep(FpGrid fp_g, int d) {
 // Elimination of the nodes whose queue links and forward rows fit in an LDS
 // slice: cls 0 with four waves per workgroup (a quarter of the per-node LDS
 // each), cls 1 with one wave owning the large slice.
-__global__ void __launch_bounds__(FP_WG) k_sym_elim(FpGrid fp_g, int d, int cls) {
+__global__ void __launch_bounds__(FP_WG) k_sym_elim(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d, int cls) {
   MESH;
   FP_LDS_DECL;
   if (d > C->D) return;
@@ -1187,13 +1190,13 @@ __global__ void __launch_bounds__(FP_WG) k_sym_elim(FpGrid fp_g, int d, int cls)
   for (int x = wv; x < cnt; x += nw) sym_elim<true>(M, lo + x, cls, slice, lw);
 }
 // nodes too large for the whole LDS: links and rows in global memory
-__global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(FpGrid fp_g, int d) {
+__global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d > C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
   for (int x = vw(fp_s); x < cnt; x += vn(fp_s)) sym_elim<false>(M, lo + x, 2, nullptr, 0);
 }
-__global__ void __launch_bounds__(FP_WG) k_sym_emit(FpGrid fp_g, int d) {
+__global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d > C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
@@ -1203,14 +1206,14 @@ __global__ void __launch_bounds__(FP_WG) k_sym_emit(FpGrid fp_g, int d) {
 // positions of the neighbours of vertex vperm[p].  One pass with a thread per
 // position; the symbolic kernels then read contiguous rows instead of
 // chasing vperm -> row pointers -> columns -> viperm per entry.
-__global__ void k_prow_deg(FpGrid fp_g) {
+__global__ void k_prow_deg(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   for (int p = vt(fp_s); p < M.n; p += vs(fp_s)) {
     const int v = M.vperm[p];
     M.pcnt[p] = (unsigned)v < (unsigned)M.n ? M.grp[v + 1] - M.grp[v] : 0;
   }
 }
-__global__ void k_prow_fill(FpGrid fp_g) {
+__global__ void k_prow_fill(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   for (int p = vt(fp_s); p < M.n; p += vs(fp_s)) {
     const int v = M.vperm[p];
@@ -1220,7 +1223,7 @@ __global__ void k_prow_fill(FpGrid fp_g) {
   }
 }
 // nnz(L): the column counts summed per workgroup, one atomic each
-__global__ void __launch_bounds__(FP_WG) k_nnzl(FpGrid fp_g) {
+__global__ void __launch_bounds__(FP_WG) k_nnzl(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH_WG;
   __shared__ long long part[FP_WAVES];
   long long s = 0;
@@ -1238,7 +1241,7 @@ __global__ void __launch_bounds__(FP_WG) k_nnzl(FpGrid fp_g) {
 // ==========================================================================
 // block expansion and outputs (Sec. 6.5)
 // ==========================================================================
-__global__ void k_expand(FpGrid fp_g) {
+__global__ void k_expand(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
   const int nn = C->nn;
   const int b = M.b;
@@ -1258,7 +1261,7 @@ __global__ void k_expand(FpGrid fp_g) {
       if (M.node_size_out) M.node_size_out[x] = M.nsize[x] * b;
     }
 }
-__global__ void k_finish(FpGrid fp_g) {
+__global__ void k_finish(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH0;
   if (vt(fp_s) != 0) return;
   const int nn = C->nn;
@@ -1446,7 +1449,7 @@ struct Pipe {
       if (b <= 0) return;
       const bool t = tk(name);
       if (t) tk_begin(s);
-      hipLaunchKernelGGL(kern, dim3((unsigned)b), T, lds, s, FpGrid{dm, nullptr, 1}, args...);
+      hipLaunchKernelGGL(kern, dim3((unsigned)b), T, lds, s, dm, (const int*)nullptr, 1, args...);
       if (t) tk_end(s);
       return;
     }
@@ -1468,7 +1471,7 @@ struct Pipe {
     }
     const int tot = tab[at + n];
     if (tot <= 0) return;
-    hipLaunchKernelGGL(kern, dim3((unsigned)tot), T, lds, s, FpGrid{dm, dtab + at, n}, args...);
+    hipLaunchKernelGGL(kern, dim3((unsigned)tot), T, lds, s, dm, (const int*)(dtab + at), n, args...);
   }
   void check() {
     if (!plan && hipGetLastError() != hipSuccess) hip_failed = true;
