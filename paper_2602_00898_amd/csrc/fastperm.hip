@@ -810,17 +810,20 @@ __global__ void k_sep_init(const FpMesh* __restrict__ fp_ms, const int* __restri
   if (vt(fp_s) == 0) M.segN[0] = P;
 }
 // level d of the tree: alive arcs recounted from zero
+__device__ __forceinline__ void lv_begin(const FpMesh& M, gptr<FpCtl> C, int d, int i0, int di) {
+  (void)d;
+  const int nq = min(C->nq, (int)M.Ecap);
+  for (int a = i0; a < nq; a += di) M.qcnt[a] = 0;
+}
 __global__ void k_level_begin(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d >= C->D) return;
-  const int nq = min(C->nq, (int)M.Ecap);
-  for (int a = vt(fp_s); a < nq; a += vs(fp_s)) M.qcnt[a] = 0;
+  lv_begin(M, C, d, vt(fp_s), vs(fp_s));
 }
-__global__ void k_arcs(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
-  MESH;
-  if (d >= C->D) return;
+__device__ __forceinline__ void lv_arcs(const FpMesh& M, gptr<FpCtl> C, int d, int i0, int di) {
+  (void)d;
   const int nb = C->nbnd;
-  for (int i = vt(fp_s); i < nb; i += vs(fp_s)) {
+  for (int i = i0; i < nb; i += di) {
     const int v = M.bnd[i];
     if (M.node_of[v] != -1) continue;
     const int gv = M.gmap[v];
@@ -850,6 +853,11 @@ __global__ void k_arcs(const FpMesh* __restrict__ fp_ms, const int* __restrict__
     }
   }
 }
+__global__ void k_arcs(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+  MESH;
+  if (d >= C->D) return;
+  lv_arcs(M, C, d, vt(fp_s), vs(fp_s));
+}
 __global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d,
                                                    int lds_bytes) {
   MESH_WG;
@@ -862,12 +870,11 @@ __global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ fp_
     if (m >= 2) wg_bisect(M, t, M.segS[t], m, &sh, fp_lds, lds_bytes);
   }
 }
-__global__ void k_cand(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
-  MESH;
-  if (d >= C->D) return;
+__device__ __forceinline__ void lv_cand(const FpMesh& M, gptr<FpCtl> C, int d, int i0, int di) {
+  (void)d;
   const int hi = (1 << (d + 1)) - 1;
   const int nb = C->nbnd;
-  for (int i = vt(fp_s); i < nb; i += vs(fp_s)) {
+  for (int i = i0; i < nb; i += di) {
     const int v = M.bnd[i];
     M.cand[i] = 0;
     if (M.node_of[v] != -1) continue;
@@ -897,11 +904,15 @@ __global__ void k_cand(const FpMesh* __restrict__ fp_ms, const int* __restrict__
     }
   }
 }
-__global__ void k_mark(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+__global__ void k_cand(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d >= C->D) return;
+  lv_cand(M, C, d, vt(fp_s), vs(fp_s));
+}
+__device__ __forceinline__ void lv_mark(const FpMesh& M, gptr<FpCtl> C, int d, int i0, int di) {
+  (void)d;
   const int nb = C->nbnd;
-  for (int i = vt(fp_s); i < nb; i += vs(fp_s)) {
+  for (int i = i0; i < nb; i += di) {
     if (!M.cand[i]) continue;
     const int v = M.bnd[i];
     const int c = M.pnode[M.gmap[v]];
@@ -913,6 +924,38 @@ __global__ void k_mark(const FpMesh* __restrict__ fp_ms, const int* __restrict__
       atomicSub(&M.wp[M.gmap[v]], 1);
     }
   }
+}
+__global__ void k_mark(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+  MESH;
+  if (d >= C->D) return;
+  lv_mark(M, C, d, vt(fp_s), vs(fp_s));
+}
+// One tree level in one workgroup: the steps of the level's separate
+// launches in turn, with a barrier between steps.  Used for the levels past
+// the expected depth, which only inputs with more patches than ⌈n/S⌉ (orphan
+// components, more user groups) reach; for every other input it returns at
+// once, one launch instead of five.
+__global__ void __launch_bounds__(FP_WG) k_level_wg(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d,
+                                                    int lds_bytes) {
+  MESH_WG;
+  __shared__ BisectLds sh;
+  FP_LDS_DECL;
+  if (d >= C->D) return;
+  const int i0 = (int)threadIdx.x, di = (int)blockDim.x;
+  wg_level_barrier();
+  lv_begin(M, C, d, i0, di);
+  wg_level_barrier();
+  lv_arcs(M, C, d, i0, di);
+  wg_level_barrier();
+  const int lo = (1 << d) - 1, hi = (1 << (d + 1)) - 1;
+  for (int t = lo; t < hi; t++) {
+    const int m = M.segN[t];
+    if (m >= 2) wg_bisect(M, t, M.segS[t], m, &sh, fp_lds, lds_bytes);
+  }
+  wg_level_barrier();
+  lv_cand(M, C, d, i0, di);
+  wg_level_barrier();
+  lv_mark(M, C, d, i0, di);
 }
 // leaves keep the remaining vertices of their patch
 __global__ void k_leaves(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
@@ -1201,6 +1244,40 @@ __global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ f
   if (d > C->D) return;
   const int lo = (1 << d) - 1, cnt = 1 << d;
   for (int x = vw(fp_s); x < cnt; x += vn(fp_s)) sym_emit(M, lo + x, d);
+}
+// One symbolic level in one workgroup (four waves), for the levels past the
+// expected depth: initialisation, prep, elimination of the three classes and
+// emission in turn, with a barrier between steps; wave w takes nodes w, w+4,
+// ... in every step, and wave 0 the large-LDS class with all of the LDS.
+__global__ void __launch_bounds__(FP_WG) k_sym_level_wg(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+  MESH0;
+  FP_LDS_DECL;
+  // the error word shared through the dynamic LDS (the large class below
+  // takes all of it, so no static LDS here)
+  if (threadIdx.x == 0) *(unsigned*)fp_lds = C->err;
+  __syncthreads();
+  const unsigned err = *(volatile unsigned*)fp_lds;
+  __syncthreads();
+  if (err || d > C->D) return;
+  if (threadIdx.x == 0) {
+    C->arena_top[d & 1] = 0;
+    C->pool_top = 0;
+  }
+  wg_level_barrier();
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  const int lw = M.lds_bytes / 4 / FP_WAVES;
+  int* slice = (int*)fp_lds + lw * wave_id();
+  const int w0 = uni(wave_id());
+  for (int x = w0; x < cnt; x += FP_WAVES) sym_prep(M, lo + x, d, slice, lw);
+  wg_level_barrier();
+  for (int x = w0; x < cnt; x += FP_WAVES) sym_elim<true>(M, lo + x, 0, slice, lw);
+  wg_level_barrier();
+  if (w0 == 0)
+    for (int x = 0; x < cnt; x++) sym_elim<true>(M, lo + x, 1, (int*)fp_lds, M.lds_big / 4);
+  wg_level_barrier();
+  for (int x = w0; x < cnt; x += FP_WAVES) sym_elim<false>(M, lo + x, 2, nullptr, 0);
+  wg_level_barrier();
+  for (int x = w0; x < cnt; x += FP_WAVES) sym_emit(M, lo + x, d);
 }
 // The permuted pattern by position, for the symbolic stage: row p lists the
 // positions of the neighbours of vertex vperm[p].  One pass with a thread per
@@ -1674,18 +1751,18 @@ fp_status run_pipe(Pipe& P) {
                          P.h->side_ok && !P.fixed && ensure_side(P.h)
                      ? std::min(FP_TOP_LEVELS, mp[0].Dmax)
                      : 0;
-  auto lvl = [&](int d, long long items) {  // a tree level of mesh i: small past Dexp
+  // a tree level of mesh i in separate launches up to its expected depth,
+  // past it in one workgroup (k_level_wg)
+  auto in_launches = [&](int d, int i) { return d < mp[i].Dmax && d <= mp[i].Dexp; };
+  auto lvl = [&](int d, long long items) {
     return [&, d, items](int i) -> long long {
-      if (d >= mp[i].Dmax) return 0;
-      return d <= mp[i].Dexp ? P.blk(items > 0 ? items : mp[i].n) : 1;
+      return in_launches(d, i) ? P.blk(items > 0 ? items : mp[i].n) : 0;
     };
   };
   for (int d = 0; d < Dmax; d++) {
     FPG("k_level_begin", k_level_begin,
-        [&, d](int i) -> long long {
-          return d >= mp[i].Dmax ? 0 : d <= mp[i].Dexp ? P.blk(8ll * mp[i].Pexp) : 1;
-        },
-        T, 0, st, d);
+        [&, d](int i) -> long long { return in_launches(d, i) ? P.blk(8ll * mp[i].Pexp) : 0; }, T, 0,
+        st, d);
     FPG("k_arcs", k_arcs, lvl(d, 0), T, 0, st, d);
     {
       // LDS for the local quotient subgraphs: a node at depth d holds about
@@ -1704,13 +1781,15 @@ fp_status run_pipe(Pipe& P) {
       const int lb = (int)std::min<long long>(P.h->lds_big - 1024, std::max(want, 256ll));
       FPG("k_bisect", k_bisect,
           [&, d](int i) -> long long {
-            if (d >= mp[i].Dmax) return 0;
-            return d <= mp[i].Dexp ? std::min(1 << std::min(d, 30), 4 * P.ncu()) : 1;
+            return in_launches(d, i) ? std::min(1 << std::min(d, 30), 4 * P.ncu()) : 0;
           },
           T, lb, st, d, lb);
+      FPG("k_cand", k_cand, lvl(d, 0), T, 0, st, d);
+      FPG("k_mark", k_mark, lvl(d, 0), T, 0, st, d);
+      FPG("k_level_wg", k_level_wg,
+          [&, d](int i) -> long long { return d < mp[i].Dmax && !in_launches(d, i) ? 1 : 0; }, T,
+          lb, st, d, lb);
     }
-    FPG("k_cand", k_cand, lvl(d, 0), T, 0, st, d);
-    FPG("k_mark", k_mark, lvl(d, 0), T, 0, st, d);
     if (d < TL) {
       const long long b = P.blk(mp[0].n);
       FPG("k_top_count", k_top_count, [&](int) { return b; }, T, 0, st, d);
@@ -1787,23 +1866,25 @@ fp_status run_pipe(Pipe& P) {
   FPG("k_prow_fill", k_prow_fill, per_n, T, 0, st);
   for (int d = Dmax; d >= 0; d--) {
     const int cnt = 1 << d;
+    // separate launches up to the expected depth, one workgroup past it
     auto G = [&, d, cnt](int i) -> long long {
-      if (d > mp[i].Dmax) return 0;
-      return d <= mp[i].Dexp
-                 ? std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * P.ncu()))
-                 : 1;
+      if (d > mp[i].Dmax || d > mp[i].Dexp) return 0;
+      return std::max(1, std::min((cnt + FP_WAVES - 1) / FP_WAVES, 16 * P.ncu()));
     };
     auto G1 = [&, d, cnt](int i) -> long long {
-      if (d > mp[i].Dmax) return 0;
-      return d <= mp[i].Dexp ? std::max(1, std::min(cnt, 4 * P.ncu())) : 1;
+      if (d > mp[i].Dmax || d > mp[i].Dexp) return 0;
+      return std::max(1, std::min(cnt, 4 * P.ncu()));
     };
-    auto G0 = [&, d](int i) -> long long { return d > mp[i].Dmax ? 0 : 1; };
+    auto G0 = [&, d](int i) -> long long { return d > mp[i].Dmax || d > mp[i].Dexp ? 0 : 1; };
     FPG("k_sym_init", k_sym_init, G0, dim3(64), 0, st, d);
     FPG("k_sym_prep", k_sym_prep, G, T, P.h->lds_bytes, st, d);
     FPG("k_sym_elim", k_sym_elim, G, T, P.h->lds_bytes, st, d, 0);
     FPG("k_sym_elim", k_sym_elim, G1, T, P.h->lds_big, st, d, 1);
     FPG("k_sym_elim_glb", k_sym_elim_glb, G, T, 0, st, d);
     FPG("k_sym_emit", k_sym_emit, G, T, 0, st, d);
+    FPG("k_sym_level_wg", k_sym_level_wg,
+        [&, d](int i) -> long long { return d <= mp[i].Dmax && d > mp[i].Dexp ? 1 : 0; }, T,
+        P.h->lds_big, st, d);
     P.check();
   }
   FPG("k_nnzl", k_nnzl, [&](int i) { return std::min(P.blk(mp[i].n), 2ll * P.ncu()); }, T, 0, st);
@@ -1878,7 +1959,11 @@ static int big_lds(int device) {
       hipFuncSetAttribute((const void*)k_bisect, hipFuncAttributeMaxDynamicSharedMemorySize,
                           big - 1024) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_sym_elim, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          big) != hipSuccess) {
+                          big) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_level_wg, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          big - 1024) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_sym_level_wg,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, big) != hipSuccess) {
     (void)hipGetLastError();
     return FP_LDS_BYTES;
   }

@@ -78,6 +78,25 @@ def test_batch_blocks_user_groups_and_options():
             "post order, lloyd 2")
 
 
+def test_batch_with_deep_and_shallow_trees():
+    """One batch whose meshes take the levels past their expected depth in
+    different ways: a mesh with 150 isolated vertices next to ordinary ones."""
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+    A = mesh(16, 16, True, 27)
+    iso = 150
+    rp = np.concatenate([A.rowptr[:-1], A.nnz + np.arange(iso + 1)]).astype(np.int32)
+    ci = np.concatenate([A.colind, A.n + np.arange(iso)]).astype(np.int32)
+    deep = mg.CSR(A.n + iso, rp, ci)
+    cases = [(mesh(20, 20, True, 3, 0.05), 40, 3), (deep, 300, 4), (mesh(33, 33, True, 5, 0.05), 64, 5)]
+    say("[batch] deep and shallow trees")
+    outs = fpm.order_batch(_device_meshes(cases))
+    torch.cuda.synchronize()
+    for (M, S, s), out in zip(cases, outs):
+        compare(_to_dict(out, M), cpu_order(M, patch_size=S, seed=s), f"batch n={M.n}")
+
+
 def test_batch_concatenated_arrays():
     """fp_order_batch_concat over one concatenated CSR (local indices per
     mesh) gives each mesh its own fp_order result, in the concatenated

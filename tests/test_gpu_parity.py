@@ -88,6 +88,21 @@ def test_disconnected_and_isolated():
     check(C, "disconnected", patch_size=200, seed=2)
 
 
+def test_many_more_patches_than_expected():
+    """Inputs with far more patches than n / S (many orphan components, many
+    small user groups) take the tree and symbolic levels past the expected
+    depth in the one-workgroup kernels."""
+    A = mesh(20, 20, True, 25)
+    iso = 300
+    n = A.n + iso
+    rp = np.concatenate([A.rowptr[:-1], A.nnz + np.arange(iso + 1)]).astype(np.int32)
+    ci = np.concatenate([A.colind, A.n + np.arange(iso)]).astype(np.int32)
+    check(mg.CSR(n, rp, ci), "300 isolated vertices", patch_size=400, seed=3)
+    B = mesh(30, 30, False, 26)
+    g = (np.arange(B.n) // 3).astype(np.int32)  # 300 groups where n / S = 3
+    check(B, "300 user groups", patch_size=300, user_gmap=g)
+
+
 def test_degenerate_sizes():
     one = mg.CSR(1, np.array([0, 1], np.int32), np.array([0], np.int32))
     check(one, "n=1", patch_size=4)
