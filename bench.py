@@ -232,7 +232,9 @@ def run_plain(args, A):
     n, nnz = A.n, A.nnz
     rp = torch.from_numpy(A.rowptr).to(dev)
     ci = torch.from_numpy(A.colind).to(dev)
+    from paper_2602_00898_amd import autotune
     h = fpm.Handle()
+    autotune.apply(h, autotune.exec_for(n))  # execution settings only: same result
     opts = fpm.options(PATCH, fpm.SCHED_LEVEL, 1, 1, MESH_SEED, fpm.FLAG_TIMING)
     ws_bytes, max_nodes = fpm.query(h, n, rp, ci, opts)
     out = fpm._alloc_out(n, max_nodes, 1, dev)
@@ -293,7 +295,7 @@ def run_plain(args, A):
     per_launch_bytes = kernel_bytes(dom, n, nnz, top_vertices) * args.steps / max(kt_launch, 1)
     avg_ms = kt_ms / max(kt_launch, 1)
     achieved = per_launch_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
-    return dict(n=n, nnz=nnz, nnzL=nnzL, P=P, D=D, ms=dt * 1e3 / args.steps,
+    return dict(n=n, nnz=nnz, nnzL=nnzL, P=P, D=D, ms=dt * 1e3 / args.steps, tuning=h.tuning()[:2],
                 stage_ms={k: sum(v) / len(v) for k, v in stages.items()}, dom=dom,
                 dom_bytes=per_launch_bytes, dom_avg_ms=avg_ms, dom_launches=kt_launch / args.steps,
                 achieved=achieved, kernels=kern, beta=beta,
@@ -324,7 +326,9 @@ def run_batch(args, meshes):
     torch.cuda.synchronize(dev)
     t_plain = time.perf_counter() - t
     log(f"batch plain: {t_plain:.2f} s")
+    from paper_2602_00898_amd import autotune
     hb = fpm.Handle()
+    autotune.apply(hb, autotune.exec_batch())
     fpm.order_batch(dm[:8], handle=hb)  # warm-up
     torch.cuda.synchronize(dev)
     t = time.perf_counter()
@@ -339,6 +343,7 @@ def run_batch(args, meshes):
             "meshes": len(meshes), "vertices": nv,
             "plain_value": round(nv / t_plain / 1e6, 4), "batched_value": round(nv / t_batch / 1e6, 4),
             "unit": "M vertices/s", "speedup": round(t_plain / t_batch, 3),
+            "tuning": list(hb.tuning()[:2]),
             "identical_to_plain": bool(same)}
 
 
@@ -591,7 +596,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1024x1024 torus triangle mesh, seeded diagonals, S=512",
                    "n": g["n"], "nnz": g["nnz"], "patch_size": PATCH, "patches": g["P"],
-                   "depth": g["D"], "nnzL": g["nnzL"]},
+                   "depth": g["D"], "nnzL": g["nnzL"], "md_lds_bytes": g["tuning"][0],
+                   "md_blocks_per_cu": g["tuning"][1]},
         "roofline": {"bound": "hbm", "kernel": g["dom"], "achieved": round(g["achieved"], 3),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(g["achieved"] / HBM_PEAK_GBS, 6),

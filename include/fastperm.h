@@ -216,6 +216,20 @@ fp_status fp_supernodes_query(int64_t n, size_t* workspace_bytes);
 fp_status fp_supernodes(fp_handle* h, int64_t n, const int32_t* parent, const int32_t* colcount,
                         void* workspace, size_t ws_bytes, fp_super_result* out, void* stream);
 
+/* Execution settings of the local-order stage (Sec. 4.3 Step 4), for an
+ * autotuner: the LDS of each local-order workgroup (its size classes are a
+ * quarter, half and all of it; 16 KB .. max_lds_bytes, a multiple of 1 KB;
+ * 64 KB by default) and the workgroups launched per CU (1 .. 8; 2 by
+ * default).  They change speed only: every result is the same under any
+ * setting.  fp_get_tuning also reports the device's per-workgroup LDS limit. */
+typedef struct {
+  int32_t md_lds_bytes;
+  int32_t md_blocks_per_cu;
+  int32_t max_lds_bytes; /* fp_get_tuning only */
+} fp_tuning;
+fp_status fp_set_tuning(fp_handle* h, const fp_tuning* t);
+fp_status fp_get_tuning(fp_handle* h, fp_tuning* t);
+
 /* Synchronise `stream` and translate the device error bits of the last
  * call that used `workspace`. */
 fp_status fp_last_error(fp_handle* h, void* workspace, void* stream);

@@ -1844,12 +1844,13 @@ fp_status run_pipe(Pipe& P) {
     }
     for (int c = 0; c < FP_MD_CLASSES; c++) {
       hipStream_t sc = !two || c == 0 ? st : c == 1 ? P.h->side2 : P.h->side3;
-      // one workgroup per CU twice over for one mesh; in a batch, a share
-      // of that in proportion to the mesh's expected node count
+      // md_per_cu workgroups per CU (tuning) for one mesh; in a batch, a
+      // share of that in proportion to the mesh's expected node count
       FPG("k_md", k_md,
           [&](int i) -> long long {
-            if (P.single) return 2ll * P.ncu();
-            return std::max(1ll, std::min(2ll * P.ncu(), (2ll * mp[i].Pexp + FP_WAVES - 1) / FP_WAVES));
+            const long long full = (long long)P.h->md_per_cu * P.ncu();
+            if (P.single) return full;
+            return std::max(1ll, std::min(full, (2ll * mp[i].Pexp + FP_WAVES - 1) / FP_WAVES));
           },
           T, c == 3 ? P.h->lds_bytes : P.h->lds_md, sc, c);
     }
@@ -1987,6 +1988,7 @@ fp_status fp_create(fp_handle** h) {
   H->lds_bytes = FP_LDS_BYTES;
   H->lds_big = big_lds(H->device);
   H->lds_md = std::min(H->lds_big, FP_MD_LDS);
+  H->md_per_cu = 2;
   H->side_ok = true;
   H->tk_name[0] = 0;
   H->tk_n = 0;
@@ -2384,6 +2386,24 @@ fp_status fp_order_batch_concat(fp_handle* h, int32_t n_mesh, const int64_t* row
     }
   }
   return batch_impl(h, n_mesh, A.data(), nullptr, opts, workspace, ws_bytes, R.data(), stream);
+}
+
+fp_status fp_set_tuning(fp_handle* h, const fp_tuning* t) {
+  if (!h || !t) return FP_ERR_ARG;
+  if (t->md_lds_bytes < 16 * 1024 || t->md_lds_bytes > h->lds_big || (t->md_lds_bytes & 1023) ||
+      t->md_blocks_per_cu < 1 || t->md_blocks_per_cu > 8)
+    return FP_ERR_ARG;
+  h->lds_md = t->md_lds_bytes;
+  h->md_per_cu = t->md_blocks_per_cu;
+  return FP_OK;
+}
+
+fp_status fp_get_tuning(fp_handle* h, fp_tuning* t) {
+  if (!h || !t) return FP_ERR_ARG;
+  t->md_lds_bytes = h->lds_md;
+  t->md_blocks_per_cu = h->md_per_cu;
+  t->max_lds_bytes = h->lds_big;
+  return FP_OK;
 }
 
 fp_status fp_time_kernel(fp_handle* h, const char* name) {

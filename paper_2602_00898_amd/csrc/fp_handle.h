@@ -23,7 +23,8 @@ struct fp_handle {
   int ncu;
   int lds_bytes;
   int lds_big;
-  int lds_md;  // the local orders' large LDS (at most FP_MD_LDS)
+  int lds_md;     // the local orders' large LDS (tuning; FP_MD_LDS by default)
+  int md_per_cu;  // local-order workgroups per CU (tuning; 2 by default)
   // second stream: local orders of the top separators, started while the
   // separator tree is still being built; events order it after the call's
   // stream and back

@@ -58,6 +58,11 @@ class SuperResult(C.Structure):
                 ("status", C.c_void_p)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("md_lds_bytes", C.c_int32), ("md_blocks_per_cu", C.c_int32),
+                ("max_lds_bytes", C.c_int32)]
+
+
 class HostCsr(C.Structure):
     _fields_ = [("n", C.c_int64), ("nnz", C.c_int64), ("rowptr", C.c_void_p),
                 ("colind", C.c_void_p)]
@@ -115,6 +120,8 @@ def lib():
         L.fp_server_wait.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, C.POINTER(C.c_int64),
                                      C.POINTER(C.c_double)]
         L.fp_server_destroy.argtypes = [vp]
+        L.fp_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.fp_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.fp_supernodes_query.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
         L.fp_supernodes.argtypes = [vp, C.c_int64, vp, vp, vp, C.c_size_t,
                                     C.POINTER(SuperResult), vp]
@@ -144,6 +151,16 @@ class Handle:
         if getattr(self, "h", None) is not None and _lib is not None:
             _lib.fp_destroy(self.h)
             self.h = None
+
+    def tuning(self):
+        """(md_lds_bytes, md_blocks_per_cu, max_lds_bytes) of this handle."""
+        t = Tuning()
+        _check(lib().fp_get_tuning(self.h, C.byref(t)), "fp_get_tuning")
+        return t.md_lds_bytes, t.md_blocks_per_cu, t.max_lds_bytes
+
+    def set_tuning(self, md_lds_bytes, md_blocks_per_cu):
+        t = Tuning(int(md_lds_bytes), int(md_blocks_per_cu), 0)
+        _check(lib().fp_set_tuning(self.h, C.byref(t)), "fp_set_tuning")
 
     def workspace(self, nbytes, device):
         if self._ws is None or self._ws.numel() < nbytes or self._ws.device != device:
