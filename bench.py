@@ -336,15 +336,79 @@ def run_batch(args, meshes):
     torch.cuda.synchronize(dev)
     t_batch = time.perf_counter() - t
     log(f"batch batched: {t_batch:.2f} s")
-    same = all(torch.equal(a[k], b[k]) for a, b in zip(plain_out, bout)
+    # the same batch recorded once into a HIP graph, then replayed
+    gb = fpm.Graph(dm, handle=hb)
+    gb.launch()
+    torch.cuda.synchronize(dev)
+    reps = 3
+    t = time.perf_counter()
+    for _ in range(reps):
+        gout = gb.launch()
+    torch.cuda.synchronize(dev)
+    t_graph = (time.perf_counter() - t) / reps
+    log(f"batch graph replay: {t_graph:.3f} s")
+    same = all(torch.equal(a[k], b[k]) and torch.equal(a[k], c[k])
+               for a, b, c in zip(plain_out, bout, gout)
                for k in ("perm", "iperm", "parent", "colcount", "nnzL"))
+    del gb
     return {"workload": "256 grid/torus meshes, sides log-uniform 45..447, 5% edge flips, "
                         "S from the autotune table",
             "meshes": len(meshes), "vertices": nv,
             "plain_value": round(nv / t_plain / 1e6, 4), "batched_value": round(nv / t_batch / 1e6, 4),
+            "graph_replay_value": round(nv / t_graph / 1e6, 4),
             "unit": "M vertices/s", "speedup": round(t_plain / t_batch, 3),
             "tuning": list(hb.tuning()[:2]),
             "identical_to_plain": bool(same)}
+
+
+# ------------------------------------------------------------------ graph
+def run_graph(args):
+    """Latency of one small mesh: a call per ordering against the replay of
+    a recorded graph (no host work between the stages either way; the graph
+    also saves the host's per-launch cost)."""
+    import torch
+
+    from paper_2602_00898_amd import autotune
+    from paper_2602_00898_amd import fastperm as fpm
+    from paper_2602_00898_amd import meshgen as mg
+
+    dev = torch.device("cuda:0")
+    res = {}
+    for side in (64, 256):
+        A = mg.grid_mesh(side, side, True, MESH_SEED, 0.05)
+        rp = torch.from_numpy(A.rowptr).to(dev)
+        ci = torch.from_numpy(A.colind).to(dev)
+        S = autotune.patch_size_for(A.n)
+        h = fpm.Handle()
+        autotune.apply(h, autotune.exec_for(A.n))
+        opts = fpm.options(S, fpm.SCHED_LEVEL, 1, 1, MESH_SEED)
+        ws_bytes, max_nodes = fpm.query(h, A.n, rp, ci, opts)
+        out = fpm._alloc_out(A.n, max_nodes, 1, dev)
+        h.workspace(ws_bytes, dev)
+
+        def eager():
+            fpm.order(rp, ci, A.n, patch_size=S, seed=MESH_SEED, handle=h, out=out, check=False)
+
+        g = fpm.Graph([dict(rowptr=rp, colind=ci, n=A.n, patch_size=S, seed=MESH_SEED)], handle=h)
+        times = {}
+        for name, fn in (("eager", eager), ("graph", g.launch)):
+            for _ in range(5):
+                fn()
+            torch.cuda.synchronize(dev)
+            reps = 50
+            t = time.perf_counter()
+            for _ in range(reps):
+                fn()
+            torch.cuda.synchronize(dev)
+            times[name] = (time.perf_counter() - t) / reps * 1e3
+        same = all(torch.equal(out[k], g.outputs[0][k]) for k in ("perm", "parent", "colcount"))
+        res[f"torus{side}x{side}"] = {"n": A.n, "patch_size": S,
+                                      "eager_ms": round(times["eager"], 4),
+                                      "graph_ms": round(times["graph"], 4),
+                                      "identical": bool(same)}
+        log(f"graph {side}x{side}: eager {times['eager']:.3f} ms, graph {times['graph']:.3f} ms")
+        del g
+    return res
 
 
 # ------------------------------------------------------------------ update
@@ -555,6 +619,7 @@ def main():
     ap.add_argument("--slots", type=int, default=16, help="request-server slots")
     ap.add_argument("--no-update", action="store_true",
                     help="skip the pattern-change re-ordering of the benchmark mesh")
+    ap.add_argument("--no-graph", action="store_true", help="skip the recorded-graph latency")
     ap.add_argument("--no-block", action="store_true",
                     help="skip the 2048x2048 torus in 3x3 blocks (12.6M DOF)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -576,6 +641,7 @@ def main():
     batch = None if batch_meshes is None else run_batch(args, batch_meshes)
     serving = None if serve_reqs is None else run_serve(args, serve_reqs)
     update = None if args.no_update else run_update(args, A)
+    graph = None if args.no_graph else run_graph(args)
     block = None if args.no_block else run_block(args)
     cpu = None if args.no_cpu else run_cpu(A, batch_meshes)
     if cpu is not None and cpu.pop("nnzL") != g["nnzL"]:
@@ -617,6 +683,7 @@ def main():
         "batch": batch,
         "serving": serving,
         "update": update,
+        "graph": graph,
         "block": block,
         "cpu_baseline": cpu,
     }

@@ -277,7 +277,9 @@ fp_status fp_kernel_time(fp_handle* h, float* total_ms, int32_t* launches);
  * memory the handle keeps (a later batch call on the same handle first
  * waits for that copy).  Device errors of matrix i are its out[i].status
  * bits (0 = success), valid when `stream` reaches the end of the batch.
- * The call can be captured into a hipGraph. */
+ * To replay a batch without host work, record it with fp_graph_create: a
+ * stream capture of this call would record the copy from the handle's
+ * pinned memory, which a later batch call refills. */
 fp_status fp_query_batch(fp_handle* h, int32_t n_mesh, const fp_csr* A, const fp_options* opts,
                          const int32_t* const* user_gmap, size_t* workspace_bytes,
                          int32_t* max_nodes);
@@ -308,6 +310,35 @@ fp_status fp_order_batch_concat(fp_handle* h, int32_t n_mesh, const int64_t* row
                                 int32_t* colcount, int64_t* nnzL, uint32_t* status,
                                 int32_t* node_begin, int32_t* node_size, const int64_t* node_off,
                                 void* stream);
+
+/* ---------------------------------------------------------------------
+ * Recorded orderings: the whole pipeline of one matrix (the fp_order path)
+ * or of a batch (n_mesh > 1: the fp_order_batch path) recorded once into a
+ * HIP graph and replayed by fp_graph_launch with a single host call and no
+ * host work between the stages (Alg. 1 runs on the device end to end).
+ *   fp_graph_create: arguments as fp_order_batch; workspace_bytes from
+ *     fp_query_batch (for one matrix that is at least fp_query's).  The
+ *     descriptions and block tables are written into the workspace with a
+ *     synchronous copy before recording, so the workspace must be idle.
+ *     Flags other than FP_FLAG_VALIDATE (timing) give FP_ERR_ARG; the
+ *     handle's execution settings (fp_set_tuning) at this call are the
+ *     graph's.  Nothing is queued; *g receives the graph.
+ *   fp_graph_launch: queue one replay on `stream`.  Every replay reads the
+ *     inputs anew, so their contents may change between replays as long as
+ *     n and nnz stay those of the recording (the device checks every row
+ *     range against nnz); the outputs and device errors (out[i].status, or
+ *     fp_last_error on the workspace for one matrix) are those of the last
+ *     replay.  The inputs, outputs and workspace must stay allocated while
+ *     the graph exists; replays of one graph, and any other call on its
+ *     workspace, must not overlap (they share the workspace).
+ *   fp_graph_destroy: release the graph (NULL is a no-op); the caller makes
+ *     sure no replay is still running. */
+typedef struct fp_graph fp_graph;
+fp_status fp_graph_create(fp_handle* h, int32_t n_mesh, const fp_csr* A,
+                          const int32_t* const* user_gmap, const fp_options* opts, void* workspace,
+                          size_t ws_bytes, fp_result* out, fp_graph** g);
+fp_status fp_graph_launch(fp_graph* g, void* stream);
+fp_status fp_graph_destroy(fp_graph* g);
 
 /* ---------------------------------------------------------------------
  * Serving: a request loop that admits ordering requests of any size while

@@ -2235,7 +2235,7 @@ fp_status stage_batch(fp_handle* h, const void* a, size_t na, const void* b, siz
 
 fp_status batch_impl(fp_handle* h, int32_t n_mesh, const fp_csr* A,
                      const int32_t* const* user_gmap, const fp_options* opts, void* workspace,
-                     size_t ws_bytes, fp_result* out, void* stream) {
+                     size_t ws_bytes, fp_result* out, void* stream, bool staged = false) {
   if (!h || n_mesh < 0) return FP_ERR_ARG;
   if (n_mesh == 0) return FP_OK;
   if (!A || !opts || !out || !workspace) return FP_ERR_ARG;
@@ -2255,7 +2255,9 @@ fp_status batch_impl(fp_handle* h, int32_t n_mesh, const fp_csr* A,
   P.dm = (const FpMesh*)(base + L.o_desc);
   P.tab = L.tab;
   P.dtab = (const int*)(base + L.o_tab);
-  if ((s = stage_batch(h, L.desc.data(), sizeof(FpMesh) * n_mesh, L.tab.data(), 4 * L.tab.size(),
+  // (a recorded batch has its descriptions and tables in place already)
+  if (!staged &&
+      (s = stage_batch(h, L.desc.data(), sizeof(FpMesh) * n_mesh, L.tab.data(), 4 * L.tab.size(),
                        P.st, base + L.o_desc, base + L.o_tab)))
     return s;
   // every mesh's control block cleared (one block each), then the pipeline
@@ -2386,6 +2388,80 @@ fp_status fp_order_batch_concat(fp_handle* h, int32_t n_mesh, const int64_t* row
     }
   }
   return batch_impl(h, n_mesh, A.data(), nullptr, opts, workspace, ws_bytes, R.data(), stream);
+}
+
+fp_status fp_graph_create(fp_handle* h, int32_t n_mesh, const fp_csr* A,
+                          const int32_t* const* user_gmap, const fp_options* opts, void* workspace,
+                          size_t ws_bytes, fp_result* out, fp_graph** g) {
+  if (!h || !g || n_mesh < 1 || !A || !opts || !out || !workspace) return FP_ERR_ARG;
+  *g = nullptr;
+  for (int32_t i = 0; i < n_mesh; i++)
+    if (opts[i].flags & ~FP_FLAG_VALIDATE) return FP_ERR_ARG;
+  // host-side checks and sizes first: nothing is recorded for a bad batch
+  BatchLayout L;
+  char* base = (char*)workspace;
+  fp_status s = batch_layout(h, n_mesh, A, user_gmap, opts, nullptr, nullptr, &L);
+  if (s) return s;
+  if (ws_bytes < L.total) return FP_ERR_SIZE;
+  if (n_mesh > 1) {
+    if ((s = batch_layout(h, n_mesh, A, user_gmap, opts, out, base, &L))) return s;
+    if (hipMemcpy(base + L.o_desc, L.desc.data(), sizeof(FpMesh) * n_mesh,
+                  hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(base + L.o_tab, L.tab.data(), 4 * L.tab.size(), hipMemcpyHostToDevice) !=
+            hipSuccess)
+      return FP_ERR_HIP;
+  }
+  // streams and events of the pipeline exist before recording starts; the
+  // kernel timing switch is off while recording
+  if (h->side_ok) (void)ensure_side(h);
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FP_ERR_HIP;
+  char tk_saved[sizeof(h->tk_name)];
+  memcpy(tk_saved, h->tk_name, sizeof(tk_saved));
+  h->tk_name[0] = 0;
+  hipGraph_t graph = nullptr;
+  if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipStreamDestroy(cs);
+    memcpy(h->tk_name, tk_saved, sizeof(tk_saved));
+    return FP_ERR_HIP;
+  }
+  s = n_mesh == 1 ? order_impl(h, A, user_gmap ? user_gmap[0] : nullptr, opts, workspace,
+                               ws_bytes, out, cs, false)
+                  : batch_impl(h, n_mesh, A, user_gmap, opts, workspace, ws_bytes, out, cs, true);
+  const hipError_t ec = hipStreamEndCapture(cs, &graph);
+  memcpy(h->tk_name, tk_saved, sizeof(tk_saved));
+  (void)hipStreamDestroy(cs);
+  if (s == FP_OK && (ec != hipSuccess || !graph)) s = FP_ERR_HIP;
+  hipGraphExec_t exec = nullptr;
+  if (s == FP_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
+    s = FP_ERR_HIP;
+  if (s != FP_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return s;
+  }
+  fp_graph* G = new (std::nothrow) fp_graph;
+  if (!G) {
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    return FP_ERR_OOM;
+  }
+  G->graph = graph;
+  G->exec = exec;
+  *g = G;
+  return FP_OK;
+}
+
+fp_status fp_graph_launch(fp_graph* g, void* stream) {
+  if (!g) return FP_ERR_ARG;
+  return hipGraphLaunch(g->exec, (hipStream_t)stream) == hipSuccess ? FP_OK : FP_ERR_HIP;
+}
+
+fp_status fp_graph_destroy(fp_graph* g) {
+  if (!g) return FP_OK;
+  const bool ok = hipGraphExecDestroy(g->exec) == hipSuccess && hipGraphDestroy(g->graph) == hipSuccess;
+  delete g;
+  return ok ? FP_OK : FP_ERR_HIP;
 }
 
 fp_status fp_set_tuning(fp_handle* h, const fp_tuning* t) {

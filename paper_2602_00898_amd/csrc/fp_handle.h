@@ -12,6 +12,12 @@
 
 struct fp_handle;
 
+// a recorded ordering: the graph and its executable form
+struct fp_graph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+
 // one lane of the request server: a handle of its own and a stream
 struct FpLane {
   fp_handle* h;

@@ -120,6 +120,10 @@ def lib():
         L.fp_server_wait.argtypes = [vp, C.c_uint64, vp, vp, vp, vp, C.POINTER(C.c_int64),
                                      C.POINTER(C.c_double)]
         L.fp_server_destroy.argtypes = [vp]
+        L.fp_graph_create.argtypes = [vp, C.c_int32, vp, vp, vp, vp, C.c_size_t, vp,
+                                      C.POINTER(C.c_void_p)]
+        L.fp_graph_launch.argtypes = [vp, vp]
+        L.fp_graph_destroy.argtypes = [vp]
         L.fp_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.fp_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.fp_supernodes_query.argtypes = [C.c_int64, C.POINTER(C.c_size_t)]
@@ -465,6 +469,67 @@ def order_batch_concat(rowptr, colind, vtx_off, nnz_off, opts_list, *, handle=No
             raise FpError(9, f"fp_order_batch_concat: matrix {bad[0]} device bits "
                              f"0x{int(st[bad[0]]):x}")
     return out
+
+
+class Graph:
+    """A recorded ordering (fp_graph_create): one matrix or a batch, replayed
+    by launch() with one host call.  `meshes` as for order_batch.  The
+    output dicts (`outputs`, one per matrix) are written by every replay;
+    the input tensors are read anew by every replay (same n and nnz)."""
+
+    def __init__(self, meshes, *, handle=None):
+        L = lib()
+        k = len(meshes)
+        if k == 0:
+            raise ValueError("Graph needs at least one matrix")
+        self.handle = handle or Handle()
+        A = (Csr * k)()
+        O = (Options * k)()
+        R = (Result * k)()
+        G = (C.c_void_p * k)()
+        self._keep = []
+        for i, m in enumerate(meshes):
+            A[i] = make_csr(m["n"], m["rowptr"], m["colind"])
+            O[i] = options(m.get("patch_size", 512), m.get("schedule", SCHED_LEVEL),
+                           m.get("block_size", 1), m.get("lloyd_iters", 1), m.get("seed", 0),
+                           m.get("flags", FLAG_VALIDATE))
+            ug = m.get("user_gmap")
+            G[i] = None if ug is None else ug.data_ptr()
+            self._keep += [m["rowptr"], m["colind"], ug]
+        ws, mx = C.c_size_t(), C.c_int32()
+        _check(L.fp_query_batch(self.handle.h, k, A, O, G, C.byref(ws), C.byref(mx)),
+               "fp_query_batch")
+        dev = meshes[0]["colind"].device
+        self.device = dev
+        self.outputs = []
+        for i, m in enumerate(meshes):
+            self.outputs.append(_alloc_out(m["n"], mx.value, m.get("block_size", 1), dev))
+            R[i] = _result(self.outputs[i])
+        # the graph's own workspace (it must outlive the graph)
+        self.workspace = torch.empty(int(ws.value), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize(dev)
+        g = C.c_void_p()
+        _check(L.fp_graph_create(self.handle.h, k, A, G, O, _ptr(self.workspace), ws.value, R,
+                                 C.byref(g)), "fp_graph_create")
+        self.g = g
+
+    def launch(self, stream=None, check=False):
+        s = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+        _check(lib().fp_graph_launch(self.g, C.c_void_p(s)), "fp_graph_launch")
+        if check:
+            torch.cuda.synchronize(self.device)
+            st = torch.cat([o["status"] for o in self.outputs]).cpu()
+            bad = torch.nonzero(st).flatten().tolist()
+            if bad:
+                raise FpError(9, f"graph replay: matrix {bad[0]} device bits "
+                                 f"0x{int(st[bad[0]]):x}")
+        return self.outputs
+
+    def __del__(self):
+        if getattr(self, "g", None) is not None and _lib is not None:
+            torch.cuda.synchronize(self.device)
+            _lib.fp_graph_destroy(self.g)
+            self.g = None
 
 
 class Server:
