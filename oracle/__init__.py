@@ -34,7 +34,8 @@ def build(force: bool = True) -> str:
 
 class _Opts(C.Structure):
     _fields_ = [("patch_size", C.c_int32), ("lloyd_iters", C.c_int32), ("seed", C.c_uint64),
-                ("schedule", C.c_int32), ("block_size", C.c_int32)]
+                ("schedule", C.c_int32), ("block_size", C.c_int32), ("nd_level", C.c_int32),
+                ("refine", C.c_int32)]
 
 
 class _Out(C.Structure):
@@ -59,7 +60,8 @@ def lib():
         L.fpo_patches.argtypes = [C.c_int32, vp, vp, C.c_int32, C.c_int32, C.c_uint64, vp, vp]
         L.fpo_grow.restype = C.c_int64
         L.fpo_grow.argtypes = [C.c_int32, vp, vp, C.c_int32, vp, vp]
-        L.fpo_septree.argtypes = [C.c_int32, vp, vp, C.c_int32, vp, vp, vp, vp]
+        L.fpo_septree.argtypes = [C.c_int32, vp, vp, C.c_int32, vp, C.c_int32, C.c_int32, vp,
+                                  vp, vp]
         L.fpo_bisect.argtypes = [C.c_int32, vp, vp, vp, vp]
         L.fpo_md.argtypes = [C.c_int32, vp, vp, vp]
         L.fpo_brute_md.argtypes = [C.c_int32, vp, vp, vp]
@@ -129,7 +131,7 @@ def grow(grp, gci, seeds):
     return label
 
 
-def septree(grp, gci, gmap, P: int):
+def septree(grp, gci, gmap, P: int, nd_level: int = -1, refine: bool = False):
     """O2-O6: (node_of, pnode, D)."""
     n = len(grp) - 1
     grp = _i64(grp)
@@ -138,8 +140,8 @@ def septree(grp, gci, gmap, P: int):
     node_of = np.zeros(n, dtype=np.int32)
     pnode = np.zeros(max(P, 1), dtype=np.int32)
     D = np.zeros(1, dtype=np.int32)
-    _check(lib().fpo_septree(n, _p(grp), _p(gci), P, _p(gmap), _p(node_of), _p(pnode), _p(D)),
-           "septree")
+    _check(lib().fpo_septree(n, _p(grp), _p(gci), P, _p(gmap), nd_level, int(refine),
+                             _p(node_of), _p(pnode), _p(D)), "septree")
     return node_of, pnode[:P].copy(), int(D[0])
 
 
@@ -226,12 +228,14 @@ def supernodes(parent, colcount):
 
 
 def order(rowptr, colind, n_dof: int, patch_size: int = 512, lloyd_iters: int = 1,
-          seed: int = 0, schedule: int = SCHED_LEVEL, block_size: int = 1, user_gmap=None):
+          seed: int = 0, schedule: int = SCHED_LEVEL, block_size: int = 1, user_gmap=None,
+          nd_level: int = -1, refine: bool = False):
     """The whole ordering; returns a dict of numpy arrays and scalars."""
     rp = _i64(rowptr)
     ci = _i32(colind)
     n_v = n_dof // block_size
-    opts = _Opts(patch_size, lloyd_iters, seed & 0xFFFFFFFFFFFFFFFF, schedule, block_size)
+    opts = _Opts(patch_size, lloyd_iters, seed & 0xFFFFFFFFFFFFFFFF, schedule, block_size,
+                 nd_level, int(refine))
     perm = np.zeros(n_dof, dtype=np.int32)
     iperm = np.zeros(n_dof, dtype=np.int32)
     parent = np.zeros(n_dof, dtype=np.int32)

@@ -397,14 +397,103 @@ static int64_t arc_index(const int64_t* qrp, const int32_t* qci, int32_t p, int3
   return lo;
 }
 
+/* RefineSeparator, refined reading: the smallest separator inside the
+ * superset.  The two sides follow the patches (Alg. 2 induces the left and
+ * right subgraphs from the patch bipartition), so a separator of node t is
+ * any set of candidates that touches every crossing edge (an unmarked left
+ * vertex joined to an unmarked right vertex): a vertex cover of the
+ * bipartite crossing graph.  Its minimum is the size of a maximum matching
+ * (Konig 1931).  Among the minimum covers the one taken is the refinement
+ * of the one-sided separator: start from side s (the side the one-sided
+ * rule marks), let Z be the vertices reachable from the s-vertices that the
+ * matching leaves free along alternating paths (non-matching edges from s
+ * to the other side, matching edges back); the cover is (s-side candidates
+ * outside Z) plus (other-side candidates inside Z).  Z does not depend on
+ * which maximum matching is found (Dulmage and Mendelsohn 1958: its s-side
+ * part is the set of s-vertices that some maximum matching leaves free), so
+ * the result is unique.  The matching is grown by augmenting paths found by
+ * breadth-first search from every s-vertex in ascending id (Kuhn 1955). */
+static int on_side(const int32_t* node_of, const int32_t* gmap, const int32_t* newnode,
+                   int32_t u, int32_t child) {
+  return node_of[u] == -1 && newnode[gmap[u]] == child;
+}
+
+static void refine_node(const int64_t* rp, const int32_t* ci, const int32_t* gmap,
+                        const int32_t* node_of, const int32_t* newnode, int32_t t, int32_t s_child,
+                        const int32_t* cv, int32_t ncv, int32_t* mate, int32_t* par,
+                        int32_t* seen, int32_t* stamp, int32_t* queue, uint8_t* sep) {
+  const int32_t o_child = (s_child & 1) ? s_child + 1 : s_child - 1;
+  (void)t;
+  for (int32_t i = 0; i < ncv; i++) mate[cv[i]] = -1;
+  /* maximum matching: one augmenting-path search per s-vertex */
+  for (int32_t i = 0; i < ncv; i++) {
+    int32_t r = cv[i];
+    if (newnode[gmap[r]] != s_child) continue;
+    int32_t st = ++*stamp, qh = 0, qt = 0, found = -1;
+    queue[qt++] = r;
+    while (qh < qt && found < 0) {
+      int32_t x = queue[qh++];
+      for (int64_t e = rp[x]; e < rp[x + 1] && found < 0; e++) {
+        int32_t u = ci[e];
+        if (!on_side(node_of, gmap, newnode, u, o_child) || seen[u] == st) continue;
+        seen[u] = st;
+        par[u] = x;
+        if (mate[u] == -1)
+          found = u;
+        else
+          queue[qt++] = mate[u];
+      }
+    }
+    /* flip the path: every other-side vertex on it takes its predecessor */
+    for (int32_t u = found; u >= 0;) {
+      int32_t x = par[u], next = mate[x];
+      mate[x] = u;
+      mate[u] = x;
+      u = next;
+    }
+  }
+  /* Z: alternating reachability from the free s-vertices */
+  int32_t st = ++*stamp, qh = 0, qt = 0;
+  for (int32_t i = 0; i < ncv; i++) {
+    int32_t r = cv[i];
+    if (newnode[gmap[r]] == s_child && mate[r] == -1) {
+      seen[r] = st;
+      queue[qt++] = r;
+    }
+  }
+  while (qh < qt) {
+    int32_t x = queue[qh++];
+    for (int64_t e = rp[x]; e < rp[x + 1]; e++) {
+      int32_t u = ci[e];
+      if (!on_side(node_of, gmap, newnode, u, o_child) || seen[u] == st || mate[x] == u) continue;
+      seen[u] = st;
+      /* u is matched: a free u would end an augmenting path */
+      int32_t y = mate[u];
+      if (y >= 0 && seen[y] != st) {
+        seen[y] = st;
+        queue[qt++] = y;
+      }
+    }
+  }
+  for (int32_t i = 0; i < ncv; i++) {
+    int32_t v = cv[i];
+    int32_t in_z = seen[v] == st;
+    sep[v] = newnode[gmap[v]] == s_child ? !in_z : in_z;
+  }
+}
+
 int fpo_septree(int32_t n, const int64_t* rp, const int32_t* ci, int32_t P,
-                const int32_t* gmap, int32_t* node_of, int32_t* pnode, int32_t* depth_out) {
-  if (n < 0 || P < 0 || (n > 0 && P < 1)) return FPO_ERR_ARG;
+                const int32_t* gmap, int32_t nd_level, int32_t refine, int32_t* node_of,
+                int32_t* pnode, int32_t* depth_out) {
+  if (n < 0 || P < 0 || (n > 0 && P < 1) || nd_level < -1) return FPO_ERR_ARG;
   for (int32_t v = 0; v < n; v++)
     if (gmap[v] < 0 || gmap[v] >= P) return FPO_ERR_INDEX;
   int32_t D = 0;
   while ((1LL << D) < P) D++;
   if (D > 24) return FPO_ERR_SIZE;
+  /* Sec. 4.2 Step 3: the recursion stops after nd_level levels; a leaf
+   * then keeps the remaining vertices of all its patches */
+  if (nd_level >= 0 && nd_level < D) D = nd_level;
   int32_t nn = (1 << (D + 1)) - 1;
   *depth_out = D;
   for (int32_t v = 0; v < n; v++) node_of[v] = -1;
@@ -452,6 +541,16 @@ int fpo_septree(int32_t n, const int64_t* rp, const int32_t* ci, int32_t P,
   int32_t* laci = NEW(int32_t, na);
   int64_t* lw = NEW(int64_t, P);
   uint8_t* lft = NEW(uint8_t, P);
+  /* refinement scratch */
+  int32_t* mate = NEW(int32_t, n);
+  int32_t* par = NEW(int32_t, n);
+  int32_t* seen = NEW(int32_t, n);
+  int32_t* queue = NEW(int32_t, n);
+  int32_t* cv = NEW(int32_t, n);
+  int32_t* cstart = NEW(int32_t, nn + 1);
+  uint8_t* sep = NEWZ(uint8_t, n);
+  int32_t stamp = 0;
+  for (int32_t v = 0; v < n; v++) seen[v] = 0;
 
   for (int32_t d = 0; d < D; d++) {
     /* weights as of the end of the previous level (Sec. 5: the separator
@@ -526,12 +625,38 @@ int fpo_septree(int32_t n, const int64_t* rp, const int32_t* ci, int32_t P,
           cR[t]++;
       }
     }
-    for (int32_t v = 0; v < n; v++) {
-      if (!cand[v]) continue;
-      int32_t t = pnode[gmap[v]];
-      int32_t is_left = newnode[gmap[v]] & 1;
-      int32_t mark_left = cL[t] <= cR[t];
-      if (is_left == mark_left) node_of[v] = t;
+    if (!refine) {
+      for (int32_t v = 0; v < n; v++) {
+        if (!cand[v]) continue;
+        int32_t t = pnode[gmap[v]];
+        int32_t is_left = newnode[gmap[v]] & 1;
+        int32_t mark_left = cL[t] <= cR[t];
+        if (is_left == mark_left) node_of[v] = t;
+      }
+    } else {
+      /* candidates of each node, ascending id; every node refined before
+       * any vertex of this level is marked */
+      for (int32_t t = lo; t <= hi; t++) cstart[t] = 0;
+      for (int32_t v = 0; v < n; v++)
+        if (cand[v]) cstart[pnode[gmap[v]] + 1]++;
+      cstart[lo] = 0;
+      for (int32_t t = lo; t < hi; t++) cstart[t + 1] += cstart[t];
+      {
+        int32_t* fill = NEW(int32_t, hi - lo);
+        for (int32_t t = lo; t < hi; t++) fill[t - lo] = cstart[t];
+        for (int32_t v = 0; v < n; v++)
+          if (cand[v]) cv[fill[pnode[gmap[v]] - lo]++] = v;
+        free(fill);
+      }
+      for (int32_t t = lo; t < hi; t++) {
+        if (!bis[t] || cstart[t + 1] == cstart[t]) continue;
+        int32_t s_child = cL[t] <= cR[t] ? 2 * t + 1 : 2 * t + 2;
+        refine_node(rp, ci, gmap, node_of, newnode, t, s_child, cv + cstart[t],
+                    cstart[t + 1] - cstart[t], mate, par, seen, &stamp, queue, sep);
+      }
+      for (int32_t t = lo; t < hi; t++)
+        for (int32_t k = cstart[t]; k < cstart[t + 1]; k++)
+          if (sep[cv[k]]) node_of[cv[k]] = t;
     }
     for (int32_t p = 0; p < P; p++) pnode[p] = newnode[p];
   }
@@ -555,6 +680,13 @@ int fpo_septree(int32_t n, const int64_t* rp, const int32_t* ci, int32_t P,
   free(laci);
   free(lw);
   free(lft);
+  free(mate);
+  free(par);
+  free(seen);
+  free(queue);
+  free(cv);
+  free(cstart);
+  free(sep);
   return FPO_OK;
 }
 
@@ -869,7 +1001,9 @@ int fpo_order(int64_t n_dof, const int64_t* rowptr, const int32_t* colind,
               const int32_t* user_gmap, const fpo_opts* opts, fpo_out* out) {
   if (!opts || !out) return FPO_ERR_ARG;
   int32_t b = opts->block_size;
-  if (b < 1 || opts->patch_size < 1 || opts->lloyd_iters < 0) return FPO_ERR_ARG;
+  if (b < 1 || opts->patch_size < 1 || opts->lloyd_iters < 0 || opts->nd_level < -1 ||
+      (opts->refine != 0 && opts->refine != 1))
+    return FPO_ERR_ARG;
   if (opts->schedule != FPO_SCHED_LEVEL && opts->schedule != FPO_SCHED_POST) return FPO_ERR_ARG;
   if (n_dof < 0 || n_dof % b || n_dof >= (1LL << 31)) return FPO_ERR_ARG;
   int32_t n = (int32_t)(n_dof / b);
@@ -909,7 +1043,8 @@ int fpo_order(int64_t n_dof, const int64_t* rowptr, const int32_t* colind,
   int32_t* node_of = NEW(int32_t, n);
   int32_t* pnode = NEW(int32_t, P);
   int32_t D = 0;
-  if ((rc = fpo_septree(n, rp, ci, P, gmap, node_of, pnode, &D))) goto done1;
+  if ((rc = fpo_septree(n, rp, ci, P, gmap, opts->nd_level, opts->refine, node_of, pnode, &D)))
+    goto done1;
   int32_t nn = (1 << (D + 1)) - 1;
 
   /* group the vertices of each node by ascending id */

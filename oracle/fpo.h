@@ -50,6 +50,10 @@ typedef struct {
   uint64_t seed;        /* seed of the seed-selection hash */
   int32_t schedule;     /* FPO_SCHED_LEVEL or FPO_SCHED_POST (Sec. 5) */
   int32_t block_size;   /* b >= 1: DOFs per mesh vertex (Sec. 4.1 Step 2, Sec. 6.5) */
+  int32_t nd_level;     /* -1: full depth ceil(log2 P); else at most this many
+                           levels, leaves holding several patches (Sec. 4.2 Step 3) */
+  int32_t refine;       /* 0: one-sided separator (the smaller candidate side);
+                           1: smallest separator inside the superset (Sec. 5) */
 } fpo_opts;
 
 typedef struct {
@@ -98,9 +102,13 @@ int64_t fpo_grow(int32_t n, const int64_t* rp, const int32_t* ci, int32_t nseeds
 
 /* O2-O6: separator tree (Sec. 4.2 Step 3, Alg. 2, Sec. 5).  node_of[v]
  * receives the heap index of v's node, pnode[p] the final node of patch p.
- * *depth_out = D.  Capacity of the heap is 2^(D+1)-1. */
+ * *depth_out = D = min(ceil(log2 P), nd_level) (nd_level -1: no limit).
+ * Capacity of the heap is 2^(D+1)-1.  refine selects the separator inside
+ * the superset: 0 one side's candidates, 1 the minimum vertex cover of the
+ * crossing edges (see refine_node). */
 int fpo_septree(int32_t n, const int64_t* rp, const int32_t* ci, int32_t P,
-                const int32_t* gmap, int32_t* node_of, int32_t* pnode, int32_t* depth_out);
+                const int32_t* gmap, int32_t nd_level, int32_t refine, int32_t* node_of,
+                int32_t* pnode, int32_t* depth_out);
 
 /* O4: bisection of a quotient subgraph in local indices 0..m-1 (Alg. 2,
  * BiPartition).  w: node weights; (arp, aci): adjacency (symmetric, no self

@@ -250,7 +250,7 @@ def subtree(t, nn):
     return set(out)
 
 
-def check_septree(rp, ci, gmap, P, node_of, pnode, D):
+def check_septree(rp, ci, gmap, P, node_of, pnode, D, one_sided=True):
     n = len(rp) - 1
     nn = 2 ** (D + 1) - 1
     assert np.all((node_of >= 0) & (node_of < nn))
@@ -290,7 +290,10 @@ def check_septree(rp, ci, gmap, P, node_of, pnode, D):
         M = set(np.flatnonzero(node_of == t))
         pt = set(np.flatnonzero(np.isin(pnode, list(sub[t]))))
         if len(pt) >= 2:
-            assert M == (cand_L if len(cand_L) <= len(cand_R) else cand_R)
+            if one_sided:
+                assert M == (cand_L if len(cand_L) <= len(cand_R) else cand_R)
+            else:
+                assert M <= cand_L | cand_R
             # the split of the patches is the bisection of the quotient
             # subgraph as it stood before this level
             pl = sorted(pt)
