@@ -71,7 +71,9 @@ typedef struct fp_handle fp_handle;
  * FP_ERR_SIZE (the oracle has the same limit). */
 typedef struct {
   int32_t patch_size;   /* target patch size S (Sec. 6 uses 256; default 512) */
-  int32_t nd_level;     /* -1: full depth (each leaf one patch); others unsupported */
+  int32_t nd_level;     /* -1: full depth ceil(log2 P), each leaf one patch; 0..30:
+                           at most nd_level levels, a leaf then keeps the remaining
+                           vertices of all its patches (Sec. 4.2 Step 3) */
   int32_t schedule;     /* FP_SCHED_LEVEL (default) or FP_SCHED_POST */
   int32_t block_size;   /* DOFs per mesh vertex, >= 1 (default 1) */
   int32_t lloyd_iters;  /* Lloyd re-centre iterations of patching (default 1) */
@@ -90,6 +92,16 @@ typedef struct {
  * saves one pass over the graph, and an asymmetric pattern then gives an
  * unspecified ordering. */
 #define FP_FLAG_VALIDATE 2u
+/* flags: refined separators (Sec. 5, separator refinement).  The two sides
+ * of a split follow the patches, so the separator can be any set of the
+ * superset's vertices that touches every edge between the sides; with this
+ * flag it is the smallest such set (a minimum vertex cover of the crossing
+ * edges, of the size of a maximum matching), namely the one closest to the
+ * side the default rule marks: that side's candidates that every maximum
+ * matching covers, plus the other-side neighbours of the rest.  Without it
+ * the separator is the smaller side's candidate set (ties to the left).
+ * Either way the result is unique. */
+#define FP_FLAG_REFINE 4u
 
 /* Pattern of A in CSR form (device arrays).  Exactly one of rowptr32 /
  * rowptr64 is non-NULL (n+1 entries); colind has nnz entries in [0, n).
@@ -320,7 +332,7 @@ fp_status fp_order_batch_concat(fp_handle* h, int32_t n_mesh, const int64_t* row
  *     fp_query_batch (for one matrix that is at least fp_query's).  The
  *     descriptions and block tables are written into the workspace with a
  *     synchronous copy before recording, so the workspace must be idle.
- *     Flags other than FP_FLAG_VALIDATE (timing) give FP_ERR_ARG; the
+ *     FP_FLAG_TIMING gives FP_ERR_ARG; the
  *     handle's execution settings (fp_set_tuning) at this call are the
  *     graph's.  Nothing is queued; *g receives the graph.
  *   fp_graph_launch: queue one replay on `stream`.  Every replay reads the

@@ -787,6 +787,8 @@ __global__ void k_sep_init(const FpMesh* __restrict__ fp_ms, const int* __restri
   const int P = C->P;
   int D = 0;
   while ((1ll << D) < P) D++;
+  // the recursion stops after nd_level levels (Sec. 4.2 Step 3)
+  if (M.nd_level >= 0 && M.nd_level < D) D = M.nd_level;
   const int nn = (1 << (D + 1)) - 1;
   if (nn > M.NNcap) {  // never expected: NNcap holds the tree of n patches
     if (vt(fp_s) == 0) fp_fail(C, FP_E_SCRATCH, FP_SITE_TREE, nn);
@@ -911,6 +913,7 @@ __global__ void k_cand(const FpMesh* __restrict__ fp_ms, const int* __restrict__
 }
 __device__ __forceinline__ void lv_mark(const FpMesh& M, gptr<FpCtl> C, int d, int i0, int di) {
   (void)d;
+  if (M.refine) return;  // the refinement marked the level
   const int nb = C->nbnd;
   for (int i = i0; i < nb; i += di) {
     if (!M.cand[i]) continue;
@@ -929,6 +932,207 @@ __global__ void k_mark(const FpMesh* __restrict__ fp_ms, const int* __restrict__
   MESH;
   if (d >= C->D) return;
   lv_mark(M, C, d, vt(fp_s), vs(fp_s));
+}
+// --------------------------------------------------------------------------
+// Refined separators (Sec. 5, separator refinement).  The sides of a split
+// follow the patches, so a separator of node t is any set of candidates
+// touching every crossing edge: a vertex cover of the bipartite crossing
+// graph.  The smallest has the size of a maximum matching (Konig).  The one
+// taken starts from side s (the side the one-sided rule marks): with Z the
+// vertices reachable from the s-vertices a maximum matching leaves free,
+// along alternating paths, the cover is (s-candidates outside Z) plus
+// (other-side candidates in Z).  Z is the same for every maximum matching
+// (Dulmage-Mendelsohn), so the parallel matching below, whose matching
+// depends on timing, still gives a unique separator.
+// --------------------------------------------------------------------------
+#define FP_REF_EP 256  // augmenting paths taken per phase (the rest wait)
+
+// exclusive scan of the level's candidate counts into roff/rcur (one
+// workgroup; sh: FP_WG ints of LDS)
+__device__ __forceinline__ void lv_ref_place(const FpMesh& M, int d, int* sh) {
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
+  const int chunk = (cnt + nt - 1) / nt;
+  const int a = min(cnt, tid * chunk), b = min(cnt, a + chunk);
+  int sum = 0;
+  for (int x = a; x < b; x++) sum += M.cntL[lo + x] + M.cntR[lo + x];
+  sh[tid] = sum;
+  __syncthreads();
+  if (tid == 0) {
+    int run = 0;
+    for (int i = 0; i < nt; i++) {
+      const int v = sh[i];
+      sh[i] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int run = sh[tid];
+  for (int x = a; x < b; x++) {
+    M.roff[lo + x] = run;
+    M.rcur[lo + x] = run;
+    run += M.cntL[lo + x] + M.cntR[lo + x];
+  }
+  __syncthreads();
+}
+// every candidate into its node's segment; matching state cleared
+__device__ __forceinline__ void lv_ref_scatter(const FpMesh& M, gptr<FpCtl> C, int d, int i0,
+                                               int di) {
+  (void)d;
+  const int nb = C->nbnd;
+  for (int i = i0; i < nb; i += di) {
+    if (!M.cand[i]) continue;
+    const int v = M.bnd[i];
+    const int t = (M.pnode[M.gmap[v]] - 1) >> 1;
+    M.rlist[atomicAdd(&M.rcur[t], 1)] = v;
+    M.mate[v] = -1;
+    M.seen[v] = 0;
+  }
+}
+// Node t by one workgroup: greedy matching, then phases of a breadth-first
+// search from all free s-vertices at once that stop at the first level with
+// free other-side vertices; one shortest augmenting path per search tree is
+// flipped (the trees are vertex-disjoint).  A phase that finds none has
+// reached exactly Z.  sh: (16 + FP_REF_EP) ints of LDS.
+__device__ void wg_refine_node(const FpMesh& M, gptr<FpCtl> C, int t, int* sh) {
+  const int k = M.cntL[t] + M.cntR[t];
+  if (k == 0) return;
+  const int k0 = M.roff[t];
+  const int s_child = M.cntL[t] <= M.cntR[t] ? 2 * t + 1 : 2 * t + 2;
+  const int o_child = (s_child & 1) ? s_child + 1 : s_child - 1;
+  const gptr<int> L = M.rlist + k0;
+  gptr<int> fa = M.rqa + k0, fb = M.rqb + k0;
+  const int tid = (int)threadIdx.x, nt = (int)blockDim.x;
+  auto other = [&](int u) { return M.node_of[u] == -1 && M.pnode[M.gmap[u]] == o_child; };
+  auto s_side = [&](int v) { return M.pnode[M.gmap[v]] == s_child; };
+  // greedy start: each s-vertex takes its first free neighbour across
+  for (int i = tid; i < k; i += nt) {
+    const int v = L[i];
+    if (!s_side(v)) continue;
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+      const int u = M.gci[e];
+      if (other(u) && atomicCAS(&M.mate[u], -1, v) == -1) {
+        M.mate[v] = u;
+        break;
+      }
+    }
+  }
+  wg_level_barrier();
+  int stamp = 0;
+  bool ok = true;
+  while (true) {
+    if (++stamp > k + 2) {  // each phase grows the matching: never expected
+      ok = false;
+      break;
+    }
+    if (tid == 0) {
+      sh[0] = 0;  // frontier
+      sh[2] = 0;  // free other-side vertices reached
+    }
+    __syncthreads();
+    for (int i = tid; i < k; i += nt) {
+      const int v = L[i];
+      if (!s_side(v) || M.mate[v] != -1) continue;
+      M.seen[v] = stamp;
+      M.rpar[v] = -1;
+      const int j = atomicAdd(&sh[0], 1);
+      if (j < k) fa[j] = v;
+    }
+    wg_level_barrier();
+    int nf = sh[0];
+    while (nf > 0) {
+      __syncthreads();
+      if (tid == 0) sh[1] = 0;
+      __syncthreads();
+      for (int i = tid; i < nf; i += nt) {
+        const int x = fa[i];
+        const int mx = M.mate[x];
+        for (int e = M.grp[x]; e < M.grp[x + 1]; e++) {
+          const int u = M.gci[e];
+          if (u == mx || !other(u)) continue;
+          if (atomicMax(&M.seen[u], stamp) >= stamp) continue;  // reached already
+          M.rpar[u] = x;
+          const int y = M.mate[u];
+          if (y == -1) {
+            const int j = atomicAdd(&sh[2], 1);
+            if (j < FP_REF_EP) sh[16 + j] = u;
+          } else {
+            M.seen[y] = stamp;
+            M.rpar[y] = u;
+            const int j = atomicAdd(&sh[1], 1);
+            if (j < k) fb[j] = y;  // at most once per s-vertex: never past k
+          }
+        }
+      }
+      wg_level_barrier();
+      if (sh[2] > 0) break;  // the shortest augmenting paths end at this level
+      nf = sh[1];
+      if (nf > k) {
+        ok = false;
+        break;
+      }
+      const gptr<int> tmp = fa;
+      fa = fb;
+      fb = tmp;
+    }
+    if (!ok) break;
+    const int nep = min(sh[2], FP_REF_EP);
+    if (nep == 0) break;  // no augmenting path: the last search reached Z
+    for (int j = tid; j < nep; j += nt) {
+      const int end = sh[16 + j];
+      // paths alternate: an other-side vertex's predecessor is an s-vertex,
+      // an s-vertex's is the other-side vertex matched to it (or -1: root);
+      // both walks are bounded by the node's size
+      int x = M.rpar[end], steps = 0;
+      while (x >= 0 && M.rpar[x] != -1 && steps++ <= k) x = M.rpar[M.rpar[x]];
+      if (x < 0 || steps > k) {
+        fp_fail(C, FP_E_INTERNAL, FP_SITE_REFINE, t);
+        continue;
+      }
+      // one path per search tree: the first to claim the root flips its path
+      if (atomicCAS(&M.seen[x], stamp, -stamp) != stamp) continue;
+      steps = 0;
+      for (int u = end; u != -1 && steps++ <= k;) {
+        const int y = M.rpar[u];
+        const int next = M.rpar[y];
+        M.mate[u] = y;
+        M.mate[y] = u;
+        u = next;
+      }
+    }
+    wg_level_barrier();
+  }
+  if (!ok) {
+    if (tid == 0) fp_fail(C, FP_E_INTERNAL, FP_SITE_REFINE, t);
+    return;
+  }
+  for (int i = tid; i < k; i += nt) {
+    const int v = L[i];
+    const bool in_z = M.seen[v] == stamp;
+    if (s_side(v) ? !in_z : in_z) {
+      M.node_of[v] = t;
+      atomicSub(&M.wp[M.gmap[v]], 1);
+    }
+  }
+  wg_level_barrier();
+}
+__global__ void __launch_bounds__(FP_WG) k_ref_place(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+  MESH_WG;
+  __shared__ int sh[FP_WG];
+  if (d >= C->D || !M.refine) return;
+  lv_ref_place(M, d, sh);
+}
+__global__ void k_ref_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+  MESH;
+  if (d >= C->D || !M.refine) return;
+  lv_ref_scatter(M, C, d, vt(fp_s), vs(fp_s));
+}
+__global__ void __launch_bounds__(FP_WG) k_refine(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+  MESH_WG;
+  __shared__ int sh[16 + FP_REF_EP];
+  if (d >= C->D || !M.refine) return;
+  const int lo = (1 << d) - 1, hi = (2 << d) - 1;
+  for (int t = lo + fp_s.bx; t < hi; t += fp_s.gx) wg_refine_node(M, C, t, sh);
 }
 // One tree level in one workgroup: the steps of the level's separate
 // launches in turn, with a barrier between steps.  Used for the levels past
@@ -955,7 +1159,18 @@ __global__ void __launch_bounds__(FP_WG) k_level_wg(const FpMesh* __restrict__ f
   wg_level_barrier();
   lv_cand(M, C, d, i0, di);
   wg_level_barrier();
-  lv_mark(M, C, d, i0, di);
+  if (M.refine) {
+    // the refinement's scratch comes from the dynamic LDS (the bisection
+    // above is done with it)
+    int* rsh = (int*)fp_lds;
+    lv_ref_place(M, d, rsh);
+    wg_level_barrier();
+    lv_ref_scatter(M, C, d, i0, di);
+    wg_level_barrier();
+    for (int t = lo; t < hi; t++) wg_refine_node(M, C, t, rsh);
+  } else {
+    lv_mark(M, C, d, i0, di);
+  }
 }
 // leaves keep the remaining vertices of their patch
 __global__ void k_leaves(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
@@ -1395,8 +1610,8 @@ fp_status check_opts(const fp_options* o) {
   if (o->patch_size < 1 || o->block_size < 1 || o->lloyd_iters < 0 || o->lloyd_iters > 64)
     return FP_ERR_ARG;
   if (o->schedule != FP_SCHED_LEVEL && o->schedule != FP_SCHED_POST) return FP_ERR_ARG;
-  if (o->nd_level != -1 || (o->flags & ~(FP_FLAG_TIMING | FP_FLAG_VALIDATE)))
-    return FP_ERR_UNSUPPORTED;
+  if (o->nd_level < -1 || o->nd_level > 30) return FP_ERR_ARG;
+  if (o->flags & ~(FP_FLAG_TIMING | FP_FLAG_VALIDATE | FP_FLAG_REFINE)) return FP_ERR_UNSUPPORTED;
   return FP_OK;
 }
 
@@ -1444,9 +1659,11 @@ struct MeshPlan {
   int lloyd;
   bool user;      // user groups instead of patching
   bool validate;  // symmetry check
+  bool refine;    // minimum-cover separators
   int sched;      // FP_SCHED_LEVEL or FP_SCHED_POST
   int P0, Pexp;   // seed blocks; expected patch count (exact without orphans)
-  int Dexp, Dmax; // expected and largest possible tree depth (P <= n)
+  int Dpat;       // ceil(log2 Pexp): a depth-d node holds about 2^(Dpat-d) patches
+  int Dexp, Dmax; // expected and largest possible tree depth (P <= n; nd_level)
   int NNcap;
   int Lg, Ld;     // launched levels of the growth and distance BFS
 };
@@ -1459,11 +1676,17 @@ MeshPlan mesh_plan(const FpMesh& M, bool user) {
   m.lloyd = M.lloyd;
   m.user = user;
   m.validate = M.validate != 0;
+  m.refine = M.refine != 0;
   m.sched = M.sched;
   m.P0 = fp_p0(M.n, M.S);
   m.Pexp = std::max(m.P0, 1);
-  m.Dexp = ceil_log2(m.Pexp);
+  m.Dpat = ceil_log2(m.Pexp);
+  m.Dexp = m.Dpat;
   m.Dmax = ceil_log2(std::max(M.n, 1));
+  if (M.nd_level >= 0) {
+    m.Dexp = std::min(m.Dexp, M.nd_level);
+    m.Dmax = std::min(m.Dmax, M.nd_level);
+  }
   m.NNcap = M.NNcap;
   m.Lg = fp_bfs_levels(M.n, M.S, false);
   m.Ld = fp_bfs_levels(M.n, M.S, true);
@@ -1774,17 +1997,31 @@ fp_status run_pipe(Pipe& P) {
       long long want = 0;
       for (int i = 0; i < nm; i++) {
         if (d >= mp[i].Dmax) continue;
-        const long long cap = 1ll << std::max(0, mp[i].Dexp - d);
+        const long long cap = 1ll << std::max(0, mp[i].Dpat - d);
         want = std::max(want, (1ll << d) <= P.ncu() ? (long long)P.h->lds_big
                                                      : (4 * (13 * cap + 1) + 255) & ~255ll);
       }
-      const int lb = (int)std::min<long long>(P.h->lds_big - 1024, std::max(want, 256ll));
+      // (at least the refinement's scratch, which the one-workgroup
+      // levels take from the same LDS)
+      const int lb = (int)std::min<long long>(P.h->lds_big - 1024, std::max(want, 2048ll));
       FPG("k_bisect", k_bisect,
           [&, d](int i) -> long long {
             return in_launches(d, i) ? std::min(1 << std::min(d, 30), 4 * P.ncu()) : 0;
           },
           T, lb, st, d, lb);
       FPG("k_cand", k_cand, lvl(d, 0), T, 0, st, d);
+      // refined separators: candidates grouped by node, then one workgroup
+      // per node finds the minimum cover and marks it (k_mark then skips)
+      auto ref = [&, d](long long b) {
+        return [&, d, b](int i) -> long long { return in_launches(d, i) && mp[i].refine ? b : 0; };
+      };
+      FPG("k_ref_place", k_ref_place, ref(1), T, 0, st, d);
+      FPG("k_ref_scatter", k_ref_scatter,
+          [&, d](int i) -> long long {
+            return in_launches(d, i) && mp[i].refine ? P.blk(mp[i].n) : 0;
+          },
+          T, 0, st, d);
+      FPG("k_refine", k_refine, ref(std::min(1 << std::min(d, 30), 4 * P.ncu())), T, 0, st, d);
       FPG("k_mark", k_mark, lvl(d, 0), T, 0, st, d);
       FPG("k_level_wg", k_level_wg,
           [&, d](int i) -> long long { return d < mp[i].Dmax && !in_launches(d, i) ? 1 : 0; }, T,
@@ -2087,6 +2324,8 @@ fp_status describe(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   M->sched = opts->schedule;
   M->seed = opts->seed;
   M->validate = (opts->flags & FP_FLAG_VALIDATE) != 0;
+  M->nd_level = opts->nd_level;
+  M->refine = (opts->flags & FP_FLAG_REFINE) != 0;
   M->perm = out->perm;
   M->iperm = out->iperm;
   M->parent = out->parent;

@@ -48,6 +48,7 @@ enum {
   FP_SITE_GRAPH = 23,       // vertex graph larger than its capacity
   FP_SITE_QARCS = 24,       // quotient graph larger than its capacity
   FP_SITE_TREE = 25,        // separator tree larger than its capacity
+  FP_SITE_REFINE = 26,      // separator refinement past its phase bound
 };
 
 // the dynamic LDS array of every kernel that uses one

@@ -139,6 +139,8 @@ struct FpMesh {
   int sched;
   unsigned long long seed;
   int validate;   // check that the pattern is symmetric
+  int nd_level;   // -1: full tree depth; else at most this many levels
+  int refine;     // separators: 0 one side's candidates, 1 minimum cover
   // outputs (device; optional ones may be null)
   gptr<int> perm;
   gptr<int> iperm;
@@ -204,6 +206,15 @@ struct FpMesh {
   long long acap;
   gptr<long long> sdesc;  // NNcap: pool word offset of a node's symbolic scratch, -1 if none
   gptr<int> tbuf;      // n: vertex lists of the top separators
+  // refined separators: candidates grouped by node, matching and search state
+  gptr<int> rlist;     // n: candidates of each node at roff[t]
+  gptr<int> mate;      // n: matched partner, -1 if free
+  gptr<int> rpar;      // n: search tree: predecessor of a vertex
+  gptr<int> seen;      // n: phase stamp of the last search that reached a vertex
+  gptr<int> rqa;       // n: search frontiers, at roff[t]
+  gptr<int> rqb;       // n
+  gptr<int> roff;      // NNcap: first candidate of each node
+  gptr<int> rcur;      // NNcap: fill cursor
   gptr<int> prow;      // n+1: the permuted pattern by position: row pointers
   gptr<int> pent;      // Ecap: its entries, as positions
   gptr<unsigned> pool; // fallback pool (32-bit words)

@@ -23,7 +23,8 @@ struct Plan {
   size_t o_ctl, o_mesh, o_fcnt, o_grp, o_gci, o_key, o_best, o_fa, o_fb, o_gmap, o_seeds, o_pcnt, o_pptr, o_pvtx,
       o_bnd, o_qptr, o_qci, o_qcnt, o_wp, o_pnode, o_plist, o_ploc, o_node_of, o_cand, o_bs[10],
       o_nsize, o_nbegin, o_ncur, o_segS, o_segN, o_cntL, o_cntR, o_sbuf, o_eoff, o_tasks, o_gbuf,
-      o_lidx, o_vperm, o_viperm, o_vpar, o_vcc, o_arena[2], o_sdesc, o_tbuf, o_prow, o_pent, o_pool;
+      o_lidx, o_vperm, o_viperm, o_vpar, o_vcc, o_arena[2], o_sdesc, o_tbuf, o_prow, o_pent, o_pool,
+      o_rlist, o_mate, o_rpar, o_seen, o_rqa, o_rqb, o_roff, o_rcur;
 };
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -100,6 +101,14 @@ bool make_plan(long long n_dof, int b, long long nnz, int S, Plan* P) {
   P->o_arena[1] = take(4 * (size_t)P->acap);
   P->o_sdesc = take(8 * NN);
   P->o_tbuf = take(4 * N1);
+  P->o_rlist = take(4 * N1);
+  P->o_mate = take(4 * N1);
+  P->o_rpar = take(4 * N1);
+  P->o_seen = take(4 * N1);
+  P->o_rqa = take(4 * N1);
+  P->o_rqb = take(4 * N1);
+  P->o_roff = take(4 * NN);
+  P->o_rcur = take(4 * NN);
   P->o_prow = take(4 * (N1 + 1));
   P->o_pent = take(4 * (size_t)P->Ecap);
   P->o_pool = take(4 * (size_t)P->pool_words);
@@ -159,6 +168,14 @@ void fill_mesh(const Plan& P, char* ws, FpMesh* M) {
   M->arena[1] = (int*)(ws + P.o_arena[1]);
   M->sdesc = (long long*)(ws + P.o_sdesc);
   M->tbuf = (int*)(ws + P.o_tbuf);
+  M->rlist = (int*)(ws + P.o_rlist);
+  M->mate = (int*)(ws + P.o_mate);
+  M->rpar = (int*)(ws + P.o_rpar);
+  M->seen = (int*)(ws + P.o_seen);
+  M->rqa = (int*)(ws + P.o_rqa);
+  M->rqb = (int*)(ws + P.o_rqb);
+  M->roff = (int*)(ws + P.o_roff);
+  M->rcur = (int*)(ws + P.o_rcur);
   M->prow = (int*)(ws + P.o_prow);
   M->pent = (int*)(ws + P.o_pent);
   M->pool = (unsigned*)(ws + P.o_pool);

@@ -174,19 +174,30 @@ class Handle:
 
 FLAG_TIMING = 1
 FLAG_VALIDATE = 2
+FLAG_REFINE = 4
 
 
 def options(patch_size=512, schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, seed=0,
-            flags=FLAG_VALIDATE):
+            flags=FLAG_VALIDATE, nd_level=-1):
     o = Options()
     lib().fp_options_default(C.byref(o))
     o.patch_size = patch_size
+    o.nd_level = nd_level
     o.schedule = schedule
     o.block_size = block_size
     o.lloyd_iters = lloyd_iters
     o.seed = seed & 0xFFFFFFFFFFFFFFFF
     o.flags = flags
     return o
+
+
+def _mesh_options(m):
+    """Options of one matrix of a batch or graph from its dict (keys
+    patch_size, schedule, block_size, lloyd_iters, seed, nd_level, refine,
+    flags)."""
+    flags = m.get("flags", FLAG_VALIDATE) | (FLAG_REFINE if m.get("refine") else 0)
+    return options(m.get("patch_size", 512), m.get("schedule", SCHED_LEVEL), m.get("block_size", 1),
+                   m.get("lloyd_iters", 1), m.get("seed", 0), flags, m.get("nd_level", -1))
 
 
 def make_csr(n, rowptr, colind):
@@ -212,15 +223,17 @@ def query(handle, n, rowptr, colind, opts):
 
 def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size=1,
           lloyd_iters=1, seed=0, user_gmap=None, handle=None, out=None, stream=None,
-          check=True, timing=False, validate=True):
+          check=True, timing=False, validate=True, nd_level=-1, refine=False):
     """Order one matrix on the GPU.  rowptr (int32/int64) and colind (int32)
     are device tensors.  Returns a dict of device tensors; with check=True
     the call synchronises and raises on device-reported errors.  validate
-    checks on the device that the pattern is symmetric."""
+    checks on the device that the pattern is symmetric; nd_level limits the
+    tree depth (-1: full); refine selects minimum-cover separators."""
     dev = colind.device if colind.numel() else rowptr.device
     handle = handle or Handle()
     opts = options(patch_size, schedule, block_size, lloyd_iters, seed,
-                   (FLAG_TIMING if timing else 0) | (FLAG_VALIDATE if validate else 0))
+                   (FLAG_TIMING if timing else 0) | (FLAG_VALIDATE if validate else 0)
+                   | (FLAG_REFINE if refine else 0), nd_level)
     A = make_csr(n, rowptr, colind)
     ws_bytes, max_nodes = query(handle, n, rowptr, colind, opts)
     ws = handle.workspace(ws_bytes, dev)
@@ -390,8 +403,7 @@ def order_batch(meshes, *, handle=None, stream=None, check=True):
     keep, outs = [], []
     for i, m in enumerate(meshes):
         A[i] = make_csr(m["n"], m["rowptr"], m["colind"])
-        O[i] = options(m.get("patch_size", 512), m.get("schedule", SCHED_LEVEL),
-                       m.get("block_size", 1), m.get("lloyd_iters", 1), m.get("seed", 0))
+        O[i] = _mesh_options(m)
         ug = m.get("user_gmap")
         G[i] = None if ug is None else ug.data_ptr()
         keep.append(ug)
@@ -430,8 +442,7 @@ def order_batch_concat(rowptr, colind, vtx_off, nnz_off, opts_list, *, handle=No
     handle = handle or Handle()
     O = (Options * k)()
     for i, o in enumerate(opts_list):
-        O[i] = options(o.get("patch_size", 512), o.get("schedule", SCHED_LEVEL),
-                       o.get("block_size", 1), o.get("lloyd_iters", 1), o.get("seed", 0))
+        O[i] = _mesh_options(o)
     vo = np.ascontiguousarray(vtx_off, dtype=np.int64)
     no = np.ascontiguousarray(nnz_off, dtype=np.int64)
     node_off = np.zeros(k + 1, dtype=np.int64)
@@ -490,9 +501,7 @@ class Graph:
         self._keep = []
         for i, m in enumerate(meshes):
             A[i] = make_csr(m["n"], m["rowptr"], m["colind"])
-            O[i] = options(m.get("patch_size", 512), m.get("schedule", SCHED_LEVEL),
-                           m.get("block_size", 1), m.get("lloyd_iters", 1), m.get("seed", 0),
-                           m.get("flags", FLAG_VALIDATE))
+            O[i] = _mesh_options(m)
             ug = m.get("user_gmap")
             G[i] = None if ug is None else ug.data_ptr()
             self._keep += [m["rowptr"], m["colind"], ug]
