@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
 class _Opts(C.Structure):
     _fields_ = [("patch_size", C.c_int32), ("lloyd_iters", C.c_int32), ("seed", C.c_uint64),
                 ("schedule", C.c_int32), ("block_size", C.c_int32), ("nd_level", C.c_int32),
-                ("refine", C.c_int32)]
+                ("refine", C.c_int32), ("local_amd", C.c_int32)]
 
 
 class _Out(C.Structure):
@@ -65,6 +65,7 @@ def lib():
         L.fpo_bisect.argtypes = [C.c_int32, vp, vp, vp, vp]
         L.fpo_md.argtypes = [C.c_int32, vp, vp, vp]
         L.fpo_brute_md.argtypes = [C.c_int32, vp, vp, vp]
+        L.fpo_amd.argtypes = [C.c_int32, vp, vp, vp, vp]
         L.fpo_etree.argtypes = [C.c_int32, vp, vp, vp, vp, vp]
         L.fpo_colcount.argtypes = [C.c_int32, vp, vp, vp, vp, vp, vp, vp]
         L.fpo_brute_symbolic.argtypes = [C.c_int32, vp, vp, vp, vp, vp, vp]
@@ -165,6 +166,18 @@ def md(rp, ci):
     return order[:m].copy()
 
 
+def amd(rp, ci, trace=False):
+    """F3: approximate-minimum-degree order; with trace=True also the
+    (m, m) array of approximate degrees at each pivot choice."""
+    m = len(rp) - 1
+    rp = _i64(rp)
+    ci = _i32(ci)
+    order = np.zeros(max(m, 1), dtype=np.int32)
+    tr = np.zeros((m, m), dtype=np.int32) if trace else None
+    _check(lib().fpo_amd(m, _p(rp), _p(ci), _p(order), _p(tr)), "amd")
+    return (order[:m].copy(), tr) if trace else order[:m].copy()
+
+
 def brute_md(rp, ci):
     m = len(rp) - 1
     rp = _i64(rp)
@@ -229,13 +242,13 @@ def supernodes(parent, colcount):
 
 def order(rowptr, colind, n_dof: int, patch_size: int = 512, lloyd_iters: int = 1,
           seed: int = 0, schedule: int = SCHED_LEVEL, block_size: int = 1, user_gmap=None,
-          nd_level: int = -1, refine: bool = False):
+          nd_level: int = -1, refine: bool = False, local_amd: bool = False):
     """The whole ordering; returns a dict of numpy arrays and scalars."""
     rp = _i64(rowptr)
     ci = _i32(colind)
     n_v = n_dof // block_size
     opts = _Opts(patch_size, lloyd_iters, seed & 0xFFFFFFFFFFFFFFFF, schedule, block_size,
-                 nd_level, int(refine))
+                 nd_level, int(refine), int(local_amd))
     perm = np.zeros(n_dof, dtype=np.int32)
     iperm = np.zeros(n_dof, dtype=np.int32)
     parent = np.zeros(n_dof, dtype=np.int32)

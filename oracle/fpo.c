@@ -759,6 +759,162 @@ int fpo_md(int32_t m, const int64_t* rp, const int32_t* ci, int32_t* order) {
   return FPO_OK;
 }
 
+/* ------------------------------------------------------------------ */
+/* F3: approximate minimum degree (Sec. 4.3 Step 4 names AMD as the     */
+/* local order; Amestoy, Davis and Duff, SIAM J. Matrix Anal. Appl.     */
+/* 17(4), 1996).  Elimination on the quotient graph: variable i keeps   */
+/* its variable neighbours A_i and its adjacent elements E_i; element e */
+/* keeps its variables L_e.  Eliminating pivot p forms the element      */
+/* L_p = (A_p + union of L_e over E_p) minus p, absorbs every element of */
+/* E_p, and for each i in L_p sets A_i = A_i minus (L_p + p) and         */
+/* E_i = (E_i minus E_p) + p.  The degree of i becomes the bound        */
+/*   min( r - 1, dbar_i + |L_p \ i|,                                     */
+/*        |A_i| + |L_p \ i| + sum over e in E_i \ p of |L_e \ L_p| )     */
+/* with r the variables left after the step; |L_e \ L_p| is |L_e| less  */
+/* the members of L_p that e touches.  The pivot is the least (dbar,    */
+/* index).  Every variable is its own supervariable here: no mass       */
+/* elimination and no aggressive absorption, so the order is defined by */
+/* the bound alone.  dtrace (nullable, m*m): dtrace[k*m+i] = dbar_i when */
+/* the k-th pivot is chosen, -1 once i is eliminated.                    */
+/* ------------------------------------------------------------------ */
+int fpo_amd(int32_t m, const int64_t* rp, const int32_t* ci, int32_t* order, int32_t* dtrace) {
+  if (m < 0) return FPO_ERR_ARG;
+  if (m == 0) return FPO_OK;
+  if (m > 65535) return FPO_ERR_SIZE;
+  /* A_i: distinct neighbours in 0..m-1 without i; E_i shares its row
+   * capacity (at most one adjacent element per original neighbour) */
+  int64_t* ro = NEW(int64_t, (int64_t)m + 1);
+  int32_t* alen = NEW(int32_t, m);
+  int32_t* elen = NEW(int32_t, m);
+  int32_t* mark = NEW(int32_t, m);
+  ro[0] = 0;
+  for (int32_t i = 0; i < m; i++) ro[i + 1] = ro[i] + (rp[i + 1] - rp[i]);
+  int32_t* arow = NEW(int32_t, ro[m] > 0 ? ro[m] : 1);
+  int32_t* erow = NEW(int32_t, ro[m] > 0 ? ro[m] : 1);
+  for (int32_t i = 0; i < m; i++) mark[i] = -1;
+  for (int32_t i = 0; i < m; i++) {
+    alen[i] = 0;
+    elen[i] = 0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; e++) {
+      int32_t j = ci[e];
+      if (j == i || j < 0 || j >= m || mark[j] == i) continue;
+      mark[j] = i;
+      arow[ro[i] + alen[i]++] = j;
+    }
+  }
+  int32_t** L = NEWZ(int32_t*, m); /* element lists, by pivot */
+  int32_t* llen = NEWZ(int32_t, m);
+  uint8_t* alive = NEW(uint8_t, m);
+  int32_t* dbar = NEW(int32_t, m);
+  int32_t* w = NEW(int32_t, m);
+  int32_t* wst = NEW(int32_t, m);
+  int32_t* lp = NEW(int32_t, m);
+  for (int32_t i = 0; i < m; i++) {
+    alive[i] = 1;
+    dbar[i] = alen[i];
+    mark[i] = -1;
+    wst[i] = -1;
+  }
+  for (int32_t k = 0; k < m; k++) {
+    if (dtrace)
+      for (int32_t i = 0; i < m; i++) dtrace[(int64_t)k * m + i] = alive[i] ? dbar[i] : -1;
+    int32_t p = -1;
+    for (int32_t i = 0; i < m; i++)
+      if (alive[i] && (p < 0 || dbar[i] < dbar[p])) p = i;
+    order[k] = p;
+    alive[p] = 0;
+    /* L_p from A_p and the elements of E_p (k is this step's mark) */
+    int32_t nl = 0;
+    for (int32_t a = 0; a < alen[p]; a++) {
+      int32_t v = arow[ro[p] + a];
+      if (alive[v] && mark[v] != k) {
+        mark[v] = k;
+        lp[nl++] = v;
+      }
+    }
+    for (int32_t a = 0; a < elen[p]; a++) {
+      int32_t e = erow[ro[p] + a];
+      for (int32_t q = 0; q < llen[e]; q++) {
+        int32_t v = L[e][q];
+        if (alive[v] && mark[v] != k) {
+          mark[v] = k;
+          lp[nl++] = v;
+        }
+      }
+    }
+    /* absorb E_p into p */
+    for (int32_t a = 0; a < elen[p]; a++) {
+      int32_t e = erow[ro[p] + a];
+      free(L[e]);
+      L[e] = NULL;
+      llen[e] = -1; /* absorbed */
+    }
+    L[p] = NEW(int32_t, nl > 0 ? nl : 1);
+    memcpy(L[p], lp, (size_t)nl * sizeof(int32_t));
+    llen[p] = nl;
+    /* quotient-graph update of every i in L_p */
+    for (int32_t q = 0; q < nl; q++) {
+      int32_t i = lp[q];
+      int32_t na = 0;
+      for (int32_t a = 0; a < alen[i]; a++) {
+        int32_t v = arow[ro[i] + a];
+        if (v != p && mark[v] != k) arow[ro[i] + na++] = v;
+      }
+      alen[i] = na;
+      int32_t ne = 0;
+      for (int32_t a = 0; a < elen[i]; a++) {
+        int32_t e = erow[ro[i] + a];
+        if (llen[e] >= 0) erow[ro[i] + ne++] = e;
+      }
+      erow[ro[i] + ne++] = p;
+      elen[i] = ne;
+    }
+    /* |L_e \ L_p| for the other elements next to L_p */
+    for (int32_t q = 0; q < nl; q++) {
+      int32_t i = lp[q];
+      for (int32_t a = 0; a < elen[i]; a++) {
+        int32_t e = erow[ro[i] + a];
+        if (e == p) continue;
+        if (wst[e] != k) {
+          wst[e] = k;
+          w[e] = llen[e];
+        }
+        w[e]--;
+      }
+    }
+    /* approximate degrees */
+    int32_t r = m - (k + 1);
+    for (int32_t q = 0; q < nl; q++) {
+      int32_t i = lp[q];
+      int64_t ext = 0;
+      for (int32_t a = 0; a < elen[i]; a++) {
+        int32_t e = erow[ro[i] + a];
+        if (e != p) ext += w[e];
+      }
+      int64_t b1 = r - 1;
+      int64_t b2 = (int64_t)dbar[i] + (nl - 1);
+      int64_t b3 = (int64_t)alen[i] + (nl - 1) + ext;
+      int64_t d = b1 < b2 ? b1 : b2;
+      dbar[i] = (int32_t)(d < b3 ? d : b3);
+    }
+  }
+  for (int32_t e = 0; e < m; e++) free(L[e]);
+  free(L);
+  free(llen);
+  free(ro);
+  free(alen);
+  free(elen);
+  free(mark);
+  free(arow);
+  free(erow);
+  free(alive);
+  free(dbar);
+  free(w);
+  free(wst);
+  free(lp);
+  return FPO_OK;
+}
+
 int fpo_brute_md(int32_t m, const int64_t* rp, const int32_t* ci, int32_t* order) {
   if (m < 0 || m > 2048) return FPO_ERR_SIZE;
   uint8_t* a = NEWZ(uint8_t, (int64_t)m * m);
@@ -1002,7 +1158,7 @@ int fpo_order(int64_t n_dof, const int64_t* rowptr, const int32_t* colind,
   if (!opts || !out) return FPO_ERR_ARG;
   int32_t b = opts->block_size;
   if (b < 1 || opts->patch_size < 1 || opts->lloyd_iters < 0 || opts->nd_level < -1 ||
-      (opts->refine != 0 && opts->refine != 1))
+      (opts->refine != 0 && opts->refine != 1) || (opts->local_amd != 0 && opts->local_amd != 1))
     return FPO_ERR_ARG;
   if (opts->schedule != FPO_SCHED_LEVEL && opts->schedule != FPO_SCHED_POST) return FPO_ERR_ARG;
   if (n_dof < 0 || n_dof % b || n_dof >= (1LL << 31)) return FPO_ERR_ARG;
@@ -1076,7 +1232,7 @@ int fpo_order(int64_t n_dof, const int64_t* rowptr, const int32_t* colind,
         if (node_of[ci[e]] == t) lci[k++] = loc[ci[e]];
       lrp[i + 1] = k;
     }
-    rc = fpo_md(m, lrp, lci, lord);
+    rc = opts->local_amd ? fpo_amd(m, lrp, lci, lord, NULL) : fpo_md(m, lrp, lci, lord);
     for (int32_t k = 0; k < m; k++) lorder[nstart[t] + k] = V[lord[k]];
   }
   if (rc) goto done2;

@@ -25,6 +25,11 @@
  *   block expansion            -- symbolic analysis of the expanded DOF pattern
  *   fpo_supernodes             -- column structures of a dense symbolic
  *                                 elimination compared set by set
+ *   fpo_amd                    -- exact minimum degree where the bound is exact
+ *                                 (trees, cycles); the traced bound re-derived
+ *                                 from the eliminated set's components
+ *   nd_level, refine           -- the full tree cut at nd_level; matching
+ *                                 numbers and the canonical cover (scipy)
  */
 #ifndef FPO_H
 #define FPO_H
@@ -54,6 +59,8 @@ typedef struct {
                            levels, leaves holding several patches (Sec. 4.2 Step 3) */
   int32_t refine;       /* 0: one-sided separator (the smaller candidate side);
                            1: smallest separator inside the superset (Sec. 5) */
+  int32_t local_amd;    /* 0: exact minimum degree local orders; 1: approximate
+                           minimum degree (fpo_amd) */
 } fpo_opts;
 
 typedef struct {
@@ -121,6 +128,13 @@ int fpo_bisect(int32_t m, const int64_t* w, const int64_t* arp, const int32_t* a
  * elimination graph, ties to the lowest index.  order[k] = k-th vertex.
  * m <= 65535 (FPO_ERR_SIZE beyond), the GPU library's limit too. */
 int fpo_md(int32_t m, const int64_t* rp, const int32_t* ci, int32_t* order);
+
+/* F3: approximate minimum degree (Amestoy, Davis, Duff 1996) on the
+ * quotient graph, each variable its own supervariable, pivot = least
+ * (approximate degree, index).  dtrace (nullable, m*m ints): the
+ * approximate degree of every variable when each pivot is chosen (-1 for
+ * eliminated ones).  m <= 65535. */
+int fpo_amd(int32_t m, const int64_t* rp, const int32_t* ci, int32_t* order, int32_t* dtrace);
 
 /* O9: elimination tree of A(perm,perm) by Liu's algorithm with path
  * compression.  G is the graph of A (no diagonal). */
