@@ -102,6 +102,13 @@ typedef struct {
  * the separator is the smaller side's candidate set (ties to the left).
  * Either way the result is unique. */
 #define FP_FLAG_REFINE 4u
+/* flags: approximate-minimum-degree local orders (Sec. 4.3 Step 4 names
+ * AMD; the degree bound of Amestoy, Davis and Duff, SIAM J. Matrix Anal.
+ * Appl. 17(4), 1996) instead of exact minimum degree: elimination on the
+ * quotient graph with element absorption, each variable its own
+ * supervariable, the pivot the least (bound, rank of the vertex id in the
+ * node).  The result is unique. */
+#define FP_FLAG_AMD 8u
 
 /* Pattern of A in CSR form (device arrays).  Exactly one of rowptr32 /
  * rowptr64 is non-NULL (n+1 entries); colind has nnz entries in [0, n).

@@ -21,6 +21,7 @@
 #include "fp_handle.h"
 #include "fp_plan.h"
 #include "fp_stages_sym.h"
+#include "fp_stages_amd.h"
 
 #define FP_CC_ROUNDS 4  // launched rounds of the orphan-component pass
 
@@ -1611,7 +1612,8 @@ fp_status check_opts(const fp_options* o) {
     return FP_ERR_ARG;
   if (o->schedule != FP_SCHED_LEVEL && o->schedule != FP_SCHED_POST) return FP_ERR_ARG;
   if (o->nd_level < -1 || o->nd_level > 30) return FP_ERR_ARG;
-  if (o->flags & ~(FP_FLAG_TIMING | FP_FLAG_VALIDATE | FP_FLAG_REFINE)) return FP_ERR_UNSUPPORTED;
+  if (o->flags & ~(FP_FLAG_TIMING | FP_FLAG_VALIDATE | FP_FLAG_REFINE | FP_FLAG_AMD))
+    return FP_ERR_UNSUPPORTED;
   return FP_OK;
 }
 
@@ -2326,6 +2328,7 @@ fp_status describe(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   M->validate = (opts->flags & FP_FLAG_VALIDATE) != 0;
   M->nd_level = opts->nd_level;
   M->refine = (opts->flags & FP_FLAG_REFINE) != 0;
+  M->amd = (opts->flags & FP_FLAG_AMD) != 0;
   M->perm = out->perm;
   M->iperm = out->iperm;
   M->parent = out->parent;

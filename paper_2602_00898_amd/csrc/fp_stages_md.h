@@ -348,6 +348,9 @@ __device__ __forceinline__ void md_sp_to_bit(const FpMesh& M, char* mem, int na,
 
 // Local order of node t: its m vertices listed at V (sorted there in place)
 // take positions pos0 .. pos0+m-1.
+// approximate-minimum-degree local order (fp_stages_amd.h)
+__device__ void md_amd_node(const FpMesh& M, int t, gptr<const int> V, int m, int pos0);
+
 __device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V, int m, int pos0,
                                              char* slice, long long slice_bytes) {
   if (m == 0) return;
@@ -392,6 +395,10 @@ __device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V
   wave_fence();
   for (int i = lane_id(); i < m; i += 64) M.lidx[V[i]] = i;
   wave_fence();
+  if (M.amd) {  // approximate minimum degree (the quotient graph in the pool)
+    md_amd_node(M, t, V, m, pos0);
+    return;
+  }
 
   const int mbit = md_bit_max(slice_bytes);
   if (m <= mbit) {

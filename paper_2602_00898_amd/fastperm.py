@@ -175,6 +175,7 @@ class Handle:
 FLAG_TIMING = 1
 FLAG_VALIDATE = 2
 FLAG_REFINE = 4
+FLAG_AMD = 8
 
 
 def options(patch_size=512, schedule=SCHED_LEVEL, block_size=1, lloyd_iters=1, seed=0,
@@ -195,7 +196,8 @@ def _mesh_options(m):
     """Options of one matrix of a batch or graph from its dict (keys
     patch_size, schedule, block_size, lloyd_iters, seed, nd_level, refine,
     flags)."""
-    flags = m.get("flags", FLAG_VALIDATE) | (FLAG_REFINE if m.get("refine") else 0)
+    flags = (m.get("flags", FLAG_VALIDATE) | (FLAG_REFINE if m.get("refine") else 0)
+             | (FLAG_AMD if m.get("amd") else 0))
     return options(m.get("patch_size", 512), m.get("schedule", SCHED_LEVEL), m.get("block_size", 1),
                    m.get("lloyd_iters", 1), m.get("seed", 0), flags, m.get("nd_level", -1))
 
@@ -223,17 +225,18 @@ def query(handle, n, rowptr, colind, opts):
 
 def order(rowptr, colind, n, *, patch_size=512, schedule=SCHED_LEVEL, block_size=1,
           lloyd_iters=1, seed=0, user_gmap=None, handle=None, out=None, stream=None,
-          check=True, timing=False, validate=True, nd_level=-1, refine=False):
+          check=True, timing=False, validate=True, nd_level=-1, refine=False, amd=False):
     """Order one matrix on the GPU.  rowptr (int32/int64) and colind (int32)
     are device tensors.  Returns a dict of device tensors; with check=True
     the call synchronises and raises on device-reported errors.  validate
     checks on the device that the pattern is symmetric; nd_level limits the
-    tree depth (-1: full); refine selects minimum-cover separators."""
+    tree depth (-1: full); refine selects minimum-cover separators; amd
+    approximate-minimum-degree local orders."""
     dev = colind.device if colind.numel() else rowptr.device
     handle = handle or Handle()
     opts = options(patch_size, schedule, block_size, lloyd_iters, seed,
                    (FLAG_TIMING if timing else 0) | (FLAG_VALIDATE if validate else 0)
-                   | (FLAG_REFINE if refine else 0), nd_level)
+                   | (FLAG_REFINE if refine else 0) | (FLAG_AMD if amd else 0), nd_level)
     A = make_csr(n, rowptr, colind)
     ws_bytes, max_nodes = query(handle, n, rowptr, colind, opts)
     ws = handle.workspace(ws_bytes, dev)

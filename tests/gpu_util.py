@@ -17,7 +17,7 @@ def say(*a):
 
 
 def gpu_order(A, *, patch_size, seed=0, schedule=0, block_size=1, lloyd_iters=1, user_gmap=None,
-              rowptr64=False, handle=None, nd_level=-1, refine=False):
+              rowptr64=False, handle=None, nd_level=-1, refine=False, amd=False):
     import torch
 
     from paper_2602_00898_amd import fastperm as fpm
@@ -27,7 +27,7 @@ def gpu_order(A, *, patch_size, seed=0, schedule=0, block_size=1, lloyd_iters=1,
     ug = None if user_gmap is None else torch.from_numpy(np.asarray(user_gmap, np.int32)).to(dev)
     out = fpm.order(rp, ci, A.n, patch_size=patch_size, seed=seed, schedule=schedule,
                     block_size=block_size, lloyd_iters=lloyd_iters, user_gmap=ug, handle=handle,
-                    nd_level=nd_level, refine=refine)
+                    nd_level=nd_level, refine=refine, amd=amd)
     torch.cuda.synchronize()
     r = {k: v.cpu().numpy() for k, v in out.items()}
     nn = int(r["n_nodes"][0])
@@ -39,10 +39,11 @@ def gpu_order(A, *, patch_size, seed=0, schedule=0, block_size=1, lloyd_iters=1,
 
 
 def cpu_order(A, *, patch_size, seed=0, schedule=0, block_size=1, lloyd_iters=1, user_gmap=None,
-              nd_level=-1, refine=False, **_):
+              nd_level=-1, refine=False, amd=False, **_):
     return oracle.order(A.rowptr, A.colind, A.n, patch_size=patch_size, seed=seed,
                         schedule=schedule, block_size=block_size, lloyd_iters=lloyd_iters,
-                        user_gmap=user_gmap, nd_level=nd_level, refine=refine)
+                        user_gmap=user_gmap, nd_level=nd_level, refine=refine,
+                        local_amd=amd)
 
 
 def compare(g, c, label=""):
