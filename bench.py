@@ -418,7 +418,7 @@ def run_graph(args):
 # ------------------------------------------------------------------ fill
 FILL_S = (64, 128, 256, 512, 1024)
 FILL_MODES = (("one-sided, full depth", -1, False), ("refined, full depth", -1, True),
-              ("refined, nd_level 10", 10, True))
+              ("refined, nd_level 10", 10, True), ("refined, AMD", -1, "amd"))
 
 
 def run_fill(args):
@@ -443,7 +443,7 @@ def run_fill(args):
             for S in FILL_S:
                 def run():
                     return fpm.order(rp, ci, A.n, patch_size=S, seed=MESH_SEED, handle=h,
-                                     nd_level=L, refine=ref)
+                                     nd_level=L, refine=bool(ref), amd=ref == "amd")
                 run()
                 torch.cuda.synchronize(dev)
                 t = time.perf_counter()
@@ -454,6 +454,47 @@ def run_fill(args):
             log(f"fill {side}x{side} {label}: {row['fill']}")
             res.append(row)
     return {"metric": "nnz(L)/nnz(A)", "patch_sizes": list(FILL_S), "rows": res}
+
+
+# ------------------------------------------------------------------ modes
+MODES = (("exact MD, one-sided separators (default)", dict()),
+         ("exact MD, refined separators", dict(refine=True)),
+         ("AMD, one-sided separators", dict(amd=True)),
+         ("AMD, refined separators", dict(amd=True, refine=True)),
+         ("AMD, refined, nd_level 10", dict(amd=True, refine=True, nd_level=10)))
+
+
+def run_modes(args, A):
+    """The headline mesh under each separator / local-order mode: time per
+    ordering (median of 7) and nnz(L)/nnz(A)."""
+    import torch
+
+    from paper_2602_00898_amd import autotune
+    from paper_2602_00898_amd import fastperm as fpm
+
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(A.rowptr).to(dev)
+    ci = torch.from_numpy(A.colind).to(dev)
+    h = fpm.Handle()
+    autotune.apply(h, autotune.exec_for(A.n))
+    res = []
+    for label, kw in MODES:
+        def run():
+            return fpm.order(rp, ci, A.n, patch_size=PATCH, seed=MESH_SEED, handle=h, **kw)
+        out = run()
+        torch.cuda.synchronize(dev)
+        ts = []
+        for _ in range(7):
+            t = time.perf_counter()
+            out = run()
+            torch.cuda.synchronize(dev)
+            ts.append(time.perf_counter() - t)
+        ms = sorted(ts)[3] * 1e3
+        res.append({"mode": label, "ms": round(ms, 3),
+                    "value": round(A.n / (ms * 1e-3) / 1e6, 3),
+                    "fill": round(int(out["nnzL"].item()) / A.nnz, 4)})
+        log(f"mode {label}: {ms:.2f} ms, fill {res[-1]['fill']}")
+    return {"workload": "1024x1024 torus, S=512", "unit": "M vertices/s", "rows": res}
 
 
 # ------------------------------------------------------------------ update
@@ -687,6 +728,7 @@ def main():
     batch = None if batch_meshes is None else run_batch(args, batch_meshes)
     graph = None if args.no_graph else run_graph(args)
     fill = None if args.no_fill else run_fill(args)
+    modes = None if args.no_fill else run_modes(args, A)
     serving = None if serve_reqs is None else run_serve(args, serve_reqs)
     update = None if args.no_update else run_update(args, A)
     block = None if args.no_block else run_block(args)
@@ -732,6 +774,7 @@ def main():
         "update": update,
         "graph": graph,
         "fill_vs_patch_size": fill,
+        "modes": modes,
         "block": block,
         "cpu_baseline": cpu,
     }
