@@ -439,11 +439,15 @@ __global__ void k_bfs_level(const FpMesh* __restrict__ fp_ms, const int* __restr
 // Levels past the last launched one, in one workgroup: a level at a time
 // with a barrier between levels, until a frontier comes out empty (a BFS has
 // fewer than n levels).  Only a BFS deeper than the launched levels does
-// any work here; late frontiers are small.  The agent-scope fences around
-// each barrier make the level's claims and appends (in L2) visible to every
-// lane's next loads, which would otherwise be served from this CU's L1.
+// any work here; late frontiers are small.  The barrier between steps that
+// share global memory within one workgroup: the release waits for the
+// workgroup's stores and atomics (which complete in L2), the agent-scope
+// acquire invalidates this CU's L1 so the next loads read L2.  No release
+// at agent scope: that would write back the whole L2 of the XCD at every
+// step, and nothing outside the workgroup reads these arrays before the
+// kernel ends.
 __device__ __forceinline__ void wg_level_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }

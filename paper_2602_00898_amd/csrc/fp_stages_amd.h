@@ -26,6 +26,13 @@
 
 #include "fp_stages_md.h"
 
+// a load served by L2, for words other lanes changed with atomics (which
+// complete in L2; the wave's L1 may still hold the line)
+template <class T>
+__device__ __forceinline__ T ld_l2(FP_GLOBAL T* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct AmdState {
   int m, G, DW;
   long long acap;
@@ -268,7 +275,7 @@ __device__ void md_amd_node(const FpMesh& M, int t, gptr<const int> V, int m, in
       long long ext = 0;
       for (int a = 0; a < le; a++) {
         const int e = S.erow[r0 + a];
-        if (e != p) ext += S.w[e];
+        if (e != p) ext += ld_l2(&S.w[e]);
       }
       const long long b1 = r - 1;
       const long long b2 = (long long)S.dbar[i] + (nl - 1);
@@ -282,7 +289,7 @@ __device__ void md_amd_node(const FpMesh& M, int t, gptr<const int> V, int m, in
     // refresh the groups whose keys changed
     for (int c = 0; c < S.DW; c += 64) {
       const int wi = c + lane;
-      const uint32_t x = wi < S.DW ? S.dirty[wi] : 0u;
+      const uint32_t x = wi < S.DW ? ld_l2(&S.dirty[wi]) : 0u;
       uint64_t bal = ballot64(x != 0u);
       while (bal) {
         const int l = __builtin_ctzll(bal);

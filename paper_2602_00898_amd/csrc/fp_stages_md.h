@@ -44,7 +44,7 @@ __device__ __forceinline__ int md_groups(int m) { return (m + 63) >> 6; }
 // LDS bytes of the BIT layout for m vertices
 __device__ __forceinline__ long long md_bit_bytes(int m) {
   const long long W = md_words(m), G = md_groups(m);
-  return 4ll * m * W + 12ll * W + 8ll * m + 12ll * G + 64;
+  return 4ll * m * W + 12ll * W + 12ll * m + 12ll * G + 64;
 }
 __device__ __forceinline__ int md_bit_max(long long bytes) {
   int lo = 0, hi = FP_MD_MAXM;
@@ -65,6 +65,7 @@ struct MdBit {
   int* nzw;
   int* nbl;
   uint32_t* key;
+  int* acc;  // per neighbour of the pivot: bits its row gained
   uint32_t* gmin;
   int* dl;  // dirty groups: flags [0,G) then list [G,2G)
   int m, W, G;
@@ -86,6 +87,8 @@ __device__ __forceinline__ void md_bit_carve(MdBit& B, char* mem, int m) {
   B.nbl = (int*)p;
   p += 4ll * m;
   B.key = (uint32_t*)p;
+  p += 4ll * m;
+  B.acc = (int*)p;
   p += 4ll * m;
   B.gmin = (uint32_t*)p;
   p += 4 * B.G;
@@ -153,8 +156,120 @@ __device__ __forceinline__ void md_map_order(const FpMesh& M, gptr<const int> vm
 // Run minimum degree steps on a BIT layout until every vertex is ordered.
 // vmap[i] = vertex id of current index i; outputs go to positions
 // pos0, pos0+1, ...
+//
+// Rows of at most 64 words (m <= 2048, so at most 32 groups): the group
+// minima live in registers (lane g holds group g's), lane w holds word w of
+// the pivot's live row, the neighbours are listed from the lanes' bits with
+// one prefix sum, and the clique update takes one lane per (neighbour,
+// nonzero word) pair, the bits each neighbour's row gains summed with LDS
+// atomics.  The groups to refresh are those of the pivot's nonzero words (a
+// group is two words) and the pivot's own; each 16-lane row of the wave
+// refreshes one of them.
+__device__ __forceinline__ void md_bit_run64(const FpMesh& M, MdBit& B, gptr<const int> vmap,
+                                             int pos0, int nsteps) {
+  const int lane = lane_id();
+  const int W = B.W, G = B.G;
+  uint32_t gm = lane < G ? B.gmin[lane] : FP_KEY_INF;
+  const int row = lane >> 4, q = lane & 15;
+  for (int s = 0; s < nsteps; s++) {
+    const uint32_t km = wave_min_u32(gm);
+    const int p = (int)(km & 0xFFFFu);
+    if (km == FP_KEY_INF || p >= B.m) {  // never expected: stop before any wild index
+      if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT, pos0);
+      md_map_order(M, vmap, B.m, pos0, s);
+      return;
+    }
+    if (lane == 0) {
+      M.vperm[pos0 + s] = p;
+      B.alive[p >> 5] &= ~(1u << (p & 31));
+      B.key[p] = FP_KEY_INF;
+    }
+    wave_fence();
+    const uint32_t* rp = B.rows + (long long)p * W;
+    const uint32_t x = lane < W ? (rp[lane] & B.alive[lane]) : 0u;
+    const uint64_t nzm = ballot64(x != 0u);
+    const int nnzw = popc64(nzm);
+    const int c = popc32(x);
+    const int inc = wave_incl_scan(c);
+    const int k = wave_bcast(inc, 63);
+    {
+      int off = inc - c;
+      uint32_t y = x;
+      while (y) {
+        const int bit = __ffs(y) - 1;
+        y &= y - 1;
+        B.nbl[off] = lane * 32 + bit;
+        B.acc[off] = 0;
+        off++;
+      }
+    }
+    if (x) {
+      B.nzw[popc64(nzm & lanemask_lt())] = lane;
+      B.nbm[lane] = x;
+    }
+    wave_fence();
+    // the neighbours become a clique: OR the pivot's live row into theirs
+    const int npair = k * nnzw;
+    for (int q0 = 0; q0 < npair; q0 += 64) {
+      const int qq = q0 + lane;
+      if (qq < npair) {
+        const int i = qq / nnzw, j = qq - i * nnzw;
+        const int u = B.nbl[i], w = B.nzw[j];
+        uint32_t* ru = B.rows + (long long)u * W;
+        const uint32_t old = ru[w];
+        uint32_t nv = old | B.nbm[w];
+        if (w == (u >> 5)) nv &= ~(1u << (u & 31));
+        ru[w] = nv;
+        const int added = popc32(nv & ~old);
+        if (added) atomicAdd(&B.acc[i], added);
+      }
+    }
+    wave_fence();
+    for (int i = lane; i < k; i += 64) {
+      const int u = B.nbl[i];
+      const uint32_t deg = (B.key[u] >> 16) + B.acc[i] - 1;
+      B.key[u] = (deg << 16) | (uint32_t)u;
+    }
+    wave_fence();
+    // groups to refresh: the pivot's, and those of its nonzero words
+    uint64_t dg = 1ull << (p >> 6);
+    for (uint64_t b = nzm; b; b &= b - 1) dg |= 1ull << (__builtin_ctzll(b) >> 1);
+    while (dg) {
+      int gs[4];
+#pragma unroll
+      for (int r = 0; r < 4; r++) {
+        gs[r] = dg ? __builtin_ctzll(dg) : -1;
+        if (dg) dg &= dg - 1;
+      }
+      const int g = row == 0 ? gs[0] : row == 1 ? gs[1] : row == 2 ? gs[2] : gs[3];
+      uint32_t kk = FP_KEY_INF;
+      if (g >= 0) {
+        const int b = g * 64 + q * 4;
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+          if (b + a < B.m) kk = min(kk, B.key[b + a]);
+      }
+      const int I = -1;  // identity of the unsigned minimum
+      kk = min(kk, (uint32_t)dpp_shr((int)kk, I, 1));
+      kk = min(kk, (uint32_t)dpp_shr((int)kk, I, 2));
+      kk = min(kk, (uint32_t)dpp_shr((int)kk, I, 4));
+      kk = min(kk, (uint32_t)dpp_shr((int)kk, I, 8));
+#pragma unroll
+      for (int r = 0; r < 4; r++) {  // lane 15 of row r holds group gs[r]'s minimum
+        const uint32_t v = (uint32_t)wave_bcast((int)kk, 16 * r + 15);
+        if (gs[r] >= 0 && lane == gs[r]) gm = v;
+      }
+    }
+  }
+  md_map_order(M, vmap, B.m, pos0, nsteps);
+}
+
 __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, gptr<const int> vmap, int pos0,
                                            int nsteps) {
+  if (B.W <= 64) {
+    md_bit_run64(M, B, vmap, pos0, nsteps);
+    return;
+  }
   const int lane = lane_id();
   const int W = B.W;
   for (int s = 0; s < nsteps; s++) {
