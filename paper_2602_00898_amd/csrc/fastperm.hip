@@ -451,13 +451,15 @@ __device__ __forceinline__ void wg_level_barrier() {
   __syncthreads();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
-// Levels of a BFS launched one by one before the tail takes over: about
-// twice the radius of a patch of S vertices on a triangle mesh, at most 64;
-// the distance BFS of Lloyd's step runs inside patches (half).
+// Levels of a BFS launched one by one before the tail takes over: one and a
+// half times the side of a patch of S vertices on a triangle mesh, plus six,
+// at most 64 (the growth from hashed seeds on the 1024 x 1024 torus at
+// S = 512 takes 34 levels, the regrowth after Lloyd's step 27); the distance
+// BFS of Lloyd's step runs inside patches (the side plus four).
 __host__ __device__ __forceinline__ int fp_bfs_levels(int n, int S, bool inner) {
   int r = 1;
   while ((long long)r * r < (long long)S && r < 64) r++;
-  const int L = (inner ? r : 2 * r) + 4;
+  const int L = inner ? r + 4 : (3 * r) / 2 + 6;
   return L < 64 ? (L < n ? L : n) : (64 < n ? 64 : n);
 }
 __global__ void __launch_bounds__(1024) k_bfs_tail(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int inner) {
@@ -1144,12 +1146,8 @@ __global__ void __launch_bounds__(FP_WG) k_refine(const FpMesh* __restrict__ fp_
 // the expected depth, which only inputs with more patches than ⌈n/S⌉ (orphan
 // components, more user groups) reach; for every other input it returns at
 // once, one launch instead of five.
-__global__ void __launch_bounds__(FP_WG) k_level_wg(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d,
-                                                    int lds_bytes) {
-  MESH_WG;
-  __shared__ BisectLds sh;
-  FP_LDS_DECL;
-  if (d >= C->D) return;
+__device__ __forceinline__ void level_wg(const FpMesh& M, gptr<FpCtl> C, int d, BisectLds& sh,
+                                         char* fp_lds, int lds_bytes) {
   const int i0 = (int)threadIdx.x, di = (int)blockDim.x;
   wg_level_barrier();
   lv_begin(M, C, d, i0, di);
@@ -1175,6 +1173,21 @@ __global__ void __launch_bounds__(FP_WG) k_level_wg(const FpMesh* __restrict__ f
     for (int t = lo; t < hi; t++) wg_refine_node(M, C, t, rsh);
   } else {
     lv_mark(M, C, d, i0, di);
+  }
+}
+// every level past the expected depth of the mesh, in turn (one launch)
+__global__ void __launch_bounds__(FP_WG) k_level_wg(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm,
+                                                    int lds_bytes) {
+  MESH0;
+  __shared__ BisectLds sh;
+  __shared__ unsigned go;
+  FP_LDS_DECL;
+  for (int d = M.dexp + 1;; d++) {
+    __syncthreads();
+    if (threadIdx.x == 0) go = C->err == 0 && d < C->D;
+    __syncthreads();
+    if (!go) return;
+    level_wg(M, C, d, sh, fp_lds, lds_bytes);
   }
 }
 // leaves keep the remaining vertices of their patch
@@ -1469,16 +1482,28 @@ __global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ f
 // expected depth: initialisation, prep, elimination of the three classes and
 // emission in turn, with a barrier between steps; wave w takes nodes w, w+4,
 // ... in every step, and wave 0 the large-LDS class with all of the LDS.
-__global__ void __launch_bounds__(FP_WG) k_sym_level_wg(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+// every level past the expected depth of the mesh, deepest first (one
+// launch); the error word and depth are shared through the dynamic LDS (the
+// large class takes all of it, so no static LDS here)
+__device__ __forceinline__ void sym_level_wg(const FpMesh& M, gptr<FpCtl> C, int d, char* fp_lds);
+__global__ void __launch_bounds__(FP_WG) k_sym_level_wg(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH0;
   FP_LDS_DECL;
-  // the error word shared through the dynamic LDS (the large class below
-  // takes all of it, so no static LDS here)
-  if (threadIdx.x == 0) *(unsigned*)fp_lds = C->err;
+  if (threadIdx.x == 0) *(int*)fp_lds = C->err ? -1 : C->D;
   __syncthreads();
-  const unsigned err = *(volatile unsigned*)fp_lds;
+  const int D = *(volatile int*)fp_lds;
   __syncthreads();
-  if (err || d > C->D) return;
+  for (int d = D; d > M.dexp; d--) {
+    if (threadIdx.x == 0) *(unsigned*)fp_lds = C->err;
+    __syncthreads();
+    const unsigned err = *(volatile unsigned*)fp_lds;
+    __syncthreads();
+    if (err) return;
+    sym_level_wg(M, C, d, fp_lds);
+    wg_level_barrier();
+  }
+}
+__device__ __forceinline__ void sym_level_wg(const FpMesh& M, gptr<FpCtl> C, int d, char* fp_lds) {
   if (threadIdx.x == 0) {
     C->arena_top[d & 1] = 0;
     C->pool_top = 0;
@@ -1687,12 +1712,9 @@ MeshPlan mesh_plan(const FpMesh& M, bool user) {
   m.P0 = fp_p0(M.n, M.S);
   m.Pexp = std::max(m.P0, 1);
   m.Dpat = ceil_log2(m.Pexp);
-  m.Dexp = m.Dpat;
+  m.Dexp = M.dexp;  // ceil(log2 Pexp), at most nd_level
   m.Dmax = ceil_log2(std::max(M.n, 1));
-  if (M.nd_level >= 0) {
-    m.Dexp = std::min(m.Dexp, M.nd_level);
-    m.Dmax = std::min(m.Dmax, M.nd_level);
-  }
+  if (M.nd_level >= 0) m.Dmax = std::min(m.Dmax, M.nd_level);
   m.NNcap = M.NNcap;
   m.Lg = fp_bfs_levels(M.n, M.S, false);
   m.Ld = fp_bfs_levels(M.n, M.S, true);
@@ -2029,9 +2051,7 @@ fp_status run_pipe(Pipe& P) {
           T, 0, st, d);
       FPG("k_refine", k_refine, ref(std::min(1 << std::min(d, 30), 4 * P.ncu())), T, 0, st, d);
       FPG("k_mark", k_mark, lvl(d, 0), T, 0, st, d);
-      FPG("k_level_wg", k_level_wg,
-          [&, d](int i) -> long long { return d < mp[i].Dmax && !in_launches(d, i) ? 1 : 0; }, T,
-          lb, st, d, lb);
+
     }
     if (d < TL) {
       const long long b = P.blk(mp[0].n);
@@ -2051,6 +2071,12 @@ fp_status run_pipe(Pipe& P) {
       FPG("k_md_top", k_md_top, [&, d](int) { return 1ll << d; }, dim3(64), P.h->lds_md, sd, d);
     }
     P.check();
+  }
+  {
+    // levels past the expected depth, in one workgroup per mesh
+    const int lbw = P.h->lds_big - 1024;
+    FPG("k_level_wg", k_level_wg,
+        [&](int i) -> long long { return mp[i].Dmax > mp[i].Dexp + 1 ? 1 : 0; }, T, lbw, st, lbw);
   }
   FPG("k_leaves", k_leaves, per_n, T, 0, st);
 
@@ -2108,6 +2134,9 @@ fp_status run_pipe(Pipe& P) {
   P.scan(FA_PCNT, FA_PROW, FN_N, FT_TOT);
   FPG("k_set", k_mptr_end, one, dim3(64), 0, st, (int)FA_PROW, (int)FN_N, (int)FT_TOT);
   FPG("k_prow_fill", k_prow_fill, per_n, T, 0, st);
+  // levels past the expected depth first, in one workgroup per mesh
+  FPG("k_sym_level_wg", k_sym_level_wg,
+      [&](int i) -> long long { return mp[i].Dmax > mp[i].Dexp ? 1 : 0; }, T, P.h->lds_big, st);
   for (int d = Dmax; d >= 0; d--) {
     const int cnt = 1 << d;
     // separate launches up to the expected depth, one workgroup past it
@@ -2126,9 +2155,6 @@ fp_status run_pipe(Pipe& P) {
     FPG("k_sym_elim", k_sym_elim, G1, T, P.h->lds_big, st, d, 1);
     FPG("k_sym_elim_glb", k_sym_elim_glb, G, T, 0, st, d);
     FPG("k_sym_emit", k_sym_emit, G, T, 0, st, d);
-    FPG("k_sym_level_wg", k_sym_level_wg,
-        [&, d](int i) -> long long { return d <= mp[i].Dmax && d > mp[i].Dexp ? 1 : 0; }, T,
-        P.h->lds_big, st, d);
     P.check();
   }
   FPG("k_nnzl", k_nnzl, [&](int i) { return std::min(P.blk(mp[i].n), 2ll * P.ncu()); }, T, 0, st);
@@ -2331,6 +2357,11 @@ fp_status describe(fp_handle* h, const fp_csr* A, const int32_t* user_gmap,
   M->seed = opts->seed;
   M->validate = (opts->flags & FP_FLAG_VALIDATE) != 0;
   M->nd_level = opts->nd_level;
+  {  // expected tree depth: ceil(log2 P0), at most nd_level
+    int dx = 0;
+    while ((1ll << dx) < std::max(fp_p0(M->n, opts->patch_size), 1)) dx++;
+    M->dexp = opts->nd_level >= 0 ? std::min(dx, opts->nd_level) : dx;
+  }
   M->refine = (opts->flags & FP_FLAG_REFINE) != 0;
   M->amd = (opts->flags & FP_FLAG_AMD) != 0;
   M->perm = out->perm;

@@ -140,6 +140,7 @@ struct FpMesh {
   unsigned long long seed;
   int validate;   // check that the pattern is symmetric
   int nd_level;   // -1: full tree depth; else at most this many levels
+  int dexp;       // expected tree depth (levels past it run in one workgroup)
   int refine;     // separators: 0 one side's candidates, 1 minimum cover
   int amd;        // local orders: 0 exact minimum degree, 1 approximate
   // outputs (device; optional ones may be null)
