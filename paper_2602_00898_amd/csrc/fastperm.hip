@@ -1852,28 +1852,53 @@ struct Pipe {
 
 #define FPG(...) P.go(__VA_ARGS__)
 
-// The side stream and its events, created on first use: every stream takes
-// one of the device's hardware queues in turn, so a handle that never uses
-// it (a lane of the served calls) should not hold one.
+// The side streams: three per device for the whole process, shared by every
+// handle on that device and created on first use.  A device has few hardware
+// queues (four by default) and every stream takes one of them in turn; once
+// a process holds more streams than queues, two streams can share a queue and
+// then run one after the other, so handles that each created their own side
+// streams (and streams made by others in between) would lose the overlap of
+// the top separators' local orders with the rest of the pipeline.  A
+// handle's events stay its own, so handles on several host threads can share
+// the streams (their work interleaves in stream order, with no cross-handle
+// waits).
+struct FpSideStreams {
+  bool ok = false;
+  hipStream_t s[3] = {nullptr, nullptr, nullptr};
+};
+static std::mutex fp_side_mu;
+static FpSideStreams fp_side[FP_MAX_DEVICES];
+
 bool ensure_side(fp_handle* h) {
   if (h->side) return true;
-  hipStream_t s[3] = {nullptr, nullptr, nullptr};
-  int ns = 0;
-  while (ns < 3 && hipStreamCreateWithFlags(&s[ns], hipStreamNonBlocking) == hipSuccess) ns++;
+  if (h->device < 0 || h->device >= FP_MAX_DEVICES) return false;
+  {
+    std::lock_guard<std::mutex> lk(fp_side_mu);
+    FpSideStreams& S = fp_side[h->device];
+    if (!S.ok) {
+      int ns = 0;
+      while (ns < 3 && hipStreamCreateWithFlags(&S.s[ns], hipStreamNonBlocking) == hipSuccess) ns++;
+      if (ns < 3) {
+        for (int j = 0; j < ns; j++) (void)hipStreamDestroy(S.s[j]);
+        (void)hipGetLastError();
+        return false;
+      }
+      S.ok = true;
+    }
+  }
   hipEvent_t* ev[7] = {&h->ev_top[0], &h->ev_top[1], &h->ev_top[2], &h->ev_join,
                        &h->ev_md,     &h->ev_join2,  &h->ev_join3};
   int ne = 0;
-  while (ns == 3 && ne < 7 && hipEventCreateWithFlags(ev[ne], hipEventDisableTiming) == hipSuccess)
-    ne++;
-  if (ns < 3 || ne < 7) {
+  while (ne < 7 && hipEventCreateWithFlags(ev[ne], hipEventDisableTiming) == hipSuccess) ne++;
+  if (ne < 7) {
     for (int j = 0; j < ne; j++) (void)hipEventDestroy(*ev[j]);
-    for (int j = 0; j < ns; j++) (void)hipStreamDestroy(s[j]);
     (void)hipGetLastError();
     return false;
   }
-  h->side = s[0];
-  h->side2 = s[1];
-  h->side3 = s[2];
+  const FpSideStreams& S = fp_side[h->device];
+  h->side = S.s[0];
+  h->side2 = S.s[1];
+  h->side3 = S.s[2];
   return true;
 }
 
@@ -2287,10 +2312,9 @@ fp_status fp_create(fp_handle** h) {
 fp_status fp_destroy(fp_handle* h) {
   if (!h) return FP_OK;
   if (h->side) {
-    for (hipStream_t s : {h->side, h->side2, h->side3}) {
-      (void)hipStreamSynchronize(s);
-      (void)hipStreamDestroy(s);
-    }
+    // the streams are shared by the device's handles and stay; this
+    // handle's work on them is done before its events go
+    for (hipEvent_t e : {h->ev_join, h->ev_join2, h->ev_join3}) (void)hipEventSynchronize(e);
     for (int i = 0; i < 3; i++) (void)hipEventDestroy(h->ev_top[i]);
     for (hipEvent_t e : {h->ev_join, h->ev_md, h->ev_join2, h->ev_join3}) (void)hipEventDestroy(e);
   }
@@ -2689,10 +2713,36 @@ fp_status fp_graph_create(fp_handle* h, int32_t n_mesh, const fp_csr* A,
       return FP_ERR_HIP;
   }
   // streams and events of the pipeline exist before recording starts; the
+  // recording uses streams of its own (the device's shared side streams may
+  // carry other handles' work meanwhile), which the graph does not keep; the
   // kernel timing switch is off while recording
-  if (h->side_ok) (void)ensure_side(h);
+  hipStream_t rec[3] = {nullptr, nullptr, nullptr}, shared[3] = {h->side, h->side2, h->side3};
+  const bool side = h->side_ok && ensure_side(h);
+  if (side) {
+    shared[0] = h->side;
+    shared[1] = h->side2;
+    shared[2] = h->side3;
+    for (int j = 0; j < 3; j++)
+      if (hipStreamCreateWithFlags(&rec[j], hipStreamNonBlocking) != hipSuccess) {
+        for (int q = 0; q < j; q++) (void)hipStreamDestroy(rec[q]);
+        return FP_ERR_HIP;
+      }
+    h->side = rec[0];
+    h->side2 = rec[1];
+    h->side3 = rec[2];
+  }
+  auto restore = [&]() {
+    if (!side) return;
+    h->side = shared[0];
+    h->side2 = shared[1];
+    h->side3 = shared[2];
+    for (int j = 0; j < 3; j++) (void)hipStreamDestroy(rec[j]);
+  };
   hipStream_t cs = nullptr;
-  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return FP_ERR_HIP;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    restore();
+    return FP_ERR_HIP;
+  }
   char tk_saved[sizeof(h->tk_name)];
   memcpy(tk_saved, h->tk_name, sizeof(tk_saved));
   h->tk_name[0] = 0;
@@ -2700,6 +2750,7 @@ fp_status fp_graph_create(fp_handle* h, int32_t n_mesh, const fp_csr* A,
   if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipStreamDestroy(cs);
     memcpy(h->tk_name, tk_saved, sizeof(tk_saved));
+    restore();
     return FP_ERR_HIP;
   }
   s = n_mesh == 1 ? order_impl(h, A, user_gmap ? user_gmap[0] : nullptr, opts, workspace,
@@ -2708,6 +2759,7 @@ fp_status fp_graph_create(fp_handle* h, int32_t n_mesh, const fp_csr* A,
   const hipError_t ec = hipStreamEndCapture(cs, &graph);
   memcpy(h->tk_name, tk_saved, sizeof(tk_saved));
   (void)hipStreamDestroy(cs);
+  restore();
   if (s == FP_OK && (ec != hipSuccess || !graph)) s = FP_ERR_HIP;
   hipGraphExec_t exec = nullptr;
   if (s == FP_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess)
