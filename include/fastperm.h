@@ -361,11 +361,15 @@ fp_status fp_graph_destroy(fp_graph* g);
 
 /* ---------------------------------------------------------------------
  * Serving: a request loop that admits ordering requests of any size while
- * others run.  A request is admitted (first come, first served) when one of
- * max_slots worker slots is free and its device footprint (input copy,
- * workspace, outputs) fits in what is left of hbm_budget bytes of device
- * memory, which the server allocates once at creation and keeps; the
- * requests in flight overlap on the device, each on its own stream.
+ * others run.  A request is admitted when one of max_slots worker slots is
+ * free and its device footprint (input copy, workspace, outputs) fits in
+ * what is left of hbm_budget bytes of device memory, which the server
+ * allocates once at creation and keeps; the requests in flight overlap on
+ * the device, each on its own stream.  Admission takes the oldest request
+ * that fits among the 64 oldest waiting, so small requests need not queue
+ * behind a large one that waits for memory; a request passed over 32 times
+ * stops every later one until it fits.  Options as for fp_order (the
+ * timing flag is ignored).
  * Inputs are HOST arrays; they must stay valid until fp_server_wait returns
  * for the ticket.  Results are the same as fp_order's for the matrix alone.
  */

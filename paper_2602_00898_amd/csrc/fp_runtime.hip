@@ -61,6 +61,7 @@ struct FpRequest {
   size_t bytes;  // device footprint
   size_t off;    // offset in the arena while in flight
   std::chrono::steady_clock::time_point t_submit, t_done;
+  int bypassed;  // later requests admitted ahead of this one
   bool done;
   fp_status status;
   int64_t nnzL;
@@ -134,8 +135,25 @@ struct fp_server {
 
 namespace {
 
-// one slot: admit the head of the queue when it fits, order it on this
-// slot's lane, copy the results back, release the memory
+// Admission: the oldest request that fits, looking at most FP_BYPASS_WINDOW
+// requests deep; a request that has been passed FP_BYPASS_MAX times blocks
+// every later one until it fits (so a large request waits for memory to
+// free up, but small ones need not queue behind it meanwhile).  Returns the
+// queue index to admit, or -1.  Called under the server lock.
+#define FP_BYPASS_WINDOW 64
+#define FP_BYPASS_MAX 32
+int pick_request(fp_server* S) {
+  const size_t lim = std::min<size_t>(S->queue.size(), FP_BYPASS_WINDOW);
+  for (size_t i = 0; i < lim; i++) {
+    FpRequest* r = S->queue[i];
+    if (S->arena.fits(r->bytes)) return (int)i;
+    if (r->bypassed >= FP_BYPASS_MAX) return -1;  // no one passes it any more
+  }
+  return -1;
+}
+
+// one slot: admit a request (pick_request), order it on this slot's lane,
+// copy the results back, release the memory
 void server_worker(fp_server* S, int w) {
   FpLane& L = S->lanes[w];
   const bool dev_ok = hipSetDevice(S->device) == hipSuccess;
@@ -143,17 +161,17 @@ void server_worker(fp_server* S, int w) {
     FpRequest* r = nullptr;
     {
       std::unique_lock<std::mutex> lk(S->mu);
+      int at = -1;
       S->cv.wait(lk, [&] {
-        return (S->stop && S->queue.empty()) ||
-               (!S->queue.empty() && S->arena.fits(S->queue.front()->bytes));
+        if (S->stop && S->queue.empty()) return true;
+        at = S->queue.empty() ? -1 : pick_request(S);
+        return at >= 0;
       });
-      if (S->queue.empty()) return;  // stopping
-      r = S->queue.front();
-      S->queue.pop_front();
-      if (!S->arena.alloc(r->bytes, &r->off)) {  // cannot happen: fits() held under the lock
-        S->queue.push_front(r);
-        continue;
-      }
+      if (at < 0) return;  // stopping
+      r = S->queue[at];
+      if (!S->arena.alloc(r->bytes, &r->off)) continue;  // cannot happen: it fit under the lock
+      for (int i = 0; i < at; i++) S->queue[i]->bypassed++;
+      S->queue.erase(S->queue.begin() + at);
     }
     fp_status st = dev_ok ? FP_OK : FP_ERR_HIP;
     const size_t n = (size_t)r->A.n, nnz = (size_t)std::max<int64_t>(r->A.nnz, 0);
@@ -263,10 +281,11 @@ fp_status fp_server_submit(fp_server* S, const fp_host_csr* A, const fp_options*
   if (!r) return FP_ERR_OOM;
   r->A = *A;
   r->o = *opts;
-  r->o.flags &= FP_FLAG_VALIDATE;  // no per-stage timing inside the server
+  r->o.flags &= ~FP_FLAG_TIMING;  // no per-stage timing inside the server
   r->ws_bytes = ws;
   r->bytes = request_bytes(*A, ws);
   r->done = false;
+  r->bypassed = 0;
   r->status = FP_OK;
   r->nnzL = 0;
   if (r->bytes > S->budget) {

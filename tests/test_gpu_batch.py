@@ -167,3 +167,33 @@ def test_server_refuses_oversize_request():
         assert e.value.code == 7  # FP_ERR_BUSY
     finally:
         srv.close()
+
+
+def test_server_small_requests_pass_a_waiting_large_one():
+    """Under a budget that holds one large request but not two, the second
+    large request waits for memory while the small ones behind it are
+    admitted; every result still equals the oracle's."""
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+    big = [mesh(300, 280, True, 31, 0.05), mesh(290, 300, False, 32, 0.05)]
+    small = [mesh(30 + 3 * i, 28, True, 40 + i, 0.05) for i in range(6)]
+    h = fpm.Handle()
+    dev = torch.device("cuda:0")
+    rp = torch.from_numpy(big[0].rowptr).to(dev)
+    ci = torch.from_numpy(big[0].colind).to(dev)
+    ws, _ = fpm.query(h, big[0].n, rp, ci, fpm.options(128))
+    foot = ws + 40 * big[0].n + 8 * big[0].nnz  # about the server's own estimate
+    srv = fpm.Server(hbm_budget=int(1.6 * foot), max_slots=4)
+    try:
+        say("[server] 2 large + 6 small requests under a tight budget")
+        reqs = [(A, 128, 31 + i) for i, A in enumerate(big)] + [(A, 32, 50 + i) for i, A in enumerate(small)]
+        tickets = [srv.submit(A.rowptr, A.colind, A.n, patch_size=S, seed=s) for A, S, s in reqs]
+        for (A, S, s), tk in zip(reqs, tickets):
+            r = srv.wait(tk)
+            c = cpu_order(A, patch_size=S, seed=s)
+            for k in ("perm", "iperm", "parent", "colcount"):
+                assert np.array_equal(r[k], c[k]), f"server n={A.n}: {k}"
+            assert r["nnzL"] == c["nnzL"]
+    finally:
+        srv.close()
