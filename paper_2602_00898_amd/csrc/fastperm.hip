@@ -952,7 +952,6 @@ __global__ void k_mark(const FpMesh* __restrict__ fp_ms, const int* __restrict__
 // (Dulmage-Mendelsohn), so the parallel matching below, whose matching
 // depends on timing, still gives a unique separator.
 // --------------------------------------------------------------------------
-#define FP_REF_EP 256  // augmenting paths taken per phase (the rest wait)
 
 // exclusive scan of the level's candidate counts into roff/rcur (one
 // workgroup; sh: FP_WG ints of LDS)
@@ -987,20 +986,26 @@ __device__ __forceinline__ void lv_ref_scatter(const FpMesh& M, gptr<FpCtl> C, i
                                                int di) {
   (void)d;
   const int nb = C->nbnd;
-  for (int i = i0; i < nb; i += di) {
-    if (!M.cand[i]) continue;
-    const int v = M.bnd[i];
-    const int t = (M.pnode[M.gmap[v]] - 1) >> 1;
-    M.rlist[atomicAdd(&M.rcur[t], 1)] = v;
-    M.mate[v] = -1;
-    M.seen[v] = 0;
+  // lanes of a wave take consecutive entries (i0 is the lane's thread index,
+  // di a multiple of 64), so one atomic per node and wave suffices
+  for (int b = i0 - lane_id(); b < nb; b += di) {
+    const int i = b + lane_id();
+    const bool act = i < nb && M.cand[i];
+    const int v = act ? M.bnd[i] : 0;
+    const int t = act ? (M.pnode[M.gmap[v]] - 1) >> 1 : 0;
+    const int slot = wave_append_keyed(M.rcur, t, act);
+    if (act) {
+      M.rlist[slot] = v;
+      M.mate[v] = -1;
+      M.seen[v] = 0;
+    }
   }
 }
 // Node t by one workgroup: greedy matching, then phases of a breadth-first
 // search from all free s-vertices at once that stop at the first level with
 // free other-side vertices; one shortest augmenting path per search tree is
 // flipped (the trees are vertex-disjoint).  A phase that finds none has
-// reached exactly Z.  sh: (16 + FP_REF_EP) ints of LDS.
+// reached exactly Z.  sh: 16 ints of LDS.
 __device__ void wg_refine_node(const FpMesh& M, gptr<FpCtl> C, int t, int* sh) {
   const int k = M.cntL[t] + M.cntR[t];
   if (k == 0) return;
@@ -1061,8 +1066,11 @@ __device__ void wg_refine_node(const FpMesh& M, gptr<FpCtl> C, int t, int* sh) {
           M.rpar[u] = x;
           const int y = M.mate[u];
           if (y == -1) {
+            // endpoints fill the next frontier's buffer from its end: the
+            // s-vertices appended from the front and the free vertices
+            // reached are at most k together
             const int j = atomicAdd(&sh[2], 1);
-            if (j < FP_REF_EP) sh[16 + j] = u;
+            if (j < k) fb[k - 1 - j] = u;
           } else {
             M.seen[y] = stamp;
             M.rpar[y] = u;
@@ -1083,10 +1091,10 @@ __device__ void wg_refine_node(const FpMesh& M, gptr<FpCtl> C, int t, int* sh) {
       fb = tmp;
     }
     if (!ok) break;
-    const int nep = min(sh[2], FP_REF_EP);
+    const int nep = min(sh[2], k);
     if (nep == 0) break;  // no augmenting path: the last search reached Z
     for (int j = tid; j < nep; j += nt) {
-      const int end = sh[16 + j];
+      const int end = fb[k - 1 - j];
       // paths alternate: an other-side vertex's predecessor is an s-vertex,
       // an s-vertex's is the other-side vertex matched to it (or -1: root);
       // both walks are bounded by the node's size
@@ -1123,6 +1131,208 @@ __device__ void wg_refine_node(const FpMesh& M, gptr<FpCtl> C, int t, int* sh) {
   }
   wg_level_barrier();
 }
+// The same for a node small enough for one wave's LDS slice: the crossing
+// graph in local candidate indices (CSR), matching, search stamps and
+// predecessors all in LDS, each step wave-synchronous.  A candidate's local
+// index is kept in rpar[v] while the adjacency is built.  Words of LDS:
+// matching, stamps, predecessors, two frontiers and the endpoints of a
+// phase's augmenting paths (6k), offsets (k + 1), the crossing entries and
+// two counters.  Every phase flips one path per search tree that reached a
+// free vertex, all of them.
+__device__ __forceinline__ long long ref_wave_words(int k, long long ecross) {
+  return 7ll * k + 1 + ecross + 2;
+}
+// crossing entries of node t (the sum of its candidates' graph degrees
+// bounds them)
+__device__ __forceinline__ long long ref_deg_sum(const FpMesh& M, int t) {
+  const int k = M.cntL[t] + M.cntR[t], k0 = M.roff[t];
+  long long e = 0;
+  for (int i = lane_id(); i < k; i += 64) {
+    const int v = M.rlist[k0 + i];
+    e += M.grp[v + 1] - M.grp[v];
+  }
+  return wave_sum_i64(e);
+}
+__device__ void wave_refine_node(const FpMesh& M, gptr<FpCtl> C, int t, int* lds, long long ecap) {
+  const int k = uni(M.cntL[t] + M.cntR[t]);
+  const int k0 = uni(M.roff[t]);
+  const int lane = lane_id();
+  const int s_child = uni(M.cntL[t] <= M.cntR[t] ? 2 * t + 1 : 2 * t + 2);
+  const int o_child = (s_child & 1) ? s_child + 1 : s_child - 1;
+  const gptr<int> L = M.rlist + k0;
+  int* mate = lds;
+  int* seen = mate + k;
+  int* par = seen + k;
+  int* fr = par + k;       // two frontiers of k
+  int* ep = fr + 2 * k;    // k endpoints
+  int* off = ep + k;       // k + 1
+  int* adj = off + k + 1;  // ecap
+  int* cnt = adj + ecap;   // 2 counters
+  auto side_of = [&](int v) { return M.pnode[M.gmap[v]]; };
+  // local indices, then the crossing adjacency
+  for (int i = lane; i < k; i += 64) M.rpar[L[i]] = i;
+  wave_fence();
+  int run = 0;
+  for (int c = 0; c < k; c += 64) {
+    const int i = c + lane;
+    int n = 0;
+    if (i < k) {
+      const int v = L[i];
+      const int oth = side_of(v) == s_child ? o_child : s_child;
+      for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+        const int u = M.gci[e];
+        n += M.node_of[u] == -1 && side_of(u) == oth;
+      }
+    }
+    const int inc = wave_incl_scan(n);
+    if (i < k) off[i] = run + inc - n;
+    run += wave_bcast(inc, 63);
+  }
+  if (lane == 0) off[k] = run;
+  wave_fence();
+  for (int i = lane; i < k; i += 64) {
+    const int v = L[i];
+    const int oth = side_of(v) == s_child ? o_child : s_child;
+    int q = off[i];
+    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) {
+      const int u = M.gci[e];
+      if (M.node_of[u] == -1 && side_of(u) == oth) adj[q++] = M.rpar[u];
+    }
+    mate[i] = -1;
+    seen[i] = 0;
+  }
+  wave_fence();
+  auto s_loc = [&](int i) { return side_of(L[i]) == s_child; };
+  // greedy start
+  for (int i = lane; i < k; i += 64) {
+    if (!s_loc(i)) continue;
+    for (int q = off[i]; q < off[i + 1]; q++)
+      if (atomicCAS(&mate[adj[q]], -1, i) == -1) {
+        mate[i] = adj[q];
+        break;
+      }
+  }
+  wave_fence();
+  int stamp = 0;
+  bool ok = true;
+  while (true) {
+    if (++stamp > k + 2) {  // each phase grows the matching: never expected
+      ok = false;
+      break;
+    }
+    int* fa = fr;
+    int* fb = fr + k;
+    int nf = 0;
+    for (int c = 0; c < k; c += 64) {
+      const int i = c + lane;
+      const bool f = i < k && s_loc(i) && mate[i] == -1;
+      const uint64_t bal = ballot64(f);
+      if (f) {
+        seen[i] = stamp;
+        par[i] = -1;
+        fa[nf + popc64(bal & lanemask_lt())] = i;
+      }
+      nf += popc64(bal);
+    }
+    if (lane == 0) cnt[1] = 0;  // endpoints found
+    wave_fence();
+    int nep = 0;
+    while (nf > 0) {
+      if (lane == 0) cnt[0] = 0;
+      wave_fence();
+      for (int c = 0; c < nf; c += 64) {
+        const int f = c + lane;
+        if (f >= nf) continue;
+        const int x = fa[f];
+        const int mx = mate[x];
+        for (int q = off[x]; q < off[x + 1]; q++) {
+          const int j = adj[q];
+          if (j == mx) continue;
+          if (atomicMax(&seen[j], stamp) >= stamp) continue;  // reached already
+          par[j] = x;
+          const int y = mate[j];
+          if (y == -1) {
+            const int e = atomicAdd(&cnt[1], 1);
+            if (e < k) ep[e] = j;  // each free vertex once: never past k
+          } else {
+            seen[y] = stamp;
+            par[y] = j;
+            const int s2 = atomicAdd(&cnt[0], 1);
+            if (s2 < k) fb[s2] = y;  // at most once per s-vertex: never past k
+          }
+        }
+      }
+      wave_fence();
+      nep = uni(cnt[1]);
+      if (nep > 0) break;  // the shortest augmenting paths end at this level
+      nf = uni(cnt[0]);
+      if (nf > k) {
+        ok = false;
+        break;
+      }
+      int* tmp = fa;
+      fa = fb;
+      fb = tmp;
+    }
+    if (!ok) break;
+    nep = min(nep, k);
+    if (nep == 0) break;  // no augmenting path: the last search reached Z
+    for (int j = lane; j < nep; j += 64) {
+      const int end = ep[j];
+      int x = par[end], steps = 0;
+      while (x >= 0 && par[x] != -1 && steps++ <= k) x = par[par[x]];
+      if (x >= 0 && steps <= k && atomicCAS(&seen[x], stamp, -stamp) == stamp) {
+        steps = 0;
+        for (int u = end; u != -1 && steps++ <= k;) {
+          const int y = par[u];
+          const int next = par[y];
+          mate[u] = y;
+          mate[y] = u;
+          u = next;
+        }
+      } else if (x < 0 || steps > k) {
+        fp_fail(C, FP_E_INTERNAL, FP_SITE_REFINE, t);
+      }
+    }
+    wave_fence();
+  }
+  if (!ok) {
+    if (lane == 0) fp_fail(C, FP_E_INTERNAL, FP_SITE_REFINE, t);
+    return;
+  }
+  for (int i = lane; i < k; i += 64) {
+    const bool in_z = seen[i] == stamp;
+    if (s_loc(i) ? !in_z : in_z) {
+      const int v = L[i];
+      M.node_of[v] = t;
+      atomicSub(&M.wp[M.gmap[v]], 1);
+    }
+  }
+  wave_fence();
+}
+// Which path refines node t: 0 a wave with a quarter of the per-node LDS,
+// 1 a wave with the whole large LDS, 2 a workgroup in global memory.
+__device__ __forceinline__ int ref_path(const FpMesh& M, long long words) {
+  if (words <= M.lds_bytes / 4 / FP_WAVES) return 0;
+  return words <= M.lds_big / 4 ? 1 : 2;
+}
+// nodes of path cls (0: four waves per workgroup, 1: one wave per
+// workgroup of 64 threads), a wave each
+__global__ void __launch_bounds__(FP_WG) k_refine_w(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d, int cls) {
+  MESH;
+  FP_LDS_DECL;
+  if (d >= C->D || !M.refine) return;
+  const int lw = cls == 0 ? M.lds_bytes / 4 / FP_WAVES : M.lds_big / 4;
+  int* lds = (int*)fp_lds + (cls == 0 ? lw * wave_id() : 0);
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  for (int x = vw(fp_s); x < cnt; x += vn(fp_s)) {
+    const int t = lo + x;
+    const int k = uni(M.cntL[t] + M.cntR[t]);
+    if (k == 0) continue;
+    const long long ec = ref_deg_sum(M, t);
+    if (ref_path(M, ref_wave_words(k, ec)) == cls) wave_refine_node(M, C, t, lds, ec);
+  }
+}
 __global__ void __launch_bounds__(FP_WG) k_ref_place(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH_WG;
   __shared__ int sh[FP_WG];
@@ -1136,10 +1346,21 @@ __global__ void k_ref_scatter(const FpMesh* __restrict__ fp_ms, const int* __res
 }
 __global__ void __launch_bounds__(FP_WG) k_refine(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH_WG;
-  __shared__ int sh[16 + FP_REF_EP];
+  __shared__ int sh[16];
   if (d >= C->D || !M.refine) return;
   const int lo = (1 << d) - 1, hi = (2 << d) - 1;
-  for (int t = lo + fp_s.bx; t < hi; t += fp_s.gx) wg_refine_node(M, C, t, sh);
+  for (int t = lo + fp_s.bx; t < hi; t += fp_s.gx) {
+    // nodes that fit a wave's LDS were refined by k_refine_w
+    const int k = M.cntL[t] + M.cntR[t];
+    if (k == 0) continue;
+    long long ec = 0;
+    if (threadIdx.x < 64) ec = ref_deg_sum(M, t);
+    if (threadIdx.x == 0) sh[2] = ref_path(M, ref_wave_words(k, ec));
+    __syncthreads();
+    const int path = sh[2];
+    __syncthreads();
+    if (path == 2) wg_refine_node(M, C, t, sh);
+  }
 }
 // One tree level in one workgroup: the steps of the level's separate
 // launches in turn, with a barrier between steps.  Used for the levels past
@@ -2074,6 +2295,16 @@ fp_status run_pipe(Pipe& P) {
             return in_launches(d, i) && mp[i].refine ? P.blk(mp[i].n) : 0;
           },
           T, 0, st, d);
+      FPG("k_refine_w", k_refine_w,
+          [&, d](int i) -> long long {
+            return in_launches(d, i) && mp[i].refine
+                       ? std::max(1ll, std::min((1ll << std::min(d, 30)) / FP_WAVES + 1,
+                                                4ll * P.ncu()))
+                       : 0;
+          },
+          T, P.h->lds_bytes, st, d, 0);
+      FPG("k_refine_w", k_refine_w, ref(std::min(1 << std::min(d, 30), 2 * P.ncu())), dim3(64),
+          P.h->lds_big, st, d, 1);
       FPG("k_refine", k_refine, ref(std::min(1 << std::min(d, 30), 4 * P.ncu())), T, 0, st, d);
       FPG("k_mark", k_mark, lvl(d, 0), T, 0, st, d);
 
@@ -2257,6 +2488,8 @@ static int big_lds(int device) {
                           big) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_level_wg, hipFuncAttributeMaxDynamicSharedMemorySize,
                           big - 1024) != hipSuccess ||
+      hipFuncSetAttribute((const void*)k_refine_w, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          big) != hipSuccess ||
       hipFuncSetAttribute((const void*)k_sym_level_wg,
                           hipFuncAttributeMaxDynamicSharedMemorySize, big) != hipSuccess) {
     (void)hipGetLastError();
