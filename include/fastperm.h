@@ -148,7 +148,13 @@ const char* fp_status_str(fp_status s);
 void fp_options_default(fp_options* opts);
 
 /* Create / destroy a handle bound to the current HIP device.  The handle
- * owns device properties and the tuning table; fp_destroy(NULL) is a no-op. */
+ * owns device properties, execution settings and its events;
+ * fp_destroy(NULL) is a no-op.  The pipeline of one matrix forks work onto
+ * three internal streams that every handle of the device shares (created on
+ * first use, kept until the process ends), so the number of streams stays
+ * within the device's hardware queues however many handles exist; calls of
+ * several handles on several host threads stay correct and may wait on each
+ * other's work on those streams. */
 fp_status fp_create(fp_handle** h);
 fp_status fp_destroy(fp_handle* h);
 
