@@ -389,11 +389,13 @@ def _result(out):
                   int(out["node_begin"].numel()))
 
 
-def order_batch(meshes, *, handle=None, stream=None, check=True):
+def order_batch(meshes, *, handle=None, stream=None, check=True, outs=None):
     """Order many matrices in one call (fp_order_batch).  `meshes` is a list
     of dicts with device tensors rowptr, colind, the size n and optional
-    patch_size, seed, schedule, block_size, lloyd_iters, user_gmap.  Returns
-    one output dict per matrix, as order() does."""
+    patch_size, seed, schedule, block_size, lloyd_iters, nd_level, refine,
+    amd, user_gmap.  Returns one output dict per matrix, as order() does;
+    `outs` (the list an earlier call on the same matrices returned) is
+    reused instead of allocating new outputs."""
     L = lib()
     k = len(meshes)
     handle = handle or Handle()
@@ -403,7 +405,7 @@ def order_batch(meshes, *, handle=None, stream=None, check=True):
     O = (Options * k)()
     R = (Result * k)()
     G = (C.c_void_p * k)()
-    keep, outs = [], []
+    keep = []
     for i, m in enumerate(meshes):
         A[i] = make_csr(m["n"], m["rowptr"], m["colind"])
         O[i] = _mesh_options(m)
@@ -413,8 +415,16 @@ def order_batch(meshes, *, handle=None, stream=None, check=True):
     ws, mx = C.c_size_t(), C.c_int32()
     _check(L.fp_query_batch(handle.h, k, A, O, G, C.byref(ws), C.byref(mx)), "fp_query_batch")
     dev = meshes[0]["colind"].device
+    reuse = outs is not None
+    if reuse and len(outs) != k:
+        raise ValueError("outs must hold one output dict per matrix")
+    outs = list(outs) if reuse else []
     for i, m in enumerate(meshes):
-        outs.append(_alloc_out(m["n"], mx.value, m.get("block_size", 1), dev))
+        if reuse:
+            if outs[i]["perm"].numel() != m["n"] or outs[i]["node_begin"].numel() < mx.value:
+                raise ValueError(f"outs[{i}] does not fit matrix {i}")
+        else:
+            outs.append(_alloc_out(m["n"], mx.value, m.get("block_size", 1), dev))
         R[i] = _result(outs[i])
     wbuf = handle.workspace(ws.value, dev)
     s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream

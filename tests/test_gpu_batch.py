@@ -197,3 +197,24 @@ def test_server_small_requests_pass_a_waiting_large_one():
             assert r["nnzL"] == c["nnzL"]
     finally:
         srv.close()
+
+
+def test_batch_reuses_outputs():
+    """A second batch call on the outputs of the first (outs=) writes the
+    same results into them."""
+    import torch
+
+    from paper_2602_00898_amd import fastperm as fpm
+    cases = [(mesh(H, W, t, s, f), S, s) for H, W, t, s, f, S in MIX[:4]]
+    say("[batch] outputs reused")
+    h = fpm.Handle()
+    dm = _device_meshes(cases)
+    outs = fpm.order_batch(dm, handle=h)
+    for o in outs:
+        o["perm"].fill_(-1)
+        o["parent"].fill_(-7)
+    again = fpm.order_batch(dm, handle=h, outs=outs)
+    torch.cuda.synchronize()
+    assert all(a["perm"] is b["perm"] for a, b in zip(outs, again))
+    for (A, S, s), out in zip(cases, again):
+        compare(_to_dict(out, A), cpu_order(A, patch_size=S, seed=s), f"reused n={A.n}")
