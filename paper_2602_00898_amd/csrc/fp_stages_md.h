@@ -9,9 +9,9 @@
 //             pivot row are OR-ed into each neighbour row,
 //   SPARSE -- fixed-capacity rows of 16-bit local ids, for large nodes of
 //             low degree (separators are path-like); when the remaining
-//             vertices fit the BIT layout, or a row would overflow, the
-//             state is re-indexed (rank order kept, so tie-breaking is
-//             unchanged) into BIT form,
+//             vertices fit the BIT layout and a pivot has more than four
+//             neighbours, or a row would overflow, the state is re-indexed
+//             (rank order kept, so tie-breaking is unchanged) into BIT form,
 //   BITG   -- BIT layout in a global-memory pool, for nodes too big for LDS.
 // The pivot is the minimum of keys (degree << 16 | index) found through a
 // 64-ary min tree: per-64 group minima are refreshed only for groups whose
@@ -44,7 +44,7 @@ __device__ __forceinline__ int md_groups(int m) { return (m + 63) >> 6; }
 // LDS bytes of the BIT layout for m vertices
 __device__ __forceinline__ long long md_bit_bytes(int m) {
   const long long W = md_words(m), G = md_groups(m);
-  return 4ll * m * W + 12ll * W + 12ll * m + 12ll * G + 64;
+  return 4ll * m * W + 12ll * W + 8ll * m + 12ll * G + 64;
 }
 __device__ __forceinline__ int md_bit_max(long long bytes) {
   int lo = 0, hi = FP_MD_MAXM;
@@ -65,7 +65,6 @@ struct MdBit {
   int* nzw;
   int* nbl;
   uint32_t* key;
-  int* acc;  // per neighbour of the pivot: bits its row gained
   uint32_t* gmin;
   int* dl;  // dirty groups: flags [0,G) then list [G,2G)
   int m, W, G;
@@ -87,8 +86,6 @@ __device__ __forceinline__ void md_bit_carve(MdBit& B, char* mem, int m) {
   B.nbl = (int*)p;
   p += 4ll * m;
   B.key = (uint32_t*)p;
-  p += 4ll * m;
-  B.acc = (int*)p;
   p += 4ll * m;
   B.gmin = (uint32_t*)p;
   p += 4 * B.G;
@@ -158,18 +155,20 @@ __device__ __forceinline__ void md_map_order(const FpMesh& M, gptr<const int> vm
 // pos0, pos0+1, ...
 //
 // Rows of at most 64 words (m <= 2048, so at most 32 groups): the group
-// minima live in registers (lane g holds group g's), lane w holds word w of
-// the pivot's live row, the neighbours are listed from the lanes' bits with
-// one prefix sum, and the clique update takes one lane per (neighbour,
-// nonzero word) pair, the bits each neighbour's row gains summed with LDS
-// atomics.  The groups to refresh are those of the pivot's nonzero words (a
-// group is two words) and the pivot's own; each 16-lane row of the wave
+// minima and the live set live in registers (lane g holds group g's
+// minimum, lane w word w of the live set), lane w holds word w of the
+// pivot's live row, the neighbours are listed from the lanes' bits with one
+// prefix sum, and the clique update takes one lane per (neighbour, nonzero
+// word) pair, each adding the bits it set to the neighbour's key with one
+// LDS atomic.  The groups to refresh are those of the pivot's nonzero words
+// (a group is two words) and the pivot's own; each 16-lane row of the wave
 // refreshes one of them.
 __device__ __forceinline__ void md_bit_run64(const FpMesh& M, MdBit& B, gptr<const int> vmap,
                                              int pos0, int nsteps) {
   const int lane = lane_id();
   const int W = B.W, G = B.G;
   uint32_t gm = lane < G ? B.gmin[lane] : FP_KEY_INF;
+  uint32_t aw = lane < W ? B.alive[lane] : 0u;  // lane w holds word w of the live set
   const int row = lane >> 4, q = lane & 15;
   for (int s = 0; s < nsteps; s++) {
     const uint32_t km = wave_min_u32(gm);
@@ -181,12 +180,12 @@ __device__ __forceinline__ void md_bit_run64(const FpMesh& M, MdBit& B, gptr<con
     }
     if (lane == 0) {
       M.vperm[pos0 + s] = p;
-      B.alive[p >> 5] &= ~(1u << (p & 31));
       B.key[p] = FP_KEY_INF;
     }
+    if (lane == (p >> 5)) aw &= ~(1u << (p & 31));
     wave_fence();
     const uint32_t* rp = B.rows + (long long)p * W;
-    const uint32_t x = lane < W ? (rp[lane] & B.alive[lane]) : 0u;
+    const uint32_t x = lane < W ? (rp[lane] & aw) : 0u;
     const uint64_t nzm = ballot64(x != 0u);
     const int nnzw = popc64(nzm);
     const int c = popc32(x);
@@ -199,7 +198,6 @@ __device__ __forceinline__ void md_bit_run64(const FpMesh& M, MdBit& B, gptr<con
         const int bit = __ffs(y) - 1;
         y &= y - 1;
         B.nbl[off] = lane * 32 + bit;
-        B.acc[off] = 0;
         off++;
       }
     }
@@ -220,15 +218,12 @@ __device__ __forceinline__ void md_bit_run64(const FpMesh& M, MdBit& B, gptr<con
         uint32_t nv = old | B.nbm[w];
         if (w == (u >> 5)) nv &= ~(1u << (u & 31));
         ru[w] = nv;
-        const int added = popc32(nv & ~old);
-        if (added) atomicAdd(&B.acc[i], added);
+        // u's degree gains the bits its row gained and loses p (counted
+        // once, on the pair of u's first word): one atomic on the key's
+        // degree field, exact in wrapping 32-bit arithmetic
+        const int d = popc32(nv & ~old) - (j == 0);
+        if (d) atomicAdd(&B.key[u], (uint32_t)d << 16);
       }
-    }
-    wave_fence();
-    for (int i = lane; i < k; i += 64) {
-      const int u = B.nbl[i];
-      const uint32_t deg = (B.key[u] >> 16) + B.acc[i] - 1;
-      B.key[u] = (deg << 16) | (uint32_t)u;
     }
     wave_fence();
     // groups to refresh: the pivot's, and those of its nonzero words
@@ -261,6 +256,7 @@ __device__ __forceinline__ void md_bit_run64(const FpMesh& M, MdBit& B, gptr<con
       }
     }
   }
+  if (lane < W) B.alive[lane] = aw;
   md_map_order(M, vmap, B.m, pos0, nsteps);
 }
 
@@ -573,36 +569,117 @@ __device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V
     // bucket sizes live in registers from here on: lane d counts degree d
     int creg = lane_id() <= C ? S.cnt[lane_id()] : 0;
     const int lane = lane_id();
-    while (na > 0 && na > mbit) {
+    while (na > 0) {
       // pivot: lowest vertex of the lowest non-empty degree bucket
       const uint64_t nz = ballot64(creg > 0);
       const int d = uni(nz ? (int)__builtin_ctzll(nz) : -1);
       int p = -1;
       if (d >= 0) {
+        // 128 words per round, both halves read at once
         const uint32_t* row = S.bk + (long long)d * S.MW;
-        for (int w0 = 0; w0 < S.MW; w0 += 64) {
-          const int w = w0 + lane;
-          const uint32_t x = w < S.MW ? row[w] : 0u;
-          const uint64_t b = ballot64(x != 0u);
-          if (b) {
-            const int l = __builtin_ctzll(b);
-            p = (w0 + l) * 32 + __ffs(wave_bcast_u32(x, l)) - 1;
+        for (int w0 = 0; w0 < S.MW; w0 += 128) {
+          const int wa = w0 + lane, wb = w0 + 64 + lane;
+          const uint32_t xa = wa < S.MW ? row[wa] : 0u;
+          const uint32_t xb = wb < S.MW ? row[wb] : 0u;
+          const uint64_t ba = ballot64(xa != 0u);
+          if (ba) {
+            const int l = __builtin_ctzll(ba);
+            p = (w0 + l) * 32 + __ffs(wave_bcast_u32(xa, l)) - 1;
+            break;
+          }
+          const uint64_t bb = ballot64(xb != 0u);
+          if (bb) {
+            const int l = __builtin_ctzll(bb);
+            p = (w0 + 64 + l) * 32 + __ffs(wave_bcast_u32(xb, l)) - 1;
             break;
           }
         }
       }
       p = uni(p);
-      if (p < 0 || p >= m || uni((int)S.len[p]) != d) {  // never expected: stop before any wild index
+      // p's row and length are read together, before the check (the
+      // address clamped to row 0 until p is known to be in range)
+      const int pc = p >= 0 && p < m ? p : 0;
+      const uint16_t* rpv = S.rows + (long long)pc * C;
+      const int rpl0 = lane < 8 ? (int)rpv[min(lane, C - 1)] : -1;
+      const int lenp = uni((int)S.len[pc]);
+      if (p < 0 || p >= m || lenp != d) {  // never expected: stop before any wild index
         if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
         md_map_order(M, vmap, m, pos0, done);
         goto fail;
       }
       const int kp = d;
-      const uint16_t* rpv = S.rows + (long long)p * C;
-      if (kp <= 8) {
+      // dense steps once the rest fits the slice and the pivots have more
+      // than four neighbours (the dense layout starts over from p)
+      if (na <= mbit && kp > 4) break;
+      if (kp <= 4) {
+        // One 16-lane row per neighbour u of p; a lane covers the slots
+        // q = lane % 16 + 16 s of u's row.  p's neighbours sit in scalar
+        // registers, each row's result gathers in its lane 15.
+        const int rpl = lane < kp ? rpl0 : -1;
+        int rp[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) rp[a] = wave_bcast(rpl, a);
+        const int g = lane >> 4, q0 = lane & 15;
+        const int u = g == 0 ? rp[0] : g == 1 ? rp[1] : g == 2 ? rp[2] : rp[3];
+        const bool act = g < kp;
+        const uint16_t* ru = S.rows + (long long)(act ? u : 0) * C;
+        const int x0 = (int)ru[min(q0, C - 1)];
+        const int lu = act ? (int)S.len[u] : 0;
+        uint32_t pk = 0u;
+        for (int q = q0; q < lu; q += 16) {
+          const int x = q == q0 ? x0 : (int)ru[q];
+#pragma unroll
+          for (int a = 0; a < 4; a++)
+            if (a < kp && x == rp[a]) pk |= 1u << a;
+          if (x == p) pk |= (uint32_t)(q + 1) << 8;
+          if (q == lu - 1) pk |= (uint32_t)x << 16;
+        }
+        pk |= (uint32_t)dpp_shr((int)pk, 0, 1);
+        pk |= (uint32_t)dpp_shr((int)pk, 0, 2);
+        pk |= (uint32_t)dpp_shr((int)pk, 0, 4);
+        pk |= (uint32_t)dpp_shr((int)pk, 0, 8);
+        const bool lead = act && q0 == 15;  // lane 16g+15 holds group g's result
+        const uint32_t missing = ((1u << kp) - 1u) & ~pk & ~(1u << g);
+        const int hole = (int)((pk >> 8) & 0xFFu) - 1;
+        const int nl = lu - 1 + __popc(missing);
+        if (ballot64(lead && hole < 0)) {  // p missing from a neighbour's row
+          if (lane == 0) fp_fail(M.ctl, FP_E_INTERNAL, FP_SITE_MD_PIVOT_SP, t);
+          md_map_order(M, vmap, m, pos0, done);
+          goto fail;
+        }
+        if (ballot64(lead && nl > C)) break;  // convert with p still present
+        if (lane == 0) {
+          M.vperm[pos0 + done] = p;  // local index; mapped below
+          atomicAnd(&S.alive[p >> 5], ~(1u << (p & 31)));
+          atomicAnd(&S.bk[(long long)d * S.MW + (p >> 5)], ~(1u << (p & 31)));
+        }
+        if (lead) {
+          uint16_t* rw = S.rows + (long long)u * C;
+          if (hole != lu - 1) rw[hole] = (uint16_t)(pk >> 16);
+#pragma unroll
+          for (int a = 0; a < 4; a++)
+            if ((missing >> a) & 1u) rw[lu - 1 + __popc(missing & ((1u << a) - 1u))] = (uint16_t)rp[a];
+          S.len[u] = (uint16_t)nl;
+          if (nl != lu) {
+            const uint32_t bit = 1u << (u & 31);
+            atomicAnd(&S.bk[(long long)lu * S.MW + (u >> 5)], ~bit);
+            atomicOr(&S.bk[(long long)nl * S.MW + (u >> 5)], bit);
+          }
+        }
+        creg -= lane == d;
+        // u of group a moves from bucket lu to bucket nl: both in one word
+        const int mv = lu | (nl << 16);
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+          if (a < kp) {
+            const int v = wave_bcast(mv, 16 * a + 15);
+            creg += (lane == (v >> 16)) - (lane == (v & 0xFFFF));
+          }
+        wave_fence();
+      } else if (kp <= 8) {
         // One group of 8 lanes per neighbour u of p; a lane covers the slots
         // q = lane % 8 + 8 s of u's row.  p's neighbours sit in registers.
-        const int rpl = lane < kp ? (int)rpv[lane] : -1;
+        const int rpl = lane < kp ? rpl0 : -1;
         int rp[8];  // p's neighbours (-1 past kp), in scalar registers
 #pragma unroll
         for (int a = 0; a < 8; a++) rp[a] = wave_bcast(rpl, a);
@@ -611,13 +688,16 @@ __device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V
 #pragma unroll
         for (int a = 0; a < 8; a++) u = g == a ? rp[a] : u;
         const bool act = g < kp;
+        // u's length and its slot q0 are read together (u = 0 for the
+        // groups past kp, whose length counts as 0)
+        const uint16_t* ru = S.rows + (long long)(act ? u : 0) * C;
+        const int x0 = (int)ru[min(q0, C - 1)];
         const int lu = act ? (int)S.len[u] : 0;
-        const uint16_t* ru = S.rows + (long long)u * C;
         // found bits (which neighbours of p u already has), the slot of p
         // (+1) and the value in u's last slot, packed for one OR reduction
         uint32_t pk = 0u;
         for (int q = q0; q < lu; q += 8) {
-          const int x = ru[q];
+          const int x = q == q0 ? x0 : (int)ru[q];
 #pragma unroll
           for (int a = 0; a < 8; a++)
             if (a < kp && x == rp[a]) pk |= 1u << a;
