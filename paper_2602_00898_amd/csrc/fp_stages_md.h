@@ -207,11 +207,14 @@ __device__ __forceinline__ void md_bit_run64(const FpMesh& M, MdBit& B, gptr<con
     }
     wave_fence();
     // the neighbours become a clique: OR the pivot's live row into theirs
-    const int npair = k * nnzw;
+    // pairs (i, j) at qq = i * 2^sh + j, the words padded to a power of two
+    // so no lane divides
+    const int sh = nnzw <= 1 ? 0 : 32 - __builtin_clz(nnzw - 1);
+    const int npair = k << sh;
     for (int q0 = 0; q0 < npair; q0 += 64) {
       const int qq = q0 + lane;
-      if (qq < npair) {
-        const int i = qq / nnzw, j = qq - i * nnzw;
+      const int i = qq >> sh, j = qq & ((1 << sh) - 1);
+      if (qq < npair && j < nnzw) {
         const int u = B.nbl[i], w = B.nzw[j];
         uint32_t* ru = B.rows + (long long)u * W;
         const uint32_t old = ru[w];
@@ -238,11 +241,16 @@ __device__ __forceinline__ void md_bit_run64(const FpMesh& M, MdBit& B, gptr<con
       }
       const int g = row == 0 ? gs[0] : row == 1 ? gs[1] : row == 2 ? gs[2] : gs[3];
       uint32_t kk = FP_KEY_INF;
-      if (g >= 0) {
-        const int b = g * 64 + q * 4;
+      {
+        // four keys per lane, all loads issued before the first use (the
+        // index clamped into the array, the values past m masked)
+        const int b = (g >= 0 ? g : 0) * 64 + q * 4;
+        uint32_t kv[4];
+#pragma unroll
+        for (int a = 0; a < 4; a++) kv[a] = B.key[min(b + a, B.m - 1)];
 #pragma unroll
         for (int a = 0; a < 4; a++)
-          if (b + a < B.m) kk = min(kk, B.key[b + a]);
+          if (g >= 0 && b + a < B.m) kk = min(kk, kv[a]);
       }
       const int I = -1;  // identity of the unsigned minimum
       kk = min(kk, (uint32_t)dpp_shr((int)kk, I, 1));
