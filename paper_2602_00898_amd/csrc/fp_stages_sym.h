@@ -386,9 +386,30 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
   // orders, child records hold positions of t or later
   {
     bool bad = b0 < 0 || m < 0 || e0 > M.n;
-    for (int k = lane_id(); k < m && !bad; k += 64) {
-      const int v = M.vperm[b0 + k];
-      bad = (unsigned)v >= (unsigned)M.n || M.viperm[v] != b0 + k;
+    if (!bad) {
+      // four columns per lane and round, every load of a round issued
+      // before the first use
+      for (int k0 = 0; k0 < m; k0 += 256) {
+        int v[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int k = k0 + lane_id() + 64 * u;
+          v[u] = k < m ? M.vperm[b0 + k] : 0;
+        }
+        int w[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int k = k0 + lane_id() + 64 * u;
+          const bool in = k < m && (unsigned)v[u] < (unsigned)M.n;
+          bad |= k < m && !in;
+          w[u] = in ? M.viperm[v[u]] : 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          const int k = k0 + lane_id() + 64 * u;
+          bad |= k < m && w[u] != b0 + k;
+        }
+      }
     }
     bad = ballot64(bad) != 0;
     int site = bad ? FP_SITE_SYM_VERTEX : 0;
@@ -449,17 +470,20 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
   // and t's ancestors, nearest first, occupy increasing positions.  Marking
   // the positions in a bitmap over the ancestors' ranges, concatenated in
   // that order, and reading the bitmap back gives them sorted and unique.
-  int na = 0;
-  long long B = 0;
-  for (int a = t; a > 0;) {
-    a = (a - 1) >> 1;
-    const int sz = uni(M.nsize[a]);
-    if (sz > 0) {
-      na++;
-      B += sz;
-    }
+  // lane i holds the i-th ancestor (nearest first): its size and start,
+  // read at once; the depth of t bounds their count
+  int dep = 0;
+  for (int a = t; a > 0; a = (a - 1) >> 1) dep++;
+  int asz = 0, abeg = 0;
+  if (lane_id() < dep) {
+    const int a = ((t + 1) >> (lane_id() + 1)) - 1;
+    asz = M.nsize[a];
+    abeg = M.nbegin[a];
   }
-  if (na > 32 || B > (1 << 29)) {
+  const uint64_t nzm = ballot64(lane_id() < dep && asz > 0);
+  const int na = popc64(nzm);
+  const long long B = wave_sum_i64(lane_id() < dep && asz > 0 ? (long long)asz : 0ll);
+  if (dep > 64 || na > 32 || B > (1 << 29)) {
     sym_drop(M, t, FP_SITE_SYM_RECORD);
     return;
   }
@@ -480,18 +504,15 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
   const int np2 = cap;  // capacity of the later-position list
   const SymView V = sym_view(base, m, np2, nfw, rows);
   int* anc = lds;  // per ancestor: begin, size, bit offset (at most 32 ancestors)
-  if (lane_id() == 0) {
-    int i = 0, off = 0;
-    for (int a = t; a > 0;) {
-      a = (a - 1) >> 1;
-      const int sz = M.nsize[a];
-      if (sz > 0) {
-        anc[3 * i] = M.nbegin[a];
-        anc[3 * i + 1] = sz;
-        anc[3 * i + 2] = off;
-        off += sz;
-        i++;
-      }
+  {
+    // the non-empty ancestors in order, their bit offsets by a prefix sum
+    const bool ne = lane_id() < dep && asz > 0;
+    const int i = popc64(nzm & lanemask_lt());
+    const int inc = wave_incl_scan(ne ? asz : 0);
+    if (ne) {
+      anc[3 * i] = abeg;
+      anc[3 * i + 1] = asz;
+      anc[3 * i + 2] = inc - asz;
     }
   }
   wave_fence();
