@@ -1432,13 +1432,38 @@ __global__ void k_nsize(const FpMesh* __restrict__ fp_ms, const int* __restrict_
     }
   }
 }
-__global__ void k_nsize_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
-  MESH;
-  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
-    const int v = v0 + lane_id();
-    const bool act = v < M.n;
-    (void)wave_append_keyed(M.nsize, act ? M.node_of[v] : 0, act);
+// Node sizes and the scatter into node ranges, one contiguous chunk of
+// vertices per workgroup: counts gather in an LDS histogram of the nodes
+// (hcap entries; past that, per-wave keyed appends), and each workgroup
+// adds its non-zero counts with one global atomic per node, so the top
+// separators, whose vertices run through every chunk, take one atomic per
+// workgroup instead of one per wave.
+__device__ __forceinline__ void chunk_of(const FpSlot& s, int n, int* v0, int* v1) {
+  const int ch = (n + s.gx - 1) / s.gx;
+  *v0 = min(n, s.bx * ch);
+  *v1 = min(n, *v0 + ch);
+}
+__global__ void __launch_bounds__(FP_WG) k_nsize_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int hcap) {
+  MESH_WG;
+  FP_LDS_DECL;
+  const int nn = C->nn;
+  int v0, v1;
+  chunk_of(fp_s, M.n, &v0, &v1);
+  if (nn > hcap) {
+    for (int b = v0 + (int)threadIdx.x - lane_id(); b < v1; b += (int)blockDim.x) {
+      const int v = b + lane_id();
+      const bool act = v < v1;
+      (void)wave_append_keyed(M.nsize, act ? M.node_of[v] : 0, act);
+    }
+    return;
   }
+  int* h = (int*)fp_lds;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int v = v0 + (int)threadIdx.x; v < v1; v += (int)blockDim.x) atomicAdd(&h[M.node_of[v]], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nn; i += blockDim.x)
+    if (h[i]) atomicAdd(&M.nsize[i], h[i]);
 }
 __global__ void k_sched_place(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
@@ -1454,14 +1479,33 @@ __global__ void k_nbegin(const FpMesh* __restrict__ fp_ms, const int* __restrict
     M.ncur[x] = b;
   }
 }
-__global__ void k_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
-  MESH;
-  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
-    const int v = v0 + lane_id();
-    const bool act = v < M.n;
-    const int slot = wave_append_keyed(M.ncur, act ? M.node_of[v] : 0, act);
-    if (act) M.gbuf[slot] = v;
+// (the order of a node's vertices in its range does not matter: the local
+// orders sort them by id)
+__global__ void __launch_bounds__(FP_WG) k_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int hcap) {
+  MESH_WG;
+  FP_LDS_DECL;
+  const int nn = C->nn;
+  int v0, v1;
+  chunk_of(fp_s, M.n, &v0, &v1);
+  if (nn > hcap) {
+    for (int b = v0 + (int)threadIdx.x - lane_id(); b < v1; b += (int)blockDim.x) {
+      const int v = b + lane_id();
+      const bool act = v < v1;
+      const int slot = wave_append_keyed(M.ncur, act ? M.node_of[v] : 0, act);
+      if (act) M.gbuf[slot] = v;
+    }
+    return;
   }
+  // this chunk's counts, then one reservation per node, then the slots
+  int* h = (int*)fp_lds;
+  for (int i = threadIdx.x; i < nn; i += blockDim.x) h[i] = 0;
+  __syncthreads();
+  for (int v = v0 + (int)threadIdx.x; v < v1; v += (int)blockDim.x) atomicAdd(&h[M.node_of[v]], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < nn; i += blockDim.x)
+    if (h[i]) h[i] = atomicAdd(&M.ncur[i], h[i]);
+  __syncthreads();
+  for (int v = v0 + (int)threadIdx.x; v < v1; v += (int)blockDim.x) M.gbuf[atomicAdd(&h[M.node_of[v]], 1)] = v;
 }
 
 // ==========================================================================
@@ -1527,14 +1571,18 @@ __global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ fp
   MESH_WG;
   const int nn = C->nn;
   __shared__ int hist[FP_MD_CLASSES * FP_TASK_BUCKETS];
+  __shared__ int cmax[FP_MD_CLASSES];  // largest node of each class's slice
+  __shared__ int wsum[32];
   for (int i = threadIdx.x; i < FP_MD_CLASSES * FP_TASK_BUCKETS; i += blockDim.x) hist[i] = 0;
+  if (threadIdx.x < FP_MD_CLASSES)
+    cmax[threadIdx.x] = md_bit_max(md_slice_bytes(threadIdx.x, M.lds_bytes, M.lds_md));
   if (threadIdx.x < 8) C->task_pop[threadIdx.x] = 0;
   __syncthreads();
   auto key = [&](int x) -> int {  // class * buckets + bucket, or -1
     const int m = M.nsize[x];
     if (m == 0 || (x < ntop && C->tearly[x])) return -1;  // top separators ordered already
     if (M.prev && M.segS[x]) return -1;                  // order reused
-    const int c = md_class(m, M.lds_bytes, M.lds_md);
+    const int c = m <= cmax[3] ? 3 : m <= cmax[2] ? 2 : m <= cmax[1] ? 1 : 0;  // md_class
     return c * FP_TASK_BUCKETS + (FP_TASK_BUCKETS - 1) - min(m >> 4, FP_TASK_BUCKETS - 1);
   };
   for (int x = threadIdx.x; x < nn; x += blockDim.x) {
@@ -1542,14 +1590,20 @@ __global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ fp
     if (k >= 0) atomicAdd(&hist[k], 1);
   }
   __syncthreads();
-  if (threadIdx.x < FP_MD_CLASSES) {
-    int run = 0;
-    for (int b = 0; b < FP_TASK_BUCKETS; b++) {
-      const int v = hist[threadIdx.x * FP_TASK_BUCKETS + b];
-      hist[threadIdx.x * FP_TASK_BUCKETS + b] = run;
-      run += v;
-    }
-    C->task_cnt[threadIdx.x] = run;
+  // exclusive scan of each class's buckets: one thread per bucket (the
+  // 1024 threads cover the four classes' 256 buckets), waves then classes
+  {
+    const int i = threadIdx.x;
+    const int v = hist[i];
+    const int inc = wave_incl_scan(v);
+    if (lane_id() == 63) wsum[wave_id()] = inc;
+    __syncthreads();
+    // waves 4c .. 4c + 3 hold class c
+    const int w = wave_id(), c0 = w & ~3;
+    int before = 0;
+    for (int q = c0; q < w; q++) before += wsum[q];
+    hist[i] = before + inc - v;
+    if ((w & 3) == 3 && lane_id() == 63) C->task_cnt[w >> 2] = before + inc;
   }
   __syncthreads();
   for (int x = threadIdx.x; x < nn; x += blockDim.x) {
@@ -1580,16 +1634,23 @@ __global__ void __launch_bounds__(FP_WG) k_md(const FpMesh* __restrict__ fp_ms, 
 // nodes, in heap order.  Their local orders, the longest serial chains of
 // the stage, then run on a second stream while the rest of the tree and the
 // grouping proceed.
-__global__ void k_top_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
-  MESH;
+// (counts and slots of the few depth-d nodes in an LDS array per chunk of
+// vertices, as in k_nsize_count and k_scatter)
+__global__ void __launch_bounds__(FP_WG) k_top_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+  MESH_WG;
+  __shared__ int hc[1 << FP_TOP_LEVELS];
   if (d >= C->D) return;
-  const int lo = (1 << d) - 1, hi = (2 << d) - 1;
-  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
-    const int v = v0 + lane_id();
-    const int t = v < M.n ? M.node_of[v] : -1;
-    const bool act = t >= lo && t < hi;
-    (void)wave_append_keyed(&C->tcnt[0], act ? t : 0, act);
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  int v0, v1;
+  chunk_of(fp_s, M.n, &v0, &v1);
+  if ((int)threadIdx.x < cnt) hc[threadIdx.x] = 0;
+  __syncthreads();
+  for (int v = v0 + (int)threadIdx.x; v < v1; v += (int)blockDim.x) {
+    const int x = M.node_of[v] - lo;
+    if (x >= 0 && x < cnt) atomicAdd(&hc[x], 1);
   }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt && hc[threadIdx.x]) atomicAdd(&C->tcnt[lo + threadIdx.x], hc[threadIdx.x]);
 }
 __global__ void k_top_place(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
@@ -1616,16 +1677,25 @@ __global__ void k_top_place(const FpMesh* __restrict__ fp_ms, const int* __restr
   }
   C->top_shallow = shallow + tot;
 }
-__global__ void k_top_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
-  MESH;
+__global__ void __launch_bounds__(FP_WG) k_top_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
+  MESH_WG;
+  __shared__ int hc[1 << FP_TOP_LEVELS];
   if (C->top_stop || d >= C->D) return;
-  const int lo = (1 << d) - 1, hi = (2 << d) - 1;
-  for (int v0 = vw(fp_s) * 64; v0 < M.n; v0 += vn(fp_s) * 64) {
-    const int v = v0 + lane_id();
-    const int t = v < M.n ? M.node_of[v] : -1;
-    const bool act = t >= lo && t < hi;
-    const int slot = wave_append_keyed(&C->tcur[0], act ? t : 0, act);
-    if (act) M.tbuf[slot] = v;
+  const int lo = (1 << d) - 1, cnt = 1 << d;
+  int v0, v1;
+  chunk_of(fp_s, M.n, &v0, &v1);
+  if ((int)threadIdx.x < cnt) hc[threadIdx.x] = 0;
+  __syncthreads();
+  for (int v = v0 + (int)threadIdx.x; v < v1; v += (int)blockDim.x) {
+    const int x = M.node_of[v] - lo;
+    if (x >= 0 && x < cnt) atomicAdd(&hc[x], 1);
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < cnt && hc[threadIdx.x]) hc[threadIdx.x] = atomicAdd(&C->tcur[lo + threadIdx.x], hc[threadIdx.x]);
+  __syncthreads();
+  for (int v = v0 + (int)threadIdx.x; v < v1; v += (int)blockDim.x) {
+    const int x = M.node_of[v] - lo;
+    if (x >= 0 && x < cnt) M.tbuf[atomicAdd(&hc[x], 1)] = v;
   }
 }
 // one wave (and the whole LDS) per depth-d node
@@ -2310,7 +2380,7 @@ fp_status run_pipe(Pipe& P) {
 
     }
     if (d < TL) {
-      const long long b = P.blk(mp[0].n);
+      const long long b = std::min(P.blk(mp[0].n), 2ll * P.ncu());
       FPG("k_top_count", k_top_count, [&](int) { return b; }, T, 0, st, d);
       FPG("k_top_place", k_top_place, one, dim3(64), 0, st, d);
       FPG("k_top_scatter", k_top_scatter, [&](int) { return b; }, T, 0, st, d);
@@ -2340,12 +2410,21 @@ fp_status run_pipe(Pipe& P) {
   P.mark(4);
   auto nnexp = [&](int i) { return P.blk((2ll << mp[i].Dexp) - 1); };
   FPG("k_nsize", k_nsize, per_n, T, 0, st);
-  FPG("k_nsize_count", k_nsize_count, per_n, T, 0, st);
+  // node histograms in LDS: up to 16 K nodes (64 KB), a chunk of vertices
+  // per workgroup
+  const int hcap = 16384;
+  auto chunks = [&](int i) { return std::min(P.blk(mp[i].n), 2ll * P.ncu()); };
+  const int hbytes = 4 * std::min(hcap, [&] {
+    int mx = 1;
+    for (const auto& x : mp) mx = std::max(mx, (int)std::min<long long>(x.NNcap, hcap));
+    return mx;
+  }());
+  FPG("k_nsize_count", k_nsize_count, chunks, T, hbytes, st, hcap);
   FPG("k_sched_place", k_sched_place, nnexp, T, 0, st);
   P.check();
   P.scan(FA_SBUF, FA_SBUF, FN_NN, FT_TOT);
   FPG("k_nbegin", k_nbegin, nnexp, T, 0, st);
-  FPG("k_scatter", k_scatter, per_n, T, 0, st);
+  FPG("k_scatter", k_scatter, chunks, T, hbytes, st, hcap);
   const int ntop = (1 << TL) - 1;
   if (ntop) FPG("k_top_check", k_top_check, one, dim3(64), 0, st, ntop);
   if (P.update) FPG("k_reuse", k_reuse, [&](int i) { return P.blk((2ll << mp[i].Dexp) - 1, 64); }, T, 0, st);

@@ -352,7 +352,7 @@ __device__ __forceinline__ void md_bit_run(const FpMesh& M, MdBit& B, gptr<const
 struct MdSp {
   uint16_t* rows;   // m*C
   uint16_t* len;    // m: degree = row length
-  uint32_t* alive;  // MW: remaining vertices
+  uint32_t* alive;  // MW: remaining vertices (set up front and at conversion)
   uint32_t* bk;     // (C+1) x MW: vertices by degree
   int* cnt;         // C+1
   int* nbl;         // 64: the pivot's neighbours
@@ -658,7 +658,6 @@ __device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V
         if (ballot64(lead && nl > C)) break;  // convert with p still present
         if (lane == 0) {
           M.vperm[pos0 + done] = p;  // local index; mapped below
-          atomicAnd(&S.alive[p >> 5], ~(1u << (p & 31)));
           atomicAnd(&S.bk[(long long)d * S.MW + (p >> 5)], ~(1u << (p & 31)));
         }
         if (lead) {
@@ -727,7 +726,6 @@ __device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V
         if (ballot64(lead && nl > C)) break;  // convert with p still present
         if (lane == 0) {
           M.vperm[pos0 + done] = p;  // local index; mapped below
-          atomicAnd(&S.alive[p >> 5], ~(1u << (p & 31)));
           atomicAnd(&S.bk[(long long)d * S.MW + (p >> 5)], ~(1u << (p & 31)));
         }
         if (lead) {
@@ -771,7 +769,6 @@ __device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V
         if (ballot64(over)) break;  // convert with p still present
         if (lane == 0) {
           M.vperm[pos0 + done] = p;  // local index; mapped below
-          atomicAnd(&S.alive[p >> 5], ~(1u << (p & 31)));
           atomicAnd(&S.bk[(long long)d * S.MW + (p >> 5)], ~(1u << (p & 31)));
         }
         for (int i = lane; i < kp; i += 64) S.nbl[i] = rpv[i];
@@ -820,6 +817,14 @@ __device__ __forceinline__ void md_node_list(const FpMesh& M, int t, gptr<int> V
     // sparse state in the pool first since the BIT layout reuses the slice
     gptr<unsigned> st = pool_alloc(M, (unsigned long long)m * C / 2 + 2ull * m + 64);
     if (!st) goto fail;
+    // the live set is the union of the degree buckets (the steps keep only
+    // the buckets)
+    for (int w = lane_id(); w < S.MW; w += 64) {
+      uint32_t x = 0u;
+      for (int dd = 0; dd <= C; dd++) x |= S.bk[(long long)dd * S.MW + w];
+      S.alive[w] = x;
+    }
+    wave_fence();
     {
       const long long wrows = ((long long)m * C + 1) / 2, wlen = (m + 1) / 2;
       gptr<uint16_t> srows = st.as<uint16_t>();
