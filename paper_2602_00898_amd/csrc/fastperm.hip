@@ -1564,8 +1564,9 @@ __global__ void k_reuse(const FpMesh* __restrict__ fp_ms, const int* __restrict_
 // local orders (Sec. 4.3 Step 4): one wave per node, LDS slice per wave
 // ==========================================================================
 // Task lists of the local orders, one per size class, largest nodes first
-// (a counting sort on size / 16, one workgroup): a class with more nodes
-// than resident slots then ends with its smallest nodes, not its largest.
+// (a counting sort on size / 16, one workgroup of 1024 threads, one per
+// class and bucket): a class with more nodes than resident slots then ends
+// with its smallest nodes, not its largest.
 #define FP_TASK_BUCKETS 256
 __global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int ntop) {
   MESH_WG;
@@ -1582,7 +1583,7 @@ __global__ void __launch_bounds__(1024) k_md_tasks(const FpMesh* __restrict__ fp
     const int m = M.nsize[x];
     if (m == 0 || (x < ntop && C->tearly[x])) return -1;  // top separators ordered already
     if (M.prev && M.segS[x]) return -1;                  // order reused
-    const int c = m <= cmax[3] ? 3 : m <= cmax[2] ? 2 : m <= cmax[1] ? 1 : 0;  // md_class
+    const int c = m <= cmax[3] ? 3 : m <= cmax[2] ? 2 : m <= cmax[1] ? 1 : 0;
     return c * FP_TASK_BUCKETS + (FP_TASK_BUCKETS - 1) - min(m >> 4, FP_TASK_BUCKETS - 1);
   };
   for (int x = threadIdx.x; x < nn; x += blockDim.x) {

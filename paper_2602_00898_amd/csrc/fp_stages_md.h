@@ -902,15 +902,12 @@ __device__ __forceinline__ void md_node(const FpMesh& M, int t, char* slice, lon
 //   3: a quarter of the per-node LDS (four waves per workgroup),
 //   2: a quarter of the large LDS, 1: half of it, 0: all of it (one wave;
 //      also every node too large for the dense layout).
-// Slices sized to the node keep several waves per CU on the mid-size nodes.
+// A node goes to the highest class whose slice holds its dense layout
+// (m <= md_bit_max of the slice), else to class 0.  Slices sized to the
+// node keep several waves per CU on the mid-size nodes.
 #define FP_MD_CLASSES 4
 __device__ __forceinline__ int md_slice_waves(int c) { return c == 0 ? 1 : c == 1 ? 2 : 4; }
 __device__ __forceinline__ long long md_slice_bytes(int c, long long lds, long long big) {
   return ((c == 3 ? lds : big) / md_slice_waves(c)) & ~15ll;
-}
-__device__ __forceinline__ int md_class(int m, long long lds, long long big) {
-  for (int c = 3; c >= 1; c--)
-    if (m <= md_bit_max(md_slice_bytes(c, lds, big))) return c;
-  return 0;
 }
 
