@@ -121,6 +121,27 @@ def test_large_nodes_sparse_local_order():
     check(mesh(64, 64, True, 5, 0.05), "two patches", patch_size=2048, seed=5)
 
 
+def test_path_like_nodes_stay_sparse():
+    """A cycle and a path of a few thousand vertices as one node: every pivot
+    has degree 2 at most, so the local order runs in the sparse layout to
+    the end (the four-neighbour step), never converting to the dense one."""
+    for n in (3000, 3001):
+        edges = [(i, i + 1) for i in range(n - 1)] + ([(n - 1, 0)] if n % 2 == 0 else [])
+        u = np.array([a for a, b in edges] + [b for a, b in edges])
+        v = np.array([b for a, b in edges] + [a for a, b in edges])
+        order = np.lexsort((v, u))
+        rp = np.searchsorted(u[order], np.arange(n + 1)).astype(np.int32)
+        check(mg.CSR(n, rp, v[order].astype(np.int32)), f"{'cycle' if n % 2 == 0 else 'path'} n={n}",
+              patch_size=10 ** 6, seed=1)
+
+
+def test_more_nodes_than_the_grouping_histogram():
+    """More than 16 K tree nodes (S = 2 on a 192x192 torus: 18432 patches,
+    depth 15): the grouping's per-workgroup LDS histogram does not hold the
+    nodes, and the node sizes and the scatter take per-wave keyed appends."""
+    check(mesh(192, 192, True, 41, 0.05), "18432 patches", patch_size=2, seed=4)
+
+
 def test_determinism():
     A = mesh(64, 64, True, 17, 0.05)
     a = gpu_order(A, patch_size=64, seed=3)
