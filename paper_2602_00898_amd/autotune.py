@@ -6,9 +6,11 @@ settings of the local-order stage (LDS per workgroup, workgroups per CU;
 `Handle.set_tuning`) change speed only, never a result.
 
 `tune()` measures on the current GPU, per size bucket, the ordering time of
-a seeded torus mesh for each S in {128, 256, 512, 1024} and keeps the
-fastest; then, with that S, the time under each execution setting of
-`EXEC_GRID`; then the same settings on a seeded batch of mixed meshes.  The
+a seeded torus mesh (5% edge flips) for each S in {128, 256, 512, 1024} and
+keeps the fastest; then, with that S, the time under each execution
+setting of `EXEC_GRID`, summed over the same torus with and without the
+flips and taken on calls queued back to back; then the same settings on a
+seeded batch of mixed meshes.  The
 table it writes (`tune_table.json` beside this file) is what
 `patch_size_for`, `exec_for` and `exec_batch` read.  Without a table the
 defaults below apply.
@@ -84,6 +86,22 @@ def apply(handle, setting) -> None:
     handle.set_tuning(big if not lds else min(int(lds), big), int(per_cu))
 
 
+def _queued_ms(fn, sync, reps, k=8):
+    """Median over reps of the time per call of k calls queued back to back
+    (one synchronisation each), as an application ordering many matrices in
+    a row sees them."""
+    fn()
+    sync()
+    ts = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        for _ in range(k):
+            fn()
+        sync()
+        ts.append((time.perf_counter() - t) / k)
+    return sorted(ts)[len(ts) // 2] * 1e3
+
+
 def _median_ms(fn, sync, reps):
     fn()
     sync()
@@ -129,11 +147,21 @@ def tune(reps: int = 3, verbose: bool = True) -> dict:
                 best = (S, ms)
         S = best[0]
         chosen.append(S)
+        # execution settings: summed over the same torus with and without the
+        # edge flips (separators of degree-5/7 meshes and of plain ones load
+        # the local orders differently), calls queued on resident outputs
+        B = mg.grid_mesh(side, side, True, 7, 0.0)
+        rpB = torch.from_numpy(B.rowptr).to(dev)
+        ciB = torch.from_numpy(B.colind).to(dev)
+        outA = fpm.order(rp, ci, A.n, patch_size=S, seed=7, handle=h)
+        outB = fpm.order(rpB, ciB, B.n, patch_size=S, seed=7, handle=h)
+        sync()
         best_e = None
         for lds, per_cu in EXEC_GRID:
             apply(h, (lds, per_cu))
-            ms = _median_ms(lambda: fpm.order(rp, ci, A.n, patch_size=S, seed=7, handle=h), sync,
-                            reps)
+            ms = sum(_queued_ms(lambda: fpm.order(r_, c_, n_, patch_size=S, seed=7, handle=h, out=o_,
+                                                  check=False), sync, reps)
+                     for r_, c_, n_, o_ in ((rp, ci, A.n, outA), (rpB, ciB, B.n, outB)))
             timings[f"{side}x{side}/S={S}/lds={lds or 0}/cu={per_cu}"] = round(ms, 3)
             say(f"{side}x{side} S={S} lds={lds or 'all'} per_cu={per_cu}: {ms:.2f} ms")
             if best_e is None or ms < best_e[1]:
