@@ -1726,17 +1726,18 @@ __global__ void k_top_check(const FpMesh* __restrict__ fp_ms, const int* __restr
 // ==========================================================================
 // elimination tree and column counts, bottom-up over the tree levels
 // ==========================================================================
-__global__ void k_sym_init(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
-  MESH;
-  if (vt(fp_s) == 0 && d <= C->D) {
-    C->arena_top[d & 1] = 0;
-    C->pool_top = 0;  // the pool holds one level's node scratch at a time
-  }
-}
+// The pool holds one level's node scratch at a time and the arena of parity
+// d & 1 the records level d emits: the counters are reset with no launch of
+// their own.  The pool's by the kernel before the first level (k_prow_deg),
+// then by each level's emission (which allocates nothing; the scratch it
+// reads stays in place, and the next level's prep allocates only after it);
+// the arena's by the prep of level d (which reads the other parity, and
+// which the emission of level d follows).
 __global__ void __launch_bounds__(FP_WG) k_sym_prep(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   FP_LDS_DECL;
   if (d > C->D) return;
+  if (vt(fp_s) == 0) C->arena_top[d & 1] = 0;
   const int lw = M.lds_bytes / 4 / FP_WAVES;
   int* slice = (int*)fp_lds + lw * wave_id();
   const int lo = (1 << d) - 1, cnt = 1 << d;
@@ -1767,6 +1768,7 @@ __global__ void __launch_bounds__(FP_WG) k_sym_elim_glb(const FpMesh* __restrict
 __global__ void __launch_bounds__(FP_WG) k_sym_emit(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
   MESH;
   if (d > C->D) return;
+  if (vt(fp_s) == 0) C->pool_top = 0;  // for the next level's prep
   const int lo = (1 << d) - 1, cnt = 1 << d;
   for (int x = vw(fp_s); x < cnt; x += vn(fp_s)) sym_emit(M, lo + x, d);
 }
@@ -1794,6 +1796,7 @@ __global__ void __launch_bounds__(FP_WG) k_sym_level_wg(const FpMesh* __restrict
     sym_level_wg(M, C, d, fp_lds);
     wg_level_barrier();
   }
+  if (threadIdx.x == 0) C->pool_top = 0;  // for the first level launched after these
 }
 __device__ __forceinline__ void sym_level_wg(const FpMesh& M, gptr<FpCtl> C, int d, char* fp_lds) {
   if (threadIdx.x == 0) {
@@ -1822,6 +1825,7 @@ __device__ __forceinline__ void sym_level_wg(const FpMesh& M, gptr<FpCtl> C, int
 // chasing vperm -> row pointers -> columns -> viperm per entry.
 __global__ void k_prow_deg(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH;
+  if (vt(fp_s) == 0) C->pool_top = 0;  // the local orders are done with the pool
   for (int p = vt(fp_s); p < M.n; p += vs(fp_s)) {
     const int v = M.vperm[p];
     M.pcnt[p] = (unsigned)v < (unsigned)M.n ? M.grp[v + 1] - M.grp[v] : 0;
@@ -2484,8 +2488,6 @@ fp_status run_pipe(Pipe& P) {
       if (d > mp[i].Dmax || d > mp[i].Dexp) return 0;
       return std::max(1, std::min(cnt, 4 * P.ncu()));
     };
-    auto G0 = [&, d](int i) -> long long { return d > mp[i].Dmax || d > mp[i].Dexp ? 0 : 1; };
-    FPG("k_sym_init", k_sym_init, G0, dim3(64), 0, st, d);
     FPG("k_sym_prep", k_sym_prep, G, T, P.h->lds_bytes, st, d);
     FPG("k_sym_elim", k_sym_elim, G, T, P.h->lds_bytes, st, d, 0);
     FPG("k_sym_elim", k_sym_elim, G1, T, P.h->lds_big, st, d, 1);
