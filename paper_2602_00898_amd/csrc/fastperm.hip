@@ -379,16 +379,20 @@ __global__ void k_seed_push(const FpMesh* __restrict__ fp_ms, const int* __restr
   if (vt(fp_s) == 0) M.fcnt[0] = nseeds;
 }
 // One frontier level: a lane per frontier vertex.  The loads of its first
-// FP_BFS_ROW neighbours (columns, then keys) go out together, and the wave's
-// claims are appended with one atomic.
+// FP_BFS_ROW neighbours (columns, then keys) go out together, and the
+// workgroup's claims are appended with one atomic (every wave taking one on
+// the next frontier's single counter had serialised the large levels).
 #define FP_BFS_ROW 8
-__global__ void k_bfs_level(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int lvl) {
-  MESH;
+__global__ void __launch_bounds__(FP_WG) k_bfs_level(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int lvl) {
+  MESH_WG;
+  __shared__ int scan_tmp[FP_WAVES + 2];
+  __shared__ int base_s;
   const int nf = M.fcnt[lvl];
   gptr<const int> cur = (lvl & 1) ? M.fb : M.fa;
   gptr<int> nxt = (lvl & 1) ? M.fa : M.fb;
-  for (int f0 = vw(fp_s) * 64; f0 < nf; f0 += vn(fp_s) * 64) {
-    const int f = f0 + lane_id();
+  // the workgroup steps together (a barrier in each step)
+  for (int b0 = fp_s.bx * FP_WG; b0 < nf; b0 += fp_s.gx * FP_WG) {
+    const int f = b0 + (int)threadIdx.x;
     int e0 = 0, deg = 0;
     unsigned long long kv = 0;
     if (f < nf) {
@@ -409,16 +413,13 @@ __global__ void k_bfs_level(const FpMesh* __restrict__ fp_ms, const int* __restr
 #pragma unroll
     for (int j = 0; j < FP_BFS_ROW; j++)
       if (u[j] >= 0 && ku[j] > kv && atomicMin(&M.key[u[j]], kv) == FP_UNSET) claims |= 1u << j;
-    // one slot range per wave for all these claims
+    // one slot range per workgroup for all these claims
     const int c = __popc(claims);
-    const int inc = wave_incl_scan(c);
-    const int tot = wave_bcast(inc, 63);
-    int base = 0;
-    if (tot) {
-      if (lane_id() == 0) base = atomicAdd(&M.fcnt[lvl + 1], tot);
-      base = wave_bcast(base, 0);
-    }
-    int o = base + inc - c;
+    int tot;
+    const int ex = wg_excl_scan(c, scan_tmp, &tot);
+    if (threadIdx.x == 0 && tot) base_s = atomicAdd(&M.fcnt[lvl + 1], tot);
+    __syncthreads();
+    int o = (tot ? base_s : 0) + ex;
 #pragma unroll
     for (int j = 0; j < FP_BFS_ROW; j++)
       if ((claims >> j) & 1u) nxt[o++] = u[j];

@@ -15,6 +15,8 @@ struct BisectLds {
   int tmp[FP_WAVES + 2];
   int tail;
   int r0;
+  int lvcnt[3];  // claims of the next level, rotating over three levels
+  int sink[64];  // per lane: the target of compare-swaps that must fail (0)
   unsigned long long red[FP_WAVES];
 };
 
@@ -56,34 +58,81 @@ __device__ __forceinline__ int wg_bfs(const FpMesh& M, int t, gptr<const int> pi
 }
 
 // The same BFS on the node's quotient subgraph held as a local CSR (lrow,
-// lcol: local indices) with its levels and queue in LDS: a level costs a few
-// LDS round trips instead of a chain of global loads per arc.
+// lcol: local indices) with its levels and queue in LDS.  A level is latency
+// bound: a lane reads its vertex's first FP_BIS_ROW neighbours and their
+// levels at once, and each wave reserves its claims' queue slots with one
+// LDS atomic on the level's own counter.  The counters rotate over three
+// levels, so that one barrier per level suffices: the one for level L+2 is
+// cleared while level L runs, after every thread has read it.  The loads
+// and compare-swaps are branch free (a lane with nothing to claim swaps on
+// its sink word, which never holds -1), so that they are all in flight
+// together.  The order inside a level depends on timing; the levels and
+// their sets do not.
+#define FP_BIS_ROW 8
 __device__ __forceinline__ int wg_bfs_lds(const int* lrow, const int* lcol, int src, int* lev,
                                           int* queue, gptr<int> ls, int* ecc_out, BisectLds* sh) {
   if (threadIdx.x == 0) {
     lev[src] = 0;
     queue[0] = src;
     ls[0] = 0;
-    sh->tail = 1;
+    sh->lvcnt[1] = 0;
   }
+  if (threadIdx.x < 64) sh->sink[threadIdx.x] = 0;
   __syncthreads();
   int head = 0, tail = 1, L = 0;
   while (true) {
-    for (int i = head + (int)threadIdx.x; i < tail; i += FP_WG) {
-      const int x = queue[i];
-      for (int a = lrow[x]; a < lrow[x + 1]; a++) {
-        const int y = lcol[a];
-        if (lev[y] == -1 && atomicCAS(&lev[y], -1, L + 1) == -1) queue[atomicAdd(&sh->tail, 1)] = y;
+    if (threadIdx.x == 0) sh->lvcnt[(L + 2) % 3] = 0;
+    int* ctr = &sh->lvcnt[(L + 1) % 3];
+    for (int i = head + (int)threadIdx.x; i - (int)threadIdx.x < tail; i += FP_WG) {
+      int y[FP_BIS_ROW];
+      unsigned claims = 0;
+      int a0 = 0, a1 = 0;
+      {
+        // a lane past the level reads vertex 0's row and claims nothing
+        const int x = i < tail ? queue[i] : 0;
+        a0 = lrow[x];
+        a1 = i < tail ? lrow[x + 1] : a0;
+        // lcol[a0 + j] past the row stays inside the LDS arrays (the
+        // level arrays follow lcol)
+#pragma unroll
+        for (int j = 0; j < FP_BIS_ROW; j++) y[j] = lcol[a0 + j];
+#pragma unroll
+        for (int j = 0; j < FP_BIS_ROW; j++) y[j] = a0 + j < a1 ? y[j] : -1;
+        int ly[FP_BIS_ROW];
+#pragma unroll
+        for (int j = 0; j < FP_BIS_ROW; j++) ly[j] = lev[y[j] >= 0 ? y[j] : 0];
+        int r[FP_BIS_ROW];
+#pragma unroll
+        for (int j = 0; j < FP_BIS_ROW; j++)
+          r[j] = atomicCAS(y[j] >= 0 && ly[j] == -1 ? &lev[y[j]] : &sh->sink[lane_id()], -1, L + 1);
+#pragma unroll
+        for (int j = 0; j < FP_BIS_ROW; j++) claims |= (unsigned)(r[j] == -1) << j;
+      }
+      const int c = __popc(claims);
+      const int inc = wave_incl_scan(c);
+      const int tot = wave_bcast(inc, 63);
+      int base = 0;
+      if (tot) {
+        if (lane_id() == 63) base = atomicAdd(ctr, tot);
+        base = wave_bcast(base, 63);
+      }
+      int o = tail + base + inc - c;
+#pragma unroll
+      for (int j = 0; j < FP_BIS_ROW; j++)
+        if (claims & (1u << j)) queue[o++] = y[j];
+      // rows longer than FP_BIS_ROW (rare on a patch quotient graph)
+      for (int a = a0 + FP_BIS_ROW; a < a1; a++) {
+        const int z = lcol[a];
+        if (lev[z] == -1 && atomicCAS(&lev[z], -1, L + 1) == -1) queue[tail + atomicAdd(ctr, 1)] = z;
       }
     }
     __syncthreads();
-    const int nt = sh->tail;
-    __syncthreads();
-    if (nt == tail) break;
+    const int nc = sh->lvcnt[(L + 1) % 3];
+    if (nc == 0) break;
     L++;
     if (threadIdx.x == 0) ls[L] = tail;
     head = tail;
-    tail = nt;
+    tail += nc;
   }
   if (threadIdx.x == 0) ls[L + 1] = tail;
   __syncthreads();
@@ -258,11 +307,20 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
     flag[i] = 0;
   }
   __syncthreads();
+  // degrees inside t: the first FP_BIS_ROW arcs' loads go out together
   for (int i = threadIdx.x; i < m; i += FP_WG) {
     const int p = pid[i];
+    const int a0 = M.qptr[p], a1 = M.qptr[p + 1];
+    int q[FP_BIS_ROW], c[FP_BIS_ROW];
+#pragma unroll
+    for (int j = 0; j < FP_BIS_ROW; j++) {
+      q[j] = a0 + j < a1 ? (int)M.qci[a0 + j] : -1;
+      c[j] = a0 + j < a1 ? (int)M.qcnt[a0 + j] : 0;
+    }
     int d = 0;
-    for (int a = M.qptr[p]; a < M.qptr[p + 1]; a++)
-      d += (M.qcnt[a] > 0 && M.pnode[M.qci[a]] == t);
+#pragma unroll
+    for (int j = 0; j < FP_BIS_ROW; j++) d += (c[j] > 0 && (q[j] >= 0 ? (int)M.pnode[q[j]] : -1) == t);
+    for (int a = a0 + FP_BIS_ROW; a < a1; a++) d += (M.qcnt[a] > 0 && M.pnode[M.qci[a]] == t);
     deg[i] = d;
   }
   __syncthreads();
@@ -290,9 +348,24 @@ __device__ __forceinline__ void wg_bisect(const FpMesh& M, int t, int s, int m, 
       for (int i = threadIdx.x; i < m; i += FP_WG) {
         const int p = pid[i];
         int o = lrow[i];
-        for (int a = M.qptr[p]; a < M.qptr[p + 1]; a++) {
-          const int q = M.qci[a];
-          if (M.qcnt[a] > 0 && M.pnode[q] == t) lcol[o++] = M.ploc[q];
+        const int a0 = M.qptr[p], a1 = M.qptr[p + 1];
+        int q[FP_BIS_ROW], c[FP_BIS_ROW], pn[FP_BIS_ROW], pl[FP_BIS_ROW];
+#pragma unroll
+        for (int j = 0; j < FP_BIS_ROW; j++) {
+          q[j] = a0 + j < a1 ? (int)M.qci[a0 + j] : -1;
+          c[j] = a0 + j < a1 ? (int)M.qcnt[a0 + j] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < FP_BIS_ROW; j++) {
+          pn[j] = q[j] >= 0 ? (int)M.pnode[q[j]] : -1;
+          pl[j] = q[j] >= 0 ? (int)M.ploc[q[j]] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < FP_BIS_ROW; j++)
+          if (c[j] > 0 && pn[j] == t) lcol[o++] = pl[j];
+        for (int a = a0 + FP_BIS_ROW; a < a1; a++) {
+          const int qq = M.qci[a];
+          if (M.qcnt[a] > 0 && M.pnode[qq] == t) lcol[o++] = M.ploc[qq];
         }
         lA[i] = -1;
         lB[i] = -1;
