@@ -135,7 +135,7 @@ __device__ __forceinline__ void prep_each(const FpMesh& M, const PrepRows& r, in
 
 // Sizes and child records of a node, for the second half of the prep.
 struct PrepIn {
-  int m, b0, e0, na, BW, np2, nfw, nce, rows, stride;
+  int m, b0, e0, na, BW, np2, nfw, nanc, nce, rows, stride;
   int cst[2], cin[2];
 };
 
@@ -204,7 +204,8 @@ __device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymV
       off += 1 + len;
     }
   }
-  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
+  // (t's rows reach no later position when the count found none)
+  for (int k0 = 0; k0 < (in.nanc ? m : 0); k0 += 64 * FP_PREP_COLS) {
     PrepRows R;
     prep_rows(M, b0, m, k0, R);
 #pragma unroll
@@ -383,29 +384,43 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
   }
   const int nce = crec[0] + crec[1];
   // inputs in range: t's positions hold vertices placed there by the local
-  // orders, child records hold positions of t or later
+  // orders, child records hold positions of t or later.  The vertex check
+  // shares its rounds with the count of forward entries and later
+  // positions: four columns per lane and round, every load of a round
+  // issued before the first use.
+  int nfw = 0, nanc = 0;
   {
     bool bad = b0 < 0 || m < 0 || e0 > M.n;
     if (!bad) {
-      // four columns per lane and round, every load of a round issued
-      // before the first use
-      for (int k0 = 0; k0 < m; k0 += 256) {
-        int v[4];
+      for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
+        int v[FP_PREP_COLS];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < FP_PREP_COLS; u++) {
           const int k = k0 + lane_id() + 64 * u;
           v[u] = k < m ? M.vperm[b0 + k] : 0;
         }
-        int w[4];
+        PrepRows R;
+        prep_rows(M, b0, m, k0, R);
+        int w[FP_PREP_COLS];
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < FP_PREP_COLS; u++) {
           const int k = k0 + lane_id() + 64 * u;
           const bool in = k < m && (unsigned)v[u] < (unsigned)M.n;
           bad |= k < m && !in;
           w[u] = in ? M.viperm[v[u]] : 0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
+        for (int u = 0; u < FP_PREP_COLS; u++) {
+          const int p = b0 + k0 + lane_id() + 64 * u;
+          prep_each(M, R, u, [&](int q) {
+            if (q > p) {
+              nfw++;
+              nanc += (q >= e0);
+            }
+          });
+        }
+#pragma unroll
+        for (int u = 0; u < FP_PREP_COLS; u++) {
           const int k = k0 + lane_id() + 64 * u;
           bad |= k < m && w[u] != b0 + k;
         }
@@ -428,9 +443,15 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
           bad = true;
           break;
         }
-        for (int i = lane_id(); i < len; i += 64) {
-          const int q = src[off + 1 + i];
-          if (q < b0 || q >= M.n) bad = true;
+        for (int i0 = 0; i0 < len; i0 += 256) {
+          int q[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            const int i = i0 + lane_id() + 64 * u;
+            q[u] = i < len ? src[off + 1 + i] : b0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; u++) bad |= q[u] < b0 || q[u] >= M.n;
         }
         off += 1 + len;
         nrec++;
@@ -441,22 +462,6 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
     if (bad) {
       sym_drop(M, t, site);
       return;
-    }
-  }
-  // forward entries and later positions
-  int nfw = 0, nanc = 0;
-  for (int k0 = 0; k0 < m; k0 += 64 * FP_PREP_COLS) {
-    PrepRows R;
-    prep_rows(M, b0, m, k0, R);
-#pragma unroll
-    for (int u = 0; u < FP_PREP_COLS; u++) {
-      const int p = b0 + k0 + lane_id() + 64 * u;
-      prep_each(M, R, u, [&](int q) {
-        if (q > p) {
-          nfw++;
-          nanc += (q >= e0);
-        }
-      });
     }
   }
   nfw = wave_sum_i32(nfw);
@@ -516,7 +521,7 @@ __device__ __forceinline__ void sym_prep(const FpMesh& M, int t, int d, int* lds
     }
   }
   wave_fence();
-  const PrepIn in{m, b0, e0, na, BW, np2, nfw, nce, rows, stride, {cst[0], cst[1]}, {cin[0], cin[1]}};
+  const PrepIn in{m, b0, e0, na, BW, np2, nfw, nanc, nce, rows, stride, {cst[0], cst[1]}, {cin[0], cin[1]}};
   if (lmode) {
     uint32_t* l = (uint32_t*)(lds + 96);
     sym_prep_tail(M, t, V, base, src, anc, in, l, l + BW, l + 2 * BW);
