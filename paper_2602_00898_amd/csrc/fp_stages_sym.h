@@ -139,6 +139,37 @@ struct PrepIn {
   int cst[2], cin[2];
 };
 
+// Bit of each later position q[j] in the bitmap over the ancestors' ranges
+// (anc: begin, size, bit offset per ancestor, begins increasing), or -1.
+// The search is branch free with a step count set by na alone (top: the
+// largest power of two <= na, 0 if na == 0), so the N lookups run side by
+// side: each step is one LDS round trip for all of them.
+template <int N>
+__device__ __forceinline__ void anc_bits(const int* anc, int na, int top, const int (&q)[N],
+                                         int (&bit)[N]) {
+  int c[N];  // ancestors beginning at or before q[j]
+#pragma unroll
+  for (int j = 0; j < N; j++) c[j] = 0;
+  for (int st = top; st > 0; st >>= 1) {
+    int bg[N];
+#pragma unroll
+    for (int j = 0; j < N; j++) bg[j] = anc[3 * (min(c[j] + st, na) - 1)];
+#pragma unroll
+    for (int j = 0; j < N; j++) c[j] += (c[j] + st <= na && bg[j] <= q[j]) ? st : 0;
+  }
+  int beg[N], sz[N], off[N];
+#pragma unroll
+  for (int j = 0; j < N; j++) {
+    const int f = max(c[j] - 1, 0);
+    beg[j] = anc[3 * f];
+    sz[j] = anc[3 * f + 1];
+    off[j] = anc[3 * f + 2];
+  }
+#pragma unroll
+  for (int j = 0; j < N; j++)
+    bit[j] = c[j] > 0 && q[j] < beg[j] + sz[j] ? off[j] + (q[j] - beg[j]) : -1;
+}
+
 // Second half of the prep: the later positions (marked in a bitmap over the
 // ancestors' ranges and read back in order), the forward rows in F
 // indices, and the incoming element rows.  bm and pre (BW words each) and
@@ -152,55 +183,85 @@ __device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymV
                                               P rbuf) {
   const int m = in.m, b0 = in.b0, e0 = in.e0, na = in.na, BW = in.BW, np2 = in.np2;
   const int lane = lane_id();
+  int top = 0;
+  if (na > 0)
+    for (top = 1; (top << 1) <= na;) top <<= 1;
   for (int w = lane; w < BW; w += 64) bm[w] = 0u;
   wave_fence();
-  // the ancestor whose range holds position q, or -1
-  auto anc_of = [&](int q) -> int {
-    int lo = 0, hi = na - 1, f = -1;
-    while (lo <= hi) {  // nearest ancestor range starting at or before q
-      const int mid = (lo + hi) >> 1;
-      if (anc[3 * mid] <= q) {
-        f = mid;
-        lo = mid + 1;
-      } else {
-        hi = mid - 1;
+  // F index of each q[j] (t's own range first, then the later positions in
+  // order; -1 if q[j] is in neither, which the callers report), the lookups
+  // of a call side by side.  Reads the bitmap only when a lane needs it.
+  auto findex_n = [&](const auto& q, auto& f) {
+    constexpr int N = std::extent<std::remove_reference_t<decltype(q)>>::value;
+    bool later = false;
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+      f[j] = q[j] >= b0 && q[j] < e0 ? q[j] - b0 : -1;
+      later |= q[j] >= e0;
+    }
+    if (ballot64(later)) {
+      int bit[N];
+      anc_bits<N>(anc, na, top, q, bit);
+      uint32_t x[N];
+      int pr[N];
+#pragma unroll
+      for (int j = 0; j < N; j++) {
+        const int wd = max(bit[j], 0) >> 5;
+        x[j] = bm[wd];
+        pr[j] = pre[wd];
+      }
+#pragma unroll
+      for (int j = 0; j < N; j++) {
+        const uint32_t b = 1u << (bit[j] & 31);
+        if (q[j] >= e0 && bit[j] >= 0 && (x[j] & b)) f[j] = m + pr[j] + popc32(x[j] & (b - 1u));
       }
     }
-    return f >= 0 && q < anc[3 * f] + anc[3 * f + 1] ? f : -1;
   };
-  // every position of the child records, four per lane loaded together
-  auto each_record_pos = [&](int off, int len, auto fn) {
-    for (int i0 = 0; i0 < len; i0 += 64 * FP_PREP_COLS) {
-      int q[FP_PREP_COLS];
-#pragma unroll
-      for (int u = 0; u < FP_PREP_COLS; u++) {
-        const int i = i0 + lane + 64 * u;
-        q[u] = i < len ? src[off + 1 + i] : -1;
-      }
-#pragma unroll
-      for (int u = 0; u < FP_PREP_COLS; u++)
-        if (i0 + lane + 64 * u < len) fn(q[u]);
-    }
+  auto findex = [&](int q) -> int {
+    const int qa[1] = {q};
+    int fa[1];
+    findex_n(qa, fa);
+    return fa[0];
   };
   // 1. mark the later positions of the child records and of t's own rows
   bool bad1 = false;
-  auto mark = [&](int q) {
-    const int f = anc_of(q);
-    if (f < 0) {
-      bad1 = true;
-      return;
+  // mark every q[j] >= e0 (the others are skipped)
+  auto mark_n = [&](const auto& q) {
+    constexpr int N = std::extent<std::remove_reference_t<decltype(q)>>::value;
+    bool need = false;
+#pragma unroll
+    for (int j = 0; j < N; j++) need |= q[j] >= e0;
+    if (!ballot64(need)) return;
+    int bit[N];
+    anc_bits<N>(anc, na, top, q, bit);
+#pragma unroll
+    for (int j = 0; j < N; j++) {
+      if (q[j] < e0) continue;
+      if (bit[j] < 0)
+        bad1 = true;
+      else
+        atomicOr(&bm[bit[j] >> 5], 1u << (bit[j] & 31));
     }
-    const int b = anc[3 * f + 2] + (q - anc[3 * f]);
-    atomicOr(&bm[b >> 5], 1u << (b & 31));
+  };
+  // the positions of a child record, four per lane loaded together
+  // (-1 past its end)
+  auto record_round = [&](int off, int len, int i0, int (&q)[FP_PREP_COLS]) {
+#pragma unroll
+    for (int u = 0; u < FP_PREP_COLS; u++) {
+      const int i = i0 + lane + 64 * u;
+      q[u] = i < len ? src[off + 1 + i] : -1;
+    }
   };
   for (int c = 0; c < 2; c++) {
     int off = in.cst[c];
     const int end = in.cst[c] + in.cin[c];
     while (off < end) {
       const int len = uni(src[off]);
-      each_record_pos(off, len, [&](int q) {
-        if (q >= e0) mark(q);
-      });
+      for (int i0 = 0; i0 < len; i0 += 64 * FP_PREP_COLS) {
+        int q[FP_PREP_COLS];
+        record_round(off, len, i0, q);
+        mark_n(q);
+      }
       off += 1 + len;
     }
   }
@@ -209,10 +270,16 @@ __device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymV
     PrepRows R;
     prep_rows(M, b0, m, k0, R);
 #pragma unroll
-    for (int u = 0; u < FP_PREP_COLS; u++)
-      prep_each(M, R, u, [&](int q) {
-        if (q >= e0) mark(q);
-      });
+    for (int u = 0; u < FP_PREP_COLS; u++) {
+      int q[FP_PREP_ROW];
+#pragma unroll
+      for (int j = 0; j < FP_PREP_ROW; j++) q[j] = j < R.deg[u] ? R.q[u][j] : -1;
+      mark_n(q);
+      for (int j = FP_PREP_ROW; j < R.deg[u]; j++) {
+        const int q1[1] = {(int)M.pent[R.e0[u] + j]};
+        mark_n(q1);
+      }
+    }
   }
   if (ballot64(bad1)) {
     sym_drop(M, t, FP_SITE_SYM_LOOKUP);
@@ -220,7 +287,8 @@ __device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymV
   }
   wave_fence();
   // read the bitmap back: positions in increasing order, and the rank
-  // prefix of every word
+  // prefix of every word.  A lane finds the ancestor of its word's first
+  // set bit, then steps forward through the ancestors as its bits rise.
   int nbd = 0;
   for (int w0 = 0; w0 < BW; w0 += 64) {
     const int w = w0 + lane;
@@ -229,21 +297,32 @@ __device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymV
     const int inc = wave_incl_scan(c);
     int o = nbd + inc - c;
     if (w < BW) pre[w] = o;
-    while (x) {
-      const int b = w * 32 + __ffs(x) - 1;
-      x &= x - 1;
+    if (x) {
+      const int b1 = w * 32 + __ffs(x) - 1;
       int lo = 0, hi = na - 1, f = 0;
-      while (lo <= hi) {  // the ancestor whose bit range holds b
+      while (lo <= hi) {  // the ancestor whose bit range holds b1
         const int mid = (lo + hi) >> 1;
-        if (anc[3 * mid + 2] <= b) {
+        if (anc[3 * mid + 2] <= b1) {
           f = mid;
           lo = mid + 1;
         } else {
           hi = mid - 1;
         }
       }
-      if (o < np2) V.bd[o] = anc[3 * f] + (b - anc[3 * f + 2]);
-      o++;
+      int fbeg = anc[3 * f], foff = anc[3 * f + 2];
+      int nxt = f + 1 < na ? anc[3 * (f + 1) + 2] : INT_MAX;
+      while (x) {
+        const int b = w * 32 + __ffs(x) - 1;
+        x &= x - 1;
+        while (b >= nxt) {
+          f++;
+          fbeg = anc[3 * f];
+          foff = nxt;
+          nxt = f + 1 < na ? anc[3 * (f + 1) + 2] : INT_MAX;
+        }
+        if (o < np2) V.bd[o] = fbeg + (b - foff);
+        o++;
+      }
     }
     nbd += wave_bcast(inc, 63);
   }
@@ -254,17 +333,6 @@ __device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymV
   wave_fence();
   const int F = m + nbd;
   const int FW = (F + 31) >> 5;
-  // F index of position q: t's own range first, then the later positions
-  // in order; -1 if q is in neither, which the callers report
-  auto findex = [&](int q) -> int {
-    if (q >= b0 && q < e0) return q - b0;
-    if (q < e0) return -1;
-    const int f = anc_of(q);
-    if (f < 0) return -1;
-    const int b = anc[3 * f + 2] + (q - anc[3 * f]);
-    const uint32_t x = bm[b >> 5], bit = 1u << (b & 31);
-    return (x & bit) ? m + (int)pre[b >> 5] + popc32(x & (bit - 1u)) : -1;
-  };
   // 2. forward rows in F indices
   {
     bool bad = false;
@@ -281,16 +349,34 @@ __device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymV
         prep_each(M, R, u, [&](int q) { cnt += q > p; });
         const int inc = wave_incl_scan(cnt);
         int o = run + inc - cnt;
+        // F indices of the first FP_PREP_ROW entries, looked up together
+        int q[FP_PREP_ROW], fi[FP_PREP_ROW];
+#pragma unroll
+        for (int j = 0; j < FP_PREP_ROW; j++) q[j] = j < R.deg[u] && k < m ? R.q[u][j] : -1;
+        findex_n(q, fi);
         if (k < m) {
           V.optr[k] = o;
-          prep_each(M, R, u, [&](int q) {
-            if (q > p) {
-              const int f = findex(q);
-              const bool ok = f > k && f < F;
+#pragma unroll
+          for (int j = 0; j < FP_PREP_ROW; j++) {
+            if (q[j] > p) {
+              const bool ok = fi[j] > k && fi[j] < F;
               bad |= !ok;
-              V.oent[o++] = ok ? f : k + 1;
+              V.oent[o++] = ok ? fi[j] : k + 1;
             }
-          });
+          }
+        }
+        // entries past FP_PREP_ROW one at a time (findex takes the whole
+        // wave, so the loop runs to the longest row of the wave)
+        const int dl = k < m ? R.deg[u] : 0;
+        const int dmax = (int)wave_max_u32((uint32_t)dl);
+        for (int j = FP_PREP_ROW; j < dmax; j++) {
+          const int qj = j < dl ? (int)M.pent[R.e0[u] + j] : -1;
+          const int f = findex(qj);
+          if (qj > p) {
+            const bool ok = f > k && f < F;
+            bad |= !ok;
+            V.oent[o++] = ok ? f : k + 1;
+          }
         }
         run += wave_bcast(inc, 63);
       }
@@ -316,15 +402,21 @@ __device__ __forceinline__ void sym_prep_tail(const FpMesh& M, int t, const SymV
       for (int w = lane; w < FW; w += 64) rbuf[w] = 0u;
       wave_fence();
       uint32_t fmin = 0xFFFFFFFFu;
-      each_record_pos(off, len, [&](int q) {
-        const int f = findex(q);
-        if (f < 0) {
-          bad3 = true;
-        } else {
-          atomicOr(&rbuf[f >> 5], 1u << (f & 31));
-          fmin = min(fmin, (uint32_t)f);
+      for (int i0 = 0; i0 < len; i0 += 64 * FP_PREP_COLS) {
+        int q[FP_PREP_COLS], f[FP_PREP_COLS];
+        record_round(off, len, i0, q);
+        findex_n(q, f);
+#pragma unroll
+        for (int u = 0; u < FP_PREP_COLS; u++) {
+          if (i0 + lane + 64 * u >= len) continue;
+          if (f[u] < 0) {
+            bad3 = true;
+          } else {
+            atomicOr(&rbuf[f[u] >> 5], 1u << (f[u] & 31));
+            fmin = min(fmin, (uint32_t)f[u]);
+          }
         }
-      });
+      }
       fmin = wave_min_u32(fmin);
       wave_fence();
       const gptr<uint32_t> row = V.rows + (long long)r * in.stride;
