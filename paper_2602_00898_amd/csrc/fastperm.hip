@@ -277,6 +277,10 @@ __global__ void k_ctl_clear_all(const FpMesh* __restrict__ ms) {
   for (int i = (int)threadIdx.x; i < words; i += (int)blockDim.x) w[i] = 0;
 }
 
+// entries of a mesh row whose loads a lane issues together (rows have 4 to 8
+// entries; longer ones take a loop for the rest)
+#define FP_BFS_ROW 8
+
 // ==========================================================================
 // ingest: graph of A without its diagonal (Sec. 4.1 Step 2, Sec. 6.5)
 // ==========================================================================
@@ -382,7 +386,6 @@ __global__ void k_seed_push(const FpMesh* __restrict__ fp_ms, const int* __restr
 // FP_BFS_ROW neighbours (columns, then keys) go out together, and the
 // workgroup's claims are appended with one atomic (every wave taking one on
 // the next frontier's single counter had serialised the large levels).
-#define FP_BFS_ROW 8
 __global__ void __launch_bounds__(FP_WG) k_bfs_level(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int lvl) {
   MESH_WG;
   __shared__ int scan_tmp[FP_WAVES + 2];
@@ -1837,8 +1840,19 @@ __global__ void k_prow_fill(const FpMesh* __restrict__ fp_ms, const int* __restr
   for (int p = vt(fp_s); p < M.n; p += vs(fp_s)) {
     const int v = M.vperm[p];
     if ((unsigned)v >= (unsigned)M.n) continue;
-    int o = M.prow[p];
-    for (int e = M.grp[v]; e < M.grp[v + 1]; e++) M.pent[o++] = M.viperm[M.gci[e]];
+    const int o = M.prow[p], e0 = M.grp[v], deg = M.grp[v + 1] - e0;
+    if (deg <= 0) continue;
+    // the first FP_BFS_ROW columns, then their positions, loaded together
+    // (indices past the row re-read its last entry; not stored)
+    int u[FP_BFS_ROW];
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) u[j] = M.gci[e0 + min(j, deg - 1)];
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) u[j] = M.viperm[u[j]];
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++)
+      if (j < deg) M.pent[o + j] = u[j];
+    for (int e = FP_BFS_ROW; e < deg; e++) M.pent[o + e] = M.viperm[M.gci[e0 + e]];
   }
 }
 // nnz(L): the column counts summed per workgroup, one atomic each

@@ -56,6 +56,51 @@ __device__ __forceinline__ int entry_vertex(const FpMesh& M, long long e, int v,
   return u == v ? -1 : u;
 }
 
+// Rows of up to FP_ROW_REG input entries (mesh rows): the entries are
+// loaded together and deduplicated and ranked in registers.
+#define FP_ROW_REG 16
+__device__ __forceinline__ int gather_vertex_row_reg(const FpMesh& M, int v, long long e0, long long e1,
+                                                     gptr<int> out, unsigned* eb) {
+  if (e1 == e0) return 0;
+  int u[FP_ROW_REG];  // entries past the row re-read its last one (ignored)
+#pragma unroll
+  for (int j = 0; j < FP_ROW_REG; j++) u[j] = M.ci_in[min(e0 + j, e1 - 1)];
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < FP_ROW_REG; j++) {
+    const int c = u[j];
+    const bool in = e0 + j < e1;
+    const bool ok = c >= 0 && (long long)c < M.n_dof;
+    bad |= in && !ok;
+    const int w = M.b == 1 ? c : c / M.b;
+    u[j] = in && ok && w != v ? w : -1;  // -1: the diagonal block or a bad index
+  }
+  if (bad) *eb |= FP_E_INDEX;
+  // an entry counts if no earlier entry names the same vertex
+#pragma unroll
+  for (int j = 1; j < FP_ROW_REG; j++) {
+    bool dup = false;
+#pragma unroll
+    for (int i = 0; i < j; i++) dup |= u[i] == u[j];
+    if (dup) u[j] = -1;
+  }
+  int cnt = 0;
+#pragma unroll
+  for (int j = 0; j < FP_ROW_REG; j++) cnt += u[j] >= 0;
+  if (out) {
+    // rank of each distinct vertex among the others: its slot in the
+    // ascending row
+#pragma unroll
+    for (int j = 0; j < FP_ROW_REG; j++) {
+      int r = 0;
+#pragma unroll
+      for (int i = 0; i < FP_ROW_REG; i++) r += u[i] >= 0 && u[i] < u[j];
+      if (u[j] >= 0) out[r] = u[j];
+    }
+  }
+  return cnt;
+}
+
 // Short rows (one lane): the distinct neighbours of v; with `out`, written
 // there in ascending order.  Returns their count, or -1 for a long row.
 __device__ __forceinline__ int gather_vertex_row(const FpMesh& M, int v, gptr<int> out, unsigned* eb) {
@@ -65,6 +110,7 @@ __device__ __forceinline__ int gather_vertex_row(const FpMesh& M, int v, gptr<in
     return 0;
   }
   if (e1 - e0 > FP_ROW_SHORT) return -1;
+  if (e1 - e0 <= FP_ROW_REG) return gather_vertex_row_reg(M, v, e0, e1, out, eb);
   int cnt = 0;
   for (long long e = e0; e < e1; e++) {
     const int u = entry_vertex(M, e, v, eb);
