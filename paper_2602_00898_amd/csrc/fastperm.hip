@@ -602,19 +602,71 @@ __global__ void k_lloyd_gmap(const FpMesh* __restrict__ fp_ms, const int* __rest
 }
 // (the loops below step a whole workgroup at a time: wg_append holds a
 // barrier, and a single list counter takes one atomic per workgroup)
-__global__ void k_lloyd_bnd(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
+// Patch-boundary flags of the vertices v = v0 + FP_WG k + threadIdx.x
+// (k < FP_BND_K): bit k is set when v < n has a neighbour in another patch;
+// g[k] is v's patch (0 past n).  The loads of a step go out together for
+// all FP_BND_K vertices: patches and row ranges, the first FP_BFS_ROW
+// columns of each row, then their patches.
+#define FP_BND_K 8
+__device__ __forceinline__ uint32_t boundary_flags(const FpMesh& M, int v0, int (&g)[FP_BND_K]) {
+  int e0[FP_BND_K], dg[FP_BND_K];
+#pragma unroll
+  for (int k = 0; k < FP_BND_K; k++) {
+    const int v = v0 + FP_WG * k + (int)threadIdx.x;
+    const bool act = v < M.n;
+    g[k] = act ? (int)M.gmap[v] : 0;
+    e0[k] = act ? (int)M.grp[v] : 0;
+    dg[k] = act ? (int)M.grp[v + 1] - e0[k] : 0;
+  }
+  int q[FP_BND_K][FP_BFS_ROW];
+#pragma unroll
+  for (int k = 0; k < FP_BND_K; k++)
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) q[k][j] = j < dg[k] ? (int)M.gci[e0[k] + j] : -1;
+#pragma unroll
+  for (int k = 0; k < FP_BND_K; k++)
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) q[k][j] = q[k][j] >= 0 ? (int)M.gmap[q[k][j]] : g[k];
+  uint32_t fl = 0;
+#pragma unroll
+  for (int k = 0; k < FP_BND_K; k++) {
+    bool b = false;
+#pragma unroll
+    for (int j = 0; j < FP_BFS_ROW; j++) b |= q[k][j] != g[k];
+    for (int e = e0[k] + FP_BFS_ROW; e < e0[k] + dg[k] && !b; e++) b = M.gmap[M.gci[e]] != g[k];
+    fl |= (uint32_t)b << k;
+  }
+  return fl;
+}
+// The flagged vertices of a step appended to list[*ctr]: one atomic per
+// workgroup and step.  Every thread calls it (barriers inside).
+template <class P, class L>
+__device__ __forceinline__ void wg_append_flags(P ctr, L list, int v0, uint32_t fl, int* tmp, int* base_s) {
+  int tot;
+  const int ex = wg_excl_scan(popc32(fl), tmp, &tot);
+  if (threadIdx.x == 0 && tot) *base_s = atomicAdd(ctr, tot);
+  __syncthreads();
+  if (!tot) return;
+  int o = *base_s + ex;
+#pragma unroll
+  for (int k = 0; k < FP_BND_K; k++)
+    if ((fl >> k) & 1u) list[o++] = v0 + FP_WG * k + (int)threadIdx.x;
+}
+// Lloyd step: the patch-boundary vertices start the distance BFS
+__global__ void __launch_bounds__(FP_WG) k_lloyd_bnd(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH_WG;
-  __shared__ int lds2[2];
-  for (int v0 = (int)(fp_s.bx * blockDim.x); v0 < M.n; v0 += (int)(fp_s.gx * blockDim.x)) {
-    const int v = v0 + (int)threadIdx.x;
-    bool isb = false;
-    if (v < M.n) {
-      const int g = M.gmap[v];
-      for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
-      M.key[v] = isb ? 0ull : FP_UNSET;
+  __shared__ int tmp[FP_WAVES + 2];
+  __shared__ int base_s;
+  // the workgroup steps together (barriers in each step)
+  for (int v0 = fp_s.bx * (FP_BND_K * FP_WG); v0 < M.n; v0 += fp_s.gx * (FP_BND_K * FP_WG)) {
+    int g[FP_BND_K];
+    const uint32_t fl = boundary_flags(M, v0, g);
+#pragma unroll
+    for (int k = 0; k < FP_BND_K; k++) {
+      const int v = v0 + FP_WG * k + (int)threadIdx.x;
+      if (v < M.n) M.key[v] = ((fl >> k) & 1u) ? 0ull : FP_UNSET;
     }
-    const int slot = wg_append(&M.fcnt[0], isb, lds2);
-    if (isb) M.fa[slot] = v;
+    wg_append_flags(&M.fcnt[0], M.fa, v0, fl, tmp, &base_s);
   }
 }
 // per patch, the candidate of largest distance (least vertex on ties); the
@@ -684,19 +736,19 @@ __global__ void k_quot_init(const FpMesh* __restrict__ fp_ms, const int* __restr
   for (int p = vt(fp_s); p <= P; p += vs(fp_s)) M.pcnt[p] = 0;
   if (vt(fp_s) == 0) C->nbnd = 0;
 }
-__global__ void k_patch_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
+// patch sizes and the boundary list
+__global__ void __launch_bounds__(FP_WG) k_patch_count(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
   MESH_WG;
-  __shared__ int lds2[2];
-  for (int v0 = (int)(fp_s.bx * blockDim.x); v0 < M.n; v0 += (int)(fp_s.gx * blockDim.x)) {
-    const int v = v0 + (int)threadIdx.x;
-    const bool act = v < M.n;
-    const int g = act ? M.gmap[v] : 0;
-    bool isb = false;
-    if (act)
-      for (int e = M.grp[v]; e < M.grp[v + 1] && !isb; e++) isb = (M.gmap[M.gci[e]] != g);
-    (void)wave_append_keyed(M.pcnt, g, act);
-    const int slot = wg_append(&C->nbnd, isb, lds2);
-    if (isb) M.bnd[slot] = v;
+  __shared__ int tmp[FP_WAVES + 2];
+  __shared__ int base_s;
+  // the workgroup steps together (barriers in each step)
+  for (int v0 = fp_s.bx * (FP_BND_K * FP_WG); v0 < M.n; v0 += fp_s.gx * (FP_BND_K * FP_WG)) {
+    int g[FP_BND_K];
+    const uint32_t fl = boundary_flags(M, v0, g);
+#pragma unroll
+    for (int k = 0; k < FP_BND_K; k++)
+      (void)wave_append_keyed(M.pcnt, g[k], v0 + FP_WG * k + (int)threadIdx.x < M.n);
+    wg_append_flags(&C->nbnd, M.bnd, v0, fl, tmp, &base_s);
   }
 }
 __global__ void k_patch_scatter(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm) {
@@ -708,26 +760,26 @@ __global__ void k_patch_scatter(const FpMesh* __restrict__ fp_ms, const int* __r
     if (act) M.pvtx[slot] = v;
   }
 }
-// distinct neighbour patches of patch p, ascending, by repeated wave-wide
-// minimum over the foreign neighbours of its members
-// Quotient row of patch p: the sorted distinct patches next to it.  With an
-// LDS bitmap over the patch ids (bm_words words per wave) one pass over the
-// members marks the neighbours, their loads issued a row at a time, and the
-// bitmap is read back in order; without it, one pass per neighbour.
-__global__ void k_qrow(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int fill, int lds_words) {
-  MESH;
+// Quotient row of patch p: the sorted distinct patches next to it, one
+// workgroup per patch.  With an LDS bitmap over the patch ids (bm_words
+// words) the workgroup's threads mark the neighbours of the members, a row's
+// loads issued together, and wave 0 reads the bitmap back in order; without
+// it, wave 0 takes the smallest unseen neighbour patch per pass (a wave-wide
+// minimum over the foreign neighbours of the members).
+__global__ void __launch_bounds__(FP_WG) k_qrow(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int fill, int lds_words) {
+  MESH_WG;
   FP_LDS_DECL;
   const int P = C->P;
   const int bm_words = (P + 31) / 32 <= lds_words ? (P + 31) / 32 : 0;
-  uint32_t* bm = (uint32_t*)fp_lds + (long long)bm_words * wave_id();
-  for (int p = vw(fp_s); p < P; p += vn(fp_s)) {
+  uint32_t* bm = (uint32_t*)fp_lds;
+  // the workgroup steps together (barriers in each step)
+  for (int p = fp_s.bx; p < P; p += fp_s.gx) {
     const int a0 = M.pptr[p], a1 = M.pptr[p + 1];
     gptr<int> out = fill ? M.qci + M.qptr[p] : gptr<int>(nullptr);
-    int cnt = 0;
     if (bm_words) {
-      for (int w = lane_id(); w < bm_words; w += 64) bm[w] = 0u;
-      wave_fence();
-      for (int i = a0 + lane_id(); i < a1; i += 64) {
+      for (int w = threadIdx.x; w < bm_words; w += FP_WG) bm[w] = 0u;
+      __syncthreads();
+      for (int i = a0 + (int)threadIdx.x; i < a1; i += FP_WG) {
         const int v = M.pvtx[i];
         const int e0 = M.grp[v], deg = M.grp[v + 1] - e0;
         int u[FP_BFS_ROW];
@@ -743,24 +795,28 @@ __global__ void k_qrow(const FpMesh* __restrict__ fp_ms, const int* __restrict__
           if (q != p) atomicOr(&bm[q >> 5], 1u << (q & 31));
         }
       }
-      wave_fence();
-      for (int w0 = 0; w0 < bm_words; w0 += 64) {
-        const int w = w0 + lane_id();
-        uint32_t x = w < bm_words ? bm[w] : 0u;
-        const int c = popc32(x);
-        const int inc = wave_incl_scan(c);
-        if (out) {
-          int o = cnt + inc - c;
-          while (x) {
-            out[o++] = w * 32 + __ffs(x) - 1;
-            x &= x - 1;
+      __syncthreads();
+      if (wave_id() == 0) {
+        int cnt = 0;
+        for (int w0 = 0; w0 < bm_words; w0 += 64) {
+          const int w = w0 + lane_id();
+          uint32_t x = w < bm_words ? bm[w] : 0u;
+          const int c = popc32(x);
+          const int inc = wave_incl_scan(c);
+          if (out) {
+            int o = cnt + inc - c;
+            while (x) {
+              out[o++] = w * 32 + __ffs(x) - 1;
+              x &= x - 1;
+            }
           }
+          cnt += wave_bcast(inc, 63);
         }
-        cnt += wave_bcast(inc, 63);
+        if (!fill && lane_id() == 0) M.pcnt[p] = cnt;
       }
-      wave_fence();
-    } else {
-      int last = -1;
+      __syncthreads();  // the bitmap is cleared for the next patch
+    } else if (wave_id() == 0) {
+      int cnt = 0, last = -1;
       while (true) {
         uint32_t m = 0xFFFFFFFFu;
         for (int i = a0 + lane_id(); i < a1; i += 64) {
@@ -776,8 +832,8 @@ __global__ void k_qrow(const FpMesh* __restrict__ fp_ms, const int* __restrict__
         cnt++;
         last = (int)m;
       }
+      if (!fill && lane_id() == 0) M.pcnt[p] = cnt;
     }
-    if (!fill && lane_id() == 0) M.pcnt[p] = cnt;
   }
 }
 
@@ -2286,7 +2342,8 @@ fp_status run_pipe(Pipe& P) {
       auto on = [&](int i) { return patching(i) && it < mp[i].lloyd; };
       auto ln = [&](int i) { return on(i) ? P.blk(mp[i].n) : 0; };
       FPG("k_lloyd_gmap", k_lloyd_gmap, ln, T, 0, st);
-      FPG("k_lloyd_bnd", k_lloyd_bnd, ln, T, 0, st);
+      FPG("k_lloyd_bnd", k_lloyd_bnd,
+          [&](int i) { return on(i) ? P.blk(mp[i].n, FP_BND_K * FP_WG) : 0; }, T, 0, st);
       P.check();
       P.bfs(true, on);
       FPG("k_lloyd_best", k_lloyd_best, ln, T, 0, st);
@@ -2304,7 +2361,8 @@ fp_status run_pipe(Pipe& P) {
   // quotient graph (P on the device)
   P.mark(2);
   FPG("k_quot_init", k_quot_init, [&](int i) { return P.blk(mp[i].Pexp + 1); }, T, 0, st);
-  FPG("k_patch_count", k_patch_count, per_n, T, 0, st);
+  FPG("k_patch_count", k_patch_count, [&](int i) { return P.blk(mp[i].n, FP_BND_K * FP_WG); }, T,
+      0, st);
   FPG("k_copy", k_mcopy, [&](int i) { return P.blk(mp[i].Pexp); }, T, 0, st, (int)FA_WP,
       (int)FA_PCNT, (int)FN_P);
   P.check();
@@ -2313,20 +2371,20 @@ fp_status run_pipe(Pipe& P) {
   FPG("k_copy", k_mcopy, [&](int i) { return P.blk(mp[i].Pexp); }, T, 0, st, (int)FA_PCNT,
       (int)FA_PPTR, (int)FN_P);
   FPG("k_patch_scatter", k_patch_scatter, per_n, T, 0, st);
-  // a patch-id bitmap per wave when four of them fit in 64 KB of LDS (for
-  // the expected patch count; the kernel checks the actual one)
+  // a patch-id bitmap per workgroup when it fits in 64 KB of LDS (for the
+  // expected patch count; the kernel checks the actual one)
   int qbw = 0;
   for (int i = 0; i < nm; i++) {
     const int w = (mp[i].Pexp + 31) / 32;
-    if ((long long)w * 4 * FP_WAVES <= 65536) qbw = std::max(qbw, w);
+    if ((long long)w * 4 <= 65536) qbw = std::max(qbw, w);
   }
-  auto qb = [&](int i) { return P.blk(mp[i].Pexp, FP_WAVES); };
-  FPG("k_qrow", k_qrow, qb, T, (size_t)qbw * 4 * FP_WAVES, st, 0, qbw);
+  auto qb = [&](int i) { return P.blk(mp[i].Pexp, 1); };
+  FPG("k_qrow", k_qrow, qb, T, (size_t)qbw * 4, st, 0, qbw);
   P.check();
   P.scan(FA_PCNT, FA_QPTR, FN_P, FT_NQ);
   FPG("k_set", k_mptr_end, one, dim3(64), 0, st, (int)FA_QPTR, (int)FN_P, (int)FT_NQ);
   FPG("k_check_arcs", k_check_arcs, one, dim3(64), 0, st);
-  FPG("k_qrow", k_qrow, qb, T, (size_t)qbw * 4 * FP_WAVES, st, 1, qbw);
+  FPG("k_qrow", k_qrow, qb, T, (size_t)qbw * 4, st, 1, qbw);
   P.check();
 
   // separator tree
