@@ -1291,17 +1291,30 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
     sym_drop(M, t, FP_SITE_SYM_LIVE);
     return;
   }
+  // record sizes, four rows per step with their loads issued together
   int total = 0;
-  for (int i = 0; i < nout; i++) {
-    const int r = uni(V.outl[i]);
-    if ((unsigned)r >= (unsigned)rows) {
+  for (int i0 = 0; i0 < nout; i0 += 4) {
+    int r[4];
+    bool bad = false;
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      r[u] = i0 + u < nout ? uni(V.outl[i0 + u]) : 0;
+      bad |= (unsigned)r[u] >= (unsigned)rows;
+    }
+    if (bad) {
       sym_drop(M, t, FP_SITE_SYM_LIVE);
       return;
     }
-    gptr<const uint32_t> row = V.rows + (long long)r * stride;
-    int c = 0;
-    for (int w = lane_id(); w < FW; w += 64) c += popc32(row[w]);
-    total += 1 + wave_sum_i32(c);
+    int c[4] = {0, 0, 0, 0};
+    for (int w = lane_id(); w < FW; w += 64) {
+      uint32_t x[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) x[u] = V.rows[(long long)r[u] * stride + w];
+#pragma unroll
+      for (int u = 0; u < 4; u++) c[u] += i0 + u < nout ? popc32(x[u]) : 0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; u++) total += i0 + u < nout ? 1 + wave_sum_i32(c[u]) : 0;
   }
   int base = 0;
   if (lane_id() == 0) {
@@ -1329,12 +1342,26 @@ __device__ __forceinline__ void sym_emit(const FpMesh& M, int t, int d) {
       const int c = popc32(x);
       const int inc = wave_incl_scan(c);
       int o = off + 1 + len + inc - c;
+      // eight set bits per step, their positions loaded together
       while (x) {
-        const int f = w * 32 + __ffs(x) - 1;
-        x &= x - 1;
-        const bool ok = f >= m && f < m + nbd;  // elements only hold later positions
-        bad |= !ok;
-        dst[o++] = ok ? V.bd[f - m] : b0;
+        int f[8], q[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          f[u] = x ? w * 32 + __ffs(x) - 1 : -1;
+          x &= x - 1;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          const bool ok = f[u] >= m && f[u] < m + nbd;  // elements only hold later positions
+          q[u] = V.bd[ok ? f[u] - m : 0];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; u++) {
+          if (f[u] < 0) continue;
+          const bool ok = f[u] >= m && f[u] < m + nbd;
+          bad |= !ok;
+          dst[o++] = ok ? q[u] : b0;
+        }
       }
       len += wave_bcast(inc, 63);
     }
