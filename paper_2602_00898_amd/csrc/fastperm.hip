@@ -939,38 +939,43 @@ __global__ void __launch_bounds__(FP_WG) k_bisect(const FpMesh* __restrict__ fp_
     if (m >= 2) wg_bisect(M, t, M.segS[t], m, &sh, fp_lds, lds_bytes);
   }
 }
+// Candidates of level d, counted per node and side.  The lanes of a wave
+// hold consecutive indices (i0 and di as the callers pass them), so the loop
+// runs wave by wave and a wave adds its candidates with one atomic per node
+// and side present in it (at the root every candidate shares one counter).
 __device__ __forceinline__ void lv_cand(const FpMesh& M, gptr<FpCtl> C, int d, int i0, int di) {
-  (void)d;
   const int hi = (1 << (d + 1)) - 1;
   const int nb = C->nbnd;
-  for (int i = i0; i < nb; i += di) {
-    const int v = M.bnd[i];
-    M.cand[i] = 0;
-    if (M.node_of[v] != -1) continue;
-    const int c = M.pnode[M.gmap[v]];
-    if (c < hi) continue;  // patch not split at this level
-    const int sib = (c & 1) ? c + 1 : c - 1;
-    const int e0 = M.grp[v], deg = M.grp[v + 1] - e0;
-    // the first FP_BFS_ROW neighbours' columns, marks and patches at once
-    int u[FP_BFS_ROW], nu[FP_BFS_ROW], gu[FP_BFS_ROW];
-#pragma unroll
-    for (int j = 0; j < FP_BFS_ROW; j++) u[j] = j < deg ? (int)M.gci[e0 + j] : -1;
-#pragma unroll
-    for (int j = 0; j < FP_BFS_ROW; j++) {
-      nu[j] = u[j] >= 0 ? (int)M.node_of[u[j]] : 0;
-      gu[j] = u[j] >= 0 ? (int)M.gmap[u[j]] : 0;
-    }
+  for (int i = i0; i - lane_id() < nb; i += di) {
     bool is = false;
+    int c = 0;
+    if (i < nb) {
+      const int v = M.bnd[i];
+      c = M.node_of[v] == -1 ? (int)M.pnode[M.gmap[v]] : 0;
+      if (c >= hi) {  // else the patch is not split at this level
+        const int sib = (c & 1) ? c + 1 : c - 1;
+        const int e0 = M.grp[v], deg = M.grp[v + 1] - e0;
+        // the first FP_BFS_ROW neighbours' columns, marks and patches at once
+        int u[FP_BFS_ROW], nu[FP_BFS_ROW], gu[FP_BFS_ROW];
 #pragma unroll
-    for (int j = 0; j < FP_BFS_ROW; j++) is |= nu[j] == -1 && M.pnode[gu[j]] == sib;
-    for (int e = e0 + FP_BFS_ROW; e < e0 + deg && !is; e++) {
-      const int w = M.gci[e];
-      is = (M.node_of[w] == -1 && M.pnode[M.gmap[w]] == sib);
+        for (int j = 0; j < FP_BFS_ROW; j++) u[j] = j < deg ? (int)M.gci[e0 + j] : -1;
+#pragma unroll
+        for (int j = 0; j < FP_BFS_ROW; j++) {
+          nu[j] = u[j] >= 0 ? (int)M.node_of[u[j]] : 0;
+          gu[j] = u[j] >= 0 ? (int)M.gmap[u[j]] : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < FP_BFS_ROW; j++) is |= nu[j] == -1 && M.pnode[gu[j]] == sib;
+        for (int e = e0 + FP_BFS_ROW; e < e0 + deg && !is; e++) {
+          const int w = M.gci[e];
+          is = (M.node_of[w] == -1 && M.pnode[M.gmap[w]] == sib);
+        }
+      }
+      M.cand[i] = is ? 1 : 0;
     }
-    if (is) {
-      M.cand[i] = 1;
-      atomicAdd((c & 1) ? &M.cntL[(c - 1) >> 1] : &M.cntR[(c - 1) >> 1], 1);
-    }
+    const int t = is ? (c - 1) >> 1 : 0;
+    (void)wave_append_keyed(M.cntL, t, is && (c & 1));
+    (void)wave_append_keyed(M.cntR, t, is && !(c & 1));
   }
 }
 __global__ void k_cand(const FpMesh* __restrict__ fp_ms, const int* __restrict__ fp_boff, int fp_nm, int d) {
