@@ -889,6 +889,8 @@ __global__ void k_level_begin(const FpMesh* __restrict__ fp_ms, const int* __res
   if (d >= C->D) return;
   lv_begin(M, C, d, vt(fp_s), vs(fp_s));
 }
+// arcs of a quotient row held in registers for the arc lookups of lv_arcs
+#define FP_ARC_ROW 16
 __device__ __forceinline__ void lv_arcs(const FpMesh& M, gptr<FpCtl> C, int d, int i0, int di) {
   (void)d;
   const int nb = C->nbnd;
@@ -897,10 +899,15 @@ __device__ __forceinline__ void lv_arcs(const FpMesh& M, gptr<FpCtl> C, int d, i
     if (M.node_of[v] != -1) continue;
     const int gv = M.gmap[v];
     const int e0 = M.grp[v], deg = M.grp[v + 1] - e0;
-    // the first FP_BFS_ROW neighbours' columns, marks and patches at once
-    int u[FP_BFS_ROW], nu[FP_BFS_ROW], gu[FP_BFS_ROW];
+    const int q0 = M.qptr[gv], qn = M.qptr[gv + 1] - q0;
+    // the first FP_BFS_ROW neighbours' columns, marks and patches at once,
+    // and v's quotient row (FP_ARC_ROW arcs) beside them: an arc is then
+    // found by comparing in registers instead of a search of dependent loads
+    int u[FP_BFS_ROW], nu[FP_BFS_ROW], gu[FP_BFS_ROW], qc[FP_ARC_ROW];
 #pragma unroll
     for (int j = 0; j < FP_BFS_ROW; j++) u[j] = j < deg ? (int)M.gci[e0 + j] : -1;
+#pragma unroll
+    for (int k = 0; k < FP_ARC_ROW; k++) qc[k] = k < qn ? (int)M.qci[q0 + k] : -1;
 #pragma unroll
     for (int j = 0; j < FP_BFS_ROW; j++) {
       nu[j] = u[j] >= 0 ? (int)M.node_of[u[j]] : 0;
@@ -909,7 +916,13 @@ __device__ __forceinline__ void lv_arcs(const FpMesh& M, gptr<FpCtl> C, int d, i
 #pragma unroll
     for (int j = 0; j < FP_BFS_ROW; j++) {
       if (nu[j] != -1 || gu[j] == gv) continue;
-      const int a = arc_index(M, gv, gu[j]);
+      int a = -1;
+      if (qn <= FP_ARC_ROW) {
+#pragma unroll
+        for (int k = 0; k < FP_ARC_ROW; k++) a = qc[k] == gu[j] ? q0 + k : a;
+      } else {
+        a = arc_index(M, gv, gu[j]);
+      }
       if (a >= 0) atomicAdd(&M.qcnt[a], 1);
     }
     for (int e = e0 + FP_BFS_ROW; e < e0 + deg; e++) {
