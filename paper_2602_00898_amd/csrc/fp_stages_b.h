@@ -209,13 +209,21 @@ __device__ __forceinline__ void wg_bisect_body(const FpMesh& M, int t, int s, in
       gptr<int> tl = lsA; lsA = lsB; lsB = tl;
       eccA = eccB;
     }
-    // order by (level, index): rank inside the level by counting smaller ids
+    // order by (level, index): rank inside the level by counting smaller
+    // ids, eight queue entries read together per step
     for (int i = threadIdx.x; i < cnt; i += FP_WG) {
       const int x = qA[i];
       const int L = levA[x];
       const int a = lsA[L], b = lsA[L + 1];
-      int r = 0;
-      for (int j = a; j < b; j++) r += (qA[j] < x);
+      int r = 0, j = a;
+      for (; j + 8 <= b; j += 8) {
+        int q[8];
+#pragma unroll
+        for (int u = 0; u < 8; u++) q[u] = qA[j + u];
+#pragma unroll
+        for (int u = 0; u < 8; u++) r += (q[u] < x);
+      }
+      for (; j < b; j++) r += (qA[j] < x);
       Q[base + a + r] = x;
     }
     __syncthreads();
